@@ -1,0 +1,27 @@
+"""FP64 CPU oracle for the randomized SVD hot path (Halko, Martinsson, Tropp).
+
+TEST INFRASTRUCTURE ONLY.  This package is the slow, plainly written reference
+that the GPU path is checked against.  Only the test suite, the smoke check of
+the package entry point and the CPU-baseline leg of the benchmark may import
+it.  The product library (the C ABI and its Python binding) never imports,
+links or calls anything in here, and shares no code with it.
+
+Contents
+--------
+philox      Counter-based generator (Philox4x64-10, published by Salmon, Moraes,
+            Dror and Shaw, SC'11) and the draws the method makes from it: the
+            Gaussian test matrix of Algorithm 4.1 and the SRFT ingredients of
+            the SRFT definition in Section 4.6.
+rsvd        The method itself, step by step in FP64 with LAPACK (through numpy)
+            for Householder QR and dense SVD: Algorithms 4.1, 4.3, 4.4, 4.5 and
+            5.1, the truncation of Remark 5.1, and the prototype randomized SVD
+            of Section 1.6.
+evaluate    Residual norms ||A - QQ*A|| and ||A - U S V*|| and the paper's error
+            bounds (Theorems 9.1-9.3, 10.5, 10.6, Corollaries 10.9, 10.10).
+
+Every function is pinned by a CPU test (tests/test_oracle_*.py) against
+something other than itself: numpy's own Philox, brute-force DFTs and SVDs,
+exact-rank recovery and the deterministic theorems of Section 9.
+"""
+
+from . import philox, rsvd, evaluate  # noqa: F401
