@@ -1,0 +1,248 @@
+"""Benchmark of the randomized SVD hot path on one MI355X.
+
+One step = the whole path on the resident input: draw Omega, Y = A Omega,
+CholeskyQR2, q power steps (A^T Q, CQR2, A Qt, CQR2), B = Q* A, the FP64 small
+SVD and the lifts -- the four C entry points rsvd_range_finder,
+rsvd_power_iter, rsvd_project and rsvd_svd.
+
+Workload (default): power-iteration rSVD of an FP32 16384 x 8192 matrix
+A = U diag(sigma) V^T with sigma_j = 1/j (U, V Haar, built on the GPU), k = 100,
+p = 20, q = 2.  The headline line is the BF16-MFMA form (bf16x3 split products,
+FP32 accumulation); the plain FP32 form runs on the same matrix for comparison.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.  `value` is algorithmic TFLOP/s of the whole step
+(flops the method must do, not padded tiles or the three bf16 products).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
+MI355X_CUS = 256
+
+
+def algorithmic_flops(m, n, l, k, q):
+    """Flops the method must do per step.
+
+    GEMM passes over A: (2q + 2) x 2 m n l.  CholeskyQR2 of an M x l matrix:
+    2 passes x (Gram M l^2 + triangular apply M l^2).  Orthonormalizations:
+    one of m rows, then n and m rows per power step.  Small SVD: Gram of Bt
+    n l^2 (+ O(l^3)).  Lifts: 2 (m + n) l k.
+    """
+    gemm = (2 * q + 2) * 2.0 * m * n * l
+    cqr = 4.0 * l * l * (m + q * (m + n))
+    small = n * l * l + 2.0 * (m + n) * l * k
+    return gemm + cqr + small
+
+
+def algorithmic_bytes(m, n, l, q, esize=4):
+    """HBM bytes the method must move per step: every pass reads A once and its
+    l-column operand, and writes its l-column result."""
+    return (2 * q + 2) * (m * n + (m + n) * l) * esize
+
+
+def spectral_norm_residual(A, U, S, V, iters=30, block=16, seed=1234):
+    """||A - U diag(S) V^T||_2 in FP64 by block subspace iteration with a final
+    Rayleigh-Ritz step (torch on the GPU; a measurement, not part of the method)."""
+    import torch
+    A64 = A.double()
+    U64, S64, V64 = U.double(), S.double(), V.double()
+    gen = torch.Generator(device=A.device)
+    gen.manual_seed(seed)
+    X = torch.randn(A.shape[1], block, generator=gen, device=A.device, dtype=torch.float64)
+
+    def E(x):
+        return A64 @ x - U64 @ (S64[:, None] * (V64.T @ x))
+
+    def Et(y):
+        return A64.T @ y - V64 @ (S64[:, None] * (U64.T @ y))
+
+    for _ in range(iters):
+        X, _ = torch.linalg.qr(Et(E(X)))
+    s = torch.linalg.svdvals(E(X))
+    out = float(s[0])
+    del A64
+    return out
+
+
+def run_path(A, k, p, q, prec, steps, warmup, seed):
+    import torch
+    import paper_0909_4061_amd as rs
+
+    m, n = A.shape
+    l = k + p
+    dev = A.device
+    pr = rs.problem(m, n, k, p, q, dtype=A.dtype, prec=prec, seed=seed, lda=A.stride(0))
+    ws = rs.Workspace(pr, dev)
+    Q = torch.empty(m, l, dtype=A.dtype, device=dev)
+    Bt = torch.empty(n, l, dtype=A.dtype, device=dev)
+    U = torch.empty(m, k, dtype=A.dtype, device=dev)
+    S = torch.empty(k, dtype=A.dtype, device=dev)
+    V = torch.empty(n, k, dtype=A.dtype, device=dev)
+    kw = dict(prec=prec, seed=seed, ws=ws)
+
+    def step():
+        rs.rsvd_range_finder(A, k, p, q=q, Q=Q, **kw)
+        rs.rsvd_power_iter(A, Q, k, p, q, **kw)
+        rs.rsvd_project(A, Q, k, p, q=q, Bt=Bt, **kw)
+        rs.rsvd_svd(Bt, Q, m, n, k, p, q=q, dtype=A.dtype, U=U, S=S, V=V, **kw)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    rs.profile_enable(64 * max(steps, 1), dev)
+    stream = torch.cuda.current_stream(dev)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t0.elapsed_time(t1)
+    prof = rs.profile_read(dev)
+    rs.profile_enable(0, dev)
+    flags = rs.device_status(dev)
+    return dict(ms_per_step=ms_total / steps, prof=prof, flags=flags, U=U, S=S, V=V)
+
+
+def roofline_for(res, m, n, l, prec):
+    """Roofline figures of the dominant kernel (the GEMM family that streams A
+    and takes the most time), from the live per-launch event timing."""
+    fam = max(("stream_nn", "stream_tn"), key=lambda f: res["prof"][f][1])
+    launches, total_ms = res["prof"][fam]
+    avg_s = total_ms / launches / 1e3
+    rows, K = (m, n) if fam == "stream_nn" else (n, m)
+    bytes_launch = 4.0 * (rows * K + (rows + K) * l)
+    flops_launch = 2.0 * rows * K * l
+    if prec == "native":
+        achieved = flops_launch / avg_s / 1e12
+        out = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+               "frac": achieved / PEAK_TFLOPS["f32"]}
+    else:
+        achieved = bytes_launch / avg_s / 1e9
+        out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+               "frac": achieved / PEAK_HBM_GBS}
+    out.update({"kernel": f"gemm_{'tn' if fam == 'stream_tn' else 'nn'}_{'f32' if prec == 'native' else prec}",
+                "launches": launches, "avg_us": avg_s * 1e6, "traffic": None,
+                "per_launch": {"bytes": bytes_launch, "flops": flops_launch}})
+    return out
+
+
+def cpu_baseline(A, k, p, q, seed, flops, budget_s=30.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload.
+
+    The sample is the first m' rows of A with m' chosen so that one run takes
+    about budget_s (at most all m rows); the rate is scaled to the same
+    algorithmic-flop unit as the GPU line."""
+    import numpy as np
+    from oracle import rsvd as orsvd
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 0) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        threads = os.cpu_count()
+    m, n = A.shape
+    # calibrate on a small slab, then size the sample
+    mc = min(m, 2048)
+    A_c = A[:mc].double().cpu().numpy()
+    t = time.perf_counter()
+    orsvd.rsvd(A_c, k, p, q, seed=seed, dtype=np.float32)
+    tc = time.perf_counter() - t
+    mm = int(min(m, max(mc, mc * budget_s / max(tc, 1e-3))))
+    mm = max(mm, k + p)
+    A_s = A[:mm].double().cpu().numpy()
+    t = time.perf_counter()
+    orsvd.rsvd(A_s, k, p, q, seed=seed, dtype=np.float32)
+    dt = time.perf_counter() - t
+    f_s = algorithmic_flops(mm, n, k + p, k, q)
+    return {"value": f_s / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"FP64 numpy oracle, full rSVD (k={k}, p={p}, q={q}) on the first {mm} of {m} rows "
+                      f"of the same matrix, {dt:.1f} s",
+            "seconds": dt, "rows": mm}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--m", type=int, default=16384)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--k", type=int, default=100)
+    ap.add_argument("--p", type=int, default=20)
+    ap.add_argument("--q", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0x09094061)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["bf16x3", "native"], default=None)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from workloads import build_matrix_torch, spectrum
+
+    m, n, k, p, q = args.m, args.n, args.k, args.p, args.q
+    l = k + p
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t = time.perf_counter()
+    sigma = spectrum("inv", min(m, n))
+    A = build_matrix_torch(m, n, sigma, seed=args.seed, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    print(f"# built A {m}x{n} on the GPU in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+
+    flops = algorithmic_flops(m, n, l, k, q)
+    hbm = algorithmic_bytes(m, n, l, q)
+    paths = {}
+    for prec in (["bf16x3", "native"] if args.only is None else [args.only]):
+        res = run_path(A, k, p, q, prec, args.steps, args.warmup, args.seed)
+        err = spectral_norm_residual(A, res["U"], res["S"], res["V"]) / sigma[k]
+        sig_err = float(np.max(np.abs(res["S"].double().cpu().numpy() - sigma[:k]) / sigma[:k]))
+        s = res["ms_per_step"] / 1e3
+        paths[prec] = {
+            "ms_per_step": res["ms_per_step"], "tflops": flops / s / 1e12, "hbm_gbs": hbm / s / 1e9,
+            "err_ratio": err, "sigma_rel_err_vs_construction": sig_err, "flags": res["flags"],
+            "roofline": roofline_for(res, m, n, l, prec),
+            "kernel_ms_per_step": {f: v[1] / args.steps for f, v in res["prof"].items()},
+        }
+        print(f"# {prec}: {res['ms_per_step']:.3f} ms/step, {paths[prec]['tflops']:.2f} TFLOP/s, "
+              f"err ratio {err:.4f}", file=sys.stderr, flush=True)
+
+    head = "bf16x3" if "bf16x3" in paths else "native"
+    hp = paths[head]
+    line = {
+        "metric": "rSVD TFLOP/s + HBM GB/s at stated ||A-USV*||/sigma_{k+1}; BF16-MFMA vs FP32",
+        "value": hp["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": hp["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if head == "bf16x3" else "f32", "prec": head, "data": "synthetic",
+        "config": {"workload": f"power-iteration rSVD, FP32 {m}x{n}, sigma_j=1/j, k={k}, p={p}, q={q}",
+                   "m": m, "n": n, "k": k, "p": p, "q": q, "sketch": "gaussian"},
+        "hbm_gbs": hp["hbm_gbs"], "err_ratio": hp["err_ratio"], "roofline": hp["roofline"],
+        "paths": {pth: {kk: vv for kk, vv in d.items() if kk != "roofline"} | {"roofline": d["roofline"]}
+                  for pth, d in paths.items()},
+    }
+    if "native" in paths and head != "native":
+        line["speedup_vs_fp32"] = paths["native"]["ms_per_step"] / hp["ms_per_step"]
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(A, k, p, q, args.seed, flops)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * rsvd.h -- C ABI of the MI355X (gfx950) randomized SVD library (librsvd.so).
+ *
+ * The library computes the two-stage randomized SVD of Halko, Martinsson and
+ * Tropp, "Finding structure with randomness" (SIAM Review 2011):
+ *
+ *   Stage A (range finding): draw a test matrix Omega, form Y = (A A*)^q A Omega
+ *     with an orthonormalization after every application of A or A*
+ *     (Algorithm 4.4, randomized subspace iteration; Algorithm 4.1 when q = 0),
+ *     or, for the SRFT test matrix of Section 4.6, Y = A Omega by FFT
+ *     (Algorithm 4.5).  Q is an orthonormal basis of range(Y).
+ *   Stage B (Algorithm 5.1, direct SVD): B = Q* A, an SVD of the small matrix
+ *     B = U~ S V*, U = Q U~, then truncation to the k leading triplets (the
+ *     truncation remark of Section 5.1).
+ *
+ * The problem statement follows the fixed-rank problem of Section 1.3: an
+ * m x n matrix A, a target rank k and an oversampling parameter p, with
+ * l = k + p samples, and q power steps (Section 1.6, Section 4.5).
+ *
+ * Conventions for every call
+ * --------------------------
+ *  * All matrices are row-major.  A has leading dimension lda >= n (elements).
+ *    Every other matrix is dense with leading dimension equal to its column
+ *    count.
+ *  * Element type: float (RSVD_F32) or double (RSVD_F64), chosen by
+ *    problem->dtype, for A, Omega, Q, Bt, U, S and V.  With the SRFT sketch,
+ *    Q, Bt, U and V are complex (interleaved re/im pairs of the element type,
+ *    the layout of torch.complex64 / complex128); S is always real.
+ *  * Pointers named A, Q, Bt, U, S, V, Omega and ws are DEVICE pointers on the
+ *    handle's device.  The problem descriptor is a HOST pointer.  `stream` is
+ *    a hipStream_t (NULL = the default stream) on which every kernel of the
+ *    call is enqueued; calls return without synchronizing.
+ *  * Ownership: the caller owns every buffer.  The library never allocates or
+ *    frees memory in these calls; scratch space is the caller's workspace `ws`
+ *    of at least rsvd_workspace_bytes(problem) bytes, 256-byte aligned.  Its
+ *    contents are undefined between calls (except as noted for rsvd_project ->
+ *    rsvd_svd, which carry nothing through it).
+ *  * Errors: argument errors are detected on the host before any launch and
+ *    returned synchronously (RSVD_E_INVAL, RSVD_E_WORKSPACE,
+ *    RSVD_E_UNSUPPORTED); a HIP launch error returns RSVD_E_DEVICE.  Numerical
+ *    conditions found on the device (a Cholesky pivot that needed a shift, a
+ *    non-finite value, a Jacobi sweep cap) are recorded in the handle's device
+ *    status word and read by rsvd_device_status.  No call throws.
+ *  * A handle is not thread-safe; calls that share a handle must be ordered.
+ */
+#ifndef RSVD_H
+#define RSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rsvd_status {
+  RSVD_OK = 0,
+  RSVD_E_INVAL = 1,        /* bad argument: null pointer, shape or parameter out of range */
+  RSVD_E_WORKSPACE = 2,    /* workspace null or smaller than rsvd_workspace_bytes() */
+  RSVD_E_DEVICE = 3,       /* a HIP call or kernel launch failed */
+  RSVD_E_UNSUPPORTED = 4,  /* valid problem outside what this build implements */
+  RSVD_E_BREAKDOWN = 5,    /* device status: a Cholesky pivot was not positive (a shift was applied) */
+  RSVD_E_NONFINITE = 6,    /* device status: a NaN or Inf reached a Gram matrix */
+  RSVD_E_NOCONV = 7        /* device status: Jacobi SVD hit its sweep cap */
+} rsvd_status;
+
+/* problem->dtype */
+enum { RSVD_F32 = 0, RSVD_F64 = 1 };
+/* problem->sketch: the test matrix of Stage A */
+enum {
+  RSVD_GAUSSIAN = 0,  /* i.i.d. N(0,1) n x l (Section 4.1) */
+  RSVD_SRFT = 1       /* sqrt(n/l) D F R with D = random +-1 signs (Section 4.6); q must be 0 */
+};
+/* problem->prec: arithmetic of the products that stream A (the sketch,
+ * power-step and projection GEMMs).  Gram matrices, Cholesky factors and the
+ * small SVD are always FP64. */
+enum {
+  RSVD_NATIVE = 0,  /* products in the element type on FP32 / FP64 MFMA */
+  RSVD_BF16 = 1,    /* FP32 data rounded to bfloat16, one BF16 MFMA product, FP32 accumulation */
+  RSVD_BF16X3 = 2   /* split-precision: a = a_hi + a_lo (bfloat16 each), three BF16 MFMA
+                       products a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32 accumulation */
+};
+
+/* Device status bits (rsvd_device_status) */
+enum {
+  RSVD_FLAG_SHIFTED = 1,    /* a Cholesky factorization needed a diagonal shift */
+  RSVD_FLAG_NONFINITE = 2,  /* a Gram matrix held NaN/Inf */
+  RSVD_FLAG_NOCONV = 4      /* the Jacobi SVD stopped at its sweep cap */
+};
+
+typedef struct rsvd_problem {
+  int64_t m, n;     /* A is m x n */
+  int64_t lda;      /* leading dimension of A in elements, lda >= n */
+  int32_t k;        /* target rank, 1 <= k */
+  int32_t p;        /* oversampling, p >= 0; l = k + p <= min(m, n) and l <= RSVD_MAX_L */
+  int32_t q;        /* power steps, q >= 0 (must be 0 with the SRFT sketch) */
+  int32_t dtype;    /* RSVD_F32 or RSVD_F64 */
+  int32_t sketch;   /* RSVD_GAUSSIAN or RSVD_SRFT */
+  int32_t prec;     /* RSVD_NATIVE, RSVD_BF16 or RSVD_BF16X3 (the last two need RSVD_F32) */
+  uint64_t seed;    /* Philox4x64-10 key word 0 */
+  uint64_t stream_id; /* Philox counter word 1: independent draws for the same seed */
+} rsvd_problem;
+
+/* Largest number of samples l = k + p this build supports (one workgroup
+ * holds the l x l factors of the small FP64 steps in its local memory). */
+#define RSVD_MAX_L 128
+
+typedef struct rsvd_handle_s* rsvd_handle;
+
+/* Create a handle on HIP device `device`: records the device and allocates the
+ * handle's 16-byte device status word.  The only allocation the library makes. */
+rsvd_status rsvd_create(rsvd_handle* handle, int device);
+rsvd_status rsvd_destroy(rsvd_handle handle);
+
+/* Pure host checks of a problem descriptor (no device, no handle).  RSVD_OK,
+ * RSVD_E_INVAL (violates the problem statement: k < 1, p < 0, q < 0,
+ * l > min(m, n), lda < n, unknown enum) or RSVD_E_UNSUPPORTED (l > RSVD_MAX_L,
+ * BF16 precisions with FP64 data, SRFT with q > 0 or n not a power of two,
+ * n > 32768 with the SRFT). */
+rsvd_status rsvd_validate(const rsvd_problem* problem);
+
+/* Bytes of workspace every call below needs for `problem` (0 if invalid).
+ * One size serves all four hot-path calls. */
+size_t rsvd_workspace_bytes(const rsvd_problem* problem);
+
+const char* rsvd_status_string(rsvd_status status);
+
+/* --- The hot path ------------------------------------------------------- */
+
+/* Stage A, first application: Algorithm 4.1 (Gaussian; step 2 of Algorithm
+ * 4.4) or Algorithm 4.5 (SRFT).  Draws Omega from (seed, stream_id), forms
+ * Y = A Omega and writes an orthonormal basis Q (m x l) of range(Y), computed
+ * by CholeskyQR2 (two passes of Gram -> Cholesky -> Y R^-1, FP64 Gram and
+ * Cholesky).  A: m x n (lda); Q: m x l output (complex with the SRFT). */
+rsvd_status rsvd_range_finder(rsvd_handle handle, const rsvd_problem* problem,
+                              const void* A, void* Q, void* ws, size_t ws_bytes,
+                              hipStream_t stream);
+
+/* Stage A, power steps: Algorithm 4.4 steps 3-6.  For j = 1..q:
+ * Qt = orth(A* Q), Q = orth(A Qt), each orth by CholeskyQR2.  Q (m x l) is
+ * read and overwritten in place.  A no-op when q = 0. */
+rsvd_status rsvd_power_iter(rsvd_handle handle, const rsvd_problem* problem,
+                            const void* A, void* Q, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* Stage B, step 1 of Algorithm 5.1: B = Q* A.  Written as its transpose
+ * Bt = A^T conj(Q) (n x l, row-major), i.e. B stored column-major: Bt[j*l + i]
+ * = B[i][j]. */
+rsvd_status rsvd_project(rsvd_handle handle, const rsvd_problem* problem,
+                         const void* A, const void* Q, void* Bt, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/* Stage B, steps 2-3 of Algorithm 5.1 plus truncation to rank k: an SVD of the
+ * small matrix B = U~ S V* (FP64: Gram B B*, Cholesky, one-sided Jacobi),
+ * U = Q U~, and the k leading triplets.  Bt: n x l (from rsvd_project);
+ * Q: m x l; outputs U: m x k, S: k (real, descending), V: n x k, with
+ * A ~ U diag(S) V*. */
+rsvd_status rsvd_svd(rsvd_handle handle, const rsvd_problem* problem,
+                     const void* Bt, const void* Q, void* U, void* S, void* V,
+                     void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* --- Diagnostics ------------------------------------------------------- */
+
+/* The Gaussian test matrix the range finder draws: Omega (n x l, element type
+ * of problem->dtype), from the generator contract documented in the library's
+ * design notes (Philox4x64-10, Box-Muller).  For parity tests. */
+rsvd_status rsvd_draw_omega(rsvd_handle handle, const rsvd_problem* problem,
+                            void* Omega, hipStream_t stream);
+
+/* The SRFT ingredients the range finder draws: signs d (n doubles, +-1) and the
+ * sampled frequencies R (l int32), drawing through the workspace.  For parity
+ * tests. */
+rsvd_status rsvd_draw_srft(rsvd_handle handle, const rsvd_problem* problem,
+                           double* d, int32_t* R, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* CholeskyQR2 of a tall matrix on its own: Y (rows x l, element type of
+ * problem->dtype, real) is overwritten by Q with Y = Q R; R (l x l, double,
+ * upper triangular, positive diagonal) is written if non-NULL.  Uses problem->k
+ * + problem->p as l and `rows` as the row count; needs
+ * rsvd_workspace_bytes(problem) with problem->m >= rows. */
+rsvd_status rsvd_orth(rsvd_handle handle, const rsvd_problem* problem,
+                      int64_t rows, void* Y, double* R, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* --- Kernel timing (a profiling aid) ------------------------------------ */
+
+/* Kernel families that can be timed. */
+enum {
+  RSVD_KERNEL_STREAM_NN = 0,  /* GEMMs that stream A: A X (sketch, power steps) */
+  RSVD_KERNEL_STREAM_TN = 1,  /* GEMMs that stream A: A^T X (power steps, projection) */
+  RSVD_KERNEL_SMALL_GEMM = 2, /* Y R^-1 and the lifts (K = l) */
+  RSVD_KERNEL_GRAM = 3,       /* block Gram + reduction */
+  RSVD_KERNEL_CHOL = 4,       /* l x l Cholesky with inverse */
+  RSVD_KERNEL_JACOBI = 5,     /* l x l one-sided Jacobi */
+  RSVD_KERNEL_KINDS = 6
+};
+
+/* capacity > 0: create `capacity` pairs of hipEvents (an allocation made here,
+ * never inside the hot-path calls) and bracket every later launch of the
+ * families above with two events recorded on the launch's stream, until the
+ * pairs run out.  capacity == 0: stop timing and release the events. */
+rsvd_status rsvd_profile_enable(rsvd_handle handle, int32_t capacity);
+
+/* Wait for the recorded events; for each family f write the number of timed
+ * launches to launches[f] and their summed durations (ms) to total_ms[f]
+ * (arrays of RSVD_KERNEL_KINDS host elements); then forget the records. */
+rsvd_status rsvd_profile_read(rsvd_handle handle, int32_t* launches,
+                              double* total_ms);
+
+/* Synchronizes `stream`, returns the accumulated device status bits in *flags
+ * (RSVD_FLAG_*) and clears them. */
+rsvd_status rsvd_device_status(rsvd_handle handle, hipStream_t stream,
+                               int32_t* flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSVD_H */

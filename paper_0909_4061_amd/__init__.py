@@ -1,0 +1,243 @@
+"""Randomized SVD (Halko, Martinsson, Tropp) on MI355X: Python binding of librsvd.so.
+
+The binding only marshals arguments: torch tensors supply device pointers and
+the current HIP stream, and every step of the method runs in the library's
+HIP kernels.  The C entry points (include/rsvd.h) appear here under the same
+names:
+
+    rsvd_range_finder(A, k, p, ...)      -> Q       Stage A, first application
+    rsvd_power_iter(A, Q, k, p, q, ...)  -> Q       Stage A, q power steps (in place)
+    rsvd_project(A, Q, k, p, ...)        -> Bt      Stage B step 1 (Bt = B^T, n x l)
+    rsvd_svd(Bt, Q, k, p, ...)           -> U, S, V Stage B steps 2-3 + truncation
+
+and rsvd(A, k, p, q, ...) runs all four.  If the library is missing the import
+of any of these raises; there is no other implementation.
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    RSVD_BF16, RSVD_BF16X3, RSVD_F32, RSVD_F64, RSVD_FLAG_NOCONV, RSVD_FLAG_NONFINITE,
+    RSVD_FLAG_SHIFTED, RSVD_GAUSSIAN, RSVD_MAX_L, RSVD_NATIVE, RSVD_SRFT, RsvdError, RsvdProblem,
+)
+
+PRECISIONS = {"native": RSVD_NATIVE, "bf16": RSVD_BF16, "bf16x3": RSVD_BF16X3}
+SKETCHES = {"gaussian": RSVD_GAUSSIAN, "srft": RSVD_SRFT}
+_DTYPES = {torch.float32: RSVD_F32, torch.float64: RSVD_F64}
+
+
+def problem(m, n, k, p, q=0, *, dtype=torch.float32, sketch="gaussian", prec="native", seed=0,
+            stream_id=0, lda=None):
+    """Build the C problem descriptor (a host struct)."""
+    pr = RsvdProblem()
+    pr.m, pr.n, pr.lda = int(m), int(n), int(lda if lda is not None else n)
+    pr.k, pr.p, pr.q = int(k), int(p), int(q)
+    pr.dtype = _DTYPES[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+    pr.sketch = SKETCHES[sketch] if isinstance(sketch, str) else int(sketch)
+    pr.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    pr.seed, pr.stream_id = int(seed) & (2**64 - 1), int(stream_id) & (2**64 - 1)
+    return pr
+
+
+class Handle:
+    """An rsvd_handle on one device (owns only the device status word)."""
+
+    def __init__(self, device):
+        self.lib = _lib.load()
+        self.device = int(device)
+        self.ptr = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.rsvd_create(ctypes.byref(self.ptr), self.device), "rsvd_create")
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                self.lib.rsvd_destroy(self.ptr)
+        except Exception:
+            pass
+
+
+_HANDLES = {}
+
+
+def handle(device=None):
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    if idx not in _HANDLES:
+        _HANDLES[idx] = Handle(idx)
+    return _HANDLES[idx]
+
+
+def validate(pr):
+    return int(_lib.load().rsvd_validate(ctypes.byref(pr)))
+
+
+def workspace_bytes(pr):
+    return int(_lib.load().rsvd_workspace_bytes(ctypes.byref(pr)))
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_matrix(A, name="A"):
+    if not A.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError(f"{name} must be a row-major 2-D tensor (unit column stride)")
+    if A.dtype not in _DTYPES:
+        raise ValueError(f"{name} must be float32 or float64")
+
+
+def _elem_dtype(pr, complex_out=False):
+    base = torch.float64 if pr.dtype == RSVD_F64 else torch.float32
+    if complex_out:
+        return torch.complex128 if base == torch.float64 else torch.complex64
+    return base
+
+
+class Workspace:
+    """A caller-owned workspace buffer sized for a problem (torch allocation)."""
+
+    def __init__(self, pr, device):
+        nbytes = workspace_bytes(pr)
+        if nbytes == 0:
+            raise RsvdError(validate(pr) or _lib.RSVD_E_INVAL, "rsvd_workspace_bytes")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.nbytes = nbytes
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+
+def _prob_for(A, k, p, q, sketch, prec, seed, stream_id):
+    _check_matrix(A)
+    m, n = A.shape
+    return problem(m, n, k, p, q, dtype=A.dtype, sketch=sketch, prec=prec, seed=seed,
+                   stream_id=stream_id, lda=A.stride(0))
+
+
+def rsvd_range_finder(A, k, p, *, q=0, sketch="gaussian", prec="native", seed=0, stream_id=0,
+                      Q=None, ws=None):
+    pr = _prob_for(A, k, p, q, sketch, prec, seed, stream_id)
+    l = k + p
+    cplx = pr.sketch == RSVD_SRFT
+    if Q is None:
+        Q = torch.empty(A.shape[0], l, dtype=_elem_dtype(pr, cplx), device=A.device)
+    ws = ws or Workspace(pr, A.device)
+    h = handle(A.device)
+    _lib.check(h.lib.rsvd_range_finder(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(Q), ws.ptr, ws.nbytes,
+                                       _stream(A.device)), "rsvd_range_finder")
+    return Q
+
+
+def rsvd_power_iter(A, Q, k, p, q, *, sketch="gaussian", prec="native", seed=0, stream_id=0, ws=None):
+    pr = _prob_for(A, k, p, q, sketch, prec, seed, stream_id)
+    ws = ws or Workspace(pr, A.device)
+    h = handle(A.device)
+    _lib.check(h.lib.rsvd_power_iter(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(Q), ws.ptr, ws.nbytes,
+                                     _stream(A.device)), "rsvd_power_iter")
+    return Q
+
+
+def rsvd_project(A, Q, k, p, *, q=0, sketch="gaussian", prec="native", seed=0, stream_id=0, Bt=None,
+                 ws=None):
+    pr = _prob_for(A, k, p, q, sketch, prec, seed, stream_id)
+    if Bt is None:
+        Bt = torch.empty(A.shape[1], k + p, dtype=Q.dtype, device=A.device)
+    ws = ws or Workspace(pr, A.device)
+    h = handle(A.device)
+    _lib.check(h.lib.rsvd_project(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(Q), _ptr(Bt), ws.ptr, ws.nbytes,
+                                  _stream(A.device)), "rsvd_project")
+    return Bt
+
+
+def rsvd_svd(Bt, Q, m, n, k, p, *, q=0, dtype=torch.float32, sketch="gaussian", prec="native", seed=0,
+             stream_id=0, U=None, S=None, V=None, ws=None):
+    pr = problem(m, n, k, p, q, dtype=dtype, sketch=sketch, prec=prec, seed=seed, stream_id=stream_id)
+    dev = Bt.device
+    real = _elem_dtype(pr)
+    if U is None:
+        U = torch.empty(m, k, dtype=Q.dtype, device=dev)
+    if S is None:
+        S = torch.empty(k, dtype=real, device=dev)
+    if V is None:
+        V = torch.empty(n, k, dtype=Bt.dtype, device=dev)
+    ws = ws or Workspace(pr, dev)
+    h = handle(dev)
+    _lib.check(h.lib.rsvd_svd(h.ptr, ctypes.byref(pr), _ptr(Bt), _ptr(Q), _ptr(U), _ptr(S), _ptr(V), ws.ptr,
+                              ws.nbytes, _stream(dev)), "rsvd_svd")
+    return U, S, V
+
+
+def rsvd(A, k, p=10, q=0, *, sketch="gaussian", prec="native", seed=0, stream_id=0, ws=None,
+         return_q=False):
+    """Randomized SVD of A: the four entry points in sequence.  Returns (U, S, V)."""
+    pr = _prob_for(A, k, p, q, sketch, prec, seed, stream_id)
+    ws = ws or Workspace(pr, A.device)
+    kw = dict(sketch=sketch, prec=prec, seed=seed, stream_id=stream_id, ws=ws)
+    Q = rsvd_range_finder(A, k, p, q=q, **kw)
+    rsvd_power_iter(A, Q, k, p, q, **kw)
+    Bt = rsvd_project(A, Q, k, p, q=q, **kw)
+    m, n = A.shape
+    U, S, V = rsvd_svd(Bt, Q, m, n, k, p, q=q, dtype=A.dtype, **kw)
+    if return_q:
+        return U, S, V, Q, Bt
+    return U, S, V
+
+
+def rsvd_draw_omega(n, k, p, *, dtype=torch.float32, seed=0, stream_id=0, device="cuda"):
+    """The Gaussian test matrix the range finder draws (n x (k+p))."""
+    pr = problem(max(n, k + p), n, k, p, 0, dtype=dtype, seed=seed, stream_id=stream_id)
+    Om = torch.empty(n, k + p, dtype=dtype, device=device)
+    h = handle(Om.device)
+    _lib.check(h.lib.rsvd_draw_omega(h.ptr, ctypes.byref(pr), _ptr(Om), _stream(Om.device)), "rsvd_draw_omega")
+    return Om
+
+
+def rsvd_orth(Y, want_r=True, ws=None):
+    """CholeskyQR2 of a tall Y (in place): returns (Q, R)."""
+    _check_matrix(Y, "Y")
+    rows, l = Y.shape
+    if Y.stride(0) != l:
+        raise ValueError("Y must be contiguous")
+    pr = problem(rows, l, l, 0, 0, dtype=Y.dtype)
+    ws = ws or Workspace(pr, Y.device)
+    R = torch.empty(l, l, dtype=torch.float64, device=Y.device) if want_r else None
+    h = handle(Y.device)
+    _lib.check(h.lib.rsvd_orth(h.ptr, ctypes.byref(pr), rows, _ptr(Y), _ptr(R), ws.ptr, ws.nbytes,
+                               _stream(Y.device)), "rsvd_orth")
+    return Y, R
+
+
+def device_status(device=None):
+    """Synchronize and return (and clear) the handle's RSVD_FLAG_* bits."""
+    h = handle(device)
+    flags = ctypes.c_int32(0)
+    dev = torch.device("cuda", h.device)
+    _lib.check(h.lib.rsvd_device_status(h.ptr, _stream(dev), ctypes.byref(flags)), "rsvd_device_status")
+    return int(flags.value)
+
+
+def profile_enable(capacity, device=None):
+    """Time every launch of the library's kernel families with HIP events (capacity launches)."""
+    h = handle(device)
+    _lib.check(h.lib.rsvd_profile_enable(h.ptr, int(capacity)), "rsvd_profile_enable")
+
+
+def profile_read(device=None):
+    """{family: (launches, total_ms)} since the last read; waits for the events."""
+    h = handle(device)
+    n = len(_lib.KERNEL_KINDS)
+    launches = (ctypes.c_int32 * n)()
+    ms = (ctypes.c_double * n)()
+    _lib.check(h.lib.rsvd_profile_read(h.ptr, launches, ms), "rsvd_profile_read")
+    return {name: (int(launches[i]), float(ms[i])) for i, name in enumerate(_lib.KERNEL_KINDS)}

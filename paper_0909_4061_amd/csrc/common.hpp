@@ -1,0 +1,123 @@
+// Shared declarations of the gfx950 randomized-SVD library: vector types for
+// the MFMA builtins, the parameter blocks of every kernel family, and the
+// host-side launchers that api.cpp drives.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rsvd.h"
+
+namespace rsvd {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Arithmetic of the GEMMs that stream A.
+enum Prec { PREC_NATIVE = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
+
+// ---------------------------------------------------------------------------
+// Tall-skinny GEMM: C (rows x ncols) = op(A) * X, op(A) = A (NN) or A^T (TN).
+// A is row-major with leading dimension lda.  NN: A is rows x K.  TN: A is
+// K x rows.  X is K x ncols row-major (ldx).  With S == 1 the result goes to
+// `out` (rows x ncols, ldo, element type of A).  With S > 1 the K range is split
+// into S chunks of kchunk and chunk s writes its partial product to
+// part[s][row][0..Lp) (element type of A, Lp = ncols rounded up to the tile
+// width); the partials are summed by a reduction kernel in a fixed order.
+struct GemmParams {
+  const void* A;
+  int64_t lda;
+  int64_t rows;
+  int64_t K;
+  const void* X;
+  int64_t ldx;
+  int32_t ncols;
+  int32_t Lp;
+  void* out;
+  int64_t ldo;
+  void* part;
+  int64_t kchunk;
+  int32_t S;
+  int32_t vec;          // 1: A rows (NN) / A columns (TN) allow 16-byte loads
+  const int32_t* gate;  // if non-null and *gate == 0 the kernel does nothing
+};
+
+// Tile geometry of each GEMM variant (rows of C per workgroup, K per stage).
+struct GemmTile { int bm, bk, lp_mult; };
+GemmTile gemm_tile(int dtype, int prec);
+
+hipError_t launch_gemm(int dtype, int prec, bool trans, const GemmParams& p, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Gram matrices and CholeskyQR.
+struct GramParams {
+  int32_t mode;          // GRAM_FROM_PART or GRAM_FROM_PLAIN
+  const void* part;      // S x rows x Lp partial products (mode PART)
+  int32_t S;
+  int32_t Lp;
+  const void* yin;       // rows x l (mode PLAIN), leading dimension ldy
+  void* yout;            // rows x l: reduced sum of the partials (mode PART)
+  int64_t ldy;
+  int64_t rows;
+  int32_t l;
+  int32_t Lg;            // l rounded up to 16
+  int32_t do_gram;       // 0: only reduce the partials into yout
+  double* gpart;         // nblk x Lg x Lg: upper 16x16 tiles of each block Gram
+  const int32_t* gate;
+};
+enum { GRAM_FROM_PART = 0, GRAM_FROM_PLAIN = 1 };
+constexpr int GRAM_ROWS = 64;  // rows of Y per Gram workgroup
+
+hipError_t launch_gram_partial(int dtype, const GramParams& p, hipStream_t st);
+hipError_t launch_gram_reduce(const double* gpart, int64_t nblk, int32_t Lg, double* G,
+                              int32_t* status, const int32_t* gate, hipStream_t st);
+
+struct CholParams {
+  const double* G;      // Lg x Lg, upper triangle read
+  int32_t Lg;
+  int32_t l;
+  int64_t rows;         // row count of the matrix whose Gram G is (for the shift)
+  double* R;            // l x l upper triangular, positive diagonal (may be null)
+  double* Rinv;         // l x l, R^-1 (may be null)
+  void* RinvT;          // l x l, R^-1 rounded to the element type (may be null)
+  int32_t dtype;
+  int32_t* shifted;     // set to 1 when a shift was needed (may be null)
+  int32_t* status;      // handle status word (RSVD_FLAG_*)
+  const int32_t* gate;
+};
+hipError_t launch_chol(const CholParams& p, hipStream_t st);
+
+// R = R2 * R1 for upper triangular l x l factors (FP64).
+hipError_t launch_trmm_upper(const double* R2, const double* R1, double* R, int32_t l,
+                             const int32_t* gate, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Small SVD: one-sided Jacobi on C = R^T (l x l) with R from the Cholesky of B B*.
+struct JacobiParams {
+  const double* R;      // l x l upper triangular
+  int32_t l;
+  int32_t k;
+  int32_t dtype;
+  double* Uh;           // l x l left singular vectors of R^T, by descending sigma
+  double* sig;          // l singular values, descending
+  void* XU;             // l x k: Uh[:, :k] in the element type
+  void* XV;             // l x k: Uh[:, :k] diag(1/sigma) in the element type
+  void* S;              // k singular values in the element type
+  int32_t* status;
+};
+hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Random test matrices (counter-based Philox4x64-10).
+hipError_t launch_omega(int dtype, void* omega, int64_t n, int32_t l, uint64_t seed,
+                        uint64_t stream_id, hipStream_t st);
+hipError_t launch_srft_draw(double* d, int32_t* R, int32_t* perm, int64_t n, int32_t l,
+                            uint64_t seed, uint64_t stream_id, hipStream_t st);
+
+// Small utilities.
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, const int32_t* gate, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st);
+
+}  // namespace rsvd

@@ -1,0 +1,309 @@
+// CholeskyQR building blocks: the orthonormalization "Y = QR" that follows
+// every application of A or A* in Stage A (Algorithm 4.1 step 3, Algorithm 4.4
+// steps 2, 4, 5; Section 4.1 allows any stable QR).  One CholeskyQR pass is
+//   W = Y^T Y (FP64),  W = R^T R (Cholesky),  Q = Y R^-1,
+// and CholeskyQR2 repeats it once on Q.  The host chains these kernels:
+//
+//   gram_partial : one workgroup per 64 rows.  Loads the rows of Y -- either
+//                  summing the split-K partial products of the GEMM that made
+//                  Y (in a fixed order) and storing Y, or reading a stored Y --
+//                  and forms the 64-row block Gram Y_b^T Y_b with FP64 MFMA
+//                  (FP32 entries are exact in FP64, so the products are exact).
+//                  Only the upper 16x16 tiles are computed.
+//   gram_reduce  : sums the block Grams in a fixed order (deterministic).
+//   chol         : one workgroup.  Symmetric elimination on [W | I] with the
+//                  l x l array held in registers (1024 threads, 4x4 entries
+//                  each), one barrier per column: after step j, row j holds
+//                  D L^T in its upper part and L^-1 in its lower part, which
+//                  gives R = D^-1/2 (D L^T) and R^-1 = L^-T D^-1/2 at once.
+//                  A pivot that is not safely positive restarts the
+//                  factorization on W + sI (shifted CholeskyQR) and raises a
+//                  flag; the host then runs a third pass.
+//   trmm_upper   : R = R2 R1 for the combined factor.
+#include <float.h>
+
+#include "common.hpp"
+
+namespace rsvd {
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram_partial_kernel(const GramParams p) {
+  constexpr int RB = GRAM_ROWS;
+  constexpr int YLD = 128 + 1;
+  __shared__ T Ys[RB * YLD];
+  if (p.gate && *p.gate == 0) return;
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * RB;
+  const int l = p.l, Lg = p.Lg;
+
+  // Stage the rows (zero beyond l columns / beyond the last row).
+  for (int idx = tid; idx < RB * Lg; idx += 256) {
+    const int rr = idx / Lg, c = idx - rr * Lg;
+    const int64_t row = row0 + rr;
+    T v = (T)0;
+    if (row < p.rows && c < l) {
+      if (p.mode == GRAM_FROM_PART) {
+        const T* part = (const T*)p.part;
+        T acc = (T)0;
+        for (int s = 0; s < p.S; ++s) acc += part[((int64_t)s * p.rows + row) * p.Lp + c];
+        v = acc;
+        ((T*)p.yout)[row * p.ldy + c] = v;
+      } else {
+        v = ((const T*)p.yin)[row * p.ldy + c];
+      }
+    }
+    Ys[rr * YLD + c] = v;
+  }
+  if (!p.do_gram) return;
+  __syncthreads();
+
+  // Upper 16x16 tiles of Y_b^T Y_b.  v_mfma_f64_16x16x4f64: A[i = lane%16][k =
+  // lane/16] = Y[k][16 ti + i], B[k = lane/16][j = lane%16] = Y[k][16 tj + j];
+  // result register e of lane holds G[16 ti + 4 e + lane/16][16 tj + lane%16].
+  const int lane = tid & 63, wave = tid >> 6;
+  const int nt = Lg / 16;
+  const int ntiles = nt * (nt + 1) / 2;
+  double* gout = p.gpart + (int64_t)blockIdx.x * Lg * Lg;
+  for (int tile = wave; tile < ntiles; tile += 4) {
+    int ti = 0, rem = tile;
+    while (rem >= nt - ti) {
+      rem -= nt - ti;
+      ++ti;
+    }
+    const int tj = ti + rem;
+    f64x4 acc = f64x4{};
+#pragma unroll 4
+    for (int ks = 0; ks < RB / 4; ++ks) {
+      const int kr = 4 * ks + (lane >> 4);
+      const double a = (double)Ys[kr * YLD + 16 * ti + (lane & 15)];
+      const double b = (double)Ys[kr * YLD + 16 * tj + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      gout[(int64_t)(16 * ti + 4 * e + (lane >> 4)) * Lg + 16 * tj + (lane & 15)] = acc[e];
+  }
+}
+
+// Four threads per Gram entry, each summing every fourth block Gram; the four
+// sums are combined in a fixed order.
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ gpart, int64_t nblk,
+                                                          int32_t Lg, double* __restrict__ G, int32_t* status,
+                                                          const int32_t* gate) {
+  __shared__ double red[4][64];
+  if (gate && *gate == 0) return;
+  const int tid = threadIdx.x;
+  const int q = tid >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + (tid & 63);
+  const int64_t LL = (int64_t)Lg * Lg;
+  const bool live = e < LL && (e % Lg) >= (e / Lg);  // upper triangle only
+  double acc = 0.0;
+  if (live)
+    for (int64_t b = q; b < nblk; b += 4) acc += gpart[b * LL + e];
+  red[q][tid & 63] = acc;
+  __syncthreads();
+  if (q == 0 && e < LL) {
+    const double v = live ? ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid] : 0.0;
+    G[e] = v;
+    if (live && !isfinite(v)) atomicOr(status, (int32_t)RSVD_FLAG_NONFINITE);
+  }
+}
+
+// Cholesky with simultaneous inverse.  Thread (tr, tc) of a 32 x 32 grid owns
+// W[a][c] for a = tr + 32 ia, c = tc + 32 ib (ia, ib < 4).  Entries with
+// c >= a start as W (upper), entries with c < a as the identity's zeros.
+__global__ __launch_bounds__(1024) void chol_kernel(const CholParams p) {
+  __shared__ double rowbuf[2][128];
+  __shared__ double diag[128];
+  __shared__ double red[32];
+  if (p.gate && *p.gate == 0) return;
+  const int tid = threadIdx.x;
+  const int tr = tid >> 5, tc = tid & 31;
+  const int l = p.l, Lg = p.Lg;
+
+  // max diagonal and trace of W (for the breakdown threshold and the shift)
+  double dmax = 0.0, trace = 0.0;
+  {
+    const double dv = (tid < l) ? p.G[(int64_t)tid * Lg + tid] : 0.0;
+    double m = dv, t = dv;
+    for (int off = 16; off > 0; off >>= 1) {
+      m = fmax(m, __shfl_xor(m, off, 32));
+      t += __shfl_xor(t, off, 32);
+    }
+    if (tid < 128 && (tid & 31) == 0) {
+      red[tid >> 5] = m;
+      red[4 + (tid >> 5)] = t;
+    }
+    __syncthreads();
+    for (int i = 0; i < 4; ++i) {
+      dmax = fmax(dmax, red[i]);
+      trace += red[4 + i];
+    }
+  }
+  const double eps = DBL_EPSILON;
+  const double thresh = (double)l * 16.0 * eps * dmax;
+
+  double w[4][4];
+  bool ok = false;
+  for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
+    // Shifted CholeskyQR: s = 11 (rows l + l (l + 1)) u ||Y||_F^2 with u the FP64 unit roundoff.
+    const double shift =
+        attempt == 0 ? 0.0 : 11.0 * ((double)p.rows * l + (double)l * (l + 1)) * (0.5 * eps) * trace;
+#pragma unroll
+    for (int ia = 0; ia < 4; ++ia) {
+      const int a = tr + 32 * ia;
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib) {
+        const int c = tc + 32 * ib;
+        double v = 0.0;
+        if (a < l && c < l && c >= a) v = p.G[(int64_t)a * Lg + c] + (c == a ? shift : 0.0);
+        w[ia][ib] = v;
+      }
+    }
+    if (tr == 0) {
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib) rowbuf[0][tc + 32 * ib] = w[0][ib];
+    }
+    ok = true;
+    for (int j = 0; j < l; ++j) {
+      const int buf = j & 1;
+      __syncthreads();
+      const double d = rowbuf[buf][j];
+      if (!(d > thresh) || !isfinite(d)) {  // uniform: every thread reads the same d
+        ok = false;
+        break;
+      }
+      if (tid == 0) diag[j] = d;
+      const double invd = 1.0 / d;
+#pragma unroll
+      for (int ia = 0; ia < 4; ++ia) {
+        const int a = tr + 32 * ia;
+        if (a <= j || a >= l) continue;
+        const double f = rowbuf[buf][a] * invd;
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+          const int c = tc + 32 * ib;
+          if (c >= l) continue;
+          if (c == j)
+            w[ia][ib] = -f;
+          else if (c < j || c >= a)
+            w[ia][ib] -= f * rowbuf[buf][c];
+        }
+      }
+      if (j + 1 < l && tr == ((j + 1) & 31)) {
+        const int ia = (j + 1) >> 5;
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+          double v = w[0][ib];
+          if (ia == 1) v = w[1][ib];
+          if (ia == 2) v = w[2][ib];
+          if (ia == 3) v = w[3][ib];
+          rowbuf[buf ^ 1][tc + 32 * ib] = v;
+        }
+      }
+    }
+    __syncthreads();
+    if (!ok && attempt == 0 && tid == 0) {
+      atomicOr(p.status, (int32_t)RSVD_FLAG_SHIFTED);
+      if (p.shifted) *p.shifted = 1;
+    }
+  }
+  if (!ok) {
+    // Shifted factorization failed as well (non-finite input): identity factors.
+    if (tid == 0) atomicOr(p.status, (int32_t)RSVD_FLAG_NONFINITE);
+    for (int idx = tid; idx < l * l; idx += 1024) {
+      const int a = idx / l, c = idx - a * l;
+      const double v = a == c ? 1.0 : 0.0;
+      if (p.R) p.R[idx] = v;
+      if (p.Rinv) p.Rinv[idx] = v;
+      if (p.RinvT) {
+        if (p.dtype == RSVD_F64) ((double*)p.RinvT)[idx] = v;
+        else ((float*)p.RinvT)[idx] = (float)v;
+      }
+    }
+    return;
+  }
+  // R[a][c] = W[a][c] / sqrt(d_a) (c >= a);  R^-1[c][a] = E[a][c] / sqrt(d_a) (c <= a, E[a][a] = 1).
+#pragma unroll
+  for (int ia = 0; ia < 4; ++ia) {
+    const int a = tr + 32 * ia;
+    if (a >= l) continue;
+    const double rs = 1.0 / sqrt(diag[a]);
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) {
+      const int c = tc + 32 * ib;
+      if (c >= l) continue;
+      if (p.R) p.R[(int64_t)a * l + c] = c >= a ? w[ia][ib] * rs : 0.0;
+      const double inv = c == a ? rs : (c < a ? w[ia][ib] * rs : 0.0);
+      // R^-1 is upper triangular: element (c, a) with c <= a; zeros below.
+      if (p.Rinv) p.Rinv[(int64_t)c * l + a] = inv;
+      if (p.RinvT) {
+        if (p.dtype == RSVD_F64) ((double*)p.RinvT)[(int64_t)c * l + a] = c <= a ? inv : 0.0;
+        else ((float*)p.RinvT)[(int64_t)c * l + a] = (float)(c <= a ? inv : 0.0);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void trmm_upper_kernel(const double* __restrict__ R2, const double* __restrict__ R1,
+                                                         double* __restrict__ R, int32_t l, const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)l * l) return;
+  const int i = (int)(idx / l), j = (int)(idx - (int64_t)i * l);
+  double acc = 0.0;
+  for (int t = i; t <= j; ++t) acc += R2[(int64_t)i * l + t] * R1[(int64_t)t * l + j];
+  R[idx] = acc;
+}
+
+__global__ __launch_bounds__(256) void copy_f64_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                       int64_t count, const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) dst[i] = src[i];
+}
+
+}  // namespace
+
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, const int32_t* gate, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, src, dst, count,
+                     gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_partial(int dtype, const GramParams& p, hipStream_t st) {
+  if (p.rows <= 0) return hipSuccess;
+  if (p.l > 128 || p.Lg % 16 != 0 || p.Lg < p.l) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((p.rows + GRAM_ROWS - 1) / GRAM_ROWS));
+  if (dtype == RSVD_F64)
+    hipLaunchKernelGGL(gram_partial_kernel<double>, grid, dim3(256), 0, st, p);
+  else
+    hipLaunchKernelGGL(gram_partial_kernel<float>, grid, dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_reduce(const double* gpart, int64_t nblk, int32_t Lg, double* G, int32_t* status,
+                              const int32_t* gate, hipStream_t st) {
+  const int64_t LL = (int64_t)Lg * Lg;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((LL + 63) / 64)), dim3(256), 0, st, gpart, nblk, Lg, G,
+                     status, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol(const CholParams& p, hipStream_t st) {
+  if (p.l > 128 || p.l < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(1024), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_trmm_upper(const double* R2, const double* R1, double* R, int32_t l, const int32_t* gate,
+                             hipStream_t st) {
+  const int64_t n = (int64_t)l * l;
+  hipLaunchKernelGGL(trmm_upper_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R2, R1, R, l, gate);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -1,0 +1,449 @@
+// Tall-skinny GEMMs that stream A: the sketch Y = A Omega (Algorithm 4.1,
+// step 2), the power steps A* Q and A Qt (Algorithm 4.4, steps 4-5), the
+// projection B = Q* A (Algorithm 5.1, step 1, written as Bt = A^T Q), and the
+// small right-hand products of CholeskyQR (Y R^-1) and of the lifts (Q U~).
+//
+// Every variant computes C (rows x ncols, ncols <= 128) = op(A) X with one
+// workgroup per block of `bm` rows of C and all columns of C, so each element
+// of A is read from HBM exactly once.  The contraction range K is split into
+// S chunks when the row blocks alone cannot fill the chip; the partials are
+// summed afterwards in a fixed order (deterministic, no atomics).  Workgroup b
+// takes K chunk b % S: consecutive workgroups land on different XCDs, so the
+// workgroups sharing one chunk of X run on the same XCD(s) and read it from
+// their own L2.
+//
+// Tiles are staged through LDS: a stage of A (bm x bk or bk x bm) is loaded
+// with 16-byte coalesced loads into registers while the previous stage is
+// multiplied, then written to LDS; X is staged alongside.
+//
+//   FP32  : v_mfma_f32_32x32x2f32, 4 waves x 32 rows, bk = 32.
+//   FP64  : v_mfma_f64_16x16x4f64, 4 waves x 16 rows, bk = 16.
+//   BF16  : v_mfma_f32_32x32x16_bf16, 4 waves x 32 rows, bk = 32.  A and X
+//           are split on the fly into bfloat16 a_hi = rn(a), a_lo = rn(a - a_hi);
+//           bf16x3 accumulates a_hi b_hi + a_hi b_lo + a_lo b_hi in FP32, plain
+//           BF16 only a_hi b_hi.
+#include "common.hpp"
+
+namespace rsvd {
+
+namespace {
+
+template <typename T>
+__device__ inline void load_run4(const T* base, int valid, bool vec, T out[4]);
+
+template <>
+__device__ inline void load_run4<float>(const float* base, int valid, bool vec, float out[4]) {
+  if (valid == 4 && vec) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(base);
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+    out[3] = v[3];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = (e < valid) ? base[e] : 0.f;
+  }
+}
+
+template <>
+__device__ inline void load_run4<double>(const double* base, int valid, bool vec, double out[4]) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  if (valid == 4 && vec) {
+    const d2 v0 = *reinterpret_cast<const d2*>(base);
+    const d2 v1 = *reinterpret_cast<const d2*>(base + 2);
+    out[0] = v0[0];
+    out[1] = v0[1];
+    out[2] = v1[0];
+    out[3] = v1[1];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = (e < valid) ? base[e] : 0.0;
+  }
+}
+
+__device__ inline int clamp_valid(int64_t v) { return v <= 0 ? 0 : (v >= 4 ? 4 : (int)v); }
+
+// Loads of one stage into registers, shared by the three variants.  A stage of
+// A is BM x BK (NN) or BK x BM (TN) elements, NRUN runs of four per thread;
+// X is BK x 128 elements, NX per thread.
+template <typename T, bool TRANS, int BM, int BK, int NRUN>
+__device__ inline void stage_load_a(const GemmParams& p, int64_t i0, int64_t k0, int64_t kend, int tid,
+                                    T (&ra)[NRUN * 4]) {
+  const T* A = (const T*)p.A;  // may alias p.out (in-place Y R^-1): not restrict
+  constexpr int RUNS_PER_ROW = TRANS ? BM / 4 : BK / 4;  // runs along the contiguous dimension
+  constexpr int ROWS_PER_PASS = 256 / RUNS_PER_ROW;
+#pragma unroll
+  for (int it = 0; it < NRUN; ++it) {
+    const int rr = tid / RUNS_PER_ROW + ROWS_PER_PASS * it;
+    const int cc = 4 * (tid % RUNS_PER_ROW);
+    int valid;
+    int64_t off;
+    if (!TRANS) {
+      const int64_t row = i0 + rr;
+      const int64_t kc = k0 + cc;
+      valid = row < p.rows ? clamp_valid(kend - kc) : 0;
+      off = row * p.lda + kc;
+    } else {
+      const int64_t kr = k0 + rr;
+      const int64_t col = i0 + cc;
+      valid = kr < kend ? clamp_valid(p.rows - col) : 0;
+      off = kr * p.lda + col;
+    }
+    T v[4];
+    load_run4<T>(A + (valid > 0 ? off : 0), valid, p.vec != 0, v);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ra[4 * it + e] = v[e];
+  }
+}
+
+template <typename T, int BK, int NX>
+__device__ inline void stage_load_x(const GemmParams& p, int64_t k0, int64_t kend, int tid, T (&rx)[NX]) {
+  const T* __restrict__ X = (const T*)p.X;
+#pragma unroll
+  for (int it = 0; it < NX; ++it) {
+    const int idx = tid + 256 * it;
+    const int kr = idx >> 7;
+    const int c = idx & 127;
+    const int64_t kk = k0 + kr;
+    rx[it] = (kk < kend && c < p.ncols) ? X[kk * p.ldx + c] : (T)0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32: v_mfma_f32_32x32x2f32.  Operand lanes: A[i = lane%32][k = lane/32],
+// B[k = lane/32][j = lane%32]; result register e of lane holds
+// C[8*(e/4) + 4*(lane/32) + e%4][lane%32].
+template <bool TRANS>
+__global__ __launch_bounds__(256, 2) void gemm_f32_kernel(const GemmParams p) {
+  constexpr int BM = 128, BK = 32;
+  constexpr int ALD = TRANS ? BM + 4 : BK + 1;
+  constexpr int XLD = 128 + 4;
+  __shared__ __attribute__((aligned(16))) float As[TRANS ? BK * (BM + 4) : BM * (BK + 1)];
+  __shared__ __attribute__((aligned(16))) float Xs[BK * XLD];
+  if (p.gate && *p.gate == 0) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int S = p.S;
+  const int s = blockIdx.x % S;
+  const int64_t i0 = (int64_t)(blockIdx.x / S) * BM;
+  const int64_t kbeg = (int64_t)s * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int NT = p.Lp / 32;
+
+  f32x16 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x16{};
+
+  float ra[16], rx[16];
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    stage_load_a<float, TRANS, BM, BK, 4>(p, i0, kbeg, kend, tid, ra);
+    stage_load_x<float, BK, 16>(p, kbeg, kend, tid, rx);
+  }
+  const int r = lane & 31, g = lane >> 5;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      if (!TRANS) {
+        const int rr = (tid >> 3) + 32 * it, cc = 4 * (tid & 7);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) As[rr * ALD + cc + e] = ra[4 * it + e];
+      } else {
+        const int rr = (tid >> 5) + 8 * it, cc = 4 * (tid & 31);
+        *reinterpret_cast<f32x4*>(&As[rr * ALD + cc]) =
+            f32x4{ra[4 * it], ra[4 * it + 1], ra[4 * it + 2], ra[4 * it + 3]};
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int idx = tid + 256 * it;
+      Xs[(idx >> 7) * XLD + (idx & 127)] = rx[it];
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      const int64_t k0 = kbeg + (kt + 1) * BK;
+      stage_load_a<float, TRANS, BM, BK, 4>(p, i0, k0, kend, tid, ra);
+      stage_load_x<float, BK, 16>(p, k0, kend, tid, rx);
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK / 2; ++ks) {
+      const int kl = 2 * ks + g;
+      const float a = TRANS ? As[kl * ALD + wave * 32 + r] : As[(wave * 32 + r) * ALD + kl];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < NT) {
+          const float b = Xs[kl * XLD + t * 32 + r];
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  float* out = (float*)p.out;
+  float* part = (float*)p.part;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t >= NT) continue;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int64_t row = i0 + wave * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
+      const int col = t * 32 + r;
+      if (row < p.rows) {
+        if (S == 1) {
+          if (col < p.ncols) out[row * p.ldo + col] = acc[t][e];
+        } else {
+          part[((int64_t)s * p.rows + row) * p.Lp + col] = acc[t][e];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64: v_mfma_f64_16x16x4f64.  Operand lanes: A[i = lane%16][k = lane/16],
+// B[k = lane/16][j = lane%16]; result register e of lane holds
+// C[4*e + lane/16][lane%16].
+template <bool TRANS>
+__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmParams p) {
+  constexpr int BM = 64, BK = 16;
+  constexpr int ALD = TRANS ? BM + 2 : BK + 1;
+  constexpr int XLD = 128 + 2;
+  __shared__ __attribute__((aligned(16))) double As[TRANS ? BK * (BM + 2) : BM * (BK + 1)];
+  __shared__ __attribute__((aligned(16))) double Xs[BK * XLD];
+  if (p.gate && *p.gate == 0) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int S = p.S;
+  const int s = blockIdx.x % S;
+  const int64_t i0 = (int64_t)(blockIdx.x / S) * BM;
+  const int64_t kbeg = (int64_t)s * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int NT = p.Lp / 16;
+
+  f64x4 acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = f64x4{};
+
+  double ra[4], rx[8];
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    stage_load_a<double, TRANS, BM, BK, 1>(p, i0, kbeg, kend, tid, ra);
+    stage_load_x<double, BK, 8>(p, kbeg, kend, tid, rx);
+  }
+  const int r = lane & 15, g = lane >> 4;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    if (!TRANS) {
+      const int rr = tid >> 2, cc = 4 * (tid & 3);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) As[rr * ALD + cc + e] = ra[e];
+    } else {
+      const int rr = tid >> 4, cc = 4 * (tid & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) As[rr * ALD + cc + e] = ra[e];
+    }
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int idx = tid + 256 * it;
+      Xs[(idx >> 7) * XLD + (idx & 127)] = rx[it];
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      const int64_t k0 = kbeg + (kt + 1) * BK;
+      stage_load_a<double, TRANS, BM, BK, 1>(p, i0, k0, kend, tid, ra);
+      stage_load_x<double, BK, 8>(p, k0, kend, tid, rx);
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kl = 4 * ks + g;
+      const double a = TRANS ? As[kl * ALD + wave * 16 + r] : As[(wave * 16 + r) * ALD + kl];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (t < NT) {
+          const double b = Xs[kl * XLD + t * 16 + r];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  double* out = (double*)p.out;
+  double* part = (double*)p.part;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    if (t >= NT) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = i0 + wave * 16 + 4 * e + g;
+      const int col = t * 16 + r;
+      if (row < p.rows) {
+        if (S == 1) {
+          if (col < p.ncols) out[row * p.ldo + col] = acc[t][e];
+        } else {
+          part[((int64_t)s * p.rows + row) * p.Lp + col] = acc[t][e];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 / bf16x3: v_mfma_f32_32x32x16_bf16.  Operand lanes: A[i = lane%32][k =
+// 8*(lane/32) + t], B[k = 8*(lane/32) + t][j = lane%32] for t = 0..7; result
+// layout as the FP32 32x32 instruction.  A stays FP32 in LDS and is split when
+// its fragment is read (each element is read by one wave once); X is split
+// once per stage into transposed hi/lo planes so a B fragment is one 16-byte
+// LDS read.
+template <bool TRANS, int NP>
+__global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const GemmParams p) {
+  constexpr int BM = 128, BK = 32;
+  constexpr int ALD = TRANS ? BM + 4 : BK + 4;
+  constexpr int XT = BK + 8;  // bf16 elements per transposed X column
+  __shared__ __attribute__((aligned(16))) float As[TRANS ? BK * (BM + 4) : BM * (BK + 4)];
+  __shared__ __attribute__((aligned(16))) __bf16 Xh[128 * XT];
+  __shared__ __attribute__((aligned(16))) __bf16 Xl[NP == 3 ? 128 * XT : 8];
+  if (p.gate && *p.gate == 0) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int S = p.S;
+  const int s = blockIdx.x % S;
+  const int64_t i0 = (int64_t)(blockIdx.x / S) * BM;
+  const int64_t kbeg = (int64_t)s * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int NT = p.Lp / 32;
+
+  f32x16 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x16{};
+
+  float ra[16], rx[16];
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    stage_load_a<float, TRANS, BM, BK, 4>(p, i0, kbeg, kend, tid, ra);
+    stage_load_x<float, BK, 16>(p, kbeg, kend, tid, rx);
+  }
+  const int r = lane & 31, g = lane >> 5;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      int rr, cc;
+      if (!TRANS) {
+        rr = (tid >> 3) + 32 * it;
+        cc = 4 * (tid & 7);
+      } else {
+        rr = (tid >> 5) + 8 * it;
+        cc = 4 * (tid & 31);
+      }
+      *reinterpret_cast<f32x4*>(&As[rr * ALD + cc]) =
+          f32x4{ra[4 * it], ra[4 * it + 1], ra[4 * it + 2], ra[4 * it + 3]};
+    }
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int idx = tid + 256 * it;
+      const int kr = idx >> 7, c = idx & 127;
+      const __bf16 hi = (__bf16)rx[it];
+      Xh[c * XT + kr] = hi;
+      if (NP == 3) Xl[c * XT + kr] = (__bf16)(rx[it] - (float)hi);
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      const int64_t k0 = kbeg + (kt + 1) * BK;
+      stage_load_a<float, TRANS, BM, BK, 4>(p, i0, k0, kend, tid, ra);
+      stage_load_x<float, BK, 16>(p, k0, kend, tid, rx);
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ++ks) {
+      const int kb = 16 * ks + 8 * g;
+      float av[8];
+      if (!TRANS) {
+        const f32x4 v0 = *reinterpret_cast<const f32x4*>(&As[(wave * 32 + r) * ALD + kb]);
+        const f32x4 v1 = *reinterpret_cast<const f32x4*>(&As[(wave * 32 + r) * ALD + kb + 4]);
+        av[0] = v0[0]; av[1] = v0[1]; av[2] = v0[2]; av[3] = v0[3];
+        av[4] = v1[0]; av[5] = v1[1]; av[6] = v1[2]; av[7] = v1[3];
+      } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) av[t] = As[(kb + t) * ALD + wave * 32 + r];
+      }
+      bf16x8 ahi, alo;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        ahi[t] = (__bf16)av[t];
+        if (NP == 3) alo[t] = (__bf16)(av[t] - (float)ahi[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < NT) {
+          const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&Xh[(t * 32 + r) * XT + kb]);
+          if (NP == 3) {
+            const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&Xl[(t * 32 + r) * XT + kb]);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, acc[t], 0, 0, 0);
+          }
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  float* out = (float*)p.out;
+  float* part = (float*)p.part;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t >= NT) continue;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int64_t row = i0 + wave * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
+      const int col = t * 32 + r;
+      if (row < p.rows) {
+        if (S == 1) {
+          if (col < p.ncols) out[row * p.ldo + col] = acc[t][e];
+        } else {
+          part[((int64_t)s * p.rows + row) * p.Lp + col] = acc[t][e];
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+GemmTile gemm_tile(int dtype, int prec) {
+  if (dtype == RSVD_F64) return GemmTile{64, 16, 16};
+  (void)prec;
+  return GemmTile{128, 32, 32};
+}
+
+hipError_t launch_gemm(int dtype, int prec, bool trans, const GemmParams& p, hipStream_t st) {
+  const GemmTile tile = gemm_tile(dtype, prec);
+  if (p.rows <= 0) return hipSuccess;
+  if (p.ncols > 128 || p.Lp > 128 || p.Lp % tile.lp_mult != 0 || p.Lp < p.ncols || p.S < 1)
+    return hipErrorInvalidValue;
+  const int64_t nrb = (p.rows + tile.bm - 1) / tile.bm;
+  const dim3 grid((unsigned)(nrb * p.S)), block(256);
+  if (dtype == RSVD_F64) {
+    if (trans)
+      hipLaunchKernelGGL(gemm_f64_kernel<true>, grid, block, 0, st, p);
+    else
+      hipLaunchKernelGGL(gemm_f64_kernel<false>, grid, block, 0, st, p);
+  } else if (prec == PREC_BF16X3) {
+    if (trans)
+      hipLaunchKernelGGL((gemm_bf16_kernel<true, 3>), grid, block, 0, st, p);
+    else
+      hipLaunchKernelGGL((gemm_bf16_kernel<false, 3>), grid, block, 0, st, p);
+  } else if (prec == PREC_BF16) {
+    if (trans)
+      hipLaunchKernelGGL((gemm_bf16_kernel<true, 1>), grid, block, 0, st, p);
+    else
+      hipLaunchKernelGGL((gemm_bf16_kernel<false, 1>), grid, block, 0, st, p);
+  } else {
+    if (trans)
+      hipLaunchKernelGGL(gemm_f32_kernel<true>, grid, block, 0, st, p);
+    else
+      hipLaunchKernelGGL(gemm_f32_kernel<false>, grid, block, 0, st, p);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

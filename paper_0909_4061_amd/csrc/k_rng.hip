@@ -1,0 +1,103 @@
+// Random test matrices of Stage A, drawn on the device.
+//
+// Gaussian Omega (Algorithm 4.1, step 1): one thread per quad of four
+// horizontally adjacent entries, one Philox4x64-10 call per quad, Box-Muller
+// on the two uniform pairs.  Entries are formed in FP64 and rounded once to
+// the element type.
+//
+// SRFT (Section 4.6): the diagonal D of random +-1 signs (one thread per
+// coordinate) and the sampler R of l coordinates drawn without replacement by
+// a partial Fisher-Yates shuffle (a single thread: l swaps on a permutation
+// initialised in parallel).
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace rsvd {
+
+namespace {
+
+constexpr double kTwoPi = 0x1.921fb54442d18p+2;  // the double nearest 2*pi
+
+template <typename T>
+__global__ __launch_bounds__(256) void omega_kernel(T* __restrict__ omega, int64_t n, int32_t l,
+                                                    uint64_t seed, uint64_t sid) {
+  const int32_t qpr = (l + 3) / 4;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * qpr) return;
+  const int64_t i = t / qpr;
+  const int32_t j0 = (int32_t)(t - i * qpr) * 4;
+  const Philox4 w = philox4x64_10((uint64_t)t, sid, 0ull, 0ull, seed, 0ull);
+  const double u0 = philox_uniform(w.w[0]), u1 = philox_uniform(w.w[1]);
+  const double u2 = philox_uniform(w.w[2]), u3 = philox_uniform(w.w[3]);
+  const double r01 = sqrt(-2.0 * log(u0));
+  const double r23 = sqrt(-2.0 * log(u2));
+  const double th01 = kTwoPi * u1;
+  const double th23 = kTwoPi * u3;
+  double g[4];
+  g[0] = r01 * cos(th01);
+  g[1] = r01 * sin(th01);
+  g[2] = r23 * cos(th23);
+  g[3] = r23 * sin(th23);
+  T* row = omega + i * l;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (j0 + r < l) row[j0 + r] = (T)g[r];
+}
+
+__global__ __launch_bounds__(256) void srft_signs_kernel(double* __restrict__ d, int32_t* __restrict__ perm,
+                                                         int64_t n, uint64_t seed, uint64_t sid) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const Philox4 w = philox4x64_10((uint64_t)p, sid, 1ull, 0ull, seed, 0ull);
+  d[p] = 1.0 - 2.0 * (double)(w.w[0] & 1ull);
+  perm[p] = (int32_t)p;
+}
+
+__global__ void srft_sample_kernel(int32_t* __restrict__ R, int32_t* __restrict__ perm, int64_t n,
+                                   int32_t l, uint64_t seed, uint64_t sid) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int32_t t = 0; t < l; ++t) {
+    const Philox4 w = philox4x64_10((uint64_t)t, sid, 2ull, 0ull, seed, 0ull);
+    const double u = philox_uniform(w.w[0]);
+    int64_t j = (int64_t)t + (int64_t)floor(u * (double)(n - t));
+    if (j > n - 1) j = n - 1;
+    const int32_t a = perm[t];
+    perm[t] = perm[j];
+    perm[j] = a;
+    R[t] = perm[t];
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int32_t v, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_omega(int dtype, void* omega, int64_t n, int32_t l, uint64_t seed, uint64_t sid,
+                        hipStream_t st) {
+  const int64_t quads = n * ((l + 3) / 4);
+  const dim3 grid((unsigned)((quads + 255) / 256));
+  if (dtype == RSVD_F64)
+    hipLaunchKernelGGL(omega_kernel<double>, grid, dim3(256), 0, st, (double*)omega, n, l, seed, sid);
+  else
+    hipLaunchKernelGGL(omega_kernel<float>, grid, dim3(256), 0, st, (float*)omega, n, l, seed, sid);
+  return hipGetLastError();
+}
+
+hipError_t launch_srft_draw(double* d, int32_t* R, int32_t* perm, int64_t n, int32_t l, uint64_t seed,
+                            uint64_t sid, hipStream_t st) {
+  hipLaunchKernelGGL(srft_signs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, perm, n,
+                     seed, sid);
+  hipLaunchKernelGGL(srft_sample_kernel, dim3(1), dim3(64), 0, st, R, perm, n, l, seed, sid);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, v, count);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -1,0 +1,155 @@
+// The SVD of the small matrix B (Algorithm 5.1, step 2), in FP64.
+//
+// The host first forms the l x l Gram B B* and its Cholesky factor R (so that
+// R^T R = B B*).  The left singular vectors and singular values of B are those
+// of C = R^T:  C C^T = R^T R = B B*.  One-sided (Hestenes) Jacobi rotates pairs
+// of columns of C until all columns are mutually orthogonal; then C J = U~ S,
+// so U~ = normalized columns and S = column norms.  The right factor J is not
+// needed: the right singular vectors follow as V = B* U~ S^-1, computed by the
+// lift GEMM (B* is the stored Bt).
+//
+// One workgroup of 1024 threads holds C column-major in LDS.  Each round of a
+// sweep rotates l/2 disjoint column pairs chosen by the round-robin (circle)
+// ordering, one pair per 16-lane group; a sweep is l - 1 rounds (l rounded up
+// to even, with a zero column when l is odd), so every pair meets once.  A
+// pair is rotated when |c_i . c_j| > tol sqrt(|c_i|^2 |c_j|^2); the workgroup
+// stops after a sweep with no rotation.
+#include <float.h>
+
+#include "common.hpp"
+
+namespace rsvd {
+
+namespace {
+
+constexpr int JAC_MAXL = 128;
+constexpr int JAC_LDC = JAC_MAXL + 1;
+constexpr int JAC_MAX_SWEEPS = 40;
+
+__device__ inline double group16_sum(double v) {
+  v += __shfl_xor(v, 8, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 1, 16);
+  return v;
+}
+
+__global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
+  __shared__ double Cs[JAC_MAXL * JAC_LDC];  // column c at Cs[c * JAC_LDC + row]
+  __shared__ double sig_s[JAC_MAXL];
+  __shared__ int rank_s[JAC_MAXL];
+  __shared__ int rotated;
+  const int tid = threadIdx.x;
+  const int l = p.l;
+  const int le = l + (l & 1);
+  const int P = le / 2;
+
+  // column c of C = R^T is row c of R
+  for (int idx = tid; idx < le * JAC_LDC; idx += 1024) {
+    const int c = idx / JAC_LDC, i = idx - c * JAC_LDC;
+    Cs[idx] = (c < l && i < l) ? p.R[(int64_t)c * l + i] : 0.0;
+  }
+  if (tid == 0) rotated = 1;
+  __syncthreads();
+
+  const int grp = tid >> 4, gl = tid & 15;
+  const double tol = (double)l * DBL_EPSILON;
+  int sweep = 0;
+  for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    if (rotated == 0) break;  // read after the barrier that ended the last sweep
+    __syncthreads();
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    int any = 0;
+    for (int rnd = 0; rnd < le - 1; ++rnd) {
+      if (grp < P) {
+        // positions grp and le-1-grp; column at position x is 0 for x == 0,
+        // else 1 + (x - 1 + rnd) mod (le - 1)
+        const int xa = grp, xb = le - 1 - grp;
+        const int ca = xa == 0 ? 0 : 1 + (xa - 1 + rnd) % (le - 1);
+        const int cb = 1 + (xb - 1 + rnd) % (le - 1);
+        double* col_a = Cs + ca * JAC_LDC;
+        double* col_b = Cs + cb * JAC_LDC;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = gl; i < l; i += 16) {
+          const double x = col_a[i], y = col_b[i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        al = group16_sum(al);
+        be = group16_sum(be);
+        ga = group16_sum(ga);
+        if (ca < l && cb < l && fabs(ga) > tol * sqrt(al * be) && al > 0.0 && be > 0.0) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t);
+          const double sn = cs * t;
+          for (int i = gl; i < l; i += 16) {
+            const double x = col_a[i], y = col_b[i];
+            col_a[i] = cs * x - sn * y;
+            col_b[i] = sn * x + cs * y;
+          }
+          any = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (any) rotated = 1;  // benign race: every writer stores 1
+    __syncthreads();
+  }
+  if (tid == 0 && sweep >= JAC_MAX_SWEEPS && rotated) atomicOr(p.status, (int32_t)RSVD_FLAG_NOCONV);
+
+  // singular values = column norms; rank by descending value (ties: lower index first)
+  if (tid < l) {
+    double s2 = 0.0;
+    for (int i = 0; i < l; ++i) s2 += Cs[tid * JAC_LDC + i] * Cs[tid * JAC_LDC + i];
+    sig_s[tid] = sqrt(s2);
+  }
+  __syncthreads();
+  if (tid < l) {
+    const double me = sig_s[tid];
+    int rk = 0;
+    for (int c = 0; c < l; ++c) {
+      const double o = sig_s[c];
+      rk += (o > me) || (o == me && c < tid);
+    }
+    rank_s[tid] = rk;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < l * l; idx += 1024) {
+    const int c = idx / l, i = idx - c * l;  // element i of column c
+    const int rk = rank_s[c];
+    const double sg = sig_s[c];
+    const double u = sg > 0.0 ? Cs[c * JAC_LDC + i] / sg : 0.0;
+    p.Uh[(int64_t)i * l + rk] = u;
+    if (rk < p.k) {
+      const double v = sg > 0.0 ? u / sg : 0.0;
+      if (p.dtype == RSVD_F64) {
+        ((double*)p.XU)[(int64_t)i * p.k + rk] = u;
+        ((double*)p.XV)[(int64_t)i * p.k + rk] = v;
+      } else {
+        ((float*)p.XU)[(int64_t)i * p.k + rk] = (float)u;
+        ((float*)p.XV)[(int64_t)i * p.k + rk] = (float)v;
+      }
+    }
+  }
+  if (tid < l) {
+    const int rk = rank_s[tid];
+    p.sig[rk] = sig_s[tid];
+    if (rk < p.k) {
+      if (p.dtype == RSVD_F64) ((double*)p.S)[rk] = sig_s[tid];
+      else ((float*)p.S)[rk] = (float)sig_s[tid];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st) {
+  if (p.l < 1 || p.l > JAC_MAXL || p.k < 1 || p.k > p.l) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, st, p);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -1,0 +1,104 @@
+"""Host-only checks of the C ABI (no GPU): the library loads, exports every
+symbol include/rsvd.h declares, and validates problems before any launch."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsvd.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_0909_4061_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:rsvd_status|size_t|const char\*)\s+(rsvd_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_hot_path():
+    names = declared_functions()
+    for n in ("rsvd_range_finder", "rsvd_power_iter", "rsvd_project", "rsvd_svd"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_0909_4061_amd import _lib
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    for n in names:
+        assert hasattr(lib, n), f"{n} not exported"
+    assert sorted(_lib.EXPORTS) == names
+
+
+def _prob(**kw):
+    from paper_0909_4061_amd import problem
+    import torch
+    base = dict(m=2000, n=1000, k=20, p=10, q=0, dtype=torch.float64)
+    base.update(kw)
+    m, n, k, p, q = (base.pop(x) for x in ("m", "n", "k", "p", "q"))
+    return problem(m, n, k, p, q, **base)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    ({}, 0),
+    ({"k": 0}, 1),
+    ({"p": -1}, 1),
+    ({"q": -1}, 1),
+    ({"k": 995, "p": 10}, 1),            # l > min(m, n)
+    ({"m": 0}, 1),
+    ({"lda": 999}, 1),                    # lda < n
+    ({"k": 120, "p": 9}, 4),              # l = 129 > RSVD_MAX_L
+    ({"prec": "bf16x3"}, 4),              # BF16 arithmetic needs FP32 data
+    ({"k": 128, "p": 0}, 0),
+    ({"k": 1, "p": 0}, 0),
+])
+def test_validate(lib, kw, expect):
+    import torch
+    if kw.get("prec"):
+        pr = _prob(**kw)
+    else:
+        pr = _prob(**kw)
+    assert lib.rsvd_validate(ctypes.byref(pr)) == expect
+    ws = lib.rsvd_workspace_bytes(ctypes.byref(pr))
+    assert (ws > 0) == (expect == 0)
+    _ = torch
+
+
+def test_bad_enum_is_invalid(lib):
+    pr = _prob()
+    pr.dtype = 7
+    assert lib.rsvd_validate(ctypes.byref(pr)) == 1
+    assert lib.rsvd_validate(None) == 1
+
+
+def test_workspace_grows_with_m(lib):
+    small = lib.rsvd_workspace_bytes(ctypes.byref(_prob(m=2000)))
+    big = lib.rsvd_workspace_bytes(ctypes.byref(_prob(m=20000)))
+    assert big > small > 0
+
+
+def test_status_strings(lib):
+    for s in range(8):
+        assert lib.rsvd_status_string(s)
+    assert b"unknown" in lib.rsvd_status_string(99)
+
+
+def test_null_arguments_fail_before_launch(lib):
+    pr = _prob()
+    # no handle: rejected on the host, nothing touches a device
+    assert lib.rsvd_range_finder(None, ctypes.byref(pr), None, None, None, 0, None) == 1
+    assert lib.rsvd_power_iter(None, ctypes.byref(pr), None, None, None, 0, None) == 1
+    assert lib.rsvd_project(None, ctypes.byref(pr), None, None, None, None, 0, None) == 1
+    assert lib.rsvd_svd(None, ctypes.byref(pr), None, None, None, None, None, None, 0, None) == 1
+    assert lib.rsvd_device_status(None, None, None) == 1
+    assert lib.rsvd_create(None, 0) == 1
