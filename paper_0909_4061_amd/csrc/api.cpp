@@ -52,7 +52,7 @@ struct Plan {
   int esize;
   int dtype, prec;
   Split nn, tn;
-  size_t omega, part, Y, Qt, gpart, G, R1, R2, R3, Rt, Rinv, RinvT, XU, XV, Uh, sig, flags, srft_perm, total;
+  size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rinv, RinvT, XU, XV, Uh, sig, flags, srft_perm, total;
 };
 
 bool valid_enum(int32_t v, int32_t lo, int32_t hi) { return v >= lo && v <= hi; }
@@ -102,6 +102,7 @@ Plan make_plan(const rsvd_problem* pr) {
   P.part = take((size_t)part_elems * es);
   P.Y = take((size_t)P.Mx * P.l * es);
   P.Qt = take((size_t)P.n * P.l * es);
+  P.pack = take(pr->dtype == RSVD_F32 ? (size_t)stream_pack_bytes(P.Mx, P.Lp) : 0);
   P.gpart = take((size_t)ceil_div(P.Mx, GRAM_ROWS) * P.Lg * P.Lg * 8);
   P.G = take((size_t)P.Lg * P.Lg * 8);
   P.R1 = take(ll8);
@@ -161,7 +162,7 @@ struct Timed {
 // the result is left as partial products; otherwise it is written to `out`.
 rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda, int64_t rows, int64_t K,
                  const void* X, int64_t ldx, int32_t ncols, void* out, int64_t ldo, const Split& sp, void* part,
-                 const int32_t* gate) {
+                 const int32_t* gate, bool streams_a = false) {
   const GemmTile t = gemm_tile(c.P.dtype, prec);
   GemmParams g{};
   g.A = A;
@@ -181,9 +182,13 @@ rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda,
   g.vec = (lda % vec_mult == 0 && aligned16(A)) ? 1 : 0;
   g.gate = gate;
   if (g.S > 1 && !part) return RSVD_E_INVAL;
-  const bool streams_a = K > c.P.l;  // the big GEMMs contract over m or n; the small ones over l
   Timed t_(c.h, streams_a ? (trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN) : RSVD_KERNEL_SMALL_GEMM, c.st);
-  RSVD_TRY(launch_gemm(c.P.dtype, prec, trans, g, c.st));
+  if (streams_a && c.P.dtype == RSVD_F32) {
+    g.Lp = (int32_t)round_up(ncols, 32);
+    RSVD_TRY(launch_stream_gemm(prec, trans, g, c.at<void>(c.P.pack), c.st));
+  } else {
+    RSVD_TRY(launch_gemm(c.P.dtype, prec, trans, g, c.st));
+  }
   return RSVD_OK;
 }
 
@@ -269,7 +274,7 @@ rsvd_status apply_and_orth(const Ctx& c, const rsvd_problem* pr, bool trans, con
   const int64_t K = trans ? P.m : P.n;
   void* y = c.at<void>(P.Y);
   rsvd_status s = gemm(c, pr->prec, trans, A, pr->lda, rows, K, X, P.l, (int32_t)P.l, y, P.l, sp,
-                       sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr);
+                       sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
   if (s != RSVD_OK) return s;
   return orth(c, sp.S > 1, sp, y, rows, Q, nullptr);
 }
@@ -416,7 +421,7 @@ rsvd_status rsvd_project(rsvd_handle h, const rsvd_problem* pr, const void* A, c
   const Plan& P = c.P;
   const Split& sp = P.tn;
   rsvd_status s = gemm(c, pr->prec, true, A, pr->lda, P.n, P.m, Q, P.l, (int32_t)P.l, Bt, P.l, sp,
-                       sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr);
+                       sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
   if (s != RSVD_OK || sp.S == 1) return s;
   GramParams g{};
   g.mode = GRAM_FROM_PART;

@@ -11,11 +11,12 @@
 //                  (FP32 entries are exact in FP64, so the products are exact).
 //                  Only the upper 16x16 tiles are computed.
 //   gram_reduce  : sums the block Grams in a fixed order (deterministic).
-//   chol         : one workgroup.  Symmetric elimination on [W | I] with the
-//                  l x l array held in registers (1024 threads, 4x4 entries
-//                  each), one barrier per column: after step j, row j holds
-//                  D L^T in its upper part and L^-1 in its lower part, which
-//                  gives R = D^-1/2 (D L^T) and R^-1 = L^-T D^-1/2 at once.
+//   chol         : one workgroup.  Symmetric elimination of W with the same
+//                  row operations applied to the identity, both l x l arrays
+//                  held in registers (1024 threads, 4x4 entries each), one
+//                  barrier per column: the eliminated W is D L^T and the
+//                  accumulated operations are L^-1, which gives
+//                  R = D^-1/2 (D L^T) and R^-1 = L^-T D^-1/2 at once.
 //                  A pivot that is not safely positive restarts the
 //                  factorization on W + sI (shifted CholeskyQR) and raises a
 //                  flag; the host then runs a third pass.
@@ -38,23 +39,42 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramParams p) {
   const int64_t row0 = (int64_t)blockIdx.x * RB;
   const int l = p.l, Lg = p.Lg;
 
-  // Stage the rows (zero beyond l columns / beyond the last row).
-  for (int idx = tid; idx < RB * Lg; idx += 256) {
-    const int rr = idx / Lg, c = idx - rr * Lg;
-    const int64_t row = row0 + rr;
-    T v = (T)0;
-    if (row < p.rows && c < l) {
-      if (p.mode == GRAM_FROM_PART) {
-        const T* part = (const T*)p.part;
-        T acc = (T)0;
-        for (int s = 0; s < p.S; ++s) acc += part[((int64_t)s * p.rows + row) * p.Lp + c];
-        v = acc;
-        ((T*)p.yout)[row * p.ldy + c] = v;
-      } else {
-        v = ((const T*)p.yin)[row * p.ldy + c];
+  // Stage the rows (zero beyond l columns / beyond the last row).  Thread
+  // tid covers column tid % 128 of rows tid / 128 + 2 it; every load of the
+  // stage is issued before the first is used.
+  constexpr int ITER = RB * 128 / 256;
+  T vals[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) vals[it] = (T)0;
+  const int c = tid & 127;
+  const int rbase = tid >> 7;
+  if (p.mode == GRAM_FROM_PART) {
+    const T* __restrict__ part = (const T*)p.part;
+    for (int s = 0; s < p.S; ++s) {
+      const T* __restrict__ ps = part + (int64_t)s * p.rows * p.Lp;
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        const int64_t row = row0 + rbase + 2 * it;
+        if (row < p.rows && c < l) vals[it] += ps[row * p.Lp + c];
       }
     }
-    Ys[rr * YLD + c] = v;
+    T* __restrict__ yout = (T*)p.yout;
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int64_t row = row0 + rbase + 2 * it;
+      if (row < p.rows && c < l) yout[row * p.ldy + c] = vals[it];
+    }
+  } else {
+    const T* __restrict__ yin = (const T*)p.yin;
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int64_t row = row0 + rbase + 2 * it;
+      if (row < p.rows && c < l) vals[it] = yin[row * p.ldy + c];
+    }
+  }
+  if (c < Lg) {
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) Ys[(rbase + 2 * it) * YLD + c] = vals[it];
   }
   if (!p.do_gram) return;
   __syncthreads();
@@ -112,15 +132,24 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
 }
 
 // Cholesky with simultaneous inverse.  Thread (tr, tc) of a 32 x 32 grid owns
-// W[a][c] for a = tr + 32 ia, c = tc + 32 ib (ia, ib < 4).  Entries with
-// c >= a start as W (upper), entries with c < a as the identity's zeros.
+// the entries (a, c), a = tr + 32 ia, c = tc + 32 ib (ia, ib < 4), of two
+// register tiles: U (the eliminated matrix; only c >= a is meaningful) and E
+// (the accumulated row operations, E = L^-1, lower triangular with unit
+// diagonal).  Step j subtracts f_a = U[j][a] / U[j][j] times the pivot row from
+// every row a > j: U[a][c] -= f_a U[j][c] for c > j and E[a][c] -= f_a E[j][c]
+// for c <= j (E[j][j] = 1).  The masks fold into the multipliers, so each
+// element costs two FMAs; waves whose rows are all finished skip the update.
+// At the end U = D L^T, hence R = D^-1/2 U and R^-1 = E^T D^-1/2.
 __global__ __launch_bounds__(1024) void chol_kernel(const CholParams p) {
+  constexpr int TLD = 129;
   __shared__ double rowbuf[2][128];
   __shared__ double diag[128];
   __shared__ double red[32];
+  __shared__ double tbuf[128 * TLD];
   if (p.gate && *p.gate == 0) return;
   const int tid = threadIdx.x;
   const int tr = tid >> 5, tc = tid & 31;
+  const int wave_row_max = (tid >> 6) * 2 + 1;  // largest tr in this wave
   const int l = p.l, Lg = p.Lg;
 
   // max diagonal and trace of W (for the breakdown threshold and the shift)
@@ -145,7 +174,7 @@ __global__ __launch_bounds__(1024) void chol_kernel(const CholParams p) {
   const double eps = DBL_EPSILON;
   const double thresh = (double)l * 16.0 * eps * dmax;
 
-  double w[4][4];
+  double U[4][4], E[4][4];
   bool ok = false;
   for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
     // Shifted CholeskyQR: s = 11 (rows l + l (l + 1)) u ||Y||_F^2 with u the FP64 unit roundoff.
@@ -159,48 +188,58 @@ __global__ __launch_bounds__(1024) void chol_kernel(const CholParams p) {
         const int c = tc + 32 * ib;
         double v = 0.0;
         if (a < l && c < l && c >= a) v = p.G[(int64_t)a * Lg + c] + (c == a ? shift : 0.0);
-        w[ia][ib] = v;
+        U[ia][ib] = v;
+        E[ia][ib] = 0.0;
       }
     }
     if (tr == 0) {
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib) rowbuf[0][tc + 32 * ib] = w[0][ib];
+      for (int ib = 0; ib < 4; ++ib) rowbuf[0][tc + 32 * ib] = U[0][ib];
     }
     ok = true;
     for (int j = 0; j < l; ++j) {
       const int buf = j & 1;
       __syncthreads();
       const double d = rowbuf[buf][j];
+      double prow[4], pcol[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        prow[i] = rowbuf[buf][tr + 32 * i];
+        pcol[i] = rowbuf[buf][tc + 32 * i];
+      }
       if (!(d > thresh) || !isfinite(d)) {  // uniform: every thread reads the same d
         ok = false;
         break;
       }
       if (tid == 0) diag[j] = d;
       const double invd = 1.0 / d;
+      double pu[4], pe[4];
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib) {
+        const int c = tc + 32 * ib;
+        pu[ib] = c > j ? pcol[ib] : 0.0;
+        pe[ib] = c < j ? pcol[ib] : (c == j ? 1.0 : 0.0);
+      }
 #pragma unroll
       for (int ia = 0; ia < 4; ++ia) {
+        if (wave_row_max + 32 * ia <= j) continue;  // wave-uniform: no live row in this block
         const int a = tr + 32 * ia;
-        if (a <= j || a >= l) continue;
-        const double f = rowbuf[buf][a] * invd;
+        const double f = (a > j && a < l) ? prow[ia] * invd : 0.0;
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib) {
-          const int c = tc + 32 * ib;
-          if (c >= l) continue;
-          if (c == j)
-            w[ia][ib] = -f;
-          else if (c < j || c >= a)
-            w[ia][ib] -= f * rowbuf[buf][c];
+          U[ia][ib] -= f * pu[ib];
+          E[ia][ib] -= f * pe[ib];
         }
       }
-      if (j + 1 < l && tr == ((j + 1) & 31)) {
-        const int ia = (j + 1) >> 5;
+      // the owners of row j + 1 publish it: U part right of the diagonal, E part left
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-          double v = w[0][ib];
-          if (ia == 1) v = w[1][ib];
-          if (ia == 2) v = w[2][ib];
-          if (ia == 3) v = w[3][ib];
-          rowbuf[buf ^ 1][tc + 32 * ib] = v;
+      for (int ia = 0; ia < 4; ++ia) {
+        if (tr + 32 * ia == j + 1) {
+#pragma unroll
+          for (int ib = 0; ib < 4; ++ib) {
+            const int c = tc + 32 * ib;
+            rowbuf[buf ^ 1][c] = c >= j + 1 ? U[ia][ib] : E[ia][ib];
+          }
         }
       }
     }
@@ -225,7 +264,8 @@ __global__ __launch_bounds__(1024) void chol_kernel(const CholParams p) {
     }
     return;
   }
-  // R[a][c] = W[a][c] / sqrt(d_a) (c >= a);  R^-1[c][a] = E[a][c] / sqrt(d_a) (c <= a, E[a][a] = 1).
+  // R[a][c] = U[a][c] / sqrt(d_a) for c >= a (coalesced: consecutive threads, consecutive c).
+  // R^-1[c][a] = E[a][c] / sqrt(d_a) for c <= a: transposed through LDS.
 #pragma unroll
   for (int ia = 0; ia < 4; ++ia) {
     const int a = tr + 32 * ia;
@@ -235,14 +275,18 @@ __global__ __launch_bounds__(1024) void chol_kernel(const CholParams p) {
     for (int ib = 0; ib < 4; ++ib) {
       const int c = tc + 32 * ib;
       if (c >= l) continue;
-      if (p.R) p.R[(int64_t)a * l + c] = c >= a ? w[ia][ib] * rs : 0.0;
-      const double inv = c == a ? rs : (c < a ? w[ia][ib] * rs : 0.0);
-      // R^-1 is upper triangular: element (c, a) with c <= a; zeros below.
-      if (p.Rinv) p.Rinv[(int64_t)c * l + a] = inv;
-      if (p.RinvT) {
-        if (p.dtype == RSVD_F64) ((double*)p.RinvT)[(int64_t)c * l + a] = c <= a ? inv : 0.0;
-        else ((float*)p.RinvT)[(int64_t)c * l + a] = (float)(c <= a ? inv : 0.0);
-      }
+      if (p.R) p.R[(int64_t)a * l + c] = c >= a ? U[ia][ib] * rs : 0.0;
+      tbuf[c * TLD + a] = c == a ? rs : (c < a ? E[ia][ib] * rs : 0.0);
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < l * l; idx += 1024) {
+    const int row = idx / l, col = idx - row * l;
+    const double v = tbuf[row * TLD + col];
+    if (p.Rinv) p.Rinv[idx] = v;
+    if (p.RinvT) {
+      if (p.dtype == RSVD_F64) ((double*)p.RinvT)[idx] = v;
+      else ((float*)p.RinvT)[idx] = (float)v;
     }
   }
 }

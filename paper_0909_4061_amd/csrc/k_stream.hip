@@ -1,0 +1,450 @@
+// The GEMMs that stream A through HBM: Y = A X (sketch and power steps,
+// Algorithm 4.1 step 2, Algorithm 4.4 step 5) and Z = A^T X (power steps and
+// projection, Algorithm 4.4 step 4, Algorithm 5.1 step 1), in FP32 (FP32 MFMA)
+// or BF16 / bf16x3 (BF16 MFMA, FP32 accumulation).
+//
+// Layout of the work.  C (rows x ncols, ncols <= 128) is cut into blocks of
+// 128 rows; a workgroup of two waves computes one block over one chunk of the
+// contraction range, each wave a 64 x 128 tile (2 x 4 MFMA tiles of 32 x 32),
+// so every A fragment feeds four MFMAs and every X fragment two.  Chunks of K
+// are split across workgroups when the row blocks alone cannot fill the chip;
+// workgroup b takes chunk b % S, which spreads one chunk's X over a subset of
+// XCDs, and the partial products are summed afterwards in a fixed order.
+//
+// X is packed once per call by pack_x: zero-padded to Lp columns and a
+// multiple of 32 rows, and for BF16 split into hi/lo planes stored as 32-row
+// tiles with K contiguous per column -- the layout of the LDS stage -- so a
+// stage of X is a straight 16-byte copy.  A is loaded with 16-byte loads into
+// registers two stages ahead (enough bytes in flight per CU to cover HBM
+// latency), then written to LDS: FP32 as is, BF16 split into a_hi = rn(a),
+// a_lo = rn(a - a_hi) with K contiguous per row (for A^T the 4 x 4 register
+// block is transposed first).  LDS is double-buffered: one barrier per stage.
+#include "common.hpp"
+
+namespace rsvd {
+
+namespace {
+
+constexpr int SBM = 128;       // rows of C per workgroup
+constexpr int SBK = 32;        // K per stage
+constexpr int STHREADS = 128;  // two waves
+constexpr int BPAD = 40;       // bf16 elements per LDS row (32 + 8 pad)
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ---- pack X -----------------------------------------------------------
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void pack_x_kernel(const float* __restrict__ X, int64_t K, int64_t ldx,
+                                                     int32_t ncols, int32_t Lp, int64_t Kpad, void* __restrict__ out,
+                                                     const int32_t* gate) {
+  if (gate && *gate == 0) return;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= Kpad * Lp) return;
+  const int64_t k = idx / Lp;
+  const int c = (int)(idx - k * Lp);
+  const float v = (k < K && c < ncols) ? X[k * ldx + c] : 0.f;
+  if (!SPLIT) {
+    ((float*)out)[idx] = v;
+  } else {
+    // tile kt = k / 32: Lp x 32 block, element (c, k % 32); hi plane then lo plane
+    const int64_t kt = k >> 5;
+    const int kk = (int)(k & 31);
+    __bf16* hi = (__bf16*)out;
+    __bf16* lo = hi + Kpad * Lp;
+    const __bf16 h = (__bf16)v;
+    const int64_t o = (kt * Lp + c) * 32 + kk;
+    hi[o] = h;
+    lo[o] = (__bf16)(v - (float)h);
+  }
+}
+
+__device__ inline void split4(const f32x4 v, u32x2& hi, u32x2& lo) {
+  __bf16 h[4], l[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    h[e] = (__bf16)v[e];
+    l[e] = (__bf16)(v[e] - (float)h[e]);
+  }
+  hi.x = (uint32_t)__builtin_bit_cast(uint16_t, h[0]) | ((uint32_t)__builtin_bit_cast(uint16_t, h[1]) << 16);
+  hi.y = (uint32_t)__builtin_bit_cast(uint16_t, h[2]) | ((uint32_t)__builtin_bit_cast(uint16_t, h[3]) << 16);
+  lo.x = (uint32_t)__builtin_bit_cast(uint16_t, l[0]) | ((uint32_t)__builtin_bit_cast(uint16_t, l[1]) << 16);
+  lo.y = (uint32_t)__builtin_bit_cast(uint16_t, l[2]) | ((uint32_t)__builtin_bit_cast(uint16_t, l[3]) << 16);
+}
+
+__device__ inline f32x4 load4_guard(const float* p, int valid, bool vec) {
+  if (valid == 4 && vec) return *reinterpret_cast<const f32x4*>(p);
+  f32x4 v;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = e < valid ? p[e] : 0.f;
+  return v;
+}
+
+__device__ inline int valid4(int64_t v) { return v <= 0 ? 0 : (v >= 4 ? 4 : (int)v); }
+
+// One stage of A in registers: 8 runs of four floats per thread.
+//   NN (A rows x K): run q of thread t covers row (t / 8) + 16 q, k 4 (t % 8) .. +3.
+//   TN (A K x rows): thread t covers the 4 x 4 block k 4 (t / 32) .. +3 (plus
+//   16 for the second block), columns 4 (t % 32) .. +3; run q = 4 b + r is row r
+//   of block b.
+template <bool TRANS>
+__device__ inline void load_a_stage(const GemmParams& p, int64_t i0, int64_t k0, int64_t kend, int tid,
+                                    f32x4 (&ra)[8]) {
+  const float* A = (const float*)p.A;
+  const bool vec = p.vec != 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    int64_t off;
+    int valid;
+    if (!TRANS) {
+      const int64_t row = i0 + (tid >> 3) + 16 * q;
+      const int64_t kc = k0 + 4 * (tid & 7);
+      valid = row < p.rows ? valid4(kend - kc) : 0;
+      off = row * p.lda + kc;
+    } else {
+      const int b = q >> 2, r = q & 3;
+      const int64_t kr = k0 + 4 * (tid >> 5) + 16 * b + r;
+      const int64_t col = i0 + 4 * (tid & 31);
+      valid = kr < kend ? valid4(p.rows - col) : 0;
+      off = kr * p.lda + col;
+    }
+    ra[q] = load4_guard(A + (valid > 0 ? off : 0), valid, vec);
+  }
+}
+
+// ---- BF16 / bf16x3 ------------------------------------------------------
+// MFMA v_mfma_f32_32x32x16_bf16: lane (r = lane % 32, g = lane / 32) supplies
+// A[r][8 g + t] and B[8 g + t][r], t = 0..7; result register e holds
+// C[8 (e / 4) + 4 g + e % 4][r].
+template <bool TRANS, int NP>
+__global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_bf16_kernel(const GemmParams p, const __bf16* __restrict__ xh,
+                                                                  const __bf16* __restrict__ xl) {
+  constexpr int APLANE = SBM * BPAD;  // bf16 elements per A plane per buffer
+  constexpr int XPLANE = 128 * BPAD;
+  __shared__ __attribute__((aligned(16))) __bf16 sAh[2][APLANE];
+  __shared__ __attribute__((aligned(16))) __bf16 sAl[2][NP == 3 ? APLANE : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sXh[2][XPLANE];
+  __shared__ __attribute__((aligned(16))) __bf16 sXl[2][NP == 3 ? XPLANE : 8];
+  if (p.gate && *p.gate == 0) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int S = p.S;
+  const int s = blockIdx.x % S;
+  const int64_t i0 = (int64_t)(blockIdx.x / S) * SBM;
+  const int64_t kbeg = (int64_t)s * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int NT = p.Lp / 32;
+  const int64_t nk = kend > kbeg ? (kend - kbeg + SBK - 1) / SBK : 0;
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[a][t] = f32x16{};
+
+  // Two stages of A are kept in flight (raA / raB alternate); X, which comes
+  // from L2, one stage ahead.  X loads of a stage are issued before the A loads
+  // of the stage after it, so writing a stage to LDS waits only for its own loads.
+  f32x4 raA[8], raB[8];
+  u32x4 rxh[4], rxl[4];
+  auto load_x = [&](int64_t k0) __attribute__((always_inline)) {
+    const u32x4* gh = reinterpret_cast<const u32x4*>(xh + (k0 >> 5) * (int64_t)p.Lp * 32);
+    const u32x4* gl = reinterpret_cast<const u32x4*>(xl + (k0 >> 5) * (int64_t)p.Lp * 32);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int run = tid + STHREADS * q;
+      if (run < NT * 128) {
+        rxh[q] = gh[run];
+        if (NP == 3) rxl[q] = gl[run];
+      }
+    }
+  };
+  auto store_stage = [&](int buf, const f32x4 (&ra)[8]) __attribute__((always_inline)) {
+    // A: split and write K-contiguous rows
+    if (!TRANS) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int row = (tid >> 3) + 16 * q;
+        const int kc = 4 * (tid & 7);
+        u32x2 h, l;
+        split4(ra[q], h, l);
+        *reinterpret_cast<u32x2*>(&sAh[buf][row * BPAD + kc]) = h;
+        if (NP == 3) *reinterpret_cast<u32x2*>(&sAl[buf][row * BPAD + kc]) = l;
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int kc = 4 * (tid >> 5) + 16 * b;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = 4 * (tid & 31) + e;  // column of A = row of C
+          const f32x4 v = f32x4{ra[4 * b][e], ra[4 * b + 1][e], ra[4 * b + 2][e], ra[4 * b + 3][e]};
+          u32x2 h, l;
+          split4(v, h, l);
+          *reinterpret_cast<u32x2*>(&sAh[buf][row * BPAD + kc]) = h;
+          if (NP == 3) *reinterpret_cast<u32x2*>(&sAl[buf][row * BPAD + kc]) = l;
+        }
+      }
+    }
+    // X: 16-byte runs, run = column * 4 + quarter
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int run = tid + STHREADS * q;
+      if (run < NT * 128) {
+        const int c = run >> 2, part = run & 3;
+        *reinterpret_cast<u32x4*>(&sXh[buf][c * BPAD + 8 * part]) = rxh[q];
+        if (NP == 3) *reinterpret_cast<u32x4*>(&sXl[buf][c * BPAD + 8 * part]) = rxl[q];
+      }
+    }
+  };
+  const int r = lane & 31, g = lane >> 5;
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ks = 0; ks < SBK / 16; ++ks) {
+      const int kb = 16 * ks + 8 * g;
+      bf16x8 ah[2], al[2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const int row = wave * 64 + rt * 32 + r;
+        ah[rt] = *reinterpret_cast<const bf16x8*>(&sAh[buf][row * BPAD + kb]);
+        if (NP == 3) al[rt] = *reinterpret_cast<const bf16x8*>(&sAl[buf][row * BPAD + kb]);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < NT) {
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sXh[buf][(t * 32 + r) * BPAD + kb]);
+          bf16x8 bl;
+          if (NP == 3) bl = *reinterpret_cast<const bf16x8*>(&sXl[buf][(t * 32 + r) * BPAD + kb]);
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt) {
+            if (NP == 3) {
+              acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rt], bh, acc[rt][t], 0, 0, 0);
+              acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bl, acc[rt][t], 0, 0, 0);
+            }
+            acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bh, acc[rt][t], 0, 0, 0);
+          }
+        }
+      }
+    }
+  };
+  auto kofs = [&](int64_t stage) { return kbeg + stage * SBK; };
+
+  if (nk > 0) load_a_stage<TRANS>(p, i0, kofs(0), kend, tid, raA);
+  if (nk > 0) load_x(kofs(0));
+  if (nk > 1) load_a_stage<TRANS>(p, i0, kofs(1), kend, tid, raB);
+  if (nk > 0) store_stage(0, raA);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; kt += 2) {
+    // stage kt in buffer 0; stage kt + 1 in flight in raB
+    if (kt + 1 < nk) load_x(kofs(kt + 1));
+    if (kt + 2 < nk) load_a_stage<TRANS>(p, i0, kofs(kt + 2), kend, tid, raA);
+    compute(0);
+    if (kt + 1 < nk) store_stage(1, raB);
+    __syncthreads();
+    if (kt + 1 >= nk) break;
+    // stage kt + 1 in buffer 1; stage kt + 2 in flight in raA
+    if (kt + 2 < nk) load_x(kofs(kt + 2));
+    if (kt + 3 < nk) load_a_stage<TRANS>(p, i0, kofs(kt + 3), kend, tid, raB);
+    compute(1);
+    if (kt + 2 < nk) store_stage(0, raA);
+    __syncthreads();
+  }
+
+  float* out = (float*)p.out;
+  float* part = (float*)p.part;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t >= NT) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t row = i0 + wave * 64 + rt * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
+        const int col = t * 32 + r;
+        if (row < p.rows) {
+          if (S == 1) {
+            if (col < p.ncols) out[row * p.ldo + col] = acc[rt][t][e];
+          } else {
+            part[((int64_t)s * p.rows + row) * p.Lp + col] = acc[rt][t][e];
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---- FP32 ---------------------------------------------------------------
+// MFMA v_mfma_f32_32x32x2f32: lane (r, g) supplies A[r][g] and B[g][r]; K is
+// walked two at a time (k = 2 ks + g).
+template <bool TRANS>
+__global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_f32_kernel(const GemmParams p, const float* __restrict__ xp) {
+  constexpr int ALD = TRANS ? SBM + 4 : SBK + 1;
+  constexpr int ASZ = TRANS ? SBK * (SBM + 4) : SBM * (SBK + 1);
+  constexpr int XLD = 128 + 4;
+  __shared__ __attribute__((aligned(16))) float sA[2][ASZ];
+  __shared__ __attribute__((aligned(16))) float sX[2][SBK * XLD];
+  if (p.gate && *p.gate == 0) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int S = p.S;
+  const int s = blockIdx.x % S;
+  const int64_t i0 = (int64_t)(blockIdx.x / S) * SBM;
+  const int64_t kbeg = (int64_t)s * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int NT = p.Lp / 32;
+  const int64_t nk = kend > kbeg ? (kend - kbeg + SBK - 1) / SBK : 0;
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[a][t] = f32x16{};
+
+  // Two stages of A in flight, X one stage ahead (see the BF16 kernel).
+  f32x4 raA[8], raB[8];
+  f32x4 rx[8];
+  // X stage: 32 rows x Lp floats = 8 * Lp float4 runs
+  auto load_x = [&](int64_t k0) __attribute__((always_inline)) {
+    const f32x4* gx = reinterpret_cast<const f32x4*>(xp + k0 * p.Lp);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int run = tid + STHREADS * q;
+      if (run < SBK * p.Lp / 4) rx[q] = gx[run];
+    }
+  };
+  auto store_stage = [&](int buf, const f32x4 (&ra)[8]) __attribute__((always_inline)) {
+    if (!TRANS) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int row = (tid >> 3) + 16 * q, kc = 4 * (tid & 7);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sA[buf][row * ALD + kc + e] = ra[q][e];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int b = q >> 2, rr = q & 3;
+        const int kr = 4 * (tid >> 5) + 16 * b + rr, c = 4 * (tid & 31);
+        *reinterpret_cast<f32x4*>(&sA[buf][kr * ALD + c]) = ra[q];
+      }
+    }
+    const int q4 = p.Lp / 4;  // float4 runs per X row
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int run = tid + STHREADS * q;
+      if (run < SBK * q4) {
+        const int kr = run / q4, c = 4 * (run - kr * q4);
+        *reinterpret_cast<f32x4*>(&sX[buf][kr * XLD + c]) = rx[q];
+      }
+    }
+  };
+  const int r = lane & 31, g = lane >> 5;
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ks = 0; ks < SBK / 2; ++ks) {
+      const int kl = 2 * ks + g;
+      float a[2];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const int row = wave * 64 + rt * 32 + r;
+        a[rt] = TRANS ? sA[buf][kl * ALD + row] : sA[buf][row * ALD + kl];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < NT) {
+          const float b = sX[buf][kl * XLD + t * 32 + r];
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+            acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt], b, acc[rt][t], 0, 0, 0);
+        }
+      }
+    }
+  };
+  auto kofs = [&](int64_t stage) { return kbeg + stage * SBK; };
+
+  if (nk > 0) load_a_stage<TRANS>(p, i0, kofs(0), kend, tid, raA);
+  if (nk > 0) load_x(kofs(0));
+  if (nk > 1) load_a_stage<TRANS>(p, i0, kofs(1), kend, tid, raB);
+  if (nk > 0) store_stage(0, raA);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; kt += 2) {
+    if (kt + 1 < nk) load_x(kofs(kt + 1));
+    if (kt + 2 < nk) load_a_stage<TRANS>(p, i0, kofs(kt + 2), kend, tid, raA);
+    compute(0);
+    if (kt + 1 < nk) store_stage(1, raB);
+    __syncthreads();
+    if (kt + 1 >= nk) break;
+    if (kt + 2 < nk) load_x(kofs(kt + 2));
+    if (kt + 3 < nk) load_a_stage<TRANS>(p, i0, kofs(kt + 3), kend, tid, raB);
+    compute(1);
+    if (kt + 2 < nk) store_stage(0, raA);
+    __syncthreads();
+  }
+
+  float* out = (float*)p.out;
+  float* part = (float*)p.part;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t >= NT) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t row = i0 + wave * 64 + rt * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
+        const int col = t * 32 + r;
+        if (row < p.rows) {
+          if (S == 1) {
+            if (col < p.ncols) out[row * p.ldo + col] = acc[rt][t][e];
+          } else {
+            part[((int64_t)s * p.rows + row) * p.Lp + col] = acc[rt][t][e];
+          }
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int64_t stream_pack_bytes(int64_t K, int32_t Lp) {
+  const int64_t Kpad = (K + SBK - 1) / SBK * SBK;
+  return Kpad * Lp * 4;  // FP32, or two BF16 planes
+}
+
+hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, void* pack, hipStream_t st) {
+  if (p.rows <= 0) return hipSuccess;
+  if (p.ncols > 128 || p.Lp > 128 || p.Lp % 32 != 0 || p.Lp < p.ncols || p.S < 1) return hipErrorInvalidValue;
+  const int64_t Kpad = (p.K + SBK - 1) / SBK * SBK;
+  const int64_t nel = Kpad * p.Lp;
+  const dim3 pgrid((unsigned)((nel + 255) / 256));
+  const bool split = prec != PREC_NATIVE;
+  if (split)
+    hipLaunchKernelGGL(pack_x_kernel<true>, pgrid, dim3(256), 0, st, (const float*)p.X, p.K, p.ldx, p.ncols, p.Lp,
+                       Kpad, pack, p.gate);
+  else
+    hipLaunchKernelGGL(pack_x_kernel<false>, pgrid, dim3(256), 0, st, (const float*)p.X, p.K, p.ldx, p.ncols, p.Lp,
+                       Kpad, pack, p.gate);
+  const int64_t nrb = (p.rows + SBM - 1) / SBM;
+  const dim3 grid((unsigned)(nrb * p.S)), block(STHREADS);
+  const __bf16* xh = (const __bf16*)pack;
+  const __bf16* xl = xh + nel;
+  if (prec == PREC_BF16X3) {
+    if (trans)
+      hipLaunchKernelGGL((stream_bf16_kernel<true, 3>), grid, block, 0, st, p, xh, xl);
+    else
+      hipLaunchKernelGGL((stream_bf16_kernel<false, 3>), grid, block, 0, st, p, xh, xl);
+  } else if (prec == PREC_BF16) {
+    if (trans)
+      hipLaunchKernelGGL((stream_bf16_kernel<true, 1>), grid, block, 0, st, p, xh, xl);
+    else
+      hipLaunchKernelGGL((stream_bf16_kernel<false, 1>), grid, block, 0, st, p, xh, xl);
+  } else {
+    if (trans)
+      hipLaunchKernelGGL(stream_f32_kernel<true>, grid, block, 0, st, p, (const float*)pack);
+    else
+      hipLaunchKernelGGL(stream_f32_kernel<false>, grid, block, 0, st, p, (const float*)pack);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

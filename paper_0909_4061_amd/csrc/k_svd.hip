@@ -23,19 +23,30 @@ namespace rsvd {
 namespace {
 
 constexpr int JAC_MAXL = 128;
-constexpr int JAC_LDC = JAC_MAXL + 1;
+constexpr int JAC_LDC = JAC_MAXL + 2;  // even: 16-byte aligned column starts
 constexpr int JAC_MAX_SWEEPS = 40;
 
+// Move a double across lanes of a 16-lane DPP row.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a DPP row.  Rotations by 8 and 4 then swaps within
+// quads: every lane adds the same operands in the same pairs, so all 16 lanes
+// hold bitwise-identical sums (and so take identical rotation decisions).
 __device__ inline double group16_sum(double v) {
-  v += __shfl_xor(v, 8, 16);
-  v += __shfl_xor(v, 4, 16);
-  v += __shfl_xor(v, 2, 16);
-  v += __shfl_xor(v, 1, 16);
+  v += dpp_f64<0x128>(v);  // row_ror:8
+  v += dpp_f64<0x124>(v);  // row_ror:4
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
   return v;
 }
 
 __global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
-  __shared__ double Cs[JAC_MAXL * JAC_LDC];  // column c at Cs[c * JAC_LDC + row]
+  __shared__ __attribute__((aligned(16))) double Cs[JAC_MAXL * JAC_LDC];  // column c at Cs[c * JAC_LDC + row]
   __shared__ double sig_s[JAC_MAXL];
   __shared__ int rank_s[JAC_MAXL];
   __shared__ int rotated;
@@ -70,12 +81,24 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
         const int cb = 1 + (xb - 1 + rnd) % (le - 1);
         double* col_a = Cs + ca * JAC_LDC;
         double* col_b = Cs + cb * JAC_LDC;
+        // rows 32 r + 2 gl and 32 r + 2 gl + 1 of each column (rows past l are zeros)
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        double x[JAC_MAXL / 16], y[JAC_MAXL / 16];
+#pragma unroll
+        for (int r = 0; r < JAC_MAXL / 32; ++r) {
+          const d2 xa = *reinterpret_cast<const d2*>(col_a + 32 * r + 2 * gl);
+          const d2 yb = *reinterpret_cast<const d2*>(col_b + 32 * r + 2 * gl);
+          x[2 * r] = xa[0];
+          x[2 * r + 1] = xa[1];
+          y[2 * r] = yb[0];
+          y[2 * r + 1] = yb[1];
+        }
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < l; i += 16) {
-          const double x = col_a[i], y = col_b[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+#pragma unroll
+        for (int r = 0; r < JAC_MAXL / 16; ++r) {
+          al += x[r] * x[r];
+          be += y[r] * y[r];
+          ga += x[r] * y[r];
         }
         al = group16_sum(al);
         be = group16_sum(be);
@@ -85,10 +108,12 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t);
           const double sn = cs * t;
-          for (int i = gl; i < l; i += 16) {
-            const double x = col_a[i], y = col_b[i];
-            col_a[i] = cs * x - sn * y;
-            col_b[i] = sn * x + cs * y;
+#pragma unroll
+          for (int r = 0; r < JAC_MAXL / 32; ++r) {
+            *reinterpret_cast<d2*>(col_a + 32 * r + 2 * gl) =
+                d2{cs * x[2 * r] - sn * y[2 * r], cs * x[2 * r + 1] - sn * y[2 * r + 1]};
+            *reinterpret_cast<d2*>(col_b + 32 * r + 2 * gl) =
+                d2{sn * x[2 * r] + cs * y[2 * r], sn * x[2 * r + 1] + cs * y[2 * r + 1]};
           }
           any = 1;
         }
