@@ -111,6 +111,7 @@ struct JacobiParams {
   void* XV;             // l x k: Uh[:, :k] diag(1/sigma) in the element type
   void* S;              // k singular values in the element type
   int32_t* status;
+  int32_t* sweeps;      // if non-null: number of sweeps run (diagnostic)
 };
 hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st);
 

@@ -8,9 +8,9 @@
 // needed: the right singular vectors follow as V = B* U~ S^-1, computed by the
 // lift GEMM (B* is the stored Bt).
 //
-// One workgroup of 1024 threads holds C column-major in LDS.  Each round of a
+// One workgroup of 512 threads holds C column-major in LDS.  Each round of a
 // sweep rotates l/2 disjoint column pairs chosen by the round-robin (circle)
-// ordering, one pair per 16-lane group; a sweep is l - 1 rounds (l rounded up
+// ordering, one pair per 8-lane group; a sweep is l - 1 rounds (l rounded up
 // to even, with a zero column when l is odd), so every pair meets once.  A
 // pair is rotated when |c_i . c_j| > tol sqrt(|c_i|^2 |c_j|^2); the workgroup
 // stops after a sweep with no rotation.
@@ -34,18 +34,18 @@ __device__ inline double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum over the 16 lanes of a DPP row.  Rotations by 8 and 4 then swaps within
-// quads: every lane adds the same operands in the same pairs, so all 16 lanes
-// hold bitwise-identical sums (and so take identical rotation decisions).
-__device__ inline double group16_sum(double v) {
-  v += dpp_f64<0x128>(v);  // row_ror:8
-  v += dpp_f64<0x124>(v);  // row_ror:4
+// Sum over an aligned group of 8 lanes.  Mirror within the half-row, then
+// swaps within quads: every lane adds the same operands in the same pairs, so
+// all 8 lanes hold bitwise-identical sums (and take identical rotation
+// decisions).
+__device__ inline double group8_sum(double v) {
+  v += dpp_f64<0x141>(v);  // row_half_mirror
   v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
   return v;
 }
 
-__global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
+__global__ __launch_bounds__(512) void jacobi_kernel(const JacobiParams p) {
   __shared__ __attribute__((aligned(16))) double Cs[JAC_MAXL * JAC_LDC];  // column c at Cs[c * JAC_LDC + row]
   __shared__ double sig_s[JAC_MAXL];
   __shared__ int rank_s[JAC_MAXL];
@@ -56,14 +56,14 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
   const int P = le / 2;
 
   // column c of C = R^T is row c of R
-  for (int idx = tid; idx < le * JAC_LDC; idx += 1024) {
+  for (int idx = tid; idx < le * JAC_LDC; idx += 512) {
     const int c = idx / JAC_LDC, i = idx - c * JAC_LDC;
     Cs[idx] = (c < l && i < l) ? p.R[(int64_t)c * l + i] : 0.0;
   }
   if (tid == 0) rotated = 1;
   __syncthreads();
 
-  const int grp = tid >> 4, gl = tid & 15;
+  const int grp = tid >> 3, gl = tid & 7;
   const double tol = (double)l * DBL_EPSILON;
   int sweep = 0;
   for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
@@ -81,13 +81,13 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
         const int cb = 1 + (xb - 1 + rnd) % (le - 1);
         double* col_a = Cs + ca * JAC_LDC;
         double* col_b = Cs + cb * JAC_LDC;
-        // rows 32 r + 2 gl and 32 r + 2 gl + 1 of each column (rows past l are zeros)
+        // rows 16 r + 2 gl and 16 r + 2 gl + 1 of each column (rows past l are zeros)
         typedef double d2 __attribute__((ext_vector_type(2)));
-        double x[JAC_MAXL / 16], y[JAC_MAXL / 16];
+        double x[JAC_MAXL / 8], y[JAC_MAXL / 8];
 #pragma unroll
-        for (int r = 0; r < JAC_MAXL / 32; ++r) {
-          const d2 xa = *reinterpret_cast<const d2*>(col_a + 32 * r + 2 * gl);
-          const d2 yb = *reinterpret_cast<const d2*>(col_b + 32 * r + 2 * gl);
+        for (int r = 0; r < JAC_MAXL / 16; ++r) {
+          const d2 xa = *reinterpret_cast<const d2*>(col_a + 16 * r + 2 * gl);
+          const d2 yb = *reinterpret_cast<const d2*>(col_b + 16 * r + 2 * gl);
           x[2 * r] = xa[0];
           x[2 * r + 1] = xa[1];
           y[2 * r] = yb[0];
@@ -95,24 +95,24 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
         }
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-        for (int r = 0; r < JAC_MAXL / 16; ++r) {
+        for (int r = 0; r < JAC_MAXL / 8; ++r) {
           al += x[r] * x[r];
           be += y[r] * y[r];
           ga += x[r] * y[r];
         }
-        al = group16_sum(al);
-        be = group16_sum(be);
-        ga = group16_sum(ga);
+        al = group8_sum(al);
+        be = group8_sum(be);
+        ga = group8_sum(ga);
         if (ca < l && cb < l && fabs(ga) > tol * sqrt(al * be) && al > 0.0 && be > 0.0) {
           const double zeta = (be - al) / (2.0 * ga);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t);
           const double sn = cs * t;
 #pragma unroll
-          for (int r = 0; r < JAC_MAXL / 32; ++r) {
-            *reinterpret_cast<d2*>(col_a + 32 * r + 2 * gl) =
+          for (int r = 0; r < JAC_MAXL / 16; ++r) {
+            *reinterpret_cast<d2*>(col_a + 16 * r + 2 * gl) =
                 d2{cs * x[2 * r] - sn * y[2 * r], cs * x[2 * r + 1] - sn * y[2 * r + 1]};
-            *reinterpret_cast<d2*>(col_b + 32 * r + 2 * gl) =
+            *reinterpret_cast<d2*>(col_b + 16 * r + 2 * gl) =
                 d2{sn * x[2 * r] + cs * y[2 * r], sn * x[2 * r + 1] + cs * y[2 * r + 1]};
           }
           any = 1;
@@ -124,6 +124,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
     __syncthreads();
   }
   if (tid == 0 && sweep >= JAC_MAX_SWEEPS && rotated) atomicOr(p.status, (int32_t)RSVD_FLAG_NOCONV);
+  if (tid == 0 && p.sweeps) *p.sweeps = sweep;
 
   // singular values = column norms; rank by descending value (ties: lower index first)
   if (tid < l) {
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
     rank_s[tid] = rk;
   }
   __syncthreads();
-  for (int idx = tid; idx < l * l; idx += 1024) {
+  for (int idx = tid; idx < l * l; idx += 512) {
     const int c = idx / l, i = idx - c * l;  // element i of column c
     const int rk = rank_s[c];
     const double sg = sig_s[c];
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const JacobiParams p) {
 
 hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st) {
   if (p.l < 1 || p.l > JAC_MAXL || p.k < 1 || p.k > p.l) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, st, p);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(512), 0, st, p);
   return hipGetLastError();
 }
 
