@@ -27,6 +27,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per launch of the streaming GEMMs (scaled FETCH_SIZE + WRITE_SIZE from rocprofv3
+# counter runs, profiles/stream_gemm_power_iteration_16384x8192_hbm_counters.md), valid only for
+# the kernel source they were measured on and the 16384 x 8192, l = 120 shape.
+TRAFFIC_KERNEL_SHA = "cfad0aaff99d953a"
+TRAFFIC_SHAPE = (16384, 8192, 120)
+TRAFFIC_BYTES = {"stream_tn_bf16x3": 579446816, "stream_nn_bf16x3": 579920840,
+                 "stream_tn_native": 579500971, "stream_nn_native": 579853986}
 PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
 MI355X_CUS = 256
 
@@ -117,6 +125,19 @@ def run_path(A, k, p, q, prec, steps, warmup, seed):
     return dict(ms_per_step=ms_total / steps, prof=prof, flags=flags, U=U, S=S, V=V)
 
 
+def measured_traffic(family, prec, m, n, l):
+    """Counter-measured HBM bytes per launch, or None if the kernel source or shape differs."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_0909_4061_amd", "csrc", "k_stream.hip")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if sha != TRAFFIC_KERNEL_SHA or (m, n, l) != TRAFFIC_SHAPE:
+        return None
+    return TRAFFIC_BYTES.get(f"{family}_{prec}")
+
+
 def roofline_for(res, m, n, l, prec):
     """Roofline figures of the dominant kernel (the GEMM family that streams A
     and takes the most time), from the live per-launch event timing."""
@@ -135,7 +156,7 @@ def roofline_for(res, m, n, l, prec):
         out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                "frac": achieved / PEAK_HBM_GBS}
     out.update({"kernel": f"gemm_{'tn' if fam == 'stream_tn' else 'nn'}_{'f32' if prec == 'native' else prec}",
-                "launches": launches, "avg_us": avg_s * 1e6, "traffic": None,
+                "launches": launches, "avg_us": avg_s * 1e6, "traffic": measured_traffic(fam, prec, m, n, l),
                 "per_launch": {"bytes": bytes_launch, "flops": flops_launch}})
     return out
 
@@ -186,6 +207,12 @@ def main():
     ap.add_argument("--seed", type=int, default=0x09094061)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["bf16x3", "native"], default=None)
+    ap.add_argument("--input", choices=["construct", "randn"], default="construct",
+                    help="construct: A = U diag(1/j) V^T (the workload); randn: i.i.d. Gaussian A of the "
+                         "same shape, for hardware-counter runs only (byte counts do not depend on values)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain device copy of A (known size) before the paths, to scale "
+                         "HBM byte counters in profiling runs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -203,9 +230,21 @@ def main():
     torch.cuda.set_device(dev)
     t = time.perf_counter()
     sigma = spectrum("inv", min(m, n))
-    A = build_matrix_torch(m, n, sigma, seed=args.seed, dtype=torch.float32, device=dev)
+    if args.input == "construct":
+        A = build_matrix_torch(m, n, sigma, seed=args.seed, dtype=torch.float32, device=dev)
+    else:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(args.seed)
+        A = torch.randn(m, n, generator=gen, device=dev, dtype=torch.float32)
     torch.cuda.synchronize()
     print(f"# built A {m}x{n} on the GPU in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+
+    if args.calib_copy:
+        Ac = A.clone()
+        torch.cuda.synchronize()
+        print(f"# calibration copy: {A.numel() * A.element_size()} bytes read and written",
+              file=sys.stderr, flush=True)
+        del Ac
 
     flops = algorithmic_flops(m, n, l, k, q)
     hbm = algorithmic_bytes(m, n, l, q)
@@ -231,7 +270,8 @@ def main():
         "value": hp["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": hp["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16" if head == "bf16x3" else "f32", "prec": head, "data": "synthetic",
-        "config": {"workload": f"power-iteration rSVD, FP32 {m}x{n}, sigma_j=1/j, k={k}, p={p}, q={q}",
+        "config": {"workload": f"power-iteration rSVD, FP32 {m}x{n}, sigma_j=1/j, k={k}, p={p}, q={q}"
+                               + ("" if args.input == "construct" else " (Gaussian input: counter run)"),
                    "m": m, "n": n, "k": k, "p": p, "q": q, "sketch": "gaussian"},
         "hbm_gbs": hp["hbm_gbs"], "err_ratio": hp["err_ratio"], "roofline": hp["roofline"],
         "paths": {pth: {kk: vv for kk, vv in d.items() if kk != "roofline"} | {"roofline": d["roofline"]}

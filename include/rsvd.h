@@ -195,7 +195,8 @@ enum {
   RSVD_KERNEL_GRAM = 3,       /* block Gram + reduction */
   RSVD_KERNEL_CHOL = 4,       /* l x l Cholesky with inverse */
   RSVD_KERNEL_JACOBI = 5,     /* l x l one-sided Jacobi */
-  RSVD_KERNEL_KINDS = 6
+  RSVD_KERNEL_PACK = 6,       /* packing of the l-column operand before a streaming GEMM */
+  RSVD_KERNEL_KINDS = 7
 };
 
 /* capacity > 0: create `capacity` pairs of hipEvents (an allocation made here,

@@ -182,11 +182,16 @@ rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda,
   g.vec = (lda % vec_mult == 0 && aligned16(A)) ? 1 : 0;
   g.gate = gate;
   if (g.S > 1 && !part) return RSVD_E_INVAL;
-  Timed t_(c.h, streams_a ? (trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN) : RSVD_KERNEL_SMALL_GEMM, c.st);
   if (streams_a && c.P.dtype == RSVD_F32) {
     g.Lp = (int32_t)round_up(ncols, 32);
+    {
+      Timed t_(c.h, RSVD_KERNEL_PACK, c.st);
+      RSVD_TRY(launch_pack_x(prec, g, c.at<void>(c.P.pack), c.st));
+    }
+    Timed t_(c.h, trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN, c.st);
     RSVD_TRY(launch_stream_gemm(prec, trans, g, c.at<void>(c.P.pack), c.st));
   } else {
+    Timed t_(c.h, streams_a ? (trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN) : RSVD_KERNEL_SMALL_GEMM, c.st);
     RSVD_TRY(launch_gemm(c.P.dtype, prec, trans, g, c.st));
   }
   return RSVD_OK;

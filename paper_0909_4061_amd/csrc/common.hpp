@@ -53,7 +53,8 @@ hipError_t launch_gemm(int dtype, int prec, bool trans, const GemmParams& p, hip
 // FP32-data GEMMs that stream A (FP32 MFMA or BF16 / bf16x3 MFMA): X is first
 // packed into `pack` (stream_pack_bytes(K, Lp) bytes) by a small kernel.
 int64_t stream_pack_bytes(int64_t K, int32_t Lp);
-hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, void* pack, hipStream_t st);
+hipError_t launch_pack_x(int prec, const GemmParams& p, void* pack, hipStream_t st);
+hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, const void* pack, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Gram matrices and CholeskyQR.

@@ -34,28 +34,46 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // ---- pack X -----------------------------------------------------------
+// One workgroup per 32-row tile of X: the tile is read with coalesced loads
+// into LDS, then written as Lp columns of 32 consecutive k -- FP32 rows of Lp
+// (plain) or 16-byte runs of bf16 hi and lo planes (split).
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void pack_x_kernel(const float* __restrict__ X, int64_t K, int64_t ldx,
                                                      int32_t ncols, int32_t Lp, int64_t Kpad, void* __restrict__ out,
                                                      const int32_t* gate) {
+  __shared__ float tile[32][128 + 1];
   if (gate && *gate == 0) return;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= Kpad * Lp) return;
-  const int64_t k = idx / Lp;
-  const int c = (int)(idx - k * Lp);
-  const float v = (k < K && c < ncols) ? X[k * ldx + c] : 0.f;
+  const int tid = threadIdx.x;
+  const int64_t kt = blockIdx.x;
+  for (int idx = tid; idx < 32 * Lp; idx += 256) {
+    const int kk = idx / Lp, c = idx - kk * Lp;
+    const int64_t k = kt * 32 + kk;
+    tile[kk][c] = (k < K && c < ncols) ? X[k * ldx + c] : 0.f;
+  }
+  __syncthreads();
   if (!SPLIT) {
-    ((float*)out)[idx] = v;
+    float* o = (float*)out + kt * 32 * Lp;
+    for (int idx = tid; idx < 32 * Lp; idx += 256) {
+      const int kk = idx / Lp, c = idx - kk * Lp;
+      o[idx] = tile[kk][c];
+    }
   } else {
-    // tile kt = k / 32: Lp x 32 block, element (c, k % 32); hi plane then lo plane
-    const int64_t kt = k >> 5;
-    const int kk = (int)(k & 31);
+    // run (c, q): k = 8 q .. 8 q + 7 of column c, 16 bytes per plane
     __bf16* hi = (__bf16*)out;
     __bf16* lo = hi + Kpad * Lp;
-    const __bf16 h = (__bf16)v;
-    const int64_t o = (kt * Lp + c) * 32 + kk;
-    hi[o] = h;
-    lo[o] = (__bf16)(v - (float)h);
+    for (int run = tid; run < 4 * Lp; run += 256) {
+      const int c = run >> 2, q = run & 3;
+      bf16x8 h, l;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float v = tile[8 * q + t][c];
+        h[t] = (__bf16)v;
+        l[t] = (__bf16)(v - (float)h[t]);
+      }
+      const int64_t o = (kt * Lp + c) * 32 + 8 * q;
+      *reinterpret_cast<bf16x8*>(hi + o) = h;
+      *reinterpret_cast<bf16x8*>(lo + o) = l;
+    }
   }
 }
 
@@ -411,19 +429,24 @@ int64_t stream_pack_bytes(int64_t K, int32_t Lp) {
   return Kpad * Lp * 4;  // FP32, or two BF16 planes
 }
 
-hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, void* pack, hipStream_t st) {
-  if (p.rows <= 0) return hipSuccess;
-  if (p.ncols > 128 || p.Lp > 128 || p.Lp % 32 != 0 || p.Lp < p.ncols || p.S < 1) return hipErrorInvalidValue;
+hipError_t launch_pack_x(int prec, const GemmParams& p, void* pack, hipStream_t st) {
+  if (p.ncols > 128 || p.Lp > 128 || p.Lp % 32 != 0 || p.Lp < p.ncols) return hipErrorInvalidValue;
   const int64_t Kpad = (p.K + SBK - 1) / SBK * SBK;
-  const int64_t nel = Kpad * p.Lp;
-  const dim3 pgrid((unsigned)((nel + 255) / 256));
-  const bool split = prec != PREC_NATIVE;
-  if (split)
+  const dim3 pgrid((unsigned)(Kpad / SBK));
+  if (prec != PREC_NATIVE)
     hipLaunchKernelGGL(pack_x_kernel<true>, pgrid, dim3(256), 0, st, (const float*)p.X, p.K, p.ldx, p.ncols, p.Lp,
                        Kpad, pack, p.gate);
   else
     hipLaunchKernelGGL(pack_x_kernel<false>, pgrid, dim3(256), 0, st, (const float*)p.X, p.K, p.ldx, p.ncols, p.Lp,
                        Kpad, pack, p.gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, const void* pack, hipStream_t st) {
+  if (p.rows <= 0) return hipSuccess;
+  if (p.ncols > 128 || p.Lp > 128 || p.Lp % 32 != 0 || p.Lp < p.ncols || p.S < 1) return hipErrorInvalidValue;
+  const int64_t Kpad = (p.K + SBK - 1) / SBK * SBK;
+  const int64_t nel = Kpad * p.Lp;
   const int64_t nrb = (p.rows + SBM - 1) / SBM;
   const dim3 grid((unsigned)(nrb * p.S)), block(STHREADS);
   const __bf16* xh = (const __bf16*)pack;
