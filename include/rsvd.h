@@ -8,7 +8,12 @@
  *     with an orthonormalization after every application of A or A*
  *     (Algorithm 4.4, randomized subspace iteration; Algorithm 4.1 when q = 0),
  *     or, for the SRFT test matrix of Section 4.6, Y = A Omega by FFT
- *     (Algorithm 4.5).  Q is an orthonormal basis of range(Y).
+ *     (Algorithm 4.5).  Q is an orthonormal basis of range(Y).  A is real, and
+ *     the SRFT is its real tailoring (Section 4.6 notes that the transform can
+ *     be set up for the real or the complex case): F is replaced by the real
+ *     orthonormal Fourier basis F_r, whose columns are the constant, the
+ *     alternating and, for 0 < q < n/2, sqrt(2) cos(2 pi p q / n) and
+ *     sqrt(2) sin(2 pi p q / n), each over sqrt(n).  Every output stays real.
  *   Stage B (Algorithm 5.1, direct SVD): B = Q* A, an SVD of the small matrix
  *     B = U~ S V*, U = Q U~, then truncation to the k leading triplets (the
  *     truncation remark of Section 5.1).
@@ -23,9 +28,8 @@
  *    Every other matrix is dense with leading dimension equal to its column
  *    count.
  *  * Element type: float (RSVD_F32) or double (RSVD_F64), chosen by
- *    problem->dtype, for A, Omega, Q, Bt, U, S and V.  With the SRFT sketch,
- *    Q, Bt, U and V are complex (interleaved re/im pairs of the element type,
- *    the layout of torch.complex64 / complex128); S is always real.
+ *    problem->dtype, for A, Omega, Q, Bt, U, S and V (all real, with either
+ *    sketch).
  *  * Pointers named A, Q, Bt, U, S, V, Omega and ws are DEVICE pointers on the
  *    handle's device.  The problem descriptor is a HOST pointer.  `stream` is
  *    a hipStream_t (NULL = the default stream) on which every kernel of the
@@ -71,7 +75,8 @@ enum { RSVD_F32 = 0, RSVD_F64 = 1 };
 /* problem->sketch: the test matrix of Stage A */
 enum {
   RSVD_GAUSSIAN = 0,  /* i.i.d. N(0,1) n x l (Section 4.1) */
-  RSVD_SRFT = 1       /* sqrt(n/l) D F R with D = random +-1 signs (Section 4.6); q must be 0 */
+  RSVD_SRFT = 1       /* sqrt(n/l) D F_r R with D = random +-1 signs and F_r the real
+                         orthonormal Fourier basis (Section 4.6); q must be 0 */
 };
 /* problem->prec: arithmetic of the products that stream A (the sketch,
  * power-step and projection GEMMs).  Gram matrices, Cholesky factors and the
@@ -117,8 +122,9 @@ rsvd_status rsvd_destroy(rsvd_handle handle);
 /* Pure host checks of a problem descriptor (no device, no handle).  RSVD_OK,
  * RSVD_E_INVAL (violates the problem statement: k < 1, p < 0, q < 0,
  * l > min(m, n), lda < n, unknown enum) or RSVD_E_UNSUPPORTED (l > RSVD_MAX_L,
- * BF16 precisions with FP64 data, SRFT with q > 0 or n not a power of two,
- * n > 32768 with the SRFT). */
+ * BF16 precisions with FP64 data; with the SRFT: q > 0, n not a power of two,
+ * n < 8, or n above 16384 (FP32) / 8192 (FP64), the largest row one
+ * workgroup transforms in its local memory). */
 rsvd_status rsvd_validate(const rsvd_problem* problem);
 
 /* Bytes of workspace every call below needs for `problem` (0 if invalid).
@@ -133,7 +139,10 @@ const char* rsvd_status_string(rsvd_status status);
  * 4.4) or Algorithm 4.5 (SRFT).  Draws Omega from (seed, stream_id), forms
  * Y = A Omega and writes an orthonormal basis Q (m x l) of range(Y), computed
  * by CholeskyQR2 (two passes of Gram -> Cholesky -> Y R^-1, FP64 Gram and
- * Cholesky).  A: m x n (lda); Q: m x l output (complex with the SRFT). */
+ * Cholesky).  A: m x n (lda); Q: m x l output.  With the SRFT, Y is formed in
+ * the element type by one length-n real FFT per row of A D (the full
+ * transform, then the l sampled frequencies: the variant the remark after
+ * Algorithm 4.5 recommends); problem->prec does not apply to it. */
 rsvd_status rsvd_range_finder(rsvd_handle handle, const rsvd_problem* problem,
                               const void* A, void* Q, void* ws, size_t ws_bytes,
                               hipStream_t stream);
@@ -163,18 +172,29 @@ rsvd_status rsvd_svd(rsvd_handle handle, const rsvd_problem* problem,
 
 /* --- Diagnostics ------------------------------------------------------- */
 
+/* The sketch of Stage A on its own: Y = A Omega (m x l, element type of
+ * problem->dtype, row-major) with the test matrix the range finder draws --
+ * step 2 of Algorithm 4.1 (Gaussian, arithmetic problem->prec) or of
+ * Algorithm 4.5 (SRFT, one real FFT per row of A D, element type) -- without
+ * the orthonormalization.  Same workspace as the hot-path calls.  For parity
+ * tests of the sketch element by element. */
+rsvd_status rsvd_sketch(rsvd_handle handle, const rsvd_problem* problem,
+                        const void* A, void* Y, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+
 /* The Gaussian test matrix the range finder draws: Omega (n x l, element type
  * of problem->dtype), from the generator contract documented in the library's
  * design notes (Philox4x64-10, Box-Muller).  For parity tests. */
 rsvd_status rsvd_draw_omega(rsvd_handle handle, const rsvd_problem* problem,
                             void* Omega, hipStream_t stream);
 
-/* The SRFT ingredients the range finder draws: signs d (n doubles, +-1) and the
- * sampled frequencies R (l int32), drawing through the workspace.  For parity
+/* The SRFT ingredients the range finder draws (Section 4.6): the signs of D
+ * (d: n doubles, +-1, device) and the sampled frequencies R (l distinct int32
+ * in [0, n), device, in draw order), from the generator contract documented in
+ * the library's design notes.  problem->sketch must be RSVD_SRFT.  For parity
  * tests. */
 rsvd_status rsvd_draw_srft(rsvd_handle handle, const rsvd_problem* problem,
-                           double* d, int32_t* R, void* ws, size_t ws_bytes,
-                           hipStream_t stream);
+                           double* d, int32_t* R, hipStream_t stream);
 
 /* CholeskyQR2 of a tall matrix on its own: Y (rows x l, element type of
  * problem->dtype, real) is overwritten by Q with Y = Q R; R (l x l, double,
@@ -196,7 +216,8 @@ enum {
   RSVD_KERNEL_CHOL = 4,       /* l x l Cholesky with inverse */
   RSVD_KERNEL_JACOBI = 5,     /* l x l one-sided Jacobi */
   RSVD_KERNEL_PACK = 6,       /* packing of the l-column operand before a streaming GEMM */
-  RSVD_KERNEL_KINDS = 7
+  RSVD_KERNEL_SRFT = 7,       /* SRFT sketch: one FFT per row of A D, sampled */
+  RSVD_KERNEL_KINDS = 8
 };
 
 /* capacity > 0: create `capacity` pairs of hipEvents (an allocation made here,

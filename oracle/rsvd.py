@@ -133,6 +133,68 @@ def fast_randomized_range_finder(A, d, R):
 
 
 # ---------------------------------------------------------------------------
+# The real tailoring of the SRFT.  Section 4.6 notes that the scheme can be
+# tailored to the real or the complex case and treats the complex one.  For a
+# real A the real tailoring replaces F by the real orthonormal Fourier basis
+# F_r = F T, where T is the fixed unitary matrix that mixes each frequency pair
+# (q, n - q) into a cosine and a sine column:
+#   column 0          : f_0                      = n^-1/2
+#   column n/2        : f_{n/2}                  = n^-1/2 (-1)^p
+#   column q, q < n/2 : (f_q + f_{n-q}) / sqrt 2 = sqrt(2/n) cos(2 pi p q / n)
+#   column q, q > n/2 : with q' = n - q,
+#                       i (f_{q'} - f_q) / sqrt 2 = sqrt(2/n) sin(2 pi p q' / n)
+# (n even).  Omega = sqrt(n/l) D F_r R stays real, and so do Y, Q, B, U, V.
+# ---------------------------------------------------------------------------
+
+def real_fourier_matrix(n):
+    """F_r (n x n, real orthogonal) written out entry by entry; n even."""
+    if n % 2:
+        raise ValueError("the real Fourier basis here needs an even n")
+    p = np.arange(n)[:, None]
+    q = np.arange(n)[None, :]
+    Fr = np.zeros((n, n))
+    Fr[:, 0] = 1.0 / np.sqrt(n)
+    Fr[:, n // 2] = (-1.0) ** np.arange(n) / np.sqrt(n)
+    lo = (q > 0) & (q < n // 2)
+    hi = q > n // 2
+    Fr += np.where(lo, np.sqrt(2.0 / n) * np.cos(2 * np.pi * p * q / n), 0.0)
+    Fr += np.where(hi, np.sqrt(2.0 / n) * np.sin(2 * np.pi * p * (n - q) / n), 0.0)
+    return Fr
+
+
+def real_srft_test_matrix(n, d, R):
+    """Omega = sqrt(n/l) D F_r R, dense (for pins on small n)."""
+    l = len(R)
+    return np.sqrt(n / l) * d[:, None] * real_fourier_matrix(n)[:, np.asarray(R)]
+
+
+def real_srft_sketch(A, d, R):
+    """Y = A Omega for the real SRFT, from one FFT per row (Algorithm 4.5, step 2).
+
+    With X the unnormalized forward DFT of a row of A D, column t of Y is
+    sqrt(n/l) times the row's coefficient on column R_t of F_r:
+      R_t = 0        : X[0] / sqrt(l)
+      R_t = n/2      : X[n/2] / sqrt(l)
+      R_t < n/2      : sqrt(2/l) Re X[R_t]
+      R_t > n/2      : -sqrt(2/l) Im X[n - R_t]
+    """
+    n = A.shape[1]
+    l = len(R)
+    X = np.fft.fft(A * d[None, :], axis=1)
+    Y = np.empty((A.shape[0], l))
+    for t, q in enumerate(np.asarray(R)):
+        if q == 0:
+            Y[:, t] = X[:, 0].real / np.sqrt(l)
+        elif 2 * q == n:
+            Y[:, t] = X[:, n // 2].real / np.sqrt(l)
+        elif 2 * q < n:
+            Y[:, t] = np.sqrt(2.0 / l) * X[:, q].real
+        else:
+            Y[:, t] = -np.sqrt(2.0 / l) * X[:, n - q].imag
+    return Y
+
+
+# ---------------------------------------------------------------------------
 # Stage B: Direct SVD (Section 5.1)
 # ---------------------------------------------------------------------------
 
@@ -180,8 +242,10 @@ def rsvd(A, k, p, q=0, *, seed=0, stream=0, sketch="gaussian", dtype=np.float64,
 
     Stage A is Algorithm 4.4 for the Gaussian sketch (it reduces to Algorithm
     4.1 at q = 0) or Algorithm 4.5 for the SRFT (q = 0 only: Section 4.6 notes
-    that the structured sketch does not speed up the power scheme).  Stage B
-    is Algorithm 5.1 followed by truncation to rank k.
+    that the structured sketch does not speed up the power scheme) -- "srft"
+    is the real tailoring (real Fourier basis, real Y), "srft_complex" the
+    complex case the paper writes out.  Stage B is Algorithm 5.1 followed by
+    truncation to rank k.
 
     A must already hold exactly the values the working-precision path reads
     (an FP32 matrix promoted to FP64).  The Gaussian Omega is drawn by
@@ -200,15 +264,18 @@ def rsvd(A, k, p, q=0, *, seed=0, stream=0, sketch="gaussian", dtype=np.float64,
             Omega = gaussian_test_matrix(n, l, seed, stream, dtype)
         out["Omega"] = Omega
         Q = randomized_subspace_iteration(A, Omega, q)
-    elif sketch == "srft":
+    elif sketch in ("srft", "srft_complex"):
         if q != 0:
             raise ValueError("the SRFT range finder is used with q = 0")
         d = philox.srft_signs(n, seed, stream)
         R = philox.srft_sample(n, l, seed, stream)
         out["d"], out["R"] = d, R
-        Q = fast_randomized_range_finder(A, d, R)
+        if sketch == "srft":   # real tailoring (real A): Y real
+            Q, _ = qr_pos(real_srft_sketch(A, d, R))
+        else:                  # complex case of Section 4.6
+            Q = fast_randomized_range_finder(A, d, R)
     else:
-        raise ValueError("sketch must be 'gaussian' or 'srft'")
+        raise ValueError("sketch must be 'gaussian', 'srft' or 'srft_complex'")
     U, S, V, B = direct_svd(A, Q)
     Uk, Sk, Vk = truncate(U, S, V, k)
     out.update(Q=Q, B=B, U=U, S=S, V=V, Uk=Uk, Sk=Sk, Vk=Vk)

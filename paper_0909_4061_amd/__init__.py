@@ -96,11 +96,8 @@ def _check_matrix(A, name="A"):
         raise ValueError(f"{name} must be float32 or float64")
 
 
-def _elem_dtype(pr, complex_out=False):
-    base = torch.float64 if pr.dtype == RSVD_F64 else torch.float32
-    if complex_out:
-        return torch.complex128 if base == torch.float64 else torch.complex64
-    return base
+def _elem_dtype(pr):
+    return torch.float64 if pr.dtype == RSVD_F64 else torch.float32
 
 
 class Workspace:
@@ -129,9 +126,8 @@ def rsvd_range_finder(A, k, p, *, q=0, sketch="gaussian", prec="native", seed=0,
                       Q=None, ws=None):
     pr = _prob_for(A, k, p, q, sketch, prec, seed, stream_id)
     l = k + p
-    cplx = pr.sketch == RSVD_SRFT
     if Q is None:
-        Q = torch.empty(A.shape[0], l, dtype=_elem_dtype(pr, cplx), device=A.device)
+        Q = torch.empty(A.shape[0], l, dtype=_elem_dtype(pr), device=A.device)
     ws = ws or Workspace(pr, A.device)
     h = handle(A.device)
     _lib.check(h.lib.rsvd_range_finder(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(Q), ws.ptr, ws.nbytes,
@@ -194,6 +190,18 @@ def rsvd(A, k, p=10, q=0, *, sketch="gaussian", prec="native", seed=0, stream_id
     return U, S, V
 
 
+def rsvd_sketch(A, k, p, *, sketch="gaussian", prec="native", seed=0, stream_id=0, Y=None, ws=None):
+    """Y = A Omega (m x (k+p)) with the test matrix the range finder draws, not orthonormalized."""
+    pr = _prob_for(A, k, p, 0, sketch, prec, seed, stream_id)
+    if Y is None:
+        Y = torch.empty(A.shape[0], k + p, dtype=_elem_dtype(pr), device=A.device)
+    ws = ws or Workspace(pr, A.device)
+    h = handle(A.device)
+    _lib.check(h.lib.rsvd_sketch(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(Y), ws.ptr, ws.nbytes, _stream(A.device)),
+               "rsvd_sketch")
+    return Y
+
+
 def rsvd_draw_omega(n, k, p, *, dtype=torch.float32, seed=0, stream_id=0, device="cuda"):
     """The Gaussian test matrix the range finder draws (n x (k+p))."""
     pr = problem(max(n, k + p), n, k, p, 0, dtype=dtype, seed=seed, stream_id=stream_id)
@@ -201,6 +209,17 @@ def rsvd_draw_omega(n, k, p, *, dtype=torch.float32, seed=0, stream_id=0, device
     h = handle(Om.device)
     _lib.check(h.lib.rsvd_draw_omega(h.ptr, ctypes.byref(pr), _ptr(Om), _stream(Om.device)), "rsvd_draw_omega")
     return Om
+
+
+def rsvd_draw_srft(n, k, p, *, dtype=torch.float32, seed=0, stream_id=0, device="cuda"):
+    """The SRFT ingredients the range finder draws: signs d (n, float64) and frequencies R (k+p, int32)."""
+    pr = problem(max(n, k + p), n, k, p, 0, dtype=dtype, sketch="srft", seed=seed, stream_id=stream_id)
+    d = torch.empty(n, dtype=torch.float64, device=device)
+    R = torch.empty(k + p, dtype=torch.int32, device=device)
+    h = handle(d.device)
+    _lib.check(h.lib.rsvd_draw_srft(h.ptr, ctypes.byref(pr), _ptr(d), _ptr(R), _stream(d.device)),
+               "rsvd_draw_srft")
+    return d, R
 
 
 def rsvd_orth(Y, want_r=True, ws=None):

@@ -29,10 +29,10 @@ RSVD_MAX_L = 128
 EXPORTS = [
     "rsvd_create", "rsvd_destroy", "rsvd_validate", "rsvd_workspace_bytes", "rsvd_status_string",
     "rsvd_range_finder", "rsvd_power_iter", "rsvd_project", "rsvd_svd",
-    "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
+    "rsvd_sketch", "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
     "rsvd_profile_enable", "rsvd_profile_read",
 ]
-KERNEL_KINDS = ["stream_nn", "stream_tn", "small_gemm", "gram", "chol", "jacobi", "pack"]
+KERNEL_KINDS = ["stream_nn", "stream_tn", "small_gemm", "gram", "chol", "jacobi", "pack", "srft"]
 
 
 class RsvdProblem(ctypes.Structure):
@@ -76,8 +76,9 @@ def load():
         "rsvd_power_iter": ([vp, prob, vp, vp, vp, sz, vp], i32),
         "rsvd_project": ([vp, prob, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_svd": ([vp, prob, vp, vp, vp, vp, vp, vp, sz, vp], i32),
+        "rsvd_sketch": ([vp, prob, vp, vp, vp, sz, vp], i32),
         "rsvd_draw_omega": ([vp, prob, vp, vp], i32),
-        "rsvd_draw_srft": ([vp, prob, vp, vp, vp, sz, vp], i32),
+        "rsvd_draw_srft": ([vp, prob, vp, vp, vp], i32),
         "rsvd_orth": ([vp, prob, i64, vp, vp, vp, sz, vp], i32),
         "rsvd_device_status": ([vp, vp, ctypes.POINTER(i32)], i32),
         "rsvd_profile_enable": ([vp, i32], i32),

@@ -52,7 +52,8 @@ struct Plan {
   int esize;
   int dtype, prec;
   Split nn, tn;
-  size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rinv, RinvT, XU, XV, Uh, sig, flags, srft_perm, total;
+  size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rinv, RinvT, XU, XV, Uh, sig, flags, srft_d, srft_R,
+      total;
 };
 
 bool valid_enum(int32_t v, int32_t lo, int32_t hi) { return v >= lo && v <= hi; }
@@ -68,7 +69,11 @@ rsvd_status validate(const rsvd_problem* pr) {
   if (l > std::min(pr->m, pr->n)) return RSVD_E_INVAL;
   if (l > RSVD_MAX_L) return RSVD_E_UNSUPPORTED;
   if (pr->dtype == RSVD_F64 && pr->prec != RSVD_NATIVE) return RSVD_E_UNSUPPORTED;
-  if (pr->sketch == RSVD_SRFT) return RSVD_E_UNSUPPORTED;
+  if (pr->sketch == RSVD_SRFT) {
+    // One row of A, as n/2 complex values, is transformed in a workgroup's LDS.
+    const int64_t nmax = int64_t{2} << (pr->dtype == RSVD_F64 ? SRFT_MAX_LOGN_F64 : SRFT_MAX_LOGN_F32);
+    if (pr->q != 0 || pr->n < 8 || pr->n > nmax || (pr->n & (pr->n - 1)) != 0) return RSVD_E_UNSUPPORTED;
+  }
   return RSVD_OK;
 }
 
@@ -116,7 +121,8 @@ Plan make_plan(const rsvd_problem* pr) {
   P.Uh = take(ll8);
   P.sig = take((size_t)P.l * 8);
   P.flags = take(64);
-  P.srft_perm = take((size_t)P.n * 4);
+  P.srft_d = take(pr->sketch == RSVD_SRFT ? (size_t)P.n * 8 : 0);
+  P.srft_R = take(pr->sketch == RSVD_SRFT ? (size_t)P.l * 4 : 0);
   P.total = off;
   return P;
 }
@@ -284,6 +290,41 @@ rsvd_status apply_and_orth(const Ctx& c, const rsvd_problem* pr, bool trans, con
   return orth(c, sp.S > 1, sp, y, rows, Q, nullptr);
 }
 
+// Sum the S split-K partial products (rows x l) into `out` in a fixed order.
+rsvd_status reduce_parts(const Ctx& c, const Split& sp, int64_t rows, void* out) {
+  GramParams g{};
+  g.mode = GRAM_FROM_PART;
+  g.part = c.at<void>(c.P.part);
+  g.S = sp.S;
+  g.Lp = c.P.Lp;
+  g.yout = out;
+  g.ldy = c.P.l;
+  g.rows = rows;
+  g.l = (int32_t)c.P.l;
+  g.Lg = c.P.Lg;
+  g.do_gram = 0;
+  g.gpart = c.at<double>(c.P.gpart);
+  RSVD_TRY(launch_gram_partial(c.P.dtype, g, c.st));
+  return RSVD_OK;
+}
+
+// Y = A Omega (m x l) for either test matrix, into `y`.
+rsvd_status sketch(const Ctx& c, const rsvd_problem* pr, const void* A, void* y) {
+  const Plan& P = c.P;
+  if (pr->sketch == RSVD_SRFT) {
+    double* d = c.at<double>(P.srft_d);
+    int32_t* R = c.at<int32_t>(P.srft_R);
+    RSVD_TRY(launch_srft_draw(d, R, pr->n, (int32_t)P.l, pr->seed, pr->stream_id, c.st));
+    Timed t_(c.h, RSVD_KERNEL_SRFT, c.st);
+    RSVD_TRY(launch_srft_rows(pr->dtype, A, pr->lda, pr->m, pr->n, (int32_t)P.l, d, R, y, c.st));
+    return RSVD_OK;
+  }
+  void* omega = c.at<void>(P.omega);
+  RSVD_TRY(launch_omega(pr->dtype, omega, pr->n, (int32_t)P.l, pr->seed, pr->stream_id, c.st));
+  return gemm(c, pr->prec, false, A, pr->lda, P.m, P.n, omega, P.l, (int32_t)P.l, y, P.l, P.nn,
+              P.nn.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
+}
+
 struct Prologue {
   rsvd_status status;
   Plan plan;
@@ -396,9 +437,24 @@ rsvd_status rsvd_range_finder(rsvd_handle h, const rsvd_problem* pr, const void*
   if (pro.status != RSVD_OK) return pro.status;
   if (!A || !Q) return RSVD_E_INVAL;
   const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h};
-  void* omega = c.at<void>(c.P.omega);
-  RSVD_TRY(launch_omega(pr->dtype, omega, pr->n, (int32_t)c.P.l, pr->seed, pr->stream_id, stream));
-  return apply_and_orth(c, pr, false, A, omega, Q);
+  void* y = c.at<void>(c.P.Y);
+  const bool parts = pr->sketch == RSVD_GAUSSIAN && c.P.nn.S > 1;
+  // Y = A Omega (left as split-K partials for the Gaussian GEMM when S > 1),
+  // then CholeskyQR2 (Algorithm 4.1 step 3 / Algorithm 4.5 step 3).
+  rsvd_status s = sketch(c, pr, A, y);
+  if (s != RSVD_OK) return s;
+  return orth(c, parts, c.P.nn, y, pr->m, Q, nullptr);
+}
+
+rsvd_status rsvd_sketch(rsvd_handle h, const rsvd_problem* pr, const void* A, void* Y, void* ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  Prologue pro = prologue(h, pr, ws, ws_bytes);
+  if (pro.status != RSVD_OK) return pro.status;
+  if (!A || !Y) return RSVD_E_INVAL;
+  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h};
+  rsvd_status s = sketch(c, pr, A, Y);
+  if (s != RSVD_OK || pr->sketch == RSVD_SRFT || c.P.nn.S == 1) return s;
+  return reduce_parts(c, c.P.nn, pr->m, Y);
 }
 
 rsvd_status rsvd_power_iter(rsvd_handle h, const rsvd_problem* pr, const void* A, void* Q, void* ws,
@@ -428,20 +484,7 @@ rsvd_status rsvd_project(rsvd_handle h, const rsvd_problem* pr, const void* A, c
   rsvd_status s = gemm(c, pr->prec, true, A, pr->lda, P.n, P.m, Q, P.l, (int32_t)P.l, Bt, P.l, sp,
                        sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
   if (s != RSVD_OK || sp.S == 1) return s;
-  GramParams g{};
-  g.mode = GRAM_FROM_PART;
-  g.part = c.at<void>(P.part);
-  g.S = sp.S;
-  g.Lp = P.Lp;
-  g.yout = Bt;
-  g.ldy = P.l;
-  g.rows = P.n;
-  g.l = (int32_t)P.l;
-  g.Lg = P.Lg;
-  g.do_gram = 0;
-  g.gpart = c.at<double>(P.gpart);
-  RSVD_TRY(launch_gram_partial(P.dtype, g, stream));
-  return RSVD_OK;
+  return reduce_parts(c, sp, P.n, Bt);
 }
 
 rsvd_status rsvd_svd(rsvd_handle h, const rsvd_problem* pr, const void* Bt, const void* Q, void* U, void* S,
@@ -488,16 +531,14 @@ rsvd_status rsvd_draw_omega(rsvd_handle h, const rsvd_problem* pr, void* Omega, 
   return RSVD_OK;
 }
 
-rsvd_status rsvd_draw_srft(rsvd_handle h, const rsvd_problem* pr, double* d, int32_t* R, void* ws,
-                           size_t ws_bytes, hipStream_t stream) {
-  (void)h;
-  (void)pr;
-  (void)d;
-  (void)R;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
-  return RSVD_E_UNSUPPORTED;
+rsvd_status rsvd_draw_srft(rsvd_handle h, const rsvd_problem* pr, double* d, int32_t* R, hipStream_t stream) {
+  if (!h || !d || !R) return RSVD_E_INVAL;
+  const rsvd_status v = validate(pr);
+  if (v != RSVD_OK) return v;
+  if (pr->sketch != RSVD_SRFT) return RSVD_E_INVAL;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
+  RSVD_TRY(launch_srft_draw(d, R, pr->n, pr->k + pr->p, pr->seed, pr->stream_id, stream));
+  return RSVD_OK;
 }
 
 rsvd_status rsvd_orth(rsvd_handle h, const rsvd_problem* pr, int64_t rows, void* Y, double* R, void* ws,

@@ -120,8 +120,15 @@ hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st);
 // Random test matrices (counter-based Philox4x64-10).
 hipError_t launch_omega(int dtype, void* omega, int64_t n, int32_t l, uint64_t seed,
                         uint64_t stream_id, hipStream_t st);
-hipError_t launch_srft_draw(double* d, int32_t* R, int32_t* perm, int64_t n, int32_t l,
-                            uint64_t seed, uint64_t stream_id, hipStream_t st);
+hipError_t launch_srft_draw(double* d, int32_t* R, int64_t n, int32_t l, uint64_t seed,
+                            uint64_t stream_id, hipStream_t st);
+
+// SRFT sketch Y (m x l, row-major) = A Omega for the real SRFT with signs d
+// and sampled frequencies R; n = 2^(LOGN+1) with 2 <= LOGN <= SRFT_MAX_LOGN_*.
+constexpr int SRFT_MAX_LOGN_F32 = 13;  // n <= 16384
+constexpr int SRFT_MAX_LOGN_F64 = 12;  // n <= 8192
+hipError_t launch_srft_rows(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, int32_t l,
+                            const double* d, const int32_t* R, void* Y, hipStream_t st);
 
 // Small utilities.
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, const int32_t* gate, hipStream_t st);

@@ -7,8 +7,13 @@
 //
 // SRFT (Section 4.6): the diagonal D of random +-1 signs (one thread per
 // coordinate) and the sampler R of l coordinates drawn without replacement by
-// a partial Fisher-Yates shuffle (a single thread: l swaps on a permutation
-// initialised in parallel).
+// a partial Fisher-Yates shuffle of [0, n).  Step t swaps positions t and
+// j_t >= t and emits the value then at position t.  The draws j_t are
+// independent, so the shuffle is resolved in parallel: the value at position
+// x just before step t is x itself unless an earlier step s < t swapped into
+// x (j_s = x); then it is the value that sat at position s just before step s.
+// Each thread follows that chain back for its own t (time strictly decreases,
+// so the walk ends) and needs no permutation array.
 #include "common.hpp"
 #include "philox.hpp"
 
@@ -44,27 +49,42 @@ __global__ __launch_bounds__(256) void omega_kernel(T* __restrict__ omega, int64
     if (j0 + r < l) row[j0 + r] = (T)g[r];
 }
 
-__global__ __launch_bounds__(256) void srft_signs_kernel(double* __restrict__ d, int32_t* __restrict__ perm,
-                                                         int64_t n, uint64_t seed, uint64_t sid) {
+__global__ __launch_bounds__(256) void srft_signs_kernel(double* __restrict__ d, int64_t n, uint64_t seed,
+                                                         uint64_t sid) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const Philox4 w = philox4x64_10((uint64_t)p, sid, 1ull, 0ull, seed, 0ull);
   d[p] = 1.0 - 2.0 * (double)(w.w[0] & 1ull);
-  perm[p] = (int32_t)p;
 }
 
-__global__ void srft_sample_kernel(int32_t* __restrict__ R, int32_t* __restrict__ perm, int64_t n,
-                                   int32_t l, uint64_t seed, uint64_t sid) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  for (int32_t t = 0; t < l; ++t) {
+// One workgroup; l <= RSVD_MAX_L.
+__global__ __launch_bounds__(256) void srft_sample_kernel(int32_t* __restrict__ R, int64_t n, int32_t l,
+                                                          uint64_t seed, uint64_t sid) {
+  __shared__ int32_t J[RSVD_MAX_L];
+  for (int32_t t = threadIdx.x; t < l; t += blockDim.x) {
     const Philox4 w = philox4x64_10((uint64_t)t, sid, 2ull, 0ull, seed, 0ull);
     const double u = philox_uniform(w.w[0]);
     int64_t j = (int64_t)t + (int64_t)floor(u * (double)(n - t));
     if (j > n - 1) j = n - 1;
-    const int32_t a = perm[t];
-    perm[t] = perm[j];
-    perm[j] = a;
-    R[t] = perm[t];
+    J[t] = (int32_t)j;
+  }
+  __syncthreads();
+  for (int32_t t = threadIdx.x; t < l; t += blockDim.x) {
+    int32_t x = J[t];
+    int32_t time = t;
+    for (;;) {
+      int32_t last = -1;
+      for (int32_t s = time - 1; s >= 0; --s) {
+        if (J[s] == x) {
+          last = s;
+          break;
+        }
+      }
+      if (last < 0) break;
+      x = last;
+      time = last;
+    }
+    R[t] = x;
   }
 }
 
@@ -86,11 +106,11 @@ hipError_t launch_omega(int dtype, void* omega, int64_t n, int32_t l, uint64_t s
   return hipGetLastError();
 }
 
-hipError_t launch_srft_draw(double* d, int32_t* R, int32_t* perm, int64_t n, int32_t l, uint64_t seed,
-                            uint64_t sid, hipStream_t st) {
-  hipLaunchKernelGGL(srft_signs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, perm, n,
-                     seed, sid);
-  hipLaunchKernelGGL(srft_sample_kernel, dim3(1), dim3(64), 0, st, R, perm, n, l, seed, sid);
+hipError_t launch_srft_draw(double* d, int32_t* R, int64_t n, int32_t l, uint64_t seed, uint64_t sid,
+                            hipStream_t st) {
+  if (l < 1 || l > RSVD_MAX_L || l > n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(srft_signs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, n, seed, sid);
+  hipLaunchKernelGGL(srft_sample_kernel, dim3(1), dim3(128), 0, st, R, n, l, seed, sid);
   return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
-def compare_to_oracle(A64, out_gpu, k, p, q, seed, dtype, stream_id=0):
+def compare_to_oracle(A64, out_gpu, k, p, q, seed, dtype, stream_id=0, sketch="gaussian"):
     """Run the oracle on exactly the matrix the GPU read and return error figures.
 
     out_gpu = (U, S, V, Q) as numpy arrays.  Singular vectors are compared after
@@ -17,7 +17,7 @@ def compare_to_oracle(A64, out_gpu, k, p, q, seed, dtype, stream_id=0):
     of the same range is equally valid).
     """
     U, S, V, Q = out_gpu
-    ref = orsvd.rsvd(A64, k, p, q, seed=seed, stream=stream_id, dtype=dtype)
+    ref = orsvd.rsvd(A64, k, p, q, seed=seed, stream=stream_id, dtype=dtype, sketch=sketch)
     Uo, Vo = orsvd.normalize_signs(ref["Uk"], ref["Vk"])
     Ug, Vg = orsvd.normalize_signs(U.astype(np.float64), V.astype(np.float64))
     out = {

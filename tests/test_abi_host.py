@@ -61,17 +61,26 @@ def _prob(**kw):
     ({"prec": "bf16x3"}, 4),              # BF16 arithmetic needs FP32 data
     ({"k": 128, "p": 0}, 0),
     ({"k": 1, "p": 0}, 0),
+    # SRFT: q = 0, n a power of two in [8, 16384] (FP32) / [8, 8192] (FP64)
+    ({"n": 1024, "sketch": "srft"}, 0),
+    ({"n": 1024, "sketch": "srft", "q": 1}, 4),
+    ({"n": 1000, "sketch": "srft"}, 4),
+    ({"n": 8192, "sketch": "srft"}, 0),
+    ({"m": 20000, "n": 16384, "sketch": "srft"}, 4),
+    ({"m": 20000, "n": 16384, "sketch": "srft", "dtype": "f32"}, 0),
+    ({"m": 40000, "n": 32768, "sketch": "srft", "dtype": "f32"}, 4),
+    ({"m": 8, "n": 8, "k": 4, "p": 4, "sketch": "srft"}, 0),
+    ({"m": 8, "n": 4, "k": 2, "p": 2, "sketch": "srft"}, 4),
 ])
 def test_validate(lib, kw, expect):
     import torch
-    if kw.get("prec"):
-        pr = _prob(**kw)
-    else:
-        pr = _prob(**kw)
+    kw = dict(kw)
+    if kw.get("dtype") == "f32":
+        kw["dtype"] = torch.float32
+    pr = _prob(**kw)
     assert lib.rsvd_validate(ctypes.byref(pr)) == expect
     ws = lib.rsvd_workspace_bytes(ctypes.byref(pr))
     assert (ws > 0) == (expect == 0)
-    _ = torch
 
 
 def test_bad_enum_is_invalid(lib):
@@ -100,5 +109,7 @@ def test_null_arguments_fail_before_launch(lib):
     assert lib.rsvd_power_iter(None, ctypes.byref(pr), None, None, None, 0, None) == 1
     assert lib.rsvd_project(None, ctypes.byref(pr), None, None, None, None, 0, None) == 1
     assert lib.rsvd_svd(None, ctypes.byref(pr), None, None, None, None, None, None, 0, None) == 1
+    assert lib.rsvd_sketch(None, ctypes.byref(pr), None, None, None, 0, None) == 1
+    assert lib.rsvd_draw_srft(None, ctypes.byref(pr), None, None, None) == 1
     assert lib.rsvd_device_status(None, None, None) == 1
     assert lib.rsvd_create(None, 0) == 1

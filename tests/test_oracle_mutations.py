@@ -55,7 +55,24 @@ def _srft_drops_signs(A, d, R):
     return X[:, np.asarray(R)] / np.sqrt(len(R))
 
 
+def _real_srft_wrong_pair(A, d, R):
+    # sine and cosine columns swapped
+    n = A.shape[1]
+    l = len(R)
+    X = np.fft.fft(A * d[None, :], axis=1)
+    Y = np.empty((A.shape[0], l))
+    for t, q in enumerate(np.asarray(R)):
+        if q == 0 or 2 * q == n:
+            Y[:, t] = X[:, q % n].real / np.sqrt(l)
+        elif 2 * q < n:
+            Y[:, t] = -np.sqrt(2.0 / l) * X[:, q].imag
+        else:
+            Y[:, t] = np.sqrt(2.0 / l) * X[:, n - q].real
+    return Y
+
+
 MUTATIONS = [
+    ("real_srft_sketch", _real_srft_wrong_pair, pins.test_real_srft_sketch_equals_definition, {"n": 32, "l": 6}),
     ("randomized_subspace_iteration", _no_power_steps, pins.test_power_scheme_theorem_9_2, {"q": 1}),
     ("randomized_subspace_iteration", _transposed_adjoint,
      pins.test_subspace_iteration_spans_power_iteration, {"m": 90, "n": 90}),

@@ -159,14 +159,54 @@ def test_srft_sketch_equals_definition():
     np.testing.assert_allclose(Ofull.conj().T @ Ofull, np.eye(n), atol=1e-12)
 
 
-def test_srft_pipeline_exact_rank():
+def test_real_fourier_basis_is_the_dft_mixed_in_pairs():
+    # F_r = F T with F the unitary DFT of Section 4.6 and T unitary, pairing
+    # frequencies q and n - q: the real basis spans the same frequencies.
+    n = 16
+    p = np.arange(n)[:, None]
+    F = np.exp(-2j * np.pi * p * np.arange(n)[None, :] / n) / np.sqrt(n)
+    T = np.zeros((n, n), dtype=complex)
+    T[0, 0] = 1.0
+    T[n // 2, n // 2] = 1.0
+    for q in range(1, n // 2):
+        T[q, q] = T[n - q, q] = 1 / np.sqrt(2)            # cosine column
+        T[q, n - q], T[n - q, n - q] = 1j / np.sqrt(2), -1j / np.sqrt(2)  # sine column
+    assert np.allclose(T.conj().T @ T, np.eye(n))
+    Fr = rsvd.real_fourier_matrix(n)
+    np.testing.assert_allclose(F @ T, Fr, atol=1e-13)
+    np.testing.assert_allclose(Fr.T @ Fr, np.eye(n), atol=1e-13)
+
+
+@pytest.mark.parametrize("n,l", [(32, 6), (64, 64), (16, 3)])
+def test_real_srft_sketch_equals_definition(n, l):
+    rng = np.random.default_rng(n + l)
+    A = rng.standard_normal((9, n))
+    d = philox.srft_signs(n, seed=4)
+    R = philox.srft_sample(n, l, seed=4)
+    np.testing.assert_allclose(rsvd.real_srft_sketch(A, d, R), A @ rsvd.real_srft_test_matrix(n, d, R),
+                               atol=1e-12)
+
+
+def test_real_srft_full_sample_is_orthogonal_mixing():
+    # l = n: Omega = D F_r is orthogonal, so Y = A Omega preserves all singular values
+    n = 32
+    A = np.random.default_rng(3).standard_normal((40, n))
+    d = philox.srft_signs(n, seed=1)
+    R = philox.srft_sample(n, n, seed=1)
+    Y = rsvd.real_srft_sketch(A, d, R)
+    np.testing.assert_allclose(np.linalg.svd(Y, compute_uv=False), np.linalg.svd(A, compute_uv=False),
+                               rtol=1e-12)
+
+
+@pytest.mark.parametrize("sketch", ["srft", "srft_complex"])
+def test_srft_pipeline_exact_rank(sketch):
     m, n, rank = 64, 32, 5
     sigma = np.zeros(32)
     sigma[:rank] = [4, 3, 2, 1, 0.5]
     A, _, _ = _matrix(m, n, sigma)
-    out = rsvd.rsvd(A, rank, 7, 0, seed=2, sketch="srft")
+    out = rsvd.rsvd(A, rank, 7, 0, seed=2, sketch=sketch)
     np.testing.assert_allclose(out["Sk"], sigma[:rank], rtol=1e-12)
-    assert np.iscomplexobj(out["Q"])
+    assert np.iscomplexobj(out["Q"]) == (sketch == "srft_complex")
     assert evaluate.residual_q(A, out["Q"]) < 1e-12
     assert evaluate.orthonormality_error(out["Q"]) < 1e-13
 
