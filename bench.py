@@ -125,6 +125,109 @@ def run_path(A, k, p, q, prec, steps, warmup, seed):
     return dict(ms_per_step=ms_total / steps, prof=prof, flags=flags, U=U, S=S, V=V)
 
 
+def srft_flops(m, n, l, k):
+    """Flops of the SRFT rSVD per step: the real FFT of every row (2.5 n log2 n
+    each, the usual count for a length-n real transform), CholeskyQR2 of Y
+    (4 m l^2), the projection 2 m n l, the small SVD's Gram n l^2 and the lifts."""
+    import math
+    return 2.5 * m * n * math.log2(n) + 4.0 * m * l * l + 2.0 * m * n * l + n * l * l + 2.0 * (m + n) * l * k
+
+
+def run_srft_workload(A, k, p, prec, steps, warmup, seed):
+    """Stage A alone and the whole rSVD, with the SRFT and with the Gaussian test matrix."""
+    import torch
+    import paper_0909_4061_amd as rs
+
+    m, n = A.shape
+    l = k + p
+    dev = A.device
+    Q = torch.empty(m, l, dtype=A.dtype, device=dev)
+    Bt = torch.empty(n, l, dtype=A.dtype, device=dev)
+    U = torch.empty(m, k, dtype=A.dtype, device=dev)
+    S = torch.empty(k, dtype=A.dtype, device=dev)
+    V = torch.empty(n, k, dtype=A.dtype, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for sketch in ("srft", "gaussian"):
+        pr = rs.problem(m, n, k, p, 0, dtype=A.dtype, sketch=sketch, prec=prec, seed=seed, lda=A.stride(0))
+        ws = rs.Workspace(pr, dev)
+        kw = dict(sketch=sketch, prec=prec, seed=seed, ws=ws)
+
+        def stage_a():
+            rs.rsvd_range_finder(A, k, p, Q=Q, **kw)
+
+        def stage_b():
+            rs.rsvd_project(A, Q, k, p, Bt=Bt, **kw)
+            rs.rsvd_svd(Bt, Q, m, n, k, p, dtype=A.dtype, U=U, S=S, V=V, **kw)
+
+        for _ in range(warmup):
+            stage_a()
+            stage_b()
+        torch.cuda.synchronize()
+        rs.profile_enable(64 * max(steps, 1), dev)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for i in range(steps):
+            stage_a()
+            ev[2 * i + 1].record(stream)
+            stage_b()
+            ev[2 * i + 2].record(stream)
+        torch.cuda.synchronize()
+        a_ms = sum(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)) / steps
+        total_ms = ev[0].elapsed_time(ev[-1]) / steps
+        prof = rs.profile_read(dev)
+        rs.profile_enable(0, dev)
+        flags = rs.device_status(dev)
+        out[sketch] = dict(ms_per_step=total_ms, stage_a_ms=a_ms, prof=prof, flags=flags,
+                           U=U.clone(), S=S.clone(), V=V.clone())
+    return out
+
+
+def srft_roofline(res, m, n, l):
+    launches, total_ms = res["prof"]["srft"]
+    avg_s = total_ms / launches / 1e3
+    bytes_launch = 4.0 * m * n + 4.0 * m * l + 8.0 * n + 4.0 * l
+    achieved = bytes_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "srft_rows_f32",
+            "launches": launches, "avg_us": avg_s * 1e6, "per_launch": {"bytes": bytes_launch}}
+
+
+def main_srft(args, A, sigma):
+    import numpy as np
+    m, n = A.shape
+    k, p = args.k, args.p
+    l = k + p
+    res = run_srft_workload(A, k, p, args.srft_prec, args.steps, args.warmup, args.seed)
+    gflops = 2.0 * m * n * l * 2 + 4.0 * m * l * l + n * l * l + 2.0 * (m + n) * l * k
+    paths = {}
+    for sk, r in res.items():
+        err = spectral_norm_residual(A, r["U"], r["S"], r["V"]) / sigma[k]
+        sig_err = float(np.max(np.abs(r["S"].double().cpu().numpy() - sigma[:k]) / sigma[:k]))
+        fl = srft_flops(m, n, l, k) if sk == "srft" else gflops
+        s = r["ms_per_step"] / 1e3
+        paths[sk] = {"ms_per_step": r["ms_per_step"], "stage_a_ms": r["stage_a_ms"], "tflops": fl / s / 1e12,
+                     "a_read_gbs_stage_a": 4.0 * m * n / (r["stage_a_ms"] / 1e3) / 1e9,
+                     "err_ratio": err, "sigma_rel_err_vs_construction": sig_err, "flags": r["flags"],
+                     "kernel_ms_per_step": {f: v[1] / args.steps for f, v in r["prof"].items()}}
+        print(f"# {sk}: {r['ms_per_step']:.3f} ms/step (stage A {r['stage_a_ms']:.3f} ms), err ratio {err:.4f}",
+              file=sys.stderr, flush=True)
+    hp = paths["srft"]
+    line = {
+        "metric": "rSVD TFLOP/s + HBM GB/s at stated ||A-USV*||/sigma_{k+1}; SRFT vs Gaussian sketch",
+        "value": hp["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": hp["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "prec": args.srft_prec, "data": "synthetic",
+        "config": {"workload": f"SRFT vs Gaussian sketch rSVD, FP32 {m}x{n}, spectral gap, k={k}, p={p}, q=0",
+                   "m": m, "n": n, "k": k, "p": p, "q": 0, "sketch": "srft"},
+        "err_ratio": hp["err_ratio"], "roofline": srft_roofline(res["srft"], m, n, l),
+        "stage_a_speedup_vs_gaussian": paths["gaussian"]["stage_a_ms"] / hp["stage_a_ms"],
+        "paths": paths,
+    }
+    print(json.dumps(line))
+
+
 def measured_traffic(family, prec, m, n, l):
     """Counter-measured HBM bytes per launch, or None if the kernel source or shape differs."""
     import hashlib
@@ -210,6 +313,11 @@ def main():
     ap.add_argument("--input", choices=["construct", "randn"], default="construct",
                     help="construct: A = U diag(1/j) V^T (the workload); randn: i.i.d. Gaussian A of the "
                          "same shape, for hardware-counter runs only (byte counts do not depend on values)")
+    ap.add_argument("--workload", choices=["power", "srft"], default="power",
+                    help="power: the power-iteration rSVD (default); srft: SRFT vs Gaussian sketch, "
+                         "FP32 32768 x 16384 with a spectral gap, k = 50, p = 78, q = 0")
+    ap.add_argument("--srft-prec", choices=["bf16x3", "native"], default="bf16x3",
+                    help="arithmetic of the GEMMs that stream A in the srft workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain device copy of A (known size) before the paths, to scale "
                          "HBM byte counters in profiling runs")
@@ -224,12 +332,14 @@ def main():
     import torch
     from workloads import build_matrix_torch, spectrum
 
+    if args.workload == "srft":
+        args.m, args.n, args.k, args.p, args.q = 32768, 16384, 50, 78, 0
     m, n, k, p, q = args.m, args.n, args.k, args.p, args.q
     l = k + p
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t = time.perf_counter()
-    sigma = spectrum("inv", min(m, n))
+    sigma = spectrum("inv" if args.workload == "power" else "gap", min(m, n))
     if args.input == "construct":
         A = build_matrix_torch(m, n, sigma, seed=args.seed, dtype=torch.float32, device=dev)
     else:
@@ -245,6 +355,10 @@ def main():
         print(f"# calibration copy: {A.numel() * A.element_size()} bytes read and written",
               file=sys.stderr, flush=True)
         del Ac
+
+    if args.workload == "srft":
+        main_srft(args, A, sigma)
+        return
 
     flops = algorithmic_flops(m, n, l, k, q)
     hbm = algorithmic_bytes(m, n, l, q)

@@ -14,15 +14,20 @@
 //
 // Per row (n = 2N, N = 2^LOGN):
 //   * z_j = x_{2j} + i x_{2j+1}, a complex sequence of length N, is read
-//     straight from HBM (one 8- or 16-byte load per complex value) with the
+//     straight from HBM (one 8- or 16-byte buffer load per complex value, the
+//     next row prefetched while the current one is transformed) with the
 //     signs of D applied on the fly;
 //   * P passes of a radix-E Stockham FFT (the self-sorting formulation of
 //     Govindaraju et al., SC'08): each thread holds one radix-E butterfly in
-//     registers, twiddles come from a quarter-wave cosine table in LDS, and
-//     the N values live in LDS between passes under an XOR swizzle that keeps
-//     the stride-E stores of the first pass free of bank conflicts;
+//     registers and the N values live in LDS between passes, with one pad
+//     slot after every E values, which keeps the stride-E stores of the first
+//     pass free of bank conflicts and makes every LDS access a per-thread
+//     base plus a compile-time offset; the twiddles of the second pass come
+//     from an LDS table laid out [r][k] (conflict-free, offsets known at
+//     compile time);
 //   * the last radix-F pass is pruned: only the 2l bins Z_k, Z_{N-k} the
-//     sampled columns need are evaluated, each as an F-term sum;
+//     sampled columns need are evaluated, one per thread, each as an F-term
+//     sum whose twiddles w^r are powers of one two-level table lookup;
 //   * X_k = E_k + e^{-2 pi i k / n} O_k with E_k = (Z_k + conj Z_{N-k}) / 2 and
 //     O_k = (Z_k - conj Z_{N-k}) / 2i, the standard real-from-half-length
 //     complex FFT identity, gives the sampled row of Y.
@@ -147,22 +152,6 @@ struct RegDFT<1> {
   __device__ __forceinline__ static void run(V (&)[1]) {}
 };
 
-// exp(-2 pi i idx / N) for 0 <= idx < N from ct[i] = cos(2 pi i / N), 0 <= i <= N/4.
-template <typename V, typename T, int LOGN>
-__device__ __forceinline__ V root_n(const T* ct, uint32_t idx) {
-  constexpr uint32_t Q = (1u << LOGN) / 4;
-  const uint32_t qd = idx >> (LOGN - 2);
-  const uint32_t rr = idx & (Q - 1);
-  const T c0 = ct[rr], s0 = ct[Q - rr];
-  T c = (qd & 1) ? -s0 : c0;
-  T s = (qd & 1) ? c0 : s0;
-  if (qd & 2) {
-    c = -c;
-    s = -s;
-  }
-  return make2<V>(c, -s);
-}
-
 struct SrftRowParams {
   const void* A;
   int64_t lda;
@@ -181,146 +170,261 @@ struct SrftGeom {
   static constexpr int E = 1 << LOGE;               // radix of the full passes
   static constexpr int P = (LOGN - 1) / LOGE;       // number of full passes
   static constexpr int NSF = 1 << (P * LOGE);       // sub-transform length entering the pruned pass
-  static constexpr int F = N / NSF;                 // radix of the pruned pass, 2..E
+  static constexpr int LOGF = LOGN - P * LOGE;
+  static constexpr int F = 1 << LOGF;               // radix of the pruned pass, 2..E
   static constexpr int NB = N / E;                  // butterflies per full pass
   static constexpr int THREADS = NB > 128 ? NB : 128;
-  static constexpr size_t LDS = N * 2 * sizeof(T) + (N / 4 + 1) * sizeof(T);
+  static constexpr int NPAD = N + (N >> LOGE);      // one pad slot after every E values
+  static constexpr int BPT = (2 * RSVD_MAX_L + THREADS - 1) / THREADS;  // sampled bins per thread
+  static constexpr int TWP = P >= 2 ? E * E : 1;     // twiddles of the second full pass, [r][k]
+  static constexpr int LOGLO = (LOGN + 1) / 2;       // w_N^b = hi[b >> LOGLO] lo[b mod 2^LOGLO]
+  static constexpr int NLO = 1 << LOGLO, NHI = N >> LOGLO;
+  static constexpr size_t LDS = (size_t)(TWP + NLO + NHI + NPAD + 2 * RSVD_MAX_L) * 2 * sizeof(T);
+  static_assert(P <= 2, "at most two full passes");
 };
 
-template <int LOGE>
-__device__ __forceinline__ int swz(int i) {
-  return i ^ ((i >> LOGE) & ((1 << LOGE) - 1));
+// Raw buffer loads: the row's base address and size live in a scalar
+// resource, so the per-element offsets are a thread constant plus an SGPR.
+constexpr int kBufferWord3 = 0x00020000;
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T* row, int64_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(row), (short)0, (int)(n * (int64_t)sizeof(T)),
+                                           kBufferWord3);
 }
 
-template <typename T, int LOGN>
-__global__ __launch_bounds__(256) void srft_rows_kernel(SrftRowParams p) {
+// One complex value: a single 8- / 16-byte load when the row allows it (VEC),
+// else its two parts separately.
+template <bool VEC>
+__device__ __forceinline__ f32x2 load_pair(__amdgpu_buffer_rsrc_t rs, int voff, int soff, f32x2*) {
+  if constexpr (VEC) {
+    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+  } else {
+    f32x2 z;
+    z.x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+    z.y = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + 4, soff, 0));
+    return z;
+  }
+}
+
+template <bool VEC>
+__device__ __forceinline__ f64x2 load_pair(__amdgpu_buffer_rsrc_t rs, int voff, int soff, f64x2*) {
+  if constexpr (VEC) {
+    return __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+  } else {
+    f64x2 z;
+    z.x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+    z.y = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff + 8, soff, 0));
+    return z;
+  }
+}
+
+// x with its sign flipped when bit `pos` (0..31) of `word` is set: one shift
+// and one three-input bit operation, x ^ ((word << (31 - pos)) & 0x80000000)
+// (truth table 0x6C: the middle operand xor the AND of the outer two).
+__device__ __forceinline__ uint32_t flip_bits(uint32_t x, uint32_t word, int pos) {
+  return __builtin_amdgcn_bitop3_b32(word << (31 - pos), x, 0x80000000u, 0x6C);
+}
+__device__ __forceinline__ float flip_if(float x, uint32_t word, int pos) {
+  return __builtin_bit_cast(float, flip_bits(__builtin_bit_cast(uint32_t, x), word, pos));
+}
+__device__ __forceinline__ double flip_if(double x, uint32_t word, int pos) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t hi = flip_bits((uint32_t)(b >> 32), word, pos);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (b & 0xffffffffull));
+}
+
+// w^r for r = 1..F-1 from w^1, each by one complex product of two earlier
+// powers (squaring at powers of two), so no power is more than log2(r) + 1
+// products deep.
+template <int F, typename V>
+__device__ __forceinline__ void unit_powers(V (&w)[F], V w1) {
+  w[1] = w1;
+#pragma unroll
+  for (int r = 2; r < F; ++r) {
+    const int hb = 1 << (31 - __builtin_clz(r));  // highest power of two <= r
+    w[r] = hb == r ? cmul(w[r / 2], w[r / 2]) : cmul(w[hb], w[r - hb]);
+  }
+}
+
+template <typename T, int LOGN, bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void srft_rows_kernel(SrftRowParams p) {
   typedef typename Vec2<T>::type V;
   typedef SrftGeom<T, LOGN> G;
-  constexpr int N = G::N, E = G::E, LOGE = G::LOGE, P = G::P, NSF = G::NSF, F = G::F, NB = G::NB;
-  __shared__ V data[N];
-  __shared__ T ct[N / 4 + 1];
+  constexpr int N = G::N, E = G::E, LOGE = G::LOGE, P = G::P, NSF = G::NSF, F = G::F, NB = G::NB,
+                THREADS = G::THREADS, BPT = G::BPT;
+  constexpr int SW = (2 * E + 31) / 32;  // sign words per thread
+  __shared__ V twp[G::TWP];              // twp[r * E + k] = w_{E^2}^{r k}
+  __shared__ V tlo[G::NLO];              // w_N^j, j < NLO
+  __shared__ V thi[G::NHI];              // w_N^{j NLO}, j < NHI
+  __shared__ V data[G::NPAD];            // the row's N values, padded
+  __shared__ V zbuf[2 * RSVD_MAX_L];     // the sampled bins Z_k (first l) and Z_{N-k} (next l)
   const int tid = threadIdx.x;
+  const int l = p.l;
 
-  for (int i = tid; i <= N / 4; i += blockDim.x) ct[i] = (T)cospi(2.0 * (double)i / (double)N);
+  if constexpr (P >= 2) {
+    for (int j = tid; j < E * E; j += THREADS) {
+      double sv, cv;
+      sincospi(2.0 * (double)((j / E) * (j % E)) / (double)(E * E), &sv, &cv);
+      twp[j] = make2<V>((T)cv, (T)(-sv));
+    }
+  }
+  for (int j = tid; j < G::NLO; j += THREADS) {
+    double sv, cv;
+    sincospi(2.0 * (double)j / (double)N, &sv, &cv);
+    tlo[j] = make2<V>((T)cv, (T)(-sv));
+  }
+  for (int j = tid; j < G::NHI; j += THREADS) {
+    double sv, cv;
+    sincospi(2.0 * (double)(j * G::NLO) / (double)N, &sv, &cv);
+    thi[j] = make2<V>((T)cv, (T)(-sv));
+  }
 
-  // Signs of D for the 2E real entries this thread loads (bit 2r: real part of
-  // its r-th complex value, bit 2r+1: imaginary part).
-  uint64_t sbits = 0;
+  // Signs of D for the 2E real entries this thread loads in the first pass:
+  // bit 2r (real part) and 2r+1 (imaginary part) of its r-th complex value.
+  uint32_t sw[SW];
+#pragma unroll
+  for (int w = 0; w < SW; ++w) sw[w] = 0;
   if constexpr (P >= 1) {
     if (tid < NB) {
 #pragma unroll
       for (int r = 0; r < E; ++r) {
         const int c = tid + r * NB;
-        sbits |= (uint64_t)(p.d[2 * c] < 0.0) << (2 * r);
-        sbits |= (uint64_t)(p.d[2 * c + 1] < 0.0) << (2 * r + 1);
+        const int b0 = 2 * r, b1 = 2 * r + 1;
+        sw[b0 >> 5] |= (uint32_t)(p.d[2 * c] < 0.0) << (b0 & 31);
+        sw[b1 >> 5] |= (uint32_t)(p.d[2 * c + 1] < 0.0) << (b1 & 31);
       }
     }
   } else {
-    if (tid < N) sbits = (uint64_t)(p.d[2 * tid] < 0.0) | ((uint64_t)(p.d[2 * tid + 1] < 0.0) << 1);
+    if (tid < N) sw[0] = (uint32_t)(p.d[2 * tid] < 0.0) | ((uint32_t)(p.d[2 * tid + 1] < 0.0) << 1);
   }
 
-  // Sampled column owned by this thread: the bins it needs, the post-twiddle
-  // e^{-2 pi i k / n} and the output scale.
-  const bool has_col = tid < p.l;
-  int zb1 = 0, zb2 = 0, kind = 0;
+  // The bins this thread evaluates in the pruned pass (slot b: Z_{k_b} for
+  // b < l, Z_{N - k_{b-l}} for l <= b < 2l).
+  int bin[BPT];
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    const int b = tid + u * THREADS;
+    bin[u] = -1;
+    if (b < 2 * l) {
+      const int t = b < l ? b : b - l;
+      const int q = p.R[t];
+      const int k = q <= N ? q : 2 * N - q;
+      bin[u] = (b < l ? k : N - k) & (N - 1);
+    }
+  }
+  // The column this thread assembles: post-twiddle e^{-2 pi i k / n} and scale.
+  int kind = 0;
   V pw = make2<V>((T)1, (T)0);
   T scale = (T)0;
-  if (has_col) {
+  if (tid < l) {
     const int q = p.R[tid];
-    int k;
-    if (q <= N) {
-      k = q;
-      kind = (q == 0 || q == N) ? 0 : 1;
-    } else {
-      k = 2 * N - q;
-      kind = 2;
-    }
-    zb1 = k & (N - 1);
-    zb2 = (N - k) & (N - 1);
+    const int k = q <= N ? q : 2 * N - q;
+    kind = q > N ? 2 : ((q == 0 || q == N) ? 0 : 1);
     double sv, cv;
     sincospi((double)k / (double)N, &sv, &cv);
     pw = make2<V>((T)cv, (T)(-sv));
-    scale = (T)(kind == 0 ? 1.0 / sqrt((double)p.l) : sqrt(2.0 / (double)p.l));
+    scale = (T)(kind == 0 ? 1.0 / sqrt((double)l) : sqrt(2.0 / (double)l));
   }
   __syncthreads();
 
-  auto eval_bin = [&](int b) __attribute__((always_inline)) {
-    const int j = b & (NSF - 1);
-    V acc = data[swz<LOGE>(j)];
+  const int voff = tid * (int)sizeof(V);
+  V v[P >= 1 ? E : 1];
+  auto load_row = [&](int64_t row) __attribute__((always_inline)) {
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc(static_cast<const T*>(p.A) + row * p.lda, 2 * (int64_t)N);
+    if constexpr (P >= 1) {
+      if (tid < NB) {
 #pragma unroll
-    for (int r = 1; r < F; ++r)
-      acc += cmul(data[swz<LOGE>(j + r * NSF)], root_n<V, T, LOGN>(ct, (uint32_t)(r * b) & (N - 1)));
-    return acc;
+        for (int r = 0; r < E; ++r) v[r] = load_pair<VEC>(rs, voff, r * NB * (int)sizeof(V), (V*)nullptr);
+      }
+    } else {
+      if (tid < N) v[0] = load_pair<VEC>(rs, voff, 0, (V*)nullptr);
+    }
   };
 
   T* __restrict__ Y = static_cast<T*>(p.Y);
-  for (int64_t row = blockIdx.x; row < p.m; row += gridDim.x) {
-    const T* __restrict__ a = static_cast<const T*>(p.A) + row * p.lda;
+  int64_t row = blockIdx.x;
+  if (row < p.m) load_row(row);
+  for (; row < p.m; row += gridDim.x) {
     if constexpr (P >= 1) {
-      V v[E];
       if (tid < NB) {
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-          const int c = tid + r * NB;
-          V z;
-          if (p.vec) {
-            z = reinterpret_cast<const V*>(a)[c];
-          } else {
-            z.x = a[2 * c];
-            z.y = a[2 * c + 1];
-          }
-          if ((sbits >> (2 * r)) & 1) z.x = -z.x;
-          if ((sbits >> (2 * r + 1)) & 1) z.y = -z.y;
-          v[r] = z;
+          v[r].x = flip_if(v[r].x, sw[(2 * r) >> 5], (2 * r) & 31);
+          v[r].y = flip_if(v[r].y, sw[(2 * r + 1) >> 5], (2 * r + 1) & 31);
         }
         RegDFT<E>::run(v);
       }
       __syncthreads();  // the previous row's pruned pass has read `data`
       if (tid < NB) {
+        V* w0 = data + tid * (E + 1);
 #pragma unroll
-        for (int r = 0; r < E; ++r) data[swz<LOGE>(tid * E + r)] = v[r];
+        for (int r = 0; r < E; ++r) w0[r] = v[r];
       }
       __syncthreads();
-#pragma unroll
-      for (int pass = 1; pass < P; ++pass) {
-        const int Ns = 1 << (pass * LOGE);
-        const int L = Ns * E;
-        const int k = tid & (Ns - 1);
-        if (tid < NB) {
-#pragma unroll
-          for (int r = 0; r < E; ++r) v[r] = data[swz<LOGE>(tid + r * NB)];
-#pragma unroll
-          for (int r = 1; r < E; ++r) v[r] = cmul(v[r], root_n<V, T, LOGN>(ct, (uint32_t)(r * k) * (uint32_t)(N / L)));
-          RegDFT<E>::run(v);
-        }
-        __syncthreads();
-        if (tid < NB) {
-          const int base = (tid / Ns) * L + k;
-#pragma unroll
-          for (int r = 0; r < E; ++r) data[swz<LOGE>(base + r * Ns)] = v[r];
-        }
-        __syncthreads();
-      }
     } else {
       __syncthreads();
       if (tid < N) {
-        V z;
-        z.x = a[2 * tid];
-        z.y = a[2 * tid + 1];
-        if (sbits & 1) z.x = -z.x;
-        if (sbits & 2) z.y = -z.y;
+        V z = v[0];
+        z.x = flip_if(z.x, sw[0], 0);
+        z.y = flip_if(z.y, sw[0], 1);
         data[tid] = z;
       }
       __syncthreads();
     }
-    if (has_col) {
-      const V z1 = eval_bin(zb1);
-      const V z2 = eval_bin(zb2);
+    // The next row streams in while this one is transformed.
+    if (row + gridDim.x < p.m) load_row(row + gridDim.x);
+
+#pragma unroll
+    for (int pass = 1; pass < P; ++pass) {
+      const int Ns = 1 << (pass * LOGE);
+      const int L = Ns * E;
+      const int k = tid & (Ns - 1);
+      V u[E];
+      if (tid < NB) {
+        const V* r0 = data + tid + (tid >> LOGE);
+#pragma unroll
+        for (int r = 0; r < E; ++r) u[r] = r0[r * (NB + NB / E)];
+        // twiddle w_L^{r k}; with at most two full passes L = E^2 and k < E
+        const V* tk = twp + k;
+#pragma unroll
+        for (int r = 1; r < E; ++r) u[r] = cmul(u[r], tk[r * E]);
+        RegDFT<E>::run(u);
+      }
+      __syncthreads();
+      if (tid < NB) {
+        const int g = tid >> (pass * LOGE);
+        V* w0 = data + g * (L + L / E) + k + (k >> LOGE);
+#pragma unroll
+        for (int r = 0; r < E; ++r) w0[r * (Ns + Ns / E)] = u[r];
+      }
+      __syncthreads();
+    }
+
+    // Pruned last pass: Z_b = sum_r data[j + r NSF] w_N^{r b}, j = b mod NSF.
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+      const int b = bin[u];
+      if (b >= 0) {
+        const int j = b & (NSF - 1);
+        const V* f0 = data + j + (j >> LOGE);
+        V w[F];
+        unit_powers<F>(w, cmul(thi[b >> G::LOGLO], tlo[b & (G::NLO - 1)]));
+        V acc = f0[0];
+#pragma unroll
+        for (int r = 1; r < F; ++r) acc += cmul(f0[r * (NSF + NSF / E)], w[r]);
+        zbuf[tid + u * THREADS] = acc;
+      }
+    }
+    __syncthreads();
+    if (tid < l) {
+      const V z1 = zbuf[tid];
+      const V z2 = zbuf[l + tid];
       const T half = (T)0.5;
       const V ek = make2<V>((z1.x + z2.x) * half, (z1.y - z2.y) * half);
       const V ok = make2<V>((z1.y + z2.y) * half, (z2.x - z1.x) * half);
       const V x = ek + cmul(pw, ok);
-      Y[row * p.l + tid] = kind == 2 ? -scale * x.y : scale * x.x;
+      Y[row * l + tid] = kind == 2 ? -scale * x.y : scale * x.x;
     }
   }
 }
@@ -331,7 +435,10 @@ hipError_t launch_rows(const SrftRowParams& p, hipStream_t st) {
   // Workgroups per CU allowed by LDS (160 KB per CU on gfx950), at most 8.
   const int per_cu = (int)std::min<size_t>(8, std::max<size_t>(1, (160 * 1024) / G::LDS));
   const int64_t grid = std::min<int64_t>(p.m, (int64_t)256 * per_cu);
-  hipLaunchKernelGGL((srft_rows_kernel<T, LOGN>), dim3((unsigned)grid), dim3(G::THREADS), 0, st, p);
+  if (p.vec)
+    hipLaunchKernelGGL((srft_rows_kernel<T, LOGN, true>), dim3((unsigned)grid), dim3(G::THREADS), 0, st, p);
+  else
+    hipLaunchKernelGGL((srft_rows_kernel<T, LOGN, false>), dim3((unsigned)grid), dim3(G::THREADS), 0, st, p);
   return hipGetLastError();
 }
 
