@@ -35,8 +35,10 @@
  *    a hipStream_t (NULL = the default stream) on which every kernel of the
  *    call is enqueued; calls return without synchronizing.
  *  * Ownership: the caller owns every buffer.  The library never allocates or
- *    frees memory in these calls; scratch space is the caller's workspace `ws`
- *    of at least rsvd_workspace_bytes(problem) bytes, 256-byte aligned.  Its
+ *    frees memory in these calls (rsvd_batched excepted: its first call for a
+ *    new batch allocates the batch's launch tables, owned by the handle);
+ *    scratch space is the caller's workspace `ws` of at least
+ *    rsvd_workspace_bytes(problem) bytes, 256-byte aligned.  Its
  *    contents are undefined between calls (except as noted for rsvd_project ->
  *    rsvd_svd, which carry nothing through it).
  *  * Errors: argument errors are detected on the host before any launch and
@@ -169,6 +171,31 @@ rsvd_status rsvd_project(rsvd_handle handle, const rsvd_problem* problem,
 rsvd_status rsvd_svd(rsvd_handle handle, const rsvd_problem* problem,
                      const void* Bt, const void* Q, void* U, void* S, void* V,
                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* --- Many independent problems --------------------------------------- */
+
+/* Workspace bytes rsvd_batched needs for `count` problems (0 if any problem is
+ * invalid or the batch is not supported). */
+size_t rsvd_batched_workspace_bytes(int32_t count, const rsvd_problem* problems);
+
+/* The whole randomized SVD (rsvd_range_finder, rsvd_power_iter, rsvd_project
+ * and rsvd_svd in sequence) of `count` independent matrices of different
+ * sizes.  problems[i] (HOST array) describes A[i]; every problem must share
+ * dtype, prec and q and use the Gaussian sketch (else RSVD_E_INVAL /
+ * RSVD_E_UNSUPPORTED); m, n, lda, k, p, seed and stream_id are per problem.
+ * A, U, S, V are HOST arrays of `count` DEVICE pointers: A[i] is m x n (lda),
+ * U[i] m x k, S[i] k, V[i] n x k, with the layouts of rsvd_svd.  Each step of
+ * the sequence is one launch over all problems (the products stream A without
+ * a split of K), so the batch fills the GPU where a single small problem
+ * cannot.  The first call for a given (problems, A, U, S, V, ws) records the
+ * launch sequence, uploads its parameter tables to device memory owned by the
+ * handle and captures the launches in a HIP graph; later calls with the same
+ * arguments replay the graph (the handle keeps the four most recent batches,
+ * freed by rsvd_destroy).  Results are those of the single-problem calls up to
+ * the rounding of the K reduction order. */
+rsvd_status rsvd_batched(rsvd_handle handle, int32_t count, const rsvd_problem* problems,
+                         const void* const* A, void* const* U, void* const* S,
+                         void* const* V, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* --- Diagnostics ------------------------------------------------------- */
 

@@ -202,6 +202,61 @@ def rsvd_sketch(A, k, p, *, sketch="gaussian", prec="native", seed=0, stream_id=
     return Y
 
 
+class BatchWorkspace:
+    """A caller-owned workspace for rsvd_batched (torch allocation)."""
+
+    def __init__(self, probs, device):
+        arr = (RsvdProblem * len(probs))(*probs)
+        h = handle(device)
+        nbytes = h.lib.rsvd_batched_workspace_bytes(len(probs), arr)
+        if nbytes == 0:
+            raise RsvdError(_lib.RSVD_E_INVAL, "rsvd_batched_workspace_bytes")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.nbytes = nbytes
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+
+def rsvd_batched(As, ks, p=8, q=1, *, prec="native", seed=0, stream_id=0, outs=None, ws=None):
+    """Randomized SVDs of many independent matrices in one batched call.
+
+    As: list of 2-D CUDA tensors (same dtype), ks: target ranks (int or list).
+    Matrix i draws its test matrix from (seed, stream_id + i).  Returns a list
+    of (U, S, V).  `outs` (a previous return value) and `ws` (a BatchWorkspace)
+    may be passed back to reuse buffers, which lets the library replay its
+    recorded graph.
+    """
+    count = len(As)
+    if count == 0:
+        return []
+    ks = [int(ks)] * count if isinstance(ks, int) else [int(k) for k in ks]
+    dev = As[0].device
+    probs = []
+    for i, (A, k) in enumerate(zip(As, ks)):
+        _check_matrix(A)
+        if A.dtype != As[0].dtype or A.device != dev:
+            raise ValueError("all matrices must share dtype and device")
+        m, n = A.shape
+        probs.append(problem(m, n, k, p, q, dtype=A.dtype, prec=prec, seed=seed, stream_id=stream_id + i,
+                             lda=A.stride(0)))
+    if outs is None:
+        outs = [(torch.empty(A.shape[0], k, dtype=A.dtype, device=dev), torch.empty(k, dtype=A.dtype, device=dev),
+                 torch.empty(A.shape[1], k, dtype=A.dtype, device=dev)) for A, k in zip(As, ks)]
+    ws = ws or BatchWorkspace(probs, dev)
+    arr = (RsvdProblem * count)(*probs)
+    VP = ctypes.c_void_p * count
+    a_p = VP(*[A.data_ptr() for A in As])
+    u_p = VP(*[o[0].data_ptr() for o in outs])
+    s_p = VP(*[o[1].data_ptr() for o in outs])
+    v_p = VP(*[o[2].data_ptr() for o in outs])
+    h = handle(dev)
+    _lib.check(h.lib.rsvd_batched(h.ptr, count, arr, a_p, u_p, s_p, v_p, ws.ptr, ws.nbytes, _stream(dev)),
+               "rsvd_batched")
+    return outs
+
+
 def rsvd_draw_omega(n, k, p, *, dtype=torch.float32, seed=0, stream_id=0, device="cuda"):
     """The Gaussian test matrix the range finder draws (n x (k+p))."""
     pr = problem(max(n, k + p), n, k, p, 0, dtype=dtype, seed=seed, stream_id=stream_id)

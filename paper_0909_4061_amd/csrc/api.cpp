@@ -1,14 +1,25 @@
 // Host side of the C ABI declared in include/rsvd.h: argument validation,
-// the workspace plan, the split-K choice, and the kernel sequences of the four
+// the workspace plan, the split-K choice, and the kernel sequences of the
 // hot-path calls (range finder, power steps, projection, small SVD + lifts).
+//
+// The kernel sequence of one problem is written once, against a Runner: the
+// single-problem calls launch each kernel at once on the caller's stream; the
+// batched call records the sequence of every problem, turns each step into
+// one launch over all problems (kernel families with a batched entry), and
+// replays the recorded launches from a HIP graph cached on the handle.
 //
 // Every call enqueues its kernels on the caller's stream and returns without
 // synchronizing.  Argument errors are found here, before any launch.
 #include <algorithm>
+#include <cstring>
 #include <new>
 #include <vector>
 
 #include "common.hpp"
+
+namespace {
+struct BatchPlan;
+}
 
 struct rsvd_handle_s {
   int device;
@@ -17,6 +28,9 @@ struct rsvd_handle_s {
   std::vector<hipEvent_t> events;  // 2 per record
   std::vector<int> kinds;          // family of each record
   int used = 0;
+  // batched calls: recorded launch plans (device tables + graph), most recent last
+  std::vector<BatchPlan*> plans;
+  hipStream_t capture = nullptr;  // stream the batched graphs are captured on
 };
 
 namespace {
@@ -24,6 +38,7 @@ namespace {
 using namespace rsvd;
 
 constexpr size_t kAlign = 256;
+constexpr size_t kMaxPlans = 4;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -33,6 +48,8 @@ struct Split {
   int32_t S;
   int64_t kchunk;
 };
+
+Split no_split(int64_t K) { return Split{1, std::max<int64_t>(K, 1)}; }
 
 // Split the contraction range K so that (row blocks x S) workgroups cover the
 // 256 CUs about twice, keeping at least four K stages per workgroup.
@@ -52,8 +69,8 @@ struct Plan {
   int esize;
   int dtype, prec;
   Split nn, tn;
-  size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rinv, RinvT, XU, XV, Uh, sig, flags, srft_d, srft_R,
-      total;
+  size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rb, Rinv, RinvT, XU, XV, Uh, sig, flags, srft_d,
+      srft_R, total;
 };
 
 bool valid_enum(int32_t v, int32_t lo, int32_t hi) { return v >= lo && v <= hi; }
@@ -77,7 +94,9 @@ rsvd_status validate(const rsvd_problem* pr) {
   return RSVD_OK;
 }
 
-Plan make_plan(const rsvd_problem* pr) {
+// Workspace regions of one problem.  `batched`: no split-K (every problem of
+// a batch runs the same launch sequence, and the batch itself fills the chip).
+Plan make_plan(const rsvd_problem* pr, bool batched = false) {
   Plan P{};
   P.m = pr->m;
   P.n = pr->n;
@@ -90,8 +109,8 @@ Plan make_plan(const rsvd_problem* pr) {
   const GemmTile big = gemm_tile(pr->dtype, pr->prec);
   P.Lp = (int32_t)round_up(P.l, big.lp_mult);
   P.Lg = (int32_t)round_up(P.l, 16);
-  P.nn = choose_split(P.m, P.n, big);
-  P.tn = choose_split(P.n, P.m, big);
+  P.nn = batched ? no_split(P.n) : choose_split(P.m, P.n, big);
+  P.tn = batched ? no_split(P.m) : choose_split(P.n, P.m, big);
   int64_t part_elems = 0;
   if (P.nn.S > 1) part_elems = std::max(part_elems, (int64_t)P.nn.S * P.m * P.Lp);
   if (P.tn.S > 1) part_elems = std::max(part_elems, (int64_t)P.tn.S * P.n * P.Lp);
@@ -107,13 +126,14 @@ Plan make_plan(const rsvd_problem* pr) {
   P.part = take((size_t)part_elems * es);
   P.Y = take((size_t)P.Mx * P.l * es);
   P.Qt = take((size_t)P.n * P.l * es);
-  P.pack = take(pr->dtype == RSVD_F32 ? (size_t)stream_pack_bytes(P.Mx, P.Lp) : 0);
+  P.pack = take(pr->dtype == RSVD_F32 && !batched ? (size_t)stream_pack_bytes(P.Mx, P.Lp) : 0);
   P.gpart = take((size_t)ceil_div(P.Mx, GRAM_ROWS) * P.Lg * P.Lg * 8);
   P.G = take((size_t)P.Lg * P.Lg * 8);
   P.R1 = take(ll8);
   P.R2 = take(ll8);
   P.R3 = take(ll8);
   P.Rt = take(ll8);
+  P.Rb = take(ll8);
   P.Rinv = take(ll8);
   P.RinvT = take((size_t)P.l * P.l * es);
   P.XU = take((size_t)P.l * P.k * es);
@@ -126,26 +146,6 @@ Plan make_plan(const rsvd_problem* pr) {
   P.total = off;
   return P;
 }
-
-struct Ctx {
-  const Plan& P;
-  char* ws;
-  hipStream_t st;
-  int32_t* status;
-  rsvd_handle h;
-  template <typename T>
-  T* at(size_t off) const {
-    return reinterpret_cast<T*>(ws + off);
-  }
-  int32_t* shift_flag() const { return at<int32_t>(P.flags); }
-};
-
-#define RSVD_TRY(expr)                          \
-  do {                                          \
-    if ((expr) != hipSuccess) return RSVD_E_DEVICE; \
-  } while (0)
-
-bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 // Brackets one launch with a pair of events when timing is on.
 struct Timed {
@@ -163,6 +163,137 @@ struct Timed {
     if (idx >= 0) (void)hipEventRecord(h->events[2 * idx + 1], st);
   }
 };
+
+// ---------------------------------------------------------------------------
+// Where the kernels of one problem go.
+class Runner {
+ public:
+  virtual ~Runner() = default;
+  virtual bool records() const = 0;
+  virtual hipError_t gemm(int dtype, int prec, bool trans, const GemmParams& p, int kind) = 0;
+  virtual hipError_t gram_partial(int dtype, const GramParams& p) = 0;
+  virtual hipError_t gram_reduce(const GramReduceParams& p) = 0;
+  virtual hipError_t chol(const CholParams& p) = 0;
+  virtual hipError_t jacobi(const JacobiParams& p) = 0;
+  virtual hipError_t omega(int dtype, const OmegaParams& p) = 0;
+  virtual hipError_t fill(const FillParams& p) = 0;
+  virtual hipError_t trmm(const TrmmParams& p) = 0;
+  virtual hipError_t copy(const CopyParams& p) = 0;
+};
+
+// Launches at once on a stream (timed when the handle's timing is on).
+class DirectRunner final : public Runner {
+ public:
+  DirectRunner(rsvd_handle h, hipStream_t st) : h_(h), st_(st) {}
+  bool records() const override { return false; }
+  hipError_t gemm(int dtype, int prec, bool trans, const GemmParams& p, int kind) override {
+    Timed t(h_, kind, st_);
+    return launch_gemm(dtype, prec, trans, p, st_);
+  }
+  hipError_t gram_partial(int dtype, const GramParams& p) override {
+    Timed t(h_, RSVD_KERNEL_GRAM, st_);
+    return launch_gram_partial(dtype, p, st_);
+  }
+  hipError_t gram_reduce(const GramReduceParams& p) override {
+    Timed t(h_, RSVD_KERNEL_GRAM, st_);
+    return launch_gram_reduce(p.gpart, p.nblk, p.Lg, p.G, p.status, p.gate, st_);
+  }
+  hipError_t chol(const CholParams& p) override {
+    Timed t(h_, RSVD_KERNEL_CHOL, st_);
+    return launch_chol(p, st_);
+  }
+  hipError_t jacobi(const JacobiParams& p) override {
+    Timed t(h_, RSVD_KERNEL_JACOBI, st_);
+    return launch_jacobi(p, st_);
+  }
+  hipError_t omega(int dtype, const OmegaParams& p) override {
+    return launch_omega(dtype, p.omega, p.n, p.l, p.seed, p.sid, st_);
+  }
+  hipError_t fill(const FillParams& p) override { return launch_fill_i32(p.p, p.v, p.count, st_); }
+  hipError_t trmm(const TrmmParams& p) override { return launch_trmm_upper(p.R2, p.R1, p.R, p.l, p.gate, st_); }
+  hipError_t copy(const CopyParams& p) override { return launch_copy_f64(p.src, p.dst, p.count, p.gate, st_); }
+
+ private:
+  rsvd_handle h_;
+  hipStream_t st_;
+};
+
+// One step of a batched plan: the same kernel family and variant for every
+// problem, with the problems' parameter blocks side by side.
+enum SlotKind { SK_GEMM, SK_GRAM_PARTIAL, SK_GRAM_REDUCE, SK_CHOL, SK_JACOBI, SK_OMEGA, SK_FILL, SK_TRMM, SK_COPY };
+
+struct Slot {
+  SlotKind kind;
+  int dtype, prec;
+  bool trans;
+  size_t psize;
+  std::vector<unsigned char> params;  // problem-major, psize bytes each
+  std::vector<int64_t> blocks;        // workgroups of each problem
+};
+
+// Appends one problem's launches to the slots, in order; every problem of a
+// batch must produce the same sequence of (family, variant).
+class RecordRunner final : public Runner {
+ public:
+  explicit RecordRunner(std::vector<Slot>& slots) : slots_(slots) {}
+  bool records() const override { return true; }
+  size_t cursor() const { return cursor_; }
+  hipError_t gemm(int dtype, int prec, bool trans, const GemmParams& p, int) override {
+    return add(SK_GEMM, dtype, prec, trans, p, p.rows > 0 ? gemm_blocks(dtype, prec, p) : 0);
+  }
+  hipError_t gram_partial(int dtype, const GramParams& p) override {
+    return add(SK_GRAM_PARTIAL, dtype, 0, false, p, p.rows > 0 ? gram_partial_blocks(p) : 0);
+  }
+  hipError_t gram_reduce(const GramReduceParams& p) override {
+    return add(SK_GRAM_REDUCE, 0, 0, false, p, gram_reduce_blocks(p));
+  }
+  hipError_t chol(const CholParams& p) override { return add(SK_CHOL, 0, 0, false, p, 1); }
+  hipError_t jacobi(const JacobiParams& p) override { return add(SK_JACOBI, 0, 0, false, p, 1); }
+  hipError_t omega(int dtype, const OmegaParams& p) override {
+    return add(SK_OMEGA, dtype, 0, false, p, omega_blocks(p));
+  }
+  hipError_t fill(const FillParams& p) override { return add(SK_FILL, 0, 0, false, p, fill_blocks(p)); }
+  hipError_t trmm(const TrmmParams& p) override { return add(SK_TRMM, 0, 0, false, p, trmm_blocks(p)); }
+  hipError_t copy(const CopyParams& p) override {
+    return add(SK_COPY, 0, 0, false, p, p.count > 0 ? copy_blocks(p) : 0);
+  }
+
+ private:
+  template <typename P>
+  hipError_t add(SlotKind kind, int dtype, int prec, bool trans, const P& p, int64_t blocks) {
+    if (cursor_ == slots_.size()) slots_.push_back(Slot{kind, dtype, prec, trans, sizeof(P), {}, {}});
+    Slot& s = slots_[cursor_++];
+    if (s.kind != kind || s.dtype != dtype || s.prec != prec || s.trans != trans || s.psize != sizeof(P))
+      return hipErrorInvalidValue;
+    const auto* b = reinterpret_cast<const unsigned char*>(&p);
+    s.params.insert(s.params.end(), b, b + sizeof(P));
+    s.blocks.push_back(blocks);
+    return hipSuccess;
+  }
+  std::vector<Slot>& slots_;
+  size_t cursor_ = 0;
+};
+
+struct Ctx {
+  const Plan& P;
+  char* ws;
+  hipStream_t st;   // for the launches only the single-problem path makes
+  int32_t* status;
+  rsvd_handle h;    // for timing; null when recording
+  Runner* run;
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+  int32_t* shift_flag() const { return at<int32_t>(P.flags); }
+};
+
+#define RSVD_TRY(expr)                              \
+  do {                                              \
+    if ((expr) != hipSuccess) return RSVD_E_DEVICE; \
+  } while (0)
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 // op(A) X with the given arithmetic.  With `part` non-null and a split S > 1
 // the result is left as partial products; otherwise it is written to `out`.
@@ -188,22 +319,20 @@ rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda,
   g.vec = (lda % vec_mult == 0 && aligned16(A)) ? 1 : 0;
   g.gate = gate;
   if (g.S > 1 && !part) return RSVD_E_INVAL;
-  if (streams_a && c.P.dtype == RSVD_F32) {
+  const int kind = streams_a ? (trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN) : RSVD_KERNEL_SMALL_GEMM;
+  if (streams_a && c.P.dtype == RSVD_F32 && !c.run->records()) {
     g.Lp = (int32_t)round_up(ncols, 32);
     {
       Timed t_(c.h, RSVD_KERNEL_PACK, c.st);
       RSVD_TRY(launch_pack_x(prec, g, c.at<void>(c.P.pack), c.st));
     }
-    Timed t_(c.h, trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN, c.st);
+    Timed t_(c.h, kind, c.st);
     RSVD_TRY(launch_stream_gemm(prec, trans, g, c.at<void>(c.P.pack), c.st));
   } else {
-    Timed t_(c.h, streams_a ? (trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN) : RSVD_KERNEL_SMALL_GEMM, c.st);
-    RSVD_TRY(launch_gemm(c.P.dtype, prec, trans, g, c.st));
+    RSVD_TRY(c.run->gemm(c.P.dtype, prec, trans, g, kind));
   }
   return RSVD_OK;
 }
-
-Split no_split(int64_t K) { return Split{1, std::max<int64_t>(K, 1)}; }
 
 // Gram of a rows x l matrix into G (FP64, Lg x Lg upper).  Source: split-K
 // partials (summed and stored into `y`) or a stored `y`.
@@ -222,10 +351,9 @@ rsvd_status gram(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t
   g.do_gram = 1;
   g.gpart = c.at<double>(c.P.gpart);
   g.gate = gate;
-  Timed t_(c.h, RSVD_KERNEL_GRAM, c.st);
-  RSVD_TRY(launch_gram_partial(c.P.dtype, g, c.st));
-  RSVD_TRY(launch_gram_reduce(g.gpart, ceil_div(rows, GRAM_ROWS), c.P.Lg, c.at<double>(c.P.G), c.status, gate,
-                              c.st));
+  RSVD_TRY(c.run->gram_partial(c.P.dtype, g));
+  const GramReduceParams r{g.gpart, ceil_div(rows, GRAM_ROWS), c.P.Lg, c.at<double>(c.P.G), c.status, gate};
+  RSVD_TRY(c.run->gram_reduce(r));
   return RSVD_OK;
 }
 
@@ -242,8 +370,7 @@ rsvd_status chol(const Ctx& c, int64_t rows, double* R, bool want_inv, const int
   q.shifted = shifted;
   q.status = c.status;
   q.gate = gate;
-  Timed t_(c.h, RSVD_KERNEL_CHOL, c.st);
-  RSVD_TRY(launch_chol(q, c.st));
+  RSVD_TRY(c.run->chol(q));
   return RSVD_OK;
 }
 
@@ -254,7 +381,7 @@ rsvd_status chol(const Ctx& c, int64_t rows, double* R, bool want_inv, const int
 rsvd_status orth(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t rows, void* Q, double* R_out) {
   const int64_t l = c.P.l;
   int32_t* flag = c.shift_flag();
-  RSVD_TRY(launch_fill_i32(flag, 0, 1, c.st));
+  RSVD_TRY(c.run->fill(FillParams{flag, 0, 1}));
   double* Rs[3] = {c.at<double>(c.P.R1), c.at<double>(c.P.R2), c.at<double>(c.P.R3)};
   for (int pass = 0; pass < 3; ++pass) {
     const int32_t* gate = pass == 2 ? flag : nullptr;
@@ -269,9 +396,10 @@ rsvd_status orth(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t
     if (s != RSVD_OK) return s;
   }
   if (R_out) {
-    RSVD_TRY(launch_trmm_upper(Rs[1], Rs[0], R_out, (int32_t)l, nullptr, c.st));
-    RSVD_TRY(launch_trmm_upper(Rs[2], R_out, c.at<double>(c.P.Rt), (int32_t)l, flag, c.st));
-    RSVD_TRY(launch_copy_f64(c.at<double>(c.P.Rt), R_out, l * l, flag, c.st));
+    // R = R3 R2 R1 (R3 only when the shifted third pass ran)
+    RSVD_TRY(c.run->trmm(TrmmParams{Rs[1], Rs[0], R_out, (int32_t)l, nullptr}));
+    RSVD_TRY(c.run->trmm(TrmmParams{Rs[2], R_out, c.at<double>(c.P.Rt), (int32_t)l, flag}));
+    RSVD_TRY(c.run->copy(CopyParams{c.at<double>(c.P.Rt), R_out, l * l, flag}));
   }
   return RSVD_OK;
 }
@@ -304,14 +432,16 @@ rsvd_status reduce_parts(const Ctx& c, const Split& sp, int64_t rows, void* out)
   g.Lg = c.P.Lg;
   g.do_gram = 0;
   g.gpart = c.at<double>(c.P.gpart);
-  RSVD_TRY(launch_gram_partial(c.P.dtype, g, c.st));
+  RSVD_TRY(c.run->gram_partial(c.P.dtype, g));
   return RSVD_OK;
 }
 
-// Y = A Omega (m x l) for either test matrix, into `y`.
+// Y = A Omega (m x l) for either test matrix, into `y` (left as split-K
+// partials for the Gaussian GEMM when the plan splits it).
 rsvd_status sketch(const Ctx& c, const rsvd_problem* pr, const void* A, void* y) {
   const Plan& P = c.P;
   if (pr->sketch == RSVD_SRFT) {
+    if (c.run->records()) return RSVD_E_UNSUPPORTED;
     double* d = c.at<double>(P.srft_d);
     int32_t* R = c.at<int32_t>(P.srft_R);
     RSVD_TRY(launch_srft_draw(d, R, pr->n, (int32_t)P.l, pr->seed, pr->stream_id, c.st));
@@ -320,9 +450,83 @@ rsvd_status sketch(const Ctx& c, const rsvd_problem* pr, const void* A, void* y)
     return RSVD_OK;
   }
   void* omega = c.at<void>(P.omega);
-  RSVD_TRY(launch_omega(pr->dtype, omega, pr->n, (int32_t)P.l, pr->seed, pr->stream_id, c.st));
+  RSVD_TRY(c.run->omega(pr->dtype, OmegaParams{omega, pr->n, (int32_t)P.l, pr->seed, pr->stream_id}));
   return gemm(c, pr->prec, false, A, pr->lda, P.m, P.n, omega, P.l, (int32_t)P.l, y, P.l, P.nn,
               P.nn.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
+}
+
+// --- the steps of the hot path, shared by the single and batched calls -----
+
+// Algorithm 4.1 steps 2-3 / Algorithm 4.5: Q = orth(A Omega).
+rsvd_status range_finder_steps(const Ctx& c, const rsvd_problem* pr, const void* A, void* Q) {
+  void* y = c.at<void>(c.P.Y);
+  const bool parts = pr->sketch == RSVD_GAUSSIAN && c.P.nn.S > 1;
+  rsvd_status s = sketch(c, pr, A, y);
+  if (s != RSVD_OK) return s;
+  return orth(c, parts, c.P.nn, y, pr->m, Q, nullptr);
+}
+
+// Algorithm 4.4 steps 3-6.
+rsvd_status power_steps(const Ctx& c, const rsvd_problem* pr, const void* A, void* Q) {
+  void* Qt = c.at<void>(c.P.Qt);
+  for (int j = 0; j < pr->q; ++j) {
+    rsvd_status s = apply_and_orth(c, pr, true, A, Q, Qt);  // Qt = orth(A^T Q)
+    if (s != RSVD_OK) return s;
+    s = apply_and_orth(c, pr, false, A, Qt, Q);  // Q = orth(A Qt)
+    if (s != RSVD_OK) return s;
+  }
+  return RSVD_OK;
+}
+
+// Algorithm 5.1 step 1: Bt = A^T Q.
+rsvd_status project_steps(const Ctx& c, const rsvd_problem* pr, const void* A, const void* Q, void* Bt) {
+  const Plan& P = c.P;
+  const Split& sp = P.tn;
+  rsvd_status s = gemm(c, pr->prec, true, A, pr->lda, P.n, P.m, Q, P.l, (int32_t)P.l, Bt, P.l, sp,
+                       sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
+  if (s != RSVD_OK || sp.S == 1) return s;
+  return reduce_parts(c, sp, P.n, Bt);
+}
+
+// Algorithm 5.1 steps 2-3 and truncation.  The SVD of the small matrix B is
+// taken through a triangular factor R with R^T R = B B*: one-sided Jacobi on
+// C = R^T gives U~ and Sigma, and V = B* U~ Sigma^-1.  For FP64 data R comes
+// from CholeskyQR2 of B* (a shifted third pass when needed), which is
+// backward stable: singular values carry absolute errors of order u sigma_1,
+// as with a Householder QR.  For FP32 data R is the Cholesky factor of the
+// FP64 Gram B B* itself, whose error (u_64 sigma_1^2 / sigma_j relative to
+// sigma_j) stays below what FP32 arithmetic resolves.
+rsvd_status svd_steps(const Ctx& c, const void* Bt, const void* Q, void* U, void* S, void* V) {
+  const Plan& P = c.P;
+  double* R = c.at<double>(P.R1);
+  rsvd_status s;
+  if (P.dtype == RSVD_F64) {
+    R = c.at<double>(P.Rb);
+    // Q_B (n x l) goes to the Y region, unused by now; Bt itself is only read.
+    s = orth(c, false, no_split(1), const_cast<void*>(Bt), P.n, c.at<void>(P.Y), R);
+  } else {
+    s = gram(c, false, no_split(1), const_cast<void*>(Bt), P.n, nullptr);
+    if (s == RSVD_OK) s = chol(c, P.n, R, false, nullptr, nullptr);
+  }
+  if (s != RSVD_OK) return s;
+  JacobiParams j{};
+  j.R = R;
+  j.l = (int32_t)P.l;
+  j.k = (int32_t)P.k;
+  j.dtype = P.dtype;
+  j.Uh = c.at<double>(P.Uh);
+  j.sig = c.at<double>(P.sig);
+  j.XU = c.at<void>(P.XU);
+  j.XV = c.at<void>(P.XV);
+  j.S = S;
+  j.status = c.status;
+  RSVD_TRY(c.run->jacobi(j));
+  // U = Q U~_k (m x k), V = Bt U~_k S_k^-1 (n x k)
+  s = gemm(c, RSVD_NATIVE, false, Q, P.l, P.m, P.l, j.XU, P.k, (int32_t)P.k, U, P.k, no_split(P.l), nullptr,
+           nullptr);
+  if (s != RSVD_OK) return s;
+  return gemm(c, RSVD_NATIVE, false, Bt, P.l, P.n, P.l, j.XV, P.k, (int32_t)P.k, V, P.k, no_split(P.l), nullptr,
+              nullptr);
 }
 
 struct Prologue {
@@ -345,6 +549,192 @@ Prologue prologue(rsvd_handle h, const rsvd_problem* pr, const void* ws, size_t 
   }
   if (hipSetDevice(h->device) != hipSuccess) out.status = RSVD_E_DEVICE;
   return out;
+}
+
+// ---------------------------------------------------------------------------
+// Batched calls.
+
+// Per-problem regions of a batched workspace: Q (m x l), Bt (n x l), then the
+// problem's own plan.
+struct BatchLayout {
+  std::vector<Plan> plans;
+  std::vector<size_t> base, q_off, bt_off;
+  size_t total = 0;
+};
+
+rsvd_status batch_layout(int32_t count, const rsvd_problem* probs, BatchLayout& L) {
+  if (count < 1 || !probs) return RSVD_E_INVAL;
+  const rsvd_problem& p0 = probs[0];
+  for (int32_t i = 0; i < count; ++i) {
+    const rsvd_status v = validate(&probs[i]);
+    if (v != RSVD_OK) return v;
+    if (probs[i].dtype != p0.dtype || probs[i].prec != p0.prec || probs[i].q != p0.q) return RSVD_E_INVAL;
+    if (probs[i].sketch != RSVD_GAUSSIAN) return RSVD_E_UNSUPPORTED;
+  }
+  size_t off = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const Plan P = make_plan(&probs[i], true);
+    const size_t es = (size_t)P.esize;
+    L.q_off.push_back(off);
+    off += align_up((size_t)P.m * P.l * es);
+    L.bt_off.push_back(off);
+    off += align_up((size_t)P.n * P.l * es);
+    L.base.push_back(off);
+    off += P.total;
+    L.plans.push_back(P);
+  }
+  L.total = off;
+  return RSVD_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// A recorded batch: its identity, the device tables and the replayable graph.
+struct BatchPlan {
+  std::vector<rsvd_problem> probs;
+  std::vector<const void*> ptrs;  // A, U, S, V of every problem
+  void* ws = nullptr;
+  void* tables = nullptr;         // device: parameter blocks and block maps of every slot
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+void free_plan(BatchPlan* bp) {
+  if (!bp) return;
+  if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
+  if (bp->graph) (void)hipGraphDestroy(bp->graph);
+  if (bp->tables) (void)hipFree(bp->tables);
+  delete bp;
+}
+
+bool same_batch(const BatchPlan& bp, int32_t count, const rsvd_problem* probs, const std::vector<const void*>& ptrs,
+                void* ws) {
+  return bp.ws == ws && (int32_t)bp.probs.size() == count && bp.ptrs == ptrs &&
+         std::memcmp(bp.probs.data(), probs, sizeof(rsvd_problem) * (size_t)count) == 0;
+}
+
+// Launch every slot of a recorded batch on `st` from the device tables.
+hipError_t launch_slots(const std::vector<Slot>& slots, const std::vector<size_t>& poff,
+                        const std::vector<size_t>& boff, const std::vector<int64_t>& nblk, const char* dev,
+                        hipStream_t st) {
+  for (size_t s = 0; s < slots.size(); ++s) {
+    const Slot& sl = slots[s];
+    const void* ps = dev + poff[s];
+    const BlockMap* bm = reinterpret_cast<const BlockMap*>(dev + boff[s]);
+    hipError_t e = hipSuccess;
+    switch (sl.kind) {
+      case SK_GEMM:
+        e = launch_gemm_batched(sl.dtype, sl.prec, sl.trans, (const GemmParams*)ps, bm, nblk[s], st);
+        break;
+      case SK_GRAM_PARTIAL:
+        e = launch_gram_partial_batched(sl.dtype, (const GramParams*)ps, bm, nblk[s], st);
+        break;
+      case SK_GRAM_REDUCE:
+        e = launch_gram_reduce_batched((const GramReduceParams*)ps, bm, nblk[s], st);
+        break;
+      case SK_CHOL:
+        e = launch_chol_batched((const CholParams*)ps, bm, nblk[s], st);
+        break;
+      case SK_JACOBI:
+        e = launch_jacobi_batched((const JacobiParams*)ps, bm, nblk[s], st);
+        break;
+      case SK_OMEGA:
+        e = launch_omega_batched(sl.dtype, (const OmegaParams*)ps, bm, nblk[s], st);
+        break;
+      case SK_FILL:
+        e = launch_fill_batched((const FillParams*)ps, bm, nblk[s], st);
+        break;
+      case SK_TRMM:
+        e = launch_trmm_batched((const TrmmParams*)ps, bm, nblk[s], st);
+        break;
+      case SK_COPY:
+        e = launch_copy_batched((const CopyParams*)ps, bm, nblk[s], st);
+        break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Record the batch, upload its tables and capture its launches in a graph.
+rsvd_status build_plan(rsvd_handle h, int32_t count, const rsvd_problem* probs, const void* const* A,
+                       void* const* U, void* const* S, void* const* V, void* ws, const BatchLayout& L,
+                       BatchPlan*& out) {
+  std::vector<Slot> slots;
+  for (int32_t i = 0; i < count; ++i) {
+    RecordRunner rr(slots);
+    const Plan& P = L.plans[(size_t)i];
+    char* base = static_cast<char*>(ws);
+    const Ctx c{P, base + L.base[(size_t)i], nullptr, h->status, nullptr, &rr};
+    void* Q = base + L.q_off[(size_t)i];
+    void* Bt = base + L.bt_off[(size_t)i];
+    rsvd_status s = range_finder_steps(c, &probs[i], A[i], Q);
+    if (s == RSVD_OK) s = power_steps(c, &probs[i], A[i], Q);
+    if (s == RSVD_OK) s = project_steps(c, &probs[i], A[i], Q, Bt);
+    if (s == RSVD_OK) s = svd_steps(c, Bt, Q, U[i], S[i], V[i]);
+    if (s != RSVD_OK) return s == RSVD_E_DEVICE ? RSVD_E_INVAL : s;
+    if (rr.cursor() != slots.size()) return RSVD_E_INVAL;
+  }
+  // device tables: per slot the parameter blocks, then the block map
+  std::vector<size_t> poff, boff;
+  std::vector<int64_t> nblk;
+  size_t bytes = 0;
+  for (const Slot& sl : slots) {
+    poff.push_back(bytes);
+    bytes = align_up(bytes + sl.params.size());
+    int64_t nb = 0;
+    for (int64_t b : sl.blocks) nb += b;
+    if (nb > INT32_MAX) return RSVD_E_UNSUPPORTED;
+    nblk.push_back(nb);
+    boff.push_back(bytes);
+    bytes = align_up(bytes + (size_t)nb * sizeof(BlockMap));
+  }
+  std::vector<char> host(bytes, 0);
+  for (size_t s = 0; s < slots.size(); ++s) {
+    const Slot& sl = slots[s];
+    std::memcpy(host.data() + poff[s], sl.params.data(), sl.params.size());
+    BlockMap* bm = reinterpret_cast<BlockMap*>(host.data() + boff[s]);
+    int64_t k = 0;
+    for (size_t i = 0; i < sl.blocks.size(); ++i)
+      for (int64_t b = 0; b < sl.blocks[i]; ++b) bm[k++] = BlockMap{(int32_t)i, (int32_t)b};
+  }
+  BatchPlan* bp = new (std::nothrow) BatchPlan;
+  if (!bp) return RSVD_E_DEVICE;
+  bp->probs.assign(probs, probs + count);
+  for (int32_t i = 0; i < count; ++i) {
+    bp->ptrs.push_back(A[i]);
+    bp->ptrs.push_back(U[i]);
+    bp->ptrs.push_back(S[i]);
+    bp->ptrs.push_back(V[i]);
+  }
+  bp->ws = ws;
+  rsvd_status st = RSVD_OK;
+  if (hipMalloc(&bp->tables, std::max<size_t>(bytes, 1)) != hipSuccess ||
+      hipMemcpy(bp->tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+    st = RSVD_E_DEVICE;
+  if (st == RSVD_OK && !h->capture && hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess) {
+    h->capture = nullptr;
+    st = RSVD_E_DEVICE;
+  }
+  if (st == RSVD_OK) {
+    if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      st = RSVD_E_DEVICE;
+    } else {
+      const hipError_t le = launch_slots(slots, poff, boff, nblk, static_cast<const char*>(bp->tables), h->capture);
+      const hipError_t ce = hipStreamEndCapture(h->capture, &bp->graph);
+      if (le != hipSuccess || ce != hipSuccess ||
+          hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0) != hipSuccess)
+        st = RSVD_E_DEVICE;
+    }
+  }
+  if (st != RSVD_OK) {
+    free_plan(bp);
+    return st;
+  }
+  out = bp;
+  return RSVD_OK;
 }
 
 }  // namespace
@@ -404,6 +794,8 @@ rsvd_status rsvd_profile_read(rsvd_handle h, int32_t* launches, double* total_ms
 rsvd_status rsvd_destroy(rsvd_handle handle) {
   if (!handle) return RSVD_E_INVAL;
   (void)hipSetDevice(handle->device);
+  for (BatchPlan* bp : handle->plans) free_plan(bp);
+  if (handle->capture) (void)hipStreamDestroy(handle->capture);
   for (hipEvent_t e : handle->events) (void)hipEventDestroy(e);
   (void)hipFree(handle->status);
   delete handle;
@@ -436,14 +828,9 @@ rsvd_status rsvd_range_finder(rsvd_handle h, const rsvd_problem* pr, const void*
   Prologue pro = prologue(h, pr, ws, ws_bytes);
   if (pro.status != RSVD_OK) return pro.status;
   if (!A || !Q) return RSVD_E_INVAL;
-  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h};
-  void* y = c.at<void>(c.P.Y);
-  const bool parts = pr->sketch == RSVD_GAUSSIAN && c.P.nn.S > 1;
-  // Y = A Omega (left as split-K partials for the Gaussian GEMM when S > 1),
-  // then CholeskyQR2 (Algorithm 4.1 step 3 / Algorithm 4.5 step 3).
-  rsvd_status s = sketch(c, pr, A, y);
-  if (s != RSVD_OK) return s;
-  return orth(c, parts, c.P.nn, y, pr->m, Q, nullptr);
+  DirectRunner dr(h, stream);
+  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
+  return range_finder_steps(c, pr, A, Q);
 }
 
 rsvd_status rsvd_sketch(rsvd_handle h, const rsvd_problem* pr, const void* A, void* Y, void* ws, size_t ws_bytes,
@@ -451,7 +838,8 @@ rsvd_status rsvd_sketch(rsvd_handle h, const rsvd_problem* pr, const void* A, vo
   Prologue pro = prologue(h, pr, ws, ws_bytes);
   if (pro.status != RSVD_OK) return pro.status;
   if (!A || !Y) return RSVD_E_INVAL;
-  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h};
+  DirectRunner dr(h, stream);
+  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
   rsvd_status s = sketch(c, pr, A, Y);
   if (s != RSVD_OK || pr->sketch == RSVD_SRFT || c.P.nn.S == 1) return s;
   return reduce_parts(c, c.P.nn, pr->m, Y);
@@ -462,15 +850,9 @@ rsvd_status rsvd_power_iter(rsvd_handle h, const rsvd_problem* pr, const void* A
   Prologue pro = prologue(h, pr, ws, ws_bytes);
   if (pro.status != RSVD_OK) return pro.status;
   if (!A || !Q) return RSVD_E_INVAL;
-  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h};
-  void* Qt = c.at<void>(c.P.Qt);
-  for (int j = 0; j < pr->q; ++j) {
-    rsvd_status s = apply_and_orth(c, pr, true, A, Q, Qt);  // Qt = orth(A^T Q)
-    if (s != RSVD_OK) return s;
-    s = apply_and_orth(c, pr, false, A, Qt, Q);  // Q = orth(A Qt)
-    if (s != RSVD_OK) return s;
-  }
-  return RSVD_OK;
+  DirectRunner dr(h, stream);
+  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
+  return power_steps(c, pr, A, Q);
 }
 
 rsvd_status rsvd_project(rsvd_handle h, const rsvd_problem* pr, const void* A, const void* Q, void* Bt, void* ws,
@@ -478,13 +860,9 @@ rsvd_status rsvd_project(rsvd_handle h, const rsvd_problem* pr, const void* A, c
   Prologue pro = prologue(h, pr, ws, ws_bytes);
   if (pro.status != RSVD_OK) return pro.status;
   if (!A || !Q || !Bt) return RSVD_E_INVAL;
-  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h};
-  const Plan& P = c.P;
-  const Split& sp = P.tn;
-  rsvd_status s = gemm(c, pr->prec, true, A, pr->lda, P.n, P.m, Q, P.l, (int32_t)P.l, Bt, P.l, sp,
-                       sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
-  if (s != RSVD_OK || sp.S == 1) return s;
-  return reduce_parts(c, sp, P.n, Bt);
+  DirectRunner dr(h, stream);
+  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
+  return project_steps(c, pr, A, Q, Bt);
 }
 
 rsvd_status rsvd_svd(rsvd_handle h, const rsvd_problem* pr, const void* Bt, const void* Q, void* U, void* S,
@@ -492,34 +870,54 @@ rsvd_status rsvd_svd(rsvd_handle h, const rsvd_problem* pr, const void* Bt, cons
   Prologue pro = prologue(h, pr, ws, ws_bytes);
   if (pro.status != RSVD_OK) return pro.status;
   if (!Bt || !Q || !U || !S || !V) return RSVD_E_INVAL;
-  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h};
-  const Plan& P = c.P;
-  // Gram B B* = Bt^T Bt and its Cholesky factor R (R^T R = B B*).
-  rsvd_status s = gram(c, false, no_split(1), const_cast<void*>(Bt), P.n, nullptr);
-  if (s != RSVD_OK) return s;
-  s = chol(c, P.n, c.at<double>(P.R1), false, nullptr, nullptr);
-  if (s != RSVD_OK) return s;
-  JacobiParams j{};
-  j.R = c.at<double>(P.R1);
-  j.l = (int32_t)P.l;
-  j.k = (int32_t)P.k;
-  j.dtype = P.dtype;
-  j.Uh = c.at<double>(P.Uh);
-  j.sig = c.at<double>(P.sig);
-  j.XU = c.at<void>(P.XU);
-  j.XV = c.at<void>(P.XV);
-  j.S = S;
-  j.status = h->status;
-  {
-    Timed t_(h, RSVD_KERNEL_JACOBI, stream);
-    RSVD_TRY(launch_jacobi(j, stream));
+  DirectRunner dr(h, stream);
+  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
+  return svd_steps(c, Bt, Q, U, S, V);
+}
+
+size_t rsvd_batched_workspace_bytes(int32_t count, const rsvd_problem* probs) {
+  BatchLayout L;
+  if (batch_layout(count, probs, L) != RSVD_OK) return 0;
+  return L.total;
+}
+
+rsvd_status rsvd_batched(rsvd_handle h, int32_t count, const rsvd_problem* probs, const void* const* A,
+                         void* const* U, void* const* S, void* const* V, void* ws, size_t ws_bytes,
+                         hipStream_t stream) {
+  if (!h || !A || !U || !S || !V) return RSVD_E_INVAL;
+  BatchLayout L;
+  const rsvd_status v = batch_layout(count, probs, L);
+  if (v != RSVD_OK) return v;
+  if (!ws || ws_bytes < L.total || !aligned16(ws)) return RSVD_E_WORKSPACE;
+  std::vector<const void*> ptrs;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!A[i] || !U[i] || !S[i] || !V[i]) return RSVD_E_INVAL;
+    ptrs.push_back(A[i]);
+    ptrs.push_back(U[i]);
+    ptrs.push_back(S[i]);
+    ptrs.push_back(V[i]);
   }
-  // U = Q U~_k (m x k), V = Bt U~_k S_k^-1 (n x k)
-  s = gemm(c, RSVD_NATIVE, false, Q, P.l, P.m, P.l, j.XU, P.k, (int32_t)P.k, U, P.k, no_split(P.l), nullptr,
-           nullptr);
-  if (s != RSVD_OK) return s;
-  return gemm(c, RSVD_NATIVE, false, Bt, P.l, P.n, P.l, j.XV, P.k, (int32_t)P.k, V, P.k, no_split(P.l), nullptr,
-              nullptr);
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
+  BatchPlan* bp = nullptr;
+  for (size_t i = 0; i < h->plans.size(); ++i) {
+    if (same_batch(*h->plans[i], count, probs, ptrs, ws)) {
+      bp = h->plans[i];
+      h->plans.erase(h->plans.begin() + (std::ptrdiff_t)i);
+      h->plans.push_back(bp);  // most recently used last
+      break;
+    }
+  }
+  if (!bp) {
+    const rsvd_status s = build_plan(h, count, probs, A, U, S, V, ws, L, bp);
+    if (s != RSVD_OK) return s;
+    if (h->plans.size() >= kMaxPlans) {
+      free_plan(h->plans.front());
+      h->plans.erase(h->plans.begin());
+    }
+    h->plans.push_back(bp);
+  }
+  RSVD_TRY(hipGraphLaunch(bp->exec, stream));
+  return RSVD_OK;
 }
 
 rsvd_status rsvd_draw_omega(rsvd_handle h, const rsvd_problem* pr, void* Omega, hipStream_t stream) {
@@ -546,7 +944,8 @@ rsvd_status rsvd_orth(rsvd_handle h, const rsvd_problem* pr, int64_t rows, void*
   Prologue pro = prologue(h, pr, ws, ws_bytes);
   if (pro.status != RSVD_OK) return pro.status;
   if (!Y || rows < pro.plan.l || rows > pro.plan.Mx) return RSVD_E_INVAL;
-  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h};
+  DirectRunner dr(h, stream);
+  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
   return orth(c, false, no_split(1), Y, rows, Y, R);
 }
 

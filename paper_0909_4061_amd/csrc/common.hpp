@@ -130,6 +130,69 @@ constexpr int SRFT_MAX_LOGN_F64 = 12;  // n <= 8192
 hipError_t launch_srft_rows(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, int32_t l,
                             const double* d, const int32_t* R, void* Y, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Batched launches: one grid runs one kernel family on many independent
+// problems.  Block b of the grid runs local block bm[b].local of problem
+// bm[b].item, whose parameter block is ps[bm[b].item]; both arrays live in
+// device memory.  The per-problem block count of a family is what its
+// single-problem launcher would launch.
+struct BlockMap { int32_t item, local; };
+
+struct GramReduceParams {
+  const double* gpart;
+  int64_t nblk;
+  int32_t Lg;
+  double* G;
+  int32_t* status;
+  const int32_t* gate;
+};
+struct OmegaParams {
+  void* omega;
+  int64_t n;
+  int32_t l;
+  uint64_t seed, sid;
+};
+struct FillParams {
+  int32_t* p;
+  int32_t v;
+  int64_t count;
+};
+struct TrmmParams {  // R = R2 * R1, upper triangular l x l (FP64)
+  const double* R2;
+  const double* R1;
+  double* R;
+  int32_t l;
+  const int32_t* gate;
+};
+struct CopyParams {
+  const double* src;
+  double* dst;
+  int64_t count;
+  const int32_t* gate;
+};
+
+int64_t gemm_blocks(int dtype, int prec, const GemmParams& p);
+int64_t gram_partial_blocks(const GramParams& p);
+int64_t gram_reduce_blocks(const GramReduceParams& p);
+int64_t omega_blocks(const OmegaParams& p);
+int64_t fill_blocks(const FillParams& p);
+int64_t trmm_blocks(const TrmmParams& p);
+int64_t copy_blocks(const CopyParams& p);
+
+hipError_t launch_gemm_batched(int dtype, int prec, bool trans, const GemmParams* ps, const BlockMap* bm,
+                               int64_t nblocks, hipStream_t st);
+hipError_t launch_gram_partial_batched(int dtype, const GramParams* ps, const BlockMap* bm, int64_t nblocks,
+                                       hipStream_t st);
+hipError_t launch_gram_reduce_batched(const GramReduceParams* ps, const BlockMap* bm, int64_t nblocks,
+                                      hipStream_t st);
+hipError_t launch_chol_batched(const CholParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
+hipError_t launch_jacobi_batched(const JacobiParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
+hipError_t launch_omega_batched(int dtype, const OmegaParams* ps, const BlockMap* bm, int64_t nblocks,
+                                hipStream_t st);
+hipError_t launch_fill_batched(const FillParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
+hipError_t launch_trmm_batched(const TrmmParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
+hipError_t launch_copy_batched(const CopyParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
+
 // Small utilities.
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, const int32_t* gate, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st);

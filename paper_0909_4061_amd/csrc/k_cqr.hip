@@ -30,13 +30,13 @@ namespace rsvd {
 namespace {
 
 template <typename T>
-__global__ __launch_bounds__(256) void gram_partial_kernel(const GramParams p) {
+__device__ __forceinline__ void gram_partial_body(const GramParams& p, const int bid) {
   constexpr int RB = GRAM_ROWS;
   constexpr int YLD = 128 + 1;
   __shared__ T Ys[RB * YLD];
   if (p.gate && *p.gate == 0) return;
   const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * RB;
+  const int64_t row0 = (int64_t)bid * RB;
   const int l = p.l, Lg = p.Lg;
 
   // Stage the rows (zero beyond l columns / beyond the last row).  Thread
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramParams p) {
   const int lane = tid & 63, wave = tid >> 6;
   const int nt = Lg / 16;
   const int ntiles = nt * (nt + 1) / 2;
-  double* gout = p.gpart + (int64_t)blockIdx.x * Lg * Lg;
+  double* gout = p.gpart + (int64_t)bid * Lg * Lg;
   for (int tile = wave; tile < ntiles; tile += 4) {
     int ti = 0, rem = tile;
     while (rem >= nt - ti) {
@@ -107,28 +107,43 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramParams p) {
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void gram_partial_kernel(const GramParams p) { gram_partial_body<T>(p, blockIdx.x); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram_partial_batched(const GramParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  gram_partial_body<T>(ps[b.item], b.local);
+}
+
 // Four threads per Gram entry, each summing every fourth block Gram; the four
 // sums are combined in a fixed order.
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ gpart, int64_t nblk,
-                                                          int32_t Lg, double* __restrict__ G, int32_t* status,
-                                                          const int32_t* gate) {
+__device__ __forceinline__ void gram_reduce_body(const GramReduceParams& p, const int bid) {
   __shared__ double red[4][64];
-  if (gate && *gate == 0) return;
+  if (p.gate && *p.gate == 0) return;
   const int tid = threadIdx.x;
   const int q = tid >> 6;
-  const int64_t e = (int64_t)blockIdx.x * 64 + (tid & 63);
-  const int64_t LL = (int64_t)Lg * Lg;
-  const bool live = e < LL && (e % Lg) >= (e / Lg);  // upper triangle only
+  const int64_t e = (int64_t)bid * 64 + (tid & 63);
+  const int64_t LL = (int64_t)p.Lg * p.Lg;
+  const bool live = e < LL && (e % p.Lg) >= (e / p.Lg);  // upper triangle only
   double acc = 0.0;
   if (live)
-    for (int64_t b = q; b < nblk; b += 4) acc += gpart[b * LL + e];
+    for (int64_t b = q; b < p.nblk; b += 4) acc += p.gpart[b * LL + e];
   red[q][tid & 63] = acc;
   __syncthreads();
   if (q == 0 && e < LL) {
     const double v = live ? ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid] : 0.0;
-    G[e] = v;
-    if (live && !isfinite(v)) atomicOr(status, (int32_t)RSVD_FLAG_NONFINITE);
+    p.G[e] = v;
+    if (live && !isfinite(v)) atomicOr(p.status, (int32_t)RSVD_FLAG_NONFINITE);
   }
+}
+
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const GramReduceParams p) { gram_reduce_body(p, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void gram_reduce_batched(const GramReduceParams* __restrict__ ps,
+                                                           const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  gram_reduce_body(ps[b.item], b.local);
 }
 
 // Cholesky with simultaneous inverse.  Thread (tr, tc) of a 32 x 32 grid owns
@@ -140,7 +155,8 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
 // for c <= j (E[j][j] = 1).  The masks fold into the multipliers, so each
 // element costs two FMAs; waves whose rows are all finished skip the update.
 // At the end U = D L^T, hence R = D^-1/2 U and R^-1 = E^T D^-1/2.
-__global__ __launch_bounds__(1024) void chol_kernel(const CholParams p) {
+__device__ __forceinline__ void chol_body(const CholParams& p, const int bid) {
+  (void)bid;  // one workgroup per factorization
   constexpr int TLD = 129;
   __shared__ double rowbuf[2][128];
   __shared__ double diag[128];
@@ -291,30 +307,66 @@ __global__ __launch_bounds__(1024) void chol_kernel(const CholParams p) {
   }
 }
 
-__global__ __launch_bounds__(256) void trmm_upper_kernel(const double* __restrict__ R2, const double* __restrict__ R1,
-                                                         double* __restrict__ R, int32_t l, const int32_t* gate) {
-  if (gate && *gate == 0) return;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(1024) void chol_kernel(const CholParams p) { chol_body(p, blockIdx.x); }
+
+__global__ __launch_bounds__(1024) void chol_batched(const CholParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  chol_body(ps[b.item], b.local);
+}
+
+__device__ __forceinline__ void trmm_body(const TrmmParams& p, const int bid) {
+  if (p.gate && *p.gate == 0) return;
+  const int l = p.l;
+  const int64_t idx = (int64_t)bid * 256 + threadIdx.x;
   if (idx >= (int64_t)l * l) return;
   const int i = (int)(idx / l), j = (int)(idx - (int64_t)i * l);
   double acc = 0.0;
-  for (int t = i; t <= j; ++t) acc += R2[(int64_t)i * l + t] * R1[(int64_t)t * l + j];
-  R[idx] = acc;
+  for (int t = i; t <= j; ++t) acc += p.R2[(int64_t)i * l + t] * p.R1[(int64_t)t * l + j];
+  p.R[idx] = acc;
 }
 
-__global__ __launch_bounds__(256) void copy_f64_kernel(const double* __restrict__ src, double* __restrict__ dst,
-                                                       int64_t count, const int32_t* gate) {
-  if (gate && *gate == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < count) dst[i] = src[i];
+__global__ __launch_bounds__(256) void trmm_upper_kernel(const TrmmParams p) { trmm_body(p, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void trmm_batched(const TrmmParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  trmm_body(ps[b.item], b.local);
+}
+
+__device__ __forceinline__ void copy_body(const CopyParams& p, const int bid) {
+  if (p.gate && *p.gate == 0) return;
+  const int64_t i = (int64_t)bid * 256 + threadIdx.x;
+  if (i < p.count) p.dst[i] = p.src[i];
+}
+
+__global__ __launch_bounds__(256) void copy_f64_kernel(const CopyParams p) { copy_body(p, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void copy_batched(const CopyParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  copy_body(ps[b.item], b.local);
 }
 
 }  // namespace
 
+int64_t trmm_blocks(const TrmmParams& p) { return ((int64_t)p.l * p.l + 255) / 256; }
+
+int64_t copy_blocks(const CopyParams& p) { return (p.count + 255) / 256; }
+
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, const int32_t* gate, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, src, dst, count,
-                     gate);
+  const CopyParams p{src, dst, count, gate};
+  hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)copy_blocks(p)), dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_trmm_batched(const TrmmParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(trmm_batched, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_batched(const CopyParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_batched, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
   return hipGetLastError();
 }
 
@@ -329,11 +381,37 @@ hipError_t launch_gram_partial(int dtype, const GramParams& p, hipStream_t st) {
   return hipGetLastError();
 }
 
+int64_t gram_partial_blocks(const GramParams& p) { return (p.rows + GRAM_ROWS - 1) / GRAM_ROWS; }
+
+int64_t gram_reduce_blocks(const GramReduceParams& p) { return ((int64_t)p.Lg * p.Lg + 63) / 64; }
+
 hipError_t launch_gram_reduce(const double* gpart, int64_t nblk, int32_t Lg, double* G, int32_t* status,
                               const int32_t* gate, hipStream_t st) {
-  const int64_t LL = (int64_t)Lg * Lg;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((LL + 63) / 64)), dim3(256), 0, st, gpart, nblk, Lg, G,
-                     status, gate);
+  const GramReduceParams p{gpart, nblk, Lg, G, status, gate};
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)gram_reduce_blocks(p)), dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_partial_batched(int dtype, const GramParams* ps, const BlockMap* bm, int64_t nblocks,
+                                       hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (dtype == RSVD_F64)
+    hipLaunchKernelGGL(gram_partial_batched<double>, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  else
+    hipLaunchKernelGGL(gram_partial_batched<float>, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_reduce_batched(const GramReduceParams* ps, const BlockMap* bm, int64_t nblocks,
+                                      hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gram_reduce_batched, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_batched(const CholParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(chol_batched, dim3((unsigned)nblocks), dim3(1024), 0, st, ps, bm);
   return hipGetLastError();
 }
 
@@ -345,8 +423,8 @@ hipError_t launch_chol(const CholParams& p, hipStream_t st) {
 
 hipError_t launch_trmm_upper(const double* R2, const double* R1, double* R, int32_t l, const int32_t* gate,
                              hipStream_t st) {
-  const int64_t n = (int64_t)l * l;
-  hipLaunchKernelGGL(trmm_upper_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R2, R1, R, l, gate);
+  const TrmmParams p{R2, R1, R, l, gate};
+  hipLaunchKernelGGL(trmm_upper_kernel, dim3((unsigned)trmm_blocks(p)), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 

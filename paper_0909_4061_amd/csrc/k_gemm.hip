@@ -114,7 +114,7 @@ __device__ inline void stage_load_x(const GemmParams& p, int64_t k0, int64_t ken
 // B[k = lane/32][j = lane%32]; result register e of lane holds
 // C[8*(e/4) + 4*(lane/32) + e%4][lane%32].
 template <bool TRANS>
-__global__ __launch_bounds__(256, 2) void gemm_f32_kernel(const GemmParams p) {
+__device__ __forceinline__ void gemm_f32_body(const GemmParams& p, const int bid) {
   constexpr int BM = 128, BK = 32;
   constexpr int ALD = TRANS ? BM + 4 : BK + 1;
   constexpr int XLD = 128 + 4;
@@ -124,8 +124,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(const GemmParams p) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int S = p.S;
-  const int s = blockIdx.x % S;
-  const int64_t i0 = (int64_t)(blockIdx.x / S) * BM;
+  const int s = bid % S;
+  const int64_t i0 = (int64_t)(bid / S) * BM;
   const int64_t kbeg = (int64_t)s * p.kchunk;
   const int64_t kend = min(p.K, kbeg + p.kchunk);
   const int NT = p.Lp / 32;
@@ -200,12 +200,21 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(const GemmParams p) {
   }
 }
 
+template <bool TRANS>
+__global__ __launch_bounds__(256, 2) void gemm_f32_kernel(const GemmParams p) { gemm_f32_body<TRANS>(p, blockIdx.x); }
+
+template <bool TRANS>
+__global__ __launch_bounds__(256, 2) void gemm_f32_batched(const GemmParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  gemm_f32_body<TRANS>(ps[b.item], b.local);
+}
+
 // ---------------------------------------------------------------------------
 // FP64: v_mfma_f64_16x16x4f64.  Operand lanes: A[i = lane%16][k = lane/16],
 // B[k = lane/16][j = lane%16]; result register e of lane holds
 // C[4*e + lane/16][lane%16].
 template <bool TRANS>
-__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmParams p) {
+__device__ __forceinline__ void gemm_f64_body(const GemmParams& p, const int bid) {
   constexpr int BM = 64, BK = 16;
   constexpr int ALD = TRANS ? BM + 2 : BK + 1;
   constexpr int XLD = 128 + 2;
@@ -215,8 +224,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmParams p) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int S = p.S;
-  const int s = blockIdx.x % S;
-  const int64_t i0 = (int64_t)(blockIdx.x / S) * BM;
+  const int s = bid % S;
+  const int64_t i0 = (int64_t)(bid / S) * BM;
   const int64_t kbeg = (int64_t)s * p.kchunk;
   const int64_t kend = min(p.K, kbeg + p.kchunk);
   const int NT = p.Lp / 16;
@@ -288,6 +297,15 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmParams p) {
   }
 }
 
+template <bool TRANS>
+__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmParams p) { gemm_f64_body<TRANS>(p, blockIdx.x); }
+
+template <bool TRANS>
+__global__ __launch_bounds__(256, 2) void gemm_f64_batched(const GemmParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  gemm_f64_body<TRANS>(ps[b.item], b.local);
+}
+
 // ---------------------------------------------------------------------------
 // BF16 / bf16x3: v_mfma_f32_32x32x16_bf16.  Operand lanes: A[i = lane%32][k =
 // 8*(lane/32) + t], B[k = 8*(lane/32) + t][j = lane%32] for t = 0..7; result
@@ -296,7 +314,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmParams p) {
 // once per stage into transposed hi/lo planes so a B fragment is one 16-byte
 // LDS read.
 template <bool TRANS, int NP>
-__global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const GemmParams p) {
+__device__ __forceinline__ void gemm_bf16_body(const GemmParams& p, const int bid) {
   constexpr int BM = 128, BK = 32;
   constexpr int ALD = TRANS ? BM + 4 : BK + 4;
   constexpr int XT = BK + 8;  // bf16 elements per transposed X column
@@ -307,8 +325,8 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const GemmParams p) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int S = p.S;
-  const int s = blockIdx.x % S;
-  const int64_t i0 = (int64_t)(blockIdx.x / S) * BM;
+  const int s = bid % S;
+  const int64_t i0 = (int64_t)(bid / S) * BM;
   const int64_t kbeg = (int64_t)s * p.kchunk;
   const int64_t kend = min(p.K, kbeg + p.kchunk);
   const int NT = p.Lp / 32;
@@ -407,6 +425,15 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const GemmParams p) {
   }
 }
 
+template <bool TRANS, int NP>
+__global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(const GemmParams p) { gemm_bf16_body<TRANS, NP>(p, blockIdx.x); }
+
+template <bool TRANS, int NP>
+__global__ __launch_bounds__(256, 2) void gemm_bf16_batched(const GemmParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  gemm_bf16_body<TRANS, NP>(ps[b.item], b.local);
+}
+
 }  // namespace
 
 GemmTile gemm_tile(int dtype, int prec) {
@@ -415,13 +442,24 @@ GemmTile gemm_tile(int dtype, int prec) {
   return GemmTile{128, 32, 32};
 }
 
-hipError_t launch_gemm(int dtype, int prec, bool trans, const GemmParams& p, hipStream_t st) {
+int64_t gemm_blocks(int dtype, int prec, const GemmParams& p) {
   const GemmTile tile = gemm_tile(dtype, prec);
+  return (p.rows + tile.bm - 1) / tile.bm * p.S;
+}
+
+namespace {
+
+bool gemm_params_ok(int dtype, int prec, const GemmParams& p) {
+  const GemmTile tile = gemm_tile(dtype, prec);
+  return p.ncols <= 128 && p.Lp <= 128 && p.Lp % tile.lp_mult == 0 && p.Lp >= p.ncols && p.S >= 1;
+}
+
+}  // namespace
+
+hipError_t launch_gemm(int dtype, int prec, bool trans, const GemmParams& p, hipStream_t st) {
   if (p.rows <= 0) return hipSuccess;
-  if (p.ncols > 128 || p.Lp > 128 || p.Lp % tile.lp_mult != 0 || p.Lp < p.ncols || p.S < 1)
-    return hipErrorInvalidValue;
-  const int64_t nrb = (p.rows + tile.bm - 1) / tile.bm;
-  const dim3 grid((unsigned)(nrb * p.S)), block(256);
+  if (!gemm_params_ok(dtype, prec, p)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)gemm_blocks(dtype, prec, p)), block(256);
   if (dtype == RSVD_F64) {
     if (trans)
       hipLaunchKernelGGL(gemm_f64_kernel<true>, grid, block, 0, st, p);
@@ -442,6 +480,34 @@ hipError_t launch_gemm(int dtype, int prec, bool trans, const GemmParams& p, hip
       hipLaunchKernelGGL(gemm_f32_kernel<true>, grid, block, 0, st, p);
     else
       hipLaunchKernelGGL(gemm_f32_kernel<false>, grid, block, 0, st, p);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_batched(int dtype, int prec, bool trans, const GemmParams* ps, const BlockMap* bm,
+                               int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nblocks), block(256);
+  if (dtype == RSVD_F64) {
+    if (trans)
+      hipLaunchKernelGGL(gemm_f64_batched<true>, grid, block, 0, st, ps, bm);
+    else
+      hipLaunchKernelGGL(gemm_f64_batched<false>, grid, block, 0, st, ps, bm);
+  } else if (prec == PREC_BF16X3) {
+    if (trans)
+      hipLaunchKernelGGL((gemm_bf16_batched<true, 3>), grid, block, 0, st, ps, bm);
+    else
+      hipLaunchKernelGGL((gemm_bf16_batched<false, 3>), grid, block, 0, st, ps, bm);
+  } else if (prec == PREC_BF16) {
+    if (trans)
+      hipLaunchKernelGGL((gemm_bf16_batched<true, 1>), grid, block, 0, st, ps, bm);
+    else
+      hipLaunchKernelGGL((gemm_bf16_batched<false, 1>), grid, block, 0, st, ps, bm);
+  } else {
+    if (trans)
+      hipLaunchKernelGGL(gemm_f32_batched<true>, grid, block, 0, st, ps, bm);
+    else
+      hipLaunchKernelGGL(gemm_f32_batched<false>, grid, block, 0, st, ps, bm);
   }
   return hipGetLastError();
 }

@@ -24,14 +24,14 @@ namespace {
 constexpr double kTwoPi = 0x1.921fb54442d18p+2;  // the double nearest 2*pi
 
 template <typename T>
-__global__ __launch_bounds__(256) void omega_kernel(T* __restrict__ omega, int64_t n, int32_t l,
-                                                    uint64_t seed, uint64_t sid) {
+__device__ __forceinline__ void omega_body(const OmegaParams& p, const int bid) {
+  const int32_t l = p.l;
   const int32_t qpr = (l + 3) / 4;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * qpr) return;
+  const int64_t t = (int64_t)bid * 256 + threadIdx.x;
+  if (t >= p.n * qpr) return;
   const int64_t i = t / qpr;
   const int32_t j0 = (int32_t)(t - i * qpr) * 4;
-  const Philox4 w = philox4x64_10((uint64_t)t, sid, 0ull, 0ull, seed, 0ull);
+  const Philox4 w = philox4x64_10((uint64_t)t, p.sid, 0ull, 0ull, p.seed, 0ull);
   const double u0 = philox_uniform(w.w[0]), u1 = philox_uniform(w.w[1]);
   const double u2 = philox_uniform(w.w[2]), u3 = philox_uniform(w.w[3]);
   const double r01 = sqrt(-2.0 * log(u0));
@@ -43,10 +43,19 @@ __global__ __launch_bounds__(256) void omega_kernel(T* __restrict__ omega, int64
   g[1] = r01 * sin(th01);
   g[2] = r23 * cos(th23);
   g[3] = r23 * sin(th23);
-  T* row = omega + i * l;
+  T* row = static_cast<T*>(p.omega) + i * l;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     if (j0 + r < l) row[j0 + r] = (T)g[r];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void omega_kernel(const OmegaParams p) { omega_body<T>(p, blockIdx.x); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void omega_batched(const OmegaParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  omega_body<T>(ps[b.item], b.local);
 }
 
 __global__ __launch_bounds__(256) void srft_signs_kernel(double* __restrict__ d, int64_t n, uint64_t seed,
@@ -88,21 +97,48 @@ __global__ __launch_bounds__(256) void srft_sample_kernel(int32_t* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int32_t v, int64_t count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = v;
+__device__ __forceinline__ void fill_body(const FillParams& p, const int bid) {
+  const int64_t i = (int64_t)bid * 256 + threadIdx.x;
+  if (i < p.count) p.p[i] = p.v;
+}
+
+__global__ __launch_bounds__(256) void fill_i32_kernel(const FillParams p) { fill_body(p, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void fill_batched(const FillParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  fill_body(ps[b.item], b.local);
 }
 
 }  // namespace
 
+int64_t omega_blocks(const OmegaParams& p) { return (p.n * ((p.l + 3) / 4) + 255) / 256; }
+
+int64_t fill_blocks(const FillParams& p) { return (p.count + 255) / 256; }
+
 hipError_t launch_omega(int dtype, void* omega, int64_t n, int32_t l, uint64_t seed, uint64_t sid,
                         hipStream_t st) {
-  const int64_t quads = n * ((l + 3) / 4);
-  const dim3 grid((unsigned)((quads + 255) / 256));
+  const OmegaParams p{omega, n, l, seed, sid};
+  const dim3 grid((unsigned)omega_blocks(p));
   if (dtype == RSVD_F64)
-    hipLaunchKernelGGL(omega_kernel<double>, grid, dim3(256), 0, st, (double*)omega, n, l, seed, sid);
+    hipLaunchKernelGGL(omega_kernel<double>, grid, dim3(256), 0, st, p);
   else
-    hipLaunchKernelGGL(omega_kernel<float>, grid, dim3(256), 0, st, (float*)omega, n, l, seed, sid);
+    hipLaunchKernelGGL(omega_kernel<float>, grid, dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_omega_batched(int dtype, const OmegaParams* ps, const BlockMap* bm, int64_t nblocks,
+                                hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (dtype == RSVD_F64)
+    hipLaunchKernelGGL(omega_batched<double>, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  else
+    hipLaunchKernelGGL(omega_batched<float>, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_batched(const FillParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_batched, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
   return hipGetLastError();
 }
 
@@ -116,7 +152,8 @@ hipError_t launch_srft_draw(double* d, int32_t* R, int64_t n, int32_t l, uint64_
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, v, count);
+  const FillParams f{p, v, count};
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)fill_blocks(f)), dim3(256), 0, st, f);
   return hipGetLastError();
 }
 

@@ -45,7 +45,8 @@ __device__ inline double group8_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(512) void jacobi_kernel(const JacobiParams p) {
+__device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid) {
+  (void)bid;  // one workgroup per matrix
   __shared__ __attribute__((aligned(16))) double Cs[JAC_MAXL * JAC_LDC];  // column c at Cs[c * JAC_LDC + row]
   __shared__ double sig_s[JAC_MAXL];
   __shared__ int rank_s[JAC_MAXL];
@@ -170,11 +171,24 @@ __global__ __launch_bounds__(512) void jacobi_kernel(const JacobiParams p) {
   }
 }
 
+__global__ __launch_bounds__(512) void jacobi_kernel(const JacobiParams p) { jacobi_body(p, blockIdx.x); }
+
+__global__ __launch_bounds__(512) void jacobi_batched(const JacobiParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  jacobi_body(ps[b.item], b.local);
+}
+
 }  // namespace
 
 hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st) {
   if (p.l < 1 || p.l > JAC_MAXL || p.k < 1 || p.k > p.l) return hipErrorInvalidValue;
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(512), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_batched(const JacobiParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_batched, dim3((unsigned)nblocks), dim3(512), 0, st, ps, bm);
   return hipGetLastError();
 }
 

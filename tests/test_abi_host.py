@@ -113,3 +113,22 @@ def test_null_arguments_fail_before_launch(lib):
     assert lib.rsvd_draw_srft(None, ctypes.byref(pr), None, None, None) == 1
     assert lib.rsvd_device_status(None, None, None) == 1
     assert lib.rsvd_create(None, 0) == 1
+
+
+def test_batched_workspace_and_validation(lib):
+    import torch
+    from paper_0909_4061_amd import RsvdProblem, problem
+    ok = [problem(300, 200, 10, 8, 1, dtype=torch.float32), problem(64, 64, 4, 8, 1, dtype=torch.float32)]
+    arr = (RsvdProblem * 2)(*ok)
+    assert lib.rsvd_batched_workspace_bytes(2, arr) > 0
+    assert lib.rsvd_batched_workspace_bytes(0, arr) == 0
+    mixed = (RsvdProblem * 2)(ok[0], problem(64, 64, 4, 8, 1, dtype=torch.float64))
+    assert lib.rsvd_batched_workspace_bytes(2, mixed) == 0           # dtypes differ
+    other_q = (RsvdProblem * 2)(ok[0], problem(64, 64, 4, 8, 2, dtype=torch.float32))
+    assert lib.rsvd_batched_workspace_bytes(2, other_q) == 0         # q differs
+    srft = (RsvdProblem * 1)(problem(64, 64, 4, 8, 0, dtype=torch.float32, sketch="srft"))
+    assert lib.rsvd_batched_workspace_bytes(1, srft) == 0            # Gaussian sketch only
+    bad = (RsvdProblem * 1)(problem(64, 64, 60, 8, 1, dtype=torch.float32))
+    assert lib.rsvd_batched_workspace_bytes(1, bad) == 0             # l > min(m, n)
+    # no handle: rejected on the host before any launch
+    assert lib.rsvd_batched(None, 2, arr, None, None, None, None, None, 0, None) == 1

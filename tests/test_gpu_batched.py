@@ -1,0 +1,158 @@
+"""Batched randomized SVD (many independent matrices, one launch per step,
+replayed from a HIP graph) vs the FP64 oracle, through the C ABI (marked gpu).
+
+Every matrix of a batch is compared with the oracle run on exactly that
+matrix with its own (seed, stream) draw: |dsigma_j| <= r sigma_j +
+(4 sqrt(m) + 2 l) u sigma_1 with r = 1e-12 (FP64) / 1e-5 (FP32) and u the
+unit roundoff of the element type.
+The absolute term is the resolution of FP32 arithmetic: B = Q* A formed in
+FP32 differs from the exact product by about sqrt(m) u ||A||_2 in norm, and
+the FP32 basis Q from CholeskyQR2 is orthonormal only to about l u, so its
+columns carry about l u sigma_1 of the leading direction; by Weyl's
+inequality these bound the change of every singular value, and values of a
+fast-decaying spectrum below that level carry no relative accuracy.  In FP64
+the same holds with u = 2^-53: the small SVD works on a backward-stable
+triangular factor of B*, so its singular values have absolute errors of
+order l u sigma_1.  The residual ||A - U S V*|| must be within 1e-10 (FP64) /
+1% (FP32) of the oracle's, with the same floor; U is orthonormal.
+Inputs: U diag(exp(-j/r)) V^T with the uneven shapes of the batched workload
+(workloads.batch_shapes), scaled down where noted so the oracle finishes in
+seconds.  With decay rates r of 2 to 3 the sampled matrix after a power step
+is too ill-conditioned for an unshifted CholeskyQR in FP32, so the shifted
+third pass runs and the status word reports RSVD_FLAG_SHIFTED; only the
+non-finite and no-convergence bits count as failures.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_0909_4061_amd as rs
+from oracle import evaluate, rsvd as orsvd
+from tests.gpu_common import to_np
+from workloads import batch_shapes, build_matrix, spectrum
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+
+def _flags_ok():
+    return rs.device_status(DEV) & ~rs.RSVD_FLAG_SHIFTED == 0
+
+
+@pytest.fixture(autouse=True)
+def _clear_status():
+    # the handle's status word accumulates until read: leave it clear for the next test
+    yield
+    rs.device_status(DEV)
+
+
+def _matrices(shapes, dtype, seed0=7):
+    mats = []
+    for i, (m, n, k, r) in enumerate(shapes):
+        A64 = build_matrix(m, n, spectrum("exp_r", n, rate=r), seed=seed0 + i,
+                           dtype=np.float32 if dtype == torch.float32 else np.float64)
+        mats.append(torch.from_numpy(A64).to(DEV))
+    return mats
+
+
+def _check(As, outs, ks, p, q, seed, fp64):
+    for i, (A, (U, S, V), k) in enumerate(zip(As, outs, ks)):
+        A64 = to_np(A).astype(np.float64)
+        ref = orsvd.rsvd(A64, k, p, q, seed=seed, stream=i, dtype=np.float64 if fp64 else np.float32)
+        Sg = to_np(S).astype(np.float64)
+        floor = (4.0 * np.sqrt(max(A.shape)) + 2.0 * (k + p)) * (U64 if fp64 else U32) * ref["Sk"][0]
+        Ug, Vg = to_np(U).astype(np.float64), to_np(V).astype(np.float64)
+        res = evaluate.residual_usv(A64, Ug, Sg, Vg)
+        res_ref = evaluate.residual_usv(A64, ref["Uk"], ref["Sk"], ref["Vk"])
+        err = np.abs(Sg - ref["Sk"])
+        if fp64:
+            assert np.all(err <= 1e-12 * ref["Sk"] + floor), (i, np.max(err / (1e-12 * ref["Sk"] + floor)))
+            assert abs(res - res_ref) <= 1e-10 * res_ref + floor, (i, res, res_ref)
+            assert evaluate.orthonormality_error(Ug) <= 1e-12
+        else:
+            assert np.all(err <= 1e-5 * ref["Sk"] + floor), (i, np.max(err / (1e-5 * ref["Sk"] + floor)))
+            assert res <= max(1.01 * res_ref, res_ref + floor), (i, res, res_ref)
+            assert evaluate.orthonormality_error(Ug) <= 1e-5
+
+
+def test_batched_fp32_uneven_shapes():
+    # 24 shapes of the batched workload, m and n capped at 512 to keep the oracle quick
+    shapes = [(min(m, 512), min(n, 512, m), k, r) for m, n, k, r in batch_shapes(24)]
+    shapes = [(m, n, min(k, n - 8), r) for m, n, k, r in shapes]
+    As = _matrices(shapes, torch.float32)
+    ks = [s[2] for s in shapes]
+    outs = rs.rsvd_batched(As, ks, p=8, q=1, seed=11)
+    torch.cuda.synchronize()
+    assert _flags_ok()
+    _check(As, outs, ks, 8, 1, 11, fp64=False)
+
+
+def test_batched_fp64_edge_shapes():
+    # l = min(m, n), fewer rows than one GEMM tile, a single-column target, n = m
+    shapes = [(200, 100, 92, 5.0), (37, 20, 12, 3.0), (64, 64, 1, 8.0), (300, 300, 40, 20.0), (129, 65, 9, 2.0)]
+    As = _matrices(shapes, torch.float64, seed0=40)
+    ks = [s[2] for s in shapes]
+    outs = rs.rsvd_batched(As, ks, p=8, q=1, seed=3)
+    torch.cuda.synchronize()
+    assert _flags_ok()
+    _check(As, outs, ks, 8, 1, 3, fp64=True)
+
+
+def test_batched_replay_reads_current_inputs():
+    shapes = [(256, 128, 10, 6.0), (128, 96, 20, 12.0), (512, 64, 8, 3.0)]
+    As = _matrices(shapes, torch.float32, seed0=90)
+    ks = [s[2] for s in shapes]
+    pr = [rs.problem(A.shape[0], A.shape[1], k, 8, 1, dtype=A.dtype, seed=5, stream_id=i)
+          for i, (A, k) in enumerate(zip(As, ks))]
+    ws = rs.BatchWorkspace(pr, DEV)
+    outs = rs.rsvd_batched(As, ks, p=8, q=1, seed=5, ws=ws)        # records the plan
+    torch.cuda.synchronize()
+    first = [tuple(t.clone() for t in o) for o in outs]
+    for o in outs:
+        for t in o:
+            t.zero_()
+    rs.rsvd_batched(As, ks, p=8, q=1, seed=5, outs=outs, ws=ws)     # replays the graph
+    torch.cuda.synchronize()
+    for o, f in zip(outs, first):
+        for a, b in zip(o, f):
+            assert torch.equal(a, b)
+    # new contents in the same buffers: the replay computes the new SVDs
+    for A in As:
+        A.mul_(2.0)
+    rs.rsvd_batched(As, ks, p=8, q=1, seed=5, outs=outs, ws=ws)
+    torch.cuda.synchronize()
+    for o, f in zip(outs, first):
+        np.testing.assert_allclose(to_np(o[1]), 2.0 * to_np(f[1]), rtol=1e-5)
+    assert _flags_ok()
+
+
+def test_batched_many_plans_evicted():
+    # more distinct batches than the handle keeps: each still computes correctly
+    for j in range(6):
+        shapes = [(96 + 16 * j, 64, 6, 4.0), (80, 72, 10, 9.0)]
+        As = _matrices(shapes, torch.float64, seed0=200 + 3 * j)
+        ks = [s[2] for s in shapes]
+        outs = rs.rsvd_batched(As, ks, p=8, q=1, seed=j)
+        torch.cuda.synchronize()
+        _check(As, outs, ks, 8, 1, j, fp64=True)
+    assert _flags_ok()
+
+
+def test_batched_bf16x3_matches_fp32_quality():
+    shapes = [(min(m, 1024), min(n, 512, m), k, r) for m, n, k, r in batch_shapes(8, seed=99)]
+    shapes = [(m, n, min(k, n - 8), r) for m, n, k, r in shapes]
+    As = _matrices(shapes, torch.float32, seed0=300)
+    ks = [s[2] for s in shapes]
+    o32 = rs.rsvd_batched(As, ks, p=8, q=1, seed=2)
+    o3 = rs.rsvd_batched(As, ks, p=8, q=1, seed=2, prec="bf16x3")
+    torch.cuda.synchronize()
+    for A, a, b, k in zip(As, o32, o3, ks):
+        A64 = to_np(A).astype(np.float64)
+        ra = evaluate.residual_usv(A64, *[to_np(t).astype(np.float64) for t in a])
+        rb = evaluate.residual_usv(A64, *[to_np(t).astype(np.float64) for t in b])
+        sk = np.linalg.svd(A64, compute_uv=False)[0]
+        assert rb <= 1.01 * ra + (4.0 * np.sqrt(max(A64.shape)) + 2.0 * (k + 8)) * U32 * sk
+    assert _flags_ok()
