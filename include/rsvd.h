@@ -172,6 +172,31 @@ rsvd_status rsvd_svd(rsvd_handle handle, const rsvd_problem* problem,
                      const void* Bt, const void* Q, void* U, void* S, void* V,
                      void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* --- Differentiation ---------------------------------------------------- */
+
+/* Workspace bytes of rsvd_backward (0 if the problem is invalid or uses the
+ * SRFT sketch). */
+size_t rsvd_backward_workspace_bytes(const rsvd_problem* problem);
+
+/* Adjoint (vector-Jacobian product) of the map A -> (U, S, V) computed by
+ * rsvd_range_finder, rsvd_power_iter, rsvd_project and rsvd_svd for the same
+ * problem, with the test matrix held fixed (same seed and stream_id; Gaussian
+ * sketch only).  Given the adjoints gU (m x k), gS (k) and gV (n x k) of the
+ * outputs (DEVICE, element type, dense row-major), writes gA (m x n, dense
+ * row-major, leading dimension n) = sum of gU . dU + gS . dS + gV . dV over a
+ * perturbation dA.  The forward is recomputed inside (nothing is kept from an
+ * earlier call), then each step is differentiated in reverse: the SVD of the
+ * small matrix B (standard thin-SVD derivative, FP64), B = Q* A, every
+ * CholeskyQR of the power scheme (gY = (gQ + Q sym(-gQ^T Q)) R^-T, FP64 for
+ * the l x l parts) and the products with A; gA is the sum of 2q + 2 rank-l
+ * terms, formed by one product.  The derivative exists where B has full rank
+ * l, its k leading singular values are distinct and sigma_k > sigma_(k+1);
+ * near those points it grows like 1 / (sigma_i^2 - sigma_j^2). */
+rsvd_status rsvd_backward(rsvd_handle handle, const rsvd_problem* problem,
+                          const void* A, const void* gU, const void* gS,
+                          const void* gV, void* gA, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+
 /* --- Many independent problems --------------------------------------- */
 
 /* Workspace bytes rsvd_batched needs for `count` problems (0 if any problem is

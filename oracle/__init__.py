@@ -18,6 +18,10 @@ rsvd        The method itself, step by step in FP64 with LAPACK (through numpy)
             of Section 1.6.
 evaluate    Residual norms ||A - QQ*A|| and ||A - U S V*|| and the paper's error
             bounds (Theorems 9.1-9.3, 10.5, 10.6, Corollaries 10.9, 10.10).
+rsvd_grad   The reference gradient of the fixed-Omega randomized SVD: the same
+            forward map in plain PyTorch CPU FP64, differentiated by autograd
+            (the paper defines no derivative; this is the FP64 reference the
+            hand-written adjoint is compared with).
 
 Every function is pinned by a CPU test (tests/test_oracle_*.py) against
 something other than itself: numpy's own Philox, brute-force DFTs and SVDs,
@@ -25,3 +29,4 @@ exact-rank recovery and the deterministic theorems of Section 9.
 """
 
 from . import philox, rsvd, evaluate  # noqa: F401
+# rsvd_grad imports torch; it is imported on its own where needed.

@@ -176,7 +176,13 @@ def rsvd_svd(Bt, Q, m, n, k, p, *, q=0, dtype=torch.float32, sketch="gaussian", 
 
 def rsvd(A, k, p=10, q=0, *, sketch="gaussian", prec="native", seed=0, stream_id=0, ws=None,
          return_q=False):
-    """Randomized SVD of A: the four entry points in sequence.  Returns (U, S, V)."""
+    """Randomized SVD of A: the four entry points in sequence.  Returns (U, S, V).
+
+    When A requires grad (and grad mode is on) the result is differentiable
+    through RSVDFunction, whose backward is the library's rsvd_backward.
+    """
+    if A.requires_grad and torch.is_grad_enabled() and not return_q:
+        return RSVDFunction.apply(A, k, p, q, seed, stream_id, prec)
     pr = _prob_for(A, k, p, q, sketch, prec, seed, stream_id)
     ws = ws or Workspace(pr, A.device)
     kw = dict(sketch=sketch, prec=prec, seed=seed, stream_id=stream_id, ws=ws)
@@ -200,6 +206,49 @@ def rsvd_sketch(A, k, p, *, sketch="gaussian", prec="native", seed=0, stream_id=
     _lib.check(h.lib.rsvd_sketch(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(Y), ws.ptr, ws.nbytes, _stream(A.device)),
                "rsvd_sketch")
     return Y
+
+
+def rsvd_backward(A, gU, gS, gV, k, p, q, *, prec="native", seed=0, stream_id=0, gA=None, ws=None):
+    """gA = the adjoint of A -> (U, S, V) applied to (gU, gS, gV) (fixed test matrix)."""
+    pr = _prob_for(A, k, p, q, "gaussian", prec, seed, stream_id)
+    dev = A.device
+    h = handle(dev)
+    if ws is None:
+        nbytes = h.lib.rsvd_backward_workspace_bytes(ctypes.byref(pr))
+        if nbytes == 0:
+            raise RsvdError(validate(pr) or _lib.RSVD_E_UNSUPPORTED, "rsvd_backward_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    gU, gS, gV = (t.detach().to(A.dtype).contiguous() for t in (gU, gS, gV))
+    if gA is None:
+        gA = torch.empty(A.shape, dtype=A.dtype, device=dev)
+    _lib.check(h.lib.rsvd_backward(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(gU), _ptr(gS), _ptr(gV), _ptr(gA),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)), "rsvd_backward")
+    return gA
+
+
+class RSVDFunction(torch.autograd.Function):
+    """(U, S, V) = rsvd(A) with the library's hand-written adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, A, k, p, q, seed, stream_id, prec):
+        Ad = A.detach()
+        with torch.no_grad():
+            U, S, V = rsvd(Ad, k, p, q, seed=seed, stream_id=stream_id, prec=prec)
+        ctx.save_for_backward(Ad)
+        ctx.cfg = (k, p, q, seed, stream_id, prec)
+        return U, S, V
+
+    @staticmethod
+    def backward(ctx, gU, gS, gV):
+        (A,) = ctx.saved_tensors
+        k, p, q, seed, stream_id, prec = ctx.cfg
+        m, n = A.shape
+        z = lambda shape: torch.zeros(shape, dtype=A.dtype, device=A.device)
+        gU = z((m, k)) if gU is None else gU
+        gS = z((k,)) if gS is None else gS
+        gV = z((n, k)) if gV is None else gV
+        gA = rsvd_backward(A.contiguous(), gU, gS, gV, k, p, q, prec=prec, seed=seed, stream_id=stream_id)
+        return gA, None, None, None, None, None, None
 
 
 class BatchWorkspace:

@@ -29,7 +29,7 @@ RSVD_MAX_L = 128
 EXPORTS = [
     "rsvd_create", "rsvd_destroy", "rsvd_validate", "rsvd_workspace_bytes", "rsvd_status_string",
     "rsvd_range_finder", "rsvd_power_iter", "rsvd_project", "rsvd_svd",
-    "rsvd_batched_workspace_bytes", "rsvd_batched",
+    "rsvd_batched_workspace_bytes", "rsvd_batched", "rsvd_backward_workspace_bytes", "rsvd_backward",
     "rsvd_sketch", "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
     "rsvd_profile_enable", "rsvd_profile_read",
 ]
@@ -79,6 +79,8 @@ def load():
         "rsvd_svd": ([vp, prob, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_sketch": ([vp, prob, vp, vp, vp, sz, vp], i32),
         "rsvd_batched_workspace_bytes": ([i32, prob], sz),
+        "rsvd_backward_workspace_bytes": ([prob], sz),
+        "rsvd_backward": ([vp, prob, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_batched": ([vp, i32, prob, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                           ctypes.POINTER(vp), vp, sz, vp], i32),
         "rsvd_draw_omega": ([vp, prob, vp, vp], i32),

@@ -299,7 +299,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 // the result is left as partial products; otherwise it is written to `out`.
 rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda, int64_t rows, int64_t K,
                  const void* X, int64_t ldx, int32_t ncols, void* out, int64_t ldo, const Split& sp, void* part,
-                 const int32_t* gate, bool streams_a = false) {
+                 const int32_t* gate, bool streams_a = false, bool accum = false) {
   const GemmTile t = gemm_tile(c.P.dtype, prec);
   GemmParams g{};
   g.A = A;
@@ -318,7 +318,9 @@ rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda,
   const int vec_mult = c.P.esize == 8 ? 2 : 4;
   g.vec = (lda % vec_mult == 0 && aligned16(A)) ? 1 : 0;
   g.gate = gate;
+  g.accum = accum ? 1 : 0;
   if (g.S > 1 && !part) return RSVD_E_INVAL;
+  if (accum && (g.S > 1 || streams_a)) return RSVD_E_INVAL;
   const int kind = streams_a ? (trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN) : RSVD_KERNEL_SMALL_GEMM;
   if (streams_a && c.P.dtype == RSVD_F32 && !c.run->records()) {
     g.Lp = (int32_t)round_up(ncols, 32);
@@ -496,7 +498,7 @@ rsvd_status project_steps(const Ctx& c, const rsvd_problem* pr, const void* A, c
 // as with a Householder QR.  For FP32 data R is the Cholesky factor of the
 // FP64 Gram B B* itself, whose error (u_64 sigma_1^2 / sigma_j relative to
 // sigma_j) stays below what FP32 arithmetic resolves.
-rsvd_status svd_steps(const Ctx& c, const void* Bt, const void* Q, void* U, void* S, void* V) {
+rsvd_status small_svd(const Ctx& c, const void* Bt, void* S, JacobiParams& j) {
   const Plan& P = c.P;
   double* R = c.at<double>(P.R1);
   rsvd_status s;
@@ -509,7 +511,7 @@ rsvd_status svd_steps(const Ctx& c, const void* Bt, const void* Q, void* U, void
     if (s == RSVD_OK) s = chol(c, P.n, R, false, nullptr, nullptr);
   }
   if (s != RSVD_OK) return s;
-  JacobiParams j{};
+  j = JacobiParams{};
   j.R = R;
   j.l = (int32_t)P.l;
   j.k = (int32_t)P.k;
@@ -521,12 +523,247 @@ rsvd_status svd_steps(const Ctx& c, const void* Bt, const void* Q, void* U, void
   j.S = S;
   j.status = c.status;
   RSVD_TRY(c.run->jacobi(j));
+  return RSVD_OK;
+}
+
+rsvd_status svd_steps(const Ctx& c, const void* Bt, const void* Q, void* U, void* S, void* V) {
+  const Plan& P = c.P;
+  JacobiParams j;
+  rsvd_status s = small_svd(c, Bt, S, j);
+  if (s != RSVD_OK) return s;
   // U = Q U~_k (m x k), V = Bt U~_k S_k^-1 (n x k)
   s = gemm(c, RSVD_NATIVE, false, Q, P.l, P.m, P.l, j.XU, P.k, (int32_t)P.k, U, P.k, no_split(P.l), nullptr,
            nullptr);
   if (s != RSVD_OK) return s;
   return gemm(c, RSVD_NATIVE, false, Bt, P.l, P.n, P.l, j.XV, P.k, (int32_t)P.k, V, P.k, no_split(P.l), nullptr,
               nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the fixed-Omega randomized SVD: (gU, gS, gV) -> gA.
+
+// Workspace of the adjoint, after the forward plan: every basis of the forward
+// (Q_0..Q_q, Qt_1..Qt_q) with its combined triangular factor, B*, the
+// adjoint temporaries, and the two factors of gA = Left RightT.
+struct BwdLayout {
+  Plan P;
+  int q;
+  int64_t Kc;  // (2q + 2) l
+  size_t Qs, Qts, Rs, Rts, Bt, gBt, gQ, gQt, gYt, T1, T2, Mq, Z, W1, M1p64, UhT, Rinv, Sy, W64, SW64, M2_64, Ukt64,
+      M1p, W, SW, M2, Ukt, Sk, Left, RightT, total;
+};
+
+BwdLayout bwd_layout(const rsvd_problem* pr) {
+  BwdLayout L{};
+  L.P = make_plan(pr);
+  const Plan& P = L.P;
+  L.q = pr->q;
+  L.Kc = (int64_t)(2 * pr->q + 2) * P.l;
+  const size_t es = (size_t)P.esize, ml = (size_t)(P.m * P.l) * es, nl = (size_t)(P.n * P.l) * es;
+  const size_t ll8 = (size_t)(P.l * P.l) * 8, lle = (size_t)(P.l * P.l) * es;
+  const size_t lk8 = (size_t)(P.l * P.k) * 8, lke = (size_t)(P.l * P.k) * es;
+  size_t off = P.total;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align_up(std::max<size_t>(bytes, 1));
+    return at;
+  };
+  L.Qs = take(ml * (size_t)(L.q + 1));
+  L.Qts = take(nl * (size_t)std::max(L.q, 1));
+  L.Rs = take(ll8 * (size_t)(L.q + 1));
+  L.Rts = take(ll8 * (size_t)std::max(L.q, 1));
+  L.Bt = take(nl);
+  L.gBt = take(nl);
+  L.gQ = take(ml);
+  L.gQt = take(nl);
+  L.gYt = take(nl);
+  L.T1 = take(lke);
+  L.T2 = take(lke);
+  L.Mq = take(lle);
+  L.Z = take(ll8);
+  L.W1 = take(ll8);
+  L.M1p64 = take(ll8);
+  L.UhT = take(ll8);
+  L.Rinv = take(ll8);
+  L.Sy = take(ll8);
+  L.W64 = take(ll8);
+  L.SW64 = take(ll8);
+  L.M2_64 = take(lk8);
+  L.Ukt64 = take(lk8);
+  L.M1p = take(lle);
+  L.W = take(lle);
+  L.SW = take(lle);
+  L.M2 = take(lke);
+  L.Ukt = take(lke);
+  L.Sk = take((size_t)P.k * es);
+  L.Left = take((size_t)(P.m * L.Kc) * es);
+  L.RightT = take((size_t)(L.Kc * P.n) * es);
+  L.total = off;
+  return L;
+}
+
+rsvd_status copy2d(const Ctx& c, const void* src, int sdt, int64_t lds, void* dst, int ddt, int64_t ldd, int64_t rows,
+                   int64_t cols, bool trans) {
+  const Copy2dParams p{src, sdt, lds, dst, ddt, ldd, rows, cols, trans ? 1 : 0};
+  RSVD_TRY(launch_copy2d(p, c.st));
+  return RSVD_OK;
+}
+
+// out (rows x l, ldo) = gY for Y = Qj R (rows x l): gY = (gQ + Q sym(-gQ^T Q)) R^-T.
+rsvd_status qr_adjoint(const Ctx& c, const BwdLayout& L, const void* Qj, const double* Rj, const void* gQ,
+                       int64_t rows, void* out, int64_t ldo) {
+  const Plan& P = c.P;
+  const int64_t l = P.l;
+  const int dt = P.dtype;
+  rsvd_status s = gemm(c, RSVD_NATIVE, true, Qj, l, l, rows, gQ, l, (int32_t)l, c.at<void>(L.Mq), l,
+                       no_split(rows), nullptr, nullptr);  // M = Qj^T gQ
+  if (s != RSVD_OK) return s;
+  RSVD_TRY(launch_qr_adj_sym(c.at<void>(L.Mq), dt, (int32_t)l, c.at<double>(L.Sy), c.st));
+  RSVD_TRY(launch_tri_inv_upper(Rj, c.at<double>(L.Rinv), (int32_t)l, c.st));
+  s = copy2d(c, c.at<double>(L.Rinv), RSVD_F64, l, c.at<double>(L.W64), RSVD_F64, l, l, l, true);  // R^-T
+  if (s != RSVD_OK) return s;
+  const Plan p64 = [&] {
+    Plan q = P;
+    q.dtype = RSVD_F64;
+    q.esize = 8;
+    return q;
+  }();
+  const Ctx c64{p64, c.ws, c.st, c.status, c.h, c.run};
+  s = gemm(c64, RSVD_NATIVE, false, c.at<double>(L.Sy), l, l, l, c.at<double>(L.W64), l, (int32_t)l,
+           c.at<double>(L.SW64), l, no_split(l), nullptr, nullptr);  // S R^-T
+  if (s == RSVD_OK) s = copy2d(c, c.at<double>(L.W64), RSVD_F64, l, c.at<void>(L.W), dt, l, l, l, false);
+  if (s == RSVD_OK) s = copy2d(c, c.at<double>(L.SW64), RSVD_F64, l, c.at<void>(L.SW), dt, l, l, l, false);
+  if (s != RSVD_OK) return s;
+  s = gemm(c, RSVD_NATIVE, false, gQ, l, rows, l, c.at<void>(L.W), l, (int32_t)l, out, ldo, no_split(l), nullptr,
+           nullptr);
+  if (s != RSVD_OK) return s;
+  return gemm(c, RSVD_NATIVE, false, Qj, l, rows, l, c.at<void>(L.SW), l, (int32_t)l, out, ldo, no_split(l), nullptr,
+              nullptr, false, true);
+}
+
+// Y = op(A) X with the split-K partials summed into `out` (rows x l).
+rsvd_status stream_apply(const Ctx& c, const rsvd_problem* pr, bool trans, const void* A, const void* X, int64_t ldx,
+                         void* out) {
+  const Plan& P = c.P;
+  const Split& sp = trans ? P.tn : P.nn;
+  const int64_t rows = trans ? P.n : P.m;
+  const int64_t K = trans ? P.m : P.n;
+  rsvd_status s = gemm(c, pr->prec, trans, A, pr->lda, rows, K, X, ldx, (int32_t)P.l, out, P.l, sp,
+                       sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
+  if (s != RSVD_OK || sp.S == 1) return s;
+  return reduce_parts(c, sp, rows, out);
+}
+
+rsvd_status backward_steps(const Ctx& c, const BwdLayout& L, const rsvd_problem* pr, const void* A, const void* gU,
+                           const void* gS, const void* gV, void* gA) {
+  const Plan& P = c.P;
+  const int64_t m = P.m, n = P.n, l = P.l, k = P.k, Kc = L.Kc;
+  const int dt = P.dtype;
+  const size_t es = (size_t)P.esize;
+  auto Qb = [&](int j) { return c.at<char>(L.Qs) + (size_t)j * (size_t)(m * l) * es; };
+  auto Qtb = [&](int j) { return c.at<char>(L.Qts) + (size_t)(j - 1) * (size_t)(n * l) * es; };
+  auto Rb = [&](int j) { return c.at<double>(L.Rs) + (size_t)j * (size_t)(l * l); };
+  auto Rtb = [&](int j) { return c.at<double>(L.Rts) + (size_t)(j - 1) * (size_t)(l * l); };
+  char* left = c.at<char>(L.Left);
+  char* rightT = c.at<char>(L.RightT);
+  void* y = c.at<void>(P.Y);
+  void* Bt = c.at<void>(L.Bt);
+
+  // --- forward, keeping every basis and its triangular factor
+  rsvd_status s = sketch(c, pr, A, y);
+  if (s == RSVD_OK) s = orth(c, P.nn.S > 1, P.nn, y, m, Qb(0), Rb(0));
+  for (int j = 1; j <= L.q && s == RSVD_OK; ++j) {
+    s = gemm(c, pr->prec, true, A, pr->lda, n, m, Qb(j - 1), l, (int32_t)l, y, l, P.tn,
+             P.tn.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
+    if (s == RSVD_OK) s = orth(c, P.tn.S > 1, P.tn, y, n, Qtb(j), Rtb(j));
+    if (s == RSVD_OK)
+      s = gemm(c, pr->prec, false, A, pr->lda, m, n, Qtb(j), l, (int32_t)l, y, l, P.nn,
+               P.nn.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
+    if (s == RSVD_OK) s = orth(c, P.nn.S > 1, P.nn, y, m, Qb(j), Rb(j));
+  }
+  if (s == RSVD_OK) s = project_steps(c, pr, A, Qb(L.q), Bt);
+  JacobiParams jp;
+  if (s == RSVD_OK) s = small_svd(c, Bt, c.at<void>(L.Sk), jp);
+  if (s != RSVD_OK) return s;
+
+  // --- SVD of B and B = Q^T A: gBt = Bt M1 + gV M2, gQ = A gBt + gU U~_k^T
+  s = gemm(c, RSVD_NATIVE, true, Bt, l, l, n, gV, k, (int32_t)k, c.at<void>(L.T1), k, no_split(n), nullptr,
+           nullptr);  // T1 = B gV
+  if (s == RSVD_OK)
+    s = gemm(c, RSVD_NATIVE, true, Qb(L.q), l, l, m, gU, k, (int32_t)k, c.at<void>(L.T2), k, no_split(m), nullptr,
+             nullptr);  // T2 = Q^T gU
+  if (s != RSVD_OK) return s;
+  SvdAdjParams sa{};
+  sa.Uh = c.at<double>(P.Uh);
+  sa.sig = c.at<double>(P.sig);
+  sa.T1 = c.at<void>(L.T1);
+  sa.T2 = c.at<void>(L.T2);
+  sa.gS = gS;
+  sa.l = (int32_t)l;
+  sa.k = (int32_t)k;
+  sa.dtype = dt;
+  sa.Z = c.at<double>(L.Z);
+  sa.M2 = c.at<double>(L.M2_64);
+  sa.Ukt = c.at<double>(L.Ukt64);
+  RSVD_TRY(launch_svd_adj_coef(sa, c.st));
+  Plan p64 = P;
+  p64.dtype = RSVD_F64;
+  p64.esize = 8;
+  const Ctx c64{p64, c.ws, c.st, c.status, c.h, c.run};
+  s = copy2d(c, c.at<double>(P.Uh), RSVD_F64, l, c.at<double>(L.UhT), RSVD_F64, l, l, l, true);
+  if (s == RSVD_OK)  // W1 = Z U~^T, M1 = U~ W1
+    s = gemm(c64, RSVD_NATIVE, false, c.at<double>(L.Z), l, l, l, c.at<double>(L.UhT), l, (int32_t)l,
+             c.at<double>(L.W1), l, no_split(l), nullptr, nullptr);
+  if (s == RSVD_OK)
+    s = gemm(c64, RSVD_NATIVE, false, c.at<double>(P.Uh), l, l, l, c.at<double>(L.W1), l, (int32_t)l,
+             c.at<double>(L.M1p64), l, no_split(l), nullptr, nullptr);
+  if (s == RSVD_OK) s = copy2d(c, c.at<double>(L.M1p64), RSVD_F64, l, c.at<void>(L.M1p), dt, l, l, l, false);
+  if (s == RSVD_OK) s = copy2d(c, c.at<double>(L.M2_64), RSVD_F64, l, c.at<void>(L.M2), dt, l, k, l, false);
+  if (s == RSVD_OK) s = copy2d(c, c.at<double>(L.Ukt64), RSVD_F64, l, c.at<void>(L.Ukt), dt, l, k, l, false);
+  if (s == RSVD_OK)
+    s = gemm(c, RSVD_NATIVE, false, Bt, l, n, l, c.at<void>(L.M1p), l, (int32_t)l, c.at<void>(L.gBt), l,
+             no_split(l), nullptr, nullptr);
+  if (s == RSVD_OK)
+    s = gemm(c, RSVD_NATIVE, false, gV, k, n, k, c.at<void>(L.M2), l, (int32_t)l, c.at<void>(L.gBt), l,
+             no_split(k), nullptr, nullptr, false, true);
+  // gA block 0: Q_q gBt^T
+  if (s == RSVD_OK) s = copy2d(c, Qb(L.q), dt, l, left, dt, Kc, m, l, false);
+  if (s == RSVD_OK) s = copy2d(c, c.at<void>(L.gBt), dt, l, rightT, dt, n, n, l, true);
+  if (s == RSVD_OK) s = stream_apply(c, pr, false, A, c.at<void>(L.gBt), l, c.at<void>(L.gQ));
+  if (s == RSVD_OK)
+    s = gemm(c, RSVD_NATIVE, false, gU, k, m, k, c.at<void>(L.Ukt), l, (int32_t)l, c.at<void>(L.gQ), l,
+             no_split(k), nullptr, nullptr, false, true);
+  if (s != RSVD_OK) return s;
+
+  // --- power steps in reverse, then the sketch
+  int64_t blk = 1;
+  for (int j = L.q; j >= 1; --j) {
+    void* gYj = left + (size_t)(blk * l) * es;  // gY_j = qr adjoint at Q_j, stored as block blk of Left
+    s = qr_adjoint(c, L, Qb(j), Rb(j), c.at<void>(L.gQ), m, gYj, Kc);
+    if (s == RSVD_OK) s = copy2d(c, Qtb(j), dt, l, rightT + (size_t)(blk * l * n) * es, dt, n, n, l, true);
+    ++blk;
+    if (s == RSVD_OK) s = stream_apply(c, pr, true, A, gYj, Kc, c.at<void>(L.gQt));  // gQt_j = A^T gY_j
+    if (s == RSVD_OK) s = qr_adjoint(c, L, Qtb(j), Rtb(j), c.at<void>(L.gQt), n, c.at<void>(L.gYt), l);
+    if (s == RSVD_OK)
+      s = copy2d(c, c.at<void>(L.gYt), dt, l, rightT + (size_t)(blk * l * n) * es, dt, n, n, l, true);
+    if (s == RSVD_OK) s = copy2d(c, Qb(j - 1), dt, l, left + (size_t)(blk * l) * es, dt, Kc, m, l, false);
+    ++blk;
+    if (s == RSVD_OK) s = stream_apply(c, pr, false, A, c.at<void>(L.gYt), l, c.at<void>(L.gQ));  // gQ_{j-1}
+    if (s != RSVD_OK) return s;
+  }
+  s = qr_adjoint(c, L, Qb(0), Rb(0), c.at<void>(L.gQ), m, left + (size_t)(blk * l) * es, Kc);  // gY_0
+  if (s == RSVD_OK)
+    s = copy2d(c, c.at<void>(P.omega), dt, l, rightT + (size_t)(blk * l * n) * es, dt, n, n, l, true);
+  if (s != RSVD_OK) return s;
+
+  // --- gA = Left RightT, 128 columns at a time
+  for (int64_t c0 = 0; c0 < n; c0 += 128) {
+    const int32_t nc = (int32_t)std::min<int64_t>(128, n - c0);
+    s = gemm(c, pr->prec, false, left, Kc, m, Kc, rightT + (size_t)c0 * es, n, nc,
+             static_cast<char*>(gA) + (size_t)c0 * es, n, no_split(Kc), nullptr, nullptr);
+    if (s != RSVD_OK) return s;
+  }
+  return RSVD_OK;
 }
 
 struct Prologue {
@@ -873,6 +1110,26 @@ rsvd_status rsvd_svd(rsvd_handle h, const rsvd_problem* pr, const void* Bt, cons
   DirectRunner dr(h, stream);
   const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
   return svd_steps(c, Bt, Q, U, S, V);
+}
+
+size_t rsvd_backward_workspace_bytes(const rsvd_problem* problem) {
+  if (validate(problem) != RSVD_OK || problem->sketch != RSVD_GAUSSIAN) return 0;
+  return bwd_layout(problem).total;
+}
+
+rsvd_status rsvd_backward(rsvd_handle h, const rsvd_problem* pr, const void* A, const void* gU, const void* gS,
+                          const void* gV, void* gA, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!h) return RSVD_E_INVAL;
+  const rsvd_status v = validate(pr);
+  if (v != RSVD_OK) return v;
+  if (pr->sketch != RSVD_GAUSSIAN) return RSVD_E_UNSUPPORTED;
+  if (!A || !gU || !gS || !gV || !gA) return RSVD_E_INVAL;
+  const BwdLayout L = bwd_layout(pr);
+  if (!ws || ws_bytes < L.total || !aligned16(ws)) return RSVD_E_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
+  DirectRunner dr(h, stream);
+  const Ctx c{L.P, static_cast<char*>(ws), stream, h->status, h, &dr};
+  return backward_steps(c, L, pr, A, gU, gS, gV, gA);
 }
 
 size_t rsvd_batched_workspace_bytes(int32_t count, const rsvd_problem* probs) {

@@ -41,6 +41,7 @@ struct GemmParams {
   int64_t kchunk;
   int32_t S;
   int32_t vec;          // 1: A rows (NN) / A columns (TN) allow 16-byte loads
+  int32_t accum;        // 1: out += op(A) X (S == 1 only); 0: out = op(A) X
   const int32_t* gate;  // if non-null and *gate == 0 the kernel does nothing
 };
 
@@ -192,6 +193,34 @@ hipError_t launch_omega_batched(int dtype, const OmegaParams* ps, const BlockMap
 hipError_t launch_fill_batched(const FillParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
 hipError_t launch_trmm_batched(const TrmmParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
 hipError_t launch_copy_batched(const CopyParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Adjoint pieces (l x l algebra in FP64, strided copies).
+struct SvdAdjParams {
+  const double* Uh;   // l x l, U~ of the small SVD (row-major)
+  const double* sig;  // l singular values
+  const void* T1;     // l x k, B gV        (element type)
+  const void* T2;     // l x k, Q^T gU      (element type)
+  const void* gS;     // k                  (element type)
+  int32_t l, k, dtype;
+  double* Z;          // l x l: S^-1 (C - P1 S^-1)
+  double* M2;         // k x l: S_k^-1 U~_k^T
+  double* Ukt;        // k x l: U~_k^T
+};
+struct Copy2dParams {
+  const void* src;
+  int32_t src_dtype;
+  int64_t lds;
+  void* dst;
+  int32_t dst_dtype;
+  int64_t ldd;
+  int64_t rows, cols;  // of the source block
+  int32_t trans;       // 1: dst = src^T
+};
+hipError_t launch_svd_adj_coef(const SvdAdjParams& p, hipStream_t st);
+hipError_t launch_qr_adj_sym(const void* M, int dtype, int32_t l, double* S, hipStream_t st);
+hipError_t launch_tri_inv_upper(const double* R, double* Rinv, int32_t l, hipStream_t st);
+hipError_t launch_copy2d(const Copy2dParams& p, hipStream_t st);
 
 // Small utilities.
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, const int32_t* gate, hipStream_t st);

@@ -1,0 +1,152 @@
+// Pieces of the adjoint (reverse-mode derivative) of the fixed-Omega randomized
+// SVD that are not products with A: the l x l algebra of the SVD and QR
+// adjoints, in FP64, and a strided copy / transpose / type cast.
+//
+// SVD of the small matrix, B = U~ S V~^T (l x n, l <= n, full rank), seen as
+// the tall factorization B^T = V~ S U~^T.  With the incoming adjoints gS (k),
+// gU~ = [Q^T gU, 0] (l x l) and gV~ = [gV, 0] (n x l) (the truncation to k
+// triplets pads them with zeros), the adjoint of B^T is
+//   gB^T = V~ [ (F o (V~^T gV~ - gV~^T V~)) S + diag(gS) + S (F o (U~^T gU~ - gU~^T U~)) ] U~^T
+//          + (I - V~ V~^T) gV~ S^-1 U~^T,
+// F_ij = 1 / (s_j^2 - s_i^2) (i != j), F_ii = 0 -- the standard thin-SVD
+// derivative.  With V~ = B^T U~ S^-1 this becomes
+//   gB^T = B^T M1 + gV M2,  M1 = U~ S^-1 (C - P1 S^-1) U~^T,  M2 = S_k^-1 U~_k^T,
+// where C is the bracket and P1 = V~^T gV~ = S^-1 U~^T (B gV).
+// svd_adj_coef_kernel forms Z = S^-1 (C - P1 S^-1) entry by entry; two FP64
+// products give M1 = U~ Z U~^T.
+//
+// QR, Y = Q R with R upper triangular, positive diagonal, and only Q used
+// downstream: gY = (gQ + Q sym(-gQ^T Q)) R^-T, where sym(X) copies the lower
+// triangle of X (diagonal included) onto the upper one.
+#include "common.hpp"
+
+namespace rsvd {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ double ld_as_f64(const void* p, int64_t i) {
+  return (double)static_cast<const T*>(p)[i];
+}
+
+__device__ __forceinline__ double ld_elem(const void* p, int dtype, int64_t i) {
+  return dtype == RSVD_F64 ? ld_as_f64<double>(p, i) : ld_as_f64<float>(p, i);
+}
+
+__global__ __launch_bounds__(256) void svd_adj_coef_kernel(const SvdAdjParams p) {
+  const int l = p.l, k = p.k;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)l * l) return;
+  const int i = (int)(e / l), j = (int)(e - (int64_t)i * l);
+  const double si = p.sig[i], sj = p.sig[j];
+  // P1_ab = (1/s_a) sum_r U~_ra T1_rb  (b < k), P2_ab = sum_r U~_ra T2_rb  (b < k)
+  double d1ij = 0.0, d1ji = 0.0, d2ij = 0.0, d2ji = 0.0;
+  for (int r = 0; r < l; ++r) {
+    const double uri = p.Uh[(int64_t)r * l + i], urj = p.Uh[(int64_t)r * l + j];
+    if (j < k) {
+      d1ij += uri * ld_elem(p.T1, p.dtype, (int64_t)r * k + j);
+      d2ij += uri * ld_elem(p.T2, p.dtype, (int64_t)r * k + j);
+    }
+    if (i < k) {
+      d1ji += urj * ld_elem(p.T1, p.dtype, (int64_t)r * k + i);
+      d2ji += urj * ld_elem(p.T2, p.dtype, (int64_t)r * k + i);
+    }
+  }
+  const double p1ij = d1ij / si, p1ji = d1ji / sj;
+  const double F = i != j ? 1.0 / (sj * sj - si * si) : 0.0;
+  double c = F * (p1ij - p1ji) * sj + si * F * (d2ij - d2ji);
+  if (i == j && i < k) c += ld_elem(p.gS, p.dtype, i);
+  p.Z[e] = (c - p1ij / sj) / si;
+  if (i < k) {
+    // row i of U~_k^T and of S_k^-1 U~_k^T (column j)
+    const double u = p.Uh[(int64_t)j * l + i];
+    p.Ukt[(int64_t)i * l + j] = u;
+    p.M2[(int64_t)i * l + j] = u / si;
+  }
+}
+
+// S_ij = -M_{min(i,j), max(i,j)}: sym(-M^T) for M = Q^T gQ.
+__global__ __launch_bounds__(256) void qr_adj_sym_kernel(const void* M, int dtype, int32_t l, double* S) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)l * l) return;
+  const int i = (int)(e / l), j = (int)(e - (int64_t)i * l);
+  const int a = min(i, j), b = max(i, j);
+  S[e] = -ld_elem(M, dtype, (int64_t)a * l + b);
+}
+
+// Rinv = R^-1 for upper triangular R (l x l): thread j solves R x = e_j by
+// back substitution (x_i = 0 below the diagonal).
+__global__ __launch_bounds__(128) void tri_inv_upper_kernel(const double* __restrict__ R, double* __restrict__ Rinv,
+                                                            int32_t l) {
+  const int j = threadIdx.x;
+  if (j >= l) return;
+  for (int i = l - 1; i > j; --i) Rinv[(int64_t)i * l + j] = 0.0;
+  for (int i = j; i >= 0; --i) {
+    double acc = i == j ? 1.0 : 0.0;
+    for (int t = i + 1; t <= j; ++t) acc -= R[(int64_t)i * l + t] * Rinv[(int64_t)t * l + j];
+    Rinv[(int64_t)i * l + j] = acc / R[(int64_t)i * l + i];
+  }
+}
+
+// dst (rows x cols, or cols x rows when transposed) <- src (rows x cols),
+// with a cast between FP32 and FP64.  32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void copy2d_kernel(const Copy2dParams p) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int rr = ty; rr < 32; rr += 8) {
+    const int64_t r = r0 + rr, c = c0 + tx;
+    if (r < p.rows && c < p.cols) tile[rr][tx] = ld_elem(p.src, p.src_dtype, r * p.lds + c);
+  }
+  __syncthreads();
+  for (int rr = ty; rr < 32; rr += 8) {
+    int64_t dr, dc;
+    double v;
+    if (p.trans) {  // dst[c][r] = src[r][c]: walk dst rows = source columns
+      dc = r0 + tx;
+      dr = c0 + rr;
+      if (dc >= p.rows || dr >= p.cols) continue;
+      v = tile[tx][rr];
+    } else {
+      dr = r0 + rr;
+      dc = c0 + tx;
+      if (dr >= p.rows || dc >= p.cols) continue;
+      v = tile[rr][tx];
+    }
+    const int64_t o = dr * p.ldd + dc;
+    if (p.dst_dtype == RSVD_F64)
+      static_cast<double*>(p.dst)[o] = v;
+    else
+      static_cast<float*>(p.dst)[o] = (float)v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_svd_adj_coef(const SvdAdjParams& p, hipStream_t st) {
+  if (p.l < 1 || p.l > RSVD_MAX_L || p.k < 1 || p.k > p.l) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)p.l * p.l;
+  hipLaunchKernelGGL(svd_adj_coef_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_adj_sym(const void* M, int dtype, int32_t l, double* S, hipStream_t st) {
+  const int64_t n = (int64_t)l * l;
+  hipLaunchKernelGGL(qr_adj_sym_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, dtype, l, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_inv_upper(const double* R, double* Rinv, int32_t l, hipStream_t st) {
+  if (l < 1 || l > 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tri_inv_upper_kernel, dim3(1), dim3(128), 0, st, R, Rinv, l);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy2d(const Copy2dParams& p, hipStream_t st) {
+  if (p.rows <= 0 || p.cols <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((p.cols + 31) / 32), (unsigned)((p.rows + 31) / 32));
+  hipLaunchKernelGGL(copy2d_kernel, grid, dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

@@ -191,7 +191,10 @@ __device__ __forceinline__ void gemm_f32_body(const GemmParams& p, const int bid
       const int col = t * 32 + r;
       if (row < p.rows) {
         if (S == 1) {
-          if (col < p.ncols) out[row * p.ldo + col] = acc[t][e];
+          if (col < p.ncols) {
+            const int64_t o = row * p.ldo + col;
+            out[o] = p.accum ? out[o] + acc[t][e] : acc[t][e];
+          }
         } else {
           part[((int64_t)s * p.rows + row) * p.Lp + col] = acc[t][e];
         }
@@ -288,7 +291,10 @@ __device__ __forceinline__ void gemm_f64_body(const GemmParams& p, const int bid
       const int col = t * 16 + r;
       if (row < p.rows) {
         if (S == 1) {
-          if (col < p.ncols) out[row * p.ldo + col] = acc[t][e];
+          if (col < p.ncols) {
+            const int64_t o = row * p.ldo + col;
+            out[o] = p.accum ? out[o] + acc[t][e] : acc[t][e];
+          }
         } else {
           part[((int64_t)s * p.rows + row) * p.Lp + col] = acc[t][e];
         }
@@ -416,7 +422,10 @@ __device__ __forceinline__ void gemm_bf16_body(const GemmParams& p, const int bi
       const int col = t * 32 + r;
       if (row < p.rows) {
         if (S == 1) {
-          if (col < p.ncols) out[row * p.ldo + col] = acc[t][e];
+          if (col < p.ncols) {
+            const int64_t o = row * p.ldo + col;
+            out[o] = p.accum ? out[o] + acc[t][e] : acc[t][e];
+          }
         } else {
           part[((int64_t)s * p.rows + row) * p.Lp + col] = acc[t][e];
         }
@@ -451,7 +460,8 @@ namespace {
 
 bool gemm_params_ok(int dtype, int prec, const GemmParams& p) {
   const GemmTile tile = gemm_tile(dtype, prec);
-  return p.ncols <= 128 && p.Lp <= 128 && p.Lp % tile.lp_mult == 0 && p.Lp >= p.ncols && p.S >= 1;
+  return p.ncols <= 128 && p.Lp <= 128 && p.Lp % tile.lp_mult == 0 && p.Lp >= p.ncols && p.S >= 1 &&
+         !(p.accum && p.S > 1);
 }
 
 }  // namespace
