@@ -35,6 +35,11 @@ TRAFFIC_KERNEL_SHA = "cfad0aaff99d953a"
 TRAFFIC_SHAPE = (16384, 8192, 120)
 TRAFFIC_BYTES = {"stream_tn_bf16x3": 579446816, "stream_nn_bf16x3": 579920840,
                  "stream_tn_native": 579500971, "stream_nn_native": 579853986}
+# The same for the SRFT row-FFT kernel at 32768 x 16384, l = 128
+# (profiles/srft_sketch_32768x16384_hbm_counters.md).
+SRFT_TRAFFIC_SHA = "2b16782d46e9052b"
+SRFT_TRAFFIC_SHAPE = (32768, 16384, 128)
+SRFT_TRAFFIC_BYTES = 2165559296
 PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
 MI355X_CUS = 256
 
@@ -185,12 +190,16 @@ def run_srft_workload(A, k, p, prec, steps, warmup, seed):
 
 
 def srft_roofline(res, m, n, l):
+    import hashlib
     launches, total_ms = res["prof"]["srft"]
     avg_s = total_ms / launches / 1e3
     bytes_launch = 4.0 * m * n + 4.0 * m * l + 8.0 * n + 4.0 * l
     achieved = bytes_launch / avg_s / 1e9
+    src = os.path.join(ROOT, "paper_0909_4061_amd", "csrc", "k_srft.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    traffic = SRFT_TRAFFIC_BYTES if (sha == SRFT_TRAFFIC_SHA and (m, n, l) == SRFT_TRAFFIC_SHAPE) else None
     return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "srft_rows_f32",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": "srft_rows_f32",
             "launches": launches, "avg_us": avg_s * 1e6, "per_launch": {"bytes": bytes_launch}}
 
 
@@ -302,6 +311,73 @@ def main_batched(args):
     print(json.dumps(line))
 
 
+def main_differentiable(args):
+    """32 FP32 4096 x 2048 matrices, sigma_j = j^-1/2, k = 64, p = 16, q = 1: forward, the loss
+    ||U S V^T - T||_F^2 + w . S and its gradient in A through the hand-written adjoint."""
+    import numpy as np
+    import torch
+    import paper_0909_4061_amd as rs
+    from workloads import CONFIGS, build_matrix_torch, spectrum
+
+    cfg = CONFIGS["c5"]
+    m, n, k, p, q, count = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q, args.batch_diff
+    l = k + p
+    dev = torch.device("cuda", 0)
+    sig = spectrum(cfg.spectrum, min(m, n))
+    t = time.perf_counter()
+    As, Ts, ws_ = [], [], []
+    for i in range(count):
+        As.append(build_matrix_torch(m, n, sig, seed=args.seed + i, dtype=torch.float32, device=dev))
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(args.seed + 1000 + i)
+        Ts.append(torch.randn(m, n, generator=gen, device=dev, dtype=torch.float32))
+        ws_.append(torch.rand(k, generator=gen, device=dev, dtype=torch.float32))
+    torch.cuda.synchronize()
+    print(f"# built {count} matrices on the GPU in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    prec = args.only or "bf16x3"
+
+    def step():
+        grads = []
+        for i in range(count):
+            A = As[i].detach().requires_grad_(True)
+            U, S, V = rs.rsvd(A, k, p, q, seed=args.seed, stream_id=i, prec=prec)
+            L = ((U * S[None, :]) @ V.T - Ts[i]).square().sum() + (ws_[i] * S).sum()
+            L.backward()
+            grads.append(A.grad)
+        return grads
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(args.steps):
+        grads = step()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    fwd = algorithmic_flops(m, n, l, k, q)
+    # adjoint: forward recomputed, (2q + 1) products with A in reverse, gA = Left RightT with K = (2q + 2) l
+    bwd = fwd + (2 * q + 1) * 2.0 * m * n * l + 2.0 * m * n * (2 * q + 2) * l
+    flops = count * (fwd + bwd)
+    # loss-side products in torch (U S V^T - T and its derivatives) are not counted
+    hbm = count * (algorithmic_bytes(m, n, l, q) * 2 + (2 * q + 1) * m * n * 4 + m * n * 4)
+    gnorm = float(torch.stack([g.norm() for g in grads]).mean())
+    line = {
+        "metric": "rSVD TFLOP/s + HBM GB/s at stated ||A-USV*||/sigma_{k+1}; BF16-MFMA vs FP32",
+        "value": flops / (ms / 1e3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16" if prec == "bf16x3" else "f32", "prec": prec, "data": "synthetic",
+        "config": {"workload": f"differentiable rSVD, {count} x FP32 {m}x{n}, sigma_j=j^-1/2, k={k}, p={p}, q={q}, "
+                               "forward + loss + hand-written adjoint per matrix",
+                   "count": count, "m": m, "n": n, "k": k, "p": p, "q": q},
+        "hbm_gbs": hbm / (ms / 1e3) / 1e9, "ms_per_matrix": ms / count, "mean_grad_norm": gnorm,
+    }
+    print(json.dumps(line))
+
+
 def measured_traffic(family, prec, m, n, l):
     """Counter-measured HBM bytes per launch, or None if the kernel source or shape differs."""
     import hashlib
@@ -388,10 +464,12 @@ def main():
                     help="construct: A = U diag(1/j) V^T (the workload); randn: i.i.d. Gaussian A of the "
                          "same shape, for hardware-counter runs only (byte counts do not depend on values)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched workload")
-    ap.add_argument("--workload", choices=["power", "srft", "batched"], default="power",
+    ap.add_argument("--batch-diff", type=int, default=32, help="matrices in the differentiable workload")
+    ap.add_argument("--workload", choices=["power", "srft", "batched", "differentiable"], default="power",
                     help="power: the power-iteration rSVD (default); srft: SRFT vs Gaussian sketch, "
                          "FP32 32768 x 16384 with a spectral gap, k = 50, p = 78, q = 0; batched: 512 "
-                         "uneven FP32 matrices, p = 8, q = 1")
+                         "uneven FP32 matrices, p = 8, q = 1; differentiable: 32 FP32 4096 x 2048 "
+                         "matrices, forward + loss + adjoint")
     ap.add_argument("--srft-prec", choices=["bf16x3", "native"], default="bf16x3",
                     help="arithmetic of the GEMMs that stream A in the srft workload")
     ap.add_argument("--calib-copy", action="store_true",
@@ -410,6 +488,9 @@ def main():
 
     if args.workload == "batched":
         main_batched(args)
+        return
+    if args.workload == "differentiable":
+        main_differentiable(args)
         return
     if args.workload == "srft":
         args.m, args.n, args.k, args.p, args.q = 32768, 16384, 50, 78, 0
