@@ -248,7 +248,8 @@ class RecordRunner final : public Runner {
     return add(SK_GRAM_REDUCE, 0, 0, false, p, gram_reduce_blocks(p));
   }
   hipError_t chol(const CholParams& p) override { return add(SK_CHOL, 0, 0, false, p, 1); }
-  hipError_t jacobi(const JacobiParams& p) override { return add(SK_JACOBI, 0, 0, false, p, 1); }
+  hipError_t jacobi(const JacobiParams& p) override { return add(SK_JACOBI, 0, jacobi_maxl_, false, p, 1); }
+  int jacobi_maxl_ = 128;  // the Jacobi variant every problem of the batch runs
   hipError_t omega(int dtype, const OmegaParams& p) override {
     return add(SK_OMEGA, dtype, 0, false, p, omega_blocks(p));
   }
@@ -875,7 +876,7 @@ hipError_t launch_slots(const std::vector<Slot>& slots, const std::vector<size_t
         e = launch_chol_batched((const CholParams*)ps, bm, nblk[s], st);
         break;
       case SK_JACOBI:
-        e = launch_jacobi_batched((const JacobiParams*)ps, bm, nblk[s], st);
+        e = launch_jacobi_batched(sl.prec, (const JacobiParams*)ps, bm, nblk[s], st);
         break;
       case SK_OMEGA:
         e = launch_omega_batched(sl.dtype, (const OmegaParams*)ps, bm, nblk[s], st);
@@ -900,8 +901,11 @@ rsvd_status build_plan(rsvd_handle h, int32_t count, const rsvd_problem* probs, 
                        void* const* U, void* const* S, void* const* V, void* ws, const BatchLayout& L,
                        BatchPlan*& out) {
   std::vector<Slot> slots;
+  int32_t lmax = 1;
+  for (int32_t i = 0; i < count; ++i) lmax = std::max<int32_t>(lmax, probs[i].k + probs[i].p);
   for (int32_t i = 0; i < count; ++i) {
     RecordRunner rr(slots);
+    rr.jacobi_maxl_ = jacobi_variant(lmax);
     const Plan& P = L.plans[(size_t)i];
     char* base = static_cast<char*>(ws);
     const Ctx c{P, base + L.base[(size_t)i], nullptr, h->status, nullptr, &rr};

@@ -187,7 +187,10 @@ hipError_t launch_gram_partial_batched(int dtype, const GramParams* ps, const Bl
 hipError_t launch_gram_reduce_batched(const GramReduceParams* ps, const BlockMap* bm, int64_t nblocks,
                                       hipStream_t st);
 hipError_t launch_chol_batched(const CholParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
-hipError_t launch_jacobi_batched(const JacobiParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
+// Jacobi variants: the largest l a kernel instance holds (64 or 128).
+int jacobi_variant(int32_t l);
+hipError_t launch_jacobi_batched(int variant, const JacobiParams* ps, const BlockMap* bm, int64_t nblocks,
+                                 hipStream_t st);
 hipError_t launch_omega_batched(int dtype, const OmegaParams* ps, const BlockMap* bm, int64_t nblocks,
                                 hipStream_t st);
 hipError_t launch_fill_batched(const FillParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);

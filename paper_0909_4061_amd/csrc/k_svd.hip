@@ -8,12 +8,15 @@
 // needed: the right singular vectors follow as V = B* U~ S^-1, computed by the
 // lift GEMM (B* is the stored Bt).
 //
-// One workgroup of 512 threads holds C column-major in LDS.  Each round of a
-// sweep rotates l/2 disjoint column pairs chosen by the round-robin (circle)
-// ordering, one pair per 8-lane group; a sweep is l - 1 rounds (l rounded up
-// to even, with a zero column when l is odd), so every pair meets once.  A
-// pair is rotated when |c_i . c_j| > tol sqrt(|c_i|^2 |c_j|^2); the workgroup
-// stops after a sweep with no rotation.
+// One workgroup holds C column-major in LDS.  Each round of a sweep rotates
+// l/2 disjoint column pairs chosen by the round-robin (circle) ordering, one
+// pair per 4-lane group; a sweep is l - 1 rounds (l rounded up to even, with a
+// zero column when l is odd), so every pair meets once.  A pair is rotated
+// when |c_i . c_j| > tol sqrt(|c_i|^2 |c_j|^2); the workgroup stops after a
+// sweep with no rotation.  The round's fixed cost (three reductions, the
+// rotation angle) is paid once per wave, so fewer lanes per pair (more rows
+// per lane) make a round cheaper; the kernel is compiled for l <= 64 and
+// l <= 128 so that small matrices keep their LDS footprint small.
 #include <float.h>
 
 #include "common.hpp"
@@ -22,8 +25,6 @@ namespace rsvd {
 
 namespace {
 
-constexpr int JAC_MAXL = 128;
-constexpr int JAC_LDC = JAC_MAXL + 2;  // even: 16-byte aligned column starts
 constexpr int JAC_MAX_SWEEPS = 40;
 
 // Move a double across lanes of a 16-lane DPP row.
@@ -34,22 +35,50 @@ __device__ inline double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum over an aligned group of 8 lanes.  Mirror within the half-row, then
-// swaps within quads: every lane adds the same operands in the same pairs, so
-// all 8 lanes hold bitwise-identical sums (and take identical rotation
-// decisions).
-__device__ inline double group8_sum(double v) {
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+// Sum over an aligned group of 4 lanes: two swaps within the quad.  Every lane
+// adds the same operands in the same pairs, so all 4 lanes hold bitwise-
+// identical sums (and take identical rotation decisions).
+__device__ inline double group4_sum(double v) {
+  v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]
+  v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
   return v;
 }
 
+// 1/x and 1/sqrt(x) from the hardware estimates and two Newton steps each
+// (quadratic convergence from the estimates' ~2^-22 relative error to the
+// FP64 rounding level).  The rotation below needs c^2 + s^2 = 1 to rounding,
+// not correctly rounded quotients, and these short chains are a fraction of
+// the latency of IEEE division and square root.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * y, y, 1.0);  // 1 - x y^2
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// One workgroup of 2 MAXL threads per matrix (l <= MAXL): MAXL / 2 column
+// pairs per round, four lanes per pair, each lane holding MAXL / 4 rows of
+// both columns in registers.
+template <int MAXL>
 __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid) {
   (void)bid;  // one workgroup per matrix
-  __shared__ __attribute__((aligned(16))) double Cs[JAC_MAXL * JAC_LDC];  // column c at Cs[c * JAC_LDC + row]
-  __shared__ double sig_s[JAC_MAXL];
-  __shared__ int rank_s[JAC_MAXL];
+  constexpr int LDC = MAXL + 2;  // even: 16-byte aligned column starts
+  constexpr int THREADS = 2 * MAXL;
+  constexpr int RPL = MAXL / 4;  // rows per lane
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ __attribute__((aligned(16))) double Cs[MAXL * LDC];  // column c at Cs[c * LDC + row]
+  __shared__ double sig_s[MAXL];
+  __shared__ int rank_s[MAXL];
   __shared__ int rotated;
   const int tid = threadIdx.x;
   const int l = p.l;
@@ -57,15 +86,24 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
   const int P = le / 2;
 
   // column c of C = R^T is row c of R
-  for (int idx = tid; idx < le * JAC_LDC; idx += 512) {
-    const int c = idx / JAC_LDC, i = idx - c * JAC_LDC;
+  for (int idx = tid; idx < le * LDC; idx += THREADS) {
+    const int c = idx / LDC, i = idx - c * LDC;
     Cs[idx] = (c < l && i < l) ? p.R[(int64_t)c * l + i] : 0.0;
   }
   if (tid == 0) rotated = 1;
   __syncthreads();
 
-  const int grp = tid >> 3, gl = tid & 7;
-  const double tol = (double)l * DBL_EPSILON;
+  const int grp = tid >> 2, gl = tid & 3;
+  // Stopping threshold on |c_i . c_j| / (|c_i| |c_j|): the unit roundoff of
+  // the output type (FP32 outputs cannot show a smaller loss of
+  // orthogonality), l eps for FP64 outputs.
+  const double tol = p.dtype == RSVD_F64 ? (double)l * DBL_EPSILON : (double)FLT_EPSILON;
+  // Round-robin (circle) ordering: position 0 holds column 0; position x > 0
+  // holds column 1 + (x - 1 + rnd) mod (le - 1).  This group owns positions
+  // grp and le - 1 - grp; the offsets advance by one per round and return to
+  // their start after a sweep of le - 1 rounds.
+  const int ia0 = grp > 0 ? grp - 1 : 0;
+  const int ib0 = le - 2 - grp;
   int sweep = 0;
   for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
     if (rotated == 0) break;  // read after the barrier that ended the last sweep
@@ -73,52 +111,58 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
     if (tid == 0) rotated = 0;
     __syncthreads();
     int any = 0;
+    int ia = ia0, ib = ib0;
     for (int rnd = 0; rnd < le - 1; ++rnd) {
       if (grp < P) {
-        // positions grp and le-1-grp; column at position x is 0 for x == 0,
-        // else 1 + (x - 1 + rnd) mod (le - 1)
-        const int xa = grp, xb = le - 1 - grp;
-        const int ca = xa == 0 ? 0 : 1 + (xa - 1 + rnd) % (le - 1);
-        const int cb = 1 + (xb - 1 + rnd) % (le - 1);
-        double* col_a = Cs + ca * JAC_LDC;
-        double* col_b = Cs + cb * JAC_LDC;
-        // rows 16 r + 2 gl and 16 r + 2 gl + 1 of each column (rows past l are zeros)
-        typedef double d2 __attribute__((ext_vector_type(2)));
-        double x[JAC_MAXL / 8], y[JAC_MAXL / 8];
+        const int ca = grp == 0 ? 0 : 1 + ia;
+        const int cb = 1 + ib;
+        double* col_a = Cs + ca * LDC;
+        double* col_b = Cs + cb * LDC;
+        // rows 8 r + 2 gl and 8 r + 2 gl + 1 of each column (rows past l are zeros)
+        double x[RPL], y[RPL];
 #pragma unroll
-        for (int r = 0; r < JAC_MAXL / 16; ++r) {
-          const d2 xa = *reinterpret_cast<const d2*>(col_a + 16 * r + 2 * gl);
-          const d2 yb = *reinterpret_cast<const d2*>(col_b + 16 * r + 2 * gl);
+        for (int r = 0; r < RPL / 2; ++r) {
+          const d2 xa = *reinterpret_cast<const d2*>(col_a + 8 * r + 2 * gl);
+          const d2 yb = *reinterpret_cast<const d2*>(col_b + 8 * r + 2 * gl);
           x[2 * r] = xa[0];
           x[2 * r + 1] = xa[1];
           y[2 * r] = yb[0];
           y[2 * r + 1] = yb[1];
         }
-        double al = 0.0, be = 0.0, ga = 0.0;
+        // four partial sums per product keep the dependent chains short
+        double al4[4] = {0.0, 0.0, 0.0, 0.0}, be4[4] = {0.0, 0.0, 0.0, 0.0}, ga4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int r = 0; r < JAC_MAXL / 8; ++r) {
-          al += x[r] * x[r];
-          be += y[r] * y[r];
-          ga += x[r] * y[r];
+        for (int r = 0; r < RPL; ++r) {
+          al4[r & 3] += x[r] * x[r];
+          be4[r & 3] += y[r] * y[r];
+          ga4[r & 3] += x[r] * y[r];
         }
-        al = group8_sum(al);
-        be = group8_sum(be);
-        ga = group8_sum(ga);
-        if (ca < l && cb < l && fabs(ga) > tol * sqrt(al * be) && al > 0.0 && be > 0.0) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t);
+        double al = (al4[0] + al4[1]) + (al4[2] + al4[3]);
+        double be = (be4[0] + be4[1]) + (be4[2] + be4[3]);
+        double ga = (ga4[0] + ga4[1]) + (ga4[2] + ga4[3]);
+        al = group4_sum(al);
+        be = group4_sum(be);
+        ga = group4_sum(ga);
+        // rotate when |ga| > tol sqrt(al be), tested as ga^2 > tol^2 al be
+        if (ca < l && cb < l && ga * ga > tol * tol * al * be && al > 0.0 && be > 0.0) {
+          const double zeta = (be - al) * rcp_nr(2.0 * ga);
+          const double q = fma(zeta, zeta, 1.0);
+          const double root = q * rsq_nr(q);  // sqrt(1 + zeta^2)
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + root);
+          const double cs = rsq_nr(fma(t, t, 1.0));
           const double sn = cs * t;
 #pragma unroll
-          for (int r = 0; r < JAC_MAXL / 16; ++r) {
-            *reinterpret_cast<d2*>(col_a + 16 * r + 2 * gl) =
+          for (int r = 0; r < RPL / 2; ++r) {
+            *reinterpret_cast<d2*>(col_a + 8 * r + 2 * gl) =
                 d2{cs * x[2 * r] - sn * y[2 * r], cs * x[2 * r + 1] - sn * y[2 * r + 1]};
-            *reinterpret_cast<d2*>(col_b + 16 * r + 2 * gl) =
+            *reinterpret_cast<d2*>(col_b + 8 * r + 2 * gl) =
                 d2{sn * x[2 * r] + cs * y[2 * r], sn * x[2 * r + 1] + cs * y[2 * r + 1]};
           }
           any = 1;
         }
       }
+      ia = ia + 1 == le - 1 ? 0 : ia + 1;
+      ib = ib + 1 == le - 1 ? 0 : ib + 1;
       __syncthreads();
     }
     if (any) rotated = 1;  // benign race: every writer stores 1
@@ -130,7 +174,7 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
   // singular values = column norms; rank by descending value (ties: lower index first)
   if (tid < l) {
     double s2 = 0.0;
-    for (int i = 0; i < l; ++i) s2 += Cs[tid * JAC_LDC + i] * Cs[tid * JAC_LDC + i];
+    for (int i = 0; i < l; ++i) s2 += Cs[tid * LDC + i] * Cs[tid * LDC + i];
     sig_s[tid] = sqrt(s2);
   }
   __syncthreads();
@@ -144,11 +188,11 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
     rank_s[tid] = rk;
   }
   __syncthreads();
-  for (int idx = tid; idx < l * l; idx += 512) {
+  for (int idx = tid; idx < l * l; idx += THREADS) {
     const int c = idx / l, i = idx - c * l;  // element i of column c
     const int rk = rank_s[c];
     const double sg = sig_s[c];
-    const double u = sg > 0.0 ? Cs[c * JAC_LDC + i] / sg : 0.0;
+    const double u = sg > 0.0 ? Cs[c * LDC + i] / sg : 0.0;
     p.Uh[(int64_t)i * l + rk] = u;
     if (rk < p.k) {
       const double v = sg > 0.0 ? u / sg : 0.0;
@@ -171,24 +215,36 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
   }
 }
 
-__global__ __launch_bounds__(512) void jacobi_kernel(const JacobiParams p) { jacobi_body(p, blockIdx.x); }
+template <int MAXL>
+__global__ __launch_bounds__(2 * MAXL) void jacobi_kernel(const JacobiParams p) { jacobi_body<MAXL>(p, blockIdx.x); }
 
-__global__ __launch_bounds__(512) void jacobi_batched(const JacobiParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+template <int MAXL>
+__global__ __launch_bounds__(2 * MAXL) void jacobi_batched(const JacobiParams* __restrict__ ps,
+                                                           const BlockMap* __restrict__ bm) {
   const BlockMap b = bm[blockIdx.x];
-  jacobi_body(ps[b.item], b.local);
+  jacobi_body<MAXL>(ps[b.item], b.local);
 }
 
 }  // namespace
 
+int jacobi_variant(int32_t l) { return l <= 64 ? 64 : 128; }
+
 hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st) {
-  if (p.l < 1 || p.l > JAC_MAXL || p.k < 1 || p.k > p.l) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(512), 0, st, p);
+  if (p.l < 1 || p.l > 128 || p.k < 1 || p.k > p.l) return hipErrorInvalidValue;
+  if (jacobi_variant(p.l) == 64)
+    hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(128), 0, st, p);
+  else
+    hipLaunchKernelGGL(jacobi_kernel<128>, dim3(1), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_batched(const JacobiParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
+hipError_t launch_jacobi_batched(int variant, const JacobiParams* ps, const BlockMap* bm, int64_t nblocks,
+                                 hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_batched, dim3((unsigned)nblocks), dim3(512), 0, st, ps, bm);
+  if (variant == 64)
+    hipLaunchKernelGGL(jacobi_batched<64>, dim3((unsigned)nblocks), dim3(128), 0, st, ps, bm);
+  else
+    hipLaunchKernelGGL(jacobi_batched<128>, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
   return hipGetLastError();
 }
 
