@@ -278,6 +278,11 @@ enum {
  * pairs run out.  capacity == 0: stop timing and release the events. */
 rsvd_status rsvd_profile_enable(rsvd_handle handle, int32_t capacity);
 
+/* Restrict timing to the families whose bit (1 << family) is set in `mask`
+ * (all families after rsvd_profile_enable): a timed region that brackets only
+ * the launches of interest pays for fewer events. */
+rsvd_status rsvd_profile_select(rsvd_handle handle, uint32_t mask);
+
 /* Wait for the recorded events; for each family f write the number of timed
  * launches to launches[f] and their summed durations (ms) to total_ms[f]
  * (arrays of RSVD_KERNEL_KINDS host elements); then forget the records. */

@@ -356,6 +356,15 @@ def profile_enable(capacity, device=None):
     _lib.check(h.lib.rsvd_profile_enable(h.ptr, int(capacity)), "rsvd_profile_enable")
 
 
+def profile_select(families, device=None):
+    """Time only the named kernel families (see _lib.KERNEL_KINDS) until the next profile_enable."""
+    h = handle(device)
+    mask = 0
+    for f in families:
+        mask |= 1 << _lib.KERNEL_KINDS.index(f)
+    _lib.check(h.lib.rsvd_profile_select(h.ptr, mask), "rsvd_profile_select")
+
+
 def profile_read(device=None):
     """{family: (launches, total_ms)} since the last read; waits for the events."""
     h = handle(device)

@@ -31,7 +31,7 @@ EXPORTS = [
     "rsvd_range_finder", "rsvd_power_iter", "rsvd_project", "rsvd_svd",
     "rsvd_batched_workspace_bytes", "rsvd_batched", "rsvd_backward_workspace_bytes", "rsvd_backward",
     "rsvd_sketch", "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
-    "rsvd_profile_enable", "rsvd_profile_read",
+    "rsvd_profile_enable", "rsvd_profile_select", "rsvd_profile_read",
 ]
 KERNEL_KINDS = ["stream_nn", "stream_tn", "small_gemm", "gram", "chol", "jacobi", "pack", "srft"]
 
@@ -88,6 +88,7 @@ def load():
         "rsvd_orth": ([vp, prob, i64, vp, vp, vp, sz, vp], i32),
         "rsvd_device_status": ([vp, vp, ctypes.POINTER(i32)], i32),
         "rsvd_profile_enable": ([vp, i32], i32),
+        "rsvd_profile_select": ([vp, ctypes.c_uint32], i32),
         "rsvd_profile_read": ([vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], i32),
     }
     for name, (args, res) in sig.items():

@@ -28,6 +28,7 @@ struct rsvd_handle_s {
   std::vector<hipEvent_t> events;  // 2 per record
   std::vector<int> kinds;          // family of each record
   int used = 0;
+  uint32_t mask = ~0u;             // families that are timed
   // batched calls: recorded launch plans (device tables + graph), most recent last
   std::vector<BatchPlan*> plans;
   hipStream_t capture = nullptr;  // stream the batched graphs are captured on
@@ -153,7 +154,7 @@ struct Timed {
   hipStream_t st;
   int idx = -1;
   Timed(rsvd_handle h_, int kind, hipStream_t st_) : h(h_), st(st_) {
-    if (h && h->used < (int)h->kinds.size()) {
+    if (h && h->used < (int)h->kinds.size() && ((h->mask >> kind) & 1u)) {
       idx = h->used++;
       h->kinds[idx] = kind;
       (void)hipEventRecord(h->events[2 * idx], st);
@@ -1006,11 +1007,18 @@ rsvd_status rsvd_profile_enable(rsvd_handle h, int32_t capacity) {
   h->events.clear();
   h->kinds.clear();
   h->used = 0;
+  h->mask = ~0u;
   if (capacity == 0) return RSVD_OK;
   h->events.resize(2 * (size_t)capacity, nullptr);
   h->kinds.resize((size_t)capacity, 0);
   for (auto& e : h->events)
     if (hipEventCreate(&e) != hipSuccess) return RSVD_E_DEVICE;
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_profile_select(rsvd_handle h, uint32_t mask) {
+  if (!h) return RSVD_E_INVAL;
+  h->mask = mask;
   return RSVD_OK;
 }
 

@@ -112,6 +112,9 @@ def test_null_arguments_fail_before_launch(lib):
     assert lib.rsvd_sketch(None, ctypes.byref(pr), None, None, None, 0, None) == 1
     assert lib.rsvd_draw_srft(None, ctypes.byref(pr), None, None, None) == 1
     assert lib.rsvd_device_status(None, None, None) == 1
+    assert lib.rsvd_profile_enable(None, 4) == 1
+    assert lib.rsvd_profile_select(None, 0) == 1
+    assert lib.rsvd_profile_read(None, None, None) == 1
     assert lib.rsvd_create(None, 0) == 1
 
 
