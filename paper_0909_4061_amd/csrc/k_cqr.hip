@@ -11,12 +11,9 @@
 //                  (FP32 entries are exact in FP64, so the products are exact).
 //                  Only the upper 16x16 tiles are computed.
 //   gram_reduce  : sums the block Grams in a fixed order (deterministic).
-//   chol         : one workgroup.  Symmetric elimination of W with the same
-//                  row operations applied to the identity, both l x l arrays
-//                  held in registers (1024 threads, 4x4 entries each), one
-//                  barrier per column: the eliminated W is D L^T and the
-//                  accumulated operations are L^-1, which gives
-//                  R = D^-1/2 (D L^T) and R^-1 = L^-T D^-1/2 at once.
+//   chol         : one workgroup of 512 threads.  Blocked (by 16) Cholesky
+//                  of W in LDS, then the inverse R^-1 blockwise, a few
+//                  barriers per block instead of per column.
 //                  A pivot that is not safely positive restarts the
 //                  factorization on W + sI (shifted CholeskyQR) and raises a
 //                  flag; the host then runs a third pass.
@@ -146,131 +143,185 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const GramReduceParam
   gram_reduce_body(ps[b.item], b.local);
 }
 
-// Cholesky with simultaneous inverse.  Thread (tr, tc) of a 32 x 32 grid owns
-// the entries (a, c), a = tr + 32 ia, c = tc + 32 ib (ia, ib < 4), of two
-// register tiles: U (the eliminated matrix; only c >= a is meaningful) and E
-// (the accumulated row operations, E = L^-1, lower triangular with unit
-// diagonal).  Step j subtracts f_a = U[j][a] / U[j][j] times the pivot row from
-// every row a > j: U[a][c] -= f_a U[j][c] for c > j and E[a][c] -= f_a E[j][c]
-// for c <= j (E[j][j] = 1).  The masks fold into the multipliers, so each
-// element costs two FMAs; waves whose rows are all finished skip the update.
-// At the end U = D L^T, hence R = D^-1/2 U and R^-1 = E^T D^-1/2.
+// Cholesky factor R (W = R^T R, R upper triangular, positive diagonal) and its
+// inverse X = R^-1, blocked by 16 for one workgroup of 512 threads.  W, then
+// R, lives in the upper triangle of an LDS matrix; X^T is built in the strict
+// lower triangle (X is upper triangular) and 1 / R_ii in a vector.
+//
+// Factorization, per block column [k0, k1):
+//   1. one wave factors the panel (rows k0..k1-1) in registers, right-looking:
+//      lanes 0..15 hold the diagonal block's columns, lanes 16..63 three
+//      columns each of the block row (R_kj = R_kk^-T W_kj); the pivots and
+//      the rows of R_kk are broadcast with readlane;
+//   2. the trailing matrix is updated, W_ij -= R_ki^T R_kj for k1 <= i <= j:
+//      one column per lane, eight rows per wave, the rows of R_k read as LDS
+//      broadcasts.
+// Inverse by doubling: every 16 x 16 diagonal block inverted at once (one
+// column per lane), then for s = 16, 32, 64 each aligned pair of inverted
+// blocks [A C] is joined, X_AC = -X_AA (R_AC X_CC), again one column per lane
+// and eight rows per wave.
+// A pivot that is not positive (or not finite) restarts the factorization on
+// W + s I with the shifted-CholeskyQR shift; a second failure (non-finite
+// input) returns identity factors and raises RSVD_FLAG_NONFINITE.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// 1/sqrt(x) from the hardware estimate and two Newton steps (x > 0, finite).
+__device__ __forceinline__ double rsq_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
 __device__ __forceinline__ void chol_body(const CholParams& p, const int bid) {
   (void)bid;  // one workgroup per factorization
-  constexpr int TLD = 129;
-  __shared__ double rowbuf[2][128];
-  __shared__ double diag[128];
-  __shared__ double red[32];
-  __shared__ double tbuf[128 * TLD];
+  constexpr int NT = 512, NW = NT / 64, B = 16, LDC = 129;  // odd stride: column walks hit distinct banks
+  constexpr int RG = 8;                                      // rows per wave in the matrix phases
+  __shared__ double M[128 * LDC];
+  __shared__ double rinv_d[128];  // 1 / R_ii (0 past l)
+  __shared__ int bad_s;
   if (p.gate && *p.gate == 0) return;
-  const int tid = threadIdx.x;
-  const int tr = tid >> 5, tc = tid & 31;
-  const int wave_row_max = (tid >> 6) * 2 + 1;  // largest tr in this wave
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l = p.l, Lg = p.Lg;
-
-  // max diagonal and trace of W (for the breakdown threshold and the shift)
-  double dmax = 0.0, trace = 0.0;
-  {
-    const double dv = (tid < l) ? p.G[(int64_t)tid * Lg + tid] : 0.0;
-    double m = dv, t = dv;
-    for (int off = 16; off > 0; off >>= 1) {
-      m = fmax(m, __shfl_xor(m, off, 32));
-      t += __shfl_xor(t, off, 32);
-    }
-    if (tid < 128 && (tid & 31) == 0) {
-      red[tid >> 5] = m;
-      red[4 + (tid >> 5)] = t;
-    }
-    __syncthreads();
-    for (int i = 0; i < 4; ++i) {
-      dmax = fmax(dmax, red[i]);
-      trace += red[4 + i];
-    }
-  }
+  const int lp = (l + B - 1) & ~(B - 1);  // rows and columns past l up to lp hold zeros
+  const int tc = tid & 127, tr = tid >> 7;  // 4 x 128 thread grid for whole-matrix loops
   const double eps = DBL_EPSILON;
-  const double thresh = (double)l * 16.0 * eps * dmax;
+  double thresh = 0.0, trace = 0.0;
 
-  double U[4][4], E[4][4];
   bool ok = false;
   for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
     // Shifted CholeskyQR: s = 11 (rows l + l (l + 1)) u ||Y||_F^2 with u the FP64 unit roundoff.
     const double shift =
         attempt == 0 ? 0.0 : 11.0 * ((double)p.rows * l + (double)l * (l + 1)) * (0.5 * eps) * trace;
+    for (int a0 = tr; a0 < lp; a0 += 4 * 8) {
+      double v[8];
 #pragma unroll
-    for (int ia = 0; ia < 4; ++ia) {
-      const int a = tr + 32 * ia;
+      for (int u = 0; u < 8; ++u) {
+        const int a = a0 + 4 * u;
+        v[u] = (a < l && tc < l && tc >= a) ? p.G[(int64_t)a * Lg + tc] : 0.0;
+      }
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib) {
-        const int c = tc + 32 * ib;
-        double v = 0.0;
-        if (a < l && c < l && c >= a) v = p.G[(int64_t)a * Lg + c] + (c == a ? shift : 0.0);
-        U[ia][ib] = v;
-        E[ia][ib] = 0.0;
+      for (int u = 0; u < 8; ++u) {
+        const int a = a0 + 4 * u;
+        if (a < lp && tc < lp) M[a * LDC + tc] = v[u] + (a == tc && a < l ? shift : 0.0);
       }
     }
-    if (tr == 0) {
-#pragma unroll
-      for (int ib = 0; ib < 4; ++ib) rowbuf[0][tc + 32 * ib] = U[0][ib];
+    if (tid < 128) rinv_d[tid] = 0.0;
+    __syncthreads();
+    if (attempt == 0) {
+      // max diagonal (breakdown threshold) and trace (shift) of W, every wave for itself
+      const double d0 = lane < l ? p.G[(int64_t)lane * (Lg + 1)] : 0.0;
+      const double d1 = lane + 64 < l ? p.G[(int64_t)(lane + 64) * (Lg + 1)] : 0.0;
+      double mx = fmax(d0, d1), trs = d0 + d1;
+      for (int off = 32; off > 0; off >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+        trs += __shfl_xor(trs, off, 64);
+      }
+      thresh = (double)l * 16.0 * eps * mx;
+      trace = trs;
     }
     ok = true;
-    for (int j = 0; j < l; ++j) {
-      const int buf = j & 1;
-      __syncthreads();
-      const double d = rowbuf[buf][j];
-      double prow[4], pcol[4];
+    for (int k0 = 0; k0 < l; k0 += B) {
+      const int k1 = min(k0 + B, l), bk = k1 - k0;
+      // 1. panel by wave 0.  Past the diagonal block the block is full (bk == B):
+      //    only the last one is partial, and it has no block row.
+      if (wave == 0) {
+        int col[3];
+        bool has[3];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        prow[i] = rowbuf[buf][tr + 32 * i];
-        pcol[i] = rowbuf[buf][tc + 32 * i];
+        for (int m = 0; m < 3; ++m) {
+          col[m] = lane < B ? k0 + lane : k1 + (lane - B) + 48 * m;
+          has[m] = lane < B ? (m == 0 && lane < bk) : col[m] < l;
+        }
+        double x[3][B];
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+          for (int i = 0; i < B; ++i)
+            x[m][i] = (has[m] && (lane >= B || i <= lane)) ? M[(k0 + i) * LDC + col[m]] : 0.0;
+        int bad = 0;
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          if (j < bk && !bad) {  // uniform across the wave
+            const double djj = readlane_f64(x[0][j], j);
+            if (!(djj > thresh) || !isfinite(djj)) {
+              bad = 1;
+            } else {
+              const double rinv = rsq_refined(djj);
+              double rjj = djj * rinv;
+              rjj = fma(0.5 * rinv, fma(-rjj, rjj, djj), rjj);
+#pragma unroll
+              for (int m = 0; m < 3; ++m) x[m][j] *= rinv;  // row j of R (zeros stay zeros)
+              if (lane == j) {
+                x[0][j] = rjj;
+                rinv_d[k0 + j] = rinv;
+              }
+#pragma unroll
+              for (int i = j + 1; i < B; ++i) {
+                const double rji = readlane_f64(x[0][j], i);  // R[j][i]
+#pragma unroll
+                for (int m = 0; m < 3; ++m) x[m][i] = fma(-rji, x[m][j], x[m][i]);
+              }
+            }
+          }
+        }
+        if (!bad) {
+#pragma unroll
+          for (int m = 0; m < 3; ++m)
+            if (has[m])
+#pragma unroll
+              for (int i = 0; i < B; ++i)
+                if (lane >= B || i <= lane) M[(k0 + i) * LDC + col[m]] = x[m][i];
+        }
+        if (lane == 0) bad_s = bad;
       }
-      if (!(d > thresh) || !isfinite(d)) {  // uniform: every thread reads the same d
+      __syncthreads();
+      if (bad_s) {
         ok = false;
         break;
       }
-      if (tid == 0) diag[j] = d;
-      const double invd = 1.0 / d;
-      double pu[4], pe[4];
+      // 2. trailing update: item = (64-column chunk, 8-row group) per wave
+      const int nt = l - k1;
+      if (nt > 0) {
+        const int nrg = (nt + RG - 1) / RG, items = ((nt + 63) / 64) * nrg;
+        for (int it = wave; it < items; it += NW) {
+          const int cc = it / nrg, rg = it - cc * nrg;
+          const int i0 = k1 + RG * rg, cbase = k1 + 64 * cc;
+          if (i0 > cbase + 63) continue;  // below the diagonal (uniform)
+          const int c = cbase + lane, cl = min(c, lp - 1);
+          double acc[RG] = {};
+#pragma unroll 4
+          for (int t = 0; t < B; ++t) {
+            const double* row = M + (k0 + t) * LDC;
+            const double bv = row[cl];
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib) {
-        const int c = tc + 32 * ib;
-        pu[ib] = c > j ? pcol[ib] : 0.0;
-        pe[ib] = c < j ? pcol[ib] : (c == j ? 1.0 : 0.0);
-      }
-#pragma unroll
-      for (int ia = 0; ia < 4; ++ia) {
-        if (wave_row_max + 32 * ia <= j) continue;  // wave-uniform: no live row in this block
-        const int a = tr + 32 * ia;
-        const double f = (a > j && a < l) ? prow[ia] * invd : 0.0;
-#pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-          U[ia][ib] -= f * pu[ib];
-          E[ia][ib] -= f * pe[ib];
-        }
-      }
-      // the owners of row j + 1 publish it: U part right of the diagonal, E part left
-#pragma unroll
-      for (int ia = 0; ia < 4; ++ia) {
-        if (tr + 32 * ia == j + 1) {
-#pragma unroll
-          for (int ib = 0; ib < 4; ++ib) {
-            const int c = tc + 32 * ib;
-            rowbuf[buf ^ 1][c] = c >= j + 1 ? U[ia][ib] : E[ia][ib];
+            for (int i = 0; i < RG; ++i) acc[i] = fma(row[i0 + i], bv, acc[i]);
           }
+          if (c < l)
+#pragma unroll
+            for (int i = 0; i < RG; ++i)
+              if (i0 + i <= c) M[(i0 + i) * LDC + c] -= acc[i];
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
     if (!ok && attempt == 0 && tid == 0) {
       atomicOr(p.status, (int32_t)RSVD_FLAG_SHIFTED);
       if (p.shifted) *p.shifted = 1;
     }
+    __syncthreads();  // every thread has read bad_s before the next attempt rewrites M
   }
   if (!ok) {
     // Shifted factorization failed as well (non-finite input): identity factors.
     if (tid == 0) atomicOr(p.status, (int32_t)RSVD_FLAG_NONFINITE);
-    for (int idx = tid; idx < l * l; idx += 1024) {
-      const int a = idx / l, c = idx - a * l;
-      const double v = a == c ? 1.0 : 0.0;
+    for (int a = tr; a < l; a += 4) {
+      if (tc >= l) break;
+      const int64_t idx = (int64_t)a * l + tc;
+      const double v = a == tc ? 1.0 : 0.0;
       if (p.R) p.R[idx] = v;
       if (p.Rinv) p.Rinv[idx] = v;
       if (p.RinvT) {
@@ -280,36 +331,102 @@ __device__ __forceinline__ void chol_body(const CholParams& p, const int bid) {
     }
     return;
   }
-  // R[a][c] = U[a][c] / sqrt(d_a) for c >= a (coalesced: consecutive threads, consecutive c).
-  // R^-1[c][a] = E[a][c] / sqrt(d_a) for c <= a: transposed through LDS.
+  if (p.R && tc < l)
+    for (int a = tr; a < l; a += 4) p.R[(int64_t)a * l + tc] = tc >= a ? M[a * LDC + tc] : 0.0;
+  if (!p.Rinv && !p.RinvT) return;
+
+  // Inverse.  X[r][c] (r < c) is kept at M[c * LDC + r], X[c][c] in rinv_d.
+  const int nb = lp / B;
+  // diagonal blocks, one wave each: lane c solves R_bb x = e_c, right-looking from the bottom
+  for (int b = wave; b < nb; b += NW) {
+    const int b0 = b * B;
+    double acc[B], x[B];
 #pragma unroll
-  for (int ia = 0; ia < 4; ++ia) {
-    const int a = tr + 32 * ia;
-    if (a >= l) continue;
-    const double rs = 1.0 / sqrt(diag[a]);
+    for (int i = 0; i < B; ++i) acc[i] = 0.0;
 #pragma unroll
-    for (int ib = 0; ib < 4; ++ib) {
-      const int c = tc + 32 * ib;
-      if (c >= l) continue;
-      if (p.R) p.R[(int64_t)a * l + c] = c >= a ? U[ia][ib] * rs : 0.0;
-      tbuf[c * TLD + a] = c == a ? rs : (c < a ? E[ia][ib] * rs : 0.0);
+    for (int t = B - 1; t >= 0; --t) {
+      const double rt = rinv_d[b0 + t];
+      x[t] = t == lane ? rt : (t < lane ? -acc[t] * rt : 0.0);
+#pragma unroll
+      for (int i = 0; i < t; ++i) acc[i] = fma(M[(b0 + i) * LDC + b0 + t], x[t], acc[i]);
+    }
+    if (lane < B && b0 + lane < l) {
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+        if (i < lane) M[(b0 + lane) * LDC + b0 + i] = x[i];
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < l * l; idx += 1024) {
-    const int row = idx / l, col = idx - row * l;
-    const double v = tbuf[row * TLD + col];
-    if (p.Rinv) p.Rinv[idx] = v;
-    if (p.RinvT) {
-      if (p.dtype == RSVD_F64) ((double*)p.RinvT)[idx] = v;
-      else ((float*)p.RinvT)[idx] = (float)v;
+  // Joining pairs: A = [a0, a1) (full, s rows), C = [a1, ce) (s columns, the last
+  // pair possibly fewer).  Item = (pair, 8-row group of A) per wave, lane = column of C;
+  // npair * s / 8 = 8 items per level for l <= 128.
+  for (int s = B; s < l; s *= 2) {
+    const int npair = (l - s + 2 * s - 1) / (2 * s);
+    const int nrg = s / RG, items = npair * nrg;
+    for (int it0 = 0; it0 < items; it0 += NW) {
+      const int it = it0 + wave;
+      const int pair = it / nrg, rg = it - pair * nrg;
+      const int a1 = 2 * s * pair + s, ce = min(a1 + s, l);
+      const int r0 = a1 - s + RG * rg, c = a1 + lane;
+      const bool work = it < items && lane < s && c < ce;
+      double acc[RG] = {};
+      // T = R_AC X_CC: T[r][c] = sum_{t = a1..c} R[r][t] X[t][c]
+      if (work) {
+        for (int t = a1; t < c; ++t) {
+          const double bv = M[c * LDC + t];
+#pragma unroll
+          for (int i = 0; i < RG; ++i) acc[i] = fma(M[(r0 + i) * LDC + t], bv, acc[i]);
+        }
+        const double bv = rinv_d[c];
+#pragma unroll
+        for (int i = 0; i < RG; ++i) {
+          acc[i] = fma(M[(r0 + i) * LDC + c], bv, acc[i]);
+          M[c * LDC + r0 + i] = acc[i];
+        }
+      }
+      __syncthreads();
+      // X_AC = -X_AA T: X[r][c] = -sum_{u = r..a1-1} X[r][u] T[u][c]
+      if (work) {
+#pragma unroll
+        for (int i = 0; i < RG; ++i) acc[i] = 0.0;
+#pragma unroll
+        for (int uu = 0; uu < RG; ++uu) {
+          const int u = r0 + uu;
+          const double bv = M[c * LDC + u];
+#pragma unroll
+          for (int i = 0; i < RG; ++i) {
+            const double av = uu > i ? M[u * LDC + r0 + i] : (uu == i ? rinv_d[u] : 0.0);
+            acc[i] = fma(av, bv, acc[i]);
+          }
+        }
+        for (int u = r0 + RG; u < a1; ++u) {
+          const double bv = M[c * LDC + u];
+#pragma unroll
+          for (int i = 0; i < RG; ++i) acc[i] = fma(M[u * LDC + r0 + i], bv, acc[i]);
+        }
+      }
+      __syncthreads();
+      if (work)
+#pragma unroll
+        for (int i = 0; i < RG; ++i) M[c * LDC + r0 + i] = -acc[i];
+      __syncthreads();
     }
   }
+  if (tc < l)
+    for (int a = tr; a < l; a += 4) {
+      const int64_t idx = (int64_t)a * l + tc;
+      const double v = tc > a ? M[tc * LDC + a] : (tc == a ? rinv_d[a] : 0.0);
+      if (p.Rinv) p.Rinv[idx] = v;
+      if (p.RinvT) {
+        if (p.dtype == RSVD_F64) ((double*)p.RinvT)[idx] = v;
+        else ((float*)p.RinvT)[idx] = (float)v;
+      }
+    }
 }
 
-__global__ __launch_bounds__(1024) void chol_kernel(const CholParams p) { chol_body(p, blockIdx.x); }
+__global__ __launch_bounds__(512) void chol_kernel(const CholParams p) { chol_body(p, blockIdx.x); }
 
-__global__ __launch_bounds__(1024) void chol_batched(const CholParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+__global__ __launch_bounds__(512) void chol_batched(const CholParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
   const BlockMap b = bm[blockIdx.x];
   chol_body(ps[b.item], b.local);
 }
@@ -411,13 +528,13 @@ hipError_t launch_gram_reduce_batched(const GramReduceParams* ps, const BlockMap
 
 hipError_t launch_chol_batched(const CholParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(chol_batched, dim3((unsigned)nblocks), dim3(1024), 0, st, ps, bm);
+  hipLaunchKernelGGL(chol_batched, dim3((unsigned)nblocks), dim3(512), 0, st, ps, bm);
   return hipGetLastError();
 }
 
 hipError_t launch_chol(const CholParams& p, hipStream_t st) {
   if (p.l > 128 || p.l < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(1024), 0, st, p);
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(512), 0, st, p);
   return hipGetLastError();
 }
 
