@@ -144,30 +144,26 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const GramReduceParam
 }
 
 // Cholesky factor R (W = R^T R, R upper triangular, positive diagonal) and its
-// inverse X = R^-1, blocked by 16 for one workgroup of 512 threads.  W, then
-// R, lives in the upper triangle of an LDS matrix; X^T is built in the strict
-// lower triangle (X is upper triangular) and 1 / R_ii in a vector.
+// inverse X = R^-1, by blocked elimination on [W | I] for one workgroup of 512
+// threads.  With L = R^T, the row operations that take W to R (block row k
+// scaled by L_kk^-1, then subtracted from the rows below it) take I to L^-1 =
+// X^T, so both come out of the same passes.  One LDS matrix holds both parts:
+// the upper triangle holds W, then R; the strict lower triangle holds the
+// eliminated identity, then X^T; its diagonal (1 / R_ii) is kept in a vector.
 //
-// Factorization, per block column [k0, k1):
-//   1. one wave factors the panel (rows k0..k1-1) in registers, right-looking:
-//      lanes 0..15 hold the diagonal block's columns, lanes 16..63 three
-//      columns each of the block row (R_kj = R_kk^-T W_kj); the pivots and
-//      the rows of R_kk are broadcast with readlane;
-//   2. the trailing matrix is updated, W_ij -= R_ki^T R_kj for k1 <= i <= j:
-//      one column per lane, eight rows per wave, the rows of R_k read as LDS
-//      broadcasts.
-// Inverse by doubling: every 16 x 16 diagonal block inverted at once (one
-// column per lane), then for s = 16, 32, 64 each aligned pair of inverted
-// blocks [A C] is joined, X_AC = -X_AA (R_AC X_CC), again one column per lane
-// and eight rows per wave.
+// Per block of CB rows [k0, k1):
+//   1. panel, one wave: the diagonal block is factored in registers
+//      (right-looking, pivots and rows of R_kk broadcast within each 16-lane
+//      row by DPP; every row of lanes holds a copy), and every other column of
+//      the block row -- R part right of the block, identity part left of and
+//      inside it -- is multiplied by R_kk^-T, two columns per lane.  The
+//      finished block row is also staged in a separate LDS buffer;
+//   2. trailing update of rows k1..l-1 from the staged block row, both parts at
+//      once (columns below k1: identity part; columns >= the row: R part), in
+//      4 x 4 register tiles fed by 16-byte LDS reads.
 // A pivot that is not positive (or not finite) restarts the factorization on
 // W + s I with the shifted-CholeskyQR shift; a second failure (non-finite
 // input) returns identity factors and raises RSVD_FLAG_NONFINITE.
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
 
 // 1/sqrt(x) from the hardware estimate and two Newton steps (x > 0, finite).
 __device__ __forceinline__ double rsq_refined(double x) {
@@ -177,134 +173,185 @@ __device__ __forceinline__ double rsq_refined(double x) {
   return y;
 }
 
-__device__ __forceinline__ void chol_body(const CholParams& p, const int bid) {
-  (void)bid;  // one workgroup per factorization
-  constexpr int NT = 512, NW = NT / 64, B = 16, LDC = 129;  // odd stride: column walks hit distinct banks
-  constexpr int RG = 8;                                      // rows per wave in the matrix phases
-  __shared__ double M[128 * LDC];
+// Value of lane L of this lane's 16-lane row (DPP row_newbcast).
+template <int L>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + L, 0xF, 0xF, false);
+}
+
+// Lane index as an ordinary argument: call it only with values the unrolled
+// loops make constant, so that the switch folds to one DPP move.
+__device__ __forceinline__ double row_bcast_at(double v, int L) {
+  switch (L) {
+    case 0: return row_bcast<0>(v);
+    case 1: return row_bcast<1>(v);
+    case 2: return row_bcast<2>(v);
+    case 3: return row_bcast<3>(v);
+    case 4: return row_bcast<4>(v);
+    case 5: return row_bcast<5>(v);
+    case 6: return row_bcast<6>(v);
+    case 7: return row_bcast<7>(v);
+    case 8: return row_bcast<8>(v);
+    case 9: return row_bcast<9>(v);
+    case 10: return row_bcast<10>(v);
+    case 11: return row_bcast<11>(v);
+    case 12: return row_bcast<12>(v);
+    case 13: return row_bcast<13>(v);
+    case 14: return row_bcast<14>(v);
+    default: return row_bcast<15>(v);
+  }
+}
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+template <int CB>
+__device__ __forceinline__ void chol_body_t(const CholParams& p) {
+  static_assert(CB == 16, "the trailing update tiles are 16 x 16");
+  constexpr int NT = 512, NW = NT / 64, LDC = 130;  // even: rows start on 16-byte boundaries
+  constexpr int PLD = 144;                          // staged row: 128 columns + tile overhang
+  __shared__ __attribute__((aligned(16))) double M[128 * LDC];
+  __shared__ __attribute__((aligned(16))) double Pr[CB * PLD];
   __shared__ double rinv_d[128];  // 1 / R_ii (0 past l)
   __shared__ int bad_s;
   if (p.gate && *p.gate == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l = p.l, Lg = p.Lg;
-  const int lp = (l + B - 1) & ~(B - 1);  // rows and columns past l up to lp hold zeros
+  const int lp = (l + 15) & ~15;            // rows and columns past l up to lp hold zeros
   const int tc = tid & 127, tr = tid >> 7;  // 4 x 128 thread grid for whole-matrix loops
   const double eps = DBL_EPSILON;
-  double thresh = 0.0, trace = 0.0;
+
+  // max diagonal (breakdown threshold) and trace (shift) of W, every wave for itself
+  double thresh, trace;
+  {
+    const double d0 = lane < l ? p.G[(int64_t)lane * (Lg + 1)] : 0.0;
+    const double d1 = lane + 64 < l ? p.G[(int64_t)(lane + 64) * (Lg + 1)] : 0.0;
+    double mx = fmax(d0, d1), trs = d0 + d1;
+    for (int off = 32; off > 0; off >>= 1) {
+      mx = fmax(mx, __shfl_xor(mx, off, 64));
+      trs += __shfl_xor(trs, off, 64);
+    }
+    thresh = (double)l * 16.0 * eps * mx;
+    trace = trs;
+  }
 
   bool ok = false;
   for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
     // Shifted CholeskyQR: s = 11 (rows l + l (l + 1)) u ||Y||_F^2 with u the FP64 unit roundoff.
     const double shift =
         attempt == 0 ? 0.0 : 11.0 * ((double)p.rows * l + (double)l * (l + 1)) * (0.5 * eps) * trace;
-    for (int a0 = tr; a0 < lp; a0 += 4 * 8) {
-      double v[8];
+    {
+      // column pair 2 (tid % 64), rows tid / 64 + 8 u: every load in flight at once
+      const int cp = 2 * (tid & 63), r0 = tid >> 6;
+      dbl2 v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int a = a0 + 4 * u;
-        v[u] = (a < l && tc < l && tc >= a) ? p.G[(int64_t)a * Lg + tc] : 0.0;
+      for (int u = 0; u < 16; ++u) {
+        const int a = r0 + 8 * u;
+        v[u] = (a < l && cp + 1 >= a && cp < l) ? *reinterpret_cast<const dbl2*>(p.G + (int64_t)a * Lg + cp)
+                                                : dbl2{0.0, 0.0};
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int a = a0 + 4 * u;
-        if (a < lp && tc < lp) M[a * LDC + tc] = v[u] + (a == tc && a < l ? shift : 0.0);
+      for (int u = 0; u < 16; ++u) {
+        const int a = r0 + 8 * u;
+        if (a < lp && cp < lp) {
+          dbl2 w = v[u];
+          w.x = (cp < l && cp >= a) ? w.x + (cp == a ? shift : 0.0) : 0.0;
+          w.y = (cp + 1 < l && cp + 1 >= a) ? w.y + (cp + 1 == a ? shift : 0.0) : 0.0;
+          *reinterpret_cast<dbl2*>(M + a * LDC + cp) = w;
+        }
       }
     }
+    for (int i = tid; i < CB * PLD; i += NT) Pr[i] = 0.0;
     if (tid < 128) rinv_d[tid] = 0.0;
     __syncthreads();
-    if (attempt == 0) {
-      // max diagonal (breakdown threshold) and trace (shift) of W, every wave for itself
-      const double d0 = lane < l ? p.G[(int64_t)lane * (Lg + 1)] : 0.0;
-      const double d1 = lane + 64 < l ? p.G[(int64_t)(lane + 64) * (Lg + 1)] : 0.0;
-      double mx = fmax(d0, d1), trs = d0 + d1;
-      for (int off = 32; off > 0; off >>= 1) {
-        mx = fmax(mx, __shfl_xor(mx, off, 64));
-        trs += __shfl_xor(trs, off, 64);
-      }
-      thresh = (double)l * 16.0 * eps * mx;
-      trace = trs;
-    }
     ok = true;
-    for (int k0 = 0; k0 < l; k0 += B) {
-      const int k1 = min(k0 + B, l), bk = k1 - k0;
-      // 1. panel by wave 0.  Past the diagonal block the block is full (bk == B):
-      //    only the last one is partial, and it has no block row.
-      if (wave == 0) {
-        int col[3];
-        bool has[3];
+    for (int k0 = 0; k0 < l; k0 += CB) {
+      const int k1 = min(k0 + CB, l), bk = k1 - k0;
+      // 1. panel by waves 0 and 1.  Both factor the diagonal block (each 16-lane row
+      //    of both waves holds a copy); column sc = lane + 64 wave of the block row
+      //    is multiplied by R_kk^-T in the lane's registers.  Every load and store
+      //    stays inside M and Pr: values read from the zero padding or past lp only
+      //    ever reach entries that no later step reads.
+      const int dq = lane & (CB - 1);  // diagonal column k0 + dq
+      const int sc = lane + 64 * wave;
+      const bool diag = sc >= k0 && sc < k1;  // identity column inside the block: then dq == sc - k0
+      double x0[CB], xt[CB];
+      if (wave < 2) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          col[m] = lane < B ? k0 + lane : k1 + (lane - B) + 48 * m;
-          has[m] = lane < B ? (m == 0 && lane < bk) : col[m] < l;
+        for (int i = 0; i < CB; ++i) {
+          x0[i] = M[(k0 + i) * LDC + k0 + dq];  // below the diagonal: never read by other lanes
+          const double w = M[(k0 + i) * LDC + sc];
+          xt[i] = diag ? (i == dq ? 1.0 : 0.0) : w;
         }
-        double x[3][B];
+      }
+      __syncthreads();  // both waves hold the diagonal block before either stores into it
+      if (wave < 2) {
+        double rv = 0.0;
+        bool bad = false;
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
+        for (int j = 0; j < CB; ++j) {
+          if (j < bk) {  // uniform; a failed pivot only sets bad (the results are discarded)
+            const double djj = row_bcast_at(x0[j], j);
+            bad = bad || !(djj > thresh) || !isfinite(djj);
+            const double rinv = rsq_refined(djj);
+            double rjj = djj * rinv;
+            rjj = fma(0.5 * rinv, fma(-rjj, rjj, djj), rjj);
+            x0[j] = dq == j ? rjj : x0[j] * rinv;  // row j of R_kk
+            rv = dq == j ? rinv : rv;
+            xt[j] *= rinv;
 #pragma unroll
-          for (int i = 0; i < B; ++i)
-            x[m][i] = (has[m] && (lane >= B || i <= lane)) ? M[(k0 + i) * LDC + col[m]] : 0.0;
-        int bad = 0;
-#pragma unroll
-        for (int j = 0; j < B; ++j) {
-          if (j < bk && !bad) {  // uniform across the wave
-            const double djj = readlane_f64(x[0][j], j);
-            if (!(djj > thresh) || !isfinite(djj)) {
-              bad = 1;
-            } else {
-              const double rinv = rsq_refined(djj);
-              double rjj = djj * rinv;
-              rjj = fma(0.5 * rinv, fma(-rjj, rjj, djj), rjj);
-#pragma unroll
-              for (int m = 0; m < 3; ++m) x[m][j] *= rinv;  // row j of R (zeros stay zeros)
-              if (lane == j) {
-                x[0][j] = rjj;
-                rinv_d[k0 + j] = rinv;
-              }
-#pragma unroll
-              for (int i = j + 1; i < B; ++i) {
-                const double rji = readlane_f64(x[0][j], i);  // R[j][i]
-#pragma unroll
-                for (int m = 0; m < 3; ++m) x[m][i] = fma(-rji, x[m][j], x[m][i]);
-              }
+            for (int i = j + 1; i < CB; ++i) {
+              const double rji = row_bcast_at(x0[j], i);  // R[j][i]
+              x0[i] = fma(-rji, x0[j], x0[i]);
+              xt[i] = fma(-rji, xt[j], xt[i]);
             }
           }
         }
         if (!bad) {
+          // identity columns inside the block carry R_kk above the diagonal (the
+          // lane's copy of column k0 + dq) and X_kk^T below it
 #pragma unroll
-          for (int m = 0; m < 3; ++m)
-            if (has[m])
-#pragma unroll
-              for (int i = 0; i < B; ++i)
-                if (lane >= B || i <= lane) M[(k0 + i) * LDC + col[m]] = x[m][i];
+          for (int i = 0; i < CB; ++i) {
+            M[(k0 + i) * LDC + sc] = (diag && i <= dq) ? x0[i] : xt[i];
+            Pr[i * PLD + sc] = xt[i];
+          }
+          if (diag) rinv_d[sc] = rv;
         }
-        if (lane == 0) bad_s = bad;
+        if (tid == 0) bad_s = bad ? 1 : 0;
       }
       __syncthreads();
       if (bad_s) {
         ok = false;
         break;
       }
-      // 2. trailing update: item = (64-column chunk, 8-row group) per wave
-      const int nt = l - k1;
-      if (nt > 0) {
-        const int nrg = (nt + RG - 1) / RG, items = ((nt + 63) / 64) * nrg;
+      // 2. trailing update, one 16 x 16 output tile per wave and step, on FP64 MFMA
+      //    (K = 16: four 16x16x4 products).  Row tile r (rows k1 + 16 r ..) needs
+      //    the identity-part tiles left of k1 and the R-part tiles from its own
+      //    diagonal tile on: lp/16 - r tiles.
+      if (k1 < l) {
+        const int T = lp / 16, K1 = k1 / 16, nrt = T - K1;
+        const int items = nrt * T - nrt * (nrt - 1) / 2;
         for (int it = wave; it < items; it += NW) {
-          const int cc = it / nrg, rg = it - cc * nrg;
-          const int i0 = k1 + RG * rg, cbase = k1 + 64 * cc;
-          if (i0 > cbase + 63) continue;  // below the diagonal (uniform)
-          const int c = cbase + lane, cl = min(c, lp - 1);
-          double acc[RG] = {};
-#pragma unroll 4
-          for (int t = 0; t < B; ++t) {
-            const double* row = M + (k0 + t) * LDC;
-            const double bv = row[cl];
-#pragma unroll
-            for (int i = 0; i < RG; ++i) acc[i] = fma(row[i0 + i], bv, acc[i]);
+          int r = 0, u = it;
+          while (u >= T - r) {  // uniform: at most 8 steps
+            u -= T - r;
+            ++r;
           }
-          if (c < l)
+          const int cj = u < K1 ? u : u + r;
+          const int ib = k1 + 16 * r, cb = 16 * cj;
+          const int li = lane & 15, lk = lane >> 4;
+          f64x4 acc = f64x4{};
 #pragma unroll
-            for (int i = 0; i < RG; ++i)
-              if (i0 + i <= c) M[(i0 + i) * LDC + c] -= acc[i];
+          for (int s4 = 0; s4 < CB / 4; ++s4) {
+            const double* row = Pr + (4 * s4 + lk) * PLD;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(row[ib + li], row[cb + li], acc, 0, 0, 0);
+          }
+          // acc[e] belongs to row ib + 4 e + lk, column cb + li
+          const int c = cb + li;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int i = ib + 4 * e + lk;
+            if (i < l && c < l && (c < k1 || c >= i)) M[i * LDC + c] -= acc[e];
+          }
         }
       }
       __syncthreads();
@@ -318,103 +365,24 @@ __device__ __forceinline__ void chol_body(const CholParams& p, const int bid) {
   if (!ok) {
     // Shifted factorization failed as well (non-finite input): identity factors.
     if (tid == 0) atomicOr(p.status, (int32_t)RSVD_FLAG_NONFINITE);
-    for (int a = tr; a < l; a += 4) {
-      if (tc >= l) break;
-      const int64_t idx = (int64_t)a * l + tc;
-      const double v = a == tc ? 1.0 : 0.0;
-      if (p.R) p.R[idx] = v;
-      if (p.Rinv) p.Rinv[idx] = v;
-      if (p.RinvT) {
-        if (p.dtype == RSVD_F64) ((double*)p.RinvT)[idx] = v;
-        else ((float*)p.RinvT)[idx] = (float)v;
+    if (tc < l)
+      for (int a = tr; a < l; a += 4) {
+        const int64_t idx = (int64_t)a * l + tc;
+        const double v = a == tc ? 1.0 : 0.0;
+        if (p.R) p.R[idx] = v;
+        if (p.Rinv) p.Rinv[idx] = v;
+        if (p.RinvT) {
+          if (p.dtype == RSVD_F64) ((double*)p.RinvT)[idx] = v;
+          else ((float*)p.RinvT)[idx] = (float)v;
+        }
       }
-    }
     return;
-  }
-  if (p.R && tc < l)
-    for (int a = tr; a < l; a += 4) p.R[(int64_t)a * l + tc] = tc >= a ? M[a * LDC + tc] : 0.0;
-  if (!p.Rinv && !p.RinvT) return;
-
-  // Inverse.  X[r][c] (r < c) is kept at M[c * LDC + r], X[c][c] in rinv_d.
-  const int nb = lp / B;
-  // diagonal blocks, one wave each: lane c solves R_bb x = e_c, right-looking from the bottom
-  for (int b = wave; b < nb; b += NW) {
-    const int b0 = b * B;
-    double acc[B], x[B];
-#pragma unroll
-    for (int i = 0; i < B; ++i) acc[i] = 0.0;
-#pragma unroll
-    for (int t = B - 1; t >= 0; --t) {
-      const double rt = rinv_d[b0 + t];
-      x[t] = t == lane ? rt : (t < lane ? -acc[t] * rt : 0.0);
-#pragma unroll
-      for (int i = 0; i < t; ++i) acc[i] = fma(M[(b0 + i) * LDC + b0 + t], x[t], acc[i]);
-    }
-    if (lane < B && b0 + lane < l) {
-#pragma unroll
-      for (int i = 0; i < B; ++i)
-        if (i < lane) M[(b0 + lane) * LDC + b0 + i] = x[i];
-    }
-  }
-  __syncthreads();
-  // Joining pairs: A = [a0, a1) (full, s rows), C = [a1, ce) (s columns, the last
-  // pair possibly fewer).  Item = (pair, 8-row group of A) per wave, lane = column of C;
-  // npair * s / 8 = 8 items per level for l <= 128.
-  for (int s = B; s < l; s *= 2) {
-    const int npair = (l - s + 2 * s - 1) / (2 * s);
-    const int nrg = s / RG, items = npair * nrg;
-    for (int it0 = 0; it0 < items; it0 += NW) {
-      const int it = it0 + wave;
-      const int pair = it / nrg, rg = it - pair * nrg;
-      const int a1 = 2 * s * pair + s, ce = min(a1 + s, l);
-      const int r0 = a1 - s + RG * rg, c = a1 + lane;
-      const bool work = it < items && lane < s && c < ce;
-      double acc[RG] = {};
-      // T = R_AC X_CC: T[r][c] = sum_{t = a1..c} R[r][t] X[t][c]
-      if (work) {
-        for (int t = a1; t < c; ++t) {
-          const double bv = M[c * LDC + t];
-#pragma unroll
-          for (int i = 0; i < RG; ++i) acc[i] = fma(M[(r0 + i) * LDC + t], bv, acc[i]);
-        }
-        const double bv = rinv_d[c];
-#pragma unroll
-        for (int i = 0; i < RG; ++i) {
-          acc[i] = fma(M[(r0 + i) * LDC + c], bv, acc[i]);
-          M[c * LDC + r0 + i] = acc[i];
-        }
-      }
-      __syncthreads();
-      // X_AC = -X_AA T: X[r][c] = -sum_{u = r..a1-1} X[r][u] T[u][c]
-      if (work) {
-#pragma unroll
-        for (int i = 0; i < RG; ++i) acc[i] = 0.0;
-#pragma unroll
-        for (int uu = 0; uu < RG; ++uu) {
-          const int u = r0 + uu;
-          const double bv = M[c * LDC + u];
-#pragma unroll
-          for (int i = 0; i < RG; ++i) {
-            const double av = uu > i ? M[u * LDC + r0 + i] : (uu == i ? rinv_d[u] : 0.0);
-            acc[i] = fma(av, bv, acc[i]);
-          }
-        }
-        for (int u = r0 + RG; u < a1; ++u) {
-          const double bv = M[c * LDC + u];
-#pragma unroll
-          for (int i = 0; i < RG; ++i) acc[i] = fma(M[u * LDC + r0 + i], bv, acc[i]);
-        }
-      }
-      __syncthreads();
-      if (work)
-#pragma unroll
-        for (int i = 0; i < RG; ++i) M[c * LDC + r0 + i] = -acc[i];
-      __syncthreads();
-    }
   }
   if (tc < l)
     for (int a = tr; a < l; a += 4) {
       const int64_t idx = (int64_t)a * l + tc;
+      if (p.R) p.R[idx] = tc >= a ? M[a * LDC + tc] : 0.0;
+      // X[a][tc] = (X^T)[tc][a]
       const double v = tc > a ? M[tc * LDC + a] : (tc == a ? rinv_d[a] : 0.0);
       if (p.Rinv) p.Rinv[idx] = v;
       if (p.RinvT) {
@@ -422,6 +390,11 @@ __device__ __forceinline__ void chol_body(const CholParams& p, const int bid) {
         else ((float*)p.RinvT)[idx] = (float)v;
       }
     }
+}
+
+__device__ __forceinline__ void chol_body(const CholParams& p, const int bid) {
+  (void)bid;  // one workgroup per factorization
+  chol_body_t<16>(p);
 }
 
 __global__ __launch_bounds__(512) void chol_kernel(const CholParams p) { chol_body(p, blockIdx.x); }
