@@ -173,6 +173,7 @@ class Runner {
   virtual bool records() const = 0;
   virtual hipError_t gemm(int dtype, int prec, bool trans, const GemmParams& p, int kind) = 0;
   virtual hipError_t gram_partial(int dtype, const GramParams& p) = 0;
+  virtual hipError_t sum_parts(int dtype, const GramParams& p) = 0;
   virtual hipError_t gram_reduce(const GramReduceParams& p) = 0;
   virtual hipError_t chol(const CholParams& p) = 0;
   virtual hipError_t jacobi(const JacobiParams& p) = 0;
@@ -194,6 +195,10 @@ class DirectRunner final : public Runner {
   hipError_t gram_partial(int dtype, const GramParams& p) override {
     Timed t(h_, RSVD_KERNEL_GRAM, st_);
     return launch_gram_partial(dtype, p, st_);
+  }
+  hipError_t sum_parts(int dtype, const GramParams& p) override {
+    Timed t(h_, RSVD_KERNEL_GRAM, st_);
+    return launch_sum_parts(dtype, p, st_);
   }
   hipError_t gram_reduce(const GramReduceParams& p) override {
     Timed t(h_, RSVD_KERNEL_GRAM, st_);
@@ -245,6 +250,8 @@ class RecordRunner final : public Runner {
   hipError_t gram_partial(int dtype, const GramParams& p) override {
     return add(SK_GRAM_PARTIAL, dtype, 0, false, p, p.rows > 0 ? gram_partial_blocks(p) : 0);
   }
+  // batched problems are never split along K, so there are no partials to sum
+  hipError_t sum_parts(int, const GramParams&) override { return hipErrorNotSupported; }
   hipError_t gram_reduce(const GramReduceParams& p) override {
     return add(SK_GRAM_REDUCE, 0, 0, false, p, gram_reduce_blocks(p));
   }
@@ -321,6 +328,7 @@ rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda,
   g.vec = (lda % vec_mult == 0 && aligned16(A)) ? 1 : 0;
   g.gate = gate;
   g.accum = accum ? 1 : 0;
+  g.narrow = (!c.run->records() && !streams_a && c.P.dtype == RSVD_F32 && prec == RSVD_NATIVE) ? 1 : 0;
   if (g.S > 1 && !part) return RSVD_E_INVAL;
   if (accum && (g.S > 1 || streams_a)) return RSVD_E_INVAL;
   const int kind = streams_a ? (trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN) : RSVD_KERNEL_SMALL_GEMM;
@@ -339,10 +347,10 @@ rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda,
 }
 
 // Gram of a rows x l matrix into G (FP64, Lg x Lg upper).  Source: split-K
-// partials (summed and stored into `y`) or a stored `y`.
+// partials (summed and stored into `y` first) or a stored `y`.
 rsvd_status gram(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t rows, const int32_t* gate) {
   GramParams g{};
-  g.mode = from_part ? GRAM_FROM_PART : GRAM_FROM_PLAIN;
+  g.mode = GRAM_FROM_PLAIN;
   g.part = c.at<void>(c.P.part);
   g.S = sp.S;
   g.Lp = c.P.Lp;
@@ -355,8 +363,10 @@ rsvd_status gram(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t
   g.do_gram = 1;
   g.gpart = c.at<double>(c.P.gpart);
   g.gate = gate;
+  const int64_t nchunks = gram_geometry(rows, c.P.Lg, !c.run->records(), &g.tgroups, &g.chunk);
+  if (from_part) RSVD_TRY(c.run->sum_parts(c.P.dtype, g));
   RSVD_TRY(c.run->gram_partial(c.P.dtype, g));
-  const GramReduceParams r{g.gpart, ceil_div(rows, GRAM_ROWS), c.P.Lg, c.at<double>(c.P.G), c.status, gate};
+  const GramReduceParams r{g.gpart, nchunks, c.P.Lg, c.at<double>(c.P.G), c.status, gate};
   RSVD_TRY(c.run->gram_reduce(r));
   return RSVD_OK;
 }
@@ -425,7 +435,6 @@ rsvd_status apply_and_orth(const Ctx& c, const rsvd_problem* pr, bool trans, con
 // Sum the S split-K partial products (rows x l) into `out` in a fixed order.
 rsvd_status reduce_parts(const Ctx& c, const Split& sp, int64_t rows, void* out) {
   GramParams g{};
-  g.mode = GRAM_FROM_PART;
   g.part = c.at<void>(c.P.part);
   g.S = sp.S;
   g.Lp = c.P.Lp;
@@ -433,10 +442,7 @@ rsvd_status reduce_parts(const Ctx& c, const Split& sp, int64_t rows, void* out)
   g.ldy = c.P.l;
   g.rows = rows;
   g.l = (int32_t)c.P.l;
-  g.Lg = c.P.Lg;
-  g.do_gram = 0;
-  g.gpart = c.at<double>(c.P.gpart);
-  RSVD_TRY(c.run->gram_partial(c.P.dtype, g));
+  RSVD_TRY(c.run->sum_parts(c.P.dtype, g));
   return RSVD_OK;
 }
 

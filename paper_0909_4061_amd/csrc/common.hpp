@@ -43,6 +43,7 @@ struct GemmParams {
   int32_t vec;          // 1: A rows (NN) / A columns (TN) allow 16-byte loads
   int32_t accum;        // 1: out += op(A) X (S == 1 only); 0: out = op(A) X
   const int32_t* gate;  // if non-null and *gate == 0 the kernel does nothing
+  int32_t narrow;       // FP32 native, S == 1, K <= 256: 32-row blocks (more workgroups for one product)
 };
 
 // Tile geometry of each GEMM variant (rows of C per workgroup, K per stage).
@@ -71,11 +72,22 @@ struct GramParams {
   int32_t l;
   int32_t Lg;            // l rounded up to 16
   int32_t do_gram;       // 0: only reduce the partials into yout
-  double* gpart;         // nblk x Lg x Lg: upper 16x16 tiles of each block Gram
+  double* gpart;         // nblk x Lg x Lg: upper 16x16 tiles of each chunk's Gram
   const int32_t* gate;
+  int32_t tgroups;       // workgroup b: row chunk b / tgroups, tiles t = b % tgroups (mod tgroups)
+  int32_t chunk;         // rows per chunk, a multiple of GRAM_ROWS
 };
 enum { GRAM_FROM_PART = 0, GRAM_FROM_PLAIN = 1 };
-constexpr int GRAM_ROWS = 64;  // rows of Y per Gram workgroup
+constexpr int GRAM_ROWS = 64;  // rows of Y staged at a time by a Gram workgroup
+// Chunks and tile groups of the Gram of `rows` rows (returns the chunk count,
+// which is the number of partial Grams).  wide: split the tiles of each chunk
+// over workgroups so that a single Gram fills the chip with few partials;
+// otherwise one workgroup per GRAM_ROWS rows with every tile (a batch of Grams
+// fills the chip by itself).
+int64_t gram_geometry(int64_t rows, int32_t Lg, bool wide, int32_t* tgroups, int32_t* chunk);
+// yout (rows x l, leading dimension ldy) = sum over s of the S split-K partials
+// part[s] (rows x Lp), in the order s = 0, 1, ...
+hipError_t launch_sum_parts(int dtype, const GramParams& p, hipStream_t st);
 
 hipError_t launch_gram_partial(int dtype, const GramParams& p, hipStream_t st);
 hipError_t launch_gram_reduce(const double* gpart, int64_t nblk, int32_t Lg, double* G,

@@ -4,16 +4,20 @@
 //   W = Y^T Y (FP64),  W = R^T R (Cholesky),  Q = Y R^-1,
 // and CholeskyQR2 repeats it once on Q.  The host chains these kernels:
 //
-//   gram_partial : one workgroup per 64 rows.  Loads the rows of Y -- either
-//                  summing the split-K partial products of the GEMM that made
-//                  Y (in a fixed order) and storing Y, or reading a stored Y --
-//                  and forms the 64-row block Gram Y_b^T Y_b with FP64 MFMA
-//                  (FP32 entries are exact in FP64, so the products are exact).
-//                  Only the upper 16x16 tiles are computed.
-//   gram_reduce  : sums the block Grams in a fixed order (deterministic).
-//   chol         : one workgroup of 512 threads.  Blocked (by 16) Cholesky
-//                  of W in LDS, then the inverse R^-1 blockwise, a few
-//                  barriers per block instead of per column.
+//   sum_parts    : sums the split-K partial products of the GEMM that made Y
+//                  (fixed order) and stores Y.
+//   gram_partial : one workgroup per (row chunk, group of upper 16x16 tiles):
+//                  the chunk's rows are staged 64 at a time through LDS and
+//                  the block Gram Y_c^T Y_c accumulated on FP64 MFMA (FP32
+//                  entries are exact in FP64, so the products are exact).
+//                  A single Gram splits its tiles over several workgroups
+//                  per chunk so that it fills the chip with few partials; a
+//                  batch of Grams uses 64-row chunks with every tile.
+//   gram_reduce  : sums the chunk Grams in a fixed order (deterministic).
+//   chol         : one workgroup of 512 threads.  R and R^-1 together by
+//                  blocked (by 16) elimination on [W | I] in LDS: a panel in
+//                  registers, trailing tiles on FP64 MFMA, two barriers per
+//                  block.
 //                  A pivot that is not safely positive restarts the
 //                  factorization on W + sI (shifted CholeskyQR) and raises a
 //                  flag; the host then runs a third pass.
@@ -26,81 +30,117 @@ namespace rsvd {
 
 namespace {
 
+// Split-K partial sums: one thread per 16 bytes of a row, every partial's load
+// in flight at once, summed in the order s = 0, 1, ... (deterministic).
+template <typename T>
+__global__ __launch_bounds__(256) void sum_parts_kernel(const GramParams p) {
+  constexpr int V = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(V)));
+  if (p.gate && *p.gate == 0) return;
+  const int per_row = (p.l + V - 1) / V;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t row = idx / per_row;
+  const int cv = (int)(idx - row * per_row) * V;
+  if (row >= p.rows) return;
+  const T* __restrict__ part = (const T*)p.part;
+  vec v[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s)
+    if (s < p.S) v[s] = *reinterpret_cast<const vec*>(part + ((int64_t)s * p.rows + row) * p.Lp + cv);
+  vec acc = v[0];
+#pragma unroll
+  for (int s = 1; s < 16; ++s)
+    if (s < p.S) acc += v[s];
+  T* __restrict__ y = (T*)p.yout;
+#pragma unroll
+  for (int e = 0; e < V; ++e)
+    if (cv + e < p.l) y[row * p.ldy + cv + e] = acc[e];
+}
+
+// Partial Gram of one row chunk for one group of 16 x 16 tiles (upper
+// triangle, tiles t = group, group + tgroups, ...; wave w of the workgroup
+// takes every fourth of them), accumulated over the chunk's 64-row stages on
+// FP64 MFMA.  FP32 entries are exact in FP64, so the products are exact.  The
+// next stage's rows are loaded into registers while the current one is
+// multiplied.
 template <typename T>
 __device__ __forceinline__ void gram_partial_body(const GramParams& p, const int bid) {
   constexpr int RB = GRAM_ROWS;
   constexpr int YLD = 128 + 1;
+  constexpr int MAXT = 9;  // tiles per wave: 36 tiles / 4 waves with one group
   __shared__ T Ys[RB * YLD];
   if (p.gate && *p.gate == 0) return;
-  const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)bid * RB;
-  const int l = p.l, Lg = p.Lg;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l = p.l, Lg = p.Lg, G = p.tgroups;
+  const int chunk = bid / G, grp = bid - chunk * G;
+  const int64_t rbeg = (int64_t)chunk * p.chunk;
+  const int64_t rend = min(p.rows, rbeg + p.chunk);
+  const int nt = Lg / 16, ntiles = nt * (nt + 1) / 2;
 
-  // Stage the rows (zero beyond l columns / beyond the last row).  Thread
-  // tid covers column tid % 128 of rows tid / 128 + 2 it; every load of the
-  // stage is issued before the first is used.
+  // this wave's tiles: v_mfma_f64_16x16x4f64 with A[i = lane%16][k = lane/16] =
+  // Y[k][16 ti + i], B[k = lane/16][j = lane%16] = Y[k][16 tj + j]; result register
+  // e of lane holds G[16 ti + 4 e + lane/16][16 tj + lane%16]
+  int ti[MAXT], tj[MAXT];
+#pragma unroll
+  for (int j = 0; j < MAXT; ++j) {
+    int rem = grp + G * (wave + 4 * j), r = 0;
+    if (rem >= ntiles) rem = 0;
+    while (rem >= nt - r) {
+      rem -= nt - r;
+      ++r;
+    }
+    ti[j] = r;
+    tj[j] = r + rem;
+  }
+  f64x4 acc[MAXT];
+#pragma unroll
+  for (int j = 0; j < MAXT; ++j) acc[j] = f64x4{};
+
+  // stage loads: column tid % 128 of rows tid / 128 + 2 it
   constexpr int ITER = RB * 128 / 256;
+  const int c = tid & 127, rb = tid >> 7;
+  const T* __restrict__ yin = (const T*)p.yin;
   T vals[ITER];
 #pragma unroll
-  for (int it = 0; it < ITER; ++it) vals[it] = (T)0;
-  const int c = tid & 127;
-  const int rbase = tid >> 7;
-  if (p.mode == GRAM_FROM_PART) {
-    const T* __restrict__ part = (const T*)p.part;
-    for (int s = 0; s < p.S; ++s) {
-      const T* __restrict__ ps = part + (int64_t)s * p.rows * p.Lp;
+  for (int it = 0; it < ITER; ++it) {
+    const int64_t row = rbeg + rb + 2 * it;
+    vals[it] = (row < rend && c < l) ? yin[row * p.ldy + c] : (T)0;
+  }
+  for (int64_t r0 = rbeg; r0 < rend; r0 += RB) {
+    __syncthreads();  // the previous stage's products are done with Ys
+    if (c < Lg) {
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) Ys[(rb + 2 * it) * YLD + c] = vals[it];
+    }
+    __syncthreads();
+    if (r0 + RB < rend) {
 #pragma unroll
       for (int it = 0; it < ITER; ++it) {
-        const int64_t row = row0 + rbase + 2 * it;
-        if (row < p.rows && c < l) vals[it] += ps[row * p.Lp + c];
+        const int64_t row = r0 + RB + rb + 2 * it;
+        vals[it] = (row < rend && c < l) ? yin[row * p.ldy + c] : (T)0;
       }
     }
-    T* __restrict__ yout = (T*)p.yout;
 #pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      const int64_t row = row0 + rbase + 2 * it;
-      if (row < p.rows && c < l) yout[row * p.ldy + c] = vals[it];
-    }
-  } else {
-    const T* __restrict__ yin = (const T*)p.yin;
-#pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      const int64_t row = row0 + rbase + 2 * it;
-      if (row < p.rows && c < l) vals[it] = yin[row * p.ldy + c];
-    }
-  }
-  if (c < Lg) {
-#pragma unroll
-    for (int it = 0; it < ITER; ++it) Ys[(rbase + 2 * it) * YLD + c] = vals[it];
-  }
-  if (!p.do_gram) return;
-  __syncthreads();
-
-  // Upper 16x16 tiles of Y_b^T Y_b.  v_mfma_f64_16x16x4f64: A[i = lane%16][k =
-  // lane/16] = Y[k][16 ti + i], B[k = lane/16][j = lane%16] = Y[k][16 tj + j];
-  // result register e of lane holds G[16 ti + 4 e + lane/16][16 tj + lane%16].
-  const int lane = tid & 63, wave = tid >> 6;
-  const int nt = Lg / 16;
-  const int ntiles = nt * (nt + 1) / 2;
-  double* gout = p.gpart + (int64_t)bid * Lg * Lg;
-  for (int tile = wave; tile < ntiles; tile += 4) {
-    int ti = 0, rem = tile;
-    while (rem >= nt - ti) {
-      rem -= nt - ti;
-      ++ti;
-    }
-    const int tj = ti + rem;
-    f64x4 acc = f64x4{};
+    for (int j = 0; j < MAXT; ++j) {
+      if (grp + G * (wave + 4 * j) < ntiles) {  // uniform across the wave
 #pragma unroll 4
-    for (int ks = 0; ks < RB / 4; ++ks) {
-      const int kr = 4 * ks + (lane >> 4);
-      const double a = (double)Ys[kr * YLD + 16 * ti + (lane & 15)];
-      const double b = (double)Ys[kr * YLD + 16 * tj + (lane & 15)];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int ks = 0; ks < RB / 4; ++ks) {
+          const int kr = 4 * ks + (lane >> 4);
+          const double a = (double)Ys[kr * YLD + 16 * ti[j] + (lane & 15)];
+          const double b = (double)Ys[kr * YLD + 16 * tj[j] + (lane & 15)];
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+        }
+      }
     }
+  }
+  double* gout = p.gpart + (int64_t)chunk * Lg * Lg;
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      gout[(int64_t)(16 * ti + 4 * e + (lane >> 4)) * Lg + 16 * tj + (lane & 15)] = acc[e];
+  for (int j = 0; j < MAXT; ++j) {
+    if (grp + G * (wave + 4 * j) < ntiles) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        gout[(int64_t)(16 * ti[j] + 4 * e + (lane >> 4)) * Lg + 16 * tj[j] + (lane & 15)] = acc[j][e];
+    }
   }
 }
 
@@ -124,8 +164,10 @@ __device__ __forceinline__ void gram_reduce_body(const GramReduceParams& p, cons
   const int64_t LL = (int64_t)p.Lg * p.Lg;
   const bool live = e < LL && (e % p.Lg) >= (e / p.Lg);  // upper triangle only
   double acc = 0.0;
-  if (live)
+  if (live) {
+#pragma unroll 8
     for (int64_t b = q; b < p.nblk; b += 4) acc += p.gpart[b * LL + e];
+  }
   red[q][tid & 63] = acc;
   __syncthreads();
   if (q == 0 && e < LL) {
@@ -460,10 +502,35 @@ hipError_t launch_copy_batched(const CopyParams* ps, const BlockMap* bm, int64_t
   return hipGetLastError();
 }
 
+int64_t gram_geometry(int64_t rows, int32_t Lg, bool wide, int32_t* tgroups, int32_t* chunk) {
+  const int nt = Lg / 16, ntiles = nt * (nt + 1) / 2;
+  const int64_t nsub = (rows + GRAM_ROWS - 1) / GRAM_ROWS;
+  if (!wide) {
+    *tgroups = 1;
+    *chunk = GRAM_ROWS;
+    return nsub;
+  }
+  const int G = ntiles > 12 ? (ntiles + 11) / 12 : 1;  // at most three tiles per wave
+  const int64_t want = (256 + G - 1) / G;                // chunks that fill 256 CUs
+  const int64_t nch = nsub < want ? nsub : want;
+  const int64_t per = nch > 0 ? (nsub + nch - 1) / nch : 1;
+  *tgroups = G;
+  *chunk = (int32_t)(per * GRAM_ROWS);
+  return (rows + *chunk - 1) / *chunk;
+}
+
+namespace {
+bool gram_params_ok(const GramParams& p) {
+  const int nt = p.Lg / 16;
+  return p.l <= 128 && p.Lg % 16 == 0 && p.Lg >= p.l && p.tgroups >= 1 && p.chunk >= GRAM_ROWS &&
+         p.chunk % GRAM_ROWS == 0 && nt * (nt + 1) / 2 <= 36 * p.tgroups && p.mode == GRAM_FROM_PLAIN;
+}
+}  // namespace
+
 hipError_t launch_gram_partial(int dtype, const GramParams& p, hipStream_t st) {
   if (p.rows <= 0) return hipSuccess;
-  if (p.l > 128 || p.Lg % 16 != 0 || p.Lg < p.l) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((p.rows + GRAM_ROWS - 1) / GRAM_ROWS));
+  if (!gram_params_ok(p)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)gram_partial_blocks(p));
   if (dtype == RSVD_F64)
     hipLaunchKernelGGL(gram_partial_kernel<double>, grid, dim3(256), 0, st, p);
   else
@@ -471,7 +538,20 @@ hipError_t launch_gram_partial(int dtype, const GramParams& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-int64_t gram_partial_blocks(const GramParams& p) { return (p.rows + GRAM_ROWS - 1) / GRAM_ROWS; }
+hipError_t launch_sum_parts(int dtype, const GramParams& p, hipStream_t st) {
+  if (p.rows <= 0) return hipSuccess;
+  const int V = dtype == RSVD_F64 ? 2 : 4;
+  if (p.S < 1 || p.S > 16 || p.Lp % V != 0 || p.Lp < p.l || p.l < 1) return hipErrorInvalidValue;
+  const int64_t threads = p.rows * ((p.l + V - 1) / V);
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  if (dtype == RSVD_F64)
+    hipLaunchKernelGGL(sum_parts_kernel<double>, grid, dim3(256), 0, st, p);
+  else
+    hipLaunchKernelGGL(sum_parts_kernel<float>, grid, dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+int64_t gram_partial_blocks(const GramParams& p) { return (p.rows + p.chunk - 1) / p.chunk * p.tgroups; }
 
 int64_t gram_reduce_blocks(const GramReduceParams& p) { return ((int64_t)p.Lg * p.Lg + 63) / 64; }
 

@@ -113,13 +113,28 @@ __device__ inline void stage_load_x(const GemmParams& p, int64_t k0, int64_t ken
 // FP32: v_mfma_f32_32x32x2f32.  Operand lanes: A[i = lane%32][k = lane/32],
 // B[k = lane/32][j = lane%32]; result register e of lane holds
 // C[8*(e/4) + 4*(lane/32) + e%4][lane%32].
-template <bool TRANS>
-__device__ __forceinline__ void gemm_f32_body(const GemmParams& p, const int bid) {
-  constexpr int BM = 128, BK = 32;
+//
+// Two row-block sizes: 128 rows (each wave 32 rows x all columns), and 32 rows
+// (each wave one 32-column tile of the same 32 rows) when the caller asks for
+// it on a short contraction, so that one small product such as Y R^-1 spreads
+// over four times as many workgroups (a batch of products fills the chip
+// without it).  Either way a workgroup reads all of its rows of
+// A before it writes any row of C (in-place Y R^-1 stays safe).
+__host__ __device__ inline int f32_block_rows(const GemmParams& p) { return (p.narrow && p.S == 1 && p.K <= 256) ? 32 : 128; }
+
+constexpr int F32_BK = 32;
+constexpr int F32_AS = F32_BK * (128 + 4);  // LDS floats of the A stage (largest layout)
+constexpr int F32_XLD = 128 + 4;
+
+template <bool TRANS, int BM>
+__device__ __forceinline__ void gemm_f32_body(const GemmParams& p, const int bid, float* As, float* Xs) {
+  constexpr int BK = F32_BK;
   constexpr int ALD = TRANS ? BM + 4 : BK + 1;
-  constexpr int XLD = 128 + 4;
-  __shared__ __attribute__((aligned(16))) float As[TRANS ? BK * (BM + 4) : BM * (BK + 1)];
-  __shared__ __attribute__((aligned(16))) float Xs[BK * XLD];
+  constexpr int XLD = F32_XLD;
+  constexpr int NRUN = BM * BK / 1024;  // runs of four A elements per thread and stage
+  constexpr int RUNS_PER_ROW = TRANS ? BM / 4 : BK / 4;
+  constexpr int ROWS_PER_PASS = 256 / RUNS_PER_ROW;
+  static_assert(TRANS ? BK * ALD <= F32_AS : BM * ALD <= F32_AS, "A stage exceeds its LDS");
   if (p.gate && *p.gate == 0) return;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -129,28 +144,28 @@ __device__ __forceinline__ void gemm_f32_body(const GemmParams& p, const int bid
   const int64_t kbeg = (int64_t)s * p.kchunk;
   const int64_t kend = min(p.K, kbeg + p.kchunk);
   const int NT = p.Lp / 32;
+  const int rbase = BM == 128 ? wave * 32 : 0;  // first row of this wave's tiles
 
   f32x16 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f32x16{};
 
-  float ra[16], rx[16];
+  float ra[NRUN * 4], rx[16];
   const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   if (nk > 0) {
-    stage_load_a<float, TRANS, BM, BK, 4>(p, i0, kbeg, kend, tid, ra);
+    stage_load_a<float, TRANS, BM, BK, NRUN>(p, i0, kbeg, kend, tid, ra);
     stage_load_x<float, BK, 16>(p, kbeg, kend, tid, rx);
   }
   const int r = lane & 31, g = lane >> 5;
   for (int64_t kt = 0; kt < nk; ++kt) {
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
+    for (int it = 0; it < NRUN; ++it) {
+      const int rr = tid / RUNS_PER_ROW + ROWS_PER_PASS * it, cc = 4 * (tid % RUNS_PER_ROW);
       if (!TRANS) {
-        const int rr = (tid >> 3) + 32 * it, cc = 4 * (tid & 7);
 #pragma unroll
         for (int e = 0; e < 4; ++e) As[rr * ALD + cc + e] = ra[4 * it + e];
       } else {
-        const int rr = (tid >> 5) + 8 * it, cc = 4 * (tid & 31);
         *reinterpret_cast<f32x4*>(&As[rr * ALD + cc]) =
             f32x4{ra[4 * it], ra[4 * it + 1], ra[4 * it + 2], ra[4 * it + 3]};
       }
@@ -163,16 +178,16 @@ __device__ __forceinline__ void gemm_f32_body(const GemmParams& p, const int bid
     __syncthreads();
     if (kt + 1 < nk) {
       const int64_t k0 = kbeg + (kt + 1) * BK;
-      stage_load_a<float, TRANS, BM, BK, 4>(p, i0, k0, kend, tid, ra);
+      stage_load_a<float, TRANS, BM, BK, NRUN>(p, i0, k0, kend, tid, ra);
       stage_load_x<float, BK, 16>(p, k0, kend, tid, rx);
     }
 #pragma unroll
     for (int ks = 0; ks < BK / 2; ++ks) {
       const int kl = 2 * ks + g;
-      const float a = TRANS ? As[kl * ALD + wave * 32 + r] : As[(wave * 32 + r) * ALD + kl];
+      const float a = TRANS ? As[kl * ALD + rbase + r] : As[(rbase + r) * ALD + kl];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        if (t < NT) {
+        if (BM == 128 ? t < NT : (t == wave && t < NT)) {
           const float b = Xs[kl * XLD + t * 32 + r];
           acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[t], 0, 0, 0);
         }
@@ -184,10 +199,10 @@ __device__ __forceinline__ void gemm_f32_body(const GemmParams& p, const int bid
   float* part = (float*)p.part;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    if (t >= NT) continue;
+    if (t >= NT || (BM == 32 && t != wave)) continue;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const int64_t row = i0 + wave * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
+      const int64_t row = i0 + rbase + 8 * (e >> 2) + 4 * g + (e & 3);
       const int col = t * 32 + r;
       if (row < p.rows) {
         if (S == 1) {
@@ -204,12 +219,22 @@ __device__ __forceinline__ void gemm_f32_body(const GemmParams& p, const int bid
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(256, 2) void gemm_f32_kernel(const GemmParams p) { gemm_f32_body<TRANS>(p, blockIdx.x); }
+__device__ __forceinline__ void gemm_f32_any(const GemmParams& p, const int bid) {
+  __shared__ __attribute__((aligned(16))) float As[F32_AS];
+  __shared__ __attribute__((aligned(16))) float Xs[F32_BK * F32_XLD];
+  if (f32_block_rows(p) == 32)
+    gemm_f32_body<TRANS, 32>(p, bid, As, Xs);
+  else
+    gemm_f32_body<TRANS, 128>(p, bid, As, Xs);
+}
+
+template <bool TRANS>
+__global__ __launch_bounds__(256, 2) void gemm_f32_kernel(const GemmParams p) { gemm_f32_any<TRANS>(p, blockIdx.x); }
 
 template <bool TRANS>
 __global__ __launch_bounds__(256, 2) void gemm_f32_batched(const GemmParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
   const BlockMap b = bm[blockIdx.x];
-  gemm_f32_body<TRANS>(ps[b.item], b.local);
+  gemm_f32_any<TRANS>(ps[b.item], b.local);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,7 +478,8 @@ GemmTile gemm_tile(int dtype, int prec) {
 
 int64_t gemm_blocks(int dtype, int prec, const GemmParams& p) {
   const GemmTile tile = gemm_tile(dtype, prec);
-  return (p.rows + tile.bm - 1) / tile.bm * p.S;
+  const int bm = (dtype == RSVD_F32 && prec == PREC_NATIVE) ? f32_block_rows(p) : tile.bm;
+  return (p.rows + bm - 1) / bm * p.S;
 }
 
 namespace {
