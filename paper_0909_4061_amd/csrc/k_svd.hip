@@ -13,7 +13,10 @@
 // pair per 4-lane group; a sweep is l - 1 rounds (l rounded up to even, with a
 // zero column when l is odd), so every pair meets once.  A pair is rotated
 // when |c_i . c_j| > tol sqrt(|c_i|^2 |c_j|^2); the workgroup stops after a
-// sweep with no rotation.  The round's fixed cost (three reductions, the
+// sweep with no rotation.  The squared column norms are formed exactly in the
+// first round of every sweep and carried through its other rounds (a rotation
+// changes them by -t c_i . c_j and +t c_i . c_j), so a round forms one dot
+// product per pair instead of three.  The round's fixed cost (three reductions, the
 // rotation angle) is paid once per wave, so fewer lanes per pair (more rows
 // per lane) make a round cheaper; the kernel is compiled for l <= 64 and
 // l <= 128 so that small matrices keep their LDS footprint small.
@@ -72,12 +75,17 @@ __device__ __forceinline__ double rsq_nr(double x) {
 template <int MAXL>
 __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid) {
   (void)bid;  // one workgroup per matrix
-  constexpr int LDC = MAXL + 2;  // even: 16-byte aligned column starts
+  // Column stride: 16-byte aligned, and 64 bytes modulo the 256-byte bank
+  // width, so the 16-byte accesses of four groups with consecutive columns
+  // (four lanes each, consecutive 16-byte pieces) fall on 16 distinct bank
+  // slots instead of four lanes per slot.
+  constexpr int LDC = MAXL + 8;
   constexpr int THREADS = 2 * MAXL;
   constexpr int RPL = MAXL / 4;  // rows per lane
   typedef double d2 __attribute__((ext_vector_type(2)));
   __shared__ __attribute__((aligned(16))) double Cs[MAXL * LDC];  // column c at Cs[c * LDC + row]
   __shared__ double sig_s[MAXL];
+  __shared__ double nrm[MAXL];  // squared column norms, exact at the start of a sweep
   __shared__ int rank_s[MAXL];
   __shared__ int rotated;
   const int tid = threadIdx.x;
@@ -129,22 +137,33 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
           y[2 * r] = yb[0];
           y[2 * r + 1] = yb[1];
         }
-        // four partial sums per product keep the dependent chains short
-        double al4[4] = {0.0, 0.0, 0.0, 0.0}, be4[4] = {0.0, 0.0, 0.0, 0.0}, ga4[4] = {0.0, 0.0, 0.0, 0.0};
+        // The first round of a sweep forms every squared column norm exactly;
+        // later rounds carry them (a rotation maps al, be to al - t ga, be + t ga)
+        // and form only the cross product.  Four partial sums per product keep
+        // the dependent chains short.
+        double al, be, ga;
+        if (rnd == 0) {
+          double al4[4] = {0.0, 0.0, 0.0, 0.0}, be4[4] = {0.0, 0.0, 0.0, 0.0}, ga4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-          al4[r & 3] += x[r] * x[r];
-          be4[r & 3] += y[r] * y[r];
-          ga4[r & 3] += x[r] * y[r];
+          for (int r = 0; r < RPL; ++r) {
+            al4[r & 3] += x[r] * x[r];
+            be4[r & 3] += y[r] * y[r];
+            ga4[r & 3] += x[r] * y[r];
+          }
+          al = group4_sum((al4[0] + al4[1]) + (al4[2] + al4[3]));
+          be = group4_sum((be4[0] + be4[1]) + (be4[2] + be4[3]));
+          ga = group4_sum((ga4[0] + ga4[1]) + (ga4[2] + ga4[3]));
+        } else {
+          double ga4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) ga4[r & 3] += x[r] * y[r];
+          ga = group4_sum((ga4[0] + ga4[1]) + (ga4[2] + ga4[3]));
+          al = nrm[ca];
+          be = nrm[cb];
         }
-        double al = (al4[0] + al4[1]) + (al4[2] + al4[3]);
-        double be = (be4[0] + be4[1]) + (be4[2] + be4[3]);
-        double ga = (ga4[0] + ga4[1]) + (ga4[2] + ga4[3]);
-        al = group4_sum(al);
-        be = group4_sum(be);
-        ga = group4_sum(ga);
         // rotate when |ga| > tol sqrt(al be), tested as ga^2 > tol^2 al be
-        if (ca < l && cb < l && ga * ga > tol * tol * al * be && al > 0.0 && be > 0.0) {
+        const bool rot = ca < l && cb < l && ga * ga > tol * tol * al * be && al > 0.0 && be > 0.0;
+        if (rot) {
           const double zeta = (be - al) * rcp_nr(2.0 * ga);
           const double q = fma(zeta, zeta, 1.0);
           const double root = q * rsq_nr(q);  // sqrt(1 + zeta^2)
@@ -158,8 +177,14 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
             *reinterpret_cast<d2*>(col_b + 8 * r + 2 * gl) =
                 d2{sn * x[2 * r] + cs * y[2 * r], sn * x[2 * r + 1] + cs * y[2 * r + 1]};
           }
-          any = 1;
+          al = fma(-t, ga, al);
+          be = fma(t, ga, be);
         }
+        if (gl == 0 && (rot || rnd == 0)) {
+          nrm[ca] = al;
+          nrm[cb] = be;
+        }
+        any |= rot ? 1 : 0;
       }
       ia = ia + 1 == le - 1 ? 0 : ia + 1;
       ib = ib + 1 == le - 1 ? 0 : ib + 1;
