@@ -100,16 +100,40 @@ __device__ inline f32x4 load4_guard(const float* p, int valid, bool vec) {
 
 __device__ inline int valid4(int64_t v) { return v <= 0 ? 0 : (v >= 4 ? 4 : (int)v); }
 
+// Offset (bf16 elements) of element k (0..31) of row `row` in a BF16 A plane:
+// rows of BPAD elements, the four 16-byte pieces of a row permuted by
+// (row >> 4) & 3.  The 8-byte stores of the transposed (A^T) stage, whose
+// lanes take rows four apart, then fall on four times fewer conflicting banks;
+// the 16-byte operand reads (consecutive rows) stay conflict-free.
+__device__ inline int apos(int row, int k) { return row * BPAD + 8 * ((k >> 3) ^ ((row >> 4) & 3)) + (k & 7); }
+
 // One stage of A in registers: 8 runs of four floats per thread.
 //   NN (A rows x K): run q of thread t covers row (t / 8) + 16 q, k 4 (t % 8) .. +3.
 //   TN (A K x rows): thread t covers the 4 x 4 block k 4 (t / 32) .. +3 (plus
 //   16 for the second block), columns 4 (t % 32) .. +3; run q = 4 b + r is row r
 //   of block b.
-template <bool TRANS>
+template <bool TRANS, bool FAST = false>
 __device__ inline void load_a_stage(const GemmParams& p, int64_t i0, int64_t k0, int64_t kend, int tid,
                                     f32x4 (&ra)[8]) {
   const float* A = (const float*)p.A;
   const bool vec = p.vec != 0;
+  // FAST: a stage inside the matrix (every row / column of the block, every k
+  // of the stage) with 16-byte aligned runs takes plain 16-byte loads, no
+  // per-run guards.
+  if (FAST && vec && i0 + SBM <= p.rows && k0 + SBK <= kend) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      int64_t off;
+      if (!TRANS) {
+        off = (i0 + (tid >> 3) + 16 * q) * p.lda + k0 + 4 * (tid & 7);
+      } else {
+        const int b = q >> 2, r = q & 3;
+        off = (k0 + 4 * (tid >> 5) + 16 * b + r) * p.lda + i0 + 4 * (tid & 31);
+      }
+      ra[q] = *reinterpret_cast<const f32x4*>(A + off);
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     int64_t off;
@@ -186,8 +210,8 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
         const int kc = 4 * (tid & 7);
         u32x2 h, l;
         split4(ra[q], h, l);
-        *reinterpret_cast<u32x2*>(&sAh[buf][row * BPAD + kc]) = h;
-        if (NP == 3) *reinterpret_cast<u32x2*>(&sAl[buf][row * BPAD + kc]) = l;
+        *reinterpret_cast<u32x2*>(&sAh[buf][apos(row, kc)]) = h;
+        if (NP == 3) *reinterpret_cast<u32x2*>(&sAl[buf][apos(row, kc)]) = l;
       }
     } else {
 #pragma unroll
@@ -199,8 +223,8 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
           const f32x4 v = f32x4{ra[4 * b][e], ra[4 * b + 1][e], ra[4 * b + 2][e], ra[4 * b + 3][e]};
           u32x2 h, l;
           split4(v, h, l);
-          *reinterpret_cast<u32x2*>(&sAh[buf][row * BPAD + kc]) = h;
-          if (NP == 3) *reinterpret_cast<u32x2*>(&sAl[buf][row * BPAD + kc]) = l;
+          *reinterpret_cast<u32x2*>(&sAh[buf][apos(row, kc)]) = h;
+          if (NP == 3) *reinterpret_cast<u32x2*>(&sAl[buf][apos(row, kc)]) = l;
         }
       }
     }
@@ -224,8 +248,8 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
         const int row = wave * 64 + rt * 32 + r;
-        ah[rt] = *reinterpret_cast<const bf16x8*>(&sAh[buf][row * BPAD + kb]);
-        if (NP == 3) al[rt] = *reinterpret_cast<const bf16x8*>(&sAl[buf][row * BPAD + kb]);
+        ah[rt] = *reinterpret_cast<const bf16x8*>(&sAh[buf][apos(row, kb)]);
+        if (NP == 3) al[rt] = *reinterpret_cast<const bf16x8*>(&sAl[buf][apos(row, kb)]);
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -247,22 +271,22 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
   };
   auto kofs = [&](int64_t stage) { return kbeg + stage * SBK; };
 
-  if (nk > 0) load_a_stage<TRANS>(p, i0, kofs(0), kend, tid, raA);
+  if (nk > 0) load_a_stage<TRANS, true>(p, i0, kofs(0), kend, tid, raA);
   if (nk > 0) load_x(kofs(0));
-  if (nk > 1) load_a_stage<TRANS>(p, i0, kofs(1), kend, tid, raB);
+  if (nk > 1) load_a_stage<TRANS, true>(p, i0, kofs(1), kend, tid, raB);
   if (nk > 0) store_stage(0, raA);
   __syncthreads();
   for (int64_t kt = 0; kt < nk; kt += 2) {
     // stage kt in buffer 0; stage kt + 1 in flight in raB
     if (kt + 1 < nk) load_x(kofs(kt + 1));
-    if (kt + 2 < nk) load_a_stage<TRANS>(p, i0, kofs(kt + 2), kend, tid, raA);
+    if (kt + 2 < nk) load_a_stage<TRANS, true>(p, i0, kofs(kt + 2), kend, tid, raA);
     compute(0);
     if (kt + 1 < nk) store_stage(1, raB);
     __syncthreads();
     if (kt + 1 >= nk) break;
     // stage kt + 1 in buffer 1; stage kt + 2 in flight in raA
     if (kt + 2 < nk) load_x(kofs(kt + 2));
-    if (kt + 3 < nk) load_a_stage<TRANS>(p, i0, kofs(kt + 3), kend, tid, raB);
+    if (kt + 3 < nk) load_a_stage<TRANS, true>(p, i0, kofs(kt + 3), kend, tid, raB);
     compute(1);
     if (kt + 2 < nk) store_stage(0, raA);
     __syncthreads();
