@@ -19,6 +19,8 @@
 // latency), then written to LDS: FP32 as is, BF16 split into a_hi = rn(a),
 // a_lo = rn(a - a_hi) with K contiguous per row (for A^T the 4 x 4 register
 // block is transposed first).  LDS is double-buffered: one barrier per stage.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace rsvd {
@@ -154,6 +156,24 @@ __device__ inline void load_a_stage(const GemmParams& p, int64_t i0, int64_t k0,
   }
 }
 
+// A stage known to lie inside the matrix with 16-byte aligned runs: plain
+// 16-byte loads (the same runs as load_a_stage).
+template <bool TRANS>
+__device__ inline void load_a_full(const GemmParams& p, int64_t i0, int64_t k0, int tid, f32x4 (&ra)[8]) {
+  const float* A = (const float*)p.A;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    int64_t off;
+    if (!TRANS) {
+      off = (i0 + (tid >> 3) + 16 * q) * p.lda + k0 + 4 * (tid & 7);
+    } else {
+      const int b = q >> 2, r = q & 3;
+      off = (k0 + 4 * (tid >> 5) + 16 * b + r) * p.lda + i0 + 4 * (tid & 31);
+    }
+    ra[q] = *reinterpret_cast<const f32x4*>(A + off);
+  }
+}
+
 // ---- BF16 / bf16x3 ------------------------------------------------------
 // MFMA v_mfma_f32_32x32x16_bf16: lane (r = lane % 32, g = lane / 32) supplies
 // A[r][8 g + t] and B[8 g + t][r], t = 0..7; result register e holds
@@ -189,19 +209,21 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
   // of the stage after it, so writing a stage to LDS waits only for its own loads.
   f32x4 raA[8], raB[8];
   u32x4 rxh[4], rxl[4];
-  auto load_x = [&](int64_t k0) __attribute__((always_inline)) {
+  // F (a std::integral_constant): every stage full and all 128 columns of X
+  // present, so the per-run guards are compiled out of the steady-state loop.
+  auto load_x = [&](int64_t k0, auto F) __attribute__((always_inline)) {
     const u32x4* gh = reinterpret_cast<const u32x4*>(xh + (k0 >> 5) * (int64_t)p.Lp * 32);
     const u32x4* gl = reinterpret_cast<const u32x4*>(xl + (k0 >> 5) * (int64_t)p.Lp * 32);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int run = tid + STHREADS * q;
-      if (run < NT * 128) {
+      if (decltype(F)::value || run < NT * 128) {
         rxh[q] = gh[run];
         if (NP == 3) rxl[q] = gl[run];
       }
     }
   };
-  auto store_stage = [&](int buf, const f32x4 (&ra)[8]) __attribute__((always_inline)) {
+  auto store_stage = [&](int buf, const f32x4 (&ra)[8], auto F) __attribute__((always_inline)) {
     // A: split and write K-contiguous rows
     if (!TRANS) {
 #pragma unroll
@@ -232,7 +254,7 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int run = tid + STHREADS * q;
-      if (run < NT * 128) {
+      if (decltype(F)::value || run < NT * 128) {
         const int c = run >> 2, part = run & 3;
         *reinterpret_cast<u32x4*>(&sXh[buf][c * BPAD + 8 * part]) = rxh[q];
         if (NP == 3) *reinterpret_cast<u32x4*>(&sXl[buf][c * BPAD + 8 * part]) = rxl[q];
@@ -240,7 +262,7 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
     }
   };
   const int r = lane & 31, g = lane >> 5;
-  auto compute = [&](int buf) __attribute__((always_inline)) {
+  auto compute = [&](int buf, auto F) __attribute__((always_inline)) {
 #pragma unroll
     for (int ks = 0; ks < SBK / 16; ++ks) {
       const int kb = 16 * ks + 8 * g;
@@ -253,7 +275,7 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        if (t < NT) {
+        if (decltype(F)::value || t < NT) {
           const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sXh[buf][(t * 32 + r) * BPAD + kb]);
           bf16x8 bl;
           if (NP == 3) bl = *reinterpret_cast<const bf16x8*>(&sXl[buf][(t * 32 + r) * BPAD + kb]);
@@ -271,24 +293,44 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
   };
   auto kofs = [&](int64_t stage) { return kbeg + stage * SBK; };
 
+  const std::false_type G{};
+  const std::true_type F{};
   if (nk > 0) load_a_stage<TRANS, true>(p, i0, kofs(0), kend, tid, raA);
-  if (nk > 0) load_x(kofs(0));
+  if (nk > 0) load_x(kofs(0), G);
   if (nk > 1) load_a_stage<TRANS, true>(p, i0, kofs(1), kend, tid, raB);
-  if (nk > 0) store_stage(0, raA);
+  if (nk > 0) store_stage(0, raA, G);
   __syncthreads();
-  for (int64_t kt = 0; kt < nk; kt += 2) {
+  int64_t kt = 0;
+  // Steady state: two stages per iteration with no branch between a stage's
+  // products and the next stage's split-and-store, so the compiler can
+  // interleave the VALU work with the MFMAs.
+  if (NT == 4 && p.vec != 0 && i0 + SBM <= p.rows && (kend - kbeg) % SBK == 0) {
+    for (; kt + 3 < nk; kt += 2) {
+      load_x(kofs(kt + 1), F);
+      load_a_full<TRANS>(p, i0, kofs(kt + 2), tid, raA);
+      compute(0, F);
+      store_stage(1, raB, F);
+      __syncthreads();
+      load_x(kofs(kt + 2), F);
+      load_a_full<TRANS>(p, i0, kofs(kt + 3), tid, raB);
+      compute(1, F);
+      store_stage(0, raA, F);
+      __syncthreads();
+    }
+  }
+  for (; kt < nk; kt += 2) {
     // stage kt in buffer 0; stage kt + 1 in flight in raB
-    if (kt + 1 < nk) load_x(kofs(kt + 1));
+    if (kt + 1 < nk) load_x(kofs(kt + 1), G);
     if (kt + 2 < nk) load_a_stage<TRANS, true>(p, i0, kofs(kt + 2), kend, tid, raA);
-    compute(0);
-    if (kt + 1 < nk) store_stage(1, raB);
+    compute(0, G);
+    if (kt + 1 < nk) store_stage(1, raB, G);
     __syncthreads();
     if (kt + 1 >= nk) break;
     // stage kt + 1 in buffer 1; stage kt + 2 in flight in raA
-    if (kt + 2 < nk) load_x(kofs(kt + 2));
+    if (kt + 2 < nk) load_x(kofs(kt + 2), G);
     if (kt + 3 < nk) load_a_stage<TRANS, true>(p, i0, kofs(kt + 3), kend, tid, raB);
-    compute(1);
-    if (kt + 2 < nk) store_stage(0, raA);
+    compute(1, G);
+    if (kt + 2 < nk) store_stage(0, raA, G);
     __syncthreads();
   }
 
