@@ -70,7 +70,7 @@ struct Plan {
   int esize;
   int dtype, prec;
   Split nn, tn;
-  size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rb, Rinv, RinvT, XU, XV, Uh, sig, flags, srft_d,
+  size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rb, RinvT, XU, XV, Uh, sig, flags, srft_d,
       srft_R, total;
 };
 
@@ -135,7 +135,6 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false) {
   P.R3 = take(ll8);
   P.Rt = take(ll8);
   P.Rb = take(ll8);
-  P.Rinv = take(ll8);
   P.RinvT = take((size_t)P.l * P.l * es);
   P.XU = take((size_t)P.l * P.k * es);
   P.XV = take((size_t)P.l * P.k * es);
@@ -378,7 +377,7 @@ rsvd_status chol(const Ctx& c, int64_t rows, double* R, bool want_inv, const int
   q.l = (int32_t)c.P.l;
   q.rows = rows;
   q.R = R;
-  q.Rinv = want_inv ? c.at<double>(c.P.Rinv) : nullptr;
+  q.Rinv = nullptr;  // only R^-1 in the element type (RinvT) is used downstream
   q.RinvT = want_inv ? c.at<void>(c.P.RinvT) : nullptr;
   q.dtype = c.P.dtype;
   q.shifted = shifted;

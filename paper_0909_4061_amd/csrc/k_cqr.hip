@@ -262,20 +262,7 @@ __device__ __forceinline__ void chol_body_t(const CholParams& p) {
   const int tc = tid & 127, tr = tid >> 7;  // 4 x 128 thread grid for whole-matrix loops
   const double eps = DBL_EPSILON;
 
-  // max diagonal (breakdown threshold) and trace (shift) of W, every wave for itself
-  double thresh, trace;
-  {
-    const double d0 = lane < l ? p.G[(int64_t)lane * (Lg + 1)] : 0.0;
-    const double d1 = lane + 64 < l ? p.G[(int64_t)(lane + 64) * (Lg + 1)] : 0.0;
-    double mx = fmax(d0, d1), trs = d0 + d1;
-    for (int off = 32; off > 0; off >>= 1) {
-      mx = fmax(mx, __shfl_xor(mx, off, 64));
-      trs += __shfl_xor(trs, off, 64);
-    }
-    thresh = (double)l * 16.0 * eps * mx;
-    trace = trs;
-  }
-
+  double thresh = 0.0, trace = 0.0;
   bool ok = false;
   for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
     // Shifted CholeskyQR: s = 11 (rows l + l (l + 1)) u ||Y||_F^2 with u the FP64 unit roundoff.
@@ -290,6 +277,19 @@ __device__ __forceinline__ void chol_body_t(const CholParams& p) {
         const int a = r0 + 8 * u;
         v[u] = (a < l && cp + 1 >= a && cp < l) ? *reinterpret_cast<const dbl2*>(p.G + (int64_t)a * Lg + cp)
                                                 : dbl2{0.0, 0.0};
+      }
+      if (attempt == 0) {
+        // max diagonal (breakdown threshold) and trace (shift) of W, every wave for
+        // itself, while the loads above are in flight
+        const double d0 = lane < l ? p.G[(int64_t)lane * (Lg + 1)] : 0.0;
+        const double d1 = lane + 64 < l ? p.G[(int64_t)(lane + 64) * (Lg + 1)] : 0.0;
+        double mx = fmax(d0, d1), trs = d0 + d1;
+        for (int off = 32; off > 0; off >>= 1) {
+          mx = fmax(mx, __shfl_xor(mx, off, 64));
+          trs += __shfl_xor(trs, off, 64);
+        }
+        thresh = (double)l * 16.0 * eps * mx;
+        trace = trs;
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
