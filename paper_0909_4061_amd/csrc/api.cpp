@@ -557,8 +557,10 @@ struct BwdLayout {
   int q;
   int64_t Kc;  // (2q + 2) l
   size_t Qs, Qts, Rs, Rts, Bt, gBt, gQ, gQt, gYt, T1, T2, Mq, Z, W1, M1p64, UhT, Rinv, Sy, W64, SW64, M2_64, Ukt64,
-      M1p, W, SW, M2, Ukt, Sk, Left, RightT, total;
+      M1p, W, SW, M2, Ukt, Sk, Left, RightT, part, total;
 };
+
+constexpr int64_t kBwdMaxSplit = 16;  // K chunks of the adjoint's transposed products
 
 BwdLayout bwd_layout(const rsvd_problem* pr) {
   BwdLayout L{};
@@ -605,6 +607,7 @@ BwdLayout bwd_layout(const rsvd_problem* pr) {
   L.Sk = take((size_t)P.k * es);
   L.Left = take((size_t)(P.m * L.Kc) * es);
   L.RightT = take((size_t)(L.Kc * P.n) * es);
+  L.part = take((size_t)kBwdMaxSplit * P.l * 128 * es);  // split-K partials, rows <= l, Lp <= 128
   L.total = off;
   return L;
 }
@@ -616,14 +619,37 @@ rsvd_status copy2d(const Ctx& c, const void* src, int sdt, int64_t lds, void* ds
   return RSVD_OK;
 }
 
+// out (rows x ncols, ldo) = A^T X for the adjoint's products with few output rows
+// (rows <= l) and a long contraction K: the K range is split over up to
+// kBwdMaxSplit workgroups and the partial products summed in a fixed order.
+rsvd_status gemm_tn_splitk(const Ctx& c, const BwdLayout& L, const void* A, int64_t lda, int64_t rows, int64_t K,
+                           const void* X, int64_t ldx, int32_t ncols, void* out, int64_t ldo) {
+  const GemmTile t = gemm_tile(c.P.dtype, RSVD_NATIVE);
+  Split sp = choose_split(rows, K, t);
+  if (sp.S > kBwdMaxSplit) sp = Split{(int32_t)kBwdMaxSplit, round_up(ceil_div(K, kBwdMaxSplit), t.bk)};
+  if (sp.S == 1) return gemm(c, RSVD_NATIVE, true, A, lda, rows, K, X, ldx, ncols, out, ldo, sp, nullptr, nullptr);
+  void* part = c.at<void>(L.part);
+  rsvd_status s = gemm(c, RSVD_NATIVE, true, A, lda, rows, K, X, ldx, ncols, out, ldo, sp, part, nullptr);
+  if (s != RSVD_OK) return s;
+  GramParams g{};
+  g.part = part;
+  g.S = sp.S;
+  g.Lp = (int32_t)round_up(ncols, t.lp_mult);
+  g.yout = out;
+  g.ldy = ldo;
+  g.rows = rows;
+  g.l = ncols;
+  RSVD_TRY(c.run->sum_parts(c.P.dtype, g));
+  return RSVD_OK;
+}
+
 // out (rows x l, ldo) = gY for Y = Qj R (rows x l): gY = (gQ + Q sym(-gQ^T Q)) R^-T.
 rsvd_status qr_adjoint(const Ctx& c, const BwdLayout& L, const void* Qj, const double* Rj, const void* gQ,
                        int64_t rows, void* out, int64_t ldo) {
   const Plan& P = c.P;
   const int64_t l = P.l;
   const int dt = P.dtype;
-  rsvd_status s = gemm(c, RSVD_NATIVE, true, Qj, l, l, rows, gQ, l, (int32_t)l, c.at<void>(L.Mq), l,
-                       no_split(rows), nullptr, nullptr);  // M = Qj^T gQ
+  rsvd_status s = gemm_tn_splitk(c, L, Qj, l, l, rows, gQ, l, (int32_t)l, c.at<void>(L.Mq), l);  // M = Qj^T gQ
   if (s != RSVD_OK) return s;
   RSVD_TRY(launch_qr_adj_sym(c.at<void>(L.Mq), dt, (int32_t)l, c.at<double>(L.Sy), c.st));
   RSVD_TRY(launch_tri_inv_upper(Rj, c.at<double>(L.Rinv), (int32_t)l, c.st));
@@ -694,11 +720,8 @@ rsvd_status backward_steps(const Ctx& c, const BwdLayout& L, const rsvd_problem*
   if (s != RSVD_OK) return s;
 
   // --- SVD of B and B = Q^T A: gBt = Bt M1 + gV M2, gQ = A gBt + gU U~_k^T
-  s = gemm(c, RSVD_NATIVE, true, Bt, l, l, n, gV, k, (int32_t)k, c.at<void>(L.T1), k, no_split(n), nullptr,
-           nullptr);  // T1 = B gV
-  if (s == RSVD_OK)
-    s = gemm(c, RSVD_NATIVE, true, Qb(L.q), l, l, m, gU, k, (int32_t)k, c.at<void>(L.T2), k, no_split(m), nullptr,
-             nullptr);  // T2 = Q^T gU
+  s = gemm_tn_splitk(c, L, Bt, l, l, n, gV, k, (int32_t)k, c.at<void>(L.T1), k);  // T1 = B gV
+  if (s == RSVD_OK) s = gemm_tn_splitk(c, L, Qb(L.q), l, l, m, gU, k, (int32_t)k, c.at<void>(L.T2), k);  // T2 = Q^T gU
   if (s != RSVD_OK) return s;
   SvdAdjParams sa{};
   sa.Uh = c.at<double>(P.Uh);

@@ -74,18 +74,120 @@ __global__ __launch_bounds__(256) void qr_adj_sym_kernel(const void* M, int dtyp
   S[e] = -ld_elem(M, dtype, (int64_t)a * l + b);
 }
 
-// Rinv = R^-1 for upper triangular R (l x l): thread j solves R x = e_j by
-// back substitution (x_i = 0 below the diagonal).
-__global__ __launch_bounds__(128) void tri_inv_upper_kernel(const double* __restrict__ R, double* __restrict__ Rinv,
+// Rinv = R^-1 for upper triangular R (l x l <= 128 x 128), one workgroup of
+// 256 threads, R in LDS.  X = R^-1 by doubling: every 16 x 16 diagonal block
+// is inverted at once (one wave per block, lane c solving R_bb x = e_c from the
+// bottom), then for s = 16, 32, 64 each aligned pair of inverted blocks [A C]
+// is joined, X_AC = -X_AA (R_AC X_CC): an item is (pair, 8 rows of A) per
+// wave, one column of C per lane.  X[r][c] (r < c) is kept at M[c * LDC + r],
+// X[c][c] = 1 / R_cc in a vector; rows and columns past l up to a multiple of
+// 16 are zeros.
+__global__ __launch_bounds__(256) void tri_inv_upper_kernel(const double* __restrict__ R, double* __restrict__ Rinv,
                                                             int32_t l) {
-  const int j = threadIdx.x;
-  if (j >= l) return;
-  for (int i = l - 1; i > j; --i) Rinv[(int64_t)i * l + j] = 0.0;
-  for (int i = j; i >= 0; --i) {
-    double acc = i == j ? 1.0 : 0.0;
-    for (int t = i + 1; t <= j; ++t) acc -= R[(int64_t)i * l + t] * Rinv[(int64_t)t * l + j];
-    Rinv[(int64_t)i * l + j] = acc / R[(int64_t)i * l + i];
+  constexpr int NW = 4, B = 16, RG = 8, LDC = 129;  // odd stride: column walks hit distinct banks
+  __shared__ double M[128 * LDC];
+  __shared__ double rinv_d[128];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lp = (l + B - 1) & ~(B - 1);
+  const int tc = tid & 127, tr = tid >> 7;  // 2 x 128 thread grid for whole-matrix loops
+  if (tc < lp)
+    for (int a = tr; a < lp; a += 2) M[a * LDC + tc] = (a < l && tc < l && tc >= a) ? R[(int64_t)a * l + tc] : 0.0;
+  if (tid < 128) rinv_d[tid] = tid < l ? 1.0 / R[(int64_t)tid * l + tid] : 0.0;
+  __syncthreads();
+  // diagonal blocks
+  for (int b = wave; b < lp / B; b += NW) {
+    const int b0 = b * B;
+    double acc[B], x[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int t = B - 1; t >= 0; --t) {
+      const double rt = rinv_d[b0 + t];
+      x[t] = t == lane ? rt : (t < lane ? -acc[t] * rt : 0.0);
+#pragma unroll
+      for (int i = 0; i < t; ++i) acc[i] = fma(M[(b0 + i) * LDC + b0 + t], x[t], acc[i]);
+    }
+    if (lane < B && b0 + lane < l) {
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+        if (i < lane) M[(b0 + lane) * LDC + b0 + i] = x[i];
+    }
   }
+  __syncthreads();
+  // joining pairs: A = [a1 - s, a1) (full), C = [a1, ce) (s columns, the last pair
+  // possibly fewer); npair * s / 8 <= 8 items per level for l <= 128, two per wave.
+  // Every T of a level is formed before any X_AC, which reads T rows of the other
+  // items of its pair.
+  constexpr int IPW = 2;  // items per wave
+  for (int s = B; s < l; s *= 2) {
+    const int npair = (l - s + 2 * s - 1) / (2 * s);
+    const int nrg = s / RG, items = npair * nrg;
+    int r0[IPW], c[IPW], a1[IPW];
+    bool work[IPW];
+#pragma unroll
+    for (int j = 0; j < IPW; ++j) {
+      const int it = wave + NW * j;
+      const int pair = it / nrg, rg = it - pair * nrg;
+      a1[j] = 2 * s * pair + s;
+      const int ce = min(a1[j] + s, l);
+      r0[j] = a1[j] - s + RG * rg;
+      c[j] = a1[j] + lane;
+      work[j] = it < items && lane < s && c[j] < ce;
+    }
+    // T = R_AC X_CC: T[r][c] = sum_{t = a1..c} R[r][t] X[t][c], stored in the X_AC slots
+#pragma unroll
+    for (int j = 0; j < IPW; ++j) {
+      if (work[j]) {
+        double acc[RG] = {};
+        for (int t = a1[j]; t < c[j]; ++t) {
+          const double bv = M[c[j] * LDC + t];
+#pragma unroll
+          for (int i = 0; i < RG; ++i) acc[i] = fma(M[(r0[j] + i) * LDC + t], bv, acc[i]);
+        }
+        const double bv = rinv_d[c[j]];
+#pragma unroll
+        for (int i = 0; i < RG; ++i) {
+          acc[i] = fma(M[(r0[j] + i) * LDC + c[j]], bv, acc[i]);
+          M[c[j] * LDC + r0[j] + i] = acc[i];
+        }
+      }
+    }
+    __syncthreads();
+    // X_AC = -X_AA T: X[r][c] = -sum_{u = r..a1-1} X[r][u] T[u][c]
+    double accx[IPW][RG];
+#pragma unroll
+    for (int j = 0; j < IPW; ++j) {
+#pragma unroll
+      for (int i = 0; i < RG; ++i) accx[j][i] = 0.0;
+      if (work[j]) {
+#pragma unroll
+        for (int uu = 0; uu < RG; ++uu) {
+          const int u = r0[j] + uu;
+          const double bv = M[c[j] * LDC + u];
+#pragma unroll
+          for (int i = 0; i < RG; ++i) {
+            const double av = uu > i ? M[u * LDC + r0[j] + i] : (uu == i ? rinv_d[u] : 0.0);
+            accx[j][i] = fma(av, bv, accx[j][i]);
+          }
+        }
+        for (int u = r0[j] + RG; u < a1[j]; ++u) {
+          const double bv = M[c[j] * LDC + u];
+#pragma unroll
+          for (int i = 0; i < RG; ++i) accx[j][i] = fma(M[u * LDC + r0[j] + i], bv, accx[j][i]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPW; ++j)
+      if (work[j])
+#pragma unroll
+        for (int i = 0; i < RG; ++i) M[c[j] * LDC + r0[j] + i] = -accx[j][i];
+    __syncthreads();
+  }
+  if (tc < l)
+    for (int a = tr; a < l; a += 2)
+      Rinv[(int64_t)a * l + tc] = tc > a ? M[tc * LDC + a] : (tc == a ? rinv_d[a] : 0.0);
 }
 
 // dst (rows x cols, or cols x rows when transposed) <- src (rows x cols),
@@ -138,7 +240,7 @@ hipError_t launch_qr_adj_sym(const void* M, int dtype, int32_t l, double* S, hip
 
 hipError_t launch_tri_inv_upper(const double* R, double* Rinv, int32_t l, hipStream_t st) {
   if (l < 1 || l > 128) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(tri_inv_upper_kernel, dim3(1), dim3(128), 0, st, R, Rinv, l);
+  hipLaunchKernelGGL(tri_inv_upper_kernel, dim3(1), dim3(256), 0, st, R, Rinv, l);
   return hipGetLastError();
 }
 

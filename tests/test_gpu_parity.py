@@ -57,9 +57,13 @@ def test_omega_fp32_matches_oracle():
     assert len(mism) <= 4
 
 
+# The Gram of one call is split into row chunks x groups of 16 x 16 tiles: (40000, 100) uses
+# 512-row chunks (8 stages) and three tile groups with a 64-row last chunk; (20001, 64) uses
+# 128-row chunks, one tile group and a 33-row last chunk.
 @pytest.mark.parametrize("dtype,rows,l", [(torch.float64, 2000, 30), (torch.float32, 5000, 120),
                                           (torch.float32, 333, 45), (torch.float64, 129, 128),
-                                          (torch.float32, 64, 1)])
+                                          (torch.float32, 64, 1), (torch.float32, 40000, 100),
+                                          (torch.float32, 20001, 64)])
 def test_cholesky_qr2_matches_householder(dtype, rows, l):
     rng = np.random.default_rng(rows + l)
     Y64 = rng.standard_normal((rows, l)) @ np.diag(np.linspace(1.0, 0.05, l))
