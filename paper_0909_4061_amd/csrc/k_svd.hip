@@ -16,10 +16,11 @@
 // sweep with no rotation.  The squared column norms are formed exactly in the
 // first round of every sweep and carried through its other rounds (a rotation
 // changes them by -t c_i . c_j and +t c_i . c_j), so a round forms one dot
-// product per pair instead of three.  The round's fixed cost (three reductions, the
-// rotation angle) is paid once per wave, so fewer lanes per pair (more rows
-// per lane) make a round cheaper; the kernel is compiled for l <= 64 and
-// l <= 128 so that small matrices keep their LDS footprint small.
+// product per pair instead of three.  The round's fixed cost (the reduction,
+// the rotation angle) is paid once per wave, so fewer lanes per pair (more rows
+// per lane) make a round cheaper.  The kernel is compiled for l <= 32, 64, 96
+// and 128: a smaller variant holds fewer rows per lane (rows past l are zeros
+// but still cost work) and less LDS (more workgroups per CU in a batch).
 #include <float.h>
 
 #include "common.hpp"
@@ -252,24 +253,30 @@ __global__ __launch_bounds__(2 * MAXL) void jacobi_batched(const JacobiParams* _
 
 }  // namespace
 
-int jacobi_variant(int32_t l) { return l <= 64 ? 64 : 128; }
+int jacobi_variant(int32_t l) { return l <= 32 ? 32 : (l <= 64 ? 64 : (l <= 96 ? 96 : 128)); }
 
 hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st) {
   if (p.l < 1 || p.l > 128 || p.k < 1 || p.k > p.l) return hipErrorInvalidValue;
-  if (jacobi_variant(p.l) == 64)
-    hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(128), 0, st, p);
-  else
-    hipLaunchKernelGGL(jacobi_kernel<128>, dim3(1), dim3(256), 0, st, p);
+  switch (jacobi_variant(p.l)) {
+    case 32: hipLaunchKernelGGL(jacobi_kernel<32>, dim3(1), dim3(64), 0, st, p); break;
+    case 64: hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(128), 0, st, p); break;
+    case 96: hipLaunchKernelGGL(jacobi_kernel<96>, dim3(1), dim3(192), 0, st, p); break;
+    default: hipLaunchKernelGGL(jacobi_kernel<128>, dim3(1), dim3(256), 0, st, p); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_jacobi_batched(int variant, const JacobiParams* ps, const BlockMap* bm, int64_t nblocks,
                                  hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  if (variant == 64)
-    hipLaunchKernelGGL(jacobi_batched<64>, dim3((unsigned)nblocks), dim3(128), 0, st, ps, bm);
-  else
-    hipLaunchKernelGGL(jacobi_batched<128>, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  const dim3 grid((unsigned)nblocks);
+  switch (variant) {
+    case 32: hipLaunchKernelGGL(jacobi_batched<32>, grid, dim3(64), 0, st, ps, bm); break;
+    case 64: hipLaunchKernelGGL(jacobi_batched<64>, grid, dim3(128), 0, st, ps, bm); break;
+    case 96: hipLaunchKernelGGL(jacobi_batched<96>, grid, dim3(192), 0, st, ps, bm); break;
+    case 128: hipLaunchKernelGGL(jacobi_batched<128>, grid, dim3(256), 0, st, ps, bm); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -96,8 +96,9 @@ def test_c1_fp64_end_to_end():
     assert sigma[k + p] * (1 - 1e-9) <= r["res_q"] <= evaluate.cor10_9_bound(sigma, k, p)
 
 
+# l = k + p spans every compiled Jacobi size: 30 (<= 32), 45 (<= 64), 80 (<= 96), 128.
 @pytest.mark.parametrize("m,n,k,p,q", [(2048, 1024, 20, 10, 2), (1000, 333, 30, 15, 1), (300, 257, 1, 0, 0),
-                                       (130, 128, 100, 28, 1)])
+                                       (130, 128, 100, 28, 1), (1500, 700, 70, 10, 1)])
 def test_fp32_power_iteration_parity(m, n, k, p, q):
     sigma = spectrum("inv", min(m, n))
     A32 = build_matrix(m, n, sigma, seed=m + n, dtype=np.float32)
