@@ -351,14 +351,26 @@ def main_differentiable(args):
     print(f"# built {count} matrices on the GPU in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     prec = args.only or "bf16x3"
 
+    # The matrices are independent: matrix i runs (forward, loss, adjoint) on stream i mod S, so the
+    # latency-bound small steps of different matrices overlap (autograd runs each backward op on the
+    # stream of its forward op; workspaces come from the allocator of the current stream).
+    nstreams = max(1, args.diff_streams)
+    streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
+
     def step():
+        cur = torch.cuda.current_stream(dev)
+        for s_ in streams:
+            s_.wait_stream(cur)
         grads = []
         for i in range(count):
-            A = As[i].detach().requires_grad_(True)
-            U, S, V = rs.rsvd(A, k, p, q, seed=args.seed, stream_id=i, prec=prec)
-            L = ((U * S[None, :]) @ V.T - Ts[i]).square().sum() + (ws_[i] * S).sum()
-            L.backward()
-            grads.append(A.grad)
+            with torch.cuda.stream(streams[i % nstreams]):
+                A = As[i].detach().requires_grad_(True)
+                U, S, V = rs.rsvd(A, k, p, q, seed=args.seed, stream_id=i, prec=prec)
+                L = ((U * S[None, :]) @ V.T - Ts[i]).square().sum() + (ws_[i] * S).sum()
+                L.backward()
+                grads.append(A.grad)
+        for s_ in streams:
+            cur.wait_stream(s_)
         return grads
 
     for _ in range(args.warmup):
@@ -387,7 +399,7 @@ def main_differentiable(args):
         "vs_baseline": None, "dtype": "bf16" if prec == "bf16x3" else "f32", "prec": prec, "data": "synthetic",
         "config": {"workload": f"differentiable rSVD, {count} x FP32 {m}x{n}, sigma_j=j^-1/2, k={k}, p={p}, q={q}, "
                                "forward + loss + hand-written adjoint per matrix",
-                   "count": count, "m": m, "n": n, "k": k, "p": p, "q": q},
+                   "count": count, "m": m, "n": n, "k": k, "p": p, "q": q, "streams": nstreams},
         "hbm_gbs": hbm / (ms / 1e3) / 1e9, "ms_per_matrix": ms / count, "mean_grad_norm": gnorm,
     }
     print(json.dumps(line))
@@ -479,6 +491,8 @@ def main():
                     help="construct: A = U diag(1/j) V^T (the workload); randn: i.i.d. Gaussian A of the "
                          "same shape, for hardware-counter runs only (byte counts do not depend on values)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched workload")
+    ap.add_argument("--diff-streams", type=int, default=8,
+                    help="streams the differentiable workload's independent matrices are spread over")
     ap.add_argument("--batch-diff", type=int, default=32, help="matrices in the differentiable workload")
     ap.add_argument("--workload", choices=["power", "srft", "batched", "differentiable"], default="power",
                     help="power: the power-iteration rSVD (default); srft: SRFT vs Gaussian sketch, "
