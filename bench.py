@@ -351,13 +351,33 @@ def main_differentiable(args):
     print(f"# built {count} matrices on the GPU in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     prec = args.only or "bf16x3"
 
-    # The matrices are independent: matrix i runs (forward, loss, adjoint) on stream i mod S, so the
-    # latency-bound small steps of different matrices overlap (autograd runs each backward op on the
-    # stream of its forward op; workspaces come from the allocator of the current stream).
+    # batched (default): one rsvd_batched call for all matrices, one stacked loss, and one
+    # rsvd_backward_batched call from autograd -- every step of the forward and of the adjoint is one
+    # launch over all matrices, replayed from a graph.
+    # streams: matrix i runs (forward, loss, adjoint) alone on stream i mod S, so the latency-bound
+    # small steps of different matrices overlap (autograd runs each backward op on the stream of its
+    # forward op; workspaces come from the allocator of the current stream).
     nstreams = max(1, args.diff_streams)
-    streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)] if args.diff_mode == "streams" else []
+    T3 = torch.stack(Ts) if args.diff_mode == "batched" else None
+    W3 = torch.stack(ws_) if args.diff_mode == "batched" else None
+    if T3 is not None:
+        del Ts[:]
+
+    def step_batched():
+        leaves = [A.detach().requires_grad_(True) for A in As]
+        outs = rs.rsvd_batched(leaves, k, p=p, q=q, seed=args.seed, prec=prec)
+        U3 = torch.stack([o[0] for o in outs])
+        S3 = torch.stack([o[1] for o in outs])
+        V3 = torch.stack([o[2] for o in outs])
+        R = torch.bmm(U3 * S3[:, None, :], V3.transpose(1, 2).contiguous()) - T3
+        L = R.square().sum() + (W3 * S3).sum()
+        L.backward()
+        return [x.grad for x in leaves]
 
     def step():
+        if args.diff_mode == "batched":
+            return step_batched()
         cur = torch.cuda.current_stream(dev)
         for s_ in streams:
             s_.wait_stream(cur)
@@ -399,7 +419,8 @@ def main_differentiable(args):
         "vs_baseline": None, "dtype": "bf16" if prec == "bf16x3" else "f32", "prec": prec, "data": "synthetic",
         "config": {"workload": f"differentiable rSVD, {count} x FP32 {m}x{n}, sigma_j=j^-1/2, k={k}, p={p}, q={q}, "
                                "forward + loss + hand-written adjoint per matrix",
-                   "count": count, "m": m, "n": n, "k": k, "p": p, "q": q, "streams": nstreams},
+                   "count": count, "m": m, "n": n, "k": k, "p": p, "q": q, "mode": args.diff_mode,
+                   **({"streams": nstreams} if args.diff_mode == "streams" else {})},
         "hbm_gbs": hbm / (ms / 1e3) / 1e9, "ms_per_matrix": ms / count, "mean_grad_norm": gnorm,
     }
     print(json.dumps(line))
@@ -491,6 +512,9 @@ def main():
                     help="construct: A = U diag(1/j) V^T (the workload); randn: i.i.d. Gaussian A of the "
                          "same shape, for hardware-counter runs only (byte counts do not depend on values)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched workload")
+    ap.add_argument("--diff-mode", choices=("batched", "streams"), default="batched",
+                    help="differentiable workload: one batched forward and adjoint, or one call per matrix "
+                         "over concurrent streams")
     ap.add_argument("--diff-streams", type=int, default=8,
                     help="streams the differentiable workload's independent matrices are spread over")
     ap.add_argument("--batch-diff", type=int, default=32, help="matrices in the differentiable workload")

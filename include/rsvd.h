@@ -35,8 +35,9 @@
  *    a hipStream_t (NULL = the default stream) on which every kernel of the
  *    call is enqueued; calls return without synchronizing.
  *  * Ownership: the caller owns every buffer.  The library never allocates or
- *    frees memory in these calls (rsvd_batched excepted: its first call for a
- *    new batch allocates the batch's launch tables, owned by the handle);
+ *    frees memory in these calls (rsvd_batched and rsvd_backward_batched
+ *    excepted: the first call for a new batch allocates the batch's launch
+ *    tables, owned by the handle);
  *    scratch space is the caller's workspace `ws` of at least
  *    rsvd_workspace_bytes(problem) bytes, 256-byte aligned.  Its
  *    contents are undefined between calls (except as noted for rsvd_project ->
@@ -212,15 +213,35 @@ size_t rsvd_batched_workspace_bytes(int32_t count, const rsvd_problem* problems)
  * U[i] m x k, S[i] k, V[i] n x k, with the layouts of rsvd_svd.  Each step of
  * the sequence is one launch over all problems (the products stream A without
  * a split of K), so the batch fills the GPU where a single small problem
- * cannot.  The first call for a given (problems, A, U, S, V, ws) records the
- * launch sequence, uploads its parameter tables to device memory owned by the
- * handle and captures the launches in a HIP graph; later calls with the same
- * arguments replay the graph (the handle keeps the four most recent batches,
- * freed by rsvd_destroy).  Results are those of the single-problem calls up to
- * the rounding of the K reduction order. */
+ * cannot.  The first call for given (problems, ws) records the launch
+ * sequence, uploads its parameter tables to device memory owned by the handle
+ * and captures the launches in a HIP graph; later calls with the same problems
+ * and workspace replay the graph.  When only the buffers A, U, S, V differ from
+ * the previous call, the sequence is recorded again on the host and its
+ * parameter tables are uploaded on `stream` (from pinned host memory owned by
+ * the handle) before the replay.  The handle keeps the eight most recent
+ * batches, freed by rsvd_destroy.  Results are those of the single-problem
+ * calls up to the rounding of the K reduction order. */
 rsvd_status rsvd_batched(rsvd_handle handle, int32_t count, const rsvd_problem* problems,
                          const void* const* A, void* const* U, void* const* S,
                          void* const* V, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes rsvd_backward_batched needs for `count` problems (0 if any
+ * problem is invalid, uses the SRFT sketch, or the batch is not supported). */
+size_t rsvd_backward_batched_workspace_bytes(int32_t count, const rsvd_problem* problems);
+
+/* rsvd_backward for `count` independent problems (the adjoint of rsvd_batched
+ * with the same problems): problems[i] (HOST array) as for rsvd_batched, and
+ * A, gU, gS, gV, gA HOST arrays of `count` DEVICE pointers with the layouts
+ * of rsvd_backward (gA[i] is m x n, leading dimension n).  Each step of the
+ * recomputed forward and of the adjoint is one launch over all problems,
+ * replayed from a HIP graph as for rsvd_batched (same plan cache, same
+ * re-pointing when only the buffers moved).  gA[i] equals rsvd_backward's
+ * for problem i up to the rounding of the K reduction order. */
+rsvd_status rsvd_backward_batched(rsvd_handle handle, int32_t count, const rsvd_problem* problems,
+                                  const void* const* A, const void* const* gU, const void* const* gS,
+                                  const void* const* gV, void* const* gA, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
 
 /* --- Diagnostics ------------------------------------------------------- */
 

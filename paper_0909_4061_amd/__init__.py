@@ -268,19 +268,11 @@ class BatchWorkspace:
         return ctypes.c_void_p(self.buf.data_ptr())
 
 
-def rsvd_batched(As, ks, p=8, q=1, *, prec="native", seed=0, stream_id=0, outs=None, ws=None):
-    """Randomized SVDs of many independent matrices in one batched call.
-
-    As: list of 2-D CUDA tensors (same dtype), ks: target ranks (int or list).
-    Matrix i draws its test matrix from (seed, stream_id + i).  Returns a list
-    of (U, S, V).  `outs` (a previous return value) and `ws` (a BatchWorkspace)
-    may be passed back to reuse buffers, which lets the library replay its
-    recorded graph.
-    """
+def _batch_problems(As, ks, p, q, prec, seed, stream_id):
     count = len(As)
-    if count == 0:
-        return []
     ks = [int(ks)] * count if isinstance(ks, int) else [int(k) for k in ks]
+    if len(ks) != count:
+        raise ValueError("one rank per matrix")
     dev = As[0].device
     probs = []
     for i, (A, k) in enumerate(zip(As, ks)):
@@ -290,20 +282,121 @@ def rsvd_batched(As, ks, p=8, q=1, *, prec="native", seed=0, stream_id=0, outs=N
         m, n = A.shape
         probs.append(problem(m, n, k, p, q, dtype=A.dtype, prec=prec, seed=seed, stream_id=stream_id + i,
                              lda=A.stride(0)))
+    return ks, probs
+
+
+def _ptrs(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+# Workspaces of the differentiable batched calls, one per (call kind, problems,
+# stream): calls on one stream are ordered, so they may share it, and a stable
+# workspace lets the library replay its recorded graph.
+_BATCH_WS = {}
+
+
+def _batch_ws(kind, probs, dev, nbytes_fn):
+    key = (kind, dev, torch.cuda.current_stream(dev).cuda_stream,
+           tuple(bytes(memoryview(pr)) for pr in probs))
+    ws = _BATCH_WS.get(key)
+    if ws is None:
+        arr = (RsvdProblem * len(probs))(*probs)
+        nbytes = nbytes_fn(len(probs), arr)
+        if nbytes == 0:
+            raise RsvdError(_lib.RSVD_E_INVAL, f"{kind} workspace")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _BATCH_WS[key] = ws
+    return ws
+
+
+def rsvd_batched(As, ks, p=8, q=1, *, prec="native", seed=0, stream_id=0, outs=None, ws=None):
+    """Randomized SVDs of many independent matrices in one batched call.
+
+    As: list of 2-D CUDA tensors (same dtype), ks: target ranks (int or list).
+    Matrix i draws its test matrix from (seed, stream_id + i).  Returns a list
+    of (U, S, V).  `outs` (a previous return value) and `ws` (a BatchWorkspace)
+    may be passed back to reuse buffers, which lets the library replay its
+    recorded graph without re-pointing it.  When any matrix requires grad (and
+    grad mode is on) the result is differentiable through
+    RSVDBatchedFunction, whose backward is rsvd_backward_batched.
+    """
+    count = len(As)
+    if count == 0:
+        return []
+    if torch.is_grad_enabled() and any(A.requires_grad for A in As):
+        flat = RSVDBatchedFunction.apply((ks, p, q, prec, seed, stream_id), *As)
+        return [tuple(flat[3 * i:3 * i + 3]) for i in range(count)]
+    ks, probs = _batch_problems(As, ks, p, q, prec, seed, stream_id)
+    dev = As[0].device
     if outs is None:
         outs = [(torch.empty(A.shape[0], k, dtype=A.dtype, device=dev), torch.empty(k, dtype=A.dtype, device=dev),
                  torch.empty(A.shape[1], k, dtype=A.dtype, device=dev)) for A, k in zip(As, ks)]
     ws = ws or BatchWorkspace(probs, dev)
     arr = (RsvdProblem * count)(*probs)
-    VP = ctypes.c_void_p * count
-    a_p = VP(*[A.data_ptr() for A in As])
-    u_p = VP(*[o[0].data_ptr() for o in outs])
-    s_p = VP(*[o[1].data_ptr() for o in outs])
-    v_p = VP(*[o[2].data_ptr() for o in outs])
     h = handle(dev)
-    _lib.check(h.lib.rsvd_batched(h.ptr, count, arr, a_p, u_p, s_p, v_p, ws.ptr, ws.nbytes, _stream(dev)),
-               "rsvd_batched")
+    _lib.check(h.lib.rsvd_batched(h.ptr, count, arr, _ptrs(As), _ptrs([o[0] for o in outs]),
+                                  _ptrs([o[1] for o in outs]), _ptrs([o[2] for o in outs]), ws.ptr, ws.nbytes,
+                                  _stream(dev)), "rsvd_batched")
     return outs
+
+
+def rsvd_backward_batched(As, gUs, gSs, gVs, ks, p, q, *, prec="native", seed=0, stream_id=0, gAs=None, ws=None):
+    """gA_i = the adjoint of A_i -> (U_i, S_i, V_i) applied to (gU_i, gS_i, gV_i) for every
+    matrix of a batch (fixed test matrices, matrix i drawing from (seed, stream_id + i))."""
+    count = len(As)
+    if count == 0:
+        return []
+    ks, probs = _batch_problems(As, ks, p, q, prec, seed, stream_id)
+    dev = As[0].device
+    h = handle(dev)
+    if ws is None:
+        ws = _batch_ws("backward", probs, dev, h.lib.rsvd_backward_batched_workspace_bytes)
+    gUs, gSs, gVs = ([t.detach().to(As[0].dtype).contiguous() for t in ts] for ts in (gUs, gSs, gVs))
+    if gAs is None:
+        gAs = [torch.empty(A.shape, dtype=A.dtype, device=dev) for A in As]
+    arr = (RsvdProblem * count)(*probs)
+    _lib.check(h.lib.rsvd_backward_batched(h.ptr, count, arr, _ptrs(As), _ptrs(gUs), _ptrs(gSs), _ptrs(gVs),
+                                           _ptrs(gAs), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)),
+               "rsvd_backward_batched")
+    return gAs
+
+
+class RSVDBatchedFunction(torch.autograd.Function):
+    """Flat (U_0, S_0, V_0, U_1, ...) = rsvd_batched(As) with rsvd_backward_batched as backward."""
+
+    @staticmethod
+    def forward(ctx, cfg, *As):
+        ks, p, q, prec, seed, stream_id = cfg
+        Ad = [A.detach() for A in As]
+        dev = Ad[0].device
+        ks_, probs = _batch_problems(Ad, ks, p, q, prec, seed, stream_id)
+        h = handle(dev)
+        ws = _batch_ws("forward", probs, dev, h.lib.rsvd_batched_workspace_bytes)
+        outs = [(torch.empty(A.shape[0], k, dtype=A.dtype, device=dev), torch.empty(k, dtype=A.dtype, device=dev),
+                 torch.empty(A.shape[1], k, dtype=A.dtype, device=dev)) for A, k in zip(Ad, ks_)]
+        arr = (RsvdProblem * len(Ad))(*probs)
+        _lib.check(h.lib.rsvd_batched(h.ptr, len(Ad), arr, _ptrs(Ad), _ptrs([o[0] for o in outs]),
+                                      _ptrs([o[1] for o in outs]), _ptrs([o[2] for o in outs]),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)), "rsvd_batched")
+        ctx.save_for_backward(*Ad)
+        ctx.cfg = (ks_, p, q, prec, seed, stream_id)
+        return tuple(t for o in outs for t in o)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        As = ctx.saved_tensors
+        ks, p, q, prec, seed, stream_id = ctx.cfg
+        gUs, gSs, gVs = [], [], []
+        for i, (A, k) in enumerate(zip(As, ks)):
+            m, n = A.shape
+            gU, gS, gV = grads[3 * i:3 * i + 3]
+            z = lambda shape: torch.zeros(shape, dtype=A.dtype, device=A.device)
+            gUs.append(z((m, k)) if gU is None else gU)
+            gSs.append(z((k,)) if gS is None else gS)
+            gVs.append(z((n, k)) if gV is None else gV)
+        gAs = rsvd_backward_batched([A.contiguous() for A in As], gUs, gSs, gVs, ks, p, q, prec=prec, seed=seed,
+                                    stream_id=stream_id)
+        return (None, *gAs)
 
 
 def rsvd_draw_omega(n, k, p, *, dtype=torch.float32, seed=0, stream_id=0, device="cuda"):

@@ -39,7 +39,7 @@ namespace {
 using namespace rsvd;
 
 constexpr size_t kAlign = 256;
-constexpr size_t kMaxPlans = 4;
+constexpr size_t kMaxPlans = 8;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -180,6 +180,11 @@ class Runner {
   virtual hipError_t fill(const FillParams& p) = 0;
   virtual hipError_t trmm(const TrmmParams& p) = 0;
   virtual hipError_t copy(const CopyParams& p) = 0;
+  // adjoint pieces
+  virtual hipError_t svd_adj_coef(const SvdAdjParams& p) = 0;
+  virtual hipError_t qr_adj_sym(const QrSymParams& p) = 0;
+  virtual hipError_t tri_inv(const TriInvParams& p) = 0;
+  virtual hipError_t copy2d(const Copy2dParams& p) = 0;
 };
 
 // Launches at once on a stream (timed when the handle's timing is on).
@@ -217,6 +222,10 @@ class DirectRunner final : public Runner {
   hipError_t fill(const FillParams& p) override { return launch_fill_i32(p.p, p.v, p.count, st_); }
   hipError_t trmm(const TrmmParams& p) override { return launch_trmm_upper(p.R2, p.R1, p.R, p.l, p.gate, st_); }
   hipError_t copy(const CopyParams& p) override { return launch_copy_f64(p.src, p.dst, p.count, p.gate, st_); }
+  hipError_t svd_adj_coef(const SvdAdjParams& p) override { return launch_svd_adj_coef(p, st_); }
+  hipError_t qr_adj_sym(const QrSymParams& p) override { return launch_qr_adj_sym(p, st_); }
+  hipError_t tri_inv(const TriInvParams& p) override { return launch_tri_inv_upper(p, st_); }
+  hipError_t copy2d(const Copy2dParams& p) override { return launch_copy2d(p, st_); }
 
  private:
   rsvd_handle h_;
@@ -225,7 +234,10 @@ class DirectRunner final : public Runner {
 
 // One step of a batched plan: the same kernel family and variant for every
 // problem, with the problems' parameter blocks side by side.
-enum SlotKind { SK_GEMM, SK_GRAM_PARTIAL, SK_GRAM_REDUCE, SK_CHOL, SK_JACOBI, SK_OMEGA, SK_FILL, SK_TRMM, SK_COPY };
+enum SlotKind {
+  SK_GEMM, SK_GRAM_PARTIAL, SK_GRAM_REDUCE, SK_CHOL, SK_JACOBI, SK_OMEGA, SK_FILL, SK_TRMM, SK_COPY,
+  SK_SUM_PARTS, SK_SVD_ADJ, SK_QR_SYM, SK_TRI_INV, SK_COPY2D
+};
 
 struct Slot {
   SlotKind kind;
@@ -249,8 +261,10 @@ class RecordRunner final : public Runner {
   hipError_t gram_partial(int dtype, const GramParams& p) override {
     return add(SK_GRAM_PARTIAL, dtype, 0, false, p, p.rows > 0 ? gram_partial_blocks(p) : 0);
   }
-  // batched problems are never split along K, so there are no partials to sum
-  hipError_t sum_parts(int, const GramParams&) override { return hipErrorNotSupported; }
+  hipError_t sum_parts(int dtype, const GramParams& p) override {
+    if (p.rows > 0 && !sum_parts_ok(dtype, p)) return hipErrorInvalidValue;
+    return add(SK_SUM_PARTS, dtype, 0, false, p, sum_parts_blocks(dtype, p));
+  }
   hipError_t gram_reduce(const GramReduceParams& p) override {
     return add(SK_GRAM_REDUCE, 0, 0, false, p, gram_reduce_blocks(p));
   }
@@ -265,6 +279,18 @@ class RecordRunner final : public Runner {
   hipError_t copy(const CopyParams& p) override {
     return add(SK_COPY, 0, 0, false, p, p.count > 0 ? copy_blocks(p) : 0);
   }
+  hipError_t svd_adj_coef(const SvdAdjParams& p) override {
+    if (!svd_adj_coef_ok(p)) return hipErrorInvalidValue;
+    return add(SK_SVD_ADJ, 0, 0, false, p, svd_adj_coef_blocks(p));
+  }
+  hipError_t qr_adj_sym(const QrSymParams& p) override {
+    return add(SK_QR_SYM, 0, 0, false, p, qr_adj_sym_blocks(p));
+  }
+  hipError_t tri_inv(const TriInvParams& p) override {
+    if (!tri_inv_ok(p)) return hipErrorInvalidValue;
+    return add(SK_TRI_INV, 0, 0, false, p, 1);
+  }
+  hipError_t copy2d(const Copy2dParams& p) override { return add(SK_COPY2D, 0, 0, false, p, copy2d_blocks(p)); }
 
  private:
   template <typename P>
@@ -555,19 +581,21 @@ rsvd_status svd_steps(const Ctx& c, const void* Bt, const void* Q, void* U, void
 struct BwdLayout {
   Plan P;
   int q;
-  int64_t Kc;  // (2q + 2) l
+  int64_t Kc;         // (2q + 2) l
+  int64_t gA_chunks;  // 128-column launches of gA = Left RightT (a batch pads to its widest problem)
   size_t Qs, Qts, Rs, Rts, Bt, gBt, gQ, gQt, gYt, T1, T2, Mq, Z, W1, M1p64, UhT, Rinv, Sy, W64, SW64, M2_64, Ukt64,
       M1p, W, SW, M2, Ukt, Sk, Left, RightT, part, total;
 };
 
 constexpr int64_t kBwdMaxSplit = 16;  // K chunks of the adjoint's transposed products
 
-BwdLayout bwd_layout(const rsvd_problem* pr) {
+BwdLayout bwd_layout(const rsvd_problem* pr, bool batched = false) {
   BwdLayout L{};
-  L.P = make_plan(pr);
+  L.P = make_plan(pr, batched);
   const Plan& P = L.P;
   L.q = pr->q;
   L.Kc = (int64_t)(2 * pr->q + 2) * P.l;
+  L.gA_chunks = ceil_div(P.n, 128);
   const size_t es = (size_t)P.esize, ml = (size_t)(P.m * P.l) * es, nl = (size_t)(P.n * P.l) * es;
   const size_t ll8 = (size_t)(P.l * P.l) * 8, lle = (size_t)(P.l * P.l) * es;
   const size_t lk8 = (size_t)(P.l * P.k) * 8, lke = (size_t)(P.l * P.k) * es;
@@ -615,7 +643,7 @@ BwdLayout bwd_layout(const rsvd_problem* pr) {
 rsvd_status copy2d(const Ctx& c, const void* src, int sdt, int64_t lds, void* dst, int ddt, int64_t ldd, int64_t rows,
                    int64_t cols, bool trans) {
   const Copy2dParams p{src, sdt, lds, dst, ddt, ldd, rows, cols, trans ? 1 : 0};
-  RSVD_TRY(launch_copy2d(p, c.st));
+  RSVD_TRY(c.run->copy2d(p));
   return RSVD_OK;
 }
 
@@ -627,8 +655,7 @@ rsvd_status gemm_tn_splitk(const Ctx& c, const BwdLayout& L, const void* A, int6
   const GemmTile t = gemm_tile(c.P.dtype, RSVD_NATIVE);
   Split sp = choose_split(rows, K, t);
   if (sp.S > kBwdMaxSplit) sp = Split{(int32_t)kBwdMaxSplit, round_up(ceil_div(K, kBwdMaxSplit), t.bk)};
-  if (sp.S == 1) return gemm(c, RSVD_NATIVE, true, A, lda, rows, K, X, ldx, ncols, out, ldo, sp, nullptr, nullptr);
-  void* part = c.at<void>(L.part);
+  void* part = sp.S > 1 ? c.at<void>(L.part) : nullptr;
   rsvd_status s = gemm(c, RSVD_NATIVE, true, A, lda, rows, K, X, ldx, ncols, out, ldo, sp, part, nullptr);
   if (s != RSVD_OK) return s;
   GramParams g{};
@@ -637,9 +664,9 @@ rsvd_status gemm_tn_splitk(const Ctx& c, const BwdLayout& L, const void* A, int6
   g.Lp = (int32_t)round_up(ncols, t.lp_mult);
   g.yout = out;
   g.ldy = ldo;
-  g.rows = rows;
+  g.rows = sp.S > 1 ? rows : 0;  // a recorded problem without a split still takes the (empty) step
   g.l = ncols;
-  RSVD_TRY(c.run->sum_parts(c.P.dtype, g));
+  if (sp.S > 1 || c.run->records()) RSVD_TRY(c.run->sum_parts(c.P.dtype, g));
   return RSVD_OK;
 }
 
@@ -651,8 +678,8 @@ rsvd_status qr_adjoint(const Ctx& c, const BwdLayout& L, const void* Qj, const d
   const int dt = P.dtype;
   rsvd_status s = gemm_tn_splitk(c, L, Qj, l, l, rows, gQ, l, (int32_t)l, c.at<void>(L.Mq), l);  // M = Qj^T gQ
   if (s != RSVD_OK) return s;
-  RSVD_TRY(launch_qr_adj_sym(c.at<void>(L.Mq), dt, (int32_t)l, c.at<double>(L.Sy), c.st));
-  RSVD_TRY(launch_tri_inv_upper(Rj, c.at<double>(L.Rinv), (int32_t)l, c.st));
+  RSVD_TRY(c.run->qr_adj_sym(QrSymParams{c.at<void>(L.Mq), dt, (int32_t)l, c.at<double>(L.Sy)}));
+  RSVD_TRY(c.run->tri_inv(TriInvParams{Rj, c.at<double>(L.Rinv), (int32_t)l}));
   s = copy2d(c, c.at<double>(L.Rinv), RSVD_F64, l, c.at<double>(L.W64), RSVD_F64, l, l, l, true);  // R^-T
   if (s != RSVD_OK) return s;
   const Plan p64 = [&] {
@@ -735,7 +762,7 @@ rsvd_status backward_steps(const Ctx& c, const BwdLayout& L, const rsvd_problem*
   sa.Z = c.at<double>(L.Z);
   sa.M2 = c.at<double>(L.M2_64);
   sa.Ukt = c.at<double>(L.Ukt64);
-  RSVD_TRY(launch_svd_adj_coef(sa, c.st));
+  RSVD_TRY(c.run->svd_adj_coef(sa));
   Plan p64 = P;
   p64.dtype = RSVD_F64;
   p64.esize = 8;
@@ -787,9 +814,11 @@ rsvd_status backward_steps(const Ctx& c, const BwdLayout& L, const rsvd_problem*
   if (s != RSVD_OK) return s;
 
   // --- gA = Left RightT, 128 columns at a time
-  for (int64_t c0 = 0; c0 < n; c0 += 128) {
-    const int32_t nc = (int32_t)std::min<int64_t>(128, n - c0);
-    s = gemm(c, pr->prec, false, left, Kc, m, Kc, rightT + (size_t)c0 * es, n, nc,
+  for (int64_t ch = 0; ch < L.gA_chunks; ++ch) {
+    const int64_t c0 = std::min<int64_t>(ch * 128, n - 1);
+    const int32_t nc = (int32_t)std::max<int64_t>(1, std::min<int64_t>(128, n - ch * 128));
+    const int64_t rows = ch * 128 < n ? m : 0;  // chunks past a narrower problem's n launch nothing
+    s = gemm(c, pr->prec, false, left, Kc, rows, Kc, rightT + (size_t)c0 * es, n, nc,
              static_cast<char*>(gA) + (size_t)c0 * es, n, no_split(Kc), nullptr, nullptr);
     if (s != RSVD_OK) return s;
   }
@@ -859,11 +888,34 @@ rsvd_status batch_layout(int32_t count, const rsvd_problem* probs, BatchLayout& 
 namespace {
 
 // A recorded batch: its identity, the device tables and the replayable graph.
+// The tables hold every slot's parameter blocks first, then every slot's block
+// map.  Only the parameter blocks hold caller pointers, so a batch whose
+// problems and workspace are unchanged but whose caller buffers moved is
+// re-pointed by uploading new parameter blocks (from pinned staging memory, on
+// the caller's stream); the block maps and the graph stay.
+enum BatchKind { BATCH_FORWARD = 0, BATCH_BACKWARD = 1 };
+
+struct SlotShape {
+  int kind, dtype, prec, trans;
+  size_t pbytes;
+  int64_t nblk;
+  bool operator==(const SlotShape& o) const {
+    return kind == o.kind && dtype == o.dtype && prec == o.prec && trans == o.trans && pbytes == o.pbytes &&
+           nblk == o.nblk;
+  }
+};
+
 struct BatchPlan {
+  int kind = BATCH_FORWARD;
   std::vector<rsvd_problem> probs;
-  std::vector<const void*> ptrs;  // A, U, S, V of every problem
+  std::vector<const void*> ptrs;  // the caller buffers of every problem
   void* ws = nullptr;
-  void* tables = nullptr;         // device: parameter blocks and block maps of every slot
+  std::vector<SlotShape> shape;
+  size_t pbytes = 0;                // parameter blocks: tables[0, pbytes)
+  void* tables = nullptr;           // device
+  void* stage = nullptr;            // pinned host: parameter blocks of the last upload
+  hipEvent_t staged = nullptr;      // the last upload from `stage` is complete
+  hipEvent_t done = nullptr;        // the last replay is complete
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -873,51 +925,104 @@ void free_plan(BatchPlan* bp) {
   if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
   if (bp->graph) (void)hipGraphDestroy(bp->graph);
   if (bp->tables) (void)hipFree(bp->tables);
+  if (bp->stage) (void)hipHostFree(bp->stage);
+  if (bp->staged) (void)hipEventDestroy(bp->staged);
+  if (bp->done) (void)hipEventDestroy(bp->done);
   delete bp;
 }
 
-bool same_batch(const BatchPlan& bp, int32_t count, const rsvd_problem* probs, const std::vector<const void*>& ptrs,
-                void* ws) {
-  return bp.ws == ws && (int32_t)bp.probs.size() == count && bp.ptrs == ptrs &&
-         std::memcmp(bp.probs.data(), probs, sizeof(rsvd_problem) * (size_t)count) == 0;
+// Records one problem's kernel sequence on the given runner.
+using Recorder = rsvd_status (*)(const void* ctx, int32_t i, Runner& run);
+
+// The recorded launches of a batch and where they go in the tables.
+struct Recorded {
+  std::vector<Slot> slots;
+  std::vector<SlotShape> shape;
+  std::vector<size_t> poff, boff;
+  size_t pbytes = 0, bytes = 0;
+};
+
+rsvd_status record_batch(int32_t count, int32_t lmax, Recorder rec, const void* ctx, Recorded& R) {
+  for (int32_t i = 0; i < count; ++i) {
+    RecordRunner rr(R.slots);
+    rr.jacobi_maxl_ = jacobi_variant(lmax);
+    const rsvd_status s = rec(ctx, i, rr);
+    if (s != RSVD_OK) return s == RSVD_E_DEVICE ? RSVD_E_INVAL : s;
+    if (rr.cursor() != R.slots.size()) return RSVD_E_INVAL;
+  }
+  size_t bytes = 0;
+  for (const Slot& sl : R.slots) {
+    int64_t nb = 0;
+    for (int64_t b : sl.blocks) nb += b;
+    if (nb > INT32_MAX) return RSVD_E_UNSUPPORTED;
+    R.shape.push_back(SlotShape{(int)sl.kind, sl.dtype, sl.prec, sl.trans ? 1 : 0, sl.params.size(), nb});
+    R.poff.push_back(bytes);
+    bytes = align_up(bytes + sl.params.size());
+  }
+  R.pbytes = bytes;
+  for (const SlotShape& sh : R.shape) {
+    R.boff.push_back(bytes);
+    bytes = align_up(bytes + (size_t)sh.nblk * sizeof(BlockMap));
+  }
+  R.bytes = bytes;
+  return RSVD_OK;
+}
+
+void write_params(const Recorded& R, char* dst) {
+  for (size_t s = 0; s < R.slots.size(); ++s)
+    std::memcpy(dst + R.poff[s], R.slots[s].params.data(), R.slots[s].params.size());
 }
 
 // Launch every slot of a recorded batch on `st` from the device tables.
-hipError_t launch_slots(const std::vector<Slot>& slots, const std::vector<size_t>& poff,
-                        const std::vector<size_t>& boff, const std::vector<int64_t>& nblk, const char* dev,
-                        hipStream_t st) {
-  for (size_t s = 0; s < slots.size(); ++s) {
-    const Slot& sl = slots[s];
-    const void* ps = dev + poff[s];
-    const BlockMap* bm = reinterpret_cast<const BlockMap*>(dev + boff[s]);
+hipError_t launch_slots(const Recorded& R, const char* dev, hipStream_t st) {
+  for (size_t s = 0; s < R.slots.size(); ++s) {
+    const Slot& sl = R.slots[s];
+    const void* ps = dev + R.poff[s];
+    const BlockMap* bm = reinterpret_cast<const BlockMap*>(dev + R.boff[s]);
+    const int64_t nb = R.shape[s].nblk;
     hipError_t e = hipSuccess;
     switch (sl.kind) {
       case SK_GEMM:
-        e = launch_gemm_batched(sl.dtype, sl.prec, sl.trans, (const GemmParams*)ps, bm, nblk[s], st);
+        e = launch_gemm_batched(sl.dtype, sl.prec, sl.trans, (const GemmParams*)ps, bm, nb, st);
         break;
       case SK_GRAM_PARTIAL:
-        e = launch_gram_partial_batched(sl.dtype, (const GramParams*)ps, bm, nblk[s], st);
+        e = launch_gram_partial_batched(sl.dtype, (const GramParams*)ps, bm, nb, st);
         break;
       case SK_GRAM_REDUCE:
-        e = launch_gram_reduce_batched((const GramReduceParams*)ps, bm, nblk[s], st);
+        e = launch_gram_reduce_batched((const GramReduceParams*)ps, bm, nb, st);
         break;
       case SK_CHOL:
-        e = launch_chol_batched((const CholParams*)ps, bm, nblk[s], st);
+        e = launch_chol_batched((const CholParams*)ps, bm, nb, st);
         break;
       case SK_JACOBI:
-        e = launch_jacobi_batched(sl.prec, (const JacobiParams*)ps, bm, nblk[s], st);
+        e = launch_jacobi_batched(sl.prec, (const JacobiParams*)ps, bm, nb, st);
         break;
       case SK_OMEGA:
-        e = launch_omega_batched(sl.dtype, (const OmegaParams*)ps, bm, nblk[s], st);
+        e = launch_omega_batched(sl.dtype, (const OmegaParams*)ps, bm, nb, st);
         break;
       case SK_FILL:
-        e = launch_fill_batched((const FillParams*)ps, bm, nblk[s], st);
+        e = launch_fill_batched((const FillParams*)ps, bm, nb, st);
         break;
       case SK_TRMM:
-        e = launch_trmm_batched((const TrmmParams*)ps, bm, nblk[s], st);
+        e = launch_trmm_batched((const TrmmParams*)ps, bm, nb, st);
         break;
       case SK_COPY:
-        e = launch_copy_batched((const CopyParams*)ps, bm, nblk[s], st);
+        e = launch_copy_batched((const CopyParams*)ps, bm, nb, st);
+        break;
+      case SK_SUM_PARTS:
+        e = launch_sum_parts_batched(sl.dtype, (const GramParams*)ps, bm, nb, st);
+        break;
+      case SK_SVD_ADJ:
+        e = launch_svd_adj_coef_batched((const SvdAdjParams*)ps, bm, nb, st);
+        break;
+      case SK_QR_SYM:
+        e = launch_qr_adj_sym_batched((const QrSymParams*)ps, bm, nb, st);
+        break;
+      case SK_TRI_INV:
+        e = launch_tri_inv_upper_batched((const TriInvParams*)ps, bm, nb, st);
+        break;
+      case SK_COPY2D:
+        e = launch_copy2d_batched((const Copy2dParams*)ps, bm, nb, st);
         break;
     }
     if (e != hipSuccess) return e;
@@ -925,64 +1030,32 @@ hipError_t launch_slots(const std::vector<Slot>& slots, const std::vector<size_t
   return hipSuccess;
 }
 
-// Record the batch, upload its tables and capture its launches in a graph.
-rsvd_status build_plan(rsvd_handle h, int32_t count, const rsvd_problem* probs, const void* const* A,
-                       void* const* U, void* const* S, void* const* V, void* ws, const BatchLayout& L,
-                       BatchPlan*& out) {
-  std::vector<Slot> slots;
-  int32_t lmax = 1;
-  for (int32_t i = 0; i < count; ++i) lmax = std::max<int32_t>(lmax, probs[i].k + probs[i].p);
-  for (int32_t i = 0; i < count; ++i) {
-    RecordRunner rr(slots);
-    rr.jacobi_maxl_ = jacobi_variant(lmax);
-    const Plan& P = L.plans[(size_t)i];
-    char* base = static_cast<char*>(ws);
-    const Ctx c{P, base + L.base[(size_t)i], nullptr, h->status, nullptr, &rr};
-    void* Q = base + L.q_off[(size_t)i];
-    void* Bt = base + L.bt_off[(size_t)i];
-    rsvd_status s = range_finder_steps(c, &probs[i], A[i], Q);
-    if (s == RSVD_OK) s = power_steps(c, &probs[i], A[i], Q);
-    if (s == RSVD_OK) s = project_steps(c, &probs[i], A[i], Q, Bt);
-    if (s == RSVD_OK) s = svd_steps(c, Bt, Q, U[i], S[i], V[i]);
-    if (s != RSVD_OK) return s == RSVD_E_DEVICE ? RSVD_E_INVAL : s;
-    if (rr.cursor() != slots.size()) return RSVD_E_INVAL;
-  }
-  // device tables: per slot the parameter blocks, then the block map
-  std::vector<size_t> poff, boff;
-  std::vector<int64_t> nblk;
-  size_t bytes = 0;
-  for (const Slot& sl : slots) {
-    poff.push_back(bytes);
-    bytes = align_up(bytes + sl.params.size());
-    int64_t nb = 0;
-    for (int64_t b : sl.blocks) nb += b;
-    if (nb > INT32_MAX) return RSVD_E_UNSUPPORTED;
-    nblk.push_back(nb);
-    boff.push_back(bytes);
-    bytes = align_up(bytes + (size_t)nb * sizeof(BlockMap));
-  }
-  std::vector<char> host(bytes, 0);
-  for (size_t s = 0; s < slots.size(); ++s) {
-    const Slot& sl = slots[s];
-    std::memcpy(host.data() + poff[s], sl.params.data(), sl.params.size());
-    BlockMap* bm = reinterpret_cast<BlockMap*>(host.data() + boff[s]);
+// Upload the tables of a recorded batch and capture its launches in a graph.
+rsvd_status build_plan(rsvd_handle h, int kind, int32_t count, const rsvd_problem* probs,
+                       const std::vector<const void*>& ptrs, void* ws, const Recorded& R, BatchPlan*& out) {
+  std::vector<char> host(R.bytes, 0);
+  write_params(R, host.data());
+  for (size_t s = 0; s < R.slots.size(); ++s) {
+    BlockMap* bm = reinterpret_cast<BlockMap*>(host.data() + R.boff[s]);
     int64_t k = 0;
+    const Slot& sl = R.slots[s];
     for (size_t i = 0; i < sl.blocks.size(); ++i)
       for (int64_t b = 0; b < sl.blocks[i]; ++b) bm[k++] = BlockMap{(int32_t)i, (int32_t)b};
   }
   BatchPlan* bp = new (std::nothrow) BatchPlan;
   if (!bp) return RSVD_E_DEVICE;
+  bp->kind = kind;
   bp->probs.assign(probs, probs + count);
-  for (int32_t i = 0; i < count; ++i) {
-    bp->ptrs.push_back(A[i]);
-    bp->ptrs.push_back(U[i]);
-    bp->ptrs.push_back(S[i]);
-    bp->ptrs.push_back(V[i]);
-  }
+  bp->ptrs = ptrs;
   bp->ws = ws;
+  bp->shape = R.shape;
+  bp->pbytes = R.pbytes;
   rsvd_status st = RSVD_OK;
-  if (hipMalloc(&bp->tables, std::max<size_t>(bytes, 1)) != hipSuccess ||
-      hipMemcpy(bp->tables, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+  if (hipMalloc(&bp->tables, std::max<size_t>(R.bytes, 1)) != hipSuccess ||
+      hipMemcpy(bp->tables, host.data(), R.bytes, hipMemcpyHostToDevice) != hipSuccess ||
+      hipHostMalloc(&bp->stage, std::max<size_t>(R.pbytes, 1), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&bp->staged, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&bp->done, hipEventDisableTiming) != hipSuccess)
     st = RSVD_E_DEVICE;
   if (st == RSVD_OK && !h->capture && hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess) {
     h->capture = nullptr;
@@ -992,7 +1065,7 @@ rsvd_status build_plan(rsvd_handle h, int32_t count, const rsvd_problem* probs, 
     if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       st = RSVD_E_DEVICE;
     } else {
-      const hipError_t le = launch_slots(slots, poff, boff, nblk, static_cast<const char*>(bp->tables), h->capture);
+      const hipError_t le = launch_slots(R, static_cast<const char*>(bp->tables), h->capture);
       const hipError_t ce = hipStreamEndCapture(h->capture, &bp->graph);
       if (le != hipSuccess || ce != hipSuccess ||
           hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0) != hipSuccess)
@@ -1005,6 +1078,145 @@ rsvd_status build_plan(rsvd_handle h, int32_t count, const rsvd_problem* probs, 
   }
   out = bp;
   return RSVD_OK;
+}
+
+// Point a plan at new caller buffers: the parameter blocks are rewritten into
+// the staging memory (once its previous upload is complete) and uploaded on
+// `stream` after the plan's previous replay.  False if the new recording does
+// not have the plan's launch structure.
+bool repoint_plan(BatchPlan* bp, const Recorded& R, const std::vector<const void*>& ptrs, hipStream_t stream) {
+  if (R.shape != bp->shape || R.pbytes != bp->pbytes) return false;
+  if (hipEventSynchronize(bp->staged) != hipSuccess) return false;
+  write_params(R, static_cast<char*>(bp->stage));
+  if (hipStreamWaitEvent(stream, bp->done, 0) != hipSuccess ||
+      hipMemcpyAsync(bp->tables, bp->stage, bp->pbytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipEventRecord(bp->staged, stream) != hipSuccess)
+    return false;
+  bp->ptrs = ptrs;
+  return true;
+}
+
+bool same_problems(const BatchPlan& bp, int kind, int32_t count, const rsvd_problem* probs, void* ws) {
+  return bp.kind == kind && bp.ws == ws && (int32_t)bp.probs.size() == count &&
+         std::memcmp(bp.probs.data(), probs, sizeof(rsvd_problem) * (size_t)count) == 0;
+}
+
+// Replay the batch (kind, problems, workspace, caller buffers) on `stream`,
+// recording it first if the handle holds no plan for it.
+rsvd_status run_batch(rsvd_handle h, int kind, int32_t count, const rsvd_problem* probs,
+                      const std::vector<const void*>& ptrs, void* ws, Recorder rec, const void* ctx,
+                      hipStream_t stream) {
+  int32_t lmax = 1;
+  for (int32_t i = 0; i < count; ++i) lmax = std::max<int32_t>(lmax, probs[i].k + probs[i].p);
+  BatchPlan* bp = nullptr;
+  size_t at = h->plans.size();
+  for (size_t i = 0; i < h->plans.size(); ++i) {
+    if (!same_problems(*h->plans[i], kind, count, probs, ws)) continue;
+    at = i;
+    if (h->plans[i]->ptrs == ptrs) break;
+  }
+  if (at < h->plans.size()) {
+    bp = h->plans[at];
+    h->plans.erase(h->plans.begin() + (std::ptrdiff_t)at);
+    if (bp->ptrs != ptrs) {
+      Recorded R;
+      const rsvd_status s = record_batch(count, lmax, rec, ctx, R);
+      if (s != RSVD_OK) {
+        h->plans.push_back(bp);
+        return s;
+      }
+      if (!repoint_plan(bp, R, ptrs, stream)) {
+        free_plan(bp);
+        bp = nullptr;
+        const rsvd_status b = build_plan(h, kind, count, probs, ptrs, ws, R, bp);
+        if (b != RSVD_OK) return b;
+      }
+    }
+  } else {
+    Recorded R;
+    rsvd_status s = record_batch(count, lmax, rec, ctx, R);
+    if (s == RSVD_OK) s = build_plan(h, kind, count, probs, ptrs, ws, R, bp);
+    if (s != RSVD_OK) return s;
+    if (h->plans.size() >= kMaxPlans) {
+      free_plan(h->plans.front());
+      h->plans.erase(h->plans.begin());
+    }
+  }
+  h->plans.push_back(bp);  // most recently used last
+  RSVD_TRY(hipGraphLaunch(bp->exec, stream));
+  RSVD_TRY(hipEventRecord(bp->done, stream));
+  return RSVD_OK;
+}
+
+// Forward batch: Q, Bt in the batch workspace, the problem's plan after them.
+struct ForwardBatch {
+  const BatchLayout* L;
+  const rsvd_problem* probs;
+  const void* const* A;
+  void* const *U, *const *S, *const *V;
+  char* ws;
+  int32_t* status;
+};
+
+rsvd_status record_forward(const void* ctx, int32_t i, Runner& run) {
+  const ForwardBatch& f = *static_cast<const ForwardBatch*>(ctx);
+  const size_t u = (size_t)i;
+  const Plan& P = f.L->plans[u];
+  const Ctx c{P, f.ws + f.L->base[u], nullptr, f.status, nullptr, &run};
+  void* Q = f.ws + f.L->q_off[u];
+  void* Bt = f.ws + f.L->bt_off[u];
+  const rsvd_problem* pr = &f.probs[u];
+  rsvd_status s = range_finder_steps(c, pr, f.A[u], Q);
+  if (s == RSVD_OK) s = power_steps(c, pr, f.A[u], Q);
+  if (s == RSVD_OK) s = project_steps(c, pr, f.A[u], Q, Bt);
+  if (s == RSVD_OK) s = svd_steps(c, Bt, Q, f.U[u], f.S[u], f.V[u]);
+  return s;
+}
+
+// Adjoint batch: each problem's adjoint workspace, one after the other.
+struct BackwardBatch {
+  std::vector<BwdLayout> L;
+  std::vector<size_t> base;
+  size_t total = 0;
+};
+
+rsvd_status backward_batch_layout(int32_t count, const rsvd_problem* probs, BackwardBatch& B) {
+  if (count < 1 || !probs) return RSVD_E_INVAL;
+  const rsvd_problem& p0 = probs[0];
+  for (int32_t i = 0; i < count; ++i) {
+    const rsvd_status v = validate(&probs[i]);
+    if (v != RSVD_OK) return v;
+    if (probs[i].dtype != p0.dtype || probs[i].prec != p0.prec || probs[i].q != p0.q) return RSVD_E_INVAL;
+    if (probs[i].sketch != RSVD_GAUSSIAN) return RSVD_E_UNSUPPORTED;
+  }
+  size_t off = 0;
+  int64_t chunks = 1;
+  for (int32_t i = 0; i < count; ++i) {
+    B.L.push_back(bwd_layout(&probs[i], true));
+    B.base.push_back(off);
+    off += align_up(B.L.back().total);
+    chunks = std::max(chunks, B.L.back().gA_chunks);
+  }
+  for (BwdLayout& L : B.L) L.gA_chunks = chunks;
+  B.total = off;
+  return RSVD_OK;
+}
+
+struct BackwardRecord {
+  const BackwardBatch* B;
+  const rsvd_problem* probs;
+  const void* const *A, *const *gU, *const *gS, *const *gV;
+  void* const* gA;
+  char* ws;
+  int32_t* status;
+};
+
+rsvd_status record_backward(const void* ctx, int32_t i, Runner& run) {
+  const BackwardRecord& b = *static_cast<const BackwardRecord*>(ctx);
+  const size_t u = (size_t)i;
+  const BwdLayout& L = b.B->L[u];
+  const Ctx c{L.P, b.ws + b.B->base[u], nullptr, b.status, nullptr, &run};
+  return backward_steps(c, L, &b.probs[u], b.A[u], b.gU[u], b.gS[u], b.gV[u], b.gA[u]);
 }
 
 }  // namespace
@@ -1189,32 +1401,35 @@ rsvd_status rsvd_batched(rsvd_handle h, int32_t count, const rsvd_problem* probs
   std::vector<const void*> ptrs;
   for (int32_t i = 0; i < count; ++i) {
     if (!A[i] || !U[i] || !S[i] || !V[i]) return RSVD_E_INVAL;
-    ptrs.push_back(A[i]);
-    ptrs.push_back(U[i]);
-    ptrs.push_back(S[i]);
-    ptrs.push_back(V[i]);
+    ptrs.insert(ptrs.end(), {A[i], U[i], S[i], V[i]});
   }
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
-  BatchPlan* bp = nullptr;
-  for (size_t i = 0; i < h->plans.size(); ++i) {
-    if (same_batch(*h->plans[i], count, probs, ptrs, ws)) {
-      bp = h->plans[i];
-      h->plans.erase(h->plans.begin() + (std::ptrdiff_t)i);
-      h->plans.push_back(bp);  // most recently used last
-      break;
-    }
+  const ForwardBatch f{&L, probs, A, U, S, V, static_cast<char*>(ws), h->status};
+  return run_batch(h, BATCH_FORWARD, count, probs, ptrs, ws, record_forward, &f, stream);
+}
+
+size_t rsvd_backward_batched_workspace_bytes(int32_t count, const rsvd_problem* probs) {
+  BackwardBatch B;
+  if (backward_batch_layout(count, probs, B) != RSVD_OK) return 0;
+  return B.total;
+}
+
+rsvd_status rsvd_backward_batched(rsvd_handle h, int32_t count, const rsvd_problem* probs, const void* const* A,
+                                  const void* const* gU, const void* const* gS, const void* const* gV,
+                                  void* const* gA, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!h || !A || !gU || !gS || !gV || !gA) return RSVD_E_INVAL;
+  BackwardBatch B;
+  const rsvd_status v = backward_batch_layout(count, probs, B);
+  if (v != RSVD_OK) return v;
+  if (!ws || ws_bytes < B.total || !aligned16(ws)) return RSVD_E_WORKSPACE;
+  std::vector<const void*> ptrs;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!A[i] || !gU[i] || !gS[i] || !gV[i] || !gA[i]) return RSVD_E_INVAL;
+    ptrs.insert(ptrs.end(), {A[i], gU[i], gS[i], gV[i], gA[i]});
   }
-  if (!bp) {
-    const rsvd_status s = build_plan(h, count, probs, A, U, S, V, ws, L, bp);
-    if (s != RSVD_OK) return s;
-    if (h->plans.size() >= kMaxPlans) {
-      free_plan(h->plans.front());
-      h->plans.erase(h->plans.begin());
-    }
-    h->plans.push_back(bp);
-  }
-  RSVD_TRY(hipGraphLaunch(bp->exec, stream));
-  return RSVD_OK;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
+  const BackwardRecord r{&B, probs, A, gU, gS, gV, gA, static_cast<char*>(ws), h->status};
+  return run_batch(h, BATCH_BACKWARD, count, probs, ptrs, ws, record_backward, &r, stream);
 }
 
 rsvd_status rsvd_draw_omega(rsvd_handle h, const rsvd_problem* pr, void* Omega, hipStream_t stream) {

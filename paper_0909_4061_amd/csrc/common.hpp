@@ -88,6 +88,8 @@ int64_t gram_geometry(int64_t rows, int32_t Lg, bool wide, int32_t* tgroups, int
 // yout (rows x l, leading dimension ldy) = sum over s of the S split-K partials
 // part[s] (rows x Lp), in the order s = 0, 1, ...
 hipError_t launch_sum_parts(int dtype, const GramParams& p, hipStream_t st);
+bool sum_parts_ok(int dtype, const GramParams& p);
+int64_t sum_parts_blocks(int dtype, const GramParams& p);
 
 hipError_t launch_gram_partial(int dtype, const GramParams& p, hipStream_t st);
 hipError_t launch_gram_reduce(const double* gpart, int64_t nblk, int32_t Lg, double* G,
@@ -208,6 +210,8 @@ hipError_t launch_omega_batched(int dtype, const OmegaParams* ps, const BlockMap
 hipError_t launch_fill_batched(const FillParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
 hipError_t launch_trmm_batched(const TrmmParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
 hipError_t launch_copy_batched(const CopyParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
+hipError_t launch_sum_parts_batched(int dtype, const GramParams* ps, const BlockMap* bm, int64_t nblocks,
+                                    hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Adjoint pieces (l x l algebra in FP64, strided copies).
@@ -232,10 +236,30 @@ struct Copy2dParams {
   int64_t rows, cols;  // of the source block
   int32_t trans;       // 1: dst = src^T
 };
+struct QrSymParams {  // S = sym(-M^T) (FP64, l x l) for M = Q^T gQ (element type)
+  const void* M;
+  int32_t dtype, l;
+  double* S;
+};
+struct TriInvParams {  // Rinv = R^-1, R upper triangular l x l (FP64), l <= 128
+  const double* R;
+  double* Rinv;
+  int32_t l;
+};
+int64_t svd_adj_coef_blocks(const SvdAdjParams& p);
+int64_t qr_adj_sym_blocks(const QrSymParams& p);
+int64_t copy2d_blocks(const Copy2dParams& p);
+bool svd_adj_coef_ok(const SvdAdjParams& p);
+bool tri_inv_ok(const TriInvParams& p);
 hipError_t launch_svd_adj_coef(const SvdAdjParams& p, hipStream_t st);
-hipError_t launch_qr_adj_sym(const void* M, int dtype, int32_t l, double* S, hipStream_t st);
-hipError_t launch_tri_inv_upper(const double* R, double* Rinv, int32_t l, hipStream_t st);
+hipError_t launch_qr_adj_sym(const QrSymParams& p, hipStream_t st);
+hipError_t launch_tri_inv_upper(const TriInvParams& p, hipStream_t st);
 hipError_t launch_copy2d(const Copy2dParams& p, hipStream_t st);
+hipError_t launch_svd_adj_coef_batched(const SvdAdjParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
+hipError_t launch_qr_adj_sym_batched(const QrSymParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
+hipError_t launch_tri_inv_upper_batched(const TriInvParams* ps, const BlockMap* bm, int64_t nblocks,
+                                        hipStream_t st);
+hipError_t launch_copy2d_batched(const Copy2dParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
 
 // Small utilities.
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, const int32_t* gate, hipStream_t st);

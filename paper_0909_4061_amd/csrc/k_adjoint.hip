@@ -33,9 +33,9 @@ __device__ __forceinline__ double ld_elem(const void* p, int dtype, int64_t i) {
   return dtype == RSVD_F64 ? ld_as_f64<double>(p, i) : ld_as_f64<float>(p, i);
 }
 
-__global__ __launch_bounds__(256) void svd_adj_coef_kernel(const SvdAdjParams p) {
+__device__ __forceinline__ void svd_adj_coef_body(const SvdAdjParams& p, const int bid) {
   const int l = p.l, k = p.k;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = (int64_t)bid * 256 + threadIdx.x;
   if (e >= (int64_t)l * l) return;
   const int i = (int)(e / l), j = (int)(e - (int64_t)i * l);
   const double si = p.sig[i], sj = p.sig[j];
@@ -65,13 +65,30 @@ __global__ __launch_bounds__(256) void svd_adj_coef_kernel(const SvdAdjParams p)
   }
 }
 
+__global__ __launch_bounds__(256) void svd_adj_coef_kernel(const SvdAdjParams p) { svd_adj_coef_body(p, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void svd_adj_coef_batched(const SvdAdjParams* __restrict__ ps,
+                                                            const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  svd_adj_coef_body(ps[b.item], b.local);
+}
+
 // S_ij = -M_{min(i,j), max(i,j)}: sym(-M^T) for M = Q^T gQ.
-__global__ __launch_bounds__(256) void qr_adj_sym_kernel(const void* M, int dtype, int32_t l, double* S) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void qr_adj_sym_body(const QrSymParams& p, const int bid) {
+  const int l = p.l;
+  const int64_t e = (int64_t)bid * 256 + threadIdx.x;
   if (e >= (int64_t)l * l) return;
   const int i = (int)(e / l), j = (int)(e - (int64_t)i * l);
   const int a = min(i, j), b = max(i, j);
-  S[e] = -ld_elem(M, dtype, (int64_t)a * l + b);
+  p.S[e] = -ld_elem(p.M, p.dtype, (int64_t)a * l + b);
+}
+
+__global__ __launch_bounds__(256) void qr_adj_sym_kernel(const QrSymParams p) { qr_adj_sym_body(p, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void qr_adj_sym_batched(const QrSymParams* __restrict__ ps,
+                                                          const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  qr_adj_sym_body(ps[b.item], b.local);
 }
 
 // Rinv = R^-1 for upper triangular R (l x l <= 128 x 128), one workgroup of
@@ -82,8 +99,10 @@ __global__ __launch_bounds__(256) void qr_adj_sym_kernel(const void* M, int dtyp
 // wave, one column of C per lane.  X[r][c] (r < c) is kept at M[c * LDC + r],
 // X[c][c] = 1 / R_cc in a vector; rows and columns past l up to a multiple of
 // 16 are zeros.
-__global__ __launch_bounds__(256) void tri_inv_upper_kernel(const double* __restrict__ R, double* __restrict__ Rinv,
-                                                            int32_t l) {
+__device__ __forceinline__ void tri_inv_upper_body(const TriInvParams& p) {
+  const double* __restrict__ R = p.R;
+  double* __restrict__ Rinv = p.Rinv;
+  const int l = p.l;
   constexpr int NW = 4, B = 16, RG = 8, LDC = 129;  // odd stride: column walks hit distinct banks
   __shared__ double M[128 * LDC];
   __shared__ double rinv_d[128];
@@ -190,11 +209,19 @@ __global__ __launch_bounds__(256) void tri_inv_upper_kernel(const double* __rest
       Rinv[(int64_t)a * l + tc] = tc > a ? M[tc * LDC + a] : (tc == a ? rinv_d[a] : 0.0);
 }
 
+__global__ __launch_bounds__(256) void tri_inv_upper_kernel(const TriInvParams p) { tri_inv_upper_body(p); }
+
+__global__ __launch_bounds__(256) void tri_inv_upper_batched(const TriInvParams* __restrict__ ps,
+                                                             const BlockMap* __restrict__ bm) {
+  tri_inv_upper_body(ps[bm[blockIdx.x].item]);
+}
+
 // dst (rows x cols, or cols x rows when transposed) <- src (rows x cols),
 // with a cast between FP32 and FP64.  32 x 32 tiles through LDS.
-__global__ __launch_bounds__(256) void copy2d_kernel(const Copy2dParams p) {
+__device__ __forceinline__ void copy2d_body(const Copy2dParams& p, const int bid) {
   __shared__ double tile[32][33];
-  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int gx = (int)((p.cols + 31) / 32);  // tiles across the source columns
+  const int64_t r0 = (int64_t)(bid / gx) * 32, c0 = (int64_t)(bid % gx) * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int rr = ty; rr < 32; rr += 8) {
     const int64_t r = r0 + rr, c = c0 + tx;
@@ -223,31 +250,71 @@ __global__ __launch_bounds__(256) void copy2d_kernel(const Copy2dParams p) {
   }
 }
 
+__global__ __launch_bounds__(256) void copy2d_kernel(const Copy2dParams p) { copy2d_body(p, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void copy2d_batched(const Copy2dParams* __restrict__ ps,
+                                                      const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  copy2d_body(ps[b.item], b.local);
+}
+
 }  // namespace
 
+int64_t svd_adj_coef_blocks(const SvdAdjParams& p) { return ((int64_t)p.l * p.l + 255) / 256; }
+int64_t qr_adj_sym_blocks(const QrSymParams& p) { return ((int64_t)p.l * p.l + 255) / 256; }
+int64_t copy2d_blocks(const Copy2dParams& p) {
+  return p.rows <= 0 || p.cols <= 0 ? 0 : ((p.cols + 31) / 32) * ((p.rows + 31) / 32);
+}
+bool svd_adj_coef_ok(const SvdAdjParams& p) { return p.l >= 1 && p.l <= RSVD_MAX_L && p.k >= 1 && p.k <= p.l; }
+bool tri_inv_ok(const TriInvParams& p) { return p.l >= 1 && p.l <= 128; }
+
 hipError_t launch_svd_adj_coef(const SvdAdjParams& p, hipStream_t st) {
-  if (p.l < 1 || p.l > RSVD_MAX_L || p.k < 1 || p.k > p.l) return hipErrorInvalidValue;
-  const int64_t n = (int64_t)p.l * p.l;
-  hipLaunchKernelGGL(svd_adj_coef_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p);
+  if (!svd_adj_coef_ok(p)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(svd_adj_coef_kernel, dim3((unsigned)svd_adj_coef_blocks(p)), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
-hipError_t launch_qr_adj_sym(const void* M, int dtype, int32_t l, double* S, hipStream_t st) {
-  const int64_t n = (int64_t)l * l;
-  hipLaunchKernelGGL(qr_adj_sym_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, dtype, l, S);
+hipError_t launch_qr_adj_sym(const QrSymParams& p, hipStream_t st) {
+  hipLaunchKernelGGL(qr_adj_sym_kernel, dim3((unsigned)qr_adj_sym_blocks(p)), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
-hipError_t launch_tri_inv_upper(const double* R, double* Rinv, int32_t l, hipStream_t st) {
-  if (l < 1 || l > 128) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(tri_inv_upper_kernel, dim3(1), dim3(256), 0, st, R, Rinv, l);
+hipError_t launch_tri_inv_upper(const TriInvParams& p, hipStream_t st) {
+  if (!tri_inv_ok(p)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tri_inv_upper_kernel, dim3(1), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
 hipError_t launch_copy2d(const Copy2dParams& p, hipStream_t st) {
-  if (p.rows <= 0 || p.cols <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((p.cols + 31) / 32), (unsigned)((p.rows + 31) / 32));
-  hipLaunchKernelGGL(copy2d_kernel, grid, dim3(256), 0, st, p);
+  const int64_t nb = copy2d_blocks(p);
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy2d_kernel, dim3((unsigned)nb), dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+// Batched launches (parameters checked when each problem was recorded).
+hipError_t launch_svd_adj_coef_batched(const SvdAdjParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(svd_adj_coef_batched, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_adj_sym_batched(const QrSymParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(qr_adj_sym_batched, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_inv_upper_batched(const TriInvParams* ps, const BlockMap* bm, int64_t nblocks,
+                                        hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tri_inv_upper_batched, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy2d_batched(const Copy2dParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy2d_batched, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
   return hipGetLastError();
 }
 

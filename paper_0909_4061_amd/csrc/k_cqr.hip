@@ -33,12 +33,12 @@ namespace {
 // Split-K partial sums: one thread per 16 bytes of a row, every partial's load
 // in flight at once, summed in the order s = 0, 1, ... (deterministic).
 template <typename T>
-__global__ __launch_bounds__(256) void sum_parts_kernel(const GramParams p) {
+__device__ __forceinline__ void sum_parts_body(const GramParams& p, const int bid) {
   constexpr int V = 16 / sizeof(T);
   typedef T vec __attribute__((ext_vector_type(V)));
   if (p.gate && *p.gate == 0) return;
   const int per_row = (p.l + V - 1) / V;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t idx = (int64_t)bid * 256 + threadIdx.x;
   const int64_t row = idx / per_row;
   const int cv = (int)(idx - row * per_row) * V;
   if (row >= p.rows) return;
@@ -55,6 +55,16 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const GramParams p) {
 #pragma unroll
   for (int e = 0; e < V; ++e)
     if (cv + e < p.l) y[row * p.ldy + cv + e] = acc[e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sum_parts_kernel(const GramParams p) { sum_parts_body<T>(p, blockIdx.x); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void sum_parts_batched(const GramParams* __restrict__ ps,
+                                                         const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  sum_parts_body<T>(ps[b.item], b.local);
 }
 
 // Partial Gram of one row chunk for one group of 16 x 16 tiles (upper
@@ -538,12 +548,20 @@ hipError_t launch_gram_partial(int dtype, const GramParams& p, hipStream_t st) {
   return hipGetLastError();
 }
 
+bool sum_parts_ok(int dtype, const GramParams& p) {
+  const int V = dtype == RSVD_F64 ? 2 : 4;
+  return p.S >= 1 && p.S <= 16 && p.Lp % V == 0 && p.Lp >= p.l && p.l >= 1;
+}
+
+int64_t sum_parts_blocks(int dtype, const GramParams& p) {
+  const int V = dtype == RSVD_F64 ? 2 : 4;
+  return p.rows <= 0 ? 0 : (p.rows * ((p.l + V - 1) / V) + 255) / 256;
+}
+
 hipError_t launch_sum_parts(int dtype, const GramParams& p, hipStream_t st) {
   if (p.rows <= 0) return hipSuccess;
-  const int V = dtype == RSVD_F64 ? 2 : 4;
-  if (p.S < 1 || p.S > 16 || p.Lp % V != 0 || p.Lp < p.l || p.l < 1) return hipErrorInvalidValue;
-  const int64_t threads = p.rows * ((p.l + V - 1) / V);
-  const dim3 grid((unsigned)((threads + 255) / 256));
+  if (!sum_parts_ok(dtype, p)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)sum_parts_blocks(dtype, p));
   if (dtype == RSVD_F64)
     hipLaunchKernelGGL(sum_parts_kernel<double>, grid, dim3(256), 0, st, p);
   else
@@ -559,6 +577,16 @@ hipError_t launch_gram_reduce(const double* gpart, int64_t nblk, int32_t Lg, dou
                               const int32_t* gate, hipStream_t st) {
   const GramReduceParams p{gpart, nblk, Lg, G, status, gate};
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)gram_reduce_blocks(p)), dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_parts_batched(int dtype, const GramParams* ps, const BlockMap* bm, int64_t nblocks,
+                                    hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (dtype == RSVD_F64)
+    hipLaunchKernelGGL(sum_parts_batched<double>, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  else
+    hipLaunchKernelGGL(sum_parts_batched<float>, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
   return hipGetLastError();
 }
 
