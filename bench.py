@@ -406,11 +406,12 @@ def main_differentiable(args):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / args.steps
     fwd = algorithmic_flops(m, n, l, k, q)
-    # adjoint: forward recomputed, (2q + 1) products with A in reverse, gA = Left RightT with K = (2q + 2) l
-    bwd = fwd + (2 * q + 1) * 2.0 * m * n * l + 2.0 * m * n * (2 * q + 2) * l
+    # adjoint (from the state the forward kept): (2q + 1) products with A in reverse and
+    # gA = Left RightT with K = (2q + 2) l
+    bwd = (2 * q + 1) * 2.0 * m * n * l + 2.0 * m * n * (2 * q + 2) * l
     flops = count * (fwd + bwd)
     # loss-side products in torch (U S V^T - T and its derivatives) are not counted
-    hbm = count * (algorithmic_bytes(m, n, l, q) * 2 + (2 * q + 1) * m * n * 4 + m * n * 4)
+    hbm = count * (algorithmic_bytes(m, n, l, q) + (2 * q + 1) * m * n * 4 + m * n * 4)
     gnorm = float(torch.stack([g.norm() for g in grads]).mean())
     line = {
         "metric": "rSVD TFLOP/s + HBM GB/s at stated ||A-USV*||/sigma_{k+1}; BF16-MFMA vs FP32",

@@ -35,9 +35,9 @@
  *    a hipStream_t (NULL = the default stream) on which every kernel of the
  *    call is enqueued; calls return without synchronizing.
  *  * Ownership: the caller owns every buffer.  The library never allocates or
- *    frees memory in these calls (rsvd_batched and rsvd_backward_batched
- *    excepted: the first call for a new batch allocates the batch's launch
- *    tables, owned by the handle);
+ *    frees memory in these calls (the batched calls excepted: the first call
+ *    for a new batch allocates the batch's launch tables, owned by the
+ *    handle);
  *    scratch space is the caller's workspace `ws` of at least
  *    rsvd_workspace_bytes(problem) bytes, 256-byte aligned.  Its
  *    contents are undefined between calls (except as noted for rsvd_project ->
@@ -198,6 +198,24 @@ rsvd_status rsvd_backward(rsvd_handle handle, const rsvd_problem* problem,
                           const void* gV, void* gA, void* ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/* The forward of rsvd_backward kept for it: the whole randomized SVD of A
+ * (outputs U, S, V as rsvd_svd, the same values as the four hot-path calls)
+ * computed in an adjoint workspace `ws` (rsvd_backward_workspace_bytes
+ * bytes), where it leaves every basis of the power scheme with its
+ * triangular factor, B* and the SVD of B.  rsvd_backward_kept then skips the
+ * recomputation; the state stays valid while `ws` is not otherwise used. */
+rsvd_status rsvd_forward_kept(rsvd_handle handle, const rsvd_problem* problem,
+                              const void* A, void* U, void* S, void* V,
+                              void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* rsvd_backward from the state rsvd_forward_kept left in `ws` for the same
+ * problem and the same contents of A: the adjoint only, gA bit for bit equal to
+ * rsvd_backward's.  The state is only read, so the call may be repeated. */
+rsvd_status rsvd_backward_kept(rsvd_handle handle, const rsvd_problem* problem,
+                               const void* A, const void* gU, const void* gS,
+                               const void* gV, void* gA, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+
 /* --- Many independent problems --------------------------------------- */
 
 /* Workspace bytes rsvd_batched needs for `count` problems (0 if any problem is
@@ -242,6 +260,20 @@ rsvd_status rsvd_backward_batched(rsvd_handle handle, int32_t count, const rsvd_
                                   const void* const* A, const void* const* gU, const void* const* gS,
                                   const void* const* gV, void* const* gA, void* ws, size_t ws_bytes,
                                   hipStream_t stream);
+
+/* rsvd_forward_kept and rsvd_backward_kept for a batch: rsvd_batched_kept is
+ * rsvd_batched computed in a workspace of rsvd_backward_batched_workspace_bytes
+ * bytes, where it keeps each problem's forward state; rsvd_backward_batched_kept
+ * is rsvd_backward_batched from that state (same problems, same contents of
+ * every A).  Both replay recorded graphs as rsvd_batched does. */
+rsvd_status rsvd_batched_kept(rsvd_handle handle, int32_t count, const rsvd_problem* problems,
+                              const void* const* A, void* const* U, void* const* S,
+                              void* const* V, void* ws, size_t ws_bytes, hipStream_t stream);
+rsvd_status rsvd_backward_batched_kept(rsvd_handle handle, int32_t count, const rsvd_problem* problems,
+                                       const void* const* A, const void* const* gU,
+                                       const void* const* gS, const void* const* gV,
+                                       void* const* gA, void* ws, size_t ws_bytes,
+                                       hipStream_t stream);
 
 /* --- Diagnostics ------------------------------------------------------- */
 

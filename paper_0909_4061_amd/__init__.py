@@ -208,46 +208,77 @@ def rsvd_sketch(A, k, p, *, sketch="gaussian", prec="native", seed=0, stream_id=
     return Y
 
 
-def rsvd_backward(A, gU, gS, gV, k, p, q, *, prec="native", seed=0, stream_id=0, gA=None, ws=None):
-    """gA = the adjoint of A -> (U, S, V) applied to (gU, gS, gV) (fixed test matrix)."""
-    pr = _prob_for(A, k, p, q, "gaussian", prec, seed, stream_id)
+def backward_workspace(pr, device):
+    """A workspace for the adjoint calls of one problem (torch allocation)."""
+    nbytes = handle(device).lib.rsvd_backward_workspace_bytes(ctypes.byref(pr))
+    if nbytes == 0:
+        raise RsvdError(validate(pr) or _lib.RSVD_E_UNSUPPORTED, "rsvd_backward_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _adjoint_call(fn, A, gU, gS, gV, pr, ws, gA):
     dev = A.device
     h = handle(dev)
-    if ws is None:
-        nbytes = h.lib.rsvd_backward_workspace_bytes(ctypes.byref(pr))
-        if nbytes == 0:
-            raise RsvdError(validate(pr) or _lib.RSVD_E_UNSUPPORTED, "rsvd_backward_workspace_bytes")
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     gU, gS, gV = (t.detach().to(A.dtype).contiguous() for t in (gU, gS, gV))
     if gA is None:
         gA = torch.empty(A.shape, dtype=A.dtype, device=dev)
-    _lib.check(h.lib.rsvd_backward(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(gU), _ptr(gS), _ptr(gV), _ptr(gA),
-                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)), "rsvd_backward")
+    _lib.check(getattr(h.lib, fn)(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(gU), _ptr(gS), _ptr(gV), _ptr(gA),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)), fn)
     return gA
 
 
+def rsvd_backward(A, gU, gS, gV, k, p, q, *, prec="native", seed=0, stream_id=0, gA=None, ws=None):
+    """gA = the adjoint of A -> (U, S, V) applied to (gU, gS, gV) (fixed test matrix); the
+    forward is recomputed inside."""
+    pr = _prob_for(A, k, p, q, "gaussian", prec, seed, stream_id)
+    ws = backward_workspace(pr, A.device) if ws is None else ws
+    return _adjoint_call("rsvd_backward", A, gU, gS, gV, pr, ws, gA)
+
+
+def rsvd_forward_kept(A, k, p, q, *, prec="native", seed=0, stream_id=0, ws=None):
+    """(U, S, V, ws): the randomized SVD computed in an adjoint workspace that keeps the
+    forward state for rsvd_backward_kept."""
+    pr = _prob_for(A, k, p, q, "gaussian", prec, seed, stream_id)
+    dev = A.device
+    ws = backward_workspace(pr, dev) if ws is None else ws
+    m, n = A.shape
+    U = torch.empty(m, k, dtype=A.dtype, device=dev)
+    S = torch.empty(k, dtype=A.dtype, device=dev)
+    V = torch.empty(n, k, dtype=A.dtype, device=dev)
+    h = handle(dev)
+    _lib.check(h.lib.rsvd_forward_kept(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(U), _ptr(S), _ptr(V),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)), "rsvd_forward_kept")
+    return U, S, V, ws
+
+
+def rsvd_backward_kept(A, gU, gS, gV, k, p, q, ws, *, prec="native", seed=0, stream_id=0, gA=None):
+    """rsvd_backward from the state rsvd_forward_kept left in `ws` (same problem, same A)."""
+    pr = _prob_for(A, k, p, q, "gaussian", prec, seed, stream_id)
+    return _adjoint_call("rsvd_backward_kept", A, gU, gS, gV, pr, ws, gA)
+
+
 class RSVDFunction(torch.autograd.Function):
-    """(U, S, V) = rsvd(A) with the library's hand-written adjoint as backward."""
+    """(U, S, V) = rsvd(A) with the library's hand-written adjoint as backward: the forward
+    keeps its state (rsvd_forward_kept) and the backward is rsvd_backward_kept."""
 
     @staticmethod
     def forward(ctx, A, k, p, q, seed, stream_id, prec):
         Ad = A.detach()
-        with torch.no_grad():
-            U, S, V = rsvd(Ad, k, p, q, seed=seed, stream_id=stream_id, prec=prec)
-        ctx.save_for_backward(Ad)
+        U, S, V, ws = rsvd_forward_kept(Ad, k, p, q, prec=prec, seed=seed, stream_id=stream_id)
+        ctx.save_for_backward(Ad, ws)
         ctx.cfg = (k, p, q, seed, stream_id, prec)
         return U, S, V
 
     @staticmethod
     def backward(ctx, gU, gS, gV):
-        (A,) = ctx.saved_tensors
+        A, ws = ctx.saved_tensors
         k, p, q, seed, stream_id, prec = ctx.cfg
         m, n = A.shape
         z = lambda shape: torch.zeros(shape, dtype=A.dtype, device=A.device)
         gU = z((m, k)) if gU is None else gU
         gS = z((k,)) if gS is None else gS
         gV = z((n, k)) if gV is None else gV
-        gA = rsvd_backward(A.contiguous(), gU, gS, gV, k, p, q, prec=prec, seed=seed, stream_id=stream_id)
+        gA = rsvd_backward_kept(A, gU, gS, gV, k, p, q, ws, prec=prec, seed=seed, stream_id=stream_id)
         return gA, None, None, None, None, None, None
 
 
@@ -289,26 +320,6 @@ def _ptrs(ts):
     return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
 
 
-# Workspaces of the differentiable batched calls, one per (call kind, problems,
-# stream): calls on one stream are ordered, so they may share it, and a stable
-# workspace lets the library replay its recorded graph.
-_BATCH_WS = {}
-
-
-def _batch_ws(kind, probs, dev, nbytes_fn):
-    key = (kind, dev, torch.cuda.current_stream(dev).cuda_stream,
-           tuple(bytes(memoryview(pr)) for pr in probs))
-    ws = _BATCH_WS.get(key)
-    if ws is None:
-        arr = (RsvdProblem * len(probs))(*probs)
-        nbytes = nbytes_fn(len(probs), arr)
-        if nbytes == 0:
-            raise RsvdError(_lib.RSVD_E_INVAL, f"{kind} workspace")
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        _BATCH_WS[key] = ws
-    return ws
-
-
 def rsvd_batched(As, ks, p=8, q=1, *, prec="native", seed=0, stream_id=0, outs=None, ws=None):
     """Randomized SVDs of many independent matrices in one batched call.
 
@@ -340,51 +351,76 @@ def rsvd_batched(As, ks, p=8, q=1, *, prec="native", seed=0, stream_id=0, outs=N
     return outs
 
 
-def rsvd_backward_batched(As, gUs, gSs, gVs, ks, p, q, *, prec="native", seed=0, stream_id=0, gAs=None, ws=None):
-    """gA_i = the adjoint of A_i -> (U_i, S_i, V_i) applied to (gU_i, gS_i, gV_i) for every
-    matrix of a batch (fixed test matrices, matrix i drawing from (seed, stream_id + i))."""
-    count = len(As)
-    if count == 0:
-        return []
-    ks, probs = _batch_problems(As, ks, p, q, prec, seed, stream_id)
+def backward_batched_workspace(probs, device):
+    """A workspace for the batched adjoint calls (torch allocation)."""
+    arr = (RsvdProblem * len(probs))(*probs)
+    nbytes = handle(device).lib.rsvd_backward_batched_workspace_bytes(len(probs), arr)
+    if nbytes == 0:
+        raise RsvdError(_lib.RSVD_E_INVAL, "rsvd_backward_batched_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _batched_adjoint_call(fn, As, gUs, gSs, gVs, probs, ws, gAs):
     dev = As[0].device
     h = handle(dev)
-    if ws is None:
-        ws = _batch_ws("backward", probs, dev, h.lib.rsvd_backward_batched_workspace_bytes)
     gUs, gSs, gVs = ([t.detach().to(As[0].dtype).contiguous() for t in ts] for ts in (gUs, gSs, gVs))
     if gAs is None:
         gAs = [torch.empty(A.shape, dtype=A.dtype, device=dev) for A in As]
-    arr = (RsvdProblem * count)(*probs)
-    _lib.check(h.lib.rsvd_backward_batched(h.ptr, count, arr, _ptrs(As), _ptrs(gUs), _ptrs(gSs), _ptrs(gVs),
-                                           _ptrs(gAs), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)),
-               "rsvd_backward_batched")
+    arr = (RsvdProblem * len(As))(*probs)
+    _lib.check(getattr(h.lib, fn)(h.ptr, len(As), arr, _ptrs(As), _ptrs(gUs), _ptrs(gSs), _ptrs(gVs), _ptrs(gAs),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)), fn)
     return gAs
 
 
+def rsvd_backward_batched(As, gUs, gSs, gVs, ks, p, q, *, prec="native", seed=0, stream_id=0, gAs=None, ws=None):
+    """gA_i = the adjoint of A_i -> (U_i, S_i, V_i) applied to (gU_i, gS_i, gV_i) for every
+    matrix of a batch (fixed test matrices, matrix i drawing from (seed, stream_id + i)); the
+    forward is recomputed inside."""
+    if len(As) == 0:
+        return []
+    ks, probs = _batch_problems(As, ks, p, q, prec, seed, stream_id)
+    ws = backward_batched_workspace(probs, As[0].device) if ws is None else ws
+    return _batched_adjoint_call("rsvd_backward_batched", As, gUs, gSs, gVs, probs, ws, gAs)
+
+
+def rsvd_batched_kept(As, ks, p=8, q=1, *, prec="native", seed=0, stream_id=0, ws=None):
+    """(outs, ws): rsvd_batched computed in a batched adjoint workspace that keeps every
+    problem's forward state for rsvd_backward_batched_kept."""
+    ks, probs = _batch_problems(As, ks, p, q, prec, seed, stream_id)
+    dev = As[0].device
+    ws = backward_batched_workspace(probs, dev) if ws is None else ws
+    outs = [(torch.empty(A.shape[0], k, dtype=A.dtype, device=dev), torch.empty(k, dtype=A.dtype, device=dev),
+             torch.empty(A.shape[1], k, dtype=A.dtype, device=dev)) for A, k in zip(As, ks)]
+    arr = (RsvdProblem * len(As))(*probs)
+    h = handle(dev)
+    _lib.check(h.lib.rsvd_batched_kept(h.ptr, len(As), arr, _ptrs(As), _ptrs([o[0] for o in outs]),
+                                       _ptrs([o[1] for o in outs]), _ptrs([o[2] for o in outs]),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)), "rsvd_batched_kept")
+    return outs, ws
+
+
+def rsvd_backward_batched_kept(As, gUs, gSs, gVs, ks, p, q, ws, *, prec="native", seed=0, stream_id=0, gAs=None):
+    """rsvd_backward_batched from the state rsvd_batched_kept left in `ws`."""
+    ks, probs = _batch_problems(As, ks, p, q, prec, seed, stream_id)
+    return _batched_adjoint_call("rsvd_backward_batched_kept", As, gUs, gSs, gVs, probs, ws, gAs)
+
+
 class RSVDBatchedFunction(torch.autograd.Function):
-    """Flat (U_0, S_0, V_0, U_1, ...) = rsvd_batched(As) with rsvd_backward_batched as backward."""
+    """Flat (U_0, S_0, V_0, U_1, ...) = rsvd_batched(As); the forward keeps its state
+    (rsvd_batched_kept) and the backward is rsvd_backward_batched_kept."""
 
     @staticmethod
     def forward(ctx, cfg, *As):
         ks, p, q, prec, seed, stream_id = cfg
         Ad = [A.detach() for A in As]
-        dev = Ad[0].device
-        ks_, probs = _batch_problems(Ad, ks, p, q, prec, seed, stream_id)
-        h = handle(dev)
-        ws = _batch_ws("forward", probs, dev, h.lib.rsvd_batched_workspace_bytes)
-        outs = [(torch.empty(A.shape[0], k, dtype=A.dtype, device=dev), torch.empty(k, dtype=A.dtype, device=dev),
-                 torch.empty(A.shape[1], k, dtype=A.dtype, device=dev)) for A, k in zip(Ad, ks_)]
-        arr = (RsvdProblem * len(Ad))(*probs)
-        _lib.check(h.lib.rsvd_batched(h.ptr, len(Ad), arr, _ptrs(Ad), _ptrs([o[0] for o in outs]),
-                                      _ptrs([o[1] for o in outs]), _ptrs([o[2] for o in outs]),
-                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)), "rsvd_batched")
-        ctx.save_for_backward(*Ad)
-        ctx.cfg = (ks_, p, q, prec, seed, stream_id)
+        outs, ws = rsvd_batched_kept(Ad, ks, p, q, prec=prec, seed=seed, stream_id=stream_id)
+        ctx.save_for_backward(ws, *Ad)
+        ctx.cfg = ([o[1].shape[0] for o in outs], p, q, prec, seed, stream_id)
         return tuple(t for o in outs for t in o)
 
     @staticmethod
     def backward(ctx, *grads):
-        As = ctx.saved_tensors
+        ws, *As = ctx.saved_tensors
         ks, p, q, prec, seed, stream_id = ctx.cfg
         gUs, gSs, gVs = [], [], []
         for i, (A, k) in enumerate(zip(As, ks)):
@@ -394,8 +430,8 @@ class RSVDBatchedFunction(torch.autograd.Function):
             gUs.append(z((m, k)) if gU is None else gU)
             gSs.append(z((k,)) if gS is None else gS)
             gVs.append(z((n, k)) if gV is None else gV)
-        gAs = rsvd_backward_batched([A.contiguous() for A in As], gUs, gSs, gVs, ks, p, q, prec=prec, seed=seed,
-                                    stream_id=stream_id)
+        gAs = rsvd_backward_batched_kept(As, gUs, gSs, gVs, ks, p, q, ws, prec=prec, seed=seed,
+                                         stream_id=stream_id)
         return (None, *gAs)
 
 

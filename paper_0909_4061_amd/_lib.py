@@ -30,7 +30,8 @@ EXPORTS = [
     "rsvd_create", "rsvd_destroy", "rsvd_validate", "rsvd_workspace_bytes", "rsvd_status_string",
     "rsvd_range_finder", "rsvd_power_iter", "rsvd_project", "rsvd_svd",
     "rsvd_batched_workspace_bytes", "rsvd_batched", "rsvd_backward_workspace_bytes", "rsvd_backward",
-    "rsvd_backward_batched_workspace_bytes", "rsvd_backward_batched",
+    "rsvd_backward_batched_workspace_bytes", "rsvd_backward_batched", "rsvd_forward_kept", "rsvd_backward_kept",
+    "rsvd_batched_kept", "rsvd_backward_batched_kept",
     "rsvd_sketch", "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
     "rsvd_profile_enable", "rsvd_profile_select", "rsvd_profile_read",
 ]
@@ -86,6 +87,10 @@ def load():
                           ctypes.POINTER(vp), vp, sz, vp], i32),
         "rsvd_backward_batched_workspace_bytes": ([i32, prob], sz),
         "rsvd_backward_batched": ([vp, i32, prob] + [ctypes.POINTER(vp)] * 5 + [vp, sz, vp], i32),
+        "rsvd_backward_batched_kept": ([vp, i32, prob] + [ctypes.POINTER(vp)] * 5 + [vp, sz, vp], i32),
+        "rsvd_batched_kept": ([vp, i32, prob] + [ctypes.POINTER(vp)] * 4 + [vp, sz, vp], i32),
+        "rsvd_forward_kept": ([vp, prob, vp, vp, vp, vp, vp, sz, vp], i32),
+        "rsvd_backward_kept": ([vp, prob, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_draw_omega": ([vp, prob, vp, vp], i32),
         "rsvd_draw_srft": ([vp, prob, vp, vp, vp], i32),
         "rsvd_orth": ([vp, prob, i64, vp, vp, vp, sz, vp], i32),

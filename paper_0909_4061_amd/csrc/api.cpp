@@ -69,6 +69,7 @@ struct Plan {
   int32_t Lp, Lg;
   int esize;
   int dtype, prec;
+  bool stream;  // FP32 data: the A-streaming products take the streaming kernels (X packed first)
   Split nn, tn;
   size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rb, RinvT, XU, XV, Uh, sig, flags, srft_d,
       srft_R, total;
@@ -96,8 +97,9 @@ rsvd_status validate(const rsvd_problem* pr) {
 }
 
 // Workspace regions of one problem.  `batched`: no split-K (every problem of
-// a batch runs the same launch sequence, and the batch itself fills the chip).
-Plan make_plan(const rsvd_problem* pr, bool batched = false) {
+// a batch runs the same launch sequence, and the batch itself fills the chip);
+// `stream`: the products with A take the streaming kernels.
+Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true) {
   Plan P{};
   P.m = pr->m;
   P.n = pr->n;
@@ -107,6 +109,7 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false) {
   P.dtype = pr->dtype;
   P.prec = pr->prec;
   P.esize = pr->dtype == RSVD_F64 ? 8 : 4;
+  P.stream = stream && pr->dtype == RSVD_F32;
   const GemmTile big = gemm_tile(pr->dtype, pr->prec);
   P.Lp = (int32_t)round_up(P.l, big.lp_mult);
   P.Lg = (int32_t)round_up(P.l, 16);
@@ -127,7 +130,7 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false) {
   P.part = take((size_t)part_elems * es);
   P.Y = take((size_t)P.Mx * P.l * es);
   P.Qt = take((size_t)P.n * P.l * es);
-  P.pack = take(pr->dtype == RSVD_F32 && !batched ? (size_t)stream_pack_bytes(P.Mx, P.Lp) : 0);
+  P.pack = take(P.stream ? (size_t)stream_pack_bytes(P.Mx, round_up(P.l, 32)) : 0);
   P.gpart = take((size_t)ceil_div(P.Mx, GRAM_ROWS) * P.Lg * P.Lg * 8);
   P.G = take((size_t)P.Lg * P.Lg * 8);
   P.R1 = take(ll8);
@@ -171,6 +174,9 @@ class Runner {
   virtual ~Runner() = default;
   virtual bool records() const = 0;
   virtual hipError_t gemm(int dtype, int prec, bool trans, const GemmParams& p, int kind) = 0;
+  // the A-streaming product: X packed into p.pack, then the streaming kernel
+  virtual hipError_t pack_x(int prec, const GemmParams& p) = 0;
+  virtual hipError_t stream_gemm(int prec, bool trans, const GemmParams& p, int kind) = 0;
   virtual hipError_t gram_partial(int dtype, const GramParams& p) = 0;
   virtual hipError_t sum_parts(int dtype, const GramParams& p) = 0;
   virtual hipError_t gram_reduce(const GramReduceParams& p) = 0;
@@ -195,6 +201,14 @@ class DirectRunner final : public Runner {
   hipError_t gemm(int dtype, int prec, bool trans, const GemmParams& p, int kind) override {
     Timed t(h_, kind, st_);
     return launch_gemm(dtype, prec, trans, p, st_);
+  }
+  hipError_t pack_x(int prec, const GemmParams& p) override {
+    Timed t(h_, RSVD_KERNEL_PACK, st_);
+    return launch_pack_x(prec, p, st_);
+  }
+  hipError_t stream_gemm(int prec, bool trans, const GemmParams& p, int kind) override {
+    Timed t(h_, kind, st_);
+    return launch_stream_gemm(prec, trans, p, st_);
   }
   hipError_t gram_partial(int dtype, const GramParams& p) override {
     Timed t(h_, RSVD_KERNEL_GRAM, st_);
@@ -236,7 +250,7 @@ class DirectRunner final : public Runner {
 // problem, with the problems' parameter blocks side by side.
 enum SlotKind {
   SK_GEMM, SK_GRAM_PARTIAL, SK_GRAM_REDUCE, SK_CHOL, SK_JACOBI, SK_OMEGA, SK_FILL, SK_TRMM, SK_COPY,
-  SK_SUM_PARTS, SK_SVD_ADJ, SK_QR_SYM, SK_TRI_INV, SK_COPY2D
+  SK_SUM_PARTS, SK_SVD_ADJ, SK_QR_SYM, SK_TRI_INV, SK_COPY2D, SK_PACK, SK_STREAM
 };
 
 struct Slot {
@@ -257,6 +271,14 @@ class RecordRunner final : public Runner {
   size_t cursor() const { return cursor_; }
   hipError_t gemm(int dtype, int prec, bool trans, const GemmParams& p, int) override {
     return add(SK_GEMM, dtype, prec, trans, p, p.rows > 0 ? gemm_blocks(dtype, prec, p) : 0);
+  }
+  hipError_t pack_x(int prec, const GemmParams& p) override {
+    if (!stream_params_ok(p)) return hipErrorInvalidValue;
+    return add(SK_PACK, 0, prec, false, p, p.rows > 0 ? pack_x_blocks(p) : 0);
+  }
+  hipError_t stream_gemm(int prec, bool trans, const GemmParams& p, int) override {
+    if (!stream_params_ok(p)) return hipErrorInvalidValue;
+    return add(SK_STREAM, 0, prec, trans, p, stream_gemm_blocks(p));
   }
   hipError_t gram_partial(int dtype, const GramParams& p) override {
     return add(SK_GRAM_PARTIAL, dtype, 0, false, p, p.rows > 0 ? gram_partial_blocks(p) : 0);
@@ -357,14 +379,11 @@ rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda,
   if (g.S > 1 && !part) return RSVD_E_INVAL;
   if (accum && (g.S > 1 || streams_a)) return RSVD_E_INVAL;
   const int kind = streams_a ? (trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN) : RSVD_KERNEL_SMALL_GEMM;
-  if (streams_a && c.P.dtype == RSVD_F32 && !c.run->records()) {
+  if (streams_a && c.P.stream) {
     g.Lp = (int32_t)round_up(ncols, 32);
-    {
-      Timed t_(c.h, RSVD_KERNEL_PACK, c.st);
-      RSVD_TRY(launch_pack_x(prec, g, c.at<void>(c.P.pack), c.st));
-    }
-    Timed t_(c.h, kind, c.st);
-    RSVD_TRY(launch_stream_gemm(prec, trans, g, c.at<void>(c.P.pack), c.st));
+    g.pack = c.at<void>(c.P.pack);
+    RSVD_TRY(c.run->pack_x(prec, g));
+    RSVD_TRY(c.run->stream_gemm(prec, trans, g, kind));
   } else {
     RSVD_TRY(c.run->gemm(c.P.dtype, prec, trans, g, kind));
   }
@@ -589,9 +608,9 @@ struct BwdLayout {
 
 constexpr int64_t kBwdMaxSplit = 16;  // K chunks of the adjoint's transposed products
 
-BwdLayout bwd_layout(const rsvd_problem* pr, bool batched = false) {
+BwdLayout bwd_layout(const rsvd_problem* pr, bool batched = false, bool stream = true) {
   BwdLayout L{};
-  L.P = make_plan(pr, batched);
+  L.P = make_plan(pr, batched, stream);
   const Plan& P = L.P;
   L.q = pr->q;
   L.Kc = (int64_t)(2 * pr->q + 2) * P.l;
@@ -714,37 +733,66 @@ rsvd_status stream_apply(const Ctx& c, const rsvd_problem* pr, bool trans, const
   return reduce_parts(c, sp, rows, out);
 }
 
-rsvd_status backward_steps(const Ctx& c, const BwdLayout& L, const rsvd_problem* pr, const void* A, const void* gU,
-                           const void* gS, const void* gV, void* gA) {
+// Regions of the kept forward state in an adjoint workspace.
+char* kept_Q(const Ctx& c, const BwdLayout& L, int j) {  // Q_j, m x l (j = 0..q)
+  return c.at<char>(L.Qs) + (size_t)j * (size_t)(c.P.m * c.P.l) * (size_t)c.P.esize;
+}
+char* kept_Qt(const Ctx& c, const BwdLayout& L, int j) {  // Qt_j, n x l (j = 1..q)
+  return c.at<char>(L.Qts) + (size_t)(j - 1) * (size_t)(c.P.n * c.P.l) * (size_t)c.P.esize;
+}
+double* kept_R(const Ctx& c, const BwdLayout& L, int j) { return c.at<double>(L.Rs) + (size_t)j * (size_t)(c.P.l * c.P.l); }
+double* kept_Rt(const Ctx& c, const BwdLayout& L, int j) {
+  return c.at<double>(L.Rts) + (size_t)(j - 1) * (size_t)(c.P.l * c.P.l);
+}
+
+// The forward of the adjoint: the range finder and power scheme keeping every
+// basis Q_j, Qt_j with its combined triangular factor, B* and the small SVD
+// (U~ and sigma in the plan's regions, the k leading singular values in the
+// element type to S).  With U and V non-null also the lifts of rsvd_svd,
+// U = Q U~_k and V = B* U~_k S_k^-1.  Omega stays in the plan's region.
+rsvd_status kept_forward(const Ctx& c, const BwdLayout& L, const rsvd_problem* pr, const void* A, void* U, void* S,
+                         void* V) {
+  const Plan& P = c.P;
+  const int64_t m = P.m, n = P.n, l = P.l, k = P.k;
+  void* y = c.at<void>(P.Y);
+  void* Bt = c.at<void>(L.Bt);
+  rsvd_status s = sketch(c, pr, A, y);
+  if (s == RSVD_OK) s = orth(c, P.nn.S > 1, P.nn, y, m, kept_Q(c, L, 0), kept_R(c, L, 0));
+  for (int j = 1; j <= L.q && s == RSVD_OK; ++j) {
+    s = gemm(c, pr->prec, true, A, pr->lda, n, m, kept_Q(c, L, j - 1), l, (int32_t)l, y, l, P.tn,
+             P.tn.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
+    if (s == RSVD_OK) s = orth(c, P.tn.S > 1, P.tn, y, n, kept_Qt(c, L, j), kept_Rt(c, L, j));
+    if (s == RSVD_OK)
+      s = gemm(c, pr->prec, false, A, pr->lda, m, n, kept_Qt(c, L, j), l, (int32_t)l, y, l, P.nn,
+               P.nn.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
+    if (s == RSVD_OK) s = orth(c, P.nn.S > 1, P.nn, y, m, kept_Q(c, L, j), kept_R(c, L, j));
+  }
+  if (s == RSVD_OK) s = project_steps(c, pr, A, kept_Q(c, L, L.q), Bt);
+  JacobiParams jp;
+  if (s == RSVD_OK) s = small_svd(c, Bt, S, jp);
+  if (s != RSVD_OK || !U) return s;
+  s = gemm(c, RSVD_NATIVE, false, kept_Q(c, L, L.q), l, m, l, jp.XU, k, (int32_t)k, U, k, no_split(l), nullptr,
+           nullptr);
+  if (s != RSVD_OK) return s;
+  return gemm(c, RSVD_NATIVE, false, Bt, l, n, l, jp.XV, k, (int32_t)k, V, k, no_split(l), nullptr, nullptr);
+}
+
+// The adjoint proper, from the state kept_forward left in the workspace (which
+// it only reads: it may run again on the same state).
+rsvd_status adjoint_steps(const Ctx& c, const BwdLayout& L, const rsvd_problem* pr, const void* A, const void* gU,
+                          const void* gS, const void* gV, void* gA) {
   const Plan& P = c.P;
   const int64_t m = P.m, n = P.n, l = P.l, k = P.k, Kc = L.Kc;
   const int dt = P.dtype;
   const size_t es = (size_t)P.esize;
-  auto Qb = [&](int j) { return c.at<char>(L.Qs) + (size_t)j * (size_t)(m * l) * es; };
-  auto Qtb = [&](int j) { return c.at<char>(L.Qts) + (size_t)(j - 1) * (size_t)(n * l) * es; };
-  auto Rb = [&](int j) { return c.at<double>(L.Rs) + (size_t)j * (size_t)(l * l); };
-  auto Rtb = [&](int j) { return c.at<double>(L.Rts) + (size_t)(j - 1) * (size_t)(l * l); };
+  auto Qb = [&](int j) { return kept_Q(c, L, j); };
+  auto Qtb = [&](int j) { return kept_Qt(c, L, j); };
+  auto Rb = [&](int j) { return kept_R(c, L, j); };
+  auto Rtb = [&](int j) { return kept_Rt(c, L, j); };
   char* left = c.at<char>(L.Left);
   char* rightT = c.at<char>(L.RightT);
-  void* y = c.at<void>(P.Y);
   void* Bt = c.at<void>(L.Bt);
-
-  // --- forward, keeping every basis and its triangular factor
-  rsvd_status s = sketch(c, pr, A, y);
-  if (s == RSVD_OK) s = orth(c, P.nn.S > 1, P.nn, y, m, Qb(0), Rb(0));
-  for (int j = 1; j <= L.q && s == RSVD_OK; ++j) {
-    s = gemm(c, pr->prec, true, A, pr->lda, n, m, Qb(j - 1), l, (int32_t)l, y, l, P.tn,
-             P.tn.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
-    if (s == RSVD_OK) s = orth(c, P.tn.S > 1, P.tn, y, n, Qtb(j), Rtb(j));
-    if (s == RSVD_OK)
-      s = gemm(c, pr->prec, false, A, pr->lda, m, n, Qtb(j), l, (int32_t)l, y, l, P.nn,
-               P.nn.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
-    if (s == RSVD_OK) s = orth(c, P.nn.S > 1, P.nn, y, m, Qb(j), Rb(j));
-  }
-  if (s == RSVD_OK) s = project_steps(c, pr, A, Qb(L.q), Bt);
-  JacobiParams jp;
-  if (s == RSVD_OK) s = small_svd(c, Bt, c.at<void>(L.Sk), jp);
-  if (s != RSVD_OK) return s;
+  rsvd_status s;
 
   // --- SVD of B and B = Q^T A: gBt = Bt M1 + gV M2, gQ = A gBt + gU U~_k^T
   s = gemm_tn_splitk(c, L, Bt, l, l, n, gV, k, (int32_t)k, c.at<void>(L.T1), k);  // T1 = B gV
@@ -825,6 +873,14 @@ rsvd_status backward_steps(const Ctx& c, const BwdLayout& L, const rsvd_problem*
   return RSVD_OK;
 }
 
+// The adjoint with the forward recomputed first.
+rsvd_status backward_steps(const Ctx& c, const BwdLayout& L, const rsvd_problem* pr, const void* A, const void* gU,
+                           const void* gS, const void* gV, void* gA) {
+  const rsvd_status s = kept_forward(c, L, pr, A, nullptr, c.at<void>(L.Sk), nullptr);
+  if (s != RSVD_OK) return s;
+  return adjoint_steps(c, L, pr, A, gU, gS, gV, gA);
+}
+
 struct Prologue {
   rsvd_status status;
   Plan plan;
@@ -858,6 +914,16 @@ struct BatchLayout {
   size_t total = 0;
 };
 
+// A batch of large matrices (4M elements or more on average) streams A with
+// the streaming kernels, one 128-row block of two waves per workgroup; for
+// many small matrices the general batched GEMM, with more rows per workgroup
+// and no packing pass, is faster.
+bool batch_streams(int32_t count, const rsvd_problem* probs) {
+  double elems = 0.0;
+  for (int32_t i = 0; i < count; ++i) elems += (double)probs[i].m * (double)probs[i].n;
+  return elems >= 4194304.0 * count;
+}
+
 rsvd_status batch_layout(int32_t count, const rsvd_problem* probs, BatchLayout& L) {
   if (count < 1 || !probs) return RSVD_E_INVAL;
   const rsvd_problem& p0 = probs[0];
@@ -867,9 +933,10 @@ rsvd_status batch_layout(int32_t count, const rsvd_problem* probs, BatchLayout& 
     if (probs[i].dtype != p0.dtype || probs[i].prec != p0.prec || probs[i].q != p0.q) return RSVD_E_INVAL;
     if (probs[i].sketch != RSVD_GAUSSIAN) return RSVD_E_UNSUPPORTED;
   }
+  const bool stream = batch_streams(count, probs);
   size_t off = 0;
   for (int32_t i = 0; i < count; ++i) {
-    const Plan P = make_plan(&probs[i], true);
+    const Plan P = make_plan(&probs[i], true, stream);
     const size_t es = (size_t)P.esize;
     L.q_off.push_back(off);
     off += align_up((size_t)P.m * P.l * es);
@@ -893,7 +960,7 @@ namespace {
 // problems and workspace are unchanged but whose caller buffers moved is
 // re-pointed by uploading new parameter blocks (from pinned staging memory, on
 // the caller's stream); the block maps and the graph stay.
-enum BatchKind { BATCH_FORWARD = 0, BATCH_BACKWARD = 1 };
+enum BatchKind { BATCH_FORWARD = 0, BATCH_BACKWARD = 1, BATCH_FORWARD_KEPT = 2, BATCH_ADJOINT_KEPT = 3 };
 
 struct SlotShape {
   int kind, dtype, prec, trans;
@@ -908,8 +975,7 @@ struct SlotShape {
 struct BatchPlan {
   int kind = BATCH_FORWARD;
   std::vector<rsvd_problem> probs;
-  std::vector<const void*> ptrs;  // the caller buffers of every problem
-  void* ws = nullptr;
+  std::vector<const void*> ptrs;  // the caller buffers of every problem, then the workspace
   std::vector<SlotShape> shape;
   size_t pbytes = 0;                // parameter blocks: tables[0, pbytes)
   void* tables = nullptr;           // device
@@ -1024,6 +1090,12 @@ hipError_t launch_slots(const Recorded& R, const char* dev, hipStream_t st) {
       case SK_COPY2D:
         e = launch_copy2d_batched((const Copy2dParams*)ps, bm, nb, st);
         break;
+      case SK_PACK:
+        e = launch_pack_x_batched(sl.prec, (const GemmParams*)ps, bm, nb, st);
+        break;
+      case SK_STREAM:
+        e = launch_stream_gemm_batched(sl.prec, sl.trans, (const GemmParams*)ps, bm, nb, st);
+        break;
     }
     if (e != hipSuccess) return e;
   }
@@ -1032,7 +1104,7 @@ hipError_t launch_slots(const Recorded& R, const char* dev, hipStream_t st) {
 
 // Upload the tables of a recorded batch and capture its launches in a graph.
 rsvd_status build_plan(rsvd_handle h, int kind, int32_t count, const rsvd_problem* probs,
-                       const std::vector<const void*>& ptrs, void* ws, const Recorded& R, BatchPlan*& out) {
+                       const std::vector<const void*>& ptrs, const Recorded& R, BatchPlan*& out) {
   std::vector<char> host(R.bytes, 0);
   write_params(R, host.data());
   for (size_t s = 0; s < R.slots.size(); ++s) {
@@ -1047,7 +1119,6 @@ rsvd_status build_plan(rsvd_handle h, int kind, int32_t count, const rsvd_proble
   bp->kind = kind;
   bp->probs.assign(probs, probs + count);
   bp->ptrs = ptrs;
-  bp->ws = ws;
   bp->shape = R.shape;
   bp->pbytes = R.pbytes;
   rsvd_status st = RSVD_OK;
@@ -1096,22 +1167,23 @@ bool repoint_plan(BatchPlan* bp, const Recorded& R, const std::vector<const void
   return true;
 }
 
-bool same_problems(const BatchPlan& bp, int kind, int32_t count, const rsvd_problem* probs, void* ws) {
-  return bp.kind == kind && bp.ws == ws && (int32_t)bp.probs.size() == count &&
+bool same_problems(const BatchPlan& bp, int kind, int32_t count, const rsvd_problem* probs) {
+  return bp.kind == kind && (int32_t)bp.probs.size() == count &&
          std::memcmp(bp.probs.data(), probs, sizeof(rsvd_problem) * (size_t)count) == 0;
 }
 
-// Replay the batch (kind, problems, workspace, caller buffers) on `stream`,
-// recording it first if the handle holds no plan for it.
+// Replay the batch (kind, problems; caller buffers and workspace) on `stream`,
+// recording it first if the handle holds no plan for these problems, and
+// re-pointing the plan if its buffers or workspace moved.
 rsvd_status run_batch(rsvd_handle h, int kind, int32_t count, const rsvd_problem* probs,
-                      const std::vector<const void*>& ptrs, void* ws, Recorder rec, const void* ctx,
-                      hipStream_t stream) {
+                      std::vector<const void*> ptrs, void* ws, Recorder rec, const void* ctx, hipStream_t stream) {
+  ptrs.push_back(ws);
   int32_t lmax = 1;
   for (int32_t i = 0; i < count; ++i) lmax = std::max<int32_t>(lmax, probs[i].k + probs[i].p);
   BatchPlan* bp = nullptr;
   size_t at = h->plans.size();
   for (size_t i = 0; i < h->plans.size(); ++i) {
-    if (!same_problems(*h->plans[i], kind, count, probs, ws)) continue;
+    if (!same_problems(*h->plans[i], kind, count, probs)) continue;
     at = i;
     if (h->plans[i]->ptrs == ptrs) break;
   }
@@ -1128,14 +1200,14 @@ rsvd_status run_batch(rsvd_handle h, int kind, int32_t count, const rsvd_problem
       if (!repoint_plan(bp, R, ptrs, stream)) {
         free_plan(bp);
         bp = nullptr;
-        const rsvd_status b = build_plan(h, kind, count, probs, ptrs, ws, R, bp);
+        const rsvd_status b = build_plan(h, kind, count, probs, ptrs, R, bp);
         if (b != RSVD_OK) return b;
       }
     }
   } else {
     Recorded R;
     rsvd_status s = record_batch(count, lmax, rec, ctx, R);
-    if (s == RSVD_OK) s = build_plan(h, kind, count, probs, ptrs, ws, R, bp);
+    if (s == RSVD_OK) s = build_plan(h, kind, count, probs, ptrs, R, bp);
     if (s != RSVD_OK) return s;
     if (h->plans.size() >= kMaxPlans) {
       free_plan(h->plans.front());
@@ -1189,10 +1261,11 @@ rsvd_status backward_batch_layout(int32_t count, const rsvd_problem* probs, Back
     if (probs[i].dtype != p0.dtype || probs[i].prec != p0.prec || probs[i].q != p0.q) return RSVD_E_INVAL;
     if (probs[i].sketch != RSVD_GAUSSIAN) return RSVD_E_UNSUPPORTED;
   }
+  const bool stream = batch_streams(count, probs);
   size_t off = 0;
   int64_t chunks = 1;
   for (int32_t i = 0; i < count; ++i) {
-    B.L.push_back(bwd_layout(&probs[i], true));
+    B.L.push_back(bwd_layout(&probs[i], true, stream));
     B.base.push_back(off);
     off += align_up(B.L.back().total);
     chunks = std::max(chunks, B.L.back().gA_chunks);
@@ -1217,6 +1290,63 @@ rsvd_status record_backward(const void* ctx, int32_t i, Runner& run) {
   const BwdLayout& L = b.B->L[u];
   const Ctx c{L.P, b.ws + b.B->base[u], nullptr, b.status, nullptr, &run};
   return backward_steps(c, L, &b.probs[u], b.A[u], b.gU[u], b.gS[u], b.gV[u], b.gA[u]);
+}
+
+rsvd_status record_adjoint_kept(const void* ctx, int32_t i, Runner& run) {
+  const BackwardRecord& b = *static_cast<const BackwardRecord*>(ctx);
+  const size_t u = (size_t)i;
+  const BwdLayout& L = b.B->L[u];
+  const Ctx c{L.P, b.ws + b.B->base[u], nullptr, b.status, nullptr, &run};
+  return adjoint_steps(c, L, &b.probs[u], b.A[u], b.gU[u], b.gS[u], b.gV[u], b.gA[u]);
+}
+
+// Kept forward batch: outputs U, S, V, the state in each problem's adjoint workspace.
+struct KeptForwardRecord {
+  const BackwardBatch* B;
+  const rsvd_problem* probs;
+  const void* const* A;
+  void* const *U, *const *S, *const *V;
+  char* ws;
+  int32_t* status;
+};
+
+rsvd_status record_forward_kept(const void* ctx, int32_t i, Runner& run) {
+  const KeptForwardRecord& f = *static_cast<const KeptForwardRecord*>(ctx);
+  const size_t u = (size_t)i;
+  const BwdLayout& L = f.B->L[u];
+  const Ctx c{L.P, f.ws + f.B->base[u], nullptr, f.status, nullptr, &run};
+  return kept_forward(c, L, &f.probs[u], f.A[u], f.U[u], f.S[u], f.V[u]);
+}
+
+rsvd_status backward_batched_call(rsvd_handle h, int32_t count, const rsvd_problem* probs, const void* const* A,
+                                  const void* const* gU, const void* const* gS, const void* const* gV,
+                                  void* const* gA, void* ws, size_t ws_bytes, hipStream_t stream, bool kept) {
+  if (!h || !A || !gU || !gS || !gV || !gA) return RSVD_E_INVAL;
+  BackwardBatch B;
+  const rsvd_status v = backward_batch_layout(count, probs, B);
+  if (v != RSVD_OK) return v;
+  if (!ws || ws_bytes < B.total || !aligned16(ws)) return RSVD_E_WORKSPACE;
+  std::vector<const void*> ptrs;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!A[i] || !gU[i] || !gS[i] || !gV[i] || !gA[i]) return RSVD_E_INVAL;
+    ptrs.insert(ptrs.end(), {A[i], gU[i], gS[i], gV[i], gA[i]});
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
+  const BackwardRecord r{&B, probs, A, gU, gS, gV, gA, static_cast<char*>(ws), h->status};
+  return run_batch(h, kept ? BATCH_ADJOINT_KEPT : BATCH_BACKWARD, count, probs, ptrs, ws,
+                   kept ? record_adjoint_kept : record_backward, &r, stream);
+}
+
+// Shared checks of the single-problem adjoint entry points.
+rsvd_status adjoint_prologue(rsvd_handle h, const rsvd_problem* pr, void* ws, size_t ws_bytes, BwdLayout& L) {
+  if (!h) return RSVD_E_INVAL;
+  const rsvd_status v = validate(pr);
+  if (v != RSVD_OK) return v;
+  if (pr->sketch != RSVD_GAUSSIAN) return RSVD_E_UNSUPPORTED;
+  L = bwd_layout(pr);
+  if (!ws || ws_bytes < L.total || !aligned16(ws)) return RSVD_E_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
+  return RSVD_OK;
 }
 
 }  // namespace
@@ -1371,17 +1501,36 @@ size_t rsvd_backward_workspace_bytes(const rsvd_problem* problem) {
 
 rsvd_status rsvd_backward(rsvd_handle h, const rsvd_problem* pr, const void* A, const void* gU, const void* gS,
                           const void* gV, void* gA, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (!h) return RSVD_E_INVAL;
-  const rsvd_status v = validate(pr);
-  if (v != RSVD_OK) return v;
-  if (pr->sketch != RSVD_GAUSSIAN) return RSVD_E_UNSUPPORTED;
   if (!A || !gU || !gS || !gV || !gA) return RSVD_E_INVAL;
-  const BwdLayout L = bwd_layout(pr);
-  if (!ws || ws_bytes < L.total || !aligned16(ws)) return RSVD_E_WORKSPACE;
-  if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
+  BwdLayout L;
+  const rsvd_status v = adjoint_prologue(h, pr, ws, ws_bytes, L);
+  if (v != RSVD_OK) return v;
   DirectRunner dr(h, stream);
   const Ctx c{L.P, static_cast<char*>(ws), stream, h->status, h, &dr};
   return backward_steps(c, L, pr, A, gU, gS, gV, gA);
+}
+
+rsvd_status rsvd_forward_kept(rsvd_handle h, const rsvd_problem* pr, const void* A, void* U, void* S, void* V,
+                              void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!A || !U || !S || !V) return RSVD_E_INVAL;
+  BwdLayout L;
+  const rsvd_status v = adjoint_prologue(h, pr, ws, ws_bytes, L);
+  if (v != RSVD_OK) return v;
+  DirectRunner dr(h, stream);
+  const Ctx c{L.P, static_cast<char*>(ws), stream, h->status, h, &dr};
+  return kept_forward(c, L, pr, A, U, S, V);
+}
+
+rsvd_status rsvd_backward_kept(rsvd_handle h, const rsvd_problem* pr, const void* A, const void* gU,
+                               const void* gS, const void* gV, void* gA, void* ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  if (!A || !gU || !gS || !gV || !gA) return RSVD_E_INVAL;
+  BwdLayout L;
+  const rsvd_status v = adjoint_prologue(h, pr, ws, ws_bytes, L);
+  if (v != RSVD_OK) return v;
+  DirectRunner dr(h, stream);
+  const Ctx c{L.P, static_cast<char*>(ws), stream, h->status, h, &dr};
+  return adjoint_steps(c, L, pr, A, gU, gS, gV, gA);
 }
 
 size_t rsvd_batched_workspace_bytes(int32_t count, const rsvd_problem* probs) {
@@ -1417,19 +1566,32 @@ size_t rsvd_backward_batched_workspace_bytes(int32_t count, const rsvd_problem* 
 rsvd_status rsvd_backward_batched(rsvd_handle h, int32_t count, const rsvd_problem* probs, const void* const* A,
                                   const void* const* gU, const void* const* gS, const void* const* gV,
                                   void* const* gA, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (!h || !A || !gU || !gS || !gV || !gA) return RSVD_E_INVAL;
+  return backward_batched_call(h, count, probs, A, gU, gS, gV, gA, ws, ws_bytes, stream, false);
+}
+
+rsvd_status rsvd_batched_kept(rsvd_handle h, int32_t count, const rsvd_problem* probs, const void* const* A,
+                              void* const* U, void* const* S, void* const* V, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  if (!h || !A || !U || !S || !V) return RSVD_E_INVAL;
   BackwardBatch B;
   const rsvd_status v = backward_batch_layout(count, probs, B);
   if (v != RSVD_OK) return v;
   if (!ws || ws_bytes < B.total || !aligned16(ws)) return RSVD_E_WORKSPACE;
   std::vector<const void*> ptrs;
   for (int32_t i = 0; i < count; ++i) {
-    if (!A[i] || !gU[i] || !gS[i] || !gV[i] || !gA[i]) return RSVD_E_INVAL;
-    ptrs.insert(ptrs.end(), {A[i], gU[i], gS[i], gV[i], gA[i]});
+    if (!A[i] || !U[i] || !S[i] || !V[i]) return RSVD_E_INVAL;
+    ptrs.insert(ptrs.end(), {A[i], U[i], S[i], V[i]});
   }
   if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
-  const BackwardRecord r{&B, probs, A, gU, gS, gV, gA, static_cast<char*>(ws), h->status};
-  return run_batch(h, BATCH_BACKWARD, count, probs, ptrs, ws, record_backward, &r, stream);
+  const KeptForwardRecord r{&B, probs, A, U, S, V, static_cast<char*>(ws), h->status};
+  return run_batch(h, BATCH_FORWARD_KEPT, count, probs, ptrs, ws, record_forward_kept, &r, stream);
+}
+
+rsvd_status rsvd_backward_batched_kept(rsvd_handle h, int32_t count, const rsvd_problem* probs,
+                                       const void* const* A, const void* const* gU, const void* const* gS,
+                                       const void* const* gV, void* const* gA, void* ws, size_t ws_bytes,
+                                       hipStream_t stream) {
+  return backward_batched_call(h, count, probs, A, gU, gS, gV, gA, ws, ws_bytes, stream, true);
 }
 
 rsvd_status rsvd_draw_omega(rsvd_handle h, const rsvd_problem* pr, void* Omega, hipStream_t stream) {

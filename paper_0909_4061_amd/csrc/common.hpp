@@ -44,6 +44,7 @@ struct GemmParams {
   int32_t accum;        // 1: out += op(A) X (S == 1 only); 0: out = op(A) X
   const int32_t* gate;  // if non-null and *gate == 0 the kernel does nothing
   int32_t narrow;       // FP32 native, S == 1, K <= 256: 32-row blocks (more workgroups for one product)
+  void* pack;           // the A-streaming kernels: X packed by pack_x (stream_pack_bytes(K, Lp) bytes)
 };
 
 // Tile geometry of each GEMM variant (rows of C per workgroup, K per stage).
@@ -55,8 +56,9 @@ hipError_t launch_gemm(int dtype, int prec, bool trans, const GemmParams& p, hip
 // FP32-data GEMMs that stream A (FP32 MFMA or BF16 / bf16x3 MFMA): X is first
 // packed into `pack` (stream_pack_bytes(K, Lp) bytes) by a small kernel.
 int64_t stream_pack_bytes(int64_t K, int32_t Lp);
-hipError_t launch_pack_x(int prec, const GemmParams& p, void* pack, hipStream_t st);
-hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, const void* pack, hipStream_t st);
+bool stream_params_ok(const GemmParams& p);
+hipError_t launch_pack_x(int prec, const GemmParams& p, hipStream_t st);
+hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Gram matrices and CholeskyQR.
@@ -212,6 +214,12 @@ hipError_t launch_trmm_batched(const TrmmParams* ps, const BlockMap* bm, int64_t
 hipError_t launch_copy_batched(const CopyParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
 hipError_t launch_sum_parts_batched(int dtype, const GramParams* ps, const BlockMap* bm, int64_t nblocks,
                                     hipStream_t st);
+int64_t pack_x_blocks(const GemmParams& p);
+int64_t stream_gemm_blocks(const GemmParams& p);
+hipError_t launch_pack_x_batched(int prec, const GemmParams* ps, const BlockMap* bm, int64_t nblocks,
+                                 hipStream_t st);
+hipError_t launch_stream_gemm_batched(int prec, bool trans, const GemmParams* ps, const BlockMap* bm,
+                                      int64_t nblocks, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Adjoint pieces (l x l algebra in FP64, strided copies).

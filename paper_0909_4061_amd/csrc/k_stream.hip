@@ -40,13 +40,14 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // into LDS, then written as Lp columns of 32 consecutive k -- FP32 rows of Lp
 // (plain) or 16-byte runs of bf16 hi and lo planes (split).
 template <bool SPLIT>
-__global__ __launch_bounds__(256) void pack_x_kernel(const float* __restrict__ X, int64_t K, int64_t ldx,
-                                                     int32_t ncols, int32_t Lp, int64_t Kpad, void* __restrict__ out,
-                                                     const int32_t* gate) {
+__device__ __forceinline__ void pack_x_body(const GemmParams& p, const int64_t kt) {
   __shared__ float tile[32][128 + 1];
-  if (gate && *gate == 0) return;
+  if (p.gate && *p.gate == 0) return;
+  const float* __restrict__ X = (const float*)p.X;
+  const int64_t K = p.K, ldx = p.ldx, Kpad = (p.K + SBK - 1) / SBK * SBK;
+  const int32_t ncols = p.ncols, Lp = p.Lp;
+  void* __restrict__ out = p.pack;
   const int tid = threadIdx.x;
-  const int64_t kt = blockIdx.x;
   for (int idx = tid; idx < 32 * Lp; idx += 256) {
     const int kk = idx / Lp, c = idx - kk * Lp;
     const int64_t k = kt * 32 + kk;
@@ -77,6 +78,17 @@ __global__ __launch_bounds__(256) void pack_x_kernel(const float* __restrict__ X
       *reinterpret_cast<bf16x8*>(lo + o) = l;
     }
   }
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void pack_x_kernel(const GemmParams p) { pack_x_body<SPLIT>(p, blockIdx.x); }
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void pack_x_batched(const GemmParams* __restrict__ ps,
+                                                      const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  const GemmParams p = ps[b.item];
+  pack_x_body<SPLIT>(p, b.local);
 }
 
 __device__ inline void split4(const f32x4 v, u32x2& hi, u32x2& lo) {
@@ -179,8 +191,8 @@ __device__ inline void load_a_full(const GemmParams& p, int64_t i0, int64_t k0, 
 // A[r][8 g + t] and B[8 g + t][r], t = 0..7; result register e holds
 // C[8 (e / 4) + 4 g + e % 4][r].
 template <bool TRANS, int NP>
-__global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_bf16_kernel(const GemmParams p, const __bf16* __restrict__ xh,
-                                                                  const __bf16* __restrict__ xl) {
+__device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf16* __restrict__ xh,
+                                                 const __bf16* __restrict__ xl, const int bid) {
   constexpr int APLANE = SBM * BPAD;  // bf16 elements per A plane per buffer
   constexpr int XPLANE = 128 * BPAD;
   __shared__ __attribute__((aligned(16))) __bf16 sAh[2][APLANE];
@@ -191,8 +203,8 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int S = p.S;
-  const int s = blockIdx.x % S;
-  const int64_t i0 = (int64_t)(blockIdx.x / S) * SBM;
+  const int s = bid % S;
+  const int64_t i0 = (int64_t)(bid / S) * SBM;
   const int64_t kbeg = (int64_t)s * p.kchunk;
   const int64_t kend = min(p.K, kbeg + p.kchunk);
   const int NT = p.Lp / 32;
@@ -357,11 +369,27 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
   }
 }
 
+template <bool TRANS, int NP>
+__global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_bf16_kernel(
+    const GemmParams p, const __bf16* __restrict__ xh, const __bf16* __restrict__ xl) {
+  stream_bf16_body<TRANS, NP>(p, xh, xl, blockIdx.x);
+}
+
+// Batched: problem bm[b].item, its own packed X (hi plane, then lo plane) at p.pack.
+template <bool TRANS, int NP>
+__global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_bf16_batched(
+    const GemmParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  const GemmParams p = ps[b.item];
+  const __bf16* xh = (const __bf16*)p.pack;
+  stream_bf16_body<TRANS, NP>(p, xh, xh + (p.K + SBK - 1) / SBK * SBK * p.Lp, b.local);
+}
+
 // ---- FP32 ---------------------------------------------------------------
 // MFMA v_mfma_f32_32x32x2f32: lane (r, g) supplies A[r][g] and B[g][r]; K is
 // walked two at a time (k = 2 ks + g).
 template <bool TRANS>
-__global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_f32_kernel(const GemmParams p, const float* __restrict__ xp) {
+__device__ __forceinline__ void stream_f32_body(const GemmParams& p, const float* __restrict__ xp, const int bid) {
   constexpr int ALD = TRANS ? SBM + 4 : SBK + 1;
   constexpr int ASZ = TRANS ? SBK * (SBM + 4) : SBM * (SBK + 1);
   constexpr int XLD = 128 + 4;
@@ -371,8 +399,8 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int S = p.S;
-  const int s = blockIdx.x % S;
-  const int64_t i0 = (int64_t)(blockIdx.x / S) * SBM;
+  const int s = bid % S;
+  const int64_t i0 = (int64_t)(bid / S) * SBM;
   const int64_t kbeg = (int64_t)s * p.kchunk;
   const int64_t kend = min(p.K, kbeg + p.kchunk);
   const int NT = p.Lp / 32;
@@ -488,6 +516,20 @@ __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 
   }
 }
 
+template <bool TRANS>
+__global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_f32_kernel(
+    const GemmParams p, const float* __restrict__ xp) {
+  stream_f32_body<TRANS>(p, xp, blockIdx.x);
+}
+
+template <bool TRANS>
+__global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_f32_batched(
+    const GemmParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  const GemmParams p = ps[b.item];
+  stream_f32_body<TRANS>(p, (const float*)p.pack, b.local);
+}
+
 }  // namespace
 
 int64_t stream_pack_bytes(int64_t K, int32_t Lp) {
@@ -495,27 +537,31 @@ int64_t stream_pack_bytes(int64_t K, int32_t Lp) {
   return Kpad * Lp * 4;  // FP32, or two BF16 planes
 }
 
-hipError_t launch_pack_x(int prec, const GemmParams& p, void* pack, hipStream_t st) {
-  if (p.ncols > 128 || p.Lp > 128 || p.Lp % 32 != 0 || p.Lp < p.ncols) return hipErrorInvalidValue;
-  const int64_t Kpad = (p.K + SBK - 1) / SBK * SBK;
-  const dim3 pgrid((unsigned)(Kpad / SBK));
+bool stream_params_ok(const GemmParams& p) {
+  return p.ncols <= 128 && p.Lp <= 128 && p.Lp % 32 == 0 && p.Lp >= p.ncols && p.S >= 1;
+}
+
+int64_t pack_x_blocks(const GemmParams& p) { return (p.K + SBK - 1) / SBK; }
+
+int64_t stream_gemm_blocks(const GemmParams& p) { return p.rows <= 0 ? 0 : (p.rows + SBM - 1) / SBM * p.S; }
+
+hipError_t launch_pack_x(int prec, const GemmParams& p, hipStream_t st) {
+  if (!stream_params_ok(p)) return hipErrorInvalidValue;
+  const dim3 pgrid((unsigned)pack_x_blocks(p));
   if (prec != PREC_NATIVE)
-    hipLaunchKernelGGL(pack_x_kernel<true>, pgrid, dim3(256), 0, st, (const float*)p.X, p.K, p.ldx, p.ncols, p.Lp,
-                       Kpad, pack, p.gate);
+    hipLaunchKernelGGL(pack_x_kernel<true>, pgrid, dim3(256), 0, st, p);
   else
-    hipLaunchKernelGGL(pack_x_kernel<false>, pgrid, dim3(256), 0, st, (const float*)p.X, p.K, p.ldx, p.ncols, p.Lp,
-                       Kpad, pack, p.gate);
+    hipLaunchKernelGGL(pack_x_kernel<false>, pgrid, dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
-hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, const void* pack, hipStream_t st) {
+hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, hipStream_t st) {
   if (p.rows <= 0) return hipSuccess;
-  if (p.ncols > 128 || p.Lp > 128 || p.Lp % 32 != 0 || p.Lp < p.ncols || p.S < 1) return hipErrorInvalidValue;
+  if (!stream_params_ok(p)) return hipErrorInvalidValue;
   const int64_t Kpad = (p.K + SBK - 1) / SBK * SBK;
   const int64_t nel = Kpad * p.Lp;
-  const int64_t nrb = (p.rows + SBM - 1) / SBM;
-  const dim3 grid((unsigned)(nrb * p.S)), block(STHREADS);
-  const __bf16* xh = (const __bf16*)pack;
+  const dim3 grid((unsigned)stream_gemm_blocks(p)), block(STHREADS);
+  const __bf16* xh = (const __bf16*)p.pack;
   const __bf16* xl = xh + nel;
   if (prec == PREC_BF16X3) {
     if (trans)
@@ -529,9 +575,43 @@ hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, const v
       hipLaunchKernelGGL((stream_bf16_kernel<false, 1>), grid, block, 0, st, p, xh, xl);
   } else {
     if (trans)
-      hipLaunchKernelGGL(stream_f32_kernel<true>, grid, block, 0, st, p, (const float*)pack);
+      hipLaunchKernelGGL(stream_f32_kernel<true>, grid, block, 0, st, p, (const float*)p.pack);
     else
-      hipLaunchKernelGGL(stream_f32_kernel<false>, grid, block, 0, st, p, (const float*)pack);
+      hipLaunchKernelGGL(stream_f32_kernel<false>, grid, block, 0, st, p, (const float*)p.pack);
+  }
+  return hipGetLastError();
+}
+
+// Batched launches (parameters checked when each problem was recorded).
+hipError_t launch_pack_x_batched(int prec, const GemmParams* ps, const BlockMap* bm, int64_t nblocks,
+                                 hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (prec != PREC_NATIVE)
+    hipLaunchKernelGGL(pack_x_batched<true>, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  else
+    hipLaunchKernelGGL(pack_x_batched<false>, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_gemm_batched(int prec, bool trans, const GemmParams* ps, const BlockMap* bm,
+                                      int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nblocks), block(STHREADS);
+  if (prec == PREC_BF16X3) {
+    if (trans)
+      hipLaunchKernelGGL((stream_bf16_batched<true, 3>), grid, block, 0, st, ps, bm);
+    else
+      hipLaunchKernelGGL((stream_bf16_batched<false, 3>), grid, block, 0, st, ps, bm);
+  } else if (prec == PREC_BF16) {
+    if (trans)
+      hipLaunchKernelGGL((stream_bf16_batched<true, 1>), grid, block, 0, st, ps, bm);
+    else
+      hipLaunchKernelGGL((stream_bf16_batched<false, 1>), grid, block, 0, st, ps, bm);
+  } else {
+    if (trans)
+      hipLaunchKernelGGL(stream_f32_batched<true>, grid, block, 0, st, ps, bm);
+    else
+      hipLaunchKernelGGL(stream_f32_batched<false>, grid, block, 0, st, ps, bm);
   }
   return hipGetLastError();
 }

@@ -122,3 +122,25 @@ def test_backward_matches_finite_differences_of_gpu_forward():
         fd = (loss(A + h * E) - loss(A - h * E)) / (2 * h)
         an = float(np.sum(G * to_np(E)))
         assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+@pytest.mark.parametrize("dtype,prec", [(torch.float64, "native"), (torch.float32, "bf16x3")])
+def test_kept_forward_state_matches_recomputation(dtype, prec):
+    # rsvd_forward_kept returns the hot-path outputs and rsvd_backward_kept, which
+    # skips the recomputation, the same gA bit for bit, also when called twice
+    m, n, k, p, q = 700, 300, 12, 8, 2
+    A64 = build_matrix(m, n, spectrum("invsqrt", n), seed=14,
+                       dtype=np.float32 if dtype == torch.float32 else np.float64)
+    A = torch.from_numpy(A64).to(DEV)
+    rng = np.random.default_rng(14)
+    gU = torch.from_numpy(rng.standard_normal((m, k))).to(DEV, dtype)
+    gS = torch.from_numpy(rng.standard_normal(k)).to(DEV, dtype)
+    gV = torch.from_numpy(rng.standard_normal((n, k))).to(DEV, dtype)
+    U0, S0, V0 = rs.rsvd(A, k, p, q, seed=6, prec=prec)
+    U, S, V, ws = rs.rsvd_forward_kept(A, k, p, q, seed=6, prec=prec)
+    g_re = rs.rsvd_backward(A, gU, gS, gV, k, p, q, seed=6, prec=prec)
+    g1 = rs.rsvd_backward_kept(A, gU, gS, gV, k, p, q, ws, seed=6, prec=prec)
+    g2 = rs.rsvd_backward_kept(A, gU, gS, gV, k, p, q, ws, seed=6, prec=prec)
+    torch.cuda.synchronize()
+    for a, b in ((U, U0), (S, S0), (V, V0), (g1, g_re), (g2, g_re)):
+        assert torch.equal(a, b)

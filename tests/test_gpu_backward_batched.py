@@ -151,3 +151,26 @@ def test_backward_batched_full_size_differentiable_workload():
     Gref = _reference(As[1], k, p, q, seed, 1, Ts[1], ws[1], torch.float32)
     err = _rel(grads[1], Gref)
     assert err <= 64.0 * (k + p) * UNIT[torch.float32], err
+
+
+def test_backward_batched_kept_matches_recomputation():
+    # the kept batched forward returns rsvd_batched's outputs and the kept adjoint
+    # the recomputing adjoint's gA, bit for bit
+    shapes = [(400, 300, 10), (200, 150, 6), (900, 700, 20)]
+    p, q, seed = 6, 1, 8
+    ks = [s[2] for s in shapes]
+    As, _, _ = _inputs(shapes, torch.float32, seed0=120)
+    rng = np.random.default_rng(8)
+    gUs = [torch.from_numpy(rng.standard_normal((A.shape[0], k))).to(DEV, torch.float32) for A, k in zip(As, ks)]
+    gSs = [torch.from_numpy(rng.standard_normal(k)).to(DEV, torch.float32) for k in ks]
+    gVs = [torch.from_numpy(rng.standard_normal((A.shape[1], k))).to(DEV, torch.float32) for A, k in zip(As, ks)]
+    ref = rs.rsvd_batched(As, ks, p=p, q=q, seed=seed)
+    outs, ws = rs.rsvd_batched_kept(As, ks, p, q, seed=seed)
+    g_re = rs.rsvd_backward_batched(As, gUs, gSs, gVs, ks, p, q, seed=seed)
+    g_kept = rs.rsvd_backward_batched_kept(As, gUs, gSs, gVs, ks, p, q, ws, seed=seed)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        for a, b in zip(o, r):
+            assert torch.equal(a, b)
+    for a, b in zip(g_kept, g_re):
+        assert torch.equal(a, b)

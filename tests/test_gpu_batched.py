@@ -90,6 +90,19 @@ def test_batched_fp32_uneven_shapes():
     _check(As, outs, ks, 8, 1, 11, fp64=False)
 
 
+@pytest.mark.parametrize("prec", ["native", "bf16x3"])
+def test_batched_fp32_large_matrices_streaming_kernels(prec):
+    # 4M elements or more on average: the batch takes the A-streaming kernels
+    # (packed X, ragged row blocks and K tails in both products)
+    shapes = [(4100, 1030, 40, 30.0), (2600, 1800, 64, 50.0)]
+    As = _matrices(shapes, torch.float32, seed0=70)
+    ks = [s[2] for s in shapes]
+    outs = rs.rsvd_batched(As, ks, p=8, q=1, seed=13, prec=prec)
+    torch.cuda.synchronize()
+    assert _flags_ok()
+    _check(As, outs, ks, 8, 1, 13, fp64=False)
+
+
 def test_batched_fp64_edge_shapes():
     # l = min(m, n), fewer rows than one GEMM tile, a single-column target, n = m
     shapes = [(200, 100, 92, 5.0), (37, 20, 12, 3.0), (64, 64, 1, 8.0), (300, 300, 40, 20.0), (129, 65, 9, 2.0)]
