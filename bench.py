@@ -31,10 +31,10 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the streaming GEMMs (scaled FETCH_SIZE + WRITE_SIZE from rocprofv3
 # counter runs, profiles/stream_gemm_power_iteration_16384x8192_hbm_counters.md), valid only for
 # the kernel source they were measured on and the 16384 x 8192, l = 120 shape.
-TRAFFIC_KERNEL_SHA = "33f16fc0cf7ceb52"
+TRAFFIC_KERNEL_SHA = "e2ebc1dc9472b5e4"
 TRAFFIC_SHAPE = (16384, 8192, 120)
-TRAFFIC_BYTES = {"stream_tn_bf16x3": 580171807, "stream_nn_bf16x3": 580637689,
-                 "stream_tn_native": 579491926, "stream_nn_native": 579805449}
+TRAFFIC_BYTES = {"stream_tn_bf16x3": 579447830, "stream_nn_bf16x3": 579850646,
+                 "stream_tn_native": 579487764, "stream_nn_native": 579720606}
 # The same for the SRFT row-FFT kernel at 32768 x 16384, l = 128
 # (profiles/srft_sketch_32768x16384_hbm_counters.md).
 SRFT_TRAFFIC_SHA = "2b16782d46e9052b"
