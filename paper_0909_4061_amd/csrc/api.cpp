@@ -111,7 +111,9 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   P.esize = pr->dtype == RSVD_F64 ? 8 : 4;
   P.stream = stream && pr->dtype == RSVD_F32;
   const GemmTile big = gemm_tile(pr->dtype, pr->prec);
-  P.Lp = (int32_t)round_up(P.l, big.lp_mult);
+  // padded width of the A-streaming products' X and split-K partials (128 for
+  // the BF16 streaming kernels, see gemm())
+  P.Lp = (P.stream && pr->prec != RSVD_NATIVE) ? 128 : (int32_t)round_up(P.l, big.lp_mult);
   P.Lg = (int32_t)round_up(P.l, 16);
   P.nn = batched ? no_split(P.n) : choose_split(P.m, P.n, big);
   P.tn = batched ? no_split(P.m) : choose_split(P.n, P.m, big);
@@ -130,7 +132,7 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   P.part = take((size_t)part_elems * es);
   P.Y = take((size_t)P.Mx * P.l * es);
   P.Qt = take((size_t)P.n * P.l * es);
-  P.pack = take(P.stream ? (size_t)stream_pack_bytes(P.Mx, round_up(P.l, 32)) : 0);
+  P.pack = take(P.stream ? (size_t)stream_pack_bytes(P.Mx, 128) : 0);
   P.gpart = take((size_t)ceil_div(P.Mx, GRAM_ROWS) * P.Lg * P.Lg * 8);
   P.G = take((size_t)P.Lg * P.Lg * 8);
   P.R1 = take(ll8);
@@ -380,7 +382,12 @@ rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda,
   if (accum && (g.S > 1 || streams_a)) return RSVD_E_INVAL;
   const int kind = streams_a ? (trans ? RSVD_KERNEL_STREAM_TN : RSVD_KERNEL_STREAM_NN) : RSVD_KERNEL_SMALL_GEMM;
   if (streams_a && c.P.stream) {
-    g.Lp = (int32_t)round_up(ncols, 32);
+    // BF16 products pad X to 128 columns: the streaming kernel's branch-free
+    // steady-state loop needs all four 32-column tiles, and these products are
+    // bound by HBM, not by the padded MFMA work.  FP32 products are bound by
+    // the MFMA rate and keep the 32-column rounding.
+    g.Lp = prec == RSVD_NATIVE ? (int32_t)round_up(ncols, 32) : 128;
+    if (g.S > 1 && g.Lp != c.P.Lp) return RSVD_E_INVAL;  // partials are read with the plan's width
     g.pack = c.at<void>(c.P.pack);
     RSVD_TRY(c.run->pack_x(prec, g));
     RSVD_TRY(c.run->stream_gemm(prec, trans, g, kind));
