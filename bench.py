@@ -31,10 +31,10 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the streaming GEMMs (scaled FETCH_SIZE + WRITE_SIZE from rocprofv3
 # counter runs, profiles/stream_gemm_power_iteration_16384x8192_hbm_counters.md), valid only for
 # the kernel source they were measured on and the 16384 x 8192, l = 120 shape.
-TRAFFIC_KERNEL_SHA = "e2ebc1dc9472b5e4"
+TRAFFIC_KERNEL_SHA = "2d8512d5f3de71f7"
 TRAFFIC_SHAPE = (16384, 8192, 120)
-TRAFFIC_BYTES = {"stream_tn_bf16x3": 579447830, "stream_nn_bf16x3": 579850646,
-                 "stream_tn_native": 579487764, "stream_nn_native": 579720606}
+TRAFFIC_BYTES = {"stream_tn_bf16x3": 579480805, "stream_nn_bf16x3": 579902255,
+                 "stream_tn_native": 579489406, "stream_nn_native": 579685386}
 # The same for the SRFT row-FFT kernel at 32768 x 16384, l = 128
 # (profiles/srft_sketch_32768x16384_hbm_counters.md).
 SRFT_TRAFFIC_SHA = "2b16782d46e9052b"
@@ -364,14 +364,23 @@ def main_differentiable(args):
     if T3 is not None:
         del Ts[:]
 
+    # ||U S V^T - T||_F^2 = tr(U^T U S V^T V S) - 2 sum_j s_j u_j^T T v_j + ||T||_F^2 for any U, V:
+    # the same loss (and the same gradients in U, S, V) from one (m x n)(n x k) product per
+    # matrix instead of the m x n residual.
+    T3sq = T3.square().sum() if T3 is not None else None
+
     def step_batched():
         leaves = [A.detach().requires_grad_(True) for A in As]
         outs = rs.rsvd_batched(leaves, k, p=p, q=q, seed=args.seed, prec=prec)
         U3 = torch.stack([o[0] for o in outs])
         S3 = torch.stack([o[1] for o in outs])
         V3 = torch.stack([o[2] for o in outs])
-        R = torch.bmm(U3 * S3[:, None, :], V3.transpose(1, 2).contiguous()) - T3
-        L = R.square().sum() + (W3 * S3).sum()
+        TV = torch.bmm(T3, V3)  # m x k per matrix
+        GU = torch.bmm(U3.transpose(1, 2).contiguous(), U3)
+        GV = torch.bmm(V3.transpose(1, 2).contiguous(), V3)
+        quad = (GU * GV * (S3[:, :, None] * S3[:, None, :])).sum()
+        cross = (S3 * (U3 * TV).sum(dim=1)).sum()
+        L = quad - 2.0 * cross + T3sq + (W3 * S3).sum()
         L.backward()
         return [x.grad for x in leaves]
 

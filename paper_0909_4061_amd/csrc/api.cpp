@@ -275,12 +275,12 @@ class RecordRunner final : public Runner {
     return add(SK_GEMM, dtype, prec, trans, p, p.rows > 0 ? gemm_blocks(dtype, prec, p) : 0);
   }
   hipError_t pack_x(int prec, const GemmParams& p) override {
-    if (!stream_params_ok(p)) return hipErrorInvalidValue;
+    if (!stream_params_ok(prec, p)) return hipErrorInvalidValue;
     return add(SK_PACK, 0, prec, false, p, p.rows > 0 ? pack_x_blocks(p) : 0);
   }
   hipError_t stream_gemm(int prec, bool trans, const GemmParams& p, int) override {
-    if (!stream_params_ok(p)) return hipErrorInvalidValue;
-    return add(SK_STREAM, 0, prec, trans, p, stream_gemm_blocks(p));
+    if (!stream_params_ok(prec, p)) return hipErrorInvalidValue;
+    return add(SK_STREAM, p.wide, prec, trans, p, stream_gemm_blocks(p));  // the dtype slot holds `wide`
   }
   hipError_t gram_partial(int dtype, const GramParams& p) override {
     return add(SK_GRAM_PARTIAL, dtype, 0, false, p, p.rows > 0 ? gram_partial_blocks(p) : 0);
@@ -357,7 +357,8 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 // the result is left as partial products; otherwise it is written to `out`.
 rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda, int64_t rows, int64_t K,
                  const void* X, int64_t ldx, int32_t ncols, void* out, int64_t ldo, const Split& sp, void* part,
-                 const int32_t* gate, bool streams_a = false, bool accum = false) {
+                 const int32_t* gate, bool streams_a = false, bool accum = false, void* pack = nullptr,
+                 bool wide = false) {
   const GemmTile t = gemm_tile(c.P.dtype, prec);
   GemmParams g{};
   g.A = A;
@@ -386,9 +387,10 @@ rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda,
     // steady-state loop needs all four 32-column tiles, and these products are
     // bound by HBM, not by the padded MFMA work.  FP32 products are bound by
     // the MFMA rate and keep the 32-column rounding.
-    g.Lp = prec == RSVD_NATIVE ? (int32_t)round_up(ncols, 32) : 128;
+    g.wide = wide && prec != RSVD_NATIVE ? 1 : 0;
+    g.Lp = prec == RSVD_NATIVE ? (int32_t)round_up(ncols, 32) : (int32_t)round_up(std::max(ncols, 128), 128);
     if (g.S > 1 && g.Lp != c.P.Lp) return RSVD_E_INVAL;  // partials are read with the plan's width
-    g.pack = c.at<void>(c.P.pack);
+    g.pack = pack ? pack : c.at<void>(c.P.pack);
     RSVD_TRY(c.run->pack_x(prec, g));
     RSVD_TRY(c.run->stream_gemm(prec, trans, g, kind));
   } else {
@@ -610,7 +612,7 @@ struct BwdLayout {
   int64_t Kc;         // (2q + 2) l
   int64_t gA_chunks;  // 128-column launches of gA = Left RightT (a batch pads to its widest problem)
   size_t Qs, Qts, Rs, Rts, Bt, gBt, gQ, gQt, gYt, T1, T2, Mq, Z, W1, M1p64, UhT, Rinv, Sy, W64, SW64, M2_64, Ukt64,
-      M1p, W, SW, M2, Ukt, Sk, Left, RightT, part, total;
+      M1p, W, SW, M2, Ukt, Sk, Left, RightT, part, gApack, total;
 };
 
 constexpr int64_t kBwdMaxSplit = 16;  // K chunks of the adjoint's transposed products
@@ -662,6 +664,10 @@ BwdLayout bwd_layout(const rsvd_problem* pr, bool batched = false, bool stream =
   L.Left = take((size_t)(P.m * L.Kc) * es);
   L.RightT = take((size_t)(L.Kc * P.n) * es);
   L.part = take((size_t)kBwdMaxSplit * P.l * 128 * es);  // split-K partials, rows <= l, Lp <= 128
+  // packed RightT for the streaming launches of gA: K = Kc rows, all columns at
+  // once (BF16 products) or 128 per launch (FP32)
+  const int32_t gA_lp = P.prec != RSVD_NATIVE ? (int32_t)round_up(P.n, 128) : 128;
+  L.gApack = take(P.stream ? (size_t)stream_pack_bytes(L.Kc, gA_lp) : 0);
   L.total = off;
   return L;
 }
@@ -868,13 +874,19 @@ rsvd_status adjoint_steps(const Ctx& c, const BwdLayout& L, const rsvd_problem* 
     s = copy2d(c, c.at<void>(P.omega), dt, l, rightT + (size_t)(blk * l * n) * es, dt, n, n, l, true);
   if (s != RSVD_OK) return s;
 
-  // --- gA = Left RightT, 128 columns at a time
+  // --- gA = Left RightT.  BF16 products: one streaming launch over every
+  // 128-column chunk (RightT packed once); otherwise 128 columns per launch
+  // (FP32 data: the streaming kernels, K = (2q + 2) l in whole 32-deep stages).
+  if (P.stream && P.prec != RSVD_NATIVE)
+    return gemm(c, pr->prec, false, left, Kc, m, Kc, rightT, n, (int32_t)n, gA, n, no_split(Kc), nullptr, nullptr,
+                true, false, c.at<void>(L.gApack), true);
   for (int64_t ch = 0; ch < L.gA_chunks; ++ch) {
     const int64_t c0 = std::min<int64_t>(ch * 128, n - 1);
     const int32_t nc = (int32_t)std::max<int64_t>(1, std::min<int64_t>(128, n - ch * 128));
     const int64_t rows = ch * 128 < n ? m : 0;  // chunks past a narrower problem's n launch nothing
     s = gemm(c, pr->prec, false, left, Kc, rows, Kc, rightT + (size_t)c0 * es, n, nc,
-             static_cast<char*>(gA) + (size_t)c0 * es, n, no_split(Kc), nullptr, nullptr);
+             static_cast<char*>(gA) + (size_t)c0 * es, n, no_split(Kc), nullptr, nullptr, P.stream, false,
+             P.stream ? c.at<void>(L.gApack) : nullptr);
     if (s != RSVD_OK) return s;
   }
   return RSVD_OK;
@@ -1101,7 +1113,7 @@ hipError_t launch_slots(const Recorded& R, const char* dev, hipStream_t st) {
         e = launch_pack_x_batched(sl.prec, (const GemmParams*)ps, bm, nb, st);
         break;
       case SK_STREAM:
-        e = launch_stream_gemm_batched(sl.prec, sl.trans, (const GemmParams*)ps, bm, nb, st);
+        e = launch_stream_gemm_batched(sl.prec, sl.trans, sl.dtype != 0, (const GemmParams*)ps, bm, nb, st);
         break;
     }
     if (e != hipSuccess) return e;

@@ -45,6 +45,7 @@ struct GemmParams {
   const int32_t* gate;  // if non-null and *gate == 0 the kernel does nothing
   int32_t narrow;       // FP32 native, S == 1, K <= 256: 32-row blocks (more workgroups for one product)
   void* pack;           // the A-streaming kernels: X packed by pack_x (stream_pack_bytes(K, Lp) bytes)
+  int32_t wide;         // the A-streaming BF16 kernels: Lp > 128 allowed, 128-column chunks per workgroup
 };
 
 // Tile geometry of each GEMM variant (rows of C per workgroup, K per stage).
@@ -56,7 +57,7 @@ hipError_t launch_gemm(int dtype, int prec, bool trans, const GemmParams& p, hip
 // FP32-data GEMMs that stream A (FP32 MFMA or BF16 / bf16x3 MFMA): X is first
 // packed into `pack` (stream_pack_bytes(K, Lp) bytes) by a small kernel.
 int64_t stream_pack_bytes(int64_t K, int32_t Lp);
-bool stream_params_ok(const GemmParams& p);
+bool stream_params_ok(int prec, const GemmParams& p);
 hipError_t launch_pack_x(int prec, const GemmParams& p, hipStream_t st);
 hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, hipStream_t st);
 
@@ -218,7 +219,7 @@ int64_t pack_x_blocks(const GemmParams& p);
 int64_t stream_gemm_blocks(const GemmParams& p);
 hipError_t launch_pack_x_batched(int prec, const GemmParams* ps, const BlockMap* bm, int64_t nblocks,
                                  hipStream_t st);
-hipError_t launch_stream_gemm_batched(int prec, bool trans, const GemmParams* ps, const BlockMap* bm,
+hipError_t launch_stream_gemm_batched(int prec, bool trans, bool wide, const GemmParams* ps, const BlockMap* bm,
                                       int64_t nblocks, hipStream_t st);
 
 // ---------------------------------------------------------------------------

@@ -39,32 +39,38 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // One workgroup per 32-row tile of X: the tile is read with coalesced loads
 // into LDS, then written as Lp columns of 32 consecutive k -- FP32 rows of Lp
 // (plain) or 16-byte runs of bf16 hi and lo planes (split).
+// Workgroup b packs the 32-row tile b / nch of X, columns 128 (b % nch) ..
+// +127 (nch = Lp / 128 chunks when Lp > 128, else one chunk of Lp columns).
 template <bool SPLIT>
-__device__ __forceinline__ void pack_x_body(const GemmParams& p, const int64_t kt) {
+__device__ __forceinline__ void pack_x_body(const GemmParams& p, const int64_t bid) {
   __shared__ float tile[32][128 + 1];
   if (p.gate && *p.gate == 0) return;
   const float* __restrict__ X = (const float*)p.X;
   const int64_t K = p.K, ldx = p.ldx, Kpad = (p.K + SBK - 1) / SBK * SBK;
   const int32_t ncols = p.ncols, Lp = p.Lp;
+  const int nch = (Lp + 127) >> 7;
+  const int64_t kt = bid / nch;
+  const int c0 = 128 * (int)(bid - kt * nch);
+  const int w = min(128, Lp - c0);  // columns of this chunk
   void* __restrict__ out = p.pack;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < 32 * Lp; idx += 256) {
-    const int kk = idx / Lp, c = idx - kk * Lp;
+  for (int idx = tid; idx < 32 * w; idx += 256) {
+    const int kk = idx / w, c = idx - kk * w;
     const int64_t k = kt * 32 + kk;
-    tile[kk][c] = (k < K && c < ncols) ? X[k * ldx + c] : 0.f;
+    tile[kk][c] = (k < K && c0 + c < ncols) ? X[k * ldx + c0 + c] : 0.f;
   }
   __syncthreads();
   if (!SPLIT) {
-    float* o = (float*)out + kt * 32 * Lp;
-    for (int idx = tid; idx < 32 * Lp; idx += 256) {
-      const int kk = idx / Lp, c = idx - kk * Lp;
-      o[idx] = tile[kk][c];
+    float* o = (float*)out + kt * 32 * Lp + c0;
+    for (int idx = tid; idx < 32 * w; idx += 256) {
+      const int kk = idx / w, c = idx - kk * w;
+      o[kk * Lp + c] = tile[kk][c];
     }
   } else {
-    // run (c, q): k = 8 q .. 8 q + 7 of column c, 16 bytes per plane
+    // run (c, q): k = 8 q .. 8 q + 7 of column c0 + c, 16 bytes per plane
     __bf16* hi = (__bf16*)out;
     __bf16* lo = hi + Kpad * Lp;
-    for (int run = tid; run < 4 * Lp; run += 256) {
+    for (int run = tid; run < 4 * w; run += 256) {
       const int c = run >> 2, q = run & 3;
       bf16x8 h, l;
 #pragma unroll
@@ -73,7 +79,7 @@ __device__ __forceinline__ void pack_x_body(const GemmParams& p, const int64_t k
         h[t] = (__bf16)v;
         l[t] = (__bf16)(v - (float)h[t]);
       }
-      const int64_t o = (kt * Lp + c) * 32 + 8 * q;
+      const int64_t o = (kt * Lp + c0 + c) * 32 + 8 * q;
       *reinterpret_cast<bf16x8*>(hi + o) = h;
       *reinterpret_cast<bf16x8*>(lo + o) = l;
     }
@@ -190,7 +196,9 @@ __device__ inline void load_a_full(const GemmParams& p, int64_t i0, int64_t k0, 
 // MFMA v_mfma_f32_32x32x16_bf16: lane (r = lane % 32, g = lane / 32) supplies
 // A[r][8 g + t] and B[8 g + t][r], t = 0..7; result register e holds
 // C[8 (e / 4) + 4 g + e % 4][r].
-template <bool TRANS, int NP>
+// WIDE: C and X wider than 128 columns, one 128-column chunk per workgroup
+// (the chunk index is a runtime quantity only in this variant).
+template <bool TRANS, int NP, bool WIDE>
 __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf16* __restrict__ xh,
                                                  const __bf16* __restrict__ xl, const int bid) {
   constexpr int APLANE = SBM * BPAD;  // bf16 elements per A plane per buffer
@@ -203,12 +211,20 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int S = p.S;
+  // workgroup -> (row block, 128-column chunk of C, K chunk s)
+  const int nch = WIDE ? (p.Lp + 127) >> 7 : 1;
   const int s = bid % S;
-  const int64_t i0 = (int64_t)(bid / S) * SBM;
+  const int tb = bid / S;
+  const int ch = WIDE ? tb % nch : 0;
+  const int64_t i0 = (int64_t)(WIDE ? tb / nch : tb) * SBM;
   const int64_t kbeg = (int64_t)s * p.kchunk;
   const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int NT = p.Lp / 32;
+  const int NT = WIDE ? min(4, (p.Lp - 128 * ch) >> 5) : p.Lp / 32;
   const int64_t nk = kend > kbeg ? (kend - kbeg + SBK - 1) / SBK : 0;
+  if (WIDE) {  // the chunk's columns within every 32-row tile of packed X
+    xh += 128 * 32 * ch;
+    xl += 128 * 32 * ch;
+  }
 
   f32x16 acc[2][4];
 #pragma unroll
@@ -356,7 +372,7 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int64_t row = i0 + wave * 64 + rt * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
-        const int col = t * 32 + r;
+        const int col = 128 * ch + t * 32 + r;
         if (row < p.rows) {
           if (S == 1) {
             if (col < p.ncols) out[row * p.ldo + col] = acc[rt][t][e];
@@ -369,20 +385,20 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
   }
 }
 
-template <bool TRANS, int NP>
+template <bool TRANS, int NP, bool WIDE>
 __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_bf16_kernel(
     const GemmParams p, const __bf16* __restrict__ xh, const __bf16* __restrict__ xl) {
-  stream_bf16_body<TRANS, NP>(p, xh, xl, blockIdx.x);
+  stream_bf16_body<TRANS, NP, WIDE>(p, xh, xl, blockIdx.x);
 }
 
 // Batched: problem bm[b].item, its own packed X (hi plane, then lo plane) at p.pack.
-template <bool TRANS, int NP>
+template <bool TRANS, int NP, bool WIDE>
 __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_bf16_batched(
     const GemmParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
   const BlockMap b = bm[blockIdx.x];
   const GemmParams p = ps[b.item];
   const __bf16* xh = (const __bf16*)p.pack;
-  stream_bf16_body<TRANS, NP>(p, xh, xh + (p.K + SBK - 1) / SBK * SBK * p.Lp, b.local);
+  stream_bf16_body<TRANS, NP, WIDE>(p, xh, xh + (p.K + SBK - 1) / SBK * SBK * p.Lp, b.local);
 }
 
 // ---- FP32 ---------------------------------------------------------------
@@ -537,16 +553,20 @@ int64_t stream_pack_bytes(int64_t K, int32_t Lp) {
   return Kpad * Lp * 4;  // FP32, or two BF16 planes
 }
 
-bool stream_params_ok(const GemmParams& p) {
-  return p.ncols <= 128 && p.Lp <= 128 && p.Lp % 32 == 0 && p.Lp >= p.ncols && p.S >= 1;
+// X wider than 128 columns (BF16 kernels only) is taken in 128-column chunks.
+bool stream_params_ok(int prec, const GemmParams& p) {
+  const bool wide_ok = p.wide && prec != PREC_NATIVE && p.Lp % 128 == 0;
+  return p.ncols >= 1 && p.Lp >= p.ncols && p.Lp % 32 == 0 && (p.Lp <= 128 || wide_ok) && p.S >= 1;
 }
 
-int64_t pack_x_blocks(const GemmParams& p) { return (p.K + SBK - 1) / SBK; }
+int64_t pack_x_blocks(const GemmParams& p) { return (p.K + SBK - 1) / SBK * ((p.Lp + 127) / 128); }
 
-int64_t stream_gemm_blocks(const GemmParams& p) { return p.rows <= 0 ? 0 : (p.rows + SBM - 1) / SBM * p.S; }
+int64_t stream_gemm_blocks(const GemmParams& p) {
+  return p.rows <= 0 ? 0 : (p.rows + SBM - 1) / SBM * ((p.Lp + 127) / 128) * p.S;
+}
 
 hipError_t launch_pack_x(int prec, const GemmParams& p, hipStream_t st) {
-  if (!stream_params_ok(p)) return hipErrorInvalidValue;
+  if (!stream_params_ok(prec, p)) return hipErrorInvalidValue;
   const dim3 pgrid((unsigned)pack_x_blocks(p));
   if (prec != PREC_NATIVE)
     hipLaunchKernelGGL(pack_x_kernel<true>, pgrid, dim3(256), 0, st, p);
@@ -555,34 +575,66 @@ hipError_t launch_pack_x(int prec, const GemmParams& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, hipStream_t st) {
-  if (p.rows <= 0) return hipSuccess;
-  if (!stream_params_ok(p)) return hipErrorInvalidValue;
-  const int64_t Kpad = (p.K + SBK - 1) / SBK * SBK;
-  const int64_t nel = Kpad * p.Lp;
-  const dim3 grid((unsigned)stream_gemm_blocks(p)), block(STHREADS);
-  const __bf16* xh = (const __bf16*)p.pack;
-  const __bf16* xl = xh + nel;
+namespace {
+
+template <bool WIDE>
+void launch_bf16_single(int prec, bool trans, const GemmParams& p, dim3 grid, const __bf16* xh, const __bf16* xl,
+                        hipStream_t st) {
+  const dim3 block(STHREADS);
   if (prec == PREC_BF16X3) {
     if (trans)
-      hipLaunchKernelGGL((stream_bf16_kernel<true, 3>), grid, block, 0, st, p, xh, xl);
+      hipLaunchKernelGGL((stream_bf16_kernel<true, 3, WIDE>), grid, block, 0, st, p, xh, xl);
     else
-      hipLaunchKernelGGL((stream_bf16_kernel<false, 3>), grid, block, 0, st, p, xh, xl);
-  } else if (prec == PREC_BF16) {
-    if (trans)
-      hipLaunchKernelGGL((stream_bf16_kernel<true, 1>), grid, block, 0, st, p, xh, xl);
-    else
-      hipLaunchKernelGGL((stream_bf16_kernel<false, 1>), grid, block, 0, st, p, xh, xl);
+      hipLaunchKernelGGL((stream_bf16_kernel<false, 3, WIDE>), grid, block, 0, st, p, xh, xl);
   } else {
     if (trans)
-      hipLaunchKernelGGL(stream_f32_kernel<true>, grid, block, 0, st, p, (const float*)p.pack);
+      hipLaunchKernelGGL((stream_bf16_kernel<true, 1, WIDE>), grid, block, 0, st, p, xh, xl);
     else
-      hipLaunchKernelGGL(stream_f32_kernel<false>, grid, block, 0, st, p, (const float*)p.pack);
+      hipLaunchKernelGGL((stream_bf16_kernel<false, 1, WIDE>), grid, block, 0, st, p, xh, xl);
   }
+}
+
+template <bool WIDE>
+void launch_bf16_batched(int prec, bool trans, const GemmParams* ps, const BlockMap* bm, dim3 grid, hipStream_t st) {
+  const dim3 block(STHREADS);
+  if (prec == PREC_BF16X3) {
+    if (trans)
+      hipLaunchKernelGGL((stream_bf16_batched<true, 3, WIDE>), grid, block, 0, st, ps, bm);
+    else
+      hipLaunchKernelGGL((stream_bf16_batched<false, 3, WIDE>), grid, block, 0, st, ps, bm);
+  } else {
+    if (trans)
+      hipLaunchKernelGGL((stream_bf16_batched<true, 1, WIDE>), grid, block, 0, st, ps, bm);
+    else
+      hipLaunchKernelGGL((stream_bf16_batched<false, 1, WIDE>), grid, block, 0, st, ps, bm);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, hipStream_t st) {
+  if (p.rows <= 0) return hipSuccess;
+  if (!stream_params_ok(prec, p)) return hipErrorInvalidValue;
+  const int64_t Kpad = (p.K + SBK - 1) / SBK * SBK;
+  const dim3 grid((unsigned)stream_gemm_blocks(p));
+  if (prec == PREC_NATIVE) {
+    if (trans)
+      hipLaunchKernelGGL(stream_f32_kernel<true>, grid, dim3(STHREADS), 0, st, p, (const float*)p.pack);
+    else
+      hipLaunchKernelGGL(stream_f32_kernel<false>, grid, dim3(STHREADS), 0, st, p, (const float*)p.pack);
+    return hipGetLastError();
+  }
+  const __bf16* xh = (const __bf16*)p.pack;
+  const __bf16* xl = xh + Kpad * p.Lp;
+  if (p.wide)
+    launch_bf16_single<true>(prec, trans, p, grid, xh, xl, st);
+  else
+    launch_bf16_single<false>(prec, trans, p, grid, xh, xl, st);
   return hipGetLastError();
 }
 
-// Batched launches (parameters checked when each problem was recorded).
+// Batched launches (parameters checked when each problem was recorded; `wide`
+// is the same for every problem of a step).
 hipError_t launch_pack_x_batched(int prec, const GemmParams* ps, const BlockMap* bm, int64_t nblocks,
                                  hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
@@ -593,25 +645,19 @@ hipError_t launch_pack_x_batched(int prec, const GemmParams* ps, const BlockMap*
   return hipGetLastError();
 }
 
-hipError_t launch_stream_gemm_batched(int prec, bool trans, const GemmParams* ps, const BlockMap* bm,
+hipError_t launch_stream_gemm_batched(int prec, bool trans, bool wide, const GemmParams* ps, const BlockMap* bm,
                                       int64_t nblocks, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  const dim3 grid((unsigned)nblocks), block(STHREADS);
-  if (prec == PREC_BF16X3) {
+  const dim3 grid((unsigned)nblocks);
+  if (prec == PREC_NATIVE) {
     if (trans)
-      hipLaunchKernelGGL((stream_bf16_batched<true, 3>), grid, block, 0, st, ps, bm);
+      hipLaunchKernelGGL(stream_f32_batched<true>, grid, dim3(STHREADS), 0, st, ps, bm);
     else
-      hipLaunchKernelGGL((stream_bf16_batched<false, 3>), grid, block, 0, st, ps, bm);
-  } else if (prec == PREC_BF16) {
-    if (trans)
-      hipLaunchKernelGGL((stream_bf16_batched<true, 1>), grid, block, 0, st, ps, bm);
-    else
-      hipLaunchKernelGGL((stream_bf16_batched<false, 1>), grid, block, 0, st, ps, bm);
+      hipLaunchKernelGGL(stream_f32_batched<false>, grid, dim3(STHREADS), 0, st, ps, bm);
+  } else if (wide) {
+    launch_bf16_batched<true>(prec, trans, ps, bm, grid, st);
   } else {
-    if (trans)
-      hipLaunchKernelGGL(stream_f32_batched<true>, grid, block, 0, st, ps, bm);
-    else
-      hipLaunchKernelGGL(stream_f32_batched<false>, grid, block, 0, st, ps, bm);
+    launch_bf16_batched<false>(prec, trans, ps, bm, grid, st);
   }
   return hipGetLastError();
 }

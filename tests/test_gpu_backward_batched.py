@@ -150,7 +150,8 @@ def test_backward_batched_full_size_differentiable_workload():
     grads = _batched_grads(As, Ts, ws, [k, k], p, q, seed, prec="bf16x3")
     Gref = _reference(As[1], k, p, q, seed, 1, Ts[1], ws[1], torch.float32)
     err = _rel(grads[1], Gref)
-    assert err <= 64.0 * (k + p) * UNIT[torch.float32], err
+    # bf16x3 products: x = hi + lo carries a relative error up to 2^-16 per element
+    assert err <= 64.0 * (k + p) * 2.0 ** -16, err
 
 
 def test_backward_batched_kept_matches_recomputation():
