@@ -1121,17 +1121,50 @@ hipError_t launch_slots(const Recorded& R, const char* dev, hipStream_t st) {
   return hipSuccess;
 }
 
+// Workgroup order of one batched step: problems with the longest workgroups
+// first (the contraction length of a product, l for the Cholesky and Jacobi
+// kernels, the row chunk of a Gram), so that the dispatcher fills the gaps the
+// long ones leave with short ones instead of starting a long one last.
+int64_t block_weight(const Slot& sl, size_t i) {
+  const unsigned char* p = sl.params.data() + i * sl.psize;
+  switch (sl.kind) {
+    case SK_GEMM:
+    case SK_STREAM: {
+      const GemmParams& g = *reinterpret_cast<const GemmParams*>(p);
+      return std::min(g.K, g.kchunk);
+    }
+    case SK_GRAM_PARTIAL:
+      return reinterpret_cast<const GramParams*>(p)->chunk;
+    case SK_CHOL:
+      return reinterpret_cast<const CholParams*>(p)->l;
+    case SK_JACOBI:
+      return reinterpret_cast<const JacobiParams*>(p)->l;
+    default:
+      return 0;
+  }
+}
+
+void block_order(const Slot& sl, std::vector<int32_t>& order) {
+  order.resize(sl.blocks.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::vector<int64_t> w(order.size());
+  for (size_t i = 0; i < w.size(); ++i) w[i] = block_weight(sl, i);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return w[(size_t)a] > w[(size_t)b]; });
+}
+
 // Upload the tables of a recorded batch and capture its launches in a graph.
 rsvd_status build_plan(rsvd_handle h, int kind, int32_t count, const rsvd_problem* probs,
                        const std::vector<const void*>& ptrs, const Recorded& R, BatchPlan*& out) {
   std::vector<char> host(R.bytes, 0);
   write_params(R, host.data());
+  std::vector<int32_t> order;
   for (size_t s = 0; s < R.slots.size(); ++s) {
     BlockMap* bm = reinterpret_cast<BlockMap*>(host.data() + R.boff[s]);
     int64_t k = 0;
     const Slot& sl = R.slots[s];
-    for (size_t i = 0; i < sl.blocks.size(); ++i)
-      for (int64_t b = 0; b < sl.blocks[i]; ++b) bm[k++] = BlockMap{(int32_t)i, (int32_t)b};
+    block_order(sl, order);
+    for (const int32_t i : order)
+      for (int64_t b = 0; b < sl.blocks[(size_t)i]; ++b) bm[k++] = BlockMap{i, (int32_t)b};
   }
   BatchPlan* bp = new (std::nothrow) BatchPlan;
   if (!bp) return RSVD_E_DEVICE;
