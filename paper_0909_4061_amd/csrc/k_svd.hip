@@ -39,12 +39,18 @@ __device__ inline double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum over an aligned group of 4 lanes: two swaps within the quad.  Every lane
-// adds the same operands in the same pairs, so all 4 lanes hold bitwise-
-// identical sums (and take identical rotation decisions).
-__device__ inline double group4_sum(double v) {
+// Sum over an aligned group of 4, 8 or 16 lanes: two swaps within the quad,
+// then the other quad's sum by a mirror within the half-row (8 lanes), then
+// the other half-row's by a mirror within the row (16 lanes).  Every lane
+// adds the same operands in the same pairs (the last addition in either
+// order, which is exact to the same bits), so all lanes of a group hold
+// bitwise-identical sums and take identical rotation decisions.
+template <int LPP>
+__device__ inline double group_sum(double v) {
   v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]
   v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
+  if (LPP >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror: lane i <- lane 7 - i of its 8
+  if (LPP == 16) v += dpp_f64<0x140>(v);  // row_mirror: lane i <- lane 15 - i of its 16
   return v;
 }
 
@@ -70,19 +76,22 @@ __device__ __forceinline__ double rsq_nr(double x) {
   return y;
 }
 
-// One workgroup of 2 MAXL threads per matrix (l <= MAXL): MAXL / 2 column
-// pairs per round, four lanes per pair, each lane holding MAXL / 4 rows of
-// both columns in registers.
-template <int MAXL>
+// One workgroup of MAXL / 2 * LPP threads per matrix (l <= MAXL): MAXL / 2
+// column pairs per round, LPP lanes per pair, each lane holding MAXL / LPP
+// rows of both columns in registers.
+template <int MAXL, int LPP>
+constexpr int jac_threads() { return MAXL / 2 * LPP; }
+
+template <int MAXL, int LPP>
 __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid) {
   (void)bid;  // one workgroup per matrix
-  // Column stride: 16-byte aligned, and 64 bytes modulo the 256-byte bank
-  // width, so the 16-byte accesses of four groups with consecutive columns
-  // (four lanes each, consecutive 16-byte pieces) fall on 16 distinct bank
-  // slots instead of four lanes per slot.
-  constexpr int LDC = MAXL + 8;
-  constexpr int THREADS = 2 * MAXL;
-  constexpr int RPL = MAXL / 4;  // rows per lane
+  // Column stride: 16-byte aligned and, modulo the 256-byte bank width, 64
+  // bytes (four lanes per pair) or 128 bytes (eight), so the 16-byte accesses
+  // of the groups of one wave, consecutive columns, fall on distinct bank slots
+  // (sixteen lanes read 256 contiguous bytes, one per bank, at any stride).
+  constexpr int LDC = LPP == 8 ? MAXL + 16 : MAXL + 8;
+  constexpr int THREADS = jac_threads<MAXL, LPP>();
+  constexpr int RPL = MAXL / LPP;  // rows per lane
   typedef double d2 __attribute__((ext_vector_type(2)));
   __shared__ __attribute__((aligned(16))) double Cs[MAXL * LDC];  // column c at Cs[c * LDC + row]
   __shared__ double sig_s[MAXL];
@@ -102,7 +111,7 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
   if (tid == 0) rotated = 1;
   __syncthreads();
 
-  const int grp = tid >> 2, gl = tid & 3;
+  const int grp = tid / LPP, gl = tid % LPP;
   // Stopping threshold on |c_i . c_j| / (|c_i| |c_j|): the unit roundoff of
   // the output type (FP32 outputs cannot show a smaller loss of
   // orthogonality), l eps for FP64 outputs.
@@ -127,12 +136,12 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
         const int cb = 1 + ib;
         double* col_a = Cs + ca * LDC;
         double* col_b = Cs + cb * LDC;
-        // rows 8 r + 2 gl and 8 r + 2 gl + 1 of each column (rows past l are zeros)
+        // rows 2 LPP r + 2 gl and 2 LPP r + 2 gl + 1 of each column (rows past l are zeros)
         double x[RPL], y[RPL];
 #pragma unroll
         for (int r = 0; r < RPL / 2; ++r) {
-          const d2 xa = *reinterpret_cast<const d2*>(col_a + 8 * r + 2 * gl);
-          const d2 yb = *reinterpret_cast<const d2*>(col_b + 8 * r + 2 * gl);
+          const d2 xa = *reinterpret_cast<const d2*>(col_a + 2 * LPP * r + 2 * gl);
+          const d2 yb = *reinterpret_cast<const d2*>(col_b + 2 * LPP * r + 2 * gl);
           x[2 * r] = xa[0];
           x[2 * r + 1] = xa[1];
           y[2 * r] = yb[0];
@@ -151,14 +160,14 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
             be4[r & 3] += y[r] * y[r];
             ga4[r & 3] += x[r] * y[r];
           }
-          al = group4_sum((al4[0] + al4[1]) + (al4[2] + al4[3]));
-          be = group4_sum((be4[0] + be4[1]) + (be4[2] + be4[3]));
-          ga = group4_sum((ga4[0] + ga4[1]) + (ga4[2] + ga4[3]));
+          al = group_sum<LPP>((al4[0] + al4[1]) + (al4[2] + al4[3]));
+          be = group_sum<LPP>((be4[0] + be4[1]) + (be4[2] + be4[3]));
+          ga = group_sum<LPP>((ga4[0] + ga4[1]) + (ga4[2] + ga4[3]));
         } else {
           double ga4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int r = 0; r < RPL; ++r) ga4[r & 3] += x[r] * y[r];
-          ga = group4_sum((ga4[0] + ga4[1]) + (ga4[2] + ga4[3]));
+          ga = group_sum<LPP>((ga4[0] + ga4[1]) + (ga4[2] + ga4[3]));
           al = nrm[ca];
           be = nrm[cb];
         }
@@ -173,9 +182,9 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
           const double sn = cs * t;
 #pragma unroll
           for (int r = 0; r < RPL / 2; ++r) {
-            *reinterpret_cast<d2*>(col_a + 8 * r + 2 * gl) =
+            *reinterpret_cast<d2*>(col_a + 2 * LPP * r + 2 * gl) =
                 d2{cs * x[2 * r] - sn * y[2 * r], cs * x[2 * r + 1] - sn * y[2 * r + 1]};
-            *reinterpret_cast<d2*>(col_b + 8 * r + 2 * gl) =
+            *reinterpret_cast<d2*>(col_b + 2 * LPP * r + 2 * gl) =
                 d2{sn * x[2 * r] + cs * y[2 * r], sn * x[2 * r + 1] + cs * y[2 * r + 1]};
           }
           al = fma(-t, ga, al);
@@ -241,14 +250,22 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
   }
 }
 
-template <int MAXL>
-__global__ __launch_bounds__(2 * MAXL) void jacobi_kernel(const JacobiParams p) { jacobi_body<MAXL>(p, blockIdx.x); }
+// Lanes per column pair: eight for a single matrix (two waves per SIMD hide
+// each other's LDS and FP64 latencies), four in a batch (several workgroups
+// per CU already do).
+constexpr int JAC_LPP_SINGLE = 8;
+constexpr int JAC_LPP_BATCH = 4;
 
 template <int MAXL>
-__global__ __launch_bounds__(2 * MAXL) void jacobi_batched(const JacobiParams* __restrict__ ps,
-                                                           const BlockMap* __restrict__ bm) {
+__global__ __launch_bounds__((jac_threads<MAXL, JAC_LPP_SINGLE>())) void jacobi_kernel(const JacobiParams p) {
+  jacobi_body<MAXL, JAC_LPP_SINGLE>(p, blockIdx.x);
+}
+
+template <int MAXL>
+__global__ __launch_bounds__((jac_threads<MAXL, JAC_LPP_BATCH>())) void jacobi_batched(const JacobiParams* __restrict__ ps,
+                                                                                   const BlockMap* __restrict__ bm) {
   const BlockMap b = bm[blockIdx.x];
-  jacobi_body<MAXL>(ps[b.item], b.local);
+  jacobi_body<MAXL, JAC_LPP_BATCH>(ps[b.item], b.local);
 }
 
 }  // namespace
@@ -258,10 +275,12 @@ int jacobi_variant(int32_t l) { return l <= 32 ? 32 : (l <= 64 ? 64 : (l <= 96 ?
 hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st) {
   if (p.l < 1 || p.l > 128 || p.k < 1 || p.k > p.l) return hipErrorInvalidValue;
   switch (jacobi_variant(p.l)) {
-    case 32: hipLaunchKernelGGL(jacobi_kernel<32>, dim3(1), dim3(64), 0, st, p); break;
-    case 64: hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(128), 0, st, p); break;
-    case 96: hipLaunchKernelGGL(jacobi_kernel<96>, dim3(1), dim3(192), 0, st, p); break;
-    default: hipLaunchKernelGGL(jacobi_kernel<128>, dim3(1), dim3(256), 0, st, p); break;
+    case 32: hipLaunchKernelGGL(jacobi_kernel<32>, dim3(1), dim3(jac_threads<32, JAC_LPP_SINGLE>()), 0, st, p); break;
+    case 64: hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(jac_threads<64, JAC_LPP_SINGLE>()), 0, st, p); break;
+    case 96: hipLaunchKernelGGL(jacobi_kernel<96>, dim3(1), dim3(jac_threads<96, JAC_LPP_SINGLE>()), 0, st, p); break;
+    default:
+      hipLaunchKernelGGL(jacobi_kernel<128>, dim3(1), dim3(jac_threads<128, JAC_LPP_SINGLE>()), 0, st, p);
+      break;
   }
   return hipGetLastError();
 }
@@ -271,10 +290,12 @@ hipError_t launch_jacobi_batched(int variant, const JacobiParams* ps, const Bloc
   if (nblocks <= 0) return hipSuccess;
   const dim3 grid((unsigned)nblocks);
   switch (variant) {
-    case 32: hipLaunchKernelGGL(jacobi_batched<32>, grid, dim3(64), 0, st, ps, bm); break;
-    case 64: hipLaunchKernelGGL(jacobi_batched<64>, grid, dim3(128), 0, st, ps, bm); break;
-    case 96: hipLaunchKernelGGL(jacobi_batched<96>, grid, dim3(192), 0, st, ps, bm); break;
-    case 128: hipLaunchKernelGGL(jacobi_batched<128>, grid, dim3(256), 0, st, ps, bm); break;
+    case 32: hipLaunchKernelGGL(jacobi_batched<32>, grid, dim3(jac_threads<32, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
+    case 64: hipLaunchKernelGGL(jacobi_batched<64>, grid, dim3(jac_threads<64, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
+    case 96: hipLaunchKernelGGL(jacobi_batched<96>, grid, dim3(jac_threads<96, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
+    case 128:
+      hipLaunchKernelGGL(jacobi_batched<128>, grid, dim3(jac_threads<128, JAC_LPP_BATCH>()), 0, st, ps, bm);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
