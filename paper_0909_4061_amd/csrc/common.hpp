@@ -204,7 +204,7 @@ hipError_t launch_gram_partial_batched(int dtype, const GramParams* ps, const Bl
 hipError_t launch_gram_reduce_batched(const GramReduceParams* ps, const BlockMap* bm, int64_t nblocks,
                                       hipStream_t st);
 hipError_t launch_chol_batched(const CholParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
-// Jacobi variants: the largest l a kernel instance holds (64 or 128).
+// Jacobi variants: the largest l a kernel instance holds (32, 64, 80, 96 or 128).
 int jacobi_variant(int32_t l);
 hipError_t launch_jacobi_batched(int variant, const JacobiParams* ps, const BlockMap* bm, int64_t nblocks,
                                  hipStream_t st);

@@ -16,11 +16,12 @@
 // sweep with no rotation.  The squared column norms are formed exactly in the
 // first round of every sweep and carried through its other rounds (a rotation
 // changes them by -t c_i . c_j and +t c_i . c_j), so a round forms one dot
-// product per pair instead of three.  The round's fixed cost (the reduction,
-// the rotation angle) is paid once per wave, so fewer lanes per pair (more rows
-// per lane) make a round cheaper.  The kernel is compiled for l <= 32, 64, 96
-// and 128: a smaller variant holds fewer rows per lane (rows past l are zeros
-// but still cost work) and less LDS (more workgroups per CU in a batch).
+// product per pair instead of three.  A single matrix runs eight lanes per
+// pair (two waves per SIMD, which hide each other's LDS and FP64 latencies);
+// a batch runs four (several workgroups share a CU).  The kernel is compiled
+// for l <= 32, 64, 80, 96 and 128: a smaller variant holds fewer rows per lane
+// (rows past l are zeros but still cost work) and less LDS (more workgroups
+// per CU in a batch).
 #include <float.h>
 
 #include "common.hpp"
@@ -270,13 +271,14 @@ __global__ __launch_bounds__((jac_threads<MAXL, JAC_LPP_BATCH>())) void jacobi_b
 
 }  // namespace
 
-int jacobi_variant(int32_t l) { return l <= 32 ? 32 : (l <= 64 ? 64 : (l <= 96 ? 96 : 128)); }
+int jacobi_variant(int32_t l) { return l <= 32 ? 32 : (l <= 64 ? 64 : (l <= 80 ? 80 : (l <= 96 ? 96 : 128))); }
 
 hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st) {
   if (p.l < 1 || p.l > 128 || p.k < 1 || p.k > p.l) return hipErrorInvalidValue;
   switch (jacobi_variant(p.l)) {
     case 32: hipLaunchKernelGGL(jacobi_kernel<32>, dim3(1), dim3(jac_threads<32, JAC_LPP_SINGLE>()), 0, st, p); break;
     case 64: hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(jac_threads<64, JAC_LPP_SINGLE>()), 0, st, p); break;
+    case 80: hipLaunchKernelGGL(jacobi_kernel<80>, dim3(1), dim3(jac_threads<80, JAC_LPP_SINGLE>()), 0, st, p); break;
     case 96: hipLaunchKernelGGL(jacobi_kernel<96>, dim3(1), dim3(jac_threads<96, JAC_LPP_SINGLE>()), 0, st, p); break;
     default:
       hipLaunchKernelGGL(jacobi_kernel<128>, dim3(1), dim3(jac_threads<128, JAC_LPP_SINGLE>()), 0, st, p);
@@ -292,6 +294,7 @@ hipError_t launch_jacobi_batched(int variant, const JacobiParams* ps, const Bloc
   switch (variant) {
     case 32: hipLaunchKernelGGL(jacobi_batched<32>, grid, dim3(jac_threads<32, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
     case 64: hipLaunchKernelGGL(jacobi_batched<64>, grid, dim3(jac_threads<64, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
+    case 80: hipLaunchKernelGGL(jacobi_batched<80>, grid, dim3(jac_threads<80, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
     case 96: hipLaunchKernelGGL(jacobi_batched<96>, grid, dim3(jac_threads<96, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
     case 128:
       hipLaunchKernelGGL(jacobi_batched<128>, grid, dim3(jac_threads<128, JAC_LPP_BATCH>()), 0, st, ps, bm);
