@@ -251,22 +251,23 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
   }
 }
 
-// Lanes per column pair: eight for a single matrix (two waves per SIMD hide
-// each other's LDS and FP64 latencies), four in a batch (several workgroups
-// per CU already do).
+// Lanes per column pair: eight for a single matrix or a batch with fewer
+// matrices than CUs (two waves per SIMD hide each other's LDS and FP64
+// latencies), four in a larger batch (several workgroups per CU already do).
 constexpr int JAC_LPP_SINGLE = 8;
 constexpr int JAC_LPP_BATCH = 4;
+constexpr int JAC_BATCH_WIDE = 256;  // batches below this many matrices take the single-matrix form
 
 template <int MAXL>
 __global__ __launch_bounds__((jac_threads<MAXL, JAC_LPP_SINGLE>())) void jacobi_kernel(const JacobiParams p) {
   jacobi_body<MAXL, JAC_LPP_SINGLE>(p, blockIdx.x);
 }
 
-template <int MAXL>
-__global__ __launch_bounds__((jac_threads<MAXL, JAC_LPP_BATCH>())) void jacobi_batched(const JacobiParams* __restrict__ ps,
-                                                                                   const BlockMap* __restrict__ bm) {
+template <int MAXL, int LPP>
+__global__ __launch_bounds__((jac_threads<MAXL, LPP>())) void jacobi_batched(const JacobiParams* __restrict__ ps,
+                                                                           const BlockMap* __restrict__ bm) {
   const BlockMap b = bm[blockIdx.x];
-  jacobi_body<MAXL, JAC_LPP_BATCH>(ps[b.item], b.local);
+  jacobi_body<MAXL, LPP>(ps[b.item], b.local);
 }
 
 }  // namespace
@@ -287,21 +288,30 @@ hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_batched(int variant, const JacobiParams* ps, const BlockMap* bm, int64_t nblocks,
-                                 hipStream_t st) {
-  if (nblocks <= 0) return hipSuccess;
-  const dim3 grid((unsigned)nblocks);
+namespace {
+template <int LPP>
+hipError_t launch_jacobi_batched_lpp(int variant, const JacobiParams* ps, const BlockMap* bm, dim3 grid,
+                                     hipStream_t st) {
   switch (variant) {
-    case 32: hipLaunchKernelGGL(jacobi_batched<32>, grid, dim3(jac_threads<32, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
-    case 64: hipLaunchKernelGGL(jacobi_batched<64>, grid, dim3(jac_threads<64, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
-    case 80: hipLaunchKernelGGL(jacobi_batched<80>, grid, dim3(jac_threads<80, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
-    case 96: hipLaunchKernelGGL(jacobi_batched<96>, grid, dim3(jac_threads<96, JAC_LPP_BATCH>()), 0, st, ps, bm); break;
+    case 32: hipLaunchKernelGGL((jacobi_batched<32, LPP>), grid, dim3(jac_threads<32, LPP>()), 0, st, ps, bm); break;
+    case 64: hipLaunchKernelGGL((jacobi_batched<64, LPP>), grid, dim3(jac_threads<64, LPP>()), 0, st, ps, bm); break;
+    case 80: hipLaunchKernelGGL((jacobi_batched<80, LPP>), grid, dim3(jac_threads<80, LPP>()), 0, st, ps, bm); break;
+    case 96: hipLaunchKernelGGL((jacobi_batched<96, LPP>), grid, dim3(jac_threads<96, LPP>()), 0, st, ps, bm); break;
     case 128:
-      hipLaunchKernelGGL(jacobi_batched<128>, grid, dim3(jac_threads<128, JAC_LPP_BATCH>()), 0, st, ps, bm);
+      hipLaunchKernelGGL((jacobi_batched<128, LPP>), grid, dim3(jac_threads<128, LPP>()), 0, st, ps, bm);
       break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_jacobi_batched(int variant, const JacobiParams* ps, const BlockMap* bm, int64_t nblocks,
+                                 hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nblocks);
+  if (nblocks < JAC_BATCH_WIDE) return launch_jacobi_batched_lpp<JAC_LPP_SINGLE>(variant, ps, bm, grid, st);
+  return launch_jacobi_batched_lpp<JAC_LPP_BATCH>(variant, ps, bm, grid, st);
 }
 
 }  // namespace rsvd
