@@ -135,3 +135,32 @@ def test_batched_workspace_and_validation(lib):
     assert lib.rsvd_batched_workspace_bytes(1, bad) == 0             # l > min(m, n)
     # no handle: rejected on the host before any launch
     assert lib.rsvd_batched(None, 2, arr, None, None, None, None, None, 0, None) == 1
+
+
+def test_adjoint_workspace_and_validation(lib):
+    import torch
+    from paper_0909_4061_amd import RsvdProblem, problem
+    f32 = problem(300, 200, 10, 8, 1, dtype=torch.float32, prec="bf16x3")
+    one = lib.rsvd_backward_workspace_bytes(ctypes.byref(f32))
+    fwd = lib.rsvd_workspace_bytes(ctypes.byref(f32))
+    assert one > fwd > 0                                              # bases, factors and adjoint temporaries
+    srft = problem(64, 64, 4, 8, 0, dtype=torch.float32, sketch="srft")
+    assert lib.rsvd_backward_workspace_bytes(ctypes.byref(srft)) == 0  # fixed Gaussian test matrix only
+    # a larger q keeps more bases
+    assert lib.rsvd_backward_workspace_bytes(ctypes.byref(problem(300, 200, 10, 8, 3, dtype=torch.float32))) > \
+        lib.rsvd_backward_workspace_bytes(ctypes.byref(problem(300, 200, 10, 8, 1, dtype=torch.float32)))
+    ok = (RsvdProblem * 2)(f32, problem(96, 80, 16, 8, 1, dtype=torch.float32, prec="bf16x3"))
+    both = lib.rsvd_backward_batched_workspace_bytes(2, ok)
+    assert both > 0
+    assert lib.rsvd_backward_batched_workspace_bytes(0, ok) == 0
+    mixed_prec = (RsvdProblem * 2)(f32, problem(96, 80, 16, 8, 1, dtype=torch.float32))
+    assert lib.rsvd_backward_batched_workspace_bytes(2, mixed_prec) == 0
+    assert lib.rsvd_backward_batched_workspace_bytes(1, (RsvdProblem * 1)(srft)) == 0
+    # no handle: rejected on the host, nothing touches a device
+    pr = ctypes.byref(f32)
+    assert lib.rsvd_backward(None, pr, None, None, None, None, None, None, 0, None) == 1
+    assert lib.rsvd_forward_kept(None, pr, None, None, None, None, None, 0, None) == 1
+    assert lib.rsvd_backward_kept(None, pr, None, None, None, None, None, None, 0, None) == 1
+    assert lib.rsvd_backward_batched(None, 2, ok, None, None, None, None, None, None, 0, None) == 1
+    assert lib.rsvd_batched_kept(None, 2, ok, None, None, None, None, None, 0, None) == 1
+    assert lib.rsvd_backward_batched_kept(None, 2, ok, None, None, None, None, None, None, 0, None) == 1
