@@ -173,6 +173,21 @@ rsvd_status rsvd_svd(rsvd_handle handle, const rsvd_problem* problem,
                      const void* Bt, const void* Q, void* U, void* S, void* V,
                      void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Workspace bytes of rsvd_full (0 if the problem is invalid): Q and Bt as well
+ * as the hot-path workspace. */
+size_t rsvd_full_workspace_bytes(const rsvd_problem* problem);
+
+/* rsvd_range_finder, rsvd_power_iter, rsvd_project and rsvd_svd in one call,
+ * with Q and Bt kept in `ws`: U, S, V as rsvd_svd writes them, bit for bit the
+ * four calls' results.  The first call for given (problem, A, U, S, V, ws)
+ * captures the launches in a HIP graph owned by the handle (kept with the
+ * batched plans, eight at most, freed by rsvd_destroy); later calls with the
+ * same arguments replay it, so a small problem pays no host work per kernel.
+ * The graph reads and writes the same buffers on every replay: new contents of
+ * A are decomposed, and calls that overlap on one workspace race. */
+rsvd_status rsvd_full(rsvd_handle handle, const rsvd_problem* problem, const void* A,
+                      void* U, void* S, void* V, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* --- Differentiation ---------------------------------------------------- */
 
 /* Workspace bytes of rsvd_backward (0 if the problem is invalid or uses the

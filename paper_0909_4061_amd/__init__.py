@@ -196,6 +196,31 @@ def rsvd(A, k, p=10, q=0, *, sketch="gaussian", prec="native", seed=0, stream_id
     return U, S, V
 
 
+def full_workspace(pr, device):
+    """A workspace for rsvd_full (torch allocation): Q, Bt and the hot-path workspace."""
+    nbytes = handle(device).lib.rsvd_full_workspace_bytes(ctypes.byref(pr))
+    if nbytes == 0:
+        raise RsvdError(validate(pr) or _lib.RSVD_E_INVAL, "rsvd_full_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def rsvd_full(A, k, p=10, q=0, *, sketch="gaussian", prec="native", seed=0, stream_id=0, outs=None, ws=None):
+    """(U, S, V): the four hot-path calls as one, replayed from a HIP graph when `outs` (a previous
+    return value) and `ws` (from full_workspace) are passed back with the same A."""
+    pr = _prob_for(A, k, p, q, sketch, prec, seed, stream_id)
+    dev = A.device
+    ws = full_workspace(pr, dev) if ws is None else ws
+    if outs is None:
+        m, n = A.shape
+        outs = (torch.empty(m, k, dtype=A.dtype, device=dev), torch.empty(k, dtype=A.dtype, device=dev),
+                torch.empty(n, k, dtype=A.dtype, device=dev))
+    U, S, V = outs
+    h = handle(dev)
+    _lib.check(h.lib.rsvd_full(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(U), _ptr(S), _ptr(V),
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)), "rsvd_full")
+    return U, S, V
+
+
 def rsvd_sketch(A, k, p, *, sketch="gaussian", prec="native", seed=0, stream_id=0, Y=None, ws=None):
     """Y = A Omega (m x (k+p)) with the test matrix the range finder draws, not orthonormalized."""
     pr = _prob_for(A, k, p, 0, sketch, prec, seed, stream_id)

@@ -31,7 +31,7 @@ EXPORTS = [
     "rsvd_range_finder", "rsvd_power_iter", "rsvd_project", "rsvd_svd",
     "rsvd_batched_workspace_bytes", "rsvd_batched", "rsvd_backward_workspace_bytes", "rsvd_backward",
     "rsvd_backward_batched_workspace_bytes", "rsvd_backward_batched", "rsvd_forward_kept", "rsvd_backward_kept",
-    "rsvd_batched_kept", "rsvd_backward_batched_kept",
+    "rsvd_batched_kept", "rsvd_backward_batched_kept", "rsvd_full_workspace_bytes", "rsvd_full",
     "rsvd_sketch", "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
     "rsvd_profile_enable", "rsvd_profile_select", "rsvd_profile_read",
 ]
@@ -90,6 +90,8 @@ def load():
         "rsvd_backward_batched_kept": ([vp, i32, prob] + [ctypes.POINTER(vp)] * 5 + [vp, sz, vp], i32),
         "rsvd_batched_kept": ([vp, i32, prob] + [ctypes.POINTER(vp)] * 4 + [vp, sz, vp], i32),
         "rsvd_forward_kept": ([vp, prob, vp, vp, vp, vp, vp, sz, vp], i32),
+        "rsvd_full_workspace_bytes": ([prob], sz),
+        "rsvd_full": ([vp, prob, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_backward_kept": ([vp, prob, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_draw_omega": ([vp, prob, vp, vp], i32),
         "rsvd_draw_srft": ([vp, prob, vp, vp, vp], i32),

@@ -979,7 +979,10 @@ namespace {
 // problems and workspace are unchanged but whose caller buffers moved is
 // re-pointed by uploading new parameter blocks (from pinned staging memory, on
 // the caller's stream); the block maps and the graph stay.
-enum BatchKind { BATCH_FORWARD = 0, BATCH_BACKWARD = 1, BATCH_FORWARD_KEPT = 2, BATCH_ADJOINT_KEPT = 3 };
+enum BatchKind {
+  BATCH_FORWARD = 0, BATCH_BACKWARD = 1, BATCH_FORWARD_KEPT = 2, BATCH_ADJOINT_KEPT = 3,
+  SINGLE_FULL = 4  // one problem's four hot-path calls captured as launched (no tables)
+};
 
 struct SlotShape {
   int kind, dtype, prec, trans;
@@ -1389,6 +1392,60 @@ rsvd_status backward_batched_call(rsvd_handle h, int32_t count, const rsvd_probl
                    kept ? record_adjoint_kept : record_backward, &r, stream);
 }
 
+// One problem's whole rSVD in one workspace: Q (m x l), Bt (n x l), then the
+// single-problem plan (with the split of K the four calls use).
+struct FullLayout {
+  Plan P;
+  size_t q_off = 0, bt_off = 0, base = 0, total = 0;
+};
+
+FullLayout full_layout(const rsvd_problem* pr) {
+  FullLayout F;
+  F.P = make_plan(pr);
+  const size_t es = (size_t)F.P.esize;
+  F.bt_off = align_up((size_t)(F.P.m * F.P.l) * es);
+  F.base = F.bt_off + align_up((size_t)(F.P.n * F.P.l) * es);
+  F.total = F.base + F.P.total;
+  return F;
+}
+
+// Capture the four hot-path calls of one problem, launched exactly as the
+// single-problem entry points launch them, in a graph.
+rsvd_status capture_full(rsvd_handle h, const rsvd_problem* pr, const FullLayout& F, const void* A, void* U,
+                         void* S, void* V, char* ws, const std::vector<const void*>& ptrs, BatchPlan*& out) {
+  BatchPlan* bp = new (std::nothrow) BatchPlan;
+  if (!bp) return RSVD_E_DEVICE;
+  bp->kind = SINGLE_FULL;
+  bp->probs.assign(pr, pr + 1);
+  bp->ptrs = ptrs;
+  if (!h->capture && hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess) {
+    h->capture = nullptr;
+    free_plan(bp);
+    return RSVD_E_DEVICE;
+  }
+  if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    free_plan(bp);
+    return RSVD_E_DEVICE;
+  }
+  DirectRunner dr(nullptr, h->capture);  // no timing events inside a graph
+  const Ctx c{F.P, ws + F.base, h->capture, h->status, nullptr, &dr};
+  void* Q = ws + F.q_off;
+  void* Bt = ws + F.bt_off;
+  rsvd_status s = range_finder_steps(c, pr, A, Q);
+  if (s == RSVD_OK) s = power_steps(c, pr, A, Q);
+  if (s == RSVD_OK) s = project_steps(c, pr, A, Q, Bt);
+  if (s == RSVD_OK) s = svd_steps(c, Bt, Q, U, S, V);
+  const hipError_t ce = hipStreamEndCapture(h->capture, &bp->graph);
+  if (s == RSVD_OK && (ce != hipSuccess || hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0) != hipSuccess))
+    s = RSVD_E_DEVICE;
+  if (s != RSVD_OK) {
+    free_plan(bp);
+    return s;
+  }
+  out = bp;
+  return RSVD_OK;
+}
+
 // Shared checks of the single-problem adjoint entry points.
 rsvd_status adjoint_prologue(rsvd_handle h, const rsvd_problem* pr, void* ws, size_t ws_bytes, BwdLayout& L) {
   if (!h) return RSVD_E_INVAL;
@@ -1544,6 +1601,41 @@ rsvd_status rsvd_svd(rsvd_handle h, const rsvd_problem* pr, const void* Bt, cons
   DirectRunner dr(h, stream);
   const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
   return svd_steps(c, Bt, Q, U, S, V);
+}
+
+size_t rsvd_full_workspace_bytes(const rsvd_problem* problem) {
+  if (validate(problem) != RSVD_OK) return 0;
+  return full_layout(problem).total;
+}
+
+rsvd_status rsvd_full(rsvd_handle h, const rsvd_problem* pr, const void* A, void* U, void* S, void* V, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  if (!h || !A || !U || !S || !V) return RSVD_E_INVAL;
+  const rsvd_status v = validate(pr);
+  if (v != RSVD_OK) return v;
+  const FullLayout F = full_layout(pr);
+  if (!ws || ws_bytes < F.total || !aligned16(ws)) return RSVD_E_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
+  const std::vector<const void*> ptrs{A, U, S, V, ws};
+  BatchPlan* bp = nullptr;
+  for (size_t i = 0; i < h->plans.size(); ++i) {
+    if (same_problems(*h->plans[i], SINGLE_FULL, 1, pr) && h->plans[i]->ptrs == ptrs) {
+      bp = h->plans[i];
+      h->plans.erase(h->plans.begin() + (std::ptrdiff_t)i);
+      break;
+    }
+  }
+  if (!bp) {
+    const rsvd_status s = capture_full(h, pr, F, A, U, S, V, static_cast<char*>(ws), ptrs, bp);
+    if (s != RSVD_OK) return s;
+    if (h->plans.size() >= kMaxPlans) {
+      free_plan(h->plans.front());
+      h->plans.erase(h->plans.begin());
+    }
+  }
+  h->plans.push_back(bp);  // most recently used last
+  RSVD_TRY(hipGraphLaunch(bp->exec, stream));
+  return RSVD_OK;
 }
 
 size_t rsvd_backward_workspace_bytes(const rsvd_problem* problem) {
