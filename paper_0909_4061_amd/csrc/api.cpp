@@ -424,7 +424,8 @@ rsvd_status gram(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t
   return RSVD_OK;
 }
 
-rsvd_status chol(const Ctx& c, int64_t rows, double* R, bool want_inv, const int32_t* gate, int32_t* shifted) {
+rsvd_status chol(const Ctx& c, int64_t rows, double* R, bool want_inv, const int32_t* gate, int32_t* shifted,
+                 bool reset_shifted = false) {
   CholParams q{};
   q.G = c.at<double>(c.P.G);
   q.Lg = c.P.Lg;
@@ -435,6 +436,7 @@ rsvd_status chol(const Ctx& c, int64_t rows, double* R, bool want_inv, const int
   q.RinvT = want_inv ? c.at<void>(c.P.RinvT) : nullptr;
   q.dtype = c.P.dtype;
   q.shifted = shifted;
+  q.reset_shifted = reset_shifted ? 1 : 0;
   q.status = c.status;
   q.gate = gate;
   RSVD_TRY(c.run->chol(q));
@@ -447,8 +449,7 @@ rsvd_status chol(const Ctx& c, int64_t rows, double* R, bool want_inv, const int
 // non-null it receives the combined triangular factor.
 rsvd_status orth(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t rows, void* Q, double* R_out) {
   const int64_t l = c.P.l;
-  int32_t* flag = c.shift_flag();
-  RSVD_TRY(c.run->fill(FillParams{flag, 0, 1}));
+  int32_t* flag = c.shift_flag();  // cleared by the first factorization, set by a shifted one
   double* Rs[3] = {c.at<double>(c.P.R1), c.at<double>(c.P.R2), c.at<double>(c.P.R3)};
   for (int pass = 0; pass < 3; ++pass) {
     const int32_t* gate = pass == 2 ? flag : nullptr;
@@ -456,7 +457,7 @@ rsvd_status orth(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t
     void* src = pass == 0 ? y : Q;
     rsvd_status s = gram(c, src_part, sp, src, rows, gate);
     if (s != RSVD_OK) return s;
-    s = chol(c, rows, Rs[pass], true, gate, pass < 2 ? flag : nullptr);
+    s = chol(c, rows, Rs[pass], true, gate, pass < 2 ? flag : nullptr, pass == 0);
     if (s != RSVD_OK) return s;
     s = gemm(c, RSVD_NATIVE, false, src, l, rows, l, c.at<void>(c.P.RinvT), l, (int32_t)l, Q, l, no_split(l),
              nullptr, gate);

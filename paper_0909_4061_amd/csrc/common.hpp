@@ -108,6 +108,7 @@ struct CholParams {
   void* RinvT;          // l x l, R^-1 rounded to the element type (may be null)
   int32_t dtype;
   int32_t* shifted;     // set to 1 when a shift was needed (may be null)
+  int32_t reset_shifted;  // 1: *shifted is first cleared (the first factorization of a CholeskyQR)
   int32_t* status;      // handle status word (RSVD_FLAG_*)
   const int32_t* gate;
 };

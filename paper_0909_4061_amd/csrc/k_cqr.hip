@@ -267,6 +267,7 @@ __device__ __forceinline__ void chol_body_t(const CholParams& p) {
   __shared__ int bad_s;
   if (p.gate && *p.gate == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0 && p.shifted && p.reset_shifted) *p.shifted = 0;  // set again below by the same thread
   const int l = p.l, Lg = p.Lg;
   const int lp = (l + 15) & ~15;            // rows and columns past l up to lp hold zeros
   const int tc = tid & 127, tr = tid >> 7;  // 4 x 128 thread grid for whole-matrix loops
