@@ -1156,20 +1156,64 @@ void block_order(const Slot& sl, std::vector<int32_t>& order) {
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return w[(size_t)a] > w[(size_t)b]; });
 }
 
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin
+// in grid order.  A batch of at least 8 problems of one shape gives every
+// problem one XCD (longest-processing-time balance of m n), and the block map
+// interleaves the XCDs' lists, so all workgroups of a problem share one L2: its
+// packed X, and the rows of A that several column chunks read, are fetched
+// once per problem instead of once per XCD.  Other batches keep the plain
+// longest-first order: with uneven problems a balance of m n leaves steps whose
+// work follows l (Cholesky, Jacobi) unbalanced across XCDs (measured slower).
+constexpr int kXcds = 8;
+
+std::vector<int32_t> xcd_assignment(int32_t count, const rsvd_problem* probs) {
+  std::vector<int32_t> xcd((size_t)count, -1);
+  if (count < kXcds) return xcd;
+  for (int32_t i = 1; i < count; ++i)
+    if (probs[i].m != probs[0].m || probs[i].n != probs[0].n || probs[i].k + probs[i].p != probs[0].k + probs[0].p)
+      return xcd;
+  std::vector<int32_t> idx((size_t)count);
+  for (int32_t i = 0; i < count; ++i) idx[(size_t)i] = i;
+  auto work = [&](int32_t i) { return (double)probs[i].m * (double)probs[i].n; };
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return work(a) > work(b); });
+  double load[kXcds] = {};
+  for (const int32_t i : idx) {
+    int x = 0;
+    for (int y = 1; y < kXcds; ++y)
+      if (load[y] < load[x]) x = y;
+    xcd[(size_t)i] = x;
+    load[x] += work(i);
+  }
+  return xcd;
+}
+
+void fill_block_map(const Slot& sl, const std::vector<int32_t>& xcd, std::vector<int32_t>& order, BlockMap* bm) {
+  block_order(sl, order);
+  int64_t k = 0;
+  if (xcd.empty() || xcd[0] < 0) {
+    for (const int32_t i : order)
+      for (int64_t b = 0; b < sl.blocks[(size_t)i]; ++b) bm[k++] = BlockMap{i, (int32_t)b};
+    return;
+  }
+  std::vector<std::vector<BlockMap>> lists(kXcds);
+  for (const int32_t i : order)
+    for (int64_t b = 0; b < sl.blocks[(size_t)i]; ++b) lists[(size_t)xcd[(size_t)i]].push_back(BlockMap{i, (int32_t)b});
+  size_t longest = 0;
+  for (const auto& li : lists) longest = std::max(longest, li.size());
+  for (size_t j = 0; j < longest; ++j)
+    for (const auto& li : lists)
+      if (j < li.size()) bm[k++] = li[j];
+}
+
 // Upload the tables of a recorded batch and capture its launches in a graph.
 rsvd_status build_plan(rsvd_handle h, int kind, int32_t count, const rsvd_problem* probs,
                        const std::vector<const void*>& ptrs, const Recorded& R, BatchPlan*& out) {
   std::vector<char> host(R.bytes, 0);
   write_params(R, host.data());
+  const std::vector<int32_t> xcd = xcd_assignment(count, probs);
   std::vector<int32_t> order;
-  for (size_t s = 0; s < R.slots.size(); ++s) {
-    BlockMap* bm = reinterpret_cast<BlockMap*>(host.data() + R.boff[s]);
-    int64_t k = 0;
-    const Slot& sl = R.slots[s];
-    block_order(sl, order);
-    for (const int32_t i : order)
-      for (int64_t b = 0; b < sl.blocks[(size_t)i]; ++b) bm[k++] = BlockMap{i, (int32_t)b};
-  }
+  for (size_t s = 0; s < R.slots.size(); ++s)
+    fill_block_map(R.slots[s], xcd, order, reinterpret_cast<BlockMap*>(host.data() + R.boff[s]));
   BatchPlan* bp = new (std::nothrow) BatchPlan;
   if (!bp) return RSVD_E_DEVICE;
   bp->kind = kind;
