@@ -185,7 +185,6 @@ class Runner {
   virtual hipError_t chol(const CholParams& p) = 0;
   virtual hipError_t jacobi(const JacobiParams& p) = 0;
   virtual hipError_t omega(int dtype, const OmegaParams& p) = 0;
-  virtual hipError_t fill(const FillParams& p) = 0;
   virtual hipError_t trmm(const TrmmParams& p) = 0;
   virtual hipError_t copy(const CopyParams& p) = 0;
   // adjoint pieces
@@ -235,7 +234,6 @@ class DirectRunner final : public Runner {
   hipError_t omega(int dtype, const OmegaParams& p) override {
     return launch_omega(dtype, p.omega, p.n, p.l, p.seed, p.sid, st_);
   }
-  hipError_t fill(const FillParams& p) override { return launch_fill_i32(p.p, p.v, p.count, st_); }
   hipError_t trmm(const TrmmParams& p) override { return launch_trmm_upper(p.R2, p.R1, p.R, p.l, p.gate, st_); }
   hipError_t copy(const CopyParams& p) override { return launch_copy_f64(p.src, p.dst, p.count, p.gate, st_); }
   hipError_t svd_adj_coef(const SvdAdjParams& p) override { return launch_svd_adj_coef(p, st_); }
@@ -251,7 +249,7 @@ class DirectRunner final : public Runner {
 // One step of a batched plan: the same kernel family and variant for every
 // problem, with the problems' parameter blocks side by side.
 enum SlotKind {
-  SK_GEMM, SK_GRAM_PARTIAL, SK_GRAM_REDUCE, SK_CHOL, SK_JACOBI, SK_OMEGA, SK_FILL, SK_TRMM, SK_COPY,
+  SK_GEMM, SK_GRAM_PARTIAL, SK_GRAM_REDUCE, SK_CHOL, SK_JACOBI, SK_OMEGA, SK_TRMM, SK_COPY,
   SK_SUM_PARTS, SK_SVD_ADJ, SK_QR_SYM, SK_TRI_INV, SK_COPY2D, SK_PACK, SK_STREAM
 };
 
@@ -298,7 +296,6 @@ class RecordRunner final : public Runner {
   hipError_t omega(int dtype, const OmegaParams& p) override {
     return add(SK_OMEGA, dtype, 0, false, p, omega_blocks(p));
   }
-  hipError_t fill(const FillParams& p) override { return add(SK_FILL, 0, 0, false, p, fill_blocks(p)); }
   hipError_t trmm(const TrmmParams& p) override { return add(SK_TRMM, 0, 0, false, p, trmm_blocks(p)); }
   hipError_t copy(const CopyParams& p) override {
     return add(SK_COPY, 0, 0, false, p, p.count > 0 ? copy_blocks(p) : 0);
@@ -403,7 +400,6 @@ rsvd_status gemm(const Ctx& c, int prec, bool trans, const void* A, int64_t lda,
 // partials (summed and stored into `y` first) or a stored `y`.
 rsvd_status gram(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t rows, const int32_t* gate) {
   GramParams g{};
-  g.mode = GRAM_FROM_PLAIN;
   g.part = c.at<void>(c.P.part);
   g.S = sp.S;
   g.Lp = c.P.Lp;
@@ -413,7 +409,6 @@ rsvd_status gram(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t
   g.rows = rows;
   g.l = (int32_t)c.P.l;
   g.Lg = c.P.Lg;
-  g.do_gram = 1;
   g.gpart = c.at<double>(c.P.gpart);
   g.gate = gate;
   const int64_t nchunks = gram_geometry(rows, c.P.Lg, !c.run->records(), &g.tgroups, &g.chunk);
@@ -1088,9 +1083,6 @@ hipError_t launch_slots(const Recorded& R, const char* dev, hipStream_t st) {
         break;
       case SK_OMEGA:
         e = launch_omega_batched(sl.dtype, (const OmegaParams*)ps, bm, nb, st);
-        break;
-      case SK_FILL:
-        e = launch_fill_batched((const FillParams*)ps, bm, nb, st);
         break;
       case SK_TRMM:
         e = launch_trmm_batched((const TrmmParams*)ps, bm, nb, st);

@@ -64,23 +64,20 @@ hipError_t launch_stream_gemm(int prec, bool trans, const GemmParams& p, hipStre
 // ---------------------------------------------------------------------------
 // Gram matrices and CholeskyQR.
 struct GramParams {
-  int32_t mode;          // GRAM_FROM_PART or GRAM_FROM_PLAIN
-  const void* part;      // S x rows x Lp partial products (mode PART)
+  const void* part;      // S x rows x Lp split-K partial products (summed by sum_parts)
   int32_t S;
   int32_t Lp;
-  const void* yin;       // rows x l (mode PLAIN), leading dimension ldy
-  void* yout;            // rows x l: reduced sum of the partials (mode PART)
+  const void* yin;       // rows x l read by the Gram, leading dimension ldy
+  void* yout;            // rows x l written by sum_parts, leading dimension ldy
   int64_t ldy;
   int64_t rows;
   int32_t l;
   int32_t Lg;            // l rounded up to 16
-  int32_t do_gram;       // 0: only reduce the partials into yout
   double* gpart;         // nblk x Lg x Lg: upper 16x16 tiles of each chunk's Gram
   const int32_t* gate;
   int32_t tgroups;       // workgroup b: row chunk b / tgroups, tiles t = b % tgroups (mod tgroups)
   int32_t chunk;         // rows per chunk, a multiple of GRAM_ROWS
 };
-enum { GRAM_FROM_PART = 0, GRAM_FROM_PLAIN = 1 };
 constexpr int GRAM_ROWS = 64;  // rows of Y staged at a time by a Gram workgroup
 // Chunks and tile groups of the Gram of `rows` rows (returns the chunk count,
 // which is the number of partial Grams).  wide: split the tiles of each chunk
@@ -171,11 +168,6 @@ struct OmegaParams {
   int32_t l;
   uint64_t seed, sid;
 };
-struct FillParams {
-  int32_t* p;
-  int32_t v;
-  int64_t count;
-};
 struct TrmmParams {  // R = R2 * R1, upper triangular l x l (FP64)
   const double* R2;
   const double* R1;
@@ -194,7 +186,6 @@ int64_t gemm_blocks(int dtype, int prec, const GemmParams& p);
 int64_t gram_partial_blocks(const GramParams& p);
 int64_t gram_reduce_blocks(const GramReduceParams& p);
 int64_t omega_blocks(const OmegaParams& p);
-int64_t fill_blocks(const FillParams& p);
 int64_t trmm_blocks(const TrmmParams& p);
 int64_t copy_blocks(const CopyParams& p);
 
@@ -211,7 +202,6 @@ hipError_t launch_jacobi_batched(int variant, const JacobiParams* ps, const Bloc
                                  hipStream_t st);
 hipError_t launch_omega_batched(int dtype, const OmegaParams* ps, const BlockMap* bm, int64_t nblocks,
                                 hipStream_t st);
-hipError_t launch_fill_batched(const FillParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
 hipError_t launch_trmm_batched(const TrmmParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
 hipError_t launch_copy_batched(const CopyParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st);
 hipError_t launch_sum_parts_batched(int dtype, const GramParams* ps, const BlockMap* bm, int64_t nblocks,
@@ -273,6 +263,5 @@ hipError_t launch_copy2d_batched(const Copy2dParams* ps, const BlockMap* bm, int
 
 // Small utilities.
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t count, const int32_t* gate, hipStream_t st);
-hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st);
 
 }  // namespace rsvd

@@ -534,7 +534,7 @@ namespace {
 bool gram_params_ok(const GramParams& p) {
   const int nt = p.Lg / 16;
   return p.l <= 128 && p.Lg % 16 == 0 && p.Lg >= p.l && p.tgroups >= 1 && p.chunk >= GRAM_ROWS &&
-         p.chunk % GRAM_ROWS == 0 && nt * (nt + 1) / 2 <= 36 * p.tgroups && p.mode == GRAM_FROM_PLAIN;
+         p.chunk % GRAM_ROWS == 0 && nt * (nt + 1) / 2 <= 36 * p.tgroups;
 }
 }  // namespace
 

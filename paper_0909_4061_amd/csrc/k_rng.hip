@@ -97,23 +97,9 @@ __global__ __launch_bounds__(256) void srft_sample_kernel(int32_t* __restrict__ 
   }
 }
 
-__device__ __forceinline__ void fill_body(const FillParams& p, const int bid) {
-  const int64_t i = (int64_t)bid * 256 + threadIdx.x;
-  if (i < p.count) p.p[i] = p.v;
-}
-
-__global__ __launch_bounds__(256) void fill_i32_kernel(const FillParams p) { fill_body(p, blockIdx.x); }
-
-__global__ __launch_bounds__(256) void fill_batched(const FillParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
-  const BlockMap b = bm[blockIdx.x];
-  fill_body(ps[b.item], b.local);
-}
-
 }  // namespace
 
 int64_t omega_blocks(const OmegaParams& p) { return (p.n * ((p.l + 3) / 4) + 255) / 256; }
-
-int64_t fill_blocks(const FillParams& p) { return (p.count + 255) / 256; }
 
 hipError_t launch_omega(int dtype, void* omega, int64_t n, int32_t l, uint64_t seed, uint64_t sid,
                         hipStream_t st) {
@@ -136,24 +122,11 @@ hipError_t launch_omega_batched(int dtype, const OmegaParams* ps, const BlockMap
   return hipGetLastError();
 }
 
-hipError_t launch_fill_batched(const FillParams* ps, const BlockMap* bm, int64_t nblocks, hipStream_t st) {
-  if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_batched, dim3((unsigned)nblocks), dim3(256), 0, st, ps, bm);
-  return hipGetLastError();
-}
-
 hipError_t launch_srft_draw(double* d, int32_t* R, int64_t n, int32_t l, uint64_t seed, uint64_t sid,
                             hipStream_t st) {
   if (l < 1 || l > RSVD_MAX_L || l > n) return hipErrorInvalidValue;
   hipLaunchKernelGGL(srft_signs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d, n, seed, sid);
   hipLaunchKernelGGL(srft_sample_kernel, dim3(1), dim3(128), 0, st, R, n, l, seed, sid);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  const FillParams f{p, v, count};
-  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)fill_blocks(f)), dim3(256), 0, st, f);
   return hipGetLastError();
 }
 
