@@ -82,8 +82,9 @@ constexpr int GRAM_ROWS = 64;  // rows of Y staged at a time by a Gram workgroup
 // Chunks and tile groups of the Gram of `rows` rows (returns the chunk count,
 // which is the number of partial Grams).  wide: split the tiles of each chunk
 // over workgroups so that a single Gram fills the chip with few partials;
-// otherwise one workgroup per GRAM_ROWS rows with every tile (a batch of Grams
-// fills the chip by itself).
+// otherwise one workgroup per two GRAM_ROWS-row stages with every tile (a
+// batch of Grams fills the chip by itself; 64 and 512 rows measured slower,
+// 256 the same).
 int64_t gram_geometry(int64_t rows, int32_t Lg, bool wide, int32_t* tgroups, int32_t* chunk);
 // yout (rows x l, leading dimension ldy) = sum over s of the S split-K partials
 // part[s] (rows x Lp), in the order s = 0, 1, ...

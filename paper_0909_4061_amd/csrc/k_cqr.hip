@@ -518,8 +518,8 @@ int64_t gram_geometry(int64_t rows, int32_t Lg, bool wide, int32_t* tgroups, int
   const int64_t nsub = (rows + GRAM_ROWS - 1) / GRAM_ROWS;
   if (!wide) {
     *tgroups = 1;
-    *chunk = GRAM_ROWS;
-    return nsub;
+    *chunk = (int32_t)((nsub < 2 ? nsub : 2) * GRAM_ROWS);
+    return (rows + *chunk - 1) / *chunk;
   }
   const int G = ntiles > 12 ? (ntiles + 11) / 12 : 1;  // at most three tiles per wave
   const int64_t want = (256 + G - 1) / G;                // chunks that fill 256 CUs
