@@ -169,3 +169,41 @@ def test_batched_bf16x3_matches_fp32_quality():
         sk = np.linalg.svd(A64, compute_uv=False)[0]
         assert rb <= 1.01 * ra + (4.0 * np.sqrt(max(A64.shape)) + 2.0 * (k + 8)) * U32 * sk
     assert _flags_ok()
+
+
+def test_batched_full_workload_sampled():
+    # the benchmark's batch itself: 512 uneven matrices up to 2048 x 1024, FP32,
+    # bf16x3 products, p = 8, q = 1.  Every matrix: orthonormal U and singular
+    # values no larger than the construction's (interlacing, to the FP32 floor);
+    # the four largest and four random matrices: the oracle on exactly A.
+    from workloads import build_matrix_torch
+    shapes = batch_shapes(512)
+    p, q, seed = 8, 1, 0x09094061
+    As, sigmas = [], []
+    for i, (m, n, k, r) in enumerate(shapes):
+        sig = spectrum("exp_r", min(m, n), rate=r)
+        As.append(build_matrix_torch(m, n, sig, seed=seed + i, dtype=torch.float32, device=DEV))
+        sigmas.append(sig)
+    ks = [s[2] for s in shapes]
+    outs = rs.rsvd_batched(As, ks, p=p, q=q, prec="bf16x3", seed=seed)
+    torch.cuda.synchronize()
+    assert _flags_ok()
+    for i, ((U, S, V), sig) in enumerate(zip(outs, sigmas)):
+        Sg = to_np(S).astype(np.float64)
+        floor = (4.0 * np.sqrt(As[i].shape[0]) + 2.0 * (ks[i] + p)) * U32 * sig[0]
+        assert np.all(Sg <= sig[:ks[i]] * (1 + 1e-5) + floor), i
+        assert evaluate.orthonormality_error(to_np(U).astype(np.float64)) <= 1e-5, i
+    big = sorted(range(len(As)), key=lambda i: -As[i].numel())[:4]
+    rnd = list(np.random.default_rng(1).choice(len(As), 4, replace=False))
+    for i in big + [int(j) for j in rnd]:
+        A64 = to_np(As[i]).astype(np.float64)
+        k = ks[i]
+        ref = orsvd.rsvd(A64, k, p, q, seed=seed, stream=i, dtype=np.float32)
+        U, S, V = (to_np(t).astype(np.float64) for t in outs[i])
+        floor = (4.0 * np.sqrt(A64.shape[0]) + 2.0 * (k + p)) * U32 * ref["Sk"][0]
+        # bf16x3 against the FP32-arithmetic oracle: singular values within 1e-3 relative
+        # (+ the floor), residual within 1%
+        assert np.all(np.abs(S - ref["Sk"]) <= 1e-3 * ref["Sk"] + floor), i
+        res = evaluate.residual_usv(A64, U, S, V)
+        res_ref = evaluate.residual_usv(A64, ref["Uk"], ref["Sk"], ref["Vk"])
+        assert res <= max(1.01 * res_ref, res_ref + floor), (i, res, res_ref)
