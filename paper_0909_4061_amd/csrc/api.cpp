@@ -115,8 +115,16 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   // the BF16 streaming kernels, see gemm())
   P.Lp = (P.stream && pr->prec != RSVD_NATIVE) ? 128 : (int32_t)round_up(P.l, big.lp_mult);
   P.Lg = (int32_t)round_up(P.l, 16);
-  P.nn = batched ? no_split(P.n) : choose_split(P.m, P.n, big);
-  P.tn = batched ? no_split(P.m) : choose_split(P.n, P.m, big);
+  // A batch of large matrices fills the chip without a split; a batch taking the
+  // general GEMM splits K beyond 1024 so that its largest problems do not
+  // leave one long workgroup per row block running after the rest.
+  auto batch_split = [&](int64_t K) {
+    if (stream || K <= 1024) return no_split(K);
+    const int64_t kc = round_up(ceil_div(K, ceil_div(K, 1024)), big.bk);
+    return Split{(int32_t)ceil_div(K, kc), kc};
+  };
+  P.nn = batched ? batch_split(P.n) : choose_split(P.m, P.n, big);
+  P.tn = batched ? batch_split(P.m) : choose_split(P.n, P.m, big);
   int64_t part_elems = 0;
   if (P.nn.S > 1) part_elems = std::max(part_elems, (int64_t)P.nn.S * P.m * P.Lp);
   if (P.tn.S > 1) part_elems = std::max(part_elems, (int64_t)P.tn.S * P.n * P.Lp);
@@ -412,7 +420,11 @@ rsvd_status gram(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t
   g.gpart = c.at<double>(c.P.gpart);
   g.gate = gate;
   const int64_t nchunks = gram_geometry(rows, c.P.Lg, !c.run->records(), &g.tgroups, &g.chunk);
-  if (from_part) RSVD_TRY(c.run->sum_parts(c.P.dtype, g));
+  if (from_part || c.run->records()) {  // a recorded problem without a split takes the (empty) step
+    GramParams gs = g;
+    if (!from_part) gs.rows = 0;
+    RSVD_TRY(c.run->sum_parts(c.P.dtype, gs));
+  }
   RSVD_TRY(c.run->gram_partial(c.P.dtype, g));
   const GramReduceParams r{g.gpart, nchunks, c.P.Lg, c.at<double>(c.P.G), c.status, gate};
   RSVD_TRY(c.run->gram_reduce(r));
@@ -483,6 +495,8 @@ rsvd_status apply_and_orth(const Ctx& c, const rsvd_problem* pr, bool trans, con
 
 // Sum the S split-K partial products (rows x l) into `out` in a fixed order.
 rsvd_status reduce_parts(const Ctx& c, const Split& sp, int64_t rows, void* out) {
+  if (sp.S == 1 && !c.run->records()) return RSVD_OK;
+  if (sp.S == 1) rows = 0;  // a recorded problem without a split takes the (empty) step
   GramParams g{};
   g.part = c.at<void>(c.P.part);
   g.S = sp.S;
@@ -543,7 +557,7 @@ rsvd_status project_steps(const Ctx& c, const rsvd_problem* pr, const void* A, c
   const Split& sp = P.tn;
   rsvd_status s = gemm(c, pr->prec, true, A, pr->lda, P.n, P.m, Q, P.l, (int32_t)P.l, Bt, P.l, sp,
                        sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
-  if (s != RSVD_OK || sp.S == 1) return s;
+  if (s != RSVD_OK) return s;
   return reduce_parts(c, sp, P.n, Bt);
 }
 
@@ -738,7 +752,7 @@ rsvd_status stream_apply(const Ctx& c, const rsvd_problem* pr, bool trans, const
   const int64_t K = trans ? P.m : P.n;
   rsvd_status s = gemm(c, pr->prec, trans, A, pr->lda, rows, K, X, ldx, (int32_t)P.l, out, P.l, sp,
                        sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
-  if (s != RSVD_OK || sp.S == 1) return s;
+  if (s != RSVD_OK) return s;
   return reduce_parts(c, sp, rows, out);
 }
 

@@ -70,8 +70,9 @@ def _rel(G, Gref):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_backward_batched_matches_reference(dtype):
-    # n = 300 / 150 / 260 / 700: three, two, three and six gA launches
-    shapes = [(400, 300, 10), (200, 150, 6), (260, 260, 12), (900, 700, 20)]
+    # n = 300 / 150 / 260 / 700 / 300: three, two, three, six and three gA launches;
+    # m = 1200 splits the transposed products with A in the batch
+    shapes = [(400, 300, 10), (200, 150, 6), (260, 260, 12), (900, 700, 20), (1200, 300, 12)]
     p, q, seed, sid = 6, 1, 11, 3
     ks = [s[2] for s in shapes]
     As, Ts, ws = _inputs(shapes, dtype, seed0=40)

@@ -103,6 +103,20 @@ def test_batched_fp32_large_matrices_streaming_kernels(prec):
     _check(As, outs, ks, 8, 1, 13, fp64=False)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_batched_split_and_unsplit_problems(dtype):
+    # contractions past 1024 are split in a batch of small matrices (m = 2100:
+    # A^T X in three parts; n = 1300: A X in two), the small problem is not:
+    # the recorded sequence gives it empty summation steps
+    shapes = [(2100, 300, 20, 8.0), (300, 200, 10, 6.0), (1500, 1300, 30, 10.0)]
+    As = _matrices(shapes, dtype, seed0=150)
+    ks = [s[2] for s in shapes]
+    outs = rs.rsvd_batched(As, ks, p=8, q=1, seed=21)
+    torch.cuda.synchronize()
+    assert _flags_ok()
+    _check(As, outs, ks, 8, 1, 21, fp64=dtype == torch.float64)
+
+
 def test_batched_fp64_edge_shapes():
     # l = min(m, n), fewer rows than one GEMM tile, a single-column target, n = m
     shapes = [(200, 100, 92, 5.0), (37, 20, 12, 3.0), (64, 64, 1, 8.0), (300, 300, 40, 20.0), (129, 65, 9, 2.0)]
