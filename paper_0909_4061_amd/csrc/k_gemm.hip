@@ -237,6 +237,86 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_batched(const GemmParams* __r
   gemm_f32_any<TRANS>(ps[b.item], b.local);
 }
 
+// FP32, one short product (C = A X with K <= 128, the 32-row blocks above):
+// all of K is loaded into registers at once, so the global-load latency is
+// exposed once rather than once per K stage.  Each wave computes one 32 x 32
+// tile of the block; the MFMA's two k slots take the two halves of K (lane
+// half g holds k in [g Kh, g Kh + Kh), Kh = ceil(K / 2)), so a lane's A values
+// are a contiguous run of its row.  Two accumulators break the chain of
+// dependent MFMAs.  A may alias C (in-place Y R^-1): every wave has consumed
+// its loads before the barrier that precedes the first store.
+__host__ __device__ inline bool f32_direct(bool trans, const GemmParams& p) {
+  return !trans && f32_block_rows(p) == 32 && p.K <= 128;
+}
+
+template <int KH>  // K <= 2 KH; every lane issues 2 KH loads and KH MFMAs whatever K is
+__global__ __launch_bounds__(256, 2) void gemm_f32_direct_kernel(const GemmParams p) {
+  if (p.gate && *p.gate == 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, t = tid >> 6;
+  const int r = lane & 31, g = lane >> 5;
+  const int64_t i0 = (int64_t)blockIdx.x * 32;
+  const int64_t row = i0 + r;
+  const int K = (int)p.K;
+  const int Kh = (K + 1) >> 1;
+  const int kb = g * Kh;
+  const int col = 32 * t + r;
+  const float* A = (const float*)p.A;  // may alias p.out: not restrict
+  const float* X = (const float*)p.X;
+  f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+  if (32 * t < p.ncols) {
+    // Branch-free loads, all issued before the first MFMA waits on them:
+    // indices are clamped into the operands and A's values past this half's
+    // K are scaled by zero (a multiply keeps every load live, where a select
+    // on the uniform bound would become a branch with a wait per load).  X
+    // past K needs no mask: its A factor is zero and its value a finite
+    // element of X.  Rows past p.rows read the last row; their results are
+    // never stored.
+    float a[KH], b[KH];
+    const int64_t rowc = row < p.rows ? row : p.rows - 1;
+    const int colc = col < p.ncols ? col : p.ncols - 1;
+    if (p.vec != 0 && K % 8 == 0) {  // 16-byte runs of the row: kb + s is a multiple of 4 below Kh
+#pragma unroll
+      for (int s = 0; s < KH; s += 4) {
+        const int sc = s < Kh ? s : 0;
+        const float m = s < Kh ? 1.f : 0.f;
+        const f32x4 v = *reinterpret_cast<const f32x4*>(A + rowc * p.lda + kb + sc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[s + e] = v[e] * m;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KH; ++s) {
+        const int k = kb + s;
+        const float m = (s < Kh && k < K) ? 1.f : 0.f;
+        a[s] = A[rowc * p.lda + (k < K ? k : K - 1)] * m;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < KH; ++s) {
+      const int k = kb + s;
+      b[s] = X[(int64_t)(k < K ? k : K - 1) * p.ldx + colc];
+    }
+#pragma unroll
+    for (int s = 0; s < KH; s += 2) {
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s + 1], b[s + 1], acc1, 0, 0, 0);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's loads have returned
+  __syncthreads();
+  if (32 * t >= p.ncols || col >= p.ncols) return;
+  float* out = (float*)p.out;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int64_t ro = i0 + 8 * (e >> 2) + 4 * g + (e & 3);
+    if (ro < p.rows) {
+      const int64_t o = ro * p.ldo + col;
+      const float v = acc0[e] + acc1[e];
+      out[o] = p.accum ? out[o] + v : v;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // FP64: v_mfma_f64_16x16x4f64.  Operand lanes: A[i = lane%16][k = lane/16],
 // B[k = lane/16][j = lane%16]; result register e of lane holds
@@ -511,6 +591,13 @@ hipError_t launch_gemm(int dtype, int prec, bool trans, const GemmParams& p, hip
       hipLaunchKernelGGL((gemm_bf16_kernel<true, 1>), grid, block, 0, st, p);
     else
       hipLaunchKernelGGL((gemm_bf16_kernel<false, 1>), grid, block, 0, st, p);
+  } else if (f32_direct(trans, p)) {
+    if (p.K <= 32)
+      hipLaunchKernelGGL(gemm_f32_direct_kernel<16>, grid, block, 0, st, p);
+    else if (p.K <= 64)
+      hipLaunchKernelGGL(gemm_f32_direct_kernel<32>, grid, block, 0, st, p);
+    else
+      hipLaunchKernelGGL(gemm_f32_direct_kernel<64>, grid, block, 0, st, p);
   } else {
     if (trans)
       hipLaunchKernelGGL(gemm_f32_kernel<true>, grid, block, 0, st, p);
