@@ -33,8 +33,8 @@ PEAK_HBM_GBS = 8000.0
 # the kernel source they were measured on and the 16384 x 8192, l = 120 shape.
 TRAFFIC_KERNEL_SHA = "2d8512d5f3de71f7"
 TRAFFIC_SHAPE = (16384, 8192, 120)
-TRAFFIC_BYTES = {"stream_tn_bf16x3": 579480805, "stream_nn_bf16x3": 579902255,
-                 "stream_tn_native": 579489406, "stream_nn_native": 579685386}
+TRAFFIC_BYTES = {"stream_tn_bf16x3": 579479555, "stream_nn_bf16x3": 579886875,
+                 "stream_tn_native": 579488361, "stream_nn_native": 579707277}
 # The same for the SRFT row-FFT kernel at 32768 x 16384, l = 128
 # (profiles/srft_sketch_32768x16384_hbm_counters.md).
 SRFT_TRAFFIC_SHA = "2b16782d46e9052b"
