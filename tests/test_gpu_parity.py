@@ -59,11 +59,17 @@ def test_omega_fp32_matches_oracle():
 
 # The Gram of one call is split into row chunks x groups of 16 x 16 tiles: (40000, 100) uses
 # 512-row chunks (8 stages) and three tile groups with a 64-row last chunk; (20001, 64) uses
-# 128-row chunks, one tile group and a 33-row last chunk.
+# 128-row chunks, one tile group and a 33-row last chunk.  FP32 Q = Y R^-1 runs in place on the
+# short-product kernel (32-row blocks, all of K = l in registers): 16-byte row loads when
+# l % 8 == 0 (120, 64, 128, 96), element loads otherwise (100, 45, 33, 7, 1); odd l leaves the
+# second K half one short (33, 7, 45, 1); l <= 32 / <= 64 / <= 128 take the three register
+# sizes; l <= 96 leaves waves without columns; 24 rows are fewer than one block.
 @pytest.mark.parametrize("dtype,rows,l", [(torch.float64, 2000, 30), (torch.float32, 5000, 120),
                                           (torch.float32, 333, 45), (torch.float64, 129, 128),
                                           (torch.float32, 64, 1), (torch.float32, 40000, 100),
-                                          (torch.float32, 20001, 64)])
+                                          (torch.float32, 20001, 64), (torch.float32, 1001, 7),
+                                          (torch.float32, 517, 33), (torch.float32, 300, 128),
+                                          (torch.float32, 1001, 96), (torch.float32, 24, 24)])
 def test_cholesky_qr2_matches_householder(dtype, rows, l):
     rng = np.random.default_rng(rows + l)
     Y64 = rng.standard_normal((rows, l)) @ np.diag(np.linspace(1.0, 0.05, l))
