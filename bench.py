@@ -334,7 +334,7 @@ def main_differentiable(args):
     import paper_0909_4061_amd as rs
     from workloads import CONFIGS, build_matrix_torch, spectrum
 
-    cfg = CONFIGS["c5"]
+    cfg = CONFIGS["differentiable_32x4096x2048"]
     m, n, k, p, q, count = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q, args.batch_diff
     l = k + p
     dev = torch.device("cuda", 0)
@@ -478,7 +478,7 @@ def main_fp64(args):
     import torch
     from workloads import CONFIGS, build_matrix_torch, spectrum
 
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["fp64_2000x1000"]
     m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
     l = k + p
     dev = torch.device("cuda", 0)
@@ -625,7 +625,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 

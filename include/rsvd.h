@@ -67,7 +67,7 @@ typedef enum rsvd_status {
   RSVD_E_INVAL = 1,        /* bad argument: null pointer, shape or parameter out of range */
   RSVD_E_WORKSPACE = 2,    /* workspace null or smaller than rsvd_workspace_bytes() */
   RSVD_E_DEVICE = 3,       /* a HIP call or kernel launch failed */
-  RSVD_E_UNSUPPORTED = 4,  /* valid problem outside what this build implements */
+  RSVD_E_UNSUPPORTED = 4,  /* valid problem outside what the library implements */
   RSVD_E_BREAKDOWN = 5,    /* device status: a Cholesky pivot was not positive (a shift was applied) */
   RSVD_E_NONFINITE = 6,    /* device status: a NaN or Inf reached a Gram matrix */
   RSVD_E_NOCONV = 7        /* device status: Jacobi SVD hit its sweep cap */
@@ -111,7 +111,7 @@ typedef struct rsvd_problem {
   uint64_t stream_id; /* Philox counter word 1: independent draws for the same seed */
 } rsvd_problem;
 
-/* Largest number of samples l = k + p this build supports (one workgroup
+/* Largest number of samples l = k + p the library supports (one workgroup
  * holds the l x l factors of the small FP64 steps in its local memory). */
 #define RSVD_MAX_L 128
 

@@ -1594,7 +1594,7 @@ const char* rsvd_status_string(rsvd_status s) {
     case RSVD_E_INVAL: return "invalid argument";
     case RSVD_E_WORKSPACE: return "workspace missing, misaligned or too small";
     case RSVD_E_DEVICE: return "HIP device error";
-    case RSVD_E_UNSUPPORTED: return "unsupported problem for this build";
+    case RSVD_E_UNSUPPORTED: return "unsupported problem for this library";
     case RSVD_E_BREAKDOWN: return "Cholesky breakdown (shift applied)";
     case RSVD_E_NONFINITE: return "non-finite values encountered";
     case RSVD_E_NOCONV: return "Jacobi SVD did not converge";

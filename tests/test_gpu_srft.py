@@ -88,7 +88,7 @@ def test_srft_sketch_fp32(m, n, l, lda_pad):
 def test_srft_sketch_full_size_sampled_rows():
     # 32768 x 16384 FP32 (the SRFT workload's shape), l = 128, in the launch
     # configuration the benchmark times; the oracle recomputes 64 sampled rows.
-    cfg = CONFIGS["c3"]
+    cfg = CONFIGS["srft_32768x16384"]
     sig = spectrum(cfg.spectrum, min(cfg.m, cfg.n))
     A = build_matrix_torch(cfg.m, cfg.n, sig, dtype=torch.float32, device=DEV)
     Y = rs.rsvd_sketch(A, cfg.k, cfg.p, sketch="srft", seed=cfg.m)

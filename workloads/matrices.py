@@ -42,15 +42,15 @@ class Config:
 
 CONFIGS = {
     # Plain rSVD in FP64: sigma_j = exp(-j/20), Gaussian Omega 1000 x 30.
-    "c1": Config("c1", 2000, 1000, 20, 10, 0, "f64", "exp20"),
+    "fp64_2000x1000": Config("fp64_2000x1000", 2000, 1000, 20, 10, 0, "f64", "exp20"),
     # Power-iteration rSVD, FP32 16384 x 8192, sigma_j = 1/j, q = 2.
-    "c2": Config("c2", 16384, 8192, 100, 20, 2, "f32", "inv"),
+    "power_16384x8192": Config("power_16384x8192", 16384, 8192, 100, 20, 2, "f32", "inv"),
     # SRFT vs Gaussian sketch, FP32 32768 x 16384 with a spectral gap, l = 128.
-    "c3": Config("c3", 32768, 16384, 50, 78, 0, "f32", "gap", sketch="srft"),
+    "srft_32768x16384": Config("srft_32768x16384", 32768, 16384, 50, 78, 0, "f32", "gap", sketch="srft"),
     # 512 uneven FP32 matrices, p = 8, q = 1 (shapes from batch_shapes()).
-    "c4": Config("c4", 2048, 1024, 64, 8, 1, "f32", "exp_r", batch=512),
+    "batched_512": Config("batched_512", 2048, 1024, 64, 8, 1, "f32", "exp_r", batch=512),
     # Differentiable rSVD: 32 x (4096 x 2048), sigma_j = j^-1/2, k = 64, p = 16, q = 1.
-    "c5": Config("c5", 4096, 2048, 64, 16, 1, "f32", "invsqrt", batch=32),
+    "differentiable_32x4096x2048": Config("differentiable_32x4096x2048", 4096, 2048, 64, 16, 1, "f32", "invsqrt", batch=32),
 }
 
 
