@@ -87,10 +87,14 @@ template <int MAXL, int LPP>
 __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid) {
   (void)bid;  // one workgroup per matrix
   // Column stride: 16-byte aligned and, modulo the 256-byte bank width, 64
-  // bytes (four lanes per pair) or 128 bytes (eight), so the 16-byte accesses
-  // of the groups of one wave, consecutive columns, fall on distinct bank slots
-  // (sixteen lanes read 256 contiguous bytes, one per bank, at any stride).
-  constexpr int LDC = LPP == 8 ? MAXL + 16 : MAXL + 8;
+  // bytes (four lanes per pair; 192 serves as well) or 128 bytes (eight), so
+  // the 16-byte accesses of the groups of one wave, consecutive columns, fall
+  // on distinct bank slots (sixteen lanes read 256 contiguous bytes, one per
+  // bank, at any stride).  With eight lanes, MAXL = 80 is already 128 bytes
+  // modulo 256; MAXL + 16 would put every group on the same half.
+  constexpr int LDC = LPP == 8 ? (MAXL % 32 == 16 ? MAXL : MAXL + 16) : MAXL + 8;
+  static_assert((LDC * 8) % 256 == (LPP == 8 ? 128 : 64) || (LPP == 4 && (LDC * 8) % 256 == 192),
+                "column stride off the bank pattern");
   constexpr int THREADS = jac_threads<MAXL, LPP>();
   constexpr int RPL = MAXL / LPP;  // rows per lane
   typedef double d2 __attribute__((ext_vector_type(2)));
