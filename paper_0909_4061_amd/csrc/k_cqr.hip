@@ -76,7 +76,11 @@ __global__ __launch_bounds__(256) void sum_parts_batched(const GramParams* __res
 template <typename T>
 __device__ __forceinline__ void gram_partial_body(const GramParams& p, const int bid) {
   constexpr int RB = GRAM_ROWS;
-  constexpr int YLD = 128 + 1;
+  // Row stride of the staged rows: 144 = 16 modulo the 64 banks, so the four
+  // rows of 16 consecutive elements that one MFMA operand read takes fall on
+  // four disjoint quarters of the banks (129 put them one bank apart: four
+  // lanes per bank).
+  constexpr int YLD = 144;
   constexpr int MAXT = 9;  // tiles per wave: 36 tiles / 4 waves with one group
   __shared__ T Ys[RB * YLD];
   if (p.gate && *p.gate == 0) return;
