@@ -122,15 +122,19 @@ __device__ inline void stage_load_x(const GemmParams& p, int64_t k0, int64_t ken
 // A before it writes any row of C (in-place Y R^-1 stays safe).
 __host__ __device__ inline int f32_block_rows(const GemmParams& p) { return (p.narrow && p.S == 1 && p.K <= 256) ? 32 : 128; }
 
+// LDS row strides of the stages: an MFMA operand read takes 32 consecutive
+// elements from each of two rows (one per half-wave), so a stride of 32
+// modulo the 64 banks puts the halves on disjoint banks.
 constexpr int F32_BK = 32;
-constexpr int F32_AS = F32_BK * (128 + 4);  // LDS floats of the A stage (largest layout)
-constexpr int F32_XLD = 128 + 4;
+constexpr int F32_AS = F32_BK * (128 + 32);  // LDS floats of the A stage (largest layout)
+constexpr int F32_XLD = 128 + 32;
 
 template <bool TRANS, int BM>
 __device__ __forceinline__ void gemm_f32_body(const GemmParams& p, const int bid, float* As, float* Xs) {
   constexpr int BK = F32_BK;
-  constexpr int ALD = TRANS ? BM + 4 : BK + 1;
+  constexpr int ALD = TRANS ? (BM % 64 == 32 ? BM : BM + 32) : BK + 1;
   constexpr int XLD = F32_XLD;
+  static_assert(XLD % 64 == 32 && (!TRANS || ALD % 64 == 32), "stage strides off the bank pattern");
   constexpr int NRUN = BM * BK / 1024;  // runs of four A elements per thread and stage
   constexpr int RUNS_PER_ROW = TRANS ? BM / 4 : BK / 4;
   constexpr int ROWS_PER_PASS = 256 / RUNS_PER_ROW;
