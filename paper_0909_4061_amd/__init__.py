@@ -174,15 +174,31 @@ def rsvd_svd(Bt, Q, m, n, k, p, *, q=0, dtype=torch.float32, sketch="gaussian", 
     return U, S, V
 
 
+def _check_differentiable(sketch):
+    """The adjoint holds the test matrix fixed as an explicit Omega: only the Gaussian sketch
+    has one (the SRFT's Omega is applied implicitly by FFTs).  Refused like the C ABI's
+    rsvd_backward_workspace_bytes refuses it, rather than silently switching sketches."""
+    name = sketch if isinstance(sketch, str) else {v: k for k, v in SKETCHES.items()}.get(int(sketch), sketch)
+    if name != "gaussian":
+        raise RsvdError(_lib.RSVD_E_UNSUPPORTED,
+                        f"rsvd under autograd: the adjoint supports the Gaussian sketch only (got {name!r})")
+
+
 def rsvd(A, k, p=10, q=0, *, sketch="gaussian", prec="native", seed=0, stream_id=0, ws=None,
-         return_q=False):
+         return_q=False, keep_state=False):
     """Randomized SVD of A: the four entry points in sequence.  Returns (U, S, V).
 
     When A requires grad (and grad mode is on) the result is differentiable
-    through RSVDFunction, whose backward is the library's rsvd_backward.
+    through RSVDFunction.  By default its backward is rsvd_backward, which
+    recomputes the forward (nothing but A is held between the two passes);
+    keep_state=True instead runs rsvd_forward_kept / rsvd_backward_kept, which
+    hold every basis of the power scheme, (q + 1) m l + q n l elements plus the
+    l x l factors, from the forward to the backward to skip the recomputation.
+    Only the Gaussian sketch is differentiable (RsvdError otherwise).
     """
     if A.requires_grad and torch.is_grad_enabled() and not return_q:
-        return RSVDFunction.apply(A, k, p, q, seed, stream_id, prec)
+        _check_differentiable(sketch)
+        return RSVDFunction.apply(A, k, p, q, seed, stream_id, prec, bool(keep_state))
     pr = _prob_for(A, k, p, q, sketch, prec, seed, stream_id)
     ws = ws or Workspace(pr, A.device)
     kw = dict(sketch=sketch, prec=prec, seed=seed, stream_id=stream_id, ws=ws)
@@ -283,28 +299,40 @@ def rsvd_backward_kept(A, gU, gS, gV, k, p, q, ws, *, prec="native", seed=0, str
 
 
 class RSVDFunction(torch.autograd.Function):
-    """(U, S, V) = rsvd(A) with the library's hand-written adjoint as backward: the forward
-    keeps its state (rsvd_forward_kept) and the backward is rsvd_backward_kept."""
+    """(U, S, V) = rsvd(A) with the library's hand-written adjoint as backward.
+
+    keep_state False (the default): the forward is the four hot-path calls and the backward
+    is rsvd_backward, which recomputes the forward's bases from A and the fixed test matrix.
+    keep_state True: the forward keeps its state (rsvd_forward_kept) and the backward is
+    rsvd_backward_kept; gA is the same either way."""
 
     @staticmethod
-    def forward(ctx, A, k, p, q, seed, stream_id, prec):
+    def forward(ctx, A, k, p, q, seed, stream_id, prec, keep_state=False):
         Ad = A.detach()
-        U, S, V, ws = rsvd_forward_kept(Ad, k, p, q, prec=prec, seed=seed, stream_id=stream_id)
-        ctx.save_for_backward(Ad, ws)
-        ctx.cfg = (k, p, q, seed, stream_id, prec)
+        if keep_state:
+            U, S, V, ws = rsvd_forward_kept(Ad, k, p, q, prec=prec, seed=seed, stream_id=stream_id)
+            ctx.save_for_backward(Ad, ws)
+        else:
+            U, S, V = rsvd(Ad, k, p, q, prec=prec, seed=seed, stream_id=stream_id)
+            ctx.save_for_backward(Ad)
+        ctx.cfg = (k, p, q, seed, stream_id, prec, keep_state)
         return U, S, V
 
     @staticmethod
     def backward(ctx, gU, gS, gV):
-        A, ws = ctx.saved_tensors
-        k, p, q, seed, stream_id, prec = ctx.cfg
+        k, p, q, seed, stream_id, prec, keep_state = ctx.cfg
+        A = ctx.saved_tensors[0]
         m, n = A.shape
         z = lambda shape: torch.zeros(shape, dtype=A.dtype, device=A.device)
         gU = z((m, k)) if gU is None else gU
         gS = z((k,)) if gS is None else gS
         gV = z((n, k)) if gV is None else gV
-        gA = rsvd_backward_kept(A, gU, gS, gV, k, p, q, ws, prec=prec, seed=seed, stream_id=stream_id)
-        return gA, None, None, None, None, None, None
+        if keep_state:
+            gA = rsvd_backward_kept(A, gU, gS, gV, k, p, q, ctx.saved_tensors[1], prec=prec, seed=seed,
+                                    stream_id=stream_id)
+        else:
+            gA = rsvd_backward(A, gU, gS, gV, k, p, q, prec=prec, seed=seed, stream_id=stream_id)
+        return gA, None, None, None, None, None, None, None
 
 
 class BatchWorkspace:
@@ -345,7 +373,8 @@ def _ptrs(ts):
     return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
 
 
-def rsvd_batched(As, ks, p=8, q=1, *, prec="native", seed=0, stream_id=0, outs=None, ws=None):
+def rsvd_batched(As, ks, p=8, q=1, *, prec="native", seed=0, stream_id=0, outs=None, ws=None,
+                 keep_state=False):
     """Randomized SVDs of many independent matrices in one batched call.
 
     As: list of 2-D CUDA tensors (same dtype), ks: target ranks (int or list).
@@ -354,13 +383,15 @@ def rsvd_batched(As, ks, p=8, q=1, *, prec="native", seed=0, stream_id=0, outs=N
     may be passed back to reuse buffers, which lets the library replay its
     recorded graph without re-pointing it.  When any matrix requires grad (and
     grad mode is on) the result is differentiable through
-    RSVDBatchedFunction, whose backward is rsvd_backward_batched.
+    RSVDBatchedFunction, whose backward is rsvd_backward_batched (the forward
+    recomputed); keep_state=True holds every problem's forward state instead
+    (rsvd_batched_kept / rsvd_backward_batched_kept).
     """
     count = len(As)
     if count == 0:
         return []
     if torch.is_grad_enabled() and any(A.requires_grad for A in As):
-        flat = RSVDBatchedFunction.apply((ks, p, q, prec, seed, stream_id), *As)
+        flat = RSVDBatchedFunction.apply((ks, p, q, prec, seed, stream_id, bool(keep_state)), *As)
         return [tuple(flat[3 * i:3 * i + 3]) for i in range(count)]
     ks, probs = _batch_problems(As, ks, p, q, prec, seed, stream_id)
     dev = As[0].device
@@ -431,22 +462,31 @@ def rsvd_backward_batched_kept(As, gUs, gSs, gVs, ks, p, q, ws, *, prec="native"
 
 
 class RSVDBatchedFunction(torch.autograd.Function):
-    """Flat (U_0, S_0, V_0, U_1, ...) = rsvd_batched(As); the forward keeps its state
-    (rsvd_batched_kept) and the backward is rsvd_backward_batched_kept."""
+    """Flat (U_0, S_0, V_0, U_1, ...) = rsvd_batched(As).  By default the forward is
+    rsvd_batched and the backward rsvd_backward_batched (the forward recomputed); with
+    keep_state the forward keeps its state (rsvd_batched_kept) and the backward is
+    rsvd_backward_batched_kept."""
 
     @staticmethod
     def forward(ctx, cfg, *As):
-        ks, p, q, prec, seed, stream_id = cfg
+        ks, p, q, prec, seed, stream_id, keep_state = cfg
         Ad = [A.detach() for A in As]
-        outs, ws = rsvd_batched_kept(Ad, ks, p, q, prec=prec, seed=seed, stream_id=stream_id)
-        ctx.save_for_backward(ws, *Ad)
-        ctx.cfg = ([o[1].shape[0] for o in outs], p, q, prec, seed, stream_id)
+        if keep_state:
+            outs, ws = rsvd_batched_kept(Ad, ks, p, q, prec=prec, seed=seed, stream_id=stream_id)
+            ctx.save_for_backward(ws, *Ad)
+        else:
+            outs = rsvd_batched(Ad, ks, p, q, prec=prec, seed=seed, stream_id=stream_id)
+            ctx.save_for_backward(*Ad)
+        ctx.cfg = ([o[1].shape[0] for o in outs], p, q, prec, seed, stream_id, keep_state)
         return tuple(t for o in outs for t in o)
 
     @staticmethod
     def backward(ctx, *grads):
-        ws, *As = ctx.saved_tensors
-        ks, p, q, prec, seed, stream_id = ctx.cfg
+        ks, p, q, prec, seed, stream_id, keep_state = ctx.cfg
+        if keep_state:
+            ws, *As = ctx.saved_tensors
+        else:
+            ws, As = None, list(ctx.saved_tensors)
         gUs, gSs, gVs = [], [], []
         for i, (A, k) in enumerate(zip(As, ks)):
             m, n = A.shape
@@ -455,8 +495,11 @@ class RSVDBatchedFunction(torch.autograd.Function):
             gUs.append(z((m, k)) if gU is None else gU)
             gSs.append(z((k,)) if gS is None else gS)
             gVs.append(z((n, k)) if gV is None else gV)
-        gAs = rsvd_backward_batched_kept(As, gUs, gSs, gVs, ks, p, q, ws, prec=prec, seed=seed,
-                                         stream_id=stream_id)
+        if keep_state:
+            gAs = rsvd_backward_batched_kept(As, gUs, gSs, gVs, ks, p, q, ws, prec=prec, seed=seed,
+                                             stream_id=stream_id)
+        else:
+            gAs = rsvd_backward_batched(As, gUs, gSs, gVs, ks, p, q, prec=prec, seed=seed, stream_id=stream_id)
         return (None, *gAs)
 
 

@@ -1018,8 +1018,13 @@ struct BatchPlan {
   hipGraphExec_t exec = nullptr;
 };
 
+// A plan's last replay (and its last parameter upload) may still be running on
+// the caller's stream when the plan is evicted or replaced: wait for both before
+// the graph, the device tables and the pinned staging memory they read go away.
 void free_plan(BatchPlan* bp) {
   if (!bp) return;
+  if (bp->done) (void)hipEventSynchronize(bp->done);
+  if (bp->staged) (void)hipEventSynchronize(bp->staged);
   if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
   if (bp->graph) (void)hipGraphDestroy(bp->graph);
   if (bp->tables) (void)hipFree(bp->tables);

@@ -164,3 +164,19 @@ def test_adjoint_workspace_and_validation(lib):
     assert lib.rsvd_backward_batched(None, 2, ok, None, None, None, None, None, None, 0, None) == 1
     assert lib.rsvd_batched_kept(None, 2, ok, None, None, None, None, None, 0, None) == 1
     assert lib.rsvd_backward_batched_kept(None, 2, ok, None, None, None, None, None, None, 0, None) == 1
+
+
+@pytest.mark.parametrize("sketch", ["srft", 1])
+def test_srft_under_autograd_is_refused(lib, sketch):
+    # The adjoint holds an explicit Gaussian Omega fixed; an SRFT call that requires grad must
+    # raise before any device work instead of returning Gaussian-sketch factors.
+    import torch
+    import paper_0909_4061_amd as rs
+    A = torch.zeros(64, 32, dtype=torch.float32, requires_grad=True)
+    with pytest.raises(rs.RsvdError) as e:
+        rs.rsvd(A, 4, 2, 0, sketch=sketch)
+    assert e.value.status == rs._lib.RSVD_E_UNSUPPORTED
+    # the same call without grad is not refused by this check (it then needs a device tensor)
+    with torch.no_grad(), pytest.raises(ValueError):
+        rs.rsvd(A, 4, 2, 0, sketch=sketch)
+
