@@ -188,6 +188,25 @@ size_t rsvd_full_workspace_bytes(const rsvd_problem* problem);
 rsvd_status rsvd_full(rsvd_handle handle, const rsvd_problem* problem, const void* A,
                       void* U, void* S, void* V, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Size of the device array that rsvd_full_static uses as its workspace. */
+#define RSVD_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rsvd_full
+ * with no workspace argument and no allocation of any kind.  Q, Bt and the
+ * hot-path workspace live in a file-scope device array of
+ * RSVD_STATIC_SCRATCH_BYTES (32 MiB), one copy per device, held from the
+ * library's first use on that device until the process ends; rsvd_create
+ * looks up its device address.  The kernels are launched directly on `stream`
+ * (no graph), so U, S, V are bit for bit those of rsvd_full and of the four
+ * hot-path calls.  A problem whose rsvd_full_workspace_bytes exceeds
+ * RSVD_STATIC_SCRATCH_BYTES returns RSVD_E_WORKSPACE before any launch.
+ * Every call on one device shares that device's array and leaves its
+ * contents behind (nothing in it has to start at zero): calls that overlap on
+ * one device -- on different streams, or through different handles -- race. */
+rsvd_status rsvd_full_static(rsvd_handle handle, const rsvd_problem* problem, const void* A,
+                             void* U, void* S, void* V, hipStream_t stream);
+
 /* --- Differentiation ---------------------------------------------------- */
 
 /* Workspace bytes of rsvd_backward (0 if the problem is invalid or uses the

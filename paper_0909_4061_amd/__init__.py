@@ -237,6 +237,23 @@ def rsvd_full(A, k, p=10, q=0, *, sketch="gaussian", prec="native", seed=0, stre
     return U, S, V
 
 
+def rsvd_full_static(A, k, p=10, q=0, *, sketch="gaussian", prec="native", seed=0, stream_id=0, outs=None):
+    """(U, S, V) = rsvd_full with the library's static device workspace: no workspace argument
+    and no allocation inside the call (the outputs are allocated here unless `outs` is given).
+    Problems whose rsvd_full workspace exceeds RSVD_STATIC_SCRATCH_BYTES raise RsvdError."""
+    pr = _prob_for(A, k, p, q, sketch, prec, seed, stream_id)
+    dev = A.device
+    if outs is None:
+        m, n = A.shape
+        outs = (torch.empty(m, k, dtype=A.dtype, device=dev), torch.empty(k, dtype=A.dtype, device=dev),
+                torch.empty(n, k, dtype=A.dtype, device=dev))
+    U, S, V = outs
+    h = handle(dev)
+    _lib.check(h.lib.rsvd_full_static(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(U), _ptr(S), _ptr(V), _stream(dev)),
+               "rsvd_full_static")
+    return U, S, V
+
+
 def rsvd_sketch(A, k, p, *, sketch="gaussian", prec="native", seed=0, stream_id=0, Y=None, ws=None):
     """Y = A Omega (m x (k+p)) with the test matrix the range finder draws, not orthonormalized."""
     pr = _prob_for(A, k, p, 0, sketch, prec, seed, stream_id)

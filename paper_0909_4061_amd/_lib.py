@@ -25,6 +25,7 @@ RSVD_GAUSSIAN, RSVD_SRFT = 0, 1
 RSVD_NATIVE, RSVD_BF16, RSVD_BF16X3 = 0, 1, 2
 RSVD_FLAG_SHIFTED, RSVD_FLAG_NONFINITE, RSVD_FLAG_NOCONV = 1, 2, 4
 RSVD_MAX_L = 128
+RSVD_STATIC_SCRATCH_BYTES = 32 << 20
 
 EXPORTS = [
     "rsvd_create", "rsvd_destroy", "rsvd_validate", "rsvd_workspace_bytes", "rsvd_status_string",
@@ -32,6 +33,7 @@ EXPORTS = [
     "rsvd_batched_workspace_bytes", "rsvd_batched", "rsvd_backward_workspace_bytes", "rsvd_backward",
     "rsvd_backward_batched_workspace_bytes", "rsvd_backward_batched", "rsvd_forward_kept", "rsvd_backward_kept",
     "rsvd_batched_kept", "rsvd_backward_batched_kept", "rsvd_full_workspace_bytes", "rsvd_full",
+    "rsvd_full_static",
     "rsvd_sketch", "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
     "rsvd_profile_enable", "rsvd_profile_select", "rsvd_profile_read",
 ]
@@ -92,6 +94,7 @@ def load():
         "rsvd_forward_kept": ([vp, prob, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_full_workspace_bytes": ([prob], sz),
         "rsvd_full": ([vp, prob, vp, vp, vp, vp, vp, sz, vp], i32),
+        "rsvd_full_static": ([vp, prob, vp, vp, vp, vp, vp], i32),
         "rsvd_backward_kept": ([vp, prob, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_draw_omega": ([vp, prob, vp, vp], i32),
         "rsvd_draw_srft": ([vp, prob, vp, vp, vp], i32),

@@ -24,6 +24,7 @@ struct BatchPlan;
 struct rsvd_handle_s {
   int device;
   int32_t* status;  // device word: RSVD_FLAG_* bits accumulated by the kernels
+  char* scratch = nullptr;  // device address of this device's copy of `scratch` (rsvd_full_static)
   // optional launch timing (rsvd_profile_enable)
   std::vector<hipEvent_t> events;  // 2 per record
   std::vector<int> kinds;          // family of each record
@@ -33,6 +34,13 @@ struct rsvd_handle_s {
   std::vector<BatchPlan*> plans;
   hipStream_t capture = nullptr;  // stream the batched graphs are captured on
 };
+
+// Workspace of rsvd_full_static, for callers that cannot allocate: one copy
+// per device, held from the library's first use on that device until the
+// process ends.  Host code never passes `scratch` itself to a kernel (its
+// host-side name is not a device address): rsvd_create looks up the device
+// address once, with the handle's device current, and every launch takes that.
+static __device__ __align__(256) unsigned char scratch[RSVD_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -1526,7 +1534,9 @@ rsvd_status rsvd_create(rsvd_handle* handle, int device) {
   if (!h) return RSVD_E_DEVICE;
   h->device = device;
   h->status = nullptr;
-  if (hipMalloc(&h->status, 16) != hipSuccess || hipMemset(h->status, 0, 16) != hipSuccess) {
+  if (hipMalloc(&h->status, 16) != hipSuccess || hipMemset(h->status, 0, 16) != hipSuccess ||
+      hipGetSymbolAddress(reinterpret_cast<void**>(&h->scratch), HIP_SYMBOL(scratch)) != hipSuccess ||
+      !h->scratch) {
     if (h->status) (void)hipFree(h->status);
     delete h;
     return RSVD_E_DEVICE;
@@ -1692,6 +1702,28 @@ rsvd_status rsvd_full(rsvd_handle h, const rsvd_problem* pr, const void* A, void
   h->plans.push_back(bp);  // most recently used last
   RSVD_TRY(hipGraphLaunch(bp->exec, stream));
   return RSVD_OK;
+}
+
+rsvd_status rsvd_full_static(rsvd_handle h, const rsvd_problem* pr, const void* A, void* U, void* S, void* V,
+                             hipStream_t stream) {
+  const rsvd_status v = validate(pr);
+  if (v != RSVD_OK) return v;
+  const FullLayout F = full_layout(pr);
+  if (F.total > (size_t)RSVD_STATIC_SCRATCH_BYTES) return RSVD_E_WORKSPACE;
+  if (!h || !h->scratch || !A || !U || !S || !V) return RSVD_E_INVAL;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
+  // The kernel sequence of rsvd_full, launched directly (a graph would allocate);
+  // nothing in the workspace has to start at zero.
+  char* ws = h->scratch;
+  DirectRunner dr(h, stream);
+  const Ctx c{F.P, ws + F.base, stream, h->status, h, &dr};
+  void* Q = ws + F.q_off;
+  void* Bt = ws + F.bt_off;
+  rsvd_status s = range_finder_steps(c, pr, A, Q);
+  if (s == RSVD_OK) s = power_steps(c, pr, A, Q);
+  if (s == RSVD_OK) s = project_steps(c, pr, A, Q, Bt);
+  if (s == RSVD_OK) s = svd_steps(c, Bt, Q, U, S, V);
+  return s;
 }
 
 size_t rsvd_backward_workspace_bytes(const rsvd_problem* problem) {

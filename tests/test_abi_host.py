@@ -180,3 +180,16 @@ def test_srft_under_autograd_is_refused(lib, sketch):
     with torch.no_grad(), pytest.raises(ValueError):
         rs.rsvd(A, 4, 2, 0, sketch=sketch)
 
+
+def test_full_static_size_limit_before_handle(lib):
+    # rsvd_full_static checks the problem and its workspace size on the host before it looks at
+    # the handle or any pointer: an oversized problem is refused with RSVD_E_WORKSPACE.
+    from paper_0909_4061_amd import _lib
+    big = _prob(m=4096, n=2048, k=64, p=16, q=1, dtype=__import__("torch").float32)
+    assert lib.rsvd_full_workspace_bytes(ctypes.byref(big)) > _lib.RSVD_STATIC_SCRATCH_BYTES
+    assert lib.rsvd_full_static(None, ctypes.byref(big), None, None, None, None, None) == _lib.RSVD_E_WORKSPACE
+    small = _prob()
+    assert lib.rsvd_full_workspace_bytes(ctypes.byref(small)) <= _lib.RSVD_STATIC_SCRATCH_BYTES
+    assert lib.rsvd_full_static(None, ctypes.byref(small), None, None, None, None, None) == _lib.RSVD_E_INVAL
+    bad = _prob(k=0)
+    assert lib.rsvd_full_static(None, ctypes.byref(bad), None, None, None, None, None) == _lib.RSVD_E_INVAL
