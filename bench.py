@@ -64,9 +64,12 @@ def algorithmic_bytes(m, n, l, q, esize=4):
     return (2 * q + 2) * (m * n + (m + n) * l) * esize
 
 
-def spectral_norm_residual(A, U, S, V, iters=30, block=16, seed=1234):
+def spectral_norm_residual(A, U, S, V, iters=40, block=32, seed=1234):
     """||A - U diag(S) V^T||_2 in FP64 by block subspace iteration with a final
-    Rayleigh-Ritz step (torch on the GPU; a measurement, not part of the method)."""
+    Rayleigh-Ritz step (torch on the GPU; a measurement, not part of the method).
+    40 iterations of a 32-column block agree with the dense-SVD norm to 2e-8
+    relative even when the residual's leading singular values form a flat
+    cluster (tests/test_evaluator.py); 30 x 16 left 9e-5 there."""
     import torch
     A64 = A.double()
     U64, S64, V64 = U.double(), S.double(), V.double()

@@ -165,8 +165,10 @@ rsvd_status rsvd_project(rsvd_handle handle, const rsvd_problem* problem,
                          size_t ws_bytes, hipStream_t stream);
 
 /* Stage B, steps 2-3 of Algorithm 5.1 plus truncation to rank k: an SVD of the
- * small matrix B = U~ S V* (FP64: Gram B B*, Cholesky, one-sided Jacobi),
- * U = Q U~, and the k leading triplets.  Bt: n x l (from rsvd_project);
+ * small matrix B = U~ S V* in FP64, U = Q U~, and the k leading triplets.  For
+ * FP64 data: CholeskyQR of B* = Q_B R, one-sided Jacobi on R^T (backward
+ * stable); for FP32 data: the eigendecomposition of the Gram B B* = U~ S^2 U~*
+ * (Householder tridiagonalization, bisection, inverse iteration).  Bt: n x l (from rsvd_project);
  * Q: m x l; outputs U: m x k, S: k (real, descending), V: n x k, with
  * A ~ U diag(S) V*. */
 rsvd_status rsvd_svd(rsvd_handle handle, const rsvd_problem* problem,
@@ -356,7 +358,8 @@ enum {
   RSVD_KERNEL_JACOBI = 5,     /* l x l one-sided Jacobi */
   RSVD_KERNEL_PACK = 6,       /* packing of the l-column operand before a streaming GEMM */
   RSVD_KERNEL_SRFT = 7,       /* SRFT sketch: one FFT per row of A D, sampled */
-  RSVD_KERNEL_KINDS = 8
+  RSVD_KERNEL_EIG = 8,        /* l x l symmetric eigensolver of B B* (small SVD of FP32 data) */
+  RSVD_KERNEL_KINDS = 9
 };
 
 /* capacity > 0: create `capacity` pairs of hipEvents (an allocation made here,

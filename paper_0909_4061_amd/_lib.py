@@ -37,7 +37,7 @@ EXPORTS = [
     "rsvd_sketch", "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
     "rsvd_profile_enable", "rsvd_profile_select", "rsvd_profile_read",
 ]
-KERNEL_KINDS = ["stream_nn", "stream_tn", "small_gemm", "gram", "chol", "jacobi", "pack", "srft"]
+KERNEL_KINDS = ["stream_nn", "stream_tn", "small_gemm", "gram", "chol", "jacobi", "pack", "srft", "eig"]
 
 
 class RsvdProblem(ctypes.Structure):

@@ -80,7 +80,7 @@ struct Plan {
   bool stream;  // FP32 data: the A-streaming products take the streaming kernels (X packed first)
   Split nn, tn;
   size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rb, RinvT, XU, XV, Uh, sig, flags, srft_d,
-      srft_R, total;
+      srft_R, eigV, eigZ, eigT, total;
 };
 
 bool valid_enum(int32_t v, int32_t lo, int32_t hi) { return v >= lo && v <= hi; }
@@ -164,6 +164,12 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   P.flags = take(64);
   P.srft_d = take(pr->sketch == RSVD_SRFT ? (size_t)P.n * 8 : 0);
   P.srft_R = take(pr->sketch == RSVD_SRFT ? (size_t)P.l * 4 : 0);
+  // eigensolver of the small SVD (FP32 data): reflectors, eigenvectors, then
+  // d, e, tau, the eigenvalues, the norm bound and the flags
+  const bool eig = pr->dtype == RSVD_F32;
+  P.eigV = take(eig ? ll8 : 0);
+  P.eigZ = take(eig ? ll8 : 0);
+  P.eigT = take(eig ? (size_t)(4 * P.l + 1) * 8 + (size_t)P.l * 4 : 0);
   P.total = off;
   return P;
 }
@@ -200,6 +206,7 @@ class Runner {
   virtual hipError_t gram_reduce(const GramReduceParams& p) = 0;
   virtual hipError_t chol(const CholParams& p) = 0;
   virtual hipError_t jacobi(const JacobiParams& p) = 0;
+  virtual hipError_t eig(int stage, const EigParams& p) = 0;
   virtual hipError_t omega(int dtype, const OmegaParams& p) = 0;
   virtual hipError_t trmm(const TrmmParams& p) = 0;
   virtual hipError_t copy(const CopyParams& p) = 0;
@@ -247,6 +254,10 @@ class DirectRunner final : public Runner {
     Timed t(h_, RSVD_KERNEL_JACOBI, st_);
     return launch_jacobi(p, st_);
   }
+  hipError_t eig(int stage, const EigParams& p) override {
+    Timed t(h_, RSVD_KERNEL_EIG, st_);
+    return launch_eig(stage, p, st_);
+  }
   hipError_t omega(int dtype, const OmegaParams& p) override {
     return launch_omega(dtype, p.omega, p.n, p.l, p.seed, p.sid, st_);
   }
@@ -266,7 +277,7 @@ class DirectRunner final : public Runner {
 // problem, with the problems' parameter blocks side by side.
 enum SlotKind {
   SK_GEMM, SK_GRAM_PARTIAL, SK_GRAM_REDUCE, SK_CHOL, SK_JACOBI, SK_OMEGA, SK_TRMM, SK_COPY,
-  SK_SUM_PARTS, SK_SVD_ADJ, SK_QR_SYM, SK_TRI_INV, SK_COPY2D, SK_PACK, SK_STREAM
+  SK_SUM_PARTS, SK_SVD_ADJ, SK_QR_SYM, SK_TRI_INV, SK_COPY2D, SK_PACK, SK_STREAM, SK_EIG
 };
 
 struct Slot {
@@ -309,6 +320,12 @@ class RecordRunner final : public Runner {
   hipError_t chol(const CholParams& p) override { return add(SK_CHOL, 0, 0, false, p, 1); }
   hipError_t jacobi(const JacobiParams& p) override { return add(SK_JACOBI, 0, jacobi_maxl_, false, p, 1); }
   int jacobi_maxl_ = 128;  // the Jacobi variant every problem of the batch runs
+  // eigensolver stage s is recorded with the stage in the dtype slot and the
+  // variant every problem of the batch runs in the prec slot
+  hipError_t eig(int stage, const EigParams& p) override {
+    return add(SK_EIG, stage, eig_maxl_, false, p, eig_blocks(stage, p));
+  }
+  int eig_maxl_ = 128;
   hipError_t omega(int dtype, const OmegaParams& p) override {
     return add(SK_OMEGA, dtype, 0, false, p, omega_blocks(p));
   }
@@ -462,6 +479,7 @@ rsvd_status chol(const Ctx& c, int64_t rows, double* R, bool want_inv, const int
 // Source: the split-K partials of the GEMM that produced it (from_part; the sum
 // is stored into `y`) or `y` itself.  Q (rows x l) may alias y.  If R_out is
 // non-null it receives the combined triangular factor.
+
 rsvd_status orth(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t rows, void* Q, double* R_out) {
   const int64_t l = c.P.l;
   int32_t* flag = c.shift_flag();  // cleared by the first factorization, set by a shifted one
@@ -581,15 +599,6 @@ rsvd_status small_svd(const Ctx& c, const void* Bt, void* S, JacobiParams& j) {
   const Plan& P = c.P;
   double* R = c.at<double>(P.R1);
   rsvd_status s;
-  if (P.dtype == RSVD_F64) {
-    R = c.at<double>(P.Rb);
-    // Q_B (n x l) goes to the Y region, unused by now; Bt itself is only read.
-    s = orth(c, false, no_split(1), const_cast<void*>(Bt), P.n, c.at<void>(P.Y), R);
-  } else {
-    s = gram(c, false, no_split(1), const_cast<void*>(Bt), P.n, nullptr);
-    if (s == RSVD_OK) s = chol(c, P.n, R, false, nullptr, nullptr);
-  }
-  if (s != RSVD_OK) return s;
   j = JacobiParams{};
   j.R = R;
   j.l = (int32_t)P.l;
@@ -601,7 +610,38 @@ rsvd_status small_svd(const Ctx& c, const void* Bt, void* S, JacobiParams& j) {
   j.XV = c.at<void>(P.XV);
   j.S = S;
   j.status = c.status;
-  RSVD_TRY(c.run->jacobi(j));
+  if (P.dtype == RSVD_F64) {
+    R = c.at<double>(P.Rb);
+    j.R = R;
+    // Q_B (n x l) goes to the Y region, unused by now; Bt itself is only read.
+    s = orth(c, false, no_split(1), const_cast<void*>(Bt), P.n, c.at<void>(P.Y), R);
+    if (s != RSVD_OK) return s;
+    RSVD_TRY(c.run->jacobi(j));
+    return RSVD_OK;
+  }
+  // FP32 data: the eigendecomposition of the FP64 Gram B B* = U~ S^2 U~*
+  s = gram(c, false, no_split(1), const_cast<void*>(Bt), P.n, nullptr);
+  if (s != RSVD_OK) return s;
+  EigParams e{};
+  e.G = c.at<double>(P.G);
+  e.Lg = P.Lg;
+  e.l = (int32_t)P.l;
+  e.k = (int32_t)P.k;
+  e.dtype = P.dtype;
+  e.V = c.at<double>(P.eigV);
+  e.Z = c.at<double>(P.eigZ);
+  double* t = c.at<double>(P.eigT);
+  e.tri = t;
+  e.lam = t + 3 * P.l;
+  e.tnorm = t + 4 * P.l;
+  e.flag = reinterpret_cast<int32_t*>(t + 4 * P.l + 1);
+  e.Uh = j.Uh;
+  e.sig = j.sig;
+  e.XU = j.XU;
+  e.XV = j.XV;
+  e.S = S;
+  e.status = c.status;
+  for (int stage = 0; stage < 3; ++stage) RSVD_TRY(c.run->eig(stage, e));
   return RSVD_OK;
 }
 
@@ -1057,6 +1097,7 @@ rsvd_status record_batch(int32_t count, int32_t lmax, Recorder rec, const void* 
   for (int32_t i = 0; i < count; ++i) {
     RecordRunner rr(R.slots);
     rr.jacobi_maxl_ = jacobi_variant(lmax);
+    rr.eig_maxl_ = eig_variant(lmax);
     const rsvd_status s = rec(ctx, i, rr);
     if (s != RSVD_OK) return s == RSVD_E_DEVICE ? RSVD_E_INVAL : s;
     if (rr.cursor() != R.slots.size()) return RSVD_E_INVAL;
@@ -1138,6 +1179,9 @@ hipError_t launch_slots(const Recorded& R, const char* dev, hipStream_t st) {
       case SK_STREAM:
         e = launch_stream_gemm_batched(sl.prec, sl.trans, sl.dtype != 0, (const GemmParams*)ps, bm, nb, st);
         break;
+      case SK_EIG:
+        e = launch_eig_batched(sl.dtype, sl.prec, (const EigParams*)ps, bm, nb, st);
+        break;
     }
     if (e != hipSuccess) return e;
   }
@@ -1162,6 +1206,8 @@ int64_t block_weight(const Slot& sl, size_t i) {
       return reinterpret_cast<const CholParams*>(p)->l;
     case SK_JACOBI:
       return reinterpret_cast<const JacobiParams*>(p)->l;
+    case SK_EIG:
+      return reinterpret_cast<const EigParams*>(p)->l;
     default:
       return 0;
   }

@@ -155,6 +155,36 @@ hipError_t launch_srft_rows(int dtype, const void* A, int64_t lda, int64_t m, in
 // single-problem launcher would launch.
 struct BlockMap { int32_t item, local; };
 
+// ---------------------------------------------------------------------------
+// Symmetric eigensolver of the FP64 Gram W = B B* (small SVD of FP32 data):
+// stage 0 tridiagonalizes W (one workgroup), stage 1 finds each eigenpair of
+// T and transforms it back (one wave per eigenvalue), stage 2 orthogonalizes
+// clustered and flagged columns (one workgroup).  Outputs as JacobiParams.
+struct EigParams {
+  const double* G;  // Lg x Lg, the upper triangle of W (row i, columns >= i)
+  int32_t Lg;
+  int32_t l;
+  int32_t k;
+  int32_t dtype;    // element type of XU, XV, S
+  double* V;        // l x l workspace: row i = Householder vector of step i
+  double* tri;      // 3 l workspace: diagonal d, off-diagonal e, tau
+  double* lam;      // l workspace: eigenvalues of W, descending
+  double* Z;        // l x l workspace: row j = eigenvector j
+  int32_t* flag;    // l workspace
+  double* tnorm;    // 1 workspace: Gershgorin bound of ||T||
+  double* Uh;       // l x l: column j = eigenvector j (descending)
+  double* sig;      // l: sqrt(max(lambda_j, 0))
+  void* XU;         // l x k: Uh[:, :k] in the element type
+  void* XV;         // l x k: Uh[:, :k] diag(1/sig) in the element type
+  void* S;          // k
+  int32_t* status;
+};
+int eig_variant(int32_t l);
+int64_t eig_blocks(int stage, const EigParams& p);
+hipError_t launch_eig(int stage, const EigParams& p, hipStream_t st);
+hipError_t launch_eig_batched(int stage, int variant, const EigParams* ps, const BlockMap* bm, int64_t nblocks,
+                              hipStream_t st);
+
 struct GramReduceParams {
   const double* gpart;
   int64_t nblk;

@@ -1,0 +1,616 @@
+// The SVD of the small matrix B (Algorithm 5.1, step 2) for FP32 data, from
+// the FP64 Gram W = B B* (l x l): the eigenvalues of W are the squared
+// singular values of B and its eigenvectors are B's left singular vectors U~.
+// For FP32 data this carries the accuracy of the Gram itself (relative error
+// about u_64 (sigma_1 / sigma_j)^2 in sigma_j), well below what FP32 arithmetic
+// resolves.  Three launches:
+//
+//   tridiag  : one workgroup.  Householder reduction W = Q_T T Q_T^T with T
+//              symmetric tridiagonal.  The workgroup holds W in registers, a
+//              2 x (l/16) tile per thread, 16 threads (one DPP row) per pair
+//              of rows; step i takes its reflector from row i (the column by
+//              symmetry), forms p = tau W v with 16-lane reductions, and
+//              applies the symmetric rank-2 update W -= v w^T + w v^T.  Two
+//              barriers per step (the reflector; the products p), with the
+//              LDS vectors double-buffered.  Writes d, e, tau and the
+//              reflectors.
+//   tri_eig  : one wave per eigenvalue, four per workgroup.  Bisection on T
+//              scaled to norm below one, by Sturm counts (three-term
+//              recurrence of the leading minors, rescaled by powers of two)
+//              at 64 points per round (one per lane): 9 rounds give 54 bits.
+//              Then two steps of inverse iteration on T (LDL^T of T - lambda I
+//              with tiny pivots lifted) from a pseudo-random start, the back
+//              transform by the reflectors, and the outputs of this column.
+//              An eigenvalue at the level of roundoff (|lambda| <= 64 eps ||T||)
+//              or a failed solve keeps the random start and is flagged.
+//   eig_fix  : one workgroup.  Eigenvalues closer than 2^-24 ||T|| form a
+//              cluster: inverse iteration gives each member accurately within
+//              the cluster's subspace but not orthogonal to the others, so the
+//              members are orthogonalized in order (Gram-Schmidt, twice).
+//              Flagged columns are orthogonalized against every other column
+//              (a single flagged column becomes the missing eigenvector, since
+//              the others span its complement).  Returns at once when no
+//              column needs it.
+#include <float.h>
+
+#include "common.hpp"
+
+namespace rsvd {
+
+namespace {
+
+// Move a double across lanes of a 16-lane DPP row.
+template <int CTRL>
+__device__ __forceinline__ double eig_dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a DPP row; every lane ends with the same bits
+// (each addition pairs the same two operands in all lanes).
+__device__ __forceinline__ double row_sum16(double v) {
+  v += eig_dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += eig_dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += eig_dpp<0x141>(v);  // row_half_mirror
+  v += eig_dpp<0x140>(v);  // row_mirror
+  return v;
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the whole wave, the same value in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row_sum16(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, eig_dpp<0x4E>(v));
+  v = fmax(v, eig_dpp<0xB1>(v));
+  v = fmax(v, eig_dpp<0x141>(v));
+  v = fmax(v, eig_dpp<0x140>(v));
+  return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
+}
+
+__device__ __forceinline__ double rcp_refined(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Deterministic start vector of inverse iteration for eigenvalue j: a uniform
+// value in [-1, 1) from an integer hash of (j, i).
+__device__ __forceinline__ double start_value(int j, int i) {
+  uint32_t h = (uint32_t)j * 0x9E3779B1u ^ ((uint32_t)i + 0x7F4A7C15u) * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  return (double)(h >> 8) * 0x1p-23 - 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// tridiag: W -> (d, e, tau, reflectors).  Thread t owns rows 2 (t / 16) and
+// 2 (t / 16) + 1, columns TC (t % 16) .. TC (t % 16) + TC - 1.
+template <int MAXL>
+__device__ __forceinline__ void tridiag_body(const EigParams& p) {
+  constexpr int TR = 2, TC = MAXL / 16, NA = MAXL / TR;
+  static_assert(MAXL % 16 == 0 && NA <= 64, "tile layout");
+  __shared__ __attribute__((aligned(16))) double vbuf[2][MAXL];
+  __shared__ __attribute__((aligned(16))) double pbuf[2][MAXL];
+  __shared__ double kpart[2][NA];
+  __shared__ double taus[2];
+  const int tid = threadIdx.x, a = tid >> 4, b = tid & 15, lane = tid & 63, wave = tid >> 6;
+  const int l = p.l, Lg = p.Lg;
+  const int r0 = TR * a, c0 = TC * b;
+  double* __restrict__ dvec = p.tri;
+  double* __restrict__ evec = p.tri + l;
+  double* __restrict__ tvec = p.tri + 2 * l;
+
+  double w[TR][TC];
+#pragma unroll
+  for (int ri = 0; ri < TR; ++ri)
+#pragma unroll
+    for (int cc = 0; cc < TC; ++cc) {
+      const int r = r0 + ri, c = c0 + cc;
+      w[ri][cc] = (r < l && c < l) ? p.G[(int64_t)min(r, c) * Lg + max(r, c)] : 0.0;
+    }
+
+  for (int i = 0; i + 2 < l; ++i) {
+    const int buf = i & 1;
+    // 1. reflector of row i (= column i) by its tile-row
+    if (a == (i >> 1)) {
+      // row i of the tile (constant register indices on either branch)
+      double x[TC];
+      if (i & 1) {
+#pragma unroll
+        for (int cc = 0; cc < TC; ++cc) x[cc] = w[1][cc];
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < TC; ++cc) x[cc] = w[0][cc];
+      }
+      double s2 = 0.0, x0 = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < TC; ++cc) {
+        const int c = c0 + cc;
+        s2 += c >= i + 2 ? x[cc] * x[cc] : 0.0;
+        x0 += c == i + 1 ? x[cc] : 0.0;
+      }
+      s2 = row_sum16(s2);
+      x0 = row_sum16(x0);
+      double tau = 0.0, beta = x0, scal = 0.0;
+      if (s2 > 0.0) {
+        beta = -copysign(sqrt(fma(x0, x0, s2)), x0);
+        tau = (beta - x0) / beta;
+        scal = 1.0 / (x0 - beta);
+      }
+#pragma unroll
+      for (int cc = 0; cc < TC; ++cc) {
+        const int c = c0 + cc;
+        const double v = c == i + 1 ? 1.0 : (c >= i + 2 ? x[cc] * scal : 0.0);
+        vbuf[buf][c] = v;
+        if (c < l) p.V[(int64_t)i * l + c] = v;
+        if (c == i) dvec[i] = x[cc];
+      }
+      if (b == 0) {
+        taus[buf] = tau;
+        tvec[i] = tau;
+        evec[i] = beta;
+      }
+    }
+    __syncthreads();
+    // 2. p = tau W v over the rows below i (waves whose rows are all <= i are done)
+    const bool live = 8 * wave + 7 > i;
+    double vr[TR], vc[TC], pr[TR];
+    const double tau = taus[buf];
+#pragma unroll
+    for (int ri = 0; ri < TR; ++ri) vr[ri] = vbuf[buf][r0 + ri];
+#pragma unroll
+    for (int cc = 0; cc < TC; ++cc) vc[cc] = vbuf[buf][c0 + cc];
+    if (live) {
+      double kp = 0.0;
+#pragma unroll
+      for (int ri = 0; ri < TR; ++ri) {
+        double s = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < TC; ++cc) s = fma(w[ri][cc], vc[cc], s);
+        s = row_sum16(s) * tau;
+        pr[ri] = r0 + ri > i ? s : 0.0;
+        kp = fma(pr[ri], vr[ri], kp);
+      }
+      if (b == 0) {
+#pragma unroll
+        for (int ri = 0; ri < TR; ++ri) pbuf[buf][r0 + ri] = pr[ri];
+        kpart[buf][a] = kp;
+      }
+    }
+    __syncthreads();
+    // 3. K = tau/2 p.v, w = p - K v, W -= v w^T + w v^T (the products of rows and
+    //    columns <= i are zeros, read as such)
+    if (live) {
+      const double kin = (lane < NA && 2 * lane + 1 > i) ? kpart[buf][lane] : 0.0;
+      const double K = 0.5 * tau * wave_sum(kin);
+      double wr[TR];
+#pragma unroll
+      for (int ri = 0; ri < TR; ++ri) wr[ri] = fma(-K, vr[ri], pr[ri]);
+#pragma unroll
+      for (int cc = 0; cc < TC; ++cc) {
+        const int c = c0 + cc;
+        const double wc = fma(-K, vc[cc], c > i ? pbuf[buf][c] : 0.0);
+#pragma unroll
+        for (int ri = 0; ri < TR; ++ri) w[ri][cc] = fma(-vr[ri], wc, fma(-wr[ri], vc[cc], w[ri][cc]));
+      }
+    }
+  }
+  // the last 2 x 2 block (or 1 x 1) is already tridiagonal
+#pragma unroll
+  for (int ri = 0; ri < TR; ++ri)
+#pragma unroll
+    for (int cc = 0; cc < TC; ++cc) {
+      const int r = r0 + ri, c = c0 + cc;
+      if (r < l && r >= l - 2 && c == r) dvec[r] = w[ri][cc];
+      if (l >= 2 && r == l - 2 && c == l - 1) evec[l - 2] = w[ri][cc];
+    }
+  if (tid == 0) {
+    if (l >= 1) evec[l - 1] = 0.0;
+    for (int i = max(l - 2, 0); i < l; ++i) tvec[i] = 0.0;
+  }
+}
+
+// Number of eigenvalues of the scaled T below x: sign changes of the leading
+// minors p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}, rescaled by a power of two
+// every four steps.  An exact zero minor takes the sign opposite to the one
+// before it.
+__device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const double* __restrict__ e2p, int l,
+                                           double x) {
+  double pm2 = 0.0, pm1 = 1.0;
+  int cnt = 0;
+  for (int i = 0; i < l; ++i) {
+    double pi = fma(ds[i] - x, pm1, -e2p[i] * pm2);
+    pi = pi == 0.0 ? -0x1p-60 * pm1 : pi;
+    cnt += (pi < 0.0) != (pm1 < 0.0) ? 1 : 0;
+    pm2 = pm1;
+    pm1 = pi;
+    if ((i & 3) == 3) {
+      const int ex = __builtin_amdgcn_frexp_exp(pm1);
+      pm1 = __builtin_amdgcn_ldexp(pm1, -ex);
+      pm2 = __builtin_amdgcn_ldexp(pm2, -ex);
+    }
+  }
+  return cnt;
+}
+
+// tri_eig: eigenpair j = 4 blockIdx + wave (descending order) of T, then of W.
+template <int MAXL>
+__device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) {
+  __shared__ double ds[MAXL];   // scaled diagonal
+  __shared__ double es[MAXL];   // scaled off-diagonal, es[i] couples i and i + 1
+  __shared__ double e2p[MAXL];  // es[i - 1]^2 (0 for i = 0)
+  __shared__ double invD[4][MAXL];
+  __shared__ double Lm[4][MAXL];
+  __shared__ double xs[4][MAXL];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l = p.l;
+  const double* __restrict__ dvec = p.tri;
+  const double* __restrict__ evec = p.tri + l;
+  const double* __restrict__ tvec = p.tri + 2 * l;
+  for (int i = tid; i < MAXL; i += 256) {
+    ds[i] = i < l ? dvec[i] : 0.0;
+    es[i] = i + 1 < l ? evec[i] : 0.0;
+  }
+  __syncthreads();
+  // ||T|| bound (Gershgorin) and its power-of-two scale, the same in every wave
+  double g = 0.0;
+  for (int i = lane; i < l; i += 64) g = fmax(g, fabs(ds[i]) + fabs(es[i]) + (i > 0 ? fabs(es[i - 1]) : 0.0));
+  const double tnorm = wave_max(g);
+  const int tex = tnorm > 0.0 ? __builtin_amdgcn_frexp_exp(tnorm) : 0;
+  __syncthreads();  // every wave has read the unscaled values
+  for (int i = tid; i < MAXL; i += 256) {
+    ds[i] = __builtin_amdgcn_ldexp(ds[i], -tex);
+    es[i] = __builtin_amdgcn_ldexp(es[i], -tex);
+  }
+  __syncthreads();
+  for (int i = tid; i < MAXL; i += 256) e2p[i] = i > 0 ? es[i - 1] * es[i - 1] : 0.0;
+  __syncthreads();
+  const int j = 4 * bid + wv;
+  if (j >= l) return;
+  if (bid == 0 && tid == 0) p.tnorm[0] = tnorm;
+
+  // 1. bisection for the (l - 1 - j)-th smallest eigenvalue of the scaled T
+  double glo = 0.0, ghi = 0.0;
+  {
+    double lo = 1.0, hi = -1.0;
+    for (int i = lane; i < l; i += 64) {
+      const double r = fabs(es[i]) + (i > 0 ? fabs(es[i - 1]) : 0.0);
+      lo = fmin(lo, ds[i] - r);
+      hi = fmax(hi, ds[i] + r);
+    }
+    glo = -wave_max(-lo);
+    ghi = wave_max(hi);
+  }
+  const double slack = 4.0 * DBL_EPSILON * fmax(fabs(glo), fabs(ghi)) + DBL_MIN;
+  double lo = glo - slack, hi = ghi + slack;
+  const int jasc = l - 1 - j;
+  const double frac = (double)(lane + 1) * (1.0 / 65.0);
+  for (int round = 0; round < 9; ++round) {
+    const double wdt = hi - lo;
+    const double x = fma(wdt, frac, lo);
+    const int cnt = tnorm > 0.0 ? sturm_count(ds, e2p, l, x) : (x > 0.0 ? l : 0);
+    const uint64_t mask = __ballot(cnt <= jasc);
+    const int m = __popcll(mask) - 1;  // last point at or below the eigenvalue
+    const double nlo = m >= 0 ? fma(wdt, (double)(m + 1) * (1.0 / 65.0), lo) : lo;
+    const double nhi = m + 1 <= 63 ? fma(wdt, (double)(m + 2) * (1.0 / 65.0), lo) : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  const double mu = 0.5 * (lo + hi);
+  const double lam = __builtin_amdgcn_ldexp(mu, tex);
+
+  // 2. inverse iteration (every lane runs the scalar recurrences; the stores agree)
+  double* __restrict__ iD = invD[wv];
+  double* __restrict__ L = Lm[wv];
+  double* __restrict__ x = xs[wv];
+  bool flagged = !(fabs(mu) > 64.0 * DBL_EPSILON);
+  for (int i = lane; i < l; i += 64) x[i] = start_value(j, i);
+  if (!flagged) {
+    const double ptol = 0x1p-62;
+    double D = ds[0] - mu;
+    D = fabs(D) < ptol ? (D < 0.0 ? -ptol : ptol) : D;
+    double inv = rcp_refined(D);
+    iD[0] = inv;
+    for (int i = 1; i < l; ++i) {
+      const double li = es[i - 1] * inv;
+      D = fma(-li, es[i - 1], ds[i] - mu);
+      D = fabs(D) < ptol ? (D < 0.0 ? -ptol : ptol) : D;
+      inv = rcp_refined(D);
+      iD[i] = inv;
+      L[i] = li;
+    }
+    for (int it = 0; it < 2; ++it) {
+      double y = x[0];
+      for (int i = 1; i < l; ++i) {
+        y = fma(-L[i], y, x[i]);
+        x[i] = y;
+      }
+      double xn = x[l - 1] * iD[l - 1];
+      x[l - 1] = xn;
+      for (int i = l - 2; i >= 0; --i) {
+        xn = fma(-L[i + 1], xn, x[i] * iD[i]);
+        x[i] = xn;
+      }
+      double s = 0.0;
+      for (int i = lane; i < l; i += 64) s = fma(x[i], x[i], s);
+      s = wave_sum(s);
+      if (!(s > 0.0) || !isfinite(s)) {
+        flagged = true;
+        break;
+      }
+      const double sc = 1.0 / sqrt(s);
+      for (int i = lane; i < l; i += 64) x[i] *= sc;
+    }
+    if (flagged)
+      for (int i = lane; i < l; i += 64) x[i] = start_value(j, i);
+  }
+  // 3. back transform z = H_0 H_1 ... H_{l-3} x (normalized)
+  double z0 = lane < l ? x[lane] : 0.0;
+  double z1 = lane + 64 < l ? x[lane + 64] : 0.0;
+  if (flagged) {
+    const double s = wave_sum(z0 * z0 + z1 * z1);
+    const double sc = 1.0 / sqrt(s);
+    z0 *= sc;
+    z1 *= sc;
+  }
+  for (int i = l - 3; i >= 0; --i) {
+    const double t = tvec[i];
+    const double v0 = lane < l ? p.V[(int64_t)i * l + lane] : 0.0;
+    const double v1 = lane + 64 < l ? p.V[(int64_t)i * l + lane + 64] : 0.0;
+    const double dot = wave_sum(fma(v0, z0, v1 * z1)) * t;
+    z0 = fma(-dot, v0, z0);
+    z1 = fma(-dot, v1, z1);
+  }
+  // 4. this column's outputs
+  const double sg = sqrt(fmax(lam, 0.0));
+  if (lane == 0) {
+    p.lam[j] = lam;
+    p.flag[j] = flagged ? 1 : 0;
+    p.sig[j] = sg;
+    if (j < p.k) {
+      if (p.dtype == RSVD_F64) ((double*)p.S)[j] = sg;
+      else ((float*)p.S)[j] = (float)sg;
+    }
+  }
+  const double rs = sg > 0.0 ? 1.0 / sg : 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = lane + 64 * h;
+    const double zi = h ? z1 : z0;
+    if (i < l) {
+      p.Z[(int64_t)j * l + i] = zi;
+      p.Uh[(int64_t)i * l + j] = zi;
+      if (j < p.k) {
+        if (p.dtype == RSVD_F64) {
+          ((double*)p.XU)[(int64_t)i * p.k + j] = zi;
+          ((double*)p.XV)[(int64_t)i * p.k + j] = zi * rs;
+        } else {
+          ((float*)p.XU)[(int64_t)i * p.k + j] = (float)zi;
+          ((float*)p.XV)[(int64_t)i * p.k + j] = (float)(zi * rs);
+        }
+      }
+    }
+  }
+}
+
+// eig_fix: one workgroup of 256 threads.  Column c of Zs holds eigenvector c.
+template <int MAXL>
+__device__ __forceinline__ void eig_fix_body(const EigParams& p) {
+  constexpr int LDZ = MAXL + 1;
+  __shared__ double Zs[MAXL * LDZ];  // Zs[c * LDZ + i] = component i of vector c
+  __shared__ double coef[MAXL];
+  __shared__ int todo[MAXL];         // 0 keep, 1 cluster member after the first, 2 flagged
+  __shared__ int clu0[MAXL];         // first member of the vector's cluster
+  __shared__ double lam_s[MAXL];
+  __shared__ int any_s;
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l = p.l, half = (l + 1) >> 1;
+  for (int j = tid; j < l; j += 256) {
+    lam_s[j] = p.lam[j];
+    todo[j] = p.flag[j];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double tol = 0x1p-24 * p.tnorm[0];
+    int any = 0, first = 0;
+    for (int j = 0; j < l; ++j) {
+      if (j > 0 && !(lam_s[j - 1] - lam_s[j] >= tol)) {
+        clu0[j] = first;
+      } else {
+        first = j;
+        clu0[j] = j;
+      }
+      const int t = todo[j] ? 2 : (clu0[j] != j ? 1 : 0);
+      todo[j] = t;
+      any |= t;
+    }
+    any_s = any;
+  }
+  __syncthreads();
+  if (!any_s) return;
+  for (int idx = tid; idx < l * l; idx += 256) {
+    const int c = idx / l, i = idx - c * l;
+    Zs[c * LDZ + i] = p.Z[(int64_t)c * l + i];
+  }
+  __syncthreads();
+  // phase 1 (clusters, flagged columns left out), then phase 2 (flagged columns)
+  for (int phase = 1; phase <= 2; ++phase) {
+    for (int j = 0; j < l; ++j) {
+      if (todo[j] != phase) continue;  // uniform
+      for (int attempt = 0; attempt < 2 * MAXL; ++attempt) {
+        for (int rep = 0; rep < 2; ++rep) {
+          // coefficients against the columns this one must be orthogonal to: thread
+          // pair (2 c, 2 c + 1) takes the two halves of the dot product with column c
+          {
+            const int c = tid >> 1, h = tid & 1;
+            bool use = false;
+            if (c < l) {
+              if (phase == 1) use = c >= clu0[j] && c < j && todo[c] != 2;
+              else use = c != j && (todo[c] != 2 || c < j);
+            }
+            double s = 0.0;
+            if (use)
+              for (int i = h * half; i < min(l, (h + 1) * half); ++i) s = fma(Zs[c * LDZ + i], Zs[j * LDZ + i], s);
+            s += eig_dpp<0xB1>(s);  // quad_perm [1,0,3,2]: the partner's half
+            if (c < MAXL && h == 0) coef[c] = s;
+          }
+          __syncthreads();
+          {
+            const int i = tid >> 1, h = tid & 1;
+            double s = 0.0;
+            if (i < l)
+              for (int c = h * half; c < min(l, (h + 1) * half); ++c) s = fma(-coef[c], Zs[c * LDZ + i], s);
+            s += eig_dpp<0xB1>(s);
+            __syncthreads();  // every thread has read column j for its coefficient before it changes
+            if (i < l && h == 0) Zs[j * LDZ + i] += s;
+          }
+          __syncthreads();
+        }
+        double s = 0.0;
+        for (int i = tid; i < l; i += 256) s = fma(Zs[j * LDZ + i], Zs[j * LDZ + i], s);
+        s = wave_sum(s);
+        if (lane == 0) red[wv] = s;
+        __syncthreads();
+        const double nrm2 = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+        // Two Gram-Schmidt passes leave the column orthogonal to the others to working
+        // precision unless nearly all of it was cancelled; a random column keeps about
+        // (l - #others) / l of its squared norm, at least 1 / l.
+        if (nrm2 > 0x1p-20) {
+          const double sc = 1.0 / sqrt(nrm2);
+          for (int i = tid; i < l; i += 256) Zs[j * LDZ + i] *= sc;
+          __syncthreads();
+          break;
+        }
+        // the column lay (almost) in the span of the others: restart from a unit vector
+        for (int i = tid; i < l; i += 256) Zs[j * LDZ + i] = (i == attempt % l) ? 1.0 : 0.0;
+        __syncthreads();
+      }
+    }
+  }
+  // outputs of the columns that changed
+  for (int idx = tid; idx < l * l; idx += 256) {
+    const int j = idx / l, i = idx - j * l;
+    if (todo[j] == 0) continue;
+    const double zi = Zs[j * LDZ + i];
+    p.Uh[(int64_t)i * l + j] = zi;
+    if (j < p.k) {
+      const double sg = p.sig[j];
+      const double rs = sg > 0.0 ? 1.0 / sg : 0.0;
+      if (p.dtype == RSVD_F64) {
+        ((double*)p.XU)[(int64_t)i * p.k + j] = zi;
+        ((double*)p.XV)[(int64_t)i * p.k + j] = zi * rs;
+      } else {
+        ((float*)p.XU)[(int64_t)i * p.k + j] = (float)zi;
+        ((float*)p.XV)[(int64_t)i * p.k + j] = (float)(zi * rs);
+      }
+    }
+  }
+}
+
+template <int MAXL>
+__global__ __launch_bounds__(MAXL * 8) void tridiag_kernel(const EigParams p) { tridiag_body<MAXL>(p); }
+
+template <int MAXL>
+__global__ __launch_bounds__(MAXL * 8) void tridiag_batched(const EigParams* __restrict__ ps,
+                                                          const BlockMap* __restrict__ bm) {
+  tridiag_body<MAXL>(ps[bm[blockIdx.x].item]);
+}
+
+template <int MAXL>
+__global__ __launch_bounds__(256) void tri_eig_kernel(const EigParams p) { tri_eig_body<MAXL>(p, blockIdx.x); }
+
+template <int MAXL>
+__global__ __launch_bounds__(256) void tri_eig_batched(const EigParams* __restrict__ ps,
+                                                      const BlockMap* __restrict__ bm) {
+  const BlockMap b = bm[blockIdx.x];
+  tri_eig_body<MAXL>(ps[b.item], b.local);
+}
+
+template <int MAXL>
+__global__ __launch_bounds__(256) void eig_fix_kernel(const EigParams p) { eig_fix_body<MAXL>(p); }
+
+template <int MAXL>
+__global__ __launch_bounds__(256) void eig_fix_batched(const EigParams* __restrict__ ps,
+                                                      const BlockMap* __restrict__ bm) {
+  eig_fix_body<MAXL>(ps[bm[blockIdx.x].item]);
+}
+
+bool eig_params_ok(const EigParams& p) {
+  return p.l >= 1 && p.l <= 128 && p.k >= 1 && p.k <= p.l && p.Lg >= p.l;
+}
+
+}  // namespace
+
+int eig_variant(int32_t l) { return l <= 32 ? 32 : (l <= 64 ? 64 : (l <= 96 ? 96 : 128)); }
+
+int64_t tri_eig_blocks(const EigParams& p) { return (p.l + 3) / 4; }
+
+#define RSVD_EIG_SWITCH(VAR, CALL)              \
+  switch (VAR) {                                \
+    case 32: CALL(32); break;                   \
+    case 64: CALL(64); break;                   \
+    case 96: CALL(96); break;                   \
+    case 128: CALL(128); break;                 \
+    default: return hipErrorInvalidValue;       \
+  }
+
+int64_t eig_blocks(int stage, const EigParams& p) { return stage == 1 ? tri_eig_blocks(p) : 1; }
+
+hipError_t launch_eig(int stage, const EigParams& p, hipStream_t st) {
+  if (!eig_params_ok(p) || stage < 0 || stage > 2) return hipErrorInvalidValue;
+  const int v = eig_variant(p.l);
+  const dim3 g2((unsigned)tri_eig_blocks(p));
+#define RSVD_L1(M) hipLaunchKernelGGL(tridiag_kernel<M>, dim3(1), dim3(M * 8), 0, st, p)
+#define RSVD_L2(M) hipLaunchKernelGGL(tri_eig_kernel<M>, g2, dim3(256), 0, st, p)
+#define RSVD_L3(M) hipLaunchKernelGGL(eig_fix_kernel<M>, dim3(1), dim3(256), 0, st, p)
+  if (stage == 0) {
+    RSVD_EIG_SWITCH(v, RSVD_L1)
+  } else if (stage == 1) {
+    RSVD_EIG_SWITCH(v, RSVD_L2)
+  } else {
+    RSVD_EIG_SWITCH(v, RSVD_L3)
+  }
+#undef RSVD_L1
+#undef RSVD_L2
+#undef RSVD_L3
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_batched(int stage, int variant, const EigParams* ps, const BlockMap* bm, int64_t nblocks,
+                              hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 g((unsigned)nblocks);
+#define RSVD_B1(M) hipLaunchKernelGGL(tridiag_batched<M>, g, dim3(M * 8), 0, st, ps, bm)
+#define RSVD_B2(M) hipLaunchKernelGGL(tri_eig_batched<M>, g, dim3(256), 0, st, ps, bm)
+#define RSVD_B3(M) hipLaunchKernelGGL(eig_fix_batched<M>, g, dim3(256), 0, st, ps, bm)
+  if (stage == 0) {
+    RSVD_EIG_SWITCH(variant, RSVD_B1)
+  } else if (stage == 1) {
+    RSVD_EIG_SWITCH(variant, RSVD_B2)
+  } else {
+    RSVD_EIG_SWITCH(variant, RSVD_B3)
+  }
+#undef RSVD_B1
+#undef RSVD_B2
+#undef RSVD_B3
+  return hipGetLastError();
+}
+
+}  // namespace rsvd
