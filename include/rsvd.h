@@ -151,8 +151,14 @@ rsvd_status rsvd_range_finder(rsvd_handle handle, const rsvd_problem* problem,
                               hipStream_t stream);
 
 /* Stage A, power steps: Algorithm 4.4 steps 3-6.  For j = 1..q:
- * Qt = orth(A* Q), Q = orth(A Qt), each orth by CholeskyQR2.  Q (m x l) is
- * read and overwritten in place.  A no-op when q = 0. */
+ * Qt = orth(A* Q), Q = orth(A Qt).  The last Q is orthonormalized by
+ * CholeskyQR2 (FP64 Gram and Cholesky, a shifted third pass when needed).
+ * The bases before it only feed the next product and take one CholeskyQR
+ * pass (all three when the first needed a shift): they are
+ * orthonormal to about u kappa (u the element type's unit roundoff, kappa
+ * the condition number of the product), a well-conditioned basis of the
+ * same range.  Q (m x l) is read and overwritten in place; its input need
+ * only be a well-conditioned basis.  A no-op when q = 0. */
 rsvd_status rsvd_power_iter(rsvd_handle handle, const rsvd_problem* problem,
                             const void* A, void* Q, void* ws, size_t ws_bytes,
                             hipStream_t stream);
@@ -235,10 +241,12 @@ rsvd_status rsvd_backward(rsvd_handle handle, const rsvd_problem* problem,
                           hipStream_t stream);
 
 /* The forward of rsvd_backward kept for it: the whole randomized SVD of A
- * (outputs U, S, V as rsvd_svd, the same values as the four hot-path calls)
- * computed in an adjoint workspace `ws` (rsvd_backward_workspace_bytes
- * bytes), where it leaves every basis of the power scheme with its
- * triangular factor, B* and the SVD of B.  rsvd_backward_kept then skips the
+ * (outputs U, S, V as rsvd_svd) computed in an adjoint workspace `ws`
+ * (rsvd_backward_workspace_bytes bytes), where it leaves every basis of the
+ * power scheme with its triangular factor, B* and the SVD of B.  Every basis
+ * is orthonormalized by CholeskyQR2 (the adjoint differentiates exact QR
+ * factors), so U, S, V equal the four hot-path calls' (which take one pass for
+ * the bases inside the power scheme) up to the element type's rounding.  rsvd_backward_kept then skips the
  * recomputation; the state stays valid while `ws` is not otherwise used. */
 rsvd_status rsvd_forward_kept(rsvd_handle handle, const rsvd_problem* problem,
                               const void* A, void* U, void* S, void* V,
@@ -345,6 +353,24 @@ rsvd_status rsvd_draw_srft(rsvd_handle handle, const rsvd_problem* problem,
 rsvd_status rsvd_orth(rsvd_handle handle, const rsvd_problem* problem,
                       int64_t rows, void* Y, double* R, void* ws,
                       size_t ws_bytes, hipStream_t stream);
+
+/* --- Achievable peaks (measurement aids, not part of the method) --------- */
+
+/* Read `bytes` (a multiple of 16) of the DEVICE buffer `buf` (16-byte aligned)
+ * once, with 16-byte loads over 2048 workgroups of 256 threads and eight loads
+ * in flight per thread, and write one float per workgroup to the DEVICE array
+ * `sink` (2048 floats).  Enqueued on `stream`; the caller times it.  The
+ * streaming-read rate it reaches is the HBM ceiling the benchmark reports
+ * beside the datasheet's. */
+rsvd_status rsvd_probe_hbm_read(const void* buf, size_t bytes, float* sink, hipStream_t stream);
+
+/* `blocks` workgroups of four waves, each wave issuing `iters` rounds of four
+ * independent MFMA accumulations on register operands -- kind 0: BF16
+ * 32x32x16 (32768 flops each), 1: FP32 32x32x2 (4096), 2: FP64 16x16x4
+ * (2048) -- then writing 256 floats per workgroup to the DEVICE array `sink`.
+ * Enqueued on `stream`; the caller times it.  Its rate is the MFMA ceiling the
+ * benchmark reports beside the datasheet's. */
+rsvd_status rsvd_probe_mfma(int32_t kind, int64_t iters, int64_t blocks, float* sink, hipStream_t stream);
 
 /* --- Kernel timing (a profiling aid) ------------------------------------ */
 

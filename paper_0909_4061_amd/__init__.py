@@ -587,3 +587,25 @@ def profile_read(device=None):
     ms = (ctypes.c_double * n)()
     _lib.check(h.lib.rsvd_profile_read(h.ptr, launches, ms), "rsvd_profile_read")
     return {name: (int(launches[i]), float(ms[i])) for i, name in enumerate(_lib.KERNEL_KINDS)}
+
+
+MFMA_PROBE_FLOPS = {"bf16": 32768, "fp32": 4096, "fp64": 2048}
+
+
+def probe_hbm_read(buf):
+    """Enqueue the library's streaming-read probe over the device tensor `buf` (a measurement aid:
+    the caller times it on the current stream).  Returns the sink tensor."""
+    nbytes = buf.numel() * buf.element_size() // 16 * 16
+    sink = torch.empty(2048, dtype=torch.float32, device=buf.device)
+    _lib.check(_lib.load().rsvd_probe_hbm_read(_ptr(buf), nbytes, _ptr(sink), _stream(buf.device)),
+               "rsvd_probe_hbm_read")
+    return sink, nbytes
+
+
+def probe_mfma(kind, iters, blocks, device=None):
+    """Enqueue the library's MFMA-loop probe (kind "bf16", "fp32" or "fp64"); returns (sink, flops)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    k = {"bf16": 0, "fp32": 1, "fp64": 2}[kind]
+    sink = torch.empty(int(blocks) * 256, dtype=torch.float32, device=dev)
+    _lib.check(_lib.load().rsvd_probe_mfma(k, int(iters), int(blocks), _ptr(sink), _stream(dev)), "rsvd_probe_mfma")
+    return sink, float(blocks) * 4 * 4 * float(iters) * MFMA_PROBE_FLOPS[kind]

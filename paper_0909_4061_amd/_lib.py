@@ -35,7 +35,7 @@ EXPORTS = [
     "rsvd_batched_kept", "rsvd_backward_batched_kept", "rsvd_full_workspace_bytes", "rsvd_full",
     "rsvd_full_static",
     "rsvd_sketch", "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
-    "rsvd_profile_enable", "rsvd_profile_select", "rsvd_profile_read",
+    "rsvd_profile_enable", "rsvd_profile_select", "rsvd_profile_read", "rsvd_probe_hbm_read", "rsvd_probe_mfma",
 ]
 KERNEL_KINDS = ["stream_nn", "stream_tn", "small_gemm", "gram", "chol", "jacobi", "pack", "srft", "eig"]
 
@@ -103,6 +103,8 @@ def load():
         "rsvd_profile_enable": ([vp, i32], i32),
         "rsvd_profile_select": ([vp, ctypes.c_uint32], i32),
         "rsvd_profile_read": ([vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], i32),
+        "rsvd_probe_hbm_read": ([vp, sz, vp, vp], i32),
+        "rsvd_probe_mfma": ([i32, i64, i64, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -167,7 +167,7 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   // eigensolver of the small SVD (FP32 data): reflectors, eigenvectors, then
   // d, e, tau, the eigenvalues, the norm bound and the flags
   const bool eig = pr->dtype == RSVD_F32;
-  P.eigV = take(eig ? ll8 : 0);
+  P.eigV = take(eig ? (size_t)P.l * EIG_LDV * 8 : 0);
   P.eigZ = take(eig ? ll8 : 0);
   P.eigT = take(eig ? (size_t)(4 * P.l + 1) * 8 + (size_t)P.l * 4 : 0);
   P.total = off;
@@ -479,13 +479,22 @@ rsvd_status chol(const Ctx& c, int64_t rows, double* R, bool want_inv, const int
 // Source: the split-K partials of the GEMM that produced it (from_part; the sum
 // is stored into `y`) or `y` itself.  Q (rows x l) may alias y.  If R_out is
 // non-null it receives the combined triangular factor.
-
-rsvd_status orth(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t rows, void* Q, double* R_out) {
+//
+// full == false (the bases inside the power scheme that only feed the next
+// product): the second pass, like the third, runs only when the first needed a
+// shift.  One pass with the FP64 Gram leaves Q = fl(Y R^-1) orthonormal to
+// about u kappa(Y) (u of the element type): a well-conditioned basis of the
+// same range, which is all the next application of A or A* uses, and no more
+// accurate a range than Y stored in the element type carries anyway.  A
+// shifted first pass (Y numerically rank deficient) takes all three passes, as
+// the final basis does.
+rsvd_status orth(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t rows, void* Q, double* R_out,
+                 bool full = true) {
   const int64_t l = c.P.l;
   int32_t* flag = c.shift_flag();  // cleared by the first factorization, set by a shifted one
   double* Rs[3] = {c.at<double>(c.P.R1), c.at<double>(c.P.R2), c.at<double>(c.P.R3)};
   for (int pass = 0; pass < 3; ++pass) {
-    const int32_t* gate = pass == 2 ? flag : nullptr;
+    const int32_t* gate = (pass == 2 || (pass == 1 && !full)) ? flag : nullptr;
     const bool src_part = pass == 0 && from_part;
     void* src = pass == 0 ? y : Q;
     rsvd_status s = gram(c, src_part, sp, src, rows, gate);
@@ -505,9 +514,10 @@ rsvd_status orth(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t
   return RSVD_OK;
 }
 
-// Y = A X (NN, rows m) or A^T X (TN, rows n), orthonormalized into Q.
+// Y = A X (NN, rows m) or A^T X (TN, rows n), orthonormalized into Q (one
+// CholeskyQR pass unless `full` or a shift, see orth).
 rsvd_status apply_and_orth(const Ctx& c, const rsvd_problem* pr, bool trans, const void* A, const void* X,
-                           void* Q) {
+                           void* Q, bool full) {
   const Plan& P = c.P;
   const Split& sp = trans ? P.tn : P.nn;
   const int64_t rows = trans ? P.n : P.m;
@@ -516,7 +526,7 @@ rsvd_status apply_and_orth(const Ctx& c, const rsvd_problem* pr, bool trans, con
   rsvd_status s = gemm(c, pr->prec, trans, A, pr->lda, rows, K, X, P.l, (int32_t)P.l, y, P.l, sp,
                        sp.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
   if (s != RSVD_OK) return s;
-  return orth(c, sp.S > 1, sp, y, rows, Q, nullptr);
+  return orth(c, sp.S > 1, sp, y, rows, Q, nullptr, full);
 }
 
 // Sum the S split-K partial products (rows x l) into `out` in a fixed order.
@@ -569,9 +579,10 @@ rsvd_status range_finder_steps(const Ctx& c, const rsvd_problem* pr, const void*
 rsvd_status power_steps(const Ctx& c, const rsvd_problem* pr, const void* A, void* Q) {
   void* Qt = c.at<void>(c.P.Qt);
   for (int j = 0; j < pr->q; ++j) {
-    rsvd_status s = apply_and_orth(c, pr, true, A, Q, Qt);  // Qt = orth(A^T Q)
+    // every basis but the last only feeds the next product: one CholeskyQR pass
+    rsvd_status s = apply_and_orth(c, pr, true, A, Q, Qt, false);  // Qt = orth(A^T Q)
     if (s != RSVD_OK) return s;
-    s = apply_and_orth(c, pr, false, A, Qt, Q);  // Q = orth(A Qt)
+    s = apply_and_orth(c, pr, false, A, Qt, Q, j == pr->q - 1);  // Q = orth(A Qt)
     if (s != RSVD_OK) return s;
   }
   return RSVD_OK;
@@ -1588,6 +1599,18 @@ rsvd_status rsvd_create(rsvd_handle* handle, int device) {
     return RSVD_E_DEVICE;
   }
   *handle = h;
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_probe_hbm_read(const void* buf, size_t bytes, float* sink, hipStream_t stream) {
+  if (!buf || !sink || bytes < 16 || bytes % 16 != 0 || !aligned16(buf)) return RSVD_E_INVAL;
+  RSVD_TRY(launch_hbm_read(buf, bytes, sink, stream));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_probe_mfma(int32_t kind, int64_t iters, int64_t blocks, float* sink, hipStream_t stream) {
+  if (!sink || kind < 0 || kind > 2 || iters < 1 || blocks < 1 || blocks > (int64_t)1 << 20) return RSVD_E_INVAL;
+  RSVD_TRY(launch_mfma_loop(kind, iters, blocks, sink, stream));
   return RSVD_OK;
 }
 

@@ -134,6 +134,11 @@ struct JacobiParams {
 hipError_t launch_jacobi(const JacobiParams& p, hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// Achievable-peak probes (measurement aids).
+hipError_t launch_hbm_read(const void* buf, size_t bytes, float* sink, hipStream_t st);
+hipError_t launch_mfma_loop(int kind, int64_t iters, int64_t blocks, float* sink, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // Random test matrices (counter-based Philox4x64-10).
 hipError_t launch_omega(int dtype, void* omega, int64_t n, int32_t l, uint64_t seed,
                         uint64_t stream_id, hipStream_t st);
@@ -166,7 +171,7 @@ struct EigParams {
   int32_t l;
   int32_t k;
   int32_t dtype;    // element type of XU, XV, S
-  double* V;        // l x l workspace: row i = Householder vector of step i
+  double* V;        // l x EIG_LDV workspace: row i = Householder vector of step i
   double* tri;      // 3 l workspace: diagonal d, off-diagonal e, tau
   double* lam;      // l workspace: eigenvalues of W, descending
   double* Z;        // l x l workspace: row j = eigenvector j
@@ -179,6 +184,7 @@ struct EigParams {
   void* S;          // k
   int32_t* status;
 };
+constexpr int EIG_LDV = 128;  // row stride of the reflectors (any compiled variant writes whole rows)
 int eig_variant(int32_t l);
 int64_t eig_blocks(int stage, const EigParams& p);
 hipError_t launch_eig(int stage, const EigParams& p, hipStream_t st);

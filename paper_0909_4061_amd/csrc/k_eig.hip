@@ -98,12 +98,28 @@ __device__ __forceinline__ double start_value(int j, int i) {
 }
 
 // ---------------------------------------------------------------------------
-// tridiag: W -> (d, e, tau, reflectors).  Thread t owns rows 2 (t / 16) and
-// 2 (t / 16) + 1, columns TC (t % 16) .. TC (t % 16) + TC - 1.
+// tridiag: W -> (d, e, tau, reflectors).  Thread t owns rows TR (t / 16) ..
+// TR (t / 16) + TR - 1 and columns TC (t % 16) .. TC (t % 16) + TC - 1: one
+// DPP row of 16 lanes per block of TR rows.  Four rows per tile (fewer waves
+// repeating the reductions) from l > 64 on, two below.
+template <int MAXL>
+constexpr int tri_rows() { return MAXL > 64 ? 4 : 2; }
+template <int MAXL>
+constexpr int tri_threads() { return MAXL / tri_rows<MAXL>() * 16; }
+
+// 1/sqrt(x) and 1/x from the hardware estimates and two Newton steps each.
+__device__ __forceinline__ double rsq_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
 template <int MAXL>
 __device__ __forceinline__ void tridiag_body(const EigParams& p) {
-  constexpr int TR = 2, TC = MAXL / 16, NA = MAXL / TR;
-  static_assert(MAXL % 16 == 0 && NA <= 64, "tile layout");
+  constexpr int TR = tri_rows<MAXL>(), TC = MAXL / 16, NA = MAXL / TR, RPW = 4 * TR;  // rows per wave
+  static_assert(MAXL % 16 == 0 && NA <= 64 && TC % 2 == 0, "tile layout");
+  typedef double d2 __attribute__((ext_vector_type(2)));
   __shared__ __attribute__((aligned(16))) double vbuf[2][MAXL];
   __shared__ __attribute__((aligned(16))) double pbuf[2][MAXL];
   __shared__ double kpart[2][NA];
@@ -126,40 +142,49 @@ __device__ __forceinline__ void tridiag_body(const EigParams& p) {
 
   for (int i = 0; i + 2 < l; ++i) {
     const int buf = i & 1;
-    // 1. reflector of row i (= column i) by its tile-row
-    if (a == (i >> 1)) {
-      // row i of the tile (constant register indices on either branch)
+    // 1. reflector of row i (= column i) by its block of rows (one DPP row)
+    if (a == i / TR) {
+      // row i of the tile (constant register indices on every branch)
       double x[TC];
-      if (i & 1) {
+      const int ri = i % TR;
 #pragma unroll
-        for (int cc = 0; cc < TC; ++cc) x[cc] = w[1][cc];
-      } else {
+      for (int q = 0; q < TR; ++q)
+        if (ri == q) {
 #pragma unroll
-        for (int cc = 0; cc < TC; ++cc) x[cc] = w[0][cc];
-      }
-      double s2 = 0.0, x0 = 0.0;
+          for (int cc = 0; cc < TC; ++cc) x[cc] = w[q][cc];
+        }
+      double s2 = 0.0, x0 = 0.0, dii = 0.0;
 #pragma unroll
       for (int cc = 0; cc < TC; ++cc) {
         const int c = c0 + cc;
-        s2 += c >= i + 2 ? x[cc] * x[cc] : 0.0;
-        x0 += c == i + 1 ? x[cc] : 0.0;
+        s2 = c >= i + 2 ? fma(x[cc], x[cc], s2) : s2;
+        x0 = c == i + 1 ? x[cc] : x0;
+        dii = c == i ? x[cc] : dii;
       }
       s2 = row_sum16(s2);
       x0 = row_sum16(x0);
       double tau = 0.0, beta = x0, scal = 0.0;
       if (s2 > 0.0) {
-        beta = -copysign(sqrt(fma(x0, x0, s2)), x0);
-        tau = (beta - x0) / beta;
-        scal = 1.0 / (x0 - beta);
+        const double n2 = fma(x0, x0, s2);
+        const double rn = rsq_refined(n2);   // 1 / ||x||
+        const double nrm = n2 * rn;          // ||x||
+        beta = x0 >= 0.0 ? -nrm : nrm;       // -sign(x0) ||x||
+        tau = fma(x0, x0 >= 0.0 ? rn : -rn, 1.0);  // (beta - x0) / beta = 1 - x0 / beta
+        scal = rcp_refined(x0 - beta);
       }
+      double v[TC];
 #pragma unroll
       for (int cc = 0; cc < TC; ++cc) {
         const int c = c0 + cc;
-        const double v = c == i + 1 ? 1.0 : (c >= i + 2 ? x[cc] * scal : 0.0);
-        vbuf[buf][c] = v;
-        if (c < l) p.V[(int64_t)i * l + c] = v;
-        if (c == i) dvec[i] = x[cc];
+        v[cc] = c == i + 1 ? 1.0 : (c >= i + 2 ? x[cc] * scal : 0.0);
       }
+      double* vrow = p.V + (int64_t)i * EIG_LDV + c0;
+#pragma unroll
+      for (int cc = 0; cc < TC; cc += 2) {
+        *reinterpret_cast<d2*>(&vbuf[buf][c0 + cc]) = d2{v[cc], v[cc + 1]};
+        *reinterpret_cast<d2*>(vrow + cc) = d2{v[cc], v[cc + 1]};
+      }
+      if (c0 <= i && i < c0 + TC) dvec[i] = dii;  // the lane holding the diagonal entry
       if (b == 0) {
         taus[buf] = tau;
         tvec[i] = tau;
@@ -168,14 +193,22 @@ __device__ __forceinline__ void tridiag_body(const EigParams& p) {
     }
     __syncthreads();
     // 2. p = tau W v over the rows below i (waves whose rows are all <= i are done)
-    const bool live = 8 * wave + 7 > i;
+    const bool live = RPW * wave + RPW - 1 > i;
     double vr[TR], vc[TC], pr[TR];
     const double tau = taus[buf];
-#pragma unroll
-    for (int ri = 0; ri < TR; ++ri) vr[ri] = vbuf[buf][r0 + ri];
-#pragma unroll
-    for (int cc = 0; cc < TC; ++cc) vc[cc] = vbuf[buf][c0 + cc];
     if (live) {
+#pragma unroll
+      for (int ri = 0; ri < TR; ri += 2) {
+        const d2 t = *reinterpret_cast<const d2*>(&vbuf[buf][r0 + ri]);
+        vr[ri] = t.x;
+        vr[ri + 1] = t.y;
+      }
+#pragma unroll
+      for (int cc = 0; cc < TC; cc += 2) {
+        const d2 t = *reinterpret_cast<const d2*>(&vbuf[buf][c0 + cc]);
+        vc[cc] = t.x;
+        vc[cc + 1] = t.y;
+      }
       double kp = 0.0;
 #pragma unroll
       for (int ri = 0; ri < TR; ++ri) {
@@ -188,7 +221,7 @@ __device__ __forceinline__ void tridiag_body(const EigParams& p) {
       }
       if (b == 0) {
 #pragma unroll
-        for (int ri = 0; ri < TR; ++ri) pbuf[buf][r0 + ri] = pr[ri];
+        for (int ri = 0; ri < TR; ri += 2) *reinterpret_cast<d2*>(&pbuf[buf][r0 + ri]) = d2{pr[ri], pr[ri + 1]};
         kpart[buf][a] = kp;
       }
     }
@@ -196,17 +229,22 @@ __device__ __forceinline__ void tridiag_body(const EigParams& p) {
     // 3. K = tau/2 p.v, w = p - K v, W -= v w^T + w v^T (the products of rows and
     //    columns <= i are zeros, read as such)
     if (live) {
-      const double kin = (lane < NA && 2 * lane + 1 > i) ? kpart[buf][lane] : 0.0;
+      const double kin = (lane < NA && TR * lane + TR - 1 > i) ? kpart[buf][lane] : 0.0;
       const double K = 0.5 * tau * wave_sum(kin);
       double wr[TR];
 #pragma unroll
       for (int ri = 0; ri < TR; ++ri) wr[ri] = fma(-K, vr[ri], pr[ri]);
 #pragma unroll
-      for (int cc = 0; cc < TC; ++cc) {
-        const int c = c0 + cc;
-        const double wc = fma(-K, vc[cc], c > i ? pbuf[buf][c] : 0.0);
+      for (int cc = 0; cc < TC; cc += 2) {
+        const d2 t = *reinterpret_cast<const d2*>(&pbuf[buf][c0 + cc]);
+        const double pc[2] = {c0 + cc > i ? t.x : 0.0, c0 + cc + 1 > i ? t.y : 0.0};
 #pragma unroll
-        for (int ri = 0; ri < TR; ++ri) w[ri][cc] = fma(-vr[ri], wc, fma(-wr[ri], vc[cc], w[ri][cc]));
+        for (int h = 0; h < 2; ++h) {
+          const double wc = fma(-K, vc[cc + h], pc[h]);
+#pragma unroll
+          for (int ri = 0; ri < TR; ++ri)
+            w[ri][cc + h] = fma(-vr[ri], wc, fma(-wr[ri], vc[cc + h], w[ri][cc + h]));
+        }
       }
     }
   }
@@ -225,38 +263,60 @@ __device__ __forceinline__ void tridiag_body(const EigParams& p) {
   }
 }
 
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ dbl2 ld2(const double* p) { return *reinterpret_cast<const dbl2*>(p); }
+
 // Number of eigenvalues of the scaled T below x: sign changes of the leading
 // minors p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}, rescaled by a power of two
 // every four steps.  An exact zero minor takes the sign opposite to the one
-// before it.
-__device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const double* __restrict__ e2p, int l,
+// before it.  The diagonal is padded to lq (a multiple of four) with 4 > |x|
+// and e = 0, which changes no count; the loads of the next four steps are
+// issued before the current four are computed.
+__device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const double* __restrict__ e2p, int lq,
                                            double x) {
   double pm2 = 0.0, pm1 = 1.0;
   int cnt = 0;
-  for (int i = 0; i < l; ++i) {
-    double pi = fma(ds[i] - x, pm1, -e2p[i] * pm2);
-    pi = pi == 0.0 ? -0x1p-60 * pm1 : pi;
-    cnt += (pi < 0.0) != (pm1 < 0.0) ? 1 : 0;
-    pm2 = pm1;
-    pm1 = pi;
-    if ((i & 3) == 3) {
-      const int ex = __builtin_amdgcn_frexp_exp(pm1);
-      pm1 = __builtin_amdgcn_ldexp(pm1, -ex);
-      pm2 = __builtin_amdgcn_ldexp(pm2, -ex);
+  dbl2 da = ld2(ds), db = ld2(ds + 2), ea = ld2(e2p), eb = ld2(e2p + 2);
+  for (int ib = 0; ib < lq; ib += 4) {
+    const int nb = ib + 4 < lq ? ib + 4 : ib;
+    const dbl2 nda = ld2(ds + nb), ndb = ld2(ds + nb + 2), nea = ld2(e2p + nb), neb = ld2(e2p + nb + 2);
+    const double dd[4] = {da.x, da.y, db.x, db.y}, ee[4] = {ea.x, ea.y, eb.x, eb.y};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double pi = fma(dd[u] - x, pm1, -ee[u] * pm2);
+      pi = pi == 0.0 ? -0x1p-60 * pm1 : pi;
+      cnt += (pi < 0.0) != (pm1 < 0.0) ? 1 : 0;
+      pm2 = pm1;
+      pm1 = pi;
     }
+    const int ex = __builtin_amdgcn_frexp_exp(pm1);
+    pm1 = __builtin_amdgcn_ldexp(pm1, -ex);
+    pm2 = __builtin_amdgcn_ldexp(pm2, -ex);
+    da = nda;
+    db = ndb;
+    ea = nea;
+    eb = neb;
   }
   return cnt;
 }
 
 // tri_eig: eigenpair j = 4 blockIdx + wave (descending order) of T, then of W.
-template <int MAXL>
+// STAGE: the reflectors of the back transform are staged in LDS (MAXL^2
+// doubles) once for the workgroup's four waves -- for a single matrix, whose
+// few workgroups then wait on no global loads; a batch of many matrices keeps
+// the LDS small (more workgroups per CU) and reads them from global memory one
+// reflector ahead.
+template <int MAXL, bool STAGE>
 __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) {
-  __shared__ double ds[MAXL];   // scaled diagonal
-  __shared__ double es[MAXL];   // scaled off-diagonal, es[i] couples i and i + 1
-  __shared__ double e2p[MAXL];  // es[i - 1]^2 (0 for i = 0)
-  __shared__ double invD[4][MAXL];
-  __shared__ double Lm[4][MAXL];
-  __shared__ double xs[4][MAXL];
+  __shared__ __attribute__((aligned(16))) double ds[MAXL];   // scaled diagonal (4.0 past l)
+  __shared__ __attribute__((aligned(16))) double es[MAXL];   // scaled off-diagonal, es[i] couples i and i + 1
+  __shared__ __attribute__((aligned(16))) double e2p[MAXL];  // es[i - 1]^2 (0 for i = 0)
+  __shared__ __attribute__((aligned(16))) double invD[4][MAXL];
+  __shared__ __attribute__((aligned(16))) double Lm[4][MAXL];
+  __shared__ __attribute__((aligned(16))) double xs[4][MAXL];
+  __shared__ __attribute__((aligned(16))) double Vs[STAGE ? MAXL * MAXL : 2];  // reflector i at Vs[i * MAXL]
+  __shared__ double ts[MAXL];                                                  // tau
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int l = p.l;
   const double* __restrict__ dvec = p.tri;
@@ -266,6 +326,16 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
     ds[i] = i < l ? dvec[i] : 0.0;
     es[i] = i + 1 < l ? evec[i] : 0.0;
   }
+  for (int i = tid; i < MAXL; i += 256) ts[i] = i < l ? tvec[i] : 0.0;
+  // the reflectors of the back transform, staged once for the workgroup's four waves
+  if (STAGE) {
+    const dbl2* __restrict__ src = reinterpret_cast<const dbl2*>(p.V);
+    constexpr int PER_ROW = MAXL / 2;
+    for (int q = tid; q < (l - 2 > 0 ? l - 2 : 0) * PER_ROW; q += 256) {
+      const int r = q / PER_ROW, c2 = q - r * PER_ROW;
+      *reinterpret_cast<dbl2*>(Vs + r * MAXL + 2 * c2) = src[(int64_t)r * (EIG_LDV / 2) + c2];
+    }
+  }
   __syncthreads();
   // ||T|| bound (Gershgorin) and its power-of-two scale, the same in every wave
   double g = 0.0;
@@ -274,12 +344,13 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
   const int tex = tnorm > 0.0 ? __builtin_amdgcn_frexp_exp(tnorm) : 0;
   __syncthreads();  // every wave has read the unscaled values
   for (int i = tid; i < MAXL; i += 256) {
-    ds[i] = __builtin_amdgcn_ldexp(ds[i], -tex);
+    ds[i] = i < l ? __builtin_amdgcn_ldexp(ds[i], -tex) : 4.0;
     es[i] = __builtin_amdgcn_ldexp(es[i], -tex);
   }
   __syncthreads();
   for (int i = tid; i < MAXL; i += 256) e2p[i] = i > 0 ? es[i - 1] * es[i - 1] : 0.0;
   __syncthreads();
+  const int lq = (l + 3) & ~3;  // the recurrences run over whole blocks of four
   const int j = 4 * bid + wv;
   if (j >= l) return;
   if (bid == 0 && tid == 0) p.tnorm[0] = tnorm;
@@ -303,7 +374,7 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
   for (int round = 0; round < 9; ++round) {
     const double wdt = hi - lo;
     const double x = fma(wdt, frac, lo);
-    const int cnt = tnorm > 0.0 ? sturm_count(ds, e2p, l, x) : (x > 0.0 ? l : 0);
+    const int cnt = tnorm > 0.0 ? sturm_count(ds, e2p, lq, x) : (x > 0.0 ? l : 0);
     const uint64_t mask = __ballot(cnt <= jasc);
     const int m = __popcll(mask) - 1;  // last point at or below the eigenvalue
     const double nlo = m >= 0 ? fma(wdt, (double)(m + 1) * (1.0 / 65.0), lo) : lo;
@@ -319,32 +390,85 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
   double* __restrict__ L = Lm[wv];
   double* __restrict__ x = xs[wv];
   bool flagged = !(fabs(mu) > 64.0 * DBL_EPSILON);
-  for (int i = lane; i < l; i += 64) x[i] = start_value(j, i);
+  for (int i = lane; i < MAXL; i += 64) x[i] = i < l ? start_value(j, i) : 0.0;
   if (!flagged) {
+    // LDL^T of the scaled T - mu I over lq (the padding rows decouple: e = 0), tiny
+    // pivots lifted to +-2^-62; every lane runs the recurrence and stores the same
+    // values.  Loads run four steps ahead.
     const double ptol = 0x1p-62;
-    double D = ds[0] - mu;
-    D = fabs(D) < ptol ? (D < 0.0 ? -ptol : ptol) : D;
-    double inv = rcp_refined(D);
-    iD[0] = inv;
-    for (int i = 1; i < l; ++i) {
-      const double li = es[i - 1] * inv;
-      D = fma(-li, es[i - 1], ds[i] - mu);
-      D = fabs(D) < ptol ? (D < 0.0 ? -ptol : ptol) : D;
-      inv = rcp_refined(D);
-      iD[i] = inv;
-      L[i] = li;
+    double inv = 0.0, eprev = 0.0;
+    dbl2 da = ld2(ds), db = ld2(ds + 2), ea = ld2(es), eb = ld2(es + 2);
+    for (int ib = 0; ib < lq; ib += 4) {
+      const int nb = ib + 4 < lq ? ib + 4 : ib;
+      const dbl2 nda = ld2(ds + nb), ndb = ld2(ds + nb + 2), nea = ld2(es + nb), neb = ld2(es + nb + 2);
+      const double dd[4] = {da.x, da.y, db.x, db.y}, ee[4] = {ea.x, ea.y, eb.x, eb.y};
+      double li4[4], iv4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double li = eprev * inv;  // 0 at i = 0 (eprev = 0)
+        double D = fma(-li, eprev, dd[u] - mu);
+        D = fabs(D) < ptol ? (D < 0.0 ? -ptol : ptol) : D;
+        inv = rcp_refined(D);
+        li4[u] = li;
+        iv4[u] = inv;
+        eprev = ee[u];
+      }
+      *reinterpret_cast<dbl2*>(iD + ib) = dbl2{iv4[0], iv4[1]};
+      *reinterpret_cast<dbl2*>(iD + ib + 2) = dbl2{iv4[2], iv4[3]};
+      *reinterpret_cast<dbl2*>(L + ib) = dbl2{li4[0], li4[1]};
+      *reinterpret_cast<dbl2*>(L + ib + 2) = dbl2{li4[2], li4[3]};
+      da = nda;
+      db = ndb;
+      ea = nea;
+      eb = neb;
     }
     for (int it = 0; it < 2; ++it) {
-      double y = x[0];
-      for (int i = 1; i < l; ++i) {
-        y = fma(-L[i], y, x[i]);
-        x[i] = y;
+      // L y = x (forward), then D L^T x = y (backward), in place
+      double y = 0.0;
+      dbl2 la = ld2(L), lb = ld2(L + 2), xa = ld2(x), xb = ld2(x + 2);
+      for (int ib = 0; ib < lq; ib += 4) {
+        const int nb = ib + 4 < lq ? ib + 4 : ib;
+        const dbl2 nla = ld2(L + nb), nlb = ld2(L + nb + 2), nxa = ld2(x + nb), nxb = ld2(x + nb + 2);
+        const double ll[4] = {la.x, la.y, lb.x, lb.y}, xx[4] = {xa.x, xa.y, xb.x, xb.y};
+        double yy[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          y = fma(-ll[u], y, xx[u]);  // L[0] = 0
+          yy[u] = y;
+        }
+        *reinterpret_cast<dbl2*>(x + ib) = dbl2{yy[0], yy[1]};
+        *reinterpret_cast<dbl2*>(x + ib + 2) = dbl2{yy[2], yy[3]};
+        la = nla;
+        lb = nlb;
+        xa = nxa;
+        xb = nxb;
       }
-      double xn = x[l - 1] * iD[l - 1];
-      x[l - 1] = xn;
-      for (int i = l - 2; i >= 0; --i) {
-        xn = fma(-L[i + 1], xn, x[i] * iD[i]);
-        x[i] = xn;
+      // x_i = y_i / D_i - L_{i+1} x_{i+1}, from i = lq - 1 down (L[lq] taken as 0)
+      double xn = 0.0, lnext = 0.0;
+      int ib = lq - 4;
+      dbl2 ya = ld2(x + ib), yb = ld2(x + ib + 2), va = ld2(iD + ib), vb = ld2(iD + ib + 2), la2 = ld2(L + ib),
+           lb2 = ld2(L + ib + 2);
+      for (; ib >= 0; ib -= 4) {
+        const int nb = ib >= 4 ? ib - 4 : ib;
+        const dbl2 nya = ld2(x + nb), nyb = ld2(x + nb + 2), nva = ld2(iD + nb), nvb = ld2(iD + nb + 2),
+                   nla = ld2(L + nb), nlb = ld2(L + nb + 2);
+        const double yv[4] = {ya.x, ya.y, yb.x, yb.y}, iv[4] = {va.x, va.y, vb.x, vb.y},
+                     lv[4] = {la2.x, la2.y, lb2.x, lb2.y};
+        double xo[4];
+#pragma unroll
+        for (int u = 3; u >= 0; --u) {
+          xn = fma(-lnext, xn, yv[u] * iv[u]);
+          xo[u] = xn;
+          lnext = lv[u];
+        }
+        *reinterpret_cast<dbl2*>(x + ib) = dbl2{xo[0], xo[1]};
+        *reinterpret_cast<dbl2*>(x + ib + 2) = dbl2{xo[2], xo[3]};
+        ya = nya;
+        yb = nyb;
+        va = nva;
+        vb = nvb;
+        la2 = nla;
+        lb2 = nlb;
       }
       double s = 0.0;
       for (int i = lane; i < l; i += 64) s = fma(x[i], x[i], s);
@@ -357,7 +481,7 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
       for (int i = lane; i < l; i += 64) x[i] *= sc;
     }
     if (flagged)
-      for (int i = lane; i < l; i += 64) x[i] = start_value(j, i);
+      for (int i = lane; i < MAXL; i += 64) x[i] = i < l ? start_value(j, i) : 0.0;
   }
   // 3. back transform z = H_0 H_1 ... H_{l-3} x (normalized)
   double z0 = lane < l ? x[lane] : 0.0;
@@ -368,13 +492,29 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
     z0 *= sc;
     z1 *= sc;
   }
-  for (int i = l - 3; i >= 0; --i) {
-    const double t = tvec[i];
-    const double v0 = lane < l ? p.V[(int64_t)i * l + lane] : 0.0;
-    const double v1 = lane + 64 < l ? p.V[(int64_t)i * l + lane + 64] : 0.0;
-    const double dot = wave_sum(fma(v0, z0, v1 * z1)) * t;
-    z0 = fma(-dot, v0, z0);
-    z1 = fma(-dot, v1, z1);
+  // (columns at or past l of a reflector row are masked)
+  if (STAGE) {
+    for (int i = l - 3; i >= 0; --i) {
+      const double v0 = lane < l ? Vs[i * MAXL + lane] : 0.0;
+      const double v1 = lane + 64 < l ? Vs[i * MAXL + (lane + 64 < MAXL ? lane + 64 : 0)] : 0.0;
+      const double dot = wave_sum(fma(v0, z0, v1 * z1)) * ts[i];
+      z0 = fma(-dot, v0, z0);
+      z1 = fma(-dot, v1, z1);
+    }
+  } else if (l >= 3) {
+    const double* __restrict__ V = p.V;
+    double v0 = lane < l ? V[(int64_t)(l - 3) * EIG_LDV + lane] : 0.0;
+    double v1 = lane + 64 < l ? V[(int64_t)(l - 3) * EIG_LDV + lane + 64] : 0.0;
+    for (int i = l - 3; i >= 0; --i) {
+      const int ni = i > 0 ? i - 1 : 0;
+      const double n0 = lane < l ? V[(int64_t)ni * EIG_LDV + lane] : 0.0;
+      const double n1 = lane + 64 < l ? V[(int64_t)ni * EIG_LDV + lane + 64] : 0.0;
+      const double dot = wave_sum(fma(v0, z0, v1 * z1)) * ts[i];
+      z0 = fma(-dot, v0, z0);
+      z1 = fma(-dot, v1, z1);
+      v0 = n0;
+      v1 = n1;
+    }
   }
   // 4. this column's outputs
   const double sg = sqrt(fmax(lam, 0.0));
@@ -525,22 +665,22 @@ __device__ __forceinline__ void eig_fix_body(const EigParams& p) {
 }
 
 template <int MAXL>
-__global__ __launch_bounds__(MAXL * 8) void tridiag_kernel(const EigParams p) { tridiag_body<MAXL>(p); }
+__global__ __launch_bounds__(tri_threads<MAXL>()) void tridiag_kernel(const EigParams p) { tridiag_body<MAXL>(p); }
 
 template <int MAXL>
-__global__ __launch_bounds__(MAXL * 8) void tridiag_batched(const EigParams* __restrict__ ps,
-                                                          const BlockMap* __restrict__ bm) {
+__global__ __launch_bounds__(tri_threads<MAXL>()) void tridiag_batched(const EigParams* __restrict__ ps,
+                                                                     const BlockMap* __restrict__ bm) {
   tridiag_body<MAXL>(ps[bm[blockIdx.x].item]);
 }
 
 template <int MAXL>
-__global__ __launch_bounds__(256) void tri_eig_kernel(const EigParams p) { tri_eig_body<MAXL>(p, blockIdx.x); }
+__global__ __launch_bounds__(256) void tri_eig_kernel(const EigParams p) { tri_eig_body<MAXL, true>(p, blockIdx.x); }
 
 template <int MAXL>
 __global__ __launch_bounds__(256) void tri_eig_batched(const EigParams* __restrict__ ps,
                                                       const BlockMap* __restrict__ bm) {
   const BlockMap b = bm[blockIdx.x];
-  tri_eig_body<MAXL>(ps[b.item], b.local);
+  tri_eig_body<MAXL, false>(ps[b.item], b.local);
 }
 
 template <int MAXL>
@@ -577,7 +717,7 @@ hipError_t launch_eig(int stage, const EigParams& p, hipStream_t st) {
   if (!eig_params_ok(p) || stage < 0 || stage > 2) return hipErrorInvalidValue;
   const int v = eig_variant(p.l);
   const dim3 g2((unsigned)tri_eig_blocks(p));
-#define RSVD_L1(M) hipLaunchKernelGGL(tridiag_kernel<M>, dim3(1), dim3(M * 8), 0, st, p)
+#define RSVD_L1(M) hipLaunchKernelGGL(tridiag_kernel<M>, dim3(1), dim3(tri_threads<M>()), 0, st, p)
 #define RSVD_L2(M) hipLaunchKernelGGL(tri_eig_kernel<M>, g2, dim3(256), 0, st, p)
 #define RSVD_L3(M) hipLaunchKernelGGL(eig_fix_kernel<M>, dim3(1), dim3(256), 0, st, p)
   if (stage == 0) {
@@ -597,7 +737,7 @@ hipError_t launch_eig_batched(int stage, int variant, const EigParams* ps, const
                               hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
   const dim3 g((unsigned)nblocks);
-#define RSVD_B1(M) hipLaunchKernelGGL(tridiag_batched<M>, g, dim3(M * 8), 0, st, ps, bm)
+#define RSVD_B1(M) hipLaunchKernelGGL(tridiag_batched<M>, g, dim3(tri_threads<M>()), 0, st, ps, bm)
 #define RSVD_B2(M) hipLaunchKernelGGL(tri_eig_batched<M>, g, dim3(256), 0, st, ps, bm)
 #define RSVD_B3(M) hipLaunchKernelGGL(eig_fix_batched<M>, g, dim3(256), 0, st, ps, bm)
   if (stage == 0) {

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import paper_0909_4061_amd as rs
-from oracle import philox
+from oracle import philox, rsvd as orsvd
 from oracle import rsvd_grad as og
 from tests.gpu_common import to_np
 from workloads import build_matrix, build_matrix_torch, spectrum
@@ -156,8 +156,9 @@ def test_backward_batched_full_size_differentiable_workload():
 
 
 def test_backward_batched_kept_matches_recomputation():
-    # the kept batched forward returns rsvd_batched's outputs and the kept adjoint
-    # the recomputing adjoint's gA, bit for bit
+    # the kept batched adjoint returns the recomputing adjoint's gA, bit for bit; the
+    # kept batched forward (CholeskyQR2 for every basis) returns rsvd_batched's outputs
+    # (one pass for the bases inside the power scheme) up to FP32 rounding
     shapes = [(400, 300, 10), (200, 150, 6), (900, 700, 20)]
     p, q, seed = 6, 1, 8
     ks = [s[2] for s in shapes]
@@ -171,8 +172,11 @@ def test_backward_batched_kept_matches_recomputation():
     g_re = rs.rsvd_backward_batched(As, gUs, gSs, gVs, ks, p, q, seed=seed)
     g_kept = rs.rsvd_backward_batched_kept(As, gUs, gSs, gVs, ks, p, q, ws, seed=seed)
     torch.cuda.synchronize()
-    for o, r in zip(outs, ref):
-        for a, b in zip(o, r):
-            assert torch.equal(a, b)
+    for (U, S, V), (U0, S0, V0) in zip(outs, ref):
+        S, S0 = S.double().cpu().numpy(), S0.double().cpu().numpy()
+        assert np.max(np.abs(S - S0) / S0) <= 1e-5
+        Uk, Vk = orsvd.normalize_signs(U.double().cpu().numpy(), V.double().cpu().numpy())
+        U0, V0 = orsvd.normalize_signs(U0.double().cpu().numpy(), V0.double().cpu().numpy())
+        assert max(np.max(np.abs(Uk - U0)), np.max(np.abs(Vk - V0))) <= 1e-3
     for a, b in zip(g_kept, g_re):
         assert torch.equal(a, b)
