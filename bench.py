@@ -14,6 +14,10 @@ FP32 accumulation); the plain FP32 form runs on the same matrix for comparison.
 
 Prints one JSON line.  `value` is algorithmic TFLOP/s of the whole step
 (flops the method must do, not padded tiles or the three bf16 products).
+The default run also times the other workloads briefly (FP64 2000 x 1000; the
+SRFT workload, FP32 32768 x 16384; 512 uneven matrices; 32 differentiable
+4096 x 2048 matrices) and reports them compactly under "workloads"; each has
+its own --workload mode with a full line.
 """
 
 import argparse
@@ -47,15 +51,29 @@ MI355X_CUS = 256
 def algorithmic_flops(m, n, l, k, q):
     """Flops the method must do per step.
 
-    GEMM passes over A: (2q + 2) x 2 m n l.  CholeskyQR2 of an M x l matrix:
-    2 passes x (Gram M l^2 + triangular apply M l^2).  Orthonormalizations:
-    one of m rows, then n and m rows per power step.  Small SVD: Gram of Bt
-    n l^2 (+ O(l^3)).  Lifts: 2 (m + n) l k.
+    GEMM passes over A: (2q + 2) x 2 m n l.  A QR factorization of an M x l
+    matrix: 2 M l^2 (Householder's 2 M l^2 - 2 l^3 / 3, rounded up; how many
+    CholeskyQR passes the implementation takes is not counted).  QRs: one of m
+    rows, then n and m rows per power step.  Small SVD: Gram of Bt n l^2
+    (+ O(l^3)).  Lifts: 2 (m + n) l k.
     """
     gemm = (2 * q + 2) * 2.0 * m * n * l
-    cqr = 4.0 * l * l * (m + q * (m + n))
+    qr = 2.0 * l * l * (m + q * (m + n))
     small = n * l * l + 2.0 * (m + n) * l * k
-    return gemm + cqr + small
+    return gemm + qr + small
+
+
+def e2e_floor(m, n, l, k, q, prec, esize=4):
+    """The step's roofline floor: the larger of its algorithmic HBM bytes at 8 TB/s and its
+    GEMM flops at the peak of the arithmetic that streams A (bf16x3: three BF16 products)."""
+    hbm_ms = algorithmic_bytes(m, n, l, q, esize) / (PEAK_HBM_GBS * 1e9) * 1e3
+    gemm = (2 * q + 2) * 2.0 * m * n * l
+    if prec == "native":
+        mf_ms = gemm / (PEAK_TFLOPS["f64" if esize == 8 else "f32"] * 1e12) * 1e3
+    else:
+        mf_ms = (3 if prec == "bf16x3" else 1) * gemm / (PEAK_TFLOPS["bf16"] * 1e12) * 1e3
+    bound = "hbm" if hbm_ms >= mf_ms else "mfma"
+    return {"bound": bound, "floor_ms": max(hbm_ms, mf_ms), "hbm_floor_ms": hbm_ms, "mfma_floor_ms": mf_ms}
 
 
 def algorithmic_bytes(m, n, l, q, esize=4):
@@ -221,7 +239,7 @@ def srft_roofline(res, m, n, l):
             "launches": launches, "avg_us": avg_s * 1e6, "per_launch": {"bytes": bytes_launch}}
 
 
-def main_srft(args, A, sigma):
+def workload_srft(args, A, sigma):
     import numpy as np
     m, n = A.shape
     k, p = args.k, args.p
@@ -252,10 +270,10 @@ def main_srft(args, A, sigma):
         "stage_a_speedup_vs_gaussian": paths["gaussian"]["stage_a_ms"] / hp["stage_a_ms"],
         "paths": paths,
     }
-    print(json.dumps(line))
+    return line
 
 
-def main_batched(args):
+def workload_batched(args):
     """512 uneven FP32 matrices, sigma_j = exp(-j/r), p = 8, q = 1, one rsvd_batched call per step."""
     import numpy as np
     import torch
@@ -326,10 +344,10 @@ def main_batched(args):
                    "count": len(As), "p": p, "q": q, "sketch": "gaussian"},
         "hbm_gbs": hp["hbm_gbs"], "err_ratio": hp["err_ratio_median"], "paths": out,
     }
-    print(json.dumps(line))
+    return line
 
 
-def main_differentiable(args):
+def workload_differentiable(args):
     """32 FP32 4096 x 2048 matrices, sigma_j = j^-1/2, k = 64, p = 16, q = 1: forward, the loss
     ||U S V^T - T||_F^2 + w . S and its gradient in A through the hand-written adjoint."""
     import numpy as np
@@ -374,7 +392,7 @@ def main_differentiable(args):
 
     def step_batched():
         leaves = [A.detach().requires_grad_(True) for A in As]
-        outs = rs.rsvd_batched(leaves, k, p=p, q=q, seed=args.seed, prec=prec)
+        outs = rs.rsvd_batched(leaves, k, p=p, q=q, seed=args.seed, prec=prec, keep_state=args.keep_state)
         U3 = torch.stack([o[0] for o in outs])
         S3 = torch.stack([o[1] for o in outs])
         V3 = torch.stack([o[2] for o in outs])
@@ -397,7 +415,7 @@ def main_differentiable(args):
         for i in range(count):
             with torch.cuda.stream(streams[i % nstreams]):
                 A = As[i].detach().requires_grad_(True)
-                U, S, V = rs.rsvd(A, k, p, q, seed=args.seed, stream_id=i, prec=prec)
+                U, S, V = rs.rsvd(A, k, p, q, seed=args.seed, stream_id=i, prec=prec, keep_state=args.keep_state)
                 L = ((U * S[None, :]) @ V.T - Ts[i]).square().sum() + (ws_[i] * S).sum()
                 L.backward()
                 grads.append(A.grad)
@@ -418,8 +436,8 @@ def main_differentiable(args):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / args.steps
     fwd = algorithmic_flops(m, n, l, k, q)
-    # adjoint (from the state the forward kept): (2q + 1) products with A in reverse and
-    # gA = Left RightT with K = (2q + 2) l
+    # adjoint: (2q + 1) products with A in reverse and gA = Left RightT with K = (2q + 2) l (the
+    # recomputation of the forward that the default adjoint makes is not counted)
     bwd = (2 * q + 1) * 2.0 * m * n * l + 2.0 * m * n * (2 * q + 2) * l
     flops = count * (fwd + bwd)
     # loss-side products in torch (U S V^T - T and its derivatives) are not counted
@@ -433,10 +451,11 @@ def main_differentiable(args):
         "config": {"workload": f"differentiable rSVD, {count} x FP32 {m}x{n}, sigma_j=j^-1/2, k={k}, p={p}, q={q}, "
                                "forward + loss + hand-written adjoint per matrix",
                    "count": count, "m": m, "n": n, "k": k, "p": p, "q": q, "mode": args.diff_mode,
+                   "adjoint": "kept forward state" if args.keep_state else "forward recomputed",
                    **({"streams": nstreams} if args.diff_mode == "streams" else {})},
         "hbm_gbs": hbm / (ms / 1e3) / 1e9, "ms_per_matrix": ms / count, "mean_grad_norm": gnorm,
     }
-    print(json.dumps(line))
+    return line
 
 
 def measured_traffic(family, prec, m, n, l):
@@ -475,7 +494,7 @@ def roofline_for(res, m, n, l, prec):
     return out
 
 
-def main_fp64(args):
+def workload_fp64(args):
     """FP64 2000 x 1000, sigma_j = exp(-j/20), k = 20, p = 10, q = 0: a latency-scale problem (its
     A is 16 MB).  Reports microseconds per rSVD next to the HBM and FP64-MFMA floors."""
     import torch
@@ -533,38 +552,53 @@ def main_fp64(args):
                          "us_per_rsvd": graph_ms * 1e3, "tflops": flops / (graph_ms / 1e3) / 1e12,
                          "err_ratio": graph_err},
     }
-    print(json.dumps(line))
+    return line
 
 
 def measured_ceilings(A, reps=10):
-    """Achievable HBM bandwidth on this GPU, measured with torch's own kernels on A (not part of the
-    method): a full reduction (A read once) and a device copy (A read and written)."""
+    """Achievable peaks on this GPU from the library's probe kernels (measurement aids, not part of
+    the method): a streaming read of A with 16-byte loads, and MFMA loops in BF16, FP32 and FP64."""
     import torch
-    nbytes = A.numel() * A.element_size()
-    B = torch.empty_like(A)
-    out = {}
-    for name, fn, moved in (("hbm_read_gbs", lambda: A.sum(), nbytes), ("hbm_copy_gbs", lambda: B.copy_(A), 2 * nbytes)):
+    import paper_0909_4061_amd as rs
+    dev = A.device
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        e0.record(stream)
         for _ in range(reps):
             fn()
-        e1.record()
+        e1.record(stream)
         torch.cuda.synchronize()
-        out[name] = moved * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
-    del B
-    out["how"] = f"torch sum and copy of the {nbytes}-byte input, {reps} repetitions each"
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    out = {}
+    nbytes = rs.probe_hbm_read(A)[1]
+    out["hbm_read_gbs"] = nbytes / timed(lambda: rs.probe_hbm_read(A)) / 1e9
+    blocks = 4 * MI355X_CUS
+    for kind, iters in (("bf16", 4096), ("fp32", 4096), ("fp64", 2048)):
+        flops = rs.probe_mfma(kind, iters, blocks, dev)[1]
+        out[f"mfma_{kind}_tflops"] = flops / timed(lambda: rs.probe_mfma(kind, iters, blocks, dev)) / 1e12
+    out["how"] = (f"library probe kernels: one streaming read of the {nbytes}-byte input (16-byte loads, "
+                  f"2048 workgroups); MFMA loops of four independent accumulations per wave, {blocks} "
+                  f"workgroups of four waves; {reps} repetitions each")
     return out
 
 
-def cpu_baseline(A, k, p, q, seed, flops, budget_s=30.0):
+def cpu_baseline(A, k, p, q, seed, flops, budget_s=30.0, paths_out=None, sigma=None):
     """The FP64 oracle on the host cores, on a bounded sample of the workload.
 
     The sample is the first m' rows of A with m' chosen so that one run takes
     about budget_s (at most all m rows); the rate is scaled to the same
-    algorithmic-flop unit as the GPU line."""
+    algorithmic-flop unit as the GPU line.  When the sample is the whole matrix
+    (or after one more oracle run on it), the GPU paths' results are compared
+    with the oracle's: the largest relative singular-value difference over the
+    k retained values, and the ratio of residual norms ||A - U S V*||_2 (the
+    benchmark's evaluator applied to both factorizations)."""
     import numpy as np
+    import torch
     from oracle import rsvd as orsvd
     try:
         from threadpoolctl import threadpool_info
@@ -582,13 +616,89 @@ def cpu_baseline(A, k, p, q, seed, flops, budget_s=30.0):
     mm = max(mm, k + p)
     A_s = A[:mm].double().cpu().numpy()
     t = time.perf_counter()
-    orsvd.rsvd(A_s, k, p, q, seed=seed, dtype=np.float32)
+    ref = orsvd.rsvd(A_s, k, p, q, seed=seed, dtype=np.float32)
     dt = time.perf_counter() - t
     f_s = algorithmic_flops(mm, n, k + p, k, q)
-    return {"value": f_s / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"FP64 numpy oracle, full rSVD (k={k}, p={p}, q={q}) on the first {mm} of {m} rows "
-                      f"of the same matrix, {dt:.1f} s",
-            "seconds": dt, "rows": mm}
+    out = {"value": f_s / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"FP64 numpy oracle, full rSVD (k={k}, p={p}, q={q}) on the first {mm} of {m} rows "
+                     f"of the same matrix, {dt:.1f} s",
+           "seconds": dt, "rows": mm}
+    if paths_out:
+        if mm < m:
+            ref = orsvd.rsvd(A.double().cpu().numpy(), k, p, q, seed=seed, dtype=np.float32)
+        Uo, So, Vo = (torch.from_numpy(ref[x]).to(A.device) for x in ("Uk", "Sk", "Vk"))
+        res_o = spectral_norm_residual(A, Uo, So, Vo)
+        parity = {"oracle_err_ratio": res_o / sigma[k] if sigma is not None else None}
+        for name, (U, S, V) in paths_out.items():
+            Sg = S.double().cpu().numpy()
+            parity[name] = {"sigma_rel_err_max": float(np.max(np.abs(Sg - ref["Sk"]) / ref["Sk"])),
+                            "res_ratio": spectral_norm_residual(A, U, S, V) / res_o}
+        out["parity_vs_oracle"] = parity
+    return out
+
+
+def compact_sub_workloads(args):
+    """The other workloads, timed briefly (args.sub_steps steps each) so that the default run covers
+    them; each full line is available with --workload."""
+    import copy
+    import numpy as np
+    import torch
+    from workloads import build_matrix_torch, spectrum
+    out = {}
+    sub = copy.copy(args)
+    sub.steps, sub.warmup, sub.only = args.sub_steps, 2, None
+
+    def guarded(name, fn):
+        t = time.perf_counter()
+        try:
+            out[name] = fn()
+        except Exception as e:  # a failing sub-workload is reported, not fatal to the headline line
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+        out[name]["wall_s"] = time.perf_counter() - t
+        torch.cuda.empty_cache()
+        print(f"# {name}: {json.dumps(out[name])[:300]}", file=sys.stderr, flush=True)
+
+    def fp64():
+        f = copy.copy(sub)
+        f.steps = 200
+        d = workload_fp64(f)
+        return {"us_per_rsvd": d["us_per_rsvd"], "graph_us_per_rsvd": d["graph_replay"]["us_per_rsvd"],
+                "err_ratio": d["err_ratio"], "floor_us": d["roofline"]["floor_us"], "steps": f.steps}
+
+    def srft():
+        m, n, k, p = 32768, 16384, 50, 78
+        sigma = spectrum("gap", n)
+        A = build_matrix_torch(m, n, sigma, seed=args.seed, dtype=torch.float32, device=torch.device("cuda", 0))
+        s2 = copy.copy(sub)
+        s2.k, s2.p = k, p
+        d = workload_srft(s2, A, sigma)
+        del A
+        return {"srft": {x: d["paths"]["srft"][x] for x in ("ms_per_step", "stage_a_ms", "err_ratio", "tflops")},
+                "gaussian": {x: d["paths"]["gaussian"][x] for x in ("ms_per_step", "stage_a_ms", "err_ratio",
+                                                                    "tflops")},
+                "stage_a_speedup_vs_gaussian": d["stage_a_speedup_vs_gaussian"],
+                "roofline_srft_kernel": {x: d["roofline"][x] for x in ("achieved", "frac", "avg_us")},
+                "steps": s2.steps}
+
+    def batched():
+        s2 = copy.copy(sub)
+        s2.only = "bf16x3"
+        d = workload_batched(s2)
+        pth = d["paths"]["bf16x3"]
+        return {x: pth[x] for x in ("ms_per_step", "tflops", "err_ratio_median", "err_ratio_max",
+                                    "sigma_rel_err_max")} | {"count": d["config"]["count"], "steps": s2.steps}
+
+    def differentiable():
+        d = workload_differentiable(sub)
+        return {x: d[x] for x in ("ms_per_step", "value", "ms_per_matrix")} | {
+            "unit": d["unit"], "adjoint": d["config"]["adjoint"], "count": d["config"]["count"],
+            "steps": sub.steps}
+
+    guarded("fp64_2000x1000", fp64)
+    guarded("srft_32768x16384", srft)
+    guarded("batched_512", batched)
+    guarded("differentiable_32x4096x2048", differentiable)
+    return out
 
 
 def main():
@@ -603,6 +713,8 @@ def main():
     ap.add_argument("--q", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0x09094061)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sub", action="store_true", help="skip the brief runs of the other workloads")
+    ap.add_argument("--sub-steps", type=int, default=5, help="timed steps of each other workload in the default run")
     ap.add_argument("--only", choices=["bf16x3", "native"], default=None)
     ap.add_argument("--input", choices=["construct", "randn"], default="construct",
                     help="construct: A = U diag(1/j) V^T (the workload); randn: i.i.d. Gaussian A of the "
@@ -614,6 +726,9 @@ def main():
     ap.add_argument("--diff-streams", type=int, default=8,
                     help="streams the differentiable workload's independent matrices are spread over")
     ap.add_argument("--batch-diff", type=int, default=32, help="matrices in the differentiable workload")
+    ap.add_argument("--keep-state", action="store_true",
+                    help="differentiable workload: the forward keeps its bases for the adjoint instead of the "
+                         "adjoint recomputing them")
     ap.add_argument("--workload", choices=["power", "srft", "batched", "differentiable", "fp64"], default="power",
                     help="power: the power-iteration rSVD (default); srft: SRFT vs Gaussian sketch, "
                          "FP32 32768 x 16384 with a spectral gap, k = 50, p = 78, q = 0; batched: 512 "
@@ -637,15 +752,15 @@ def main():
     from workloads import build_matrix_torch, spectrum
 
     if args.workload == "fp64":
-        main_fp64(args)
+        print(json.dumps(workload_fp64(args)))
         return
     if args.steps is None:
         args.steps = 10
     if args.workload == "batched":
-        main_batched(args)
+        print(json.dumps(workload_batched(args)))
         return
     if args.workload == "differentiable":
-        main_differentiable(args)
+        print(json.dumps(workload_differentiable(args)))
         return
     if args.workload == "srft":
         args.m, args.n, args.k, args.p, args.q = 32768, 16384, 50, 78, 0
@@ -672,25 +787,29 @@ def main():
         del Ac
 
     if args.workload == "srft":
-        main_srft(args, A, sigma)
+        print(json.dumps(workload_srft(args, A, sigma)))
         return
 
     flops = algorithmic_flops(m, n, l, k, q)
     hbm = algorithmic_bytes(m, n, l, q)
-    paths = {}
+    paths, factors = {}, {}
     for prec in (["bf16x3", "native"] if args.only is None else [args.only]):
         res = run_path(A, k, p, q, prec, args.steps, args.warmup, args.seed)
         err = spectral_norm_residual(A, res["U"], res["S"], res["V"]) / sigma[k]
         sig_err = float(np.max(np.abs(res["S"].double().cpu().numpy() - sigma[:k]) / sigma[:k]))
         s = res["ms_per_step"] / 1e3
+        fl = e2e_floor(m, n, l, k, q, prec)
         paths[prec] = {
             "ms_per_step": res["ms_per_step"], "tflops": flops / s / 1e12, "hbm_gbs": hbm / s / 1e9,
             "err_ratio": err, "sigma_rel_err_vs_construction": sig_err, "flags": res["flags"],
+            "e2e_roofline": fl | {"frac": fl["floor_ms"] / res["ms_per_step"]},
             "roofline": roofline_for(res, m, n, l, prec),
             "kernel_ms_per_step": res["breakdown"],
         }
+        factors[prec] = (res["U"].clone(), res["S"].clone(), res["V"].clone())
         print(f"# {prec}: {res['ms_per_step']:.3f} ms/step, {paths[prec]['tflops']:.2f} TFLOP/s, "
-              f"err ratio {err:.4f}", file=sys.stderr, flush=True)
+              f"err ratio {err:.4f}, {paths[prec]['e2e_roofline']['frac']:.3f} of the step's floor",
+              file=sys.stderr, flush=True)
 
     head = "bf16x3" if "bf16x3" in paths else "native"
     hp = paths[head]
@@ -703,18 +822,24 @@ def main():
                                + ("" if args.input == "construct" else " (Gaussian input: counter run)"),
                    "m": m, "n": n, "k": k, "p": p, "q": q, "sketch": "gaussian"},
         "hbm_gbs": hp["hbm_gbs"], "err_ratio": hp["err_ratio"], "roofline": hp["roofline"],
-        "paths": {pth: {kk: vv for kk, vv in d.items() if kk != "roofline"} | {"roofline": d["roofline"]}
-                  for pth, d in paths.items()},
+        "e2e_roofline": hp["e2e_roofline"],
+        "paths": paths,
     }
     if "native" in paths and head != "native":
         line["speedup_vs_fp32"] = paths["native"]["ms_per_step"] / hp["ms_per_step"]
     ceil = measured_ceilings(A)
     line["measured_ceilings"] = ceil
     for d in [line["roofline"]] + [pd["roofline"] for pd in line["paths"].values()]:
-        if d["bound"] == "hbm":  # against the best HBM rate torch's own kernels reach here (the copy)
-            d["frac_of_measured"] = d["achieved"] / max(ceil["hbm_read_gbs"], ceil["hbm_copy_gbs"])
+        d["frac_of_measured"] = d["achieved"] / (ceil["hbm_read_gbs"] if d["bound"] == "hbm"
+                                                 else ceil["mfma_fp32_tflops"])
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(A, k, p, q, args.seed, flops)
+        line["cpu_baseline"] = cpu_baseline(A, k, p, q, args.seed, flops, paths_out=factors, sigma=sigma)
+        print(f"# parity vs oracle: {json.dumps(line['cpu_baseline'].get('parity_vs_oracle'))}", file=sys.stderr,
+              flush=True)
+    del A, factors
+    torch.cuda.empty_cache()
+    if not args.no_sub:
+        line["workloads"] = compact_sub_workloads(args)
     print(json.dumps(line))
 
 

@@ -196,6 +196,39 @@ size_t rsvd_full_workspace_bytes(const rsvd_problem* problem);
 rsvd_status rsvd_full(rsvd_handle handle, const rsvd_problem* problem, const void* A,
                       void* U, void* S, void* V, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* --- Fixed-precision range finder ---------------------------------------- */
+
+/* Workspace bytes of rsvd_range_finder_tol (0 if the problem or r is not
+ * accepted, see below). */
+size_t rsvd_range_finder_tol_workspace_bytes(const rsvd_problem* problem, int32_t r);
+
+/* The fixed-precision problem of Section 1.3: an orthonormal Q (m x l) with
+ * ||(I - Q Q*) A|| <= eps, l found by the method.  Algorithm 4.2 (Adaptive
+ * Randomized Range Finder) with its samples taken in blocks (the remark after
+ * Algorithm 4.2) whose sizes double the guess for the rank (Section 4.3):
+ * b0, b0, 2 b0, 4 b0, ... with b0 = problem->k, up to the capacity
+ * lmax = problem->k + problem->p, which must be b0 times a power of two
+ * (l is then one of 0, b0, 2 b0, 4 b0, ..., lmax).  Each block first tests the
+ * current basis by the a posteriori estimate of eq. (4.3):
+ *   est = 10 sqrt(2/pi) max_i ||(I - Q Q*) A w_i||
+ * over its b >= r fresh Gaussian vectors w_i (the bound ||(I - Q Q*) A|| <= est
+ * holds with probability at least 1 - 10^-b); if est <= eps the call returns Q,
+ * otherwise the block's samples, projected twice onto range(Q)-perp and
+ * orthonormalized (CholeskyQR2; projected and refactored once more), are
+ * appended.  When Q holds lmax columns a last block of r vectors gives the
+ * final estimate.  The vectors w come from one n x (lmax + r) Gaussian test
+ * matrix drawn from (seed, stream_id) by the generator contract of
+ * rsvd_draw_omega, columns used in order.  problem->prec sets the arithmetic
+ * of the products with A; q must be 0 and the sketch Gaussian
+ * (RSVD_E_UNSUPPORTED otherwise); 1 <= r <= k (RSVD_E_INVAL otherwise).
+ * Q: m x lmax DEVICE buffer (row-major, leading dimension lmax), of which the
+ * first *l_out columns are written.  *l_out and *est_out are HOST outputs; the
+ * call synchronizes `stream` after every block (the host takes the decision).
+ * est > eps on return means the capacity was reached first. */
+rsvd_status rsvd_range_finder_tol(rsvd_handle handle, const rsvd_problem* problem, double eps, int32_t r,
+                                  const void* A, void* Q, int32_t* l_out, double* est_out, void* ws,
+                                  size_t ws_bytes, hipStream_t stream);
+
 /* Size of the device array that rsvd_full_static uses as its workspace. */
 #define RSVD_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
 

@@ -254,6 +254,27 @@ def rsvd_full_static(A, k, p=10, q=0, *, sketch="gaussian", prec="native", seed=
     return U, S, V
 
 
+def rsvd_range_finder_tol(A, eps, b0=16, lmax=128, r=10, *, prec="native", seed=0, stream_id=0, Q=None):
+    """Fixed-precision range finder (Algorithm 4.2 in blocks b0, b0, 2 b0, ... up to lmax): returns
+    (Q[:, :l], l, est) with est the a posteriori estimate of ||(I - Q Q*) A|| of eq. (4.3); est <= eps
+    unless the capacity lmax was reached first.  Synchronizes the current stream."""
+    pr = _prob_for(A, b0, lmax - b0, 0, "gaussian", prec, seed, stream_id)
+    lib = _lib.load()
+    nbytes = int(lib.rsvd_range_finder_tol_workspace_bytes(ctypes.byref(pr), int(r)))
+    if nbytes == 0:
+        raise RsvdError(validate(pr) or _lib.RSVD_E_INVAL, "rsvd_range_finder_tol_workspace_bytes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    if Q is None:
+        Q = torch.zeros(A.shape[0], lmax, dtype=_elem_dtype(pr), device=A.device)
+    l_out = ctypes.c_int32(0)
+    est = ctypes.c_double(0.0)
+    h = handle(A.device)
+    _lib.check(h.lib.rsvd_range_finder_tol(h.ptr, ctypes.byref(pr), float(eps), int(r), _ptr(A), _ptr(Q),
+                                           ctypes.byref(l_out), ctypes.byref(est), ctypes.c_void_p(ws.data_ptr()),
+                                           nbytes, _stream(A.device)), "rsvd_range_finder_tol")
+    return Q[:, :l_out.value], int(l_out.value), float(est.value)
+
+
 def rsvd_sketch(A, k, p, *, sketch="gaussian", prec="native", seed=0, stream_id=0, Y=None, ws=None):
     """Y = A Omega (m x (k+p)) with the test matrix the range finder draws, not orthonormalized."""
     pr = _prob_for(A, k, p, 0, sketch, prec, seed, stream_id)

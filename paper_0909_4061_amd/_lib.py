@@ -33,7 +33,7 @@ EXPORTS = [
     "rsvd_batched_workspace_bytes", "rsvd_batched", "rsvd_backward_workspace_bytes", "rsvd_backward",
     "rsvd_backward_batched_workspace_bytes", "rsvd_backward_batched", "rsvd_forward_kept", "rsvd_backward_kept",
     "rsvd_batched_kept", "rsvd_backward_batched_kept", "rsvd_full_workspace_bytes", "rsvd_full",
-    "rsvd_full_static",
+    "rsvd_full_static", "rsvd_range_finder_tol_workspace_bytes", "rsvd_range_finder_tol",
     "rsvd_sketch", "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
     "rsvd_profile_enable", "rsvd_profile_select", "rsvd_profile_read", "rsvd_probe_hbm_read", "rsvd_probe_mfma",
 ]
@@ -95,6 +95,9 @@ def load():
         "rsvd_full_workspace_bytes": ([prob], sz),
         "rsvd_full": ([vp, prob, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_full_static": ([vp, prob, vp, vp, vp, vp, vp], i32),
+        "rsvd_range_finder_tol_workspace_bytes": ([prob, i32], sz),
+        "rsvd_range_finder_tol": ([vp, prob, ctypes.c_double, i32, vp, vp, ctypes.POINTER(i32),
+                                   ctypes.POINTER(ctypes.c_double), vp, sz, vp], i32),
         "rsvd_backward_kept": ([vp, prob, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_draw_omega": ([vp, prob, vp, vp], i32),
         "rsvd_draw_srft": ([vp, prob, vp, vp, vp], i32),

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <cmath>
 #include <vector>
 
 #include "common.hpp"
@@ -598,13 +599,12 @@ rsvd_status project_steps(const Ctx& c, const rsvd_problem* pr, const void* A, c
   return reduce_parts(c, sp, P.n, Bt);
 }
 
-// Algorithm 5.1 steps 2-3 and truncation.  The SVD of the small matrix B is
-// taken through a triangular factor R with R^T R = B B*: one-sided Jacobi on
-// C = R^T gives U~ and Sigma, and V = B* U~ Sigma^-1.  For FP64 data R comes
-// from CholeskyQR2 of B* (a shifted third pass when needed), which is
-// backward stable: singular values carry absolute errors of order u sigma_1,
-// as with a Householder QR.  For FP32 data R is the Cholesky factor of the
-// FP64 Gram B B* itself, whose error (u_64 sigma_1^2 / sigma_j relative to
+// Algorithm 5.1 steps 2-3 and truncation: the SVD of the small matrix B gives
+// U~ and Sigma, and V = B* U~ Sigma^-1.  For FP64 data through a triangular
+// factor R of B* from CholeskyQR2 (a shifted third pass when needed) and
+// one-sided Jacobi on C = R^T (C C^T = B B*), which is backward stable:
+// singular values carry absolute errors of order u sigma_1.  For FP32 data
+// from the FP64 Gram B B*, whose error (u_64 sigma_1^2 / sigma_j relative to
 // sigma_j) stays below what FP32 arithmetic resolves.
 rsvd_status small_svd(const Ctx& c, const void* Bt, void* S, JacobiParams& j) {
   const Plan& P = c.P;
@@ -630,9 +630,19 @@ rsvd_status small_svd(const Ctx& c, const void* Bt, void* S, JacobiParams& j) {
     RSVD_TRY(c.run->jacobi(j));
     return RSVD_OK;
   }
-  // FP32 data: the eigendecomposition of the FP64 Gram B B* = U~ S^2 U~*
+  // FP32 data: from the FP64 Gram B B*.  A single problem takes its
+  // eigendecomposition B B* = U~ S^2 U~* (tridiagonalization, then one wave per
+  // eigenpair over many CUs); a batch, whose problems already fill the chip one
+  // workgroup each, takes one-sided Jacobi on C = R^T with R^T R = B B*
+  // (Cholesky), the same Gram accuracy in fewer workgroups.
   s = gram(c, false, no_split(1), const_cast<void*>(Bt), P.n, nullptr);
   if (s != RSVD_OK) return s;
+  if (c.run->records()) {
+    s = chol(c, P.n, R, false, nullptr, nullptr);
+    if (s != RSVD_OK) return s;
+    RSVD_TRY(c.run->jacobi(j));
+    return RSVD_OK;
+  }
   EigParams e{};
   e.G = c.at<double>(P.G);
   e.Lg = P.Lg;
@@ -742,8 +752,8 @@ BwdLayout bwd_layout(const rsvd_problem* pr, bool batched = false, bool stream =
 }
 
 rsvd_status copy2d(const Ctx& c, const void* src, int sdt, int64_t lds, void* dst, int ddt, int64_t ldd, int64_t rows,
-                   int64_t cols, bool trans) {
-  const Copy2dParams p{src, sdt, lds, dst, ddt, ldd, rows, cols, trans ? 1 : 0};
+                   int64_t cols, bool trans, bool negate = false) {
+  const Copy2dParams p{src, sdt, lds, dst, ddt, ldd, rows, cols, trans ? 1 : 0, negate ? 1 : 0};
   RSVD_TRY(c.run->copy2d(p));
   return RSVD_OK;
 }
@@ -751,12 +761,12 @@ rsvd_status copy2d(const Ctx& c, const void* src, int sdt, int64_t lds, void* ds
 // out (rows x ncols, ldo) = A^T X for the adjoint's products with few output rows
 // (rows <= l) and a long contraction K: the K range is split over up to
 // kBwdMaxSplit workgroups and the partial products summed in a fixed order.
-rsvd_status gemm_tn_splitk(const Ctx& c, const BwdLayout& L, const void* A, int64_t lda, int64_t rows, int64_t K,
-                           const void* X, int64_t ldx, int32_t ncols, void* out, int64_t ldo) {
+rsvd_status gemm_tn_splitk_into(const Ctx& c, void* part_buf, const void* A, int64_t lda, int64_t rows, int64_t K,
+                                const void* X, int64_t ldx, int32_t ncols, void* out, int64_t ldo) {
   const GemmTile t = gemm_tile(c.P.dtype, RSVD_NATIVE);
   Split sp = choose_split(rows, K, t);
   if (sp.S > kBwdMaxSplit) sp = Split{(int32_t)kBwdMaxSplit, round_up(ceil_div(K, kBwdMaxSplit), t.bk)};
-  void* part = sp.S > 1 ? c.at<void>(L.part) : nullptr;
+  void* part = sp.S > 1 ? part_buf : nullptr;
   rsvd_status s = gemm(c, RSVD_NATIVE, true, A, lda, rows, K, X, ldx, ncols, out, ldo, sp, part, nullptr);
   if (s != RSVD_OK) return s;
   GramParams g{};
@@ -769,6 +779,11 @@ rsvd_status gemm_tn_splitk(const Ctx& c, const BwdLayout& L, const void* A, int6
   g.l = ncols;
   if (sp.S > 1 || c.run->records()) RSVD_TRY(c.run->sum_parts(c.P.dtype, g));
   return RSVD_OK;
+}
+
+rsvd_status gemm_tn_splitk(const Ctx& c, const BwdLayout& L, const void* A, int64_t lda, int64_t rows, int64_t K,
+                           const void* X, int64_t ldx, int32_t ncols, void* out, int64_t ldo) {
+  return gemm_tn_splitk_into(c, c.at<void>(L.part), A, lda, rows, K, X, ldx, ncols, out, ldo);
 }
 
 // out (rows x l, ldo) = gY for Y = Qj R (rows x l): gY = (gQ + Q sym(-gQ^T Q)) R^-T.
@@ -1579,6 +1594,121 @@ rsvd_status adjoint_prologue(rsvd_handle h, const rsvd_problem* pr, void* ws, si
   return RSVD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Fixed-precision range finder: Algorithm 4.2 with the samples taken in blocks
+// (the remark after Algorithm 4.2) of doubling size (Section 4.3: double the
+// guess for the rank at each step).  Block t is first the test of the current
+// basis Q by eq. (4.3) -- its projected columns (I - Q Q*) A w are the
+// vectors the estimate takes its maximum over -- and is appended if the test
+// fails.  The host reads the test statistic after each block.
+
+struct TolLayout {
+  int64_t b0 = 0, lmax = 0, L = 0, bmax = 0;  // first block, capacity, test-matrix columns, largest block
+  size_t omega = 0, Y = 0, Qb = 0, C = 0, part = 0, base = 0, total = 0;
+};
+
+rsvd_problem block_problem(const rsvd_problem* pr, int64_t b) {
+  rsvd_problem s = *pr;
+  s.k = (int32_t)b;
+  s.p = 0;
+  s.q = 0;
+  return s;
+}
+
+rsvd_status tol_layout(const rsvd_problem* pr, int32_t r, TolLayout& T) {
+  const rsvd_status v = validate(pr);
+  if (v != RSVD_OK) return v;
+  if (pr->q != 0 || pr->sketch != RSVD_GAUSSIAN) return RSVD_E_UNSUPPORTED;
+  T.b0 = pr->k;
+  T.lmax = (int64_t)pr->k + pr->p;
+  const int64_t ratio = T.lmax / T.b0;
+  if (r < 1 || r > T.b0 || T.lmax % T.b0 != 0 || (ratio & (ratio - 1)) != 0) return RSVD_E_INVAL;
+  T.L = T.lmax + r;
+  T.bmax = std::max(T.b0, T.lmax / 2);
+  const size_t es = pr->dtype == RSVD_F64 ? 8 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align_up(std::max<size_t>(bytes, 1));
+    return at;
+  };
+  T.omega = take((size_t)pr->n * (size_t)T.L * es);
+  T.Y = take((size_t)pr->m * (size_t)T.bmax * es);
+  T.Qb = take((size_t)pr->m * (size_t)T.bmax * es);
+  T.C = take((size_t)T.lmax * (size_t)T.bmax * es);
+  T.part = take((size_t)kBwdMaxSplit * (size_t)T.lmax * 128 * es);
+  T.base = off;
+  const rsvd_problem bp = block_problem(pr, T.bmax);
+  T.total = T.base + make_plan(&bp).total;
+  return RSVD_OK;
+}
+
+// Y (m x b) <- (I - Q Q*) Y, twice (the reprojection of Algorithm 4.2, for a block):
+// C = Q* Y by the split-K transposed product, then Y += Q (-C).
+rsvd_status tol_project(const Ctx& cb, const TolLayout& T, char* ws, const void* Q, int64_t j, void* Y, int64_t b) {
+  if (j == 0) return RSVD_OK;
+  const int dt = cb.P.dtype;
+  void* C = ws + T.C;
+  for (int rep = 0; rep < 2; ++rep) {
+    rsvd_status s = gemm_tn_splitk_into(cb, ws + T.part, Q, T.lmax, j, cb.P.m, Y, b, (int32_t)b, C, b);
+    if (s == RSVD_OK) s = copy2d(cb, C, dt, b, C, dt, b, j, b, false, true);
+    if (s == RSVD_OK)
+      s = gemm(cb, RSVD_NATIVE, false, Q, T.lmax, cb.P.m, j, C, b, (int32_t)b, Y, b, no_split(j), nullptr, nullptr,
+               false, true);
+    if (s != RSVD_OK) return s;
+  }
+  return RSVD_OK;
+}
+
+rsvd_status range_finder_tol(rsvd_handle h, const rsvd_problem* pr, const TolLayout& T, double eps, int32_t r,
+                             const void* A, void* Q, int32_t* l_out, double* est_out, char* ws, hipStream_t st) {
+  const int dt = pr->dtype;
+  const size_t es = dt == RSVD_F64 ? 8 : 4;
+  DirectRunner dr(h, st);
+  char* omega = ws + T.omega;
+  void* Y = ws + T.Y;
+  void* Qb = ws + T.Qb;
+  const double factor = 10.0 * std::sqrt(2.0 / 3.14159265358979323846);
+  // every block draws from one n x (lmax + r) Gaussian test matrix, columns in order
+  RSVD_TRY(dr.omega(dt, OmegaParams{omega, pr->n, (int32_t)T.L, pr->seed, pr->stream_id}));
+  int64_t j = 0, col = 0;
+  std::vector<double> diag;
+  for (;;) {
+    const int64_t b = j == T.lmax ? r : (j == 0 ? T.b0 : j);
+    const rsvd_problem bp = block_problem(pr, b);
+    const Plan Pb = make_plan(&bp);
+    const Ctx cb{Pb, ws + T.base, st, h->status, h, &dr};
+    // the block's samples Y = A w for its b fresh test vectors, projected
+    rsvd_status s = gemm(cb, pr->prec, false, A, pr->lda, Pb.m, Pb.n, omega + (size_t)col * es, T.L, (int32_t)b, Y, b,
+                         Pb.nn, Pb.nn.S > 1 ? cb.at<void>(Pb.part) : nullptr, nullptr, true);
+    if (s == RSVD_OK) s = reduce_parts(cb, Pb.nn, Pb.m, Y);
+    if (s == RSVD_OK) s = tol_project(cb, T, ws, Q, j, Y, b);
+    if (s == RSVD_OK) s = gram(cb, false, no_split(1), Y, Pb.m, nullptr);
+    if (s != RSVD_OK) return s;
+    col += b;
+    // the test statistic: 10 sqrt(2/pi) max_i ||(I - Q Q*) A w_i|| (eq. 4.3)
+    diag.assign((size_t)b, 0.0);
+    RSVD_TRY(hipMemcpy2DAsync(diag.data(), sizeof(double), cb.at<double>(Pb.G), (size_t)(Pb.Lg + 1) * sizeof(double),
+                              sizeof(double), (size_t)b, hipMemcpyDeviceToHost, st));
+    RSVD_TRY(hipStreamSynchronize(st));
+    double mx = 0.0;
+    for (double d : diag) mx = std::max(mx, d);
+    const double est = factor * std::sqrt(std::max(mx, 0.0));
+    if (!(est > eps) || j == T.lmax) {
+      *l_out = (int32_t)j;
+      *est_out = est;
+      return RSVD_OK;
+    }
+    // append the block: its orthonormal factor, projected once more and refactored
+    s = orth(cb, false, no_split(1), Y, Pb.m, Qb, nullptr);
+    if (s == RSVD_OK) s = tol_project(cb, T, ws, Q, j, Qb, b);
+    if (s == RSVD_OK && j > 0) s = orth(cb, false, no_split(1), Qb, Pb.m, Qb, nullptr);
+    if (s == RSVD_OK) s = copy2d(cb, Qb, dt, b, static_cast<char*>(Q) + (size_t)j * es, dt, T.lmax, Pb.m, b, false);
+    if (s != RSVD_OK) return s;
+    j += b;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1793,6 +1923,23 @@ rsvd_status rsvd_full_static(rsvd_handle h, const rsvd_problem* pr, const void* 
   if (s == RSVD_OK) s = project_steps(c, pr, A, Q, Bt);
   if (s == RSVD_OK) s = svd_steps(c, Bt, Q, U, S, V);
   return s;
+}
+
+size_t rsvd_range_finder_tol_workspace_bytes(const rsvd_problem* problem, int32_t r) {
+  TolLayout T;
+  return tol_layout(problem, r, T) == RSVD_OK ? T.total : 0;
+}
+
+rsvd_status rsvd_range_finder_tol(rsvd_handle h, const rsvd_problem* pr, double eps, int32_t r, const void* A,
+                                  void* Q, int32_t* l_out, double* est_out, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+  TolLayout T;
+  const rsvd_status v = tol_layout(pr, r, T);
+  if (v != RSVD_OK) return v;
+  if (!h || !A || !Q || !l_out || !est_out || !(eps > 0.0) || !std::isfinite(eps)) return RSVD_E_INVAL;
+  if (!ws || ws_bytes < T.total || !aligned16(ws)) return RSVD_E_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return RSVD_E_DEVICE;
+  return range_finder_tol(h, pr, T, eps, r, A, Q, l_out, est_out, static_cast<char*>(ws), stream);
 }
 
 size_t rsvd_backward_workspace_bytes(const rsvd_problem* problem) {

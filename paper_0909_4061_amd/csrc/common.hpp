@@ -272,6 +272,7 @@ struct Copy2dParams {
   int64_t ldd;
   int64_t rows, cols;  // of the source block
   int32_t trans;       // 1: dst = src^T
+  int32_t negate;      // 1: dst = -src (or -src^T)
 };
 struct QrSymParams {  // S = sym(-M^T) (FP64, l x l) for M = Q^T gQ (element type)
   const void* M;

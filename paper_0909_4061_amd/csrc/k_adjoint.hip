@@ -243,6 +243,7 @@ __device__ __forceinline__ void copy2d_body(const Copy2dParams& p, const int bid
       v = tile[rr][tx];
     }
     const int64_t o = dr * p.ldd + dc;
+    if (p.negate) v = -v;
     if (p.dst_dtype == RSVD_F64)
       static_cast<double*>(p.dst)[o] = v;
     else

@@ -516,7 +516,20 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
       v1 = n1;
     }
   }
-  // 4. this column's outputs
+  // 4. the sign convention of the small SVD (also the Jacobi kernel's): the
+  //    component of largest magnitude, the first of equals, is positive
+  {
+    const double a0 = lane < l ? fabs(z0) : -1.0, a1 = lane + 64 < l ? fabs(z1) : -1.0;
+    const double mx = wave_max(fmax(a0, a1));
+    const uint64_t b0 = __ballot(a0 == mx), b1 = __ballot(a1 == mx);
+    const int at = b0 ? __ffsll((long long)b0) - 1 : 64 + __ffsll((long long)b1) - 1;
+    const double piv = at < 64 ? lane_value(z0, at) : lane_value(z1, at - 64);
+    if (piv < 0.0) {
+      z0 = -z0;
+      z1 = -z1;
+    }
+  }
+  // 5. this column's outputs
   const double sg = sqrt(fmax(lam, 0.0));
   if (lane == 0) {
     p.lam[j] = lam;
@@ -644,11 +657,24 @@ __device__ __forceinline__ void eig_fix_body(const EigParams& p) {
       }
     }
   }
-  // outputs of the columns that changed
+  // outputs of the columns that changed, with the sign convention of tri_eig
+  for (int j = tid; j < l; j += 256) {
+    if (todo[j] == 0) continue;
+    double mx = -1.0, piv = 1.0;
+    for (int i = 0; i < l; ++i) {
+      const double v = Zs[j * LDZ + i];
+      if (fabs(v) > mx) {
+        mx = fabs(v);
+        piv = v;
+      }
+    }
+    coef[j] = piv < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
   for (int idx = tid; idx < l * l; idx += 256) {
     const int j = idx / l, i = idx - j * l;
     if (todo[j] == 0) continue;
-    const double zi = Zs[j * LDZ + i];
+    const double zi = coef[j] * Zs[j * LDZ + i];
     p.Uh[(int64_t)i * l + j] = zi;
     if (j < p.k) {
       const double sg = p.sig[j];

@@ -102,6 +102,7 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
   __shared__ double sig_s[MAXL];
   __shared__ double nrm[MAXL];  // squared column norms, exact at the start of a sweep
   __shared__ int rank_s[MAXL];
+  __shared__ double sgn_s[MAXL];
   __shared__ int rotated;
   const int tid = threadIdx.x;
   const int l = p.l;
@@ -226,13 +227,23 @@ __device__ __forceinline__ void jacobi_body(const JacobiParams& p, const int bid
       rk += (o > me) || (o == me && c < tid);
     }
     rank_s[tid] = rk;
+    // sign convention: the component of largest magnitude (the first of equals) is positive
+    double mx = -1.0, piv = 1.0;
+    for (int i = 0; i < l; ++i) {
+      const double v = Cs[tid * LDC + i];
+      if (fabs(v) > mx) {
+        mx = fabs(v);
+        piv = v;
+      }
+    }
+    sgn_s[tid] = piv < 0.0 ? -1.0 : 1.0;
   }
   __syncthreads();
   for (int idx = tid; idx < l * l; idx += THREADS) {
     const int c = idx / l, i = idx - c * l;  // element i of column c
     const int rk = rank_s[c];
     const double sg = sig_s[c];
-    const double u = sg > 0.0 ? Cs[c * LDC + i] / sg : 0.0;
+    const double u = sg > 0.0 ? sgn_s[c] * Cs[c * LDC + i] / sg : 0.0;
     p.Uh[(int64_t)i * l + rk] = u;
     if (rk < p.k) {
       const double v = sg > 0.0 ? u / sg : 0.0;

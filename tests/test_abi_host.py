@@ -193,3 +193,22 @@ def test_full_static_size_limit_before_handle(lib):
     assert lib.rsvd_full_static(None, ctypes.byref(small), None, None, None, None, None) == _lib.RSVD_E_INVAL
     bad = _prob(k=0)
     assert lib.rsvd_full_static(None, ctypes.byref(bad), None, None, None, None, None) == _lib.RSVD_E_INVAL
+
+
+def test_range_finder_tol_validation(lib):
+    from paper_0909_4061_amd import _lib
+    ok = _prob(m=700, n=400, k=16, p=112)          # b0 = 16, lmax = 128 = 16 * 2^3
+    assert lib.rsvd_range_finder_tol_workspace_bytes(ctypes.byref(ok), 10) > 0
+    assert lib.rsvd_range_finder_tol_workspace_bytes(ctypes.byref(ok), 17) == 0   # r > b0
+    assert lib.rsvd_range_finder_tol_workspace_bytes(ctypes.byref(ok), 0) == 0
+    odd = _prob(m=700, n=400, k=16, p=32)          # lmax = 48 = 16 * 3: not a doubling schedule
+    assert lib.rsvd_range_finder_tol_workspace_bytes(ctypes.byref(odd), 10) == 0
+    powered = _prob(m=700, n=400, k=16, p=112, q=1)
+    assert lib.rsvd_range_finder_tol_workspace_bytes(ctypes.byref(powered), 10) == 0
+    l_out, est = ctypes.c_int32(0), ctypes.c_double(0.0)
+    assert lib.rsvd_range_finder_tol(None, ctypes.byref(ok), 1e-3, 10, None, None, ctypes.byref(l_out),
+                                     ctypes.byref(est), None, 0, None) == _lib.RSVD_E_INVAL
+    assert lib.rsvd_range_finder_tol(None, ctypes.byref(odd), 1e-3, 10, None, None, ctypes.byref(l_out),
+                                     ctypes.byref(est), None, 0, None) == _lib.RSVD_E_INVAL
+    assert lib.rsvd_range_finder_tol(None, ctypes.byref(powered), 1e-3, 10, None, None, ctypes.byref(l_out),
+                                     ctypes.byref(est), None, 0, None) == _lib.RSVD_E_UNSUPPORTED

@@ -14,7 +14,8 @@ fast-decaying spectrum below that level carry no relative accuracy.  In FP64
 the same holds with u = 2^-53: the small SVD works on a backward-stable
 triangular factor of B*, so its singular values have absolute errors of
 order l u sigma_1.  The residual ||A - U S V*|| must be within 1e-10 (FP64) /
-1% (FP32) of the oracle's, with the same floor; U is orthonormal.
+1% (FP32) of the oracle's, in both directions, with the same floor; U is
+orthonormal.
 Inputs: U diag(exp(-j/r)) V^T with the uneven shapes of the batched workload
 (workloads.batch_shapes), scaled down where noted so the oracle finishes in
 seconds.  With decay rates r of 2 to 3 the sampled matrix after a power step
@@ -74,7 +75,7 @@ def _check(As, outs, ks, p, q, seed, fp64):
             assert evaluate.orthonormality_error(Ug) <= 1e-12
         else:
             assert np.all(err <= 1e-5 * ref["Sk"] + floor), (i, np.max(err / (1e-5 * ref["Sk"] + floor)))
-            assert res <= max(1.01 * res_ref, res_ref + floor), (i, res, res_ref)
+            assert abs(res - res_ref) <= 0.01 * res_ref + floor, (i, res, res_ref)
             assert evaluate.orthonormality_error(Ug) <= 1e-5
 
 
@@ -181,15 +182,19 @@ def test_batched_bf16x3_matches_fp32_quality():
         ra = evaluate.residual_usv(A64, *[to_np(t).astype(np.float64) for t in a])
         rb = evaluate.residual_usv(A64, *[to_np(t).astype(np.float64) for t in b])
         sk = np.linalg.svd(A64, compute_uv=False)[0]
-        assert rb <= 1.01 * ra + (4.0 * np.sqrt(max(A64.shape)) + 2.0 * (k + 8)) * U32 * sk
+        assert abs(rb - ra) <= 0.01 * ra + (4.0 * np.sqrt(max(A64.shape)) + 2.0 * (k + 8)) * U32 * sk
     assert _flags_ok()
 
 
-def test_batched_full_workload_sampled():
-    # the benchmark's batch itself: 512 uneven matrices up to 2048 x 1024, FP32,
-    # bf16x3 products, p = 8, q = 1.  Every matrix: orthonormal U and singular
-    # values no larger than the construction's (interlacing, to the FP32 floor);
-    # the four largest and four random matrices: the oracle on exactly A.
+def test_batched_full_workload_all_vs_oracle():
+    # the benchmark's batch itself: 512 uneven matrices up to 2048 x 1024, FP32, bf16x3 products,
+    # p = 8, q = 1.  Every matrix against the oracle run on exactly that matrix with its own
+    # (seed, stream) draw.  bf16x3 against the FP32-arithmetic oracle: each product carries a
+    # relative error up to 2^-16 (the split of both operands), so by Weyl's inequality every
+    # singular value moves by at most about 2^-16 sigma_1 -- plus the FP32 floor of the module
+    # docstring for values far below sigma_1; residuals (the benchmark's evaluator for both
+    # factorizations) within 1% of the oracle's in both directions, to the same floor.
+    import bench
     from workloads import build_matrix_torch
     shapes = batch_shapes(512)
     p, q, seed = 8, 1, 0x09094061
@@ -202,22 +207,21 @@ def test_batched_full_workload_sampled():
     outs = rs.rsvd_batched(As, ks, p=p, q=q, prec="bf16x3", seed=seed)
     torch.cuda.synchronize()
     assert _flags_ok()
-    for i, ((U, S, V), sig) in enumerate(zip(outs, sigmas)):
-        Sg = to_np(S).astype(np.float64)
-        floor = (4.0 * np.sqrt(As[i].shape[0]) + 2.0 * (ks[i] + p)) * U32 * sig[0]
-        assert np.all(Sg <= sig[:ks[i]] * (1 + 1e-5) + floor), i
-        assert evaluate.orthonormality_error(to_np(U).astype(np.float64)) <= 1e-5, i
-    big = sorted(range(len(As)), key=lambda i: -As[i].numel())[:4]
-    rnd = list(np.random.default_rng(1).choice(len(As), 4, replace=False))
-    for i in big + [int(j) for j in rnd]:
-        A64 = to_np(As[i]).astype(np.float64)
-        k = ks[i]
+    worst_sig, worst_res = 0.0, 0.0
+    for i, (A, (U, S, V), k) in enumerate(zip(As, outs, ks)):
+        A64 = to_np(A).astype(np.float64)
         ref = orsvd.rsvd(A64, k, p, q, seed=seed, stream=i, dtype=np.float32)
-        U, S, V = (to_np(t).astype(np.float64) for t in outs[i])
-        floor = (4.0 * np.sqrt(A64.shape[0]) + 2.0 * (k + p)) * U32 * ref["Sk"][0]
-        # bf16x3 against the FP32-arithmetic oracle: singular values within 1e-3 relative
-        # (+ the floor), residual within 1%
-        assert np.all(np.abs(S - ref["Sk"]) <= 1e-3 * ref["Sk"] + floor), i
-        res = evaluate.residual_usv(A64, U, S, V)
-        res_ref = evaluate.residual_usv(A64, ref["Uk"], ref["Sk"], ref["Vk"])
-        assert res <= max(1.01 * res_ref, res_ref + floor), (i, res, res_ref)
+        Sg = to_np(S).astype(np.float64)
+        s1 = ref["Sk"][0]
+        floor = (4.0 * np.sqrt(A64.shape[0]) + 2.0 * (k + p)) * U32 * s1
+        bound = 1e-5 * ref["Sk"] + 2.0 ** -16 * s1 + floor
+        worst_sig = max(worst_sig, float(np.max(np.abs(Sg - ref["Sk"]) / bound)))
+        assert np.all(np.abs(Sg - ref["Sk"]) <= bound), (i, np.max(np.abs(Sg - ref["Sk"]) / bound))
+        assert evaluate.orthonormality_error(to_np(U).astype(np.float64)) <= 1e-5, i
+        res = bench.spectral_norm_residual(A, U, S, V)
+        Uo, So, Vo = (torch.from_numpy(ref[x]).to(DEV) for x in ("Uk", "Sk", "Vk"))
+        res_ref = bench.spectral_norm_residual(A, Uo, So, Vo)
+        worst_res = max(worst_res, abs(res - res_ref) / (0.01 * res_ref + floor))
+        assert abs(res - res_ref) <= 0.01 * res_ref + floor, (i, res, res_ref)
+    print(f"512-matrix batch vs oracle: worst sigma error / bound {worst_sig:.3f}, "
+          f"worst residual difference / bound {worst_res:.3f}")
