@@ -500,7 +500,9 @@ rsvd_status orth(const Ctx& c, bool from_part, const Split& sp, void* y, int64_t
     void* src = pass == 0 ? y : Q;
     rsvd_status s = gram(c, src_part, sp, src, rows, gate);
     if (s != RSVD_OK) return s;
-    s = chol(c, rows, Rs[pass], true, gate, pass < 2 ? flag : nullptr, pass == 0);
+    // R itself only when the combined factor is wanted: R^-1 (rounded to the
+    // element type) is all the apply step reads
+    s = chol(c, rows, R_out ? Rs[pass] : nullptr, true, gate, pass < 2 ? flag : nullptr, pass == 0);
     if (s != RSVD_OK) return s;
     s = gemm(c, RSVD_NATIVE, false, src, l, rows, l, c.at<void>(c.P.RinvT), l, (int32_t)l, Q, l, no_split(l),
              nullptr, gate);

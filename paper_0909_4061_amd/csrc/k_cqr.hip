@@ -201,33 +201,27 @@ __global__ __launch_bounds__(256) void gram_reduce_batched(const GramReduceParam
 
 // Cholesky factor R (W = R^T R, R upper triangular, positive diagonal) and its
 // inverse X = R^-1, by blocked elimination on [W | I] for one workgroup of 512
-// threads.  With L = R^T, the row operations that take W to R (block row k
-// scaled by L_kk^-1, then subtracted from the rows below it) take I to L^-1 =
-// X^T, so both come out of the same passes.  One LDS matrix holds both parts:
-// the upper triangle holds W, then R; the strict lower triangle holds the
+// threads (8 waves).  With L = R^T, the row operations that take W to R (block
+// row k scaled by L_kk^-1, then subtracted from the rows below it) take I to
+// L^-1 = X^T, so both come out of the same passes.  One LDS matrix holds both
+// parts: the upper triangle holds W, then R; the strict lower triangle holds the
 // eliminated identity, then X^T; its diagonal (1 / R_ii) is kept in a vector.
 //
-// Per block of CB rows [k0, k1):
-//   1. panel, one wave: the diagonal block is factored in registers
-//      (right-looking, pivots and rows of R_kk broadcast within each 16-lane
-//      row by DPP; every row of lanes holds a copy), and every other column of
-//      the block row -- R part right of the block, identity part left of and
-//      inside it -- is multiplied by R_kk^-T, two columns per lane.  The
-//      finished block row is also staged in a separate LDS buffer;
-//   2. trailing update of rows k1..l-1 from the staged block row, both parts at
-//      once (columns below k1: identity part; columns >= the row: R part), in
-//      4 x 4 register tiles fed by 16-byte LDS reads.
-// A pivot that is not positive (or not finite) restarts the factorization on
-// W + s I with the shifted-CholeskyQR shift; a second failure (non-finite
-// input) returns identity factors and raises RSVD_FLAG_NONFINITE.
-
-// 1/sqrt(x) from the hardware estimate and two Newton steps (x > 0, finite).
-__device__ __forceinline__ double rsq_refined(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-  return y;
-}
+// Blocks of 16 rows, with one block of look-ahead.  Iteration k:
+//   1. (k > 0) the rows of block k receive the update from block k - 1, one
+//      16 x 16 tile per wave on FP64 MFMA;
+//   2. waves 0 and 1 factor block k (the panel: its diagonal block in registers,
+//      pivots and rows of R_kk broadcast within each 16-lane row by DPP, every
+//      other column of the block row multiplied by R_kk^-T in the same steps, one
+//      column per lane) and write its rows of R and columns of R^-1 to global
+//      memory, while waves 2..7 apply the update from block k - 1 to the rows
+//      below block k, two tiles at a time.
+// So the serial chain of the factorization (the panels) overlaps the trailing
+// updates; block 0 is read from global memory by the panel waves while the
+// other waves load the rest of W.  A pivot that is not positive (or not finite)
+// restarts the factorization on W + s I with the shifted-CholeskyQR shift; a
+// second failure (non-finite input) returns identity factors and raises
+// RSVD_FLAG_NONFINITE.
 
 // Value of lane L of this lane's 16-lane row (DPP row_newbcast).
 template <int L>
@@ -260,167 +254,329 @@ __device__ __forceinline__ double row_bcast_at(double v, int L) {
 
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
-template <int CB>
-__device__ __forceinline__ void chol_body_t(const CholParams& p) {
-  static_assert(CB == 16, "the trailing update tiles are 16 x 16");
-  constexpr int NT = 512, NW = NT / 64, LDC = 130;  // even: rows start on 16-byte boundaries
-  constexpr int PLD = 144;                          // staged row: 128 columns + tile overhang
-  __shared__ __attribute__((aligned(16))) double M[128 * LDC];
-  __shared__ __attribute__((aligned(16))) double Pr[CB * PLD];
-  __shared__ double rinv_d[128];  // 1 / R_ii (0 past l)
-  __shared__ int bad_s;
-  if (p.gate && *p.gate == 0) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0 && p.shifted && p.reset_shifted) *p.shifted = 0;  // set again below by the same thread
-  const int l = p.l, Lg = p.Lg;
-  const int lp = (l + 15) & ~15;            // rows and columns past l up to lp hold zeros
-  const int tc = tid & 127, tr = tid >> 7;  // 4 x 128 thread grid for whole-matrix loops
-  const double eps = DBL_EPSILON;
+// 1/sqrt(d) from the hardware estimate y0 (relative error e ~ 2^-24) by one step of
+// the third-order series d^-1/2 = y0 (1 - e)^-1/2 = y0 (1 + e/2 + 3e^2/8 + O(e^3)),
+// e = 1 - d y0^2: error O(e^3) below the FP64 rounding, four dependent operations.
+__device__ __forceinline__ double rsq_series(double d) {
+  const double y0 = __builtin_amdgcn_rsq(d);
+  const double e = fma(-(d * y0), y0, 1.0);
+  return fma(y0 * e, fma(0.375, e, 0.5), y0);
+}
 
-  double thresh = 0.0, trace = 0.0;
-  bool ok = false;
-  for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
-    // Shifted CholeskyQR: s = 11 (rows l + l (l + 1)) u ||Y||_F^2 with u the FP64 unit roundoff.
-    const double shift =
-        attempt == 0 ? 0.0 : 11.0 * ((double)p.rows * l + (double)l * (l + 1)) * (0.5 * eps) * trace;
-    {
-      // column pair 2 (tid % 64), rows tid / 64 + 8 u: every load in flight at once
-      const int cp = 2 * (tid & 63), r0 = tid >> 6;
-      dbl2 v[16];
+constexpr int CHOL_LDC = 130;
+constexpr int CHOL_UPDATE_WAVES = 6;
+
+// Panel factorization of rows [k0, k0 + 16) for waves 0 and 1: column sc = lane + 64 wave of the
+// block row in xt[], a copy of column dq = lane % 16 of the diagonal block in x0[] (every 16-lane
+// row holds one; entries below a lane's diagonal are never read).  Straight-line code: a padded
+// pivot (row >= l) holds 1 and changes nothing.  Writes the rows to M, 1/R_jj to rinv_d, and the
+// finished rows of R and columns of R^-1 to global memory.  Returns true when a pivot failed.
+__device__ __forceinline__ bool chol_panel(const CholParams& p, double* M, double* rinv_d, const int k0, const int l,
+                                          const double thresh, double (&x0)[16], double (&xt)[16]) {
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));  // keep the lane masks below inside the panel loop
+  const int wave = threadIdx.x >> 6;
+  const int dq = lane & 15, sc = lane + 64 * wave;
+  const int bk = min(16, l - k0);
+  const bool diag = sc >= k0 && sc < k0 + 16;
+  double rv = 0.0, rd = 0.0, pmin = DBL_MAX;
+  bool nonfinite = false;
+  // Software-pipelined: the next pivot is broadcast and its reciprocal square root started as
+  // soon as it has its last update.  The asm statements pin every update of a step inside that
+  // step (no sinking into the next one, which would keep every broadcast live across steps).
+  double y = rsq_series(row_bcast_at(x0[0], 0));
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int a = r0 + 8 * u;
-        v[u] = (a < l && cp + 1 >= a && cp < l) ? *reinterpret_cast<const dbl2*>(p.G + (int64_t)a * Lg + cp)
-                                                : dbl2{0.0, 0.0};
+  for (int j = 0; j < 16; ++j) {
+    const double d = row_bcast_at(x0[j], j);
+    if (j < bk) {
+      pmin = d < pmin ? d : pmin;
+      nonfinite |= !isfinite(d);
+    }
+    x0[j] *= y;
+    xt[j] *= y;
+    double ynext = 1.0;
+    if (j + 1 < 16) {
+      const double r = row_bcast_at(x0[j], j + 1);
+      x0[j + 1] = fma(-r, x0[j], x0[j + 1]);
+      xt[j + 1] = fma(-r, xt[j], xt[j + 1]);
+      ynext = rsq_series(row_bcast_at(x0[j + 1], j + 1));
+    }
+#pragma unroll
+    for (int i = j + 2; i < 16; ++i) {
+      const double r = row_bcast_at(x0[j], i);
+      x0[i] = fma(-r, x0[j], x0[i]);
+      xt[i] = fma(-r, xt[j], xt[i]);
+    }
+    double rjj = d * y;
+    rjj = fma(0.5 * y, fma(-rjj, rjj, d), rjj);
+    rd = dq == j ? rjj : rd;
+    rv = dq == j ? y : rv;
+    y = ynext;
+#pragma unroll
+    for (int i = j; i < 16; ++i) asm volatile("" : "+v"(x0[i]), "+v"(xt[i]));
+    asm volatile("" : "+v"(rd), "+v"(rv), "+v"(pmin));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const bool bad = !(pmin > thresh) || nonfinite;
+  if (!bad) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) M[(k0 + i) * CHOL_LDC + sc] = xt[i];
+    if (diag) {
+      // the diagonal block: R_kk on and above the diagonal, R_kk^-T below it
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i <= dq) M[(k0 + i) * CHOL_LDC + sc] = i == dq ? rd : x0[i];
+      rinv_d[sc] = rv;
+    }
+    if (sc < l) {
+      // row block of R: R[k0 + i][sc] (coalesced across lanes); zero left of the block
+      if (p.R) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (i < bk)
+            p.R[(int64_t)(k0 + i) * l + sc] =
+                sc < k0 ? 0.0 : (diag ? (i < dq ? x0[i] : (i == dq ? rd : 0.0)) : xt[i]);
       }
-      if (attempt == 0) {
-        // max diagonal (breakdown threshold) and trace (shift) of W, every wave for
-        // itself, while the loads above are in flight
-        const double d0 = lane < l ? p.G[(int64_t)lane * (Lg + 1)] : 0.0;
-        const double d1 = lane + 64 < l ? p.G[(int64_t)(lane + 64) * (Lg + 1)] : 0.0;
-        double mx = fmax(d0, d1), trs = d0 + d1;
-        for (int off = 32; off > 0; off >>= 1) {
-          mx = fmax(mx, __shfl_xor(mx, off, 64));
-          trs += __shfl_xor(trs, off, 64);
+      // column block of X = R^-1: X[sc][k0 + i], i < bk: 16 consecutive entries per lane (zero
+      // right of the block; R_kk^-T is exactly zero above its diagonal), with 16-byte stores
+      // when the row offsets allow it
+      const bool zero = sc >= k0 + 16;
+      const int64_t xo = (int64_t)sc * l + k0;
+      if (p.RinvT && p.dtype != RSVD_F64) {
+        float* dst = (float*)p.RinvT + xo;
+        if ((l & 3) == 0 && (reinterpret_cast<uintptr_t>(p.RinvT) & 15) == 0) {
+          if (zero) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (4 * q < bk) *reinterpret_cast<float4*>(dst + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (4 * q < bk)
+                *reinterpret_cast<float4*>(dst + 4 * q) =
+                    make_float4((float)xt[4 * q], (float)xt[4 * q + 1], (float)xt[4 * q + 2], (float)xt[4 * q + 3]);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (i < bk) dst[i] = zero ? 0.f : (float)xt[i];
         }
-        thresh = (double)l * 16.0 * eps * mx;
-        trace = trs;
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int a = r0 + 8 * u;
-        if (a < lp && cp < lp) {
-          dbl2 w = v[u];
-          w.x = (cp < l && cp >= a) ? w.x + (cp == a ? shift : 0.0) : 0.0;
-          w.y = (cp + 1 < l && cp + 1 >= a) ? w.y + (cp + 1 == a ? shift : 0.0) : 0.0;
-          *reinterpret_cast<dbl2*>(M + a * LDC + cp) = w;
+      for (int w = 0; w < 2; ++w) {
+        double* base = w == 0 ? p.Rinv : (p.dtype == RSVD_F64 ? (double*)p.RinvT : nullptr);
+        if (!base) continue;
+        double* dst = base + xo;
+        if ((l & 1) == 0 && (reinterpret_cast<uintptr_t>(base) & 15) == 0) {
+          if (zero) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              if (2 * q < bk) *reinterpret_cast<dbl2*>(dst + 2 * q) = dbl2{0.0, 0.0};
+          } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              if (2 * q < bk) *reinterpret_cast<dbl2*>(dst + 2 * q) = dbl2{xt[2 * q], xt[2 * q + 1]};
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (i < bk) dst[i] = zero ? 0.0 : xt[i];
         }
       }
     }
-    for (int i = tid; i < CB * PLD; i += NT) Pr[i] = 0.0;
-    if (tid < 128) rinv_d[tid] = 0.0;
-    __syncthreads();
+  }
+  return bad;
+}
+
+// NTL 16 x 16 output tiles (row tile t[q], column tile cj[q]; a tile with t[q] < 0 is skipped)
+// of the trailing update from panel k: M[i][c] -= sum_s X[s][i] X[s][c], X = rows [k0, k0 + 16)
+// of M (the identity columns of the panel itself read R_kk^-T: strictly lower part from M,
+// diagonal from rinv_d, zero above).  Every operand of every tile is read before the first
+// product, two accumulators per tile.
+template <int NTL>
+__device__ __forceinline__ void chol_tiles(double* M, const double* rinv_d, const int k, const int (&t)[NTL],
+                                          const int (&cj)[NTL], const int l) {
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
+  const int li = lane & 15, lk = lane >> 4;
+  const int k0 = 16 * k, k1 = k0 + 16;
+  double a[NTL][4], b[NTL][4], mo[NTL][4], rvv[4];
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) rvv[s4] = rinv_d[k0 + 4 * s4 + lk];
+#pragma unroll
+  for (int q = 0; q < NTL; ++q) {
+    const int tq = t[q] < 0 ? k + 1 : t[q];  // a skipped tile reads valid rows
+    const int ib = 16 * tq, c = 16 * cj[q] + li;
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const double* row = M + (k0 + 4 * s4 + lk) * CHOL_LDC;
+      a[q][s4] = row[ib + li];
+      b[q][s4] = row[c];
+      mo[q][s4] = M[(ib + 4 * s4 + lk) * CHOL_LDC + c];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NTL; ++q)
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) asm volatile("" : "+v"(a[q][s4]), "+v"(b[q][s4]), "+v"(mo[q][s4]));
+  f64x4 acc[NTL][2];
+#pragma unroll
+  for (int q = 0; q < NTL; ++q) acc[q][0] = acc[q][1] = f64x4{};
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+    for (int q = 0; q < NTL; ++q) {
+      const int s = 4 * s4 + lk;
+      const double bb = cj[q] == k ? (li < s ? b[q][s4] : (li == s ? rvv[s4] : 0.0)) : b[q][s4];
+      acc[q][s4 & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][s4], bb, acc[q][s4 & 1], 0, 0, 0);
+    }
+#pragma unroll
+  for (int q = 0; q < NTL; ++q) {
+    if (t[q] < 0) continue;
+    const f64x4 s = acc[q][0] + acc[q][1];
+    const int ib = 16 * t[q], c = 16 * cj[q] + li;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = ib + 4 * e + lk;
+      if (i < l && c < l && (c < k1 || c >= i)) M[i * CHOL_LDC + c] = mo[q][e] - s[e];
+    }
+  }
+}
+
+__device__ __forceinline__ void chol_body(const CholParams& p, const int bid) {
+  (void)bid;  // one workgroup per factorization
+  constexpr int LDC = CHOL_LDC;
+  __shared__ __attribute__((aligned(16))) double M[128 * LDC];
+  __shared__ double rinv_d[128];
+  __shared__ int bad_s;
+  if (p.gate && *p.gate == 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0 && p.shifted && p.reset_shifted) *p.shifted = 0;
+  const int l = p.l, Lg = p.Lg;
+  const int lp = (l + 15) & ~15, T = lp >> 4;
+  const int tc = tid & 127, tr = tid >> 7;
+  const double eps = DBL_EPSILON;
+  // breakdown threshold (panel waves) and shift (all waves, only after a failure) from the
+  // diagonal of W
+  auto diag_stats = [&](double& mx_out, double& tr_out) {
+    const double d0 = lane < l ? p.G[(int64_t)lane * (Lg + 1)] : 0.0;
+    const double d1 = lane + 64 < l ? p.G[(int64_t)(lane + 64) * (Lg + 1)] : 0.0;
+    double mx = fmax(d0, d1), trs = d0 + d1;
+    for (int off = 32; off > 0; off >>= 1) {
+      mx = fmax(mx, __shfl_xor(mx, off, 64));
+      trs += __shfl_xor(trs, off, 64);
+    }
+    mx_out = mx;
+    tr_out = trs;
+  };
+  double thresh = 0.0, trace = 0.0;
+  bool ok = false;
+  for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
+    if (attempt == 1 && wave >= 2) {
+      double mx;
+      diag_stats(mx, trace);
+    }
+    const double shift =
+        attempt == 0 ? 0.0 : 11.0 * ((double)p.rows * l + (double)l * (l + 1)) * (0.5 * eps) * trace;
     ok = true;
-    for (int k0 = 0; k0 < l; k0 += CB) {
-      const int k1 = min(k0 + CB, l), bk = k1 - k0;
-      // 1. panel by waves 0 and 1.  Both factor the diagonal block (each 16-lane row
-      //    of both waves holds a copy); column sc = lane + 64 wave of the block row
-      //    is multiplied by R_kk^-T in the lane's registers.  Every load and store
-      //    stays inside M and Pr: values read from the zero padding or past lp only
-      //    ever reach entries that no later step reads.
-      const int dq = lane & (CB - 1);  // diagonal column k0 + dq
-      const int sc = lane + 64 * wave;
-      const bool diag = sc >= k0 && sc < k1;  // identity column inside the block: then dq == sc - k0
-      double x0[CB], xt[CB];
-      if (wave < 2) {
-#pragma unroll
-        for (int i = 0; i < CB; ++i) {
-          x0[i] = M[(k0 + i) * LDC + k0 + dq];  // below the diagonal: never read by other lanes
-          const double w = M[(k0 + i) * LDC + sc];
-          xt[i] = diag ? (i == dq ? 1.0 : 0.0) : w;
+    for (int k = 0; ok && 16 * k < l; ++k) {
+      if (k > 0) {
+        // rows of this panel first, one tile per wave, from the panel before
+        if (wave < T) {
+          const int tt[1] = {k}, cc[1] = {wave};
+          chol_tiles<1>(M, rinv_d, k - 1, tt, cc, l);
         }
+        __syncthreads();
       }
-      __syncthreads();  // both waves hold the diagonal block before either stores into it
+      int ln = lane;
+      asm volatile("" : "+v"(ln));  // addresses below are formed here, not hoisted and spilled
       if (wave < 2) {
-        double rv = 0.0;
-        bool bad = false;
+        const int dq = ln & 15, sc = ln + 64 * wave, k0 = 16 * k;
+        double x0[16], xt[16];
+        if (k == 0) {
+          // the first panel straight from W in global memory, while waves 2.. load the rest
 #pragma unroll
-        for (int j = 0; j < CB; ++j) {
-          if (j < bk) {  // uniform; a failed pivot only sets bad (the results are discarded)
-            const double djj = row_bcast_at(x0[j], j);
-            bad = bad || !(djj > thresh) || !isfinite(djj);
-            const double rinv = rsq_refined(djj);
-            double rjj = djj * rinv;
-            rjj = fma(0.5 * rinv, fma(-rjj, rjj, djj), rjj);
-            x0[j] = dq == j ? rjj : x0[j] * rinv;  // row j of R_kk
-            rv = dq == j ? rinv : rv;
-            xt[j] *= rinv;
+          for (int i = 0; i < 16; ++i) {
+            x0[i] = (i <= dq && dq < l) ? p.G[(int64_t)i * Lg + dq] : 0.0;
+            xt[i] = (i < l && sc >= 16 && sc < l) ? p.G[(int64_t)i * Lg + sc] : 0.0;
+          }
+          if (attempt == 0) {
+            double mx;
+            diag_stats(mx, trace);
+            thresh = (double)l * 16.0 * eps * mx;
+          }
 #pragma unroll
-            for (int i = j + 1; i < CB; ++i) {
-              const double rji = row_bcast_at(x0[j], i);  // R[j][i]
-              x0[i] = fma(-rji, x0[j], x0[i]);
-              xt[i] = fma(-rji, xt[j], xt[i]);
-            }
+          for (int i = 0; i < 16; ++i) {
+            asm volatile("" : "+v"(x0[i]), "+v"(xt[i]));
+            x0[i] = i != dq ? x0[i] : (dq < l ? x0[i] + shift : 1.0);
+            xt[i] = sc < 16 ? (i == dq ? 1.0 : 0.0) : xt[i];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            x0[i] = M[(k0 + i) * LDC + k0 + dq];
+            xt[i] = M[(k0 + i) * LDC + sc];
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            asm volatile("" : "+v"(xt[i]));
+            xt[i] = (sc >= k0 && sc < k0 + 16) ? (i == dq ? 1.0 : 0.0) : xt[i];
           }
         }
-        if (!bad) {
-          // identity columns inside the block carry R_kk above the diagonal (the
-          // lane's copy of column k0 + dq) and X_kk^T below it
-#pragma unroll
-          for (int i = 0; i < CB; ++i) {
-            M[(k0 + i) * LDC + sc] = (diag && i <= dq) ? x0[i] : xt[i];
-            Pr[i * PLD + sc] = xt[i];
-          }
-          if (diag) rinv_d[sc] = rv;
-        }
+        const bool bad = chol_panel(p, M, rinv_d, k0, l, thresh, x0, xt);
         if (tid == 0) bad_s = bad ? 1 : 0;
-      }
-      __syncthreads();
-      if (bad_s) {
-        ok = false;
-        break;
-      }
-      // 2. trailing update, one 16 x 16 output tile per wave and step, on FP64 MFMA
-      //    (K = 16: four 16x16x4 products).  Row tile r (rows k1 + 16 r ..) needs
-      //    the identity-part tiles left of k1 and the R-part tiles from its own
-      //    diagonal tile on: lp/16 - r tiles.
-      if (k1 < l) {
-        const int T = lp / 16, K1 = k1 / 16, nrt = T - K1;
-        const int items = nrt * T - nrt * (nrt - 1) / 2;
-        for (int it = wave; it < items; it += NW) {
-          int r = 0, u = it;
-          while (u >= T - r) {  // uniform: at most 8 steps
-            u -= T - r;
-            ++r;
-          }
-          const int cj = u < K1 ? u : u + r;
-          const int ib = k1 + 16 * r, cb = 16 * cj;
-          const int li = lane & 15, lk = lane >> 4;
-          f64x4 acc = f64x4{};
+      } else if (k == 0) {
+        // rows 16.. of W (upper triangle, shifted diagonal; zeros below; padded rows hold 1 on
+        // the diagonal) into M, two columns per thread
+        const int cp = 2 * ln, r0 = 16 + (wave - 2);
+        dbl2 v[19];
 #pragma unroll
-          for (int s4 = 0; s4 < CB / 4; ++s4) {
-            const double* row = Pr + (4 * s4 + lk) * PLD;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(row[ib + li], row[cb + li], acc, 0, 0, 0);
-          }
-          // acc[e] belongs to row ib + 4 e + lk, column cb + li
-          const int c = cb + li;
+        for (int u = 0; u < 19; ++u) {
+          const int a = r0 + 6 * u;
+          v[u] = (a < l && cp + 1 >= a && cp < l) ? *reinterpret_cast<const dbl2*>(p.G + (int64_t)a * Lg + cp)
+                                                  : dbl2{0.0, 0.0};
+        }
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int i = ib + 4 * e + lk;
-            if (i < l && c < l && (c < k1 || c >= i)) M[i * LDC + c] -= acc[e];
+        for (int u = 0; u < 19; ++u) {
+          const int a = r0 + 6 * u;
+          if (a < 128) {
+            dbl2 w = v[u];
+            w.x = (cp < l && cp >= a) ? w.x + (cp == a ? shift : 0.0) : (cp == a ? 1.0 : 0.0);
+            w.y = (cp + 1 < l && cp + 1 >= a) ? w.y + (cp + 1 == a ? shift : 0.0) : (cp + 1 == a ? 1.0 : 0.0);
+            *reinterpret_cast<dbl2*>(M + a * LDC + cp) = w;
           }
+        }
+      } else {
+        // the rest of the update from panel k - 1: row tiles t >= k + 1 (k identity tiles and
+        // T - t R tiles each), items wave - 2, wave + 4, ... of that list, two at a time
+        int t = k + 1, u = wave - 2;
+        while (t < T) {
+          int tt[2], cc[2];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            int cnt = k + (T - t);
+            while (t < T && u >= cnt) {
+              u -= cnt;
+              ++t;
+              cnt = k + (T - t);
+            }
+            tt[q] = t < T ? t : -1;
+            cc[q] = t < T ? (u < k ? u : t + (u - k)) : 0;
+            u += CHOL_UPDATE_WAVES;
+          }
+          if (tt[0] >= 0) chol_tiles<2>(M, rinv_d, k - 1, tt, cc, l);
         }
       }
       __syncthreads();
+      ok = bad_s == 0;
     }
     if (!ok && attempt == 0 && tid == 0) {
       atomicOr(p.status, (int32_t)RSVD_FLAG_SHIFTED);
       if (p.shifted) *p.shifted = 1;
     }
-    __syncthreads();  // every thread has read bad_s before the next attempt rewrites M
+    __syncthreads();
   }
   if (!ok) {
-    // Shifted factorization failed as well (non-finite input): identity factors.
     if (tid == 0) atomicOr(p.status, (int32_t)RSVD_FLAG_NONFINITE);
     if (tc < l)
       for (int a = tr; a < l; a += 4) {
@@ -435,23 +591,6 @@ __device__ __forceinline__ void chol_body_t(const CholParams& p) {
       }
     return;
   }
-  if (tc < l)
-    for (int a = tr; a < l; a += 4) {
-      const int64_t idx = (int64_t)a * l + tc;
-      if (p.R) p.R[idx] = tc >= a ? M[a * LDC + tc] : 0.0;
-      // X[a][tc] = (X^T)[tc][a]
-      const double v = tc > a ? M[tc * LDC + a] : (tc == a ? rinv_d[a] : 0.0);
-      if (p.Rinv) p.Rinv[idx] = v;
-      if (p.RinvT) {
-        if (p.dtype == RSVD_F64) ((double*)p.RinvT)[idx] = v;
-        else ((float*)p.RinvT)[idx] = (float)v;
-      }
-    }
-}
-
-__device__ __forceinline__ void chol_body(const CholParams& p, const int bid) {
-  (void)bid;  // one workgroup per factorization
-  chol_body_t<16>(p);
 }
 
 __global__ __launch_bounds__(512) void chol_kernel(const CholParams p) { chol_body(p, blockIdx.x); }
