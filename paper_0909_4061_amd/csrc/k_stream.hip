@@ -127,14 +127,16 @@ __device__ inline int valid4(int64_t v) { return v <= 0 ? 0 : (v >= 4 ? 4 : (int
 // the 16-byte operand reads (consecutive rows) stay conflict-free.
 __device__ inline int apos(int row, int k) { return row * BPAD + 8 * ((k >> 3) ^ ((row >> 4) & 3)) + (k & 7); }
 
-// One stage of A in registers: 8 runs of four floats per thread.
-//   NN (A rows x K): run q of thread t covers row (t / 8) + 16 q, k 4 (t % 8) .. +3.
+// One stage of A in registers: 1024 / THR runs of four floats per thread
+// (THR = 128 or 256 threads; R = THR / 8 rows or k apart).
+//   NN (A rows x K): run q of thread t covers row (t / 8) + R q, k 4 (t % 8) .. +3.
 //   TN (A K x rows): thread t covers the 4 x 4 block k 4 (t / 32) .. +3 (plus
-//   16 for the second block), columns 4 (t % 32) .. +3; run q = 4 b + r is row r
-//   of block b.
-template <bool TRANS, bool FAST = false>
+//   R b for block b), columns 4 (t % 32) .. +3; run q = 4 b + r is row r of
+//   block b.
+template <bool TRANS, bool FAST = false, int THR = STHREADS>
 __device__ inline void load_a_stage(const GemmParams& p, int64_t i0, int64_t k0, int64_t kend, int tid,
-                                    f32x4 (&ra)[8]) {
+                                    f32x4 (&ra)[1024 / THR]) {
+  constexpr int RUNS = 1024 / THR, RS = THR / 8;
   const float* A = (const float*)p.A;
   const bool vec = p.vec != 0;
   // FAST: a stage inside the matrix (every row / column of the block, every k
@@ -142,30 +144,30 @@ __device__ inline void load_a_stage(const GemmParams& p, int64_t i0, int64_t k0,
   // per-run guards.
   if (FAST && vec && i0 + SBM <= p.rows && k0 + SBK <= kend) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < RUNS; ++q) {
       int64_t off;
       if (!TRANS) {
-        off = (i0 + (tid >> 3) + 16 * q) * p.lda + k0 + 4 * (tid & 7);
+        off = (i0 + (tid >> 3) + RS * q) * p.lda + k0 + 4 * (tid & 7);
       } else {
         const int b = q >> 2, r = q & 3;
-        off = (k0 + 4 * (tid >> 5) + 16 * b + r) * p.lda + i0 + 4 * (tid & 31);
+        off = (k0 + 4 * (tid >> 5) + RS * b + r) * p.lda + i0 + 4 * (tid & 31);
       }
       ra[q] = *reinterpret_cast<const f32x4*>(A + off);
     }
     return;
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < RUNS; ++q) {
     int64_t off;
     int valid;
     if (!TRANS) {
-      const int64_t row = i0 + (tid >> 3) + 16 * q;
+      const int64_t row = i0 + (tid >> 3) + RS * q;
       const int64_t kc = k0 + 4 * (tid & 7);
       valid = row < p.rows ? valid4(kend - kc) : 0;
       off = row * p.lda + kc;
     } else {
       const int b = q >> 2, r = q & 3;
-      const int64_t kr = k0 + 4 * (tid >> 5) + 16 * b + r;
+      const int64_t kr = k0 + 4 * (tid >> 5) + RS * b + r;
       const int64_t col = i0 + 4 * (tid & 31);
       valid = kr < kend ? valid4(p.rows - col) : 0;
       off = kr * p.lda + col;
@@ -176,17 +178,18 @@ __device__ inline void load_a_stage(const GemmParams& p, int64_t i0, int64_t k0,
 
 // A stage known to lie inside the matrix with 16-byte aligned runs: plain
 // 16-byte loads (the same runs as load_a_stage).
-template <bool TRANS>
-__device__ inline void load_a_full(const GemmParams& p, int64_t i0, int64_t k0, int tid, f32x4 (&ra)[8]) {
+template <bool TRANS, int THR = STHREADS>
+__device__ inline void load_a_full(const GemmParams& p, int64_t i0, int64_t k0, int tid, f32x4 (&ra)[1024 / THR]) {
+  constexpr int RUNS = 1024 / THR, RS = THR / 8;
   const float* A = (const float*)p.A;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < RUNS; ++q) {
     int64_t off;
     if (!TRANS) {
-      off = (i0 + (tid >> 3) + 16 * q) * p.lda + k0 + 4 * (tid & 7);
+      off = (i0 + (tid >> 3) + RS * q) * p.lda + k0 + 4 * (tid & 7);
     } else {
       const int b = q >> 2, r = q & 3;
-      off = (k0 + 4 * (tid >> 5) + 16 * b + r) * p.lda + i0 + 4 * (tid & 31);
+      off = (k0 + 4 * (tid >> 5) + RS * b + r) * p.lda + i0 + 4 * (tid & 31);
     }
     ra[q] = *reinterpret_cast<const f32x4*>(A + off);
   }
@@ -198,7 +201,12 @@ __device__ inline void load_a_full(const GemmParams& p, int64_t i0, int64_t k0, 
 // C[8 (e / 4) + 4 g + e % 4][r].
 // WIDE: C and X wider than 128 columns, one 128-column chunk per workgroup
 // (the chunk index is a runtime quantity only in this variant).
-template <bool TRANS, int NP, bool WIDE>
+// NW waves per workgroup: with 2 each wave takes 64 rows x 128 columns of the
+// block (one wave per SIMD at two workgroups per CU, the LDS limit); with 4,
+// 64 rows x 64 columns, so that two waves share each SIMD and hide each
+// other's LDS and MFMA latencies.  Every element of C is accumulated by one
+// lane in the same order either way.
+template <bool TRANS, int NP, bool WIDE, int NW = 2>
 __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf16* __restrict__ xh,
                                                  const __bf16* __restrict__ xl, const int bid) {
   constexpr int APLANE = SBM * BPAD;  // bf16 elements per A plane per buffer
@@ -209,7 +217,10 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
   __shared__ __attribute__((aligned(16))) __bf16 sXl[2][NP == 3 ? XPLANE : 8];
   if (p.gate && *p.gate == 0) return;
 
+  constexpr int THR = 64 * NW, RUNS_A = 1024 / THR, RUNS_X = 512 / THR, TPW = 8 / NW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = NW == 2 ? wave : (wave & 1);  // 64-row half of the block
+  const int wc = NW == 2 ? 0 : (wave >> 1);    // 64-column half (NW = 4)
   const int S = p.S;
   // workgroup -> (row block, 128-column chunk of C, K chunk s)
   const int nch = WIDE ? (p.Lp + 127) >> 7 : 1;
@@ -226,37 +237,37 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
     xl += 128 * 32 * ch;
   }
 
-  f32x16 acc[2][4];
+  f32x16 acc[2][TPW];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[a][t] = f32x16{};
+    for (int t = 0; t < TPW; ++t) acc[a][t] = f32x16{};
 
   // Two stages of A are kept in flight (raA / raB alternate); X, which comes
   // from L2, one stage ahead.  X loads of a stage are issued before the A loads
   // of the stage after it, so writing a stage to LDS waits only for its own loads.
-  f32x4 raA[8], raB[8];
-  u32x4 rxh[4], rxl[4];
+  f32x4 raA[RUNS_A], raB[RUNS_A];
+  u32x4 rxh[RUNS_X], rxl[RUNS_X];
   // F (a std::integral_constant): every stage full and all 128 columns of X
   // present, so the per-run guards are compiled out of the steady-state loop.
   auto load_x = [&](int64_t k0, auto F) __attribute__((always_inline)) {
     const u32x4* gh = reinterpret_cast<const u32x4*>(xh + (k0 >> 5) * (int64_t)p.Lp * 32);
     const u32x4* gl = reinterpret_cast<const u32x4*>(xl + (k0 >> 5) * (int64_t)p.Lp * 32);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int run = tid + STHREADS * q;
+    for (int q = 0; q < RUNS_X; ++q) {
+      const int run = tid + THR * q;
       if (decltype(F)::value || run < NT * 128) {
         rxh[q] = gh[run];
         if (NP == 3) rxl[q] = gl[run];
       }
     }
   };
-  auto store_stage = [&](int buf, const f32x4 (&ra)[8], auto F) __attribute__((always_inline)) {
+  auto store_stage = [&](int buf, const f32x4 (&ra)[RUNS_A], auto F) __attribute__((always_inline)) {
     // A: split and write K-contiguous rows
     if (!TRANS) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int row = (tid >> 3) + 16 * q;
+      for (int q = 0; q < RUNS_A; ++q) {
+        const int row = (tid >> 3) + (THR / 8) * q;
         const int kc = 4 * (tid & 7);
         u32x2 h, l;
         split4(ra[q], h, l);
@@ -265,8 +276,8 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
       }
     } else {
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int kc = 4 * (tid >> 5) + 16 * b;
+      for (int b = 0; b < RUNS_A / 4; ++b) {
+        const int kc = 4 * (tid >> 5) + (THR / 8) * b;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int row = 4 * (tid & 31) + e;  // column of A = row of C
@@ -280,8 +291,8 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
     }
     // X: 16-byte runs, run = column * 4 + quarter
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int run = tid + STHREADS * q;
+    for (int q = 0; q < RUNS_X; ++q) {
+      const int run = tid + THR * q;
       if (decltype(F)::value || run < NT * 128) {
         const int c = run >> 2, part = run & 3;
         *reinterpret_cast<u32x4*>(&sXh[buf][c * BPAD + 8 * part]) = rxh[q];
@@ -297,12 +308,13 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
       bf16x8 ah[2], al[2];
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
-        const int row = wave * 64 + rt * 32 + r;
+        const int row = wr * 64 + rt * 32 + r;
         ah[rt] = *reinterpret_cast<const bf16x8*>(&sAh[buf][apos(row, kb)]);
         if (NP == 3) al[rt] = *reinterpret_cast<const bf16x8*>(&sAl[buf][apos(row, kb)]);
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int tt = 0; tt < TPW; ++tt) {
+        const int t = wc * TPW + tt;
         if (decltype(F)::value || t < NT) {
           const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sXh[buf][(t * 32 + r) * BPAD + kb]);
           bf16x8 bl;
@@ -310,10 +322,10 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
 #pragma unroll
           for (int rt = 0; rt < 2; ++rt) {
             if (NP == 3) {
-              acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rt], bh, acc[rt][t], 0, 0, 0);
-              acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bl, acc[rt][t], 0, 0, 0);
+              acc[rt][tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rt], bh, acc[rt][tt], 0, 0, 0);
+              acc[rt][tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bl, acc[rt][tt], 0, 0, 0);
             }
-            acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bh, acc[rt][t], 0, 0, 0);
+            acc[rt][tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bh, acc[rt][tt], 0, 0, 0);
           }
         }
       }
@@ -323,9 +335,9 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
 
   const std::false_type G{};
   const std::true_type F{};
-  if (nk > 0) load_a_stage<TRANS, true>(p, i0, kofs(0), kend, tid, raA);
+  if (nk > 0) load_a_stage<TRANS, true, THR>(p, i0, kofs(0), kend, tid, raA);
   if (nk > 0) load_x(kofs(0), G);
-  if (nk > 1) load_a_stage<TRANS, true>(p, i0, kofs(1), kend, tid, raB);
+  if (nk > 1) load_a_stage<TRANS, true, THR>(p, i0, kofs(1), kend, tid, raB);
   if (nk > 0) store_stage(0, raA, G);
   __syncthreads();
   int64_t kt = 0;
@@ -335,12 +347,12 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
   if (NT == 4 && p.vec != 0 && i0 + SBM <= p.rows && (kend - kbeg) % SBK == 0) {
     for (; kt + 3 < nk; kt += 2) {
       load_x(kofs(kt + 1), F);
-      load_a_full<TRANS>(p, i0, kofs(kt + 2), tid, raA);
+      load_a_full<TRANS, THR>(p, i0, kofs(kt + 2), tid, raA);
       compute(0, F);
       store_stage(1, raB, F);
       __syncthreads();
       load_x(kofs(kt + 2), F);
-      load_a_full<TRANS>(p, i0, kofs(kt + 3), tid, raB);
+      load_a_full<TRANS, THR>(p, i0, kofs(kt + 3), tid, raB);
       compute(1, F);
       store_stage(0, raA, F);
       __syncthreads();
@@ -349,14 +361,14 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
   for (; kt < nk; kt += 2) {
     // stage kt in buffer 0; stage kt + 1 in flight in raB
     if (kt + 1 < nk) load_x(kofs(kt + 1), G);
-    if (kt + 2 < nk) load_a_stage<TRANS, true>(p, i0, kofs(kt + 2), kend, tid, raA);
+    if (kt + 2 < nk) load_a_stage<TRANS, true, THR>(p, i0, kofs(kt + 2), kend, tid, raA);
     compute(0, G);
     if (kt + 1 < nk) store_stage(1, raB, G);
     __syncthreads();
     if (kt + 1 >= nk) break;
     // stage kt + 1 in buffer 1; stage kt + 2 in flight in raA
     if (kt + 2 < nk) load_x(kofs(kt + 2), G);
-    if (kt + 3 < nk) load_a_stage<TRANS, true>(p, i0, kofs(kt + 3), kend, tid, raB);
+    if (kt + 3 < nk) load_a_stage<TRANS, true, THR>(p, i0, kofs(kt + 3), kend, tid, raB);
     compute(1, G);
     if (kt + 2 < nk) store_stage(0, raA, G);
     __syncthreads();
@@ -367,17 +379,18 @@ __device__ __forceinline__ void stream_bf16_body(const GemmParams& p, const __bf
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int tt = 0; tt < TPW; ++tt) {
+      const int t = wc * TPW + tt;
       if (t >= NT) continue;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int64_t row = i0 + wave * 64 + rt * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
+        const int64_t row = i0 + wr * 64 + rt * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
         const int col = 128 * ch + t * 32 + r;
         if (row < p.rows) {
           if (S == 1) {
-            if (col < p.ncols) out[row * p.ldo + col] = acc[rt][t][e];
+            if (col < p.ncols) out[row * p.ldo + col] = acc[rt][tt][e];
           } else {
-            part[((int64_t)s * p.rows + row) * p.Lp + col] = acc[rt][t][e];
+            part[((int64_t)s * p.rows + row) * p.Lp + col] = acc[rt][tt][e];
           }
         }
       }
@@ -389,6 +402,13 @@ template <bool TRANS, int NP, bool WIDE>
 __global__ __launch_bounds__(STHREADS, 2) __attribute__((amdgpu_waves_per_eu(1, 1))) void stream_bf16_kernel(
     const GemmParams p, const __bf16* __restrict__ xh, const __bf16* __restrict__ xl) {
   stream_bf16_body<TRANS, NP, WIDE>(p, xh, xl, blockIdx.x);
+}
+
+// Four waves per workgroup, two per SIMD (the single-problem launches).
+template <bool TRANS, int NP, bool WIDE>
+__global__ __launch_bounds__(4 * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void stream_bf16_kernel4(
+    const GemmParams p, const __bf16* __restrict__ xh, const __bf16* __restrict__ xl) {
+  stream_bf16_body<TRANS, NP, WIDE, 4>(p, xh, xl, blockIdx.x);
 }
 
 // Batched: problem bm[b].item, its own packed X (hi plane, then lo plane) at p.pack.
@@ -577,20 +597,21 @@ hipError_t launch_pack_x(int prec, const GemmParams& p, hipStream_t st) {
 
 namespace {
 
+// Single problems take the four-wave workgroups (two waves per SIMD).
 template <bool WIDE>
 void launch_bf16_single(int prec, bool trans, const GemmParams& p, dim3 grid, const __bf16* xh, const __bf16* xl,
                         hipStream_t st) {
-  const dim3 block(STHREADS);
+  const dim3 block(4 * 64);
   if (prec == PREC_BF16X3) {
     if (trans)
-      hipLaunchKernelGGL((stream_bf16_kernel<true, 3, WIDE>), grid, block, 0, st, p, xh, xl);
+      hipLaunchKernelGGL((stream_bf16_kernel4<true, 3, WIDE>), grid, block, 0, st, p, xh, xl);
     else
-      hipLaunchKernelGGL((stream_bf16_kernel<false, 3, WIDE>), grid, block, 0, st, p, xh, xl);
+      hipLaunchKernelGGL((stream_bf16_kernel4<false, 3, WIDE>), grid, block, 0, st, p, xh, xl);
   } else {
     if (trans)
-      hipLaunchKernelGGL((stream_bf16_kernel<true, 1, WIDE>), grid, block, 0, st, p, xh, xl);
+      hipLaunchKernelGGL((stream_bf16_kernel4<true, 1, WIDE>), grid, block, 0, st, p, xh, xl);
     else
-      hipLaunchKernelGGL((stream_bf16_kernel<false, 1, WIDE>), grid, block, 0, st, p, xh, xl);
+      hipLaunchKernelGGL((stream_bf16_kernel4<false, 1, WIDE>), grid, block, 0, st, p, xh, xl);
   }
 }
 
