@@ -140,9 +140,13 @@ const char* rsvd_status_string(rsvd_status status);
 
 /* Stage A, first application: Algorithm 4.1 (Gaussian; step 2 of Algorithm
  * 4.4) or Algorithm 4.5 (SRFT).  Draws Omega from (seed, stream_id), forms
- * Y = A Omega and writes an orthonormal basis Q (m x l) of range(Y), computed
- * by CholeskyQR2 (two passes of Gram -> Cholesky -> Y R^-1, FP64 Gram and
- * Cholesky).  A: m x n (lda); Q: m x l output.  With the SRFT, Y is formed in
+ * Y = A Omega and writes a basis Q (m x l) of range(Y).  With problem->q == 0
+ * Q is orthonormal, computed by CholeskyQR2 (two passes of Gram -> Cholesky ->
+ * Y R^-1, FP64 Gram and Cholesky, a shifted third pass when needed).  With
+ * q > 0 the power steps of rsvd_power_iter follow and Q only feeds the first
+ * of them: one CholeskyQR pass (all three when the first needed a shift), a
+ * well-conditioned basis orthonormal to about u kappa(Y) (see
+ * rsvd_power_iter).  A: m x n (lda); Q: m x l output.  With the SRFT, Y is formed in
  * the element type by one length-n real FFT per row of A D (the full
  * transform, then the l sampled frequencies: the variant the remark after
  * Algorithm 4.5 recommends); problem->prec does not apply to it. */

@@ -570,12 +570,15 @@ rsvd_status sketch(const Ctx& c, const rsvd_problem* pr, const void* A, void* y)
 // --- the steps of the hot path, shared by the single and batched calls -----
 
 // Algorithm 4.1 steps 2-3 / Algorithm 4.5: Q = orth(A Omega).
-rsvd_status range_finder_steps(const Ctx& c, const rsvd_problem* pr, const void* A, void* Q) {
+// full == false (problem->q > 0: power steps follow): the basis only feeds the
+// first power step, so it takes one CholeskyQR pass like the other inner bases
+// (see orth).
+rsvd_status range_finder_steps(const Ctx& c, const rsvd_problem* pr, const void* A, void* Q, bool full = true) {
   void* y = c.at<void>(c.P.Y);
   const bool parts = pr->sketch == RSVD_GAUSSIAN && c.P.nn.S > 1;
   rsvd_status s = sketch(c, pr, A, y);
   if (s != RSVD_OK) return s;
-  return orth(c, parts, c.P.nn, y, pr->m, Q, nullptr);
+  return orth(c, parts, c.P.nn, y, pr->m, Q, nullptr, full);
 }
 
 // Algorithm 4.4 steps 3-6.
@@ -1431,7 +1434,7 @@ rsvd_status record_forward(const void* ctx, int32_t i, Runner& run) {
   void* Q = f.ws + f.L->q_off[u];
   void* Bt = f.ws + f.L->bt_off[u];
   const rsvd_problem* pr = &f.probs[u];
-  rsvd_status s = range_finder_steps(c, pr, f.A[u], Q);
+  rsvd_status s = range_finder_steps(c, pr, f.A[u], Q, pr->q == 0);
   if (s == RSVD_OK) s = power_steps(c, pr, f.A[u], Q);
   if (s == RSVD_OK) s = project_steps(c, pr, f.A[u], Q, Bt);
   if (s == RSVD_OK) s = svd_steps(c, Bt, Q, f.U[u], f.S[u], f.V[u]);
@@ -1569,7 +1572,7 @@ rsvd_status capture_full(rsvd_handle h, const rsvd_problem* pr, const FullLayout
   const Ctx c{F.P, ws + F.base, h->capture, h->status, nullptr, &dr};
   void* Q = ws + F.q_off;
   void* Bt = ws + F.bt_off;
-  rsvd_status s = range_finder_steps(c, pr, A, Q);
+  rsvd_status s = range_finder_steps(c, pr, A, Q, pr->q == 0);
   if (s == RSVD_OK) s = power_steps(c, pr, A, Q);
   if (s == RSVD_OK) s = project_steps(c, pr, A, Q, Bt);
   if (s == RSVD_OK) s = svd_steps(c, Bt, Q, U, S, V);
@@ -1825,7 +1828,7 @@ rsvd_status rsvd_range_finder(rsvd_handle h, const rsvd_problem* pr, const void*
   if (!A || !Q) return RSVD_E_INVAL;
   DirectRunner dr(h, stream);
   const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
-  return range_finder_steps(c, pr, A, Q);
+  return range_finder_steps(c, pr, A, Q, pr->q == 0);
 }
 
 rsvd_status rsvd_sketch(rsvd_handle h, const rsvd_problem* pr, const void* A, void* Y, void* ws, size_t ws_bytes,
@@ -1920,7 +1923,7 @@ rsvd_status rsvd_full_static(rsvd_handle h, const rsvd_problem* pr, const void* 
   const Ctx c{F.P, ws + F.base, stream, h->status, h, &dr};
   void* Q = ws + F.q_off;
   void* Bt = ws + F.bt_off;
-  rsvd_status s = range_finder_steps(c, pr, A, Q);
+  rsvd_status s = range_finder_steps(c, pr, A, Q, pr->q == 0);
   if (s == RSVD_OK) s = power_steps(c, pr, A, Q);
   if (s == RSVD_OK) s = project_steps(c, pr, A, Q, Bt);
   if (s == RSVD_OK) s = svd_steps(c, Bt, Q, U, S, V);
