@@ -166,6 +166,40 @@ def test_exact_rank_uses_shift():
     assert evaluate.residual_usv(A64, *out[:3]) < 1e-7
 
 
+@pytest.mark.parametrize("prec", ["native", "bf16x3"])
+@pytest.mark.parametrize("kind", ["exact_rank", "steep"])
+def test_fp32_shifted_inner_bases_match_oracle(kind, prec):
+    # FP32 data whose sketches are numerically rank deficient (exact rank 6 < l = 16, or a spectrum
+    # falling below FP32 resolution within l), so that CholeskyQR needs the shift in the inner bases
+    # of the power scheme and in the final one.  Against the oracle (Householder QR at every step): singular values within 1e-5
+    # relative plus the FP32 floor (4 sqrt(m) + 2 l) u sigma_1 (2^-16 sigma_1 for bf16x3 products),
+    # the residual within 1% of the oracle's plus that floor, orthonormal U and Q.
+    m, n, k, p, q = 1500, 600, 6, 10, 2
+    if kind == "exact_rank":
+        sigma = np.zeros(n)
+        sigma[:k] = [4.0, 3.0, 2.0, 1.5, 1.0, 0.5]
+    else:
+        sigma = spectrum("exp_r", n, rate=0.5)  # sigma_16 / sigma_1 = e^-30: below FP32 resolution
+    A32 = build_matrix(m, n, sigma, seed=11, dtype=np.float32)
+    A64 = A32.astype(np.float64)
+    A = torch.from_numpy(A32).to(DEV)
+    out, flags, _ = _run(A, k, p, q, seed=6, prec=prec)
+    if kind == "exact_rank":
+        assert flags & rs.RSVD_FLAG_SHIFTED
+    assert flags & ~rs.RSVD_FLAG_SHIFTED == 0
+    r = compare_to_oracle(A64, out, k, p, q, 6, np.float32)
+    ref = r["ref"]
+    u = 2.0 ** -24 if prec == "native" else 2.0 ** -16
+    floor = (4.0 * np.sqrt(m) + 2.0 * (k + p)) * u * ref["Sk"][0]
+    err = np.abs(out[1].astype(np.float64) - ref["Sk"])
+    print(f"{kind} {prec}: max sigma err / (1e-5 sigma + floor) "
+          f"{np.max(err / (1e-5 * ref['Sk'] + floor)):.3f}, residual {r['res_k']:.3e} vs {r['res_k_ref']:.3e}")
+    assert np.all(err <= 1e-5 * ref["Sk"] + floor)
+    assert abs(r["res_k"] - r["res_k_ref"]) <= 0.01 * r["res_k_ref"] + floor
+    assert evaluate.orthonormality_error(out[0].astype(np.float64)) <= 1e-5
+    assert r["orth_q"] <= 1e-5
+
+
 def test_strided_rows():
     # lda > n: a column slice of a wider matrix
     m, n, k, p = 700, 300, 10, 5
