@@ -39,11 +39,12 @@ namespace rsvd {
 
 namespace {
 
-// Move a double across lanes of a 16-lane DPP row.
+// Move a double across lanes of a 16-lane DPP row (every pattern used stays
+// inside the row, so no lane reads out of bounds).
 template <int CTRL>
 __device__ __forceinline__ double eig_dpp(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
@@ -98,14 +99,22 @@ __device__ __forceinline__ double start_value(int j, int i) {
 }
 
 // ---------------------------------------------------------------------------
-// tridiag: W -> (d, e, tau, reflectors).  Thread t owns rows TR (t / 16) ..
-// TR (t / 16) + TR - 1 and columns TC (t % 16) .. TC (t % 16) + TC - 1: one
-// DPP row of 16 lanes per block of TR rows.  Four rows per tile (fewer waves
-// repeating the reductions) from l > 64 on, two below.
+// tridiag: W -> (d, e, tau, reflectors).  NA groups of 16 lanes (one DPP row
+// each); group a owns rows a + NA ri (ri < TR) and lane b of it columns
+// b + 16 cc (cc < TC = MAXL / 16), both cyclic, so that the rows and columns
+// that are done (index <= i at step i) leave every lane's tile at the same
+// pace.  The steps run in segments of 16: in segment T (steps 16 T ..
+// 16 T + 15) the column blocks cc < T and the row registers ri < RS = 16 T / NA
+// hold only finished entries and are skipped at compile time, the reflector's
+// row is register RS of group i mod NA, and only column block T (and the
+// first lane of block T + 1) needs a mask.  Finished entries inside the live
+// blocks are never read as data: v and p are zero there.
 template <int MAXL>
-constexpr int tri_rows() { return MAXL > 64 ? 4 : 2; }
+constexpr int tri_groups() { return MAXL > 32 ? 32 : 16; }
 template <int MAXL>
-constexpr int tri_threads() { return MAXL / tri_rows<MAXL>() * 16; }
+constexpr int tri_rows() { return MAXL / tri_groups<MAXL>(); }
+template <int MAXL>
+constexpr int tri_threads() { return tri_groups<MAXL>() * 16; }
 
 // 1/sqrt(x) and 1/x from the hardware estimates and two Newton steps each.
 __device__ __forceinline__ double rsq_refined(double x) {
@@ -115,54 +124,43 @@ __device__ __forceinline__ double rsq_refined(double x) {
   return y;
 }
 
+// LDS vectors of the reduction, stored so that lane b of a group reads its TC
+// columns b + 16 cc contiguously: entry c sits at (c mod 16) TC + c / 16.
 template <int MAXL>
-__device__ __forceinline__ void tridiag_body(const EigParams& p) {
-  constexpr int TR = tri_rows<MAXL>(), TC = MAXL / 16, NA = MAXL / TR, RPW = 4 * TR;  // rows per wave
-  static_assert(MAXL % 16 == 0 && NA <= 64 && TC % 2 == 0, "tile layout");
+struct TriShared {
+  double vbuf[2][MAXL];  // reflector v of the step (double-buffered)
+  double pbuf[2][MAXL];  // p = tau W v
+  double kpart[2][32];   // per group: sum of p_r v_r over its rows
+  double taus[2];
+};
+
+template <int MAXL, int T>
+__device__ __forceinline__ void tridiag_segment(const EigParams& p, TriShared<MAXL>& sh,
+                                                double (&w)[tri_rows<MAXL>()][MAXL / 16], int nsteps) {
+  constexpr int TR = tri_rows<MAXL>(), TC = MAXL / 16, NA = tri_groups<MAXL>();
+  constexpr int RS = 16 * T / NA;  // first live row register
+  constexpr int RSTEP = NA / 16;   // position stride of a group's successive rows
   typedef double d2 __attribute__((ext_vector_type(2)));
-  __shared__ __attribute__((aligned(16))) double vbuf[2][MAXL];
-  __shared__ __attribute__((aligned(16))) double pbuf[2][MAXL];
-  __shared__ double kpart[2][NA];
-  __shared__ double taus[2];
-  const int tid = threadIdx.x, a = tid >> 4, b = tid & 15, lane = tid & 63, wave = tid >> 6;
-  const int l = p.l, Lg = p.Lg;
-  const int r0 = TR * a, c0 = TC * b;
-  double* __restrict__ dvec = p.tri;
-  double* __restrict__ evec = p.tri + l;
-  double* __restrict__ tvec = p.tri + 2 * l;
-
-  double w[TR][TC];
+  const int tid = threadIdx.x, a = tid >> 4, b = tid & 15, lane = tid & 63;
+  const int l = p.l;
+  const int rp0 = (a & 15) * TC + (a >> 4);  // position of row a
+  const int iend = min(16 * T + 16, nsteps);
+  for (int i = 16 * T; i < iend; ++i) {
+    const int buf = i & 1, ib = i - 16 * T;
+    // 1. reflector of row i (= column i) by group i mod NA from its register RS
+    if (a == (i & (NA - 1))) {
+      const int gl = 16 * ((i & (NA - 1)) & 3);  // first lane of the group in its wave
+      const double xt = w[RS][T];
+      const double xn = T + 1 < TC ? w[RS][T + 1 < TC ? T + 1 : T] : 0.0;
+      const double dii = lane_value(xt, gl + ib);
+      const double x0 = ib < 15 ? lane_value(xt, gl + min(ib + 1, 15)) : lane_value(xn, gl);
+      const bool mt = b >= ib + 2;             // block T: column >= i + 2
+      const bool mn = ib < 15 || b > 0;        // block T + 1: column >= i + 2
+      double s2 = mt ? xt * xt : 0.0;
+      if (T + 1 < TC) s2 = mn ? fma(xn, xn, s2) : s2;
 #pragma unroll
-  for (int ri = 0; ri < TR; ++ri)
-#pragma unroll
-    for (int cc = 0; cc < TC; ++cc) {
-      const int r = r0 + ri, c = c0 + cc;
-      w[ri][cc] = (r < l && c < l) ? p.G[(int64_t)min(r, c) * Lg + max(r, c)] : 0.0;
-    }
-
-  for (int i = 0; i + 2 < l; ++i) {
-    const int buf = i & 1;
-    // 1. reflector of row i (= column i) by its block of rows (one DPP row)
-    if (a == i / TR) {
-      // row i of the tile (constant register indices on every branch)
-      double x[TC];
-      const int ri = i % TR;
-#pragma unroll
-      for (int q = 0; q < TR; ++q)
-        if (ri == q) {
-#pragma unroll
-          for (int cc = 0; cc < TC; ++cc) x[cc] = w[q][cc];
-        }
-      double s2 = 0.0, x0 = 0.0, dii = 0.0;
-#pragma unroll
-      for (int cc = 0; cc < TC; ++cc) {
-        const int c = c0 + cc;
-        s2 = c >= i + 2 ? fma(x[cc], x[cc], s2) : s2;
-        x0 = c == i + 1 ? x[cc] : x0;
-        dii = c == i ? x[cc] : dii;
-      }
+      for (int cc = T + 2; cc < TC; ++cc) s2 = fma(w[RS][cc], w[RS][cc], s2);
       s2 = row_sum16(s2);
-      x0 = row_sum16(x0);
       double tau = 0.0, beta = x0, scal = 0.0;
       if (s2 > 0.0) {
         const double n2 = fma(x0, x0, s2);
@@ -174,92 +172,102 @@ __device__ __forceinline__ void tridiag_body(const EigParams& p) {
       }
       double v[TC];
 #pragma unroll
-      for (int cc = 0; cc < TC; ++cc) {
-        const int c = c0 + cc;
-        v[cc] = c == i + 1 ? 1.0 : (c >= i + 2 ? x[cc] * scal : 0.0);
-      }
-      double* vrow = p.V + (int64_t)i * EIG_LDV + c0;
+      for (int cc = 0; cc < TC; ++cc) v[cc] = cc > T + 1 ? w[RS][cc] * scal : 0.0;
+      v[T] = mt ? xt * scal : (b == ib + 1 ? 1.0 : 0.0);
+      if (T + 1 < TC) v[T + 1 < TC ? T + 1 : T] = mn ? xn * scal : 1.0;
 #pragma unroll
-      for (int cc = 0; cc < TC; cc += 2) {
-        *reinterpret_cast<d2*>(&vbuf[buf][c0 + cc]) = d2{v[cc], v[cc + 1]};
-        *reinterpret_cast<d2*>(vrow + cc) = d2{v[cc], v[cc + 1]};
-      }
-      if (c0 <= i && i < c0 + TC) dvec[i] = dii;  // the lane holding the diagonal entry
+      for (int cc = 0; cc < TC; cc += 2) *reinterpret_cast<d2*>(&sh.vbuf[buf][b * TC + cc]) = d2{v[cc], v[cc + 1]};
+      double* vrow = p.V + (int64_t)i * EIG_LDV + b;
+#pragma unroll
+      for (int cc = 0; cc < TC; ++cc) vrow[16 * cc] = v[cc];
       if (b == 0) {
-        taus[buf] = tau;
-        tvec[i] = tau;
-        evec[i] = beta;
+        sh.taus[buf] = tau;
+        p.tri[i] = dii;
+        p.tri[l + i] = beta;
+        p.tri[2 * l + i] = tau;
       }
     }
     __syncthreads();
-    // 2. p = tau W v over the rows below i (waves whose rows are all <= i are done)
-    const bool live = RPW * wave + RPW - 1 > i;
-    double vr[TR], vc[TC], pr[TR];
-    const double tau = taus[buf];
-    if (live) {
+    // 2. p = tau W v (rows <= i give zero), and this group's share of p.v
+    const double tau = sh.taus[buf];
+    double vr[TR], pr[TR], vc[TC];
 #pragma unroll
-      for (int ri = 0; ri < TR; ri += 2) {
-        const d2 t = *reinterpret_cast<const d2*>(&vbuf[buf][r0 + ri]);
-        vr[ri] = t.x;
-        vr[ri + 1] = t.y;
-      }
+    for (int ri = RS; ri < TR; ++ri) vr[ri] = sh.vbuf[buf][rp0 + RSTEP * ri];
 #pragma unroll
-      for (int cc = 0; cc < TC; cc += 2) {
-        const d2 t = *reinterpret_cast<const d2*>(&vbuf[buf][c0 + cc]);
-        vc[cc] = t.x;
-        vc[cc + 1] = t.y;
-      }
-      double kp = 0.0;
+    for (int cc = T & ~1; cc < TC; cc += 2) {
+      const d2 t = *reinterpret_cast<const d2*>(&sh.vbuf[buf][b * TC + cc]);
+      vc[cc] = t.x;
+      vc[cc + 1] = t.y;
+    }
+    double kp = 0.0;
 #pragma unroll
-      for (int ri = 0; ri < TR; ++ri) {
-        double s = 0.0;
+    for (int ri = RS; ri < TR; ++ri) {
+      double s = 0.0;
 #pragma unroll
-        for (int cc = 0; cc < TC; ++cc) s = fma(w[ri][cc], vc[cc], s);
-        s = row_sum16(s) * tau;
-        pr[ri] = r0 + ri > i ? s : 0.0;
-        kp = fma(pr[ri], vr[ri], kp);
-      }
-      if (b == 0) {
+      for (int cc = T; cc < TC; ++cc) s = fma(w[ri][cc], vc[cc], s);
+      s = row_sum16(s) * tau;
+      if (ri == RS) s = a + NA * RS > i ? s : 0.0;
+      pr[ri] = s;
+      kp = fma(s, vr[ri], kp);
+    }
+    if (b == 0) {
 #pragma unroll
-        for (int ri = 0; ri < TR; ri += 2) *reinterpret_cast<d2*>(&pbuf[buf][r0 + ri]) = d2{pr[ri], pr[ri + 1]};
-        kpart[buf][a] = kp;
-      }
+      for (int ri = RS; ri < TR; ++ri) sh.pbuf[buf][rp0 + RSTEP * ri] = pr[ri];
+      sh.kpart[buf][a] = kp;
     }
     __syncthreads();
-    // 3. K = tau/2 p.v, w = p - K v, W -= v w^T + w v^T (the products of rows and
-    //    columns <= i are zeros, read as such)
-    if (live) {
-      const double kin = (lane < NA && TR * lane + TR - 1 > i) ? kpart[buf][lane] : 0.0;
-      const double K = 0.5 * tau * wave_sum(kin);
-      double wr[TR];
+    // 3. K = tau/2 p.v, w = p - K v, W -= v w^T + w v^T over the live tile
+    const double K = 0.5 * tau * wave_sum(lane < NA ? sh.kpart[buf][lane] : 0.0);
+    double wr[TR];
 #pragma unroll
-      for (int ri = 0; ri < TR; ++ri) wr[ri] = fma(-K, vr[ri], pr[ri]);
+    for (int ri = RS; ri < TR; ++ri) wr[ri] = fma(-K, vr[ri], pr[ri]);
 #pragma unroll
-      for (int cc = 0; cc < TC; cc += 2) {
-        const d2 t = *reinterpret_cast<const d2*>(&pbuf[buf][c0 + cc]);
-        const double pc[2] = {c0 + cc > i ? t.x : 0.0, c0 + cc + 1 > i ? t.y : 0.0};
+    for (int cc = T & ~1; cc < TC; cc += 2) {
+      const d2 t = *reinterpret_cast<const d2*>(&sh.pbuf[buf][b * TC + cc]);
+      const double pc[2] = {t.x, t.y};
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const double wc = fma(-K, vc[cc + h], pc[h]);
+      for (int h = 0; h < 2; ++h) {
+        if (cc + h < T) continue;
+        const double wc = fma(-K, vc[cc + h], pc[h]);
 #pragma unroll
-          for (int ri = 0; ri < TR; ++ri)
-            w[ri][cc + h] = fma(-vr[ri], wc, fma(-wr[ri], vc[cc + h], w[ri][cc + h]));
-        }
+        for (int ri = RS; ri < TR; ++ri) w[ri][cc + h] = fma(-vr[ri], wc, fma(-wr[ri], vc[cc + h], w[ri][cc + h]));
       }
     }
   }
+  if constexpr (T + 1 < MAXL / 16) {
+    if (16 * (T + 1) < nsteps) tridiag_segment<MAXL, T + 1>(p, sh, w, nsteps);
+  }
+}
+
+template <int MAXL>
+__device__ __forceinline__ void tridiag_body(const EigParams& p) {
+  constexpr int TR = tri_rows<MAXL>(), TC = MAXL / 16, NA = tri_groups<MAXL>();
+  static_assert(MAXL % 16 == 0 && TC % 2 == 0 && (NA == 16 || NA == 32) && TR * NA == MAXL, "tile layout");
+  __shared__ __attribute__((aligned(16))) TriShared<MAXL> sh;
+  const int tid = threadIdx.x, a = tid >> 4, b = tid & 15;
+  const int l = p.l, Lg = p.Lg;
+  double w[TR][TC];
+#pragma unroll
+  for (int ri = 0; ri < TR; ++ri)
+#pragma unroll
+    for (int cc = 0; cc < TC; ++cc) {
+      const int r = a + NA * ri, c = b + 16 * cc;
+      w[ri][cc] = (r < l && c < l) ? p.G[(int64_t)min(r, c) * Lg + max(r, c)] : 0.0;
+    }
+  const int nsteps = l > 2 ? l - 2 : 0;
+  if (nsteps > 0) tridiag_segment<MAXL, 0>(p, sh, w, nsteps);
   // the last 2 x 2 block (or 1 x 1) is already tridiagonal
 #pragma unroll
   for (int ri = 0; ri < TR; ++ri)
 #pragma unroll
     for (int cc = 0; cc < TC; ++cc) {
-      const int r = r0 + ri, c = c0 + cc;
-      if (r < l && r >= l - 2 && c == r) dvec[r] = w[ri][cc];
-      if (l >= 2 && r == l - 2 && c == l - 1) evec[l - 2] = w[ri][cc];
+      const int r = a + NA * ri, c = b + 16 * cc;
+      if (r < l && r >= l - 2 && c == r) p.tri[r] = w[ri][cc];
+      if (l >= 2 && r == l - 2 && c == l - 1) p.tri[l + l - 2] = w[ri][cc];
     }
   if (tid == 0) {
-    if (l >= 1) evec[l - 1] = 0.0;
-    for (int i = max(l - 2, 0); i < l; ++i) tvec[i] = 0.0;
+    if (l >= 1) p.tri[l + l - 1] = 0.0;
+    for (int i = max(l - 2, 0); i < l; ++i) p.tri[2 * l + i] = 0.0;
   }
 }
 
