@@ -33,6 +33,8 @@
 //              column needs it.
 #include <float.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace rsvd {
@@ -275,36 +277,69 @@ typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ dbl2 ld2(const double* p) { return *reinterpret_cast<const dbl2*>(p); }
 
+// The vectors of the scaled T's recurrences live in registers: register b of
+// lane k holds entry 16 b + (k mod 16), the same in each of the wave's four
+// 16-lane rows, and entry 16 b + c reaches every lane by one 64-bit DPP
+// broadcast of lane c of the row.  The recurrences, which every lane runs with
+// its own shift, read no memory.
+template <int NB>
+struct TriReg {
+  double r[NB];
+};
+
+template <int NB>
+__device__ __forceinline__ TriReg<NB> tri_load(const double* __restrict__ v, int lane) {
+  TriReg<NB> t;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) t.r[b] = v[16 * b + (lane & 15)];
+  return t;
+}
+
+template <int C>
+__device__ __forceinline__ double eig_bcast(double v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + C, 0xF, 0xF, false);  // row_newbcast: lane C of the row
+}
+
+// f(std::integral_constant<int, c>) for c = C .. 15, or 15 down to C when DOWN.
+template <int C, bool DOWN = false, typename F>
+__device__ __forceinline__ void for16(F&& f) {
+  if constexpr (C < 16) {
+    if constexpr (DOWN) {
+      for16<C + 1, DOWN>(f);
+      f(std::integral_constant<int, C>{});
+    } else {
+      f(std::integral_constant<int, C>{});
+      for16<C + 1, DOWN>(f);
+    }
+  }
+}
+
 // Number of eigenvalues of the scaled T below x: sign changes of the leading
 // minors p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}, rescaled by a power of two
-// every four steps.  An exact zero minor takes the sign opposite to the one
-// before it.  The diagonal is padded to lq (a multiple of four) with 4 > |x|
-// and e = 0, which changes no count; the loads of the next four steps are
-// issued before the current four are computed.
-__device__ __forceinline__ int sturm_count(const double* __restrict__ ds, const double* __restrict__ e2p, int lq,
-                                           double x) {
+// every four steps.  A zero minor counts as non-negative: with e_i^2 > 0 the
+// minor after it is -e_i^2 times the one before it, so exactly one sign change
+// falls on the pair around the zero whichever sign the zero is given.  The
+// recurrence runs over whole blocks of 16 (nblk of them); past l the diagonal
+// holds 4 > |x|, which changes no count.
+template <int NB>
+__device__ __forceinline__ int sturm_count(const TriReg<NB>& dr, const TriReg<NB>& e2r, int nblk, double x) {
   double pm2 = 0.0, pm1 = 1.0;
   int cnt = 0;
-  dbl2 da = ld2(ds), db = ld2(ds + 2), ea = ld2(e2p), eb = ld2(e2p + 2);
-  for (int ib = 0; ib < lq; ib += 4) {
-    const int nb = ib + 4 < lq ? ib + 4 : ib;
-    const dbl2 nda = ld2(ds + nb), ndb = ld2(ds + nb + 2), nea = ld2(e2p + nb), neb = ld2(e2p + nb + 2);
-    const double dd[4] = {da.x, da.y, db.x, db.y}, ee[4] = {ea.x, ea.y, eb.x, eb.y};
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      double pi = fma(dd[u] - x, pm1, -ee[u] * pm2);
-      pi = pi == 0.0 ? -0x1p-60 * pm1 : pi;
+  for (int b = 0; b < NB; ++b) {
+    if (b >= nblk) break;
+    for16<0>([&](auto ci) {
+      constexpr int c = decltype(ci)::value;
+      const double pi = fma(eig_bcast<c>(dr.r[b]) - x, pm1, -eig_bcast<c>(e2r.r[b]) * pm2);
       cnt += (pi < 0.0) != (pm1 < 0.0) ? 1 : 0;
       pm2 = pm1;
       pm1 = pi;
-    }
-    const int ex = __builtin_amdgcn_frexp_exp(pm1);
-    pm1 = __builtin_amdgcn_ldexp(pm1, -ex);
-    pm2 = __builtin_amdgcn_ldexp(pm2, -ex);
-    da = nda;
-    db = ndb;
-    ea = nea;
-    eb = neb;
+      if constexpr (c % 4 == 3) {
+        const int ex = __builtin_amdgcn_frexp_exp(pm1);
+        pm1 = __builtin_amdgcn_ldexp(pm1, -ex);
+        pm2 = __builtin_amdgcn_ldexp(pm2, -ex);
+      }
+    });
   }
   return cnt;
 }
@@ -356,11 +391,15 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
     es[i] = __builtin_amdgcn_ldexp(es[i], -tex);
   }
   __syncthreads();
-  for (int i = tid; i < MAXL; i += 256) e2p[i] = i > 0 ? es[i - 1] * es[i - 1] : 0.0;
+  // e^2 floored at 2^-200 (eigenvalues move by at most 2^-100 of ||T||): no
+  // coupling is exactly zero, so a zero minor is always followed by a nonzero one
+  for (int i = tid; i < MAXL; i += 256) e2p[i] = i > 0 ? fmax(es[i - 1] * es[i - 1], 0x1p-200) : 0.0;
   __syncthreads();
-  const int lq = (l + 3) & ~3;  // the recurrences run over whole blocks of four
   const int j = 4 * bid + wv;
   if (j >= l) return;
+  constexpr int NB = MAXL / 16;
+  const int nblk = (l + 15) >> 4;  // the recurrences run over whole blocks of 16
+  const TriReg<NB> dr = tri_load<NB>(ds, lane), er = tri_load<NB>(es, lane), e2r = tri_load<NB>(e2p, lane);
   if (bid == 0 && tid == 0) p.tnorm[0] = tnorm;
 
   // 1. bisection for the (l - 1 - j)-th smallest eigenvalue of the scaled T
@@ -382,7 +421,7 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
   for (int round = 0; round < 9; ++round) {
     const double wdt = hi - lo;
     const double x = fma(wdt, frac, lo);
-    const int cnt = tnorm > 0.0 ? sturm_count(ds, e2p, lq, x) : (x > 0.0 ? l : 0);
+    const int cnt = tnorm > 0.0 ? sturm_count<NB>(dr, e2r, nblk, x) : (x > 0.0 ? l : 0);
     const uint64_t mask = __ballot(cnt <= jasc);
     const int m = __popcll(mask) - 1;  // last point at or below the eigenvalue
     const double nlo = m >= 0 ? fma(wdt, (double)(m + 1) * (1.0 / 65.0), lo) : lo;
@@ -400,83 +439,77 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
   bool flagged = !(fabs(mu) > 64.0 * DBL_EPSILON);
   for (int i = lane; i < MAXL; i += 64) x[i] = i < l ? start_value(j, i) : 0.0;
   if (!flagged) {
-    // LDL^T of the scaled T - mu I over lq (the padding rows decouple: e = 0), tiny
-    // pivots lifted to +-2^-62; every lane runs the recurrence and stores the same
-    // values.  Loads run four steps ahead.
+    // LDL^T of the scaled T - mu I over whole blocks of 16 (the rows past l
+    // decouple: e = 0), tiny pivots lifted to +-2^-62.  Every lane runs the
+    // recurrences and stores the same values; each pass reads its inputs from
+    // registers and the next pass reloads its outputs from LDS.
     const double ptol = 0x1p-62;
-    double inv = 0.0, eprev = 0.0;
-    dbl2 da = ld2(ds), db = ld2(ds + 2), ea = ld2(es), eb = ld2(es + 2);
-    for (int ib = 0; ib < lq; ib += 4) {
-      const int nb = ib + 4 < lq ? ib + 4 : ib;
-      const dbl2 nda = ld2(ds + nb), ndb = ld2(ds + nb + 2), nea = ld2(es + nb), neb = ld2(es + nb + 2);
-      const double dd[4] = {da.x, da.y, db.x, db.y}, ee[4] = {ea.x, ea.y, eb.x, eb.y};
-      double li4[4], iv4[4];
+    {
+      double inv = 0.0, eprev = 0.0, li4[4], iv4[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double li = eprev * inv;  // 0 at i = 0 (eprev = 0)
-        double D = fma(-li, eprev, dd[u] - mu);
-        D = fabs(D) < ptol ? (D < 0.0 ? -ptol : ptol) : D;
-        inv = rcp_refined(D);
-        li4[u] = li;
-        iv4[u] = inv;
-        eprev = ee[u];
+      for (int b = 0; b < NB; ++b) {
+        if (b >= nblk) break;
+        for16<0>([&](auto ci) {
+          constexpr int c = decltype(ci)::value;
+          const double li = eprev * inv;  // 0 at i = 0 (eprev = 0)
+          double D = fma(-li, eprev, eig_bcast<c>(dr.r[b]) - mu);
+          D = fabs(D) < ptol ? (D < 0.0 ? -ptol : ptol) : D;
+          inv = rcp_refined(D);
+          li4[c % 4] = li;
+          iv4[c % 4] = inv;
+          eprev = eig_bcast<c>(er.r[b]);
+          if constexpr (c % 4 == 3) {
+            const int i0 = 16 * b + c - 3;
+            *reinterpret_cast<dbl2*>(iD + i0) = dbl2{iv4[0], iv4[1]};
+            *reinterpret_cast<dbl2*>(iD + i0 + 2) = dbl2{iv4[2], iv4[3]};
+            *reinterpret_cast<dbl2*>(L + i0) = dbl2{li4[0], li4[1]};
+            *reinterpret_cast<dbl2*>(L + i0 + 2) = dbl2{li4[2], li4[3]};
+          }
+        });
       }
-      *reinterpret_cast<dbl2*>(iD + ib) = dbl2{iv4[0], iv4[1]};
-      *reinterpret_cast<dbl2*>(iD + ib + 2) = dbl2{iv4[2], iv4[3]};
-      *reinterpret_cast<dbl2*>(L + ib) = dbl2{li4[0], li4[1]};
-      *reinterpret_cast<dbl2*>(L + ib + 2) = dbl2{li4[2], li4[3]};
-      da = nda;
-      db = ndb;
-      ea = nea;
-      eb = neb;
     }
+    const TriReg<NB> Lr = tri_load<NB>(L, lane), iDr = tri_load<NB>(iD, lane);
     for (int it = 0; it < 2; ++it) {
       // L y = x (forward), then D L^T x = y (backward), in place
-      double y = 0.0;
-      dbl2 la = ld2(L), lb = ld2(L + 2), xa = ld2(x), xb = ld2(x + 2);
-      for (int ib = 0; ib < lq; ib += 4) {
-        const int nb = ib + 4 < lq ? ib + 4 : ib;
-        const dbl2 nla = ld2(L + nb), nlb = ld2(L + nb + 2), nxa = ld2(x + nb), nxb = ld2(x + nb + 2);
-        const double ll[4] = {la.x, la.y, lb.x, lb.y}, xx[4] = {xa.x, xa.y, xb.x, xb.y};
-        double yy[4];
+      {
+        const TriReg<NB> xr = tri_load<NB>(x, lane);
+        double y = 0.0, y4[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          y = fma(-ll[u], y, xx[u]);  // L[0] = 0
-          yy[u] = y;
+        for (int b = 0; b < NB; ++b) {
+          if (b >= nblk) break;
+          for16<0>([&](auto ci) {
+            constexpr int c = decltype(ci)::value;
+            y = fma(-eig_bcast<c>(Lr.r[b]), y, eig_bcast<c>(xr.r[b]));  // L[0] = 0
+            y4[c % 4] = y;
+            if constexpr (c % 4 == 3) {
+              const int i0 = 16 * b + c - 3;
+              *reinterpret_cast<dbl2*>(x + i0) = dbl2{y4[0], y4[1]};
+              *reinterpret_cast<dbl2*>(x + i0 + 2) = dbl2{y4[2], y4[3]};
+            }
+          });
         }
-        *reinterpret_cast<dbl2*>(x + ib) = dbl2{yy[0], yy[1]};
-        *reinterpret_cast<dbl2*>(x + ib + 2) = dbl2{yy[2], yy[3]};
-        la = nla;
-        lb = nlb;
-        xa = nxa;
-        xb = nxb;
       }
-      // x_i = y_i / D_i - L_{i+1} x_{i+1}, from i = lq - 1 down (L[lq] taken as 0)
-      double xn = 0.0, lnext = 0.0;
-      int ib = lq - 4;
-      dbl2 ya = ld2(x + ib), yb = ld2(x + ib + 2), va = ld2(iD + ib), vb = ld2(iD + ib + 2), la2 = ld2(L + ib),
-           lb2 = ld2(L + ib + 2);
-      for (; ib >= 0; ib -= 4) {
-        const int nb = ib >= 4 ? ib - 4 : ib;
-        const dbl2 nya = ld2(x + nb), nyb = ld2(x + nb + 2), nva = ld2(iD + nb), nvb = ld2(iD + nb + 2),
-                   nla = ld2(L + nb), nlb = ld2(L + nb + 2);
-        const double yv[4] = {ya.x, ya.y, yb.x, yb.y}, iv[4] = {va.x, va.y, vb.x, vb.y},
-                     lv[4] = {la2.x, la2.y, lb2.x, lb2.y};
-        double xo[4];
+      // x_i = y_i / D_i - L_{i+1} x_{i+1}, from the last row of the last block down
+      // (L past it taken as 0)
+      {
+        const TriReg<NB> yr = tri_load<NB>(x, lane);
+        double xn = 0.0, lnext = 0.0, x4[4];
 #pragma unroll
-        for (int u = 3; u >= 0; --u) {
-          xn = fma(-lnext, xn, yv[u] * iv[u]);
-          xo[u] = xn;
-          lnext = lv[u];
+        for (int bb = 0; bb < NB; ++bb) {
+          const int b = NB - 1 - bb;
+          if (b >= nblk) continue;
+          for16<0, true>([&](auto ci) {
+            constexpr int c = decltype(ci)::value;
+            xn = fma(-lnext, xn, eig_bcast<c>(yr.r[b]) * eig_bcast<c>(iDr.r[b]));
+            x4[c % 4] = xn;
+            lnext = eig_bcast<c>(Lr.r[b]);
+            if constexpr (c % 4 == 0) {
+              const int i0 = 16 * b + c;
+              *reinterpret_cast<dbl2*>(x + i0) = dbl2{x4[0], x4[1]};
+              *reinterpret_cast<dbl2*>(x + i0 + 2) = dbl2{x4[2], x4[3]};
+            }
+          });
         }
-        *reinterpret_cast<dbl2*>(x + ib) = dbl2{xo[0], xo[1]};
-        *reinterpret_cast<dbl2*>(x + ib + 2) = dbl2{xo[2], xo[3]};
-        ya = nya;
-        yb = nyb;
-        va = nva;
-        vb = nvb;
-        la2 = nla;
-        lb2 = nlb;
       }
       double s = 0.0;
       for (int i = lane; i < l; i += 64) s = fma(x[i], x[i], s);
