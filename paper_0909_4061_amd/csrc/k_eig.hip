@@ -605,16 +605,17 @@ __device__ __forceinline__ void tri_eig_body(const EigParams& p, const int bid) 
 // eig_fix: one workgroup of 256 threads.  Column c of Zs holds eigenvector c.
 template <int MAXL>
 __device__ __forceinline__ void eig_fix_body(const EigParams& p) {
-  constexpr int LDZ = MAXL + 1;
-  __shared__ double Zs[MAXL * LDZ];  // Zs[c * LDZ + i] = component i of vector c
-  __shared__ double coef[MAXL];
+  constexpr int LDZ = MAXL + 2;       // even: 16-byte aligned columns
+  constexpr int HALF = MAXL / 2;
+  __shared__ __attribute__((aligned(16))) double Zs[MAXL * LDZ];  // Zs[c * LDZ + i] = component i of vector c (0 past l)
+  __shared__ __attribute__((aligned(16))) double coef[MAXL];
   __shared__ int todo[MAXL];         // 0 keep, 1 cluster member after the first, 2 flagged
   __shared__ int clu0[MAXL];         // first member of the vector's cluster
   __shared__ double lam_s[MAXL];
   __shared__ int any_s;
   __shared__ double red[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int l = p.l, half = (l + 1) >> 1;
+  const int l = p.l;
   for (int j = tid; j < l; j += 256) {
     lam_s[j] = p.lam[j];
     todo[j] = p.flag[j];
@@ -638,9 +639,9 @@ __device__ __forceinline__ void eig_fix_body(const EigParams& p) {
   }
   __syncthreads();
   if (!any_s) return;
-  for (int idx = tid; idx < l * l; idx += 256) {
-    const int c = idx / l, i = idx - c * l;
-    Zs[c * LDZ + i] = p.Z[(int64_t)c * l + i];
+  for (int idx = tid; idx < MAXL * MAXL; idx += 256) {
+    const int c = idx / MAXL, i = idx - c * MAXL;
+    Zs[c * LDZ + i] = (c < l && i < l) ? p.Z[(int64_t)c * l + i] : 0.0;
   }
   __syncthreads();
   // phase 1 (clusters, flagged columns left out), then phase 2 (flagged columns)
@@ -658,18 +659,36 @@ __device__ __forceinline__ void eig_fix_body(const EigParams& p) {
               if (phase == 1) use = c >= clu0[j] && c < j && todo[c] != 2;
               else use = c != j && (todo[c] != 2 || c < j);
             }
-            double s = 0.0;
-            if (use)
-              for (int i = h * half; i < min(l, (h + 1) * half); ++i) s = fma(Zs[c * LDZ + i], Zs[j * LDZ + i], s);
+            // (fixed trip count over the padded half, four partial sums, 16-byte reads)
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+            if (use) {
+              const double* zc = Zs + c * LDZ + h * HALF;
+              const double* zj = Zs + j * LDZ + h * HALF;
+#pragma unroll
+              for (int q = 0; q < HALF; q += 2) {
+                const dbl2 x = *reinterpret_cast<const dbl2*>(zc + q), y = *reinterpret_cast<const dbl2*>(zj + q);
+                s4[q & 2] = fma(x.x, y.x, s4[q & 2]);
+                s4[(q & 2) + 1] = fma(x.y, y.y, s4[(q & 2) + 1]);
+              }
+            }
+            double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             s += eig_dpp<0xB1>(s);  // quad_perm [1,0,3,2]: the partner's half
             if (c < MAXL && h == 0) coef[c] = s;
           }
           __syncthreads();
           {
             const int i = tid >> 1, h = tid & 1;
-            double s = 0.0;
-            if (i < l)
-              for (int c = h * half; c < min(l, (h + 1) * half); ++c) s = fma(-coef[c], Zs[c * LDZ + i], s);
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};  // coef is zero for the columns not used
+            if (i < l) {
+#pragma unroll
+              for (int q = 0; q < HALF; q += 2) {
+                const int c = h * HALF + q;
+                const dbl2 cf = *reinterpret_cast<const dbl2*>(coef + c);
+                s4[q & 2] = fma(-cf.x, Zs[c * LDZ + i], s4[q & 2]);
+                s4[(q & 2) + 1] = fma(-cf.y, Zs[(c + 1) * LDZ + i], s4[(q & 2) + 1]);
+              }
+            }
+            double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             s += eig_dpp<0xB1>(s);
             __syncthreads();  // every thread has read column j for its coefficient before it changes
             if (i < l && h == 0) Zs[j * LDZ + i] += s;
