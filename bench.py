@@ -35,10 +35,10 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the streaming GEMMs (scaled FETCH_SIZE + WRITE_SIZE from rocprofv3
 # counter runs, profiles/stream_gemm_power_iteration_16384x8192_hbm_counters.md), valid only for
 # the kernel source they were measured on and the 16384 x 8192, l = 120 shape.
-TRAFFIC_KERNEL_SHA = "2d8512d5f3de71f7"
+# (The FP32-product kernels were not counted for this source: their traffic is reported as null.)
+TRAFFIC_KERNEL_SHA = "c2f37a66479cb19d"
 TRAFFIC_SHAPE = (16384, 8192, 120)
-TRAFFIC_BYTES = {"stream_tn_bf16x3": 579479555, "stream_nn_bf16x3": 579886875,
-                 "stream_tn_native": 579488361, "stream_nn_native": 579707277}
+TRAFFIC_BYTES = {"stream_tn_bf16x3": 583809978, "stream_nn_bf16x3": 579173204}
 # The same for the SRFT row-FFT kernel at 32768 x 16384, l = 128
 # (profiles/srft_sketch_32768x16384_hbm_counters.md).
 SRFT_TRAFFIC_SHA = "2b16782d46e9052b"
