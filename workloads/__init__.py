@@ -16,5 +16,5 @@ spectra that decay fast (exponential), slowly (1/j, j^-1/2) or have a gap.
 
 from .matrices import (  # noqa: F401
     CONFIGS, Config, spectrum, haar_factor, build_matrix, build_matrix_torch,
-    batch_shapes, grad_targets, SEED,
+    batch_shapes, grad_targets, SEED, build_symmetric, build_psd_torch,
 )

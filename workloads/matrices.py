@@ -166,3 +166,53 @@ def grad_targets(m, n, k, seed=SEED, index=0):
     gT = _rng(seed + index, STREAM_T)
     gW = _rng(seed + index, STREAM_W)
     return gT.standard_normal((m, n)), gW.uniform(0.0, 1.0, size=k)
+
+
+STREAM_SYM = 7
+
+
+def build_symmetric(n, lam, seed=SEED, dtype=np.float64, return_factors=False):
+    """A = V diag(lam) V^T (n x n, symmetric) in FP64, then rounded to `dtype`, on the CPU.
+
+    V (n x r, r = len(lam) <= n) is the Q factor (diag(R) > 0) of a seeded standard
+    Gaussian matrix, so the nonzero eigenvalues of A are exactly lam in exact
+    arithmetic (any signs; all lam >= 0 gives a positive semidefinite A).  The
+    FP64 product is replaced by its symmetric part before rounding, so A is
+    exactly symmetric in `dtype`.
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    V = haar_factor(n, lam.size, seed, STREAM_SYM)
+    A = (V * lam[None, :]) @ V.T
+    A = (0.5 * (A + A.T)).astype(dtype)
+    if return_factors:
+        return A, V
+    return A
+
+
+def build_psd_torch(n, lam, shift, seed=SEED, dtype=None, device="cuda"):
+    """A = V diag(lam) V^T + shift I (n x n, positive semidefinite for lam, shift >= 0) on a GPU.
+
+    For the large configurations: V is n x r with r = len(lam) (a thin Q factor of
+    a seeded Gaussian matrix from torch's generator, diag(R) > 0), so the
+    eigenvalues are lam + shift (r of them) and shift (the other n - r).  Built
+    in FP64, symmetrized, rounded to `dtype`.  Returns a torch tensor.
+    """
+    import torch
+
+    dtype = dtype or torch.float32
+    lam_t = torch.as_tensor(np.asarray(lam, dtype=np.float64), device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed((seed * 1000003 + STREAM_SYM) & 0x7FFFFFFFFFFFFFFF)
+    G = torch.randn(n, lam_t.numel(), generator=gen, device=device, dtype=torch.float64)
+    V, R = torch.linalg.qr(G, mode="reduced")
+    del G
+    s = torch.sign(torch.diagonal(R))
+    s[s == 0] = 1.0
+    V = V * s[None, :]
+    A = torch.matmul(V * lam_t[None, :], V.T)
+    del V
+    A.diagonal().add_(shift)
+    A = 0.5 * (A + A.T)
+    out = A.to(dtype)
+    del A
+    return out
