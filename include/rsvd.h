@@ -233,6 +233,38 @@ rsvd_status rsvd_range_finder_tol(rsvd_handle handle, const rsvd_problem* proble
                                   const void* A, void* Q, int32_t* l_out, double* est_out, void* ws,
                                   size_t ws_bytes, hipStream_t stream);
 
+/* --- Stage B for symmetric and positive semidefinite A ------------------- */
+
+/* Both calls take the problem with m == n (A is n x n, row-major, leading
+ * dimension lda) and a basis Q (n x l, l = k + p, row-major with leading
+ * dimension l, orthonormal columns: the output of rsvd_range_finder or
+ * rsvd_power_iter); problem->prec sets the arithmetic of the product A Q, the
+ * only pass over A; q, sketch, seed and stream_id are not used.  Workspace:
+ * rsvd_workspace_bytes(problem).  Outputs, DEVICE buffers in the element type:
+ * U (n x k, row-major, leading dimension k) and Lam (k).  Errors as for the
+ * hot-path calls; m != n is RSVD_E_INVAL.
+ *
+ * rsvd_eigh: Algorithm 5.3 (direct eigenvalue decomposition, Section 5.3) for
+ * symmetric A: B = Q^T A Q (l x l, replaced by its symmetric part), its
+ * eigendecomposition B = V Lambda V^T, U = Q V.  The k eigenpairs of largest
+ * |lambda| are kept, in decreasing order of |lambda| (equal magnitudes: the
+ * positive one first); Lam holds the signed eigenvalues.  With k = l,
+ * ||A - U Lam U^T|| <= 2 ||A - Q Q^T A|| (Section 5.3).
+ *
+ * rsvd_nystrom: Algorithm 5.5 (eigenvalue decomposition via the Nystrom
+ * method, Section 5.4) for positive semidefinite A: B1 = A Q, B2 = Q^T B1 (its
+ * symmetric part) = C^T C (Cholesky, C upper triangular), F = B1 C^-1,
+ * F = U Sigma V^T, Lam = Sigma^2 (the k largest, decreasing).  B2 must be
+ * positive definite to working precision (the l-th eigenvalue of A above the
+ * rounding of the product A Q, about sqrt(n) u ||A|| for element precision u):
+ * otherwise the Cholesky factorization is restarted on B2 + s I with the
+ * shifted-CholeskyQR shift and RSVD_FLAG_SHIFTED is raised in the device
+ * status word, and the result is that of the shifted core. */
+rsvd_status rsvd_eigh(rsvd_handle handle, const rsvd_problem* problem, const void* A, const void* Q, void* U,
+                      void* Lam, void* ws, size_t ws_bytes, hipStream_t stream);
+rsvd_status rsvd_nystrom(rsvd_handle handle, const rsvd_problem* problem, const void* A, const void* Q, void* U,
+                         void* Lam, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Size of the device array that rsvd_full_static uses as its workspace. */
 #define RSVD_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
 

@@ -9,8 +9,10 @@ names:
     rsvd_power_iter(A, Q, k, p, q, ...)  -> Q       Stage A, q power steps (in place)
     rsvd_project(A, Q, k, p, ...)        -> Bt      Stage B step 1 (Bt = B^T, n x l)
     rsvd_svd(Bt, Q, k, p, ...)           -> U, S, V Stage B steps 2-3 + truncation
+    rsvd_eigh(A, Q, k, ...)              -> U, Lam  Stage B for symmetric A (Algorithm 5.3)
+    rsvd_nystrom(A, Q, k, ...)           -> U, Lam  Stage B for psd A (Algorithm 5.5)
 
-and rsvd(A, k, p, q, ...) runs all four.  If the library is missing the import
+and rsvd(A, k, p, q, ...) runs the first four.  If the library is missing the import
 of any of these raises; there is no other implementation.
 """
 
@@ -172,6 +174,35 @@ def rsvd_svd(Bt, Q, m, n, k, p, *, q=0, dtype=torch.float32, sketch="gaussian", 
     _lib.check(h.lib.rsvd_svd(h.ptr, ctypes.byref(pr), _ptr(Bt), _ptr(Q), _ptr(U), _ptr(S), _ptr(V), ws.ptr,
                               ws.nbytes, _stream(dev)), "rsvd_svd")
     return U, S, V
+
+
+def _herm(fn, A, Q, k, p, prec, U, Lam, ws):
+    n = A.shape[0]
+    if A.dim() != 2 or A.shape[1] != n:
+        raise ValueError(f"{fn}: A must be square, got {tuple(A.shape)}")
+    pr = problem(n, n, k, p, 0, dtype=A.dtype, prec=prec)
+    dev = A.device
+    if U is None:
+        U = torch.empty(n, k, dtype=A.dtype, device=dev)
+    if Lam is None:
+        Lam = torch.empty(k, dtype=A.dtype, device=dev)
+    ws = ws or Workspace(pr, dev)
+    h = handle(dev)
+    _lib.check(getattr(h.lib, fn)(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(Q), _ptr(U), _ptr(Lam), ws.ptr,
+                                  ws.nbytes, _stream(dev)), fn)
+    return U, Lam
+
+
+def rsvd_eigh(A, Q, k, *, prec="native", U=None, Lam=None, ws=None):
+    """Algorithm 5.3 for symmetric A (n x n) and a basis Q (n x l, l = Q.shape[1] >= k): the k
+    eigenpairs of largest |lambda| of Q^T A Q, lifted by Q.  Returns (U (n x k), Lam (k,))."""
+    return _herm("rsvd_eigh", A, Q, k, Q.shape[1] - k, prec, U, Lam, ws)
+
+
+def rsvd_nystrom(A, Q, k, *, prec="native", U=None, Lam=None, ws=None):
+    """Algorithm 5.5 (Nystrom) for positive semidefinite A (n x n) and a basis Q (n x l):
+    returns (U (n x k), Lam (k,)) with U Lam U^T the rank-k part of (AQ)(Q^T A Q)^-1 (AQ)^T."""
+    return _herm("rsvd_nystrom", A, Q, k, Q.shape[1] - k, prec, U, Lam, ws)
 
 
 def _check_differentiable(sketch):

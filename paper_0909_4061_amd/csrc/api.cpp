@@ -137,6 +137,9 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   int64_t part_elems = 0;
   if (P.nn.S > 1) part_elems = std::max(part_elems, (int64_t)P.nn.S * P.m * P.Lp);
   if (P.tn.S > 1) part_elems = std::max(part_elems, (int64_t)P.tn.S * P.n * P.Lp);
+  // the l x l product Q^T (A Q) of the symmetric Stage B: at most 16 K chunks of
+  // l rows x 128 columns
+  if (!batched) part_elems = std::max(part_elems, (int64_t)16 * P.l * 128);
   const size_t es = (size_t)P.esize;
   const size_t ll8 = (size_t)P.l * P.l * 8;
   size_t off = 0;
@@ -165,9 +168,10 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   P.flags = take(64);
   P.srft_d = take(pr->sketch == RSVD_SRFT ? (size_t)P.n * 8 : 0);
   P.srft_R = take(pr->sketch == RSVD_SRFT ? (size_t)P.l * 4 : 0);
-  // eigensolver of the small SVD (FP32 data): reflectors, eigenvectors, then
-  // d, e, tau, the eigenvalues, the norm bound and the flags
-  const bool eig = pr->dtype == RSVD_F32;
+  // eigensolver of the small SVD (FP32 data) and of the symmetric Stage B (a
+  // single problem of either type): reflectors, eigenvectors, then d, e, tau,
+  // the eigenvalues, the norm bound and the flags
+  const bool eig = pr->dtype == RSVD_F32 || !batched;
   P.eigV = take(eig ? (size_t)P.l * EIG_LDV * 8 : 0);
   P.eigZ = take(eig ? ll8 : 0);
   P.eigT = take(eig ? (size_t)(4 * P.l + 1) * 8 + (size_t)P.l * 4 : 0);
@@ -784,6 +788,87 @@ rsvd_status gemm_tn_splitk_into(const Ctx& c, void* part_buf, const void* A, int
   g.l = ncols;
   if (sp.S > 1 || c.run->records()) RSVD_TRY(c.run->sum_parts(c.P.dtype, g));
   return RSVD_OK;
+}
+
+// The eigensolver of an l x l symmetric matrix held in G (FP64 upper triangle):
+// tridiagonalization, eigenpairs, cluster fix-up.  Outputs in the plan's Uh,
+// sig, XU, XV (value order, the first k); S (k, element type) is scratch here.
+EigParams eig_params(const Ctx& c, void* S) {
+  const Plan& P = c.P;
+  EigParams e{};
+  e.G = c.at<double>(P.G);
+  e.Lg = P.Lg;
+  e.l = (int32_t)P.l;
+  e.k = (int32_t)P.k;
+  e.dtype = P.dtype;
+  e.V = c.at<double>(P.eigV);
+  e.Z = c.at<double>(P.eigZ);
+  double* t = c.at<double>(P.eigT);
+  e.tri = t;
+  e.lam = t + 3 * P.l;
+  e.tnorm = t + 4 * P.l;
+  e.flag = reinterpret_cast<int32_t*>(t + 4 * P.l + 1);
+  e.Uh = c.at<double>(P.Uh);
+  e.sig = c.at<double>(P.sig);
+  e.XU = c.at<void>(P.XU);
+  e.XV = c.at<void>(P.XV);
+  e.S = S;
+  e.status = c.status;
+  return e;
+}
+
+// Algorithm 5.3 (nystrom == false) and Algorithm 5.5 (nystrom == true) for a
+// symmetric / psd n x n A and a basis Q (n x l).  Single problems only.
+rsvd_status herm_steps(const Ctx& c, const rsvd_problem* pr, const void* A, const void* Q, void* U, void* Lam,
+                       bool nystrom) {
+  const Plan& P = c.P;
+  if (c.run->records()) return RSVD_E_UNSUPPORTED;
+  const int64_t n = P.n, l = P.l;
+  void* y = c.at<void>(P.Y);
+  // B1 = A Q (n x l): the one pass over A
+  rsvd_status s = gemm(c, pr->prec, false, A, pr->lda, n, n, Q, l, (int32_t)l, y, l, P.nn,
+                       P.nn.S > 1 ? c.at<void>(P.part) : nullptr, nullptr, true);
+  if (s != RSVD_OK) return s;
+  s = reduce_parts(c, P.nn, n, y);
+  if (s != RSVD_OK) return s;
+  // B = Q^T B1 (l x l, element type, into the RinvT region), its symmetric part into G
+  void* B = c.at<void>(P.RinvT);
+  s = gemm_tn_splitk_into(c, c.at<void>(P.part), Q, l, l, n, y, l, (int32_t)l, B, l);
+  if (s != RSVD_OK) return s;
+  {
+    Timed t_(c.h, RSVD_KERNEL_EIG, c.st);
+    RSVD_TRY(launch_sym_gram(SymGramParams{B, P.dtype, (int32_t)l, (int32_t)l, P.Lg, c.at<double>(P.G)}, c.st));
+  }
+  EigParams e = eig_params(c, Lam);
+  EigPickParams pick{e.lam, e.Uh, e.sig, (int32_t)l, (int32_t)P.k, nystrom ? 0 : 1, P.dtype, Lam, nullptr};
+  if (!nystrom) {
+    // B = V Lambda V^T; the k of largest |lambda| and their vectors; U = Q V_k
+    for (int stage = 0; stage < 3; ++stage) RSVD_TRY(c.run->eig(stage, e));
+    pick.XU = c.at<void>(P.XU);
+    {
+      Timed t_(c.h, RSVD_KERNEL_EIG, c.st);
+      RSVD_TRY(launch_eig_pick(pick, c.st));
+    }
+    return gemm(c, RSVD_NATIVE, false, Q, l, n, l, pick.XU, P.k, (int32_t)P.k, U, P.k, no_split(l), nullptr,
+                nullptr);
+  }
+  // B2 = C^T C (C = R, upper; shifted when B2 is not positive definite to working
+  // precision), F = B1 C^-1 in place of B1
+  s = chol(c, n, nullptr, true, nullptr, c.shift_flag(), true);
+  if (s != RSVD_OK) return s;
+  s = gemm(c, RSVD_NATIVE, false, y, l, n, l, c.at<void>(P.RinvT), l, (int32_t)l, y, l, no_split(l), nullptr,
+           nullptr);
+  if (s != RSVD_OK) return s;
+  // F = U Sigma V^T from the FP64 Gram F^T F = V Sigma^2 V^T: U = F V Sigma^-1 (XV), Lam = Sigma^2
+  s = gram(c, false, no_split(1), y, n, nullptr);
+  if (s != RSVD_OK) return s;
+  for (int stage = 0; stage < 3; ++stage) RSVD_TRY(c.run->eig(stage, e));
+  {
+    Timed t_(c.h, RSVD_KERNEL_EIG, c.st);
+    RSVD_TRY(launch_eig_pick(pick, c.st));
+  }
+  return gemm(c, RSVD_NATIVE, false, y, l, n, l, c.at<void>(P.XV), P.k, (int32_t)P.k, U, P.k, no_split(l), nullptr,
+              nullptr);
 }
 
 rsvd_status gemm_tn_splitk(const Ctx& c, const BwdLayout& L, const void* A, int64_t lda, int64_t rows, int64_t K,
@@ -1871,6 +1956,27 @@ rsvd_status rsvd_svd(rsvd_handle h, const rsvd_problem* pr, const void* Bt, cons
   DirectRunner dr(h, stream);
   const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
   return svd_steps(c, Bt, Q, U, S, V);
+}
+
+static rsvd_status herm_call(rsvd_handle h, const rsvd_problem* pr, const void* A, const void* Q, void* U,
+                             void* Lam, void* ws, size_t ws_bytes, hipStream_t stream, bool nystrom) {
+  if (pr && pr->m != pr->n) return RSVD_E_INVAL;
+  Prologue pro = prologue(h, pr, ws, ws_bytes);
+  if (pro.status != RSVD_OK) return pro.status;
+  if (!A || !Q || !U || !Lam) return RSVD_E_INVAL;
+  DirectRunner dr(h, stream);
+  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
+  return herm_steps(c, pr, A, Q, U, Lam, nystrom);
+}
+
+rsvd_status rsvd_eigh(rsvd_handle h, const rsvd_problem* pr, const void* A, const void* Q, void* U, void* Lam,
+                      void* ws, size_t ws_bytes, hipStream_t stream) {
+  return herm_call(h, pr, A, Q, U, Lam, ws, ws_bytes, stream, false);
+}
+
+rsvd_status rsvd_nystrom(rsvd_handle h, const rsvd_problem* pr, const void* A, const void* Q, void* U, void* Lam,
+                         void* ws, size_t ws_bytes, hipStream_t stream) {
+  return herm_call(h, pr, A, Q, U, Lam, ws, ws_bytes, stream, true);
 }
 
 size_t rsvd_full_workspace_bytes(const rsvd_problem* problem) {

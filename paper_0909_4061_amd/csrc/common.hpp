@@ -191,6 +191,34 @@ hipError_t launch_eig(int stage, const EigParams& p, hipStream_t st);
 hipError_t launch_eig_batched(int stage, int variant, const EigParams* ps, const BlockMap* bm, int64_t nblocks,
                               hipStream_t st);
 
+// Stage B for symmetric / psd A (k_sym.hip).  sym_gram: G (FP64, upper
+// triangle, stride Lg) = (B + B^T) / 2 of an l x l matrix B (element type,
+// row stride ldb).  eig_pick: the k kept eigenpairs of an eigensolver run
+// (lam descending by value, Uh[i * l + j] = component i of eigenvector j):
+// by magnitude (Lam = lambda, XU = the matching columns, l x k) or by value
+// (Lam = sig^2 for the first k).
+struct SymGramParams {
+  const void* B;
+  int32_t dtype;
+  int32_t l;
+  int32_t ldb;
+  int32_t Lg;
+  double* G;
+};
+struct EigPickParams {
+  const double* lam;
+  const double* Uh;
+  const double* sig;
+  int32_t l;
+  int32_t k;
+  int32_t by_magnitude;
+  int32_t dtype;
+  void* Lam;  // k, element type
+  void* XU;   // l x k, element type (magnitude order only; may be null)
+};
+hipError_t launch_sym_gram(const SymGramParams& p, hipStream_t st);
+hipError_t launch_eig_pick(const EigPickParams& p, hipStream_t st);
+
 struct GramReduceParams {
   const double* gpart;
   int64_t nblk;

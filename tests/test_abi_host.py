@@ -116,6 +116,13 @@ def test_null_arguments_fail_before_launch(lib):
     assert lib.rsvd_profile_select(None, 0) == 1
     assert lib.rsvd_profile_read(None, None, None) == 1
     assert lib.rsvd_create(None, 0) == 1
+    # symmetric Stage B: no handle, and a non-square problem, are refused on the host
+    sq = _prob(m=500, n=500)
+    assert lib.rsvd_eigh(None, ctypes.byref(sq), None, None, None, None, None, 0, None) == 1
+    assert lib.rsvd_nystrom(None, ctypes.byref(sq), None, None, None, None, None, 0, None) == 1
+    rect = _prob(m=600, n=500)
+    assert lib.rsvd_eigh(None, ctypes.byref(rect), None, None, None, None, None, 0, None) == 1
+    assert lib.rsvd_nystrom(None, ctypes.byref(rect), None, None, None, None, None, 0, None) == 1
 
 
 def test_batched_workspace_and_validation(lib):
