@@ -273,6 +273,81 @@ def workload_srft(args, A, sigma):
     return line
 
 
+def workload_psd(args):
+    """Stage B for a positive semidefinite A (Algorithm 5.3 direct eigendecomposition, Algorithm 5.5
+    Nystrom) on an FP32 16384 x 16384 matrix: A = V diag(lam) V^T + 1e-4 I with lam_j = 1/j for
+    j <= 4096 (V a thin Haar basis), k = 100, p = 20, Q from the range finder with q = 1.  Each
+    Stage B call reads A once (the product A Q); it is timed alone, with its A Q launch."""
+    import numpy as np
+    import torch
+    import paper_0909_4061_amd as rs
+    from workloads import build_psd_torch
+
+    n, k, p, q, shift = 16384, 100, 20, 1, 1e-4
+    l = k + p
+    dev = torch.device("cuda", 0)
+    lam = 1.0 / np.arange(1, 4097, dtype=np.float64)
+    exact = np.concatenate([lam + shift, np.full(n - lam.size, shift)])
+    t = time.perf_counter()
+    A = build_psd_torch(n, lam, shift, seed=args.seed, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    print(f"# built psd A {n}x{n} on the GPU in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream(dev)
+    paths = {}
+    for prec in (["bf16x3", "native"] if args.only is None else [args.only]):
+        pr = rs.problem(n, n, k, p, q, dtype=A.dtype, prec=prec, seed=args.seed)
+        ws = rs.Workspace(pr, dev)
+        Q = rs.rsvd_range_finder(A, k, p, q=q, prec=prec, seed=args.seed, ws=ws)
+        rs.rsvd_power_iter(A, Q, k, p, q, prec=prec, seed=args.seed, ws=ws)
+        U = torch.empty(n, k, dtype=A.dtype, device=dev)
+        Lam = torch.empty(k, dtype=A.dtype, device=dev)
+        res = {}
+        for name, fn in (("eigh", rs.rsvd_eigh), ("nystrom", rs.rsvd_nystrom)):
+            for _ in range(args.warmup):
+                fn(A, Q, k, prec=prec, U=U, Lam=Lam, ws=ws)
+            torch.cuda.synchronize()
+            rs.device_status(dev)
+            rs.profile_enable(4 * max(args.steps, 1), dev)
+            rs.profile_select(["stream_nn"], dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                fn(A, Q, k, prec=prec, U=U, Lam=Lam, ws=ws)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            launches, tot = rs.profile_read(dev)["stream_nn"]
+            rs.profile_enable(0, dev)
+            flags = rs.device_status(dev)
+            err = spectral_norm_residual(A, U, Lam, U) / exact[k]
+            lam_err = float(np.max(np.abs(Lam.double().cpu().numpy() - exact[:k]) / exact[:k]))
+            avg_s = tot / launches / 1e3
+            bytes_launch = 4.0 * n * n + 2 * 4.0 * n * l
+            res[name] = {"ms_per_call": ms, "a_read_gbs": 4.0 * n * n / (ms / 1e3) / 1e9, "err_ratio": err,
+                         "lambda_rel_err_vs_construction": lam_err, "flags": flags,
+                         "roofline": {"bound": "hbm", "achieved": bytes_launch / avg_s / 1e9, "peak": PEAK_HBM_GBS,
+                                      "unit": "GB/s", "frac": bytes_launch / avg_s / 1e9 / PEAK_HBM_GBS,
+                                      "traffic": None, "kernel": f"gemm_nn_{prec}", "launches": launches,
+                                      "avg_us": avg_s * 1e6, "per_launch": {"bytes": bytes_launch}}}
+            print(f"# psd {prec} {name}: {ms:.3f} ms per call, err ratio {err:.4f}, "
+                  f"lambda rel err {lam_err:.2e}", file=sys.stderr, flush=True)
+        paths[prec] = res
+        del ws
+    hp = paths[args.only or "bf16x3"]["nystrom"]
+    line = {
+        "metric": "psd Stage B (Algorithm 5.5 Nystrom): A read rate of one call", "value": hp["a_read_gbs"],
+        "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": hp["ms_per_call"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "prec": args.only or "bf16x3", "data": "synthetic",
+        "config": {"workload": f"psd eigendecomposition Stage B, FP32 {n}x{n}, lam_j = 1/j (j <= 4096) + {shift}, "
+                               f"k={k}, p={p}, Q from q={q}", "n": n, "k": k, "p": p, "q": q},
+        "floor_ms": 4.0 * n * n / PEAK_HBM_GBS / 1e9 * 1e3,
+        "roofline": hp["roofline"], "paths": paths,
+    }
+    del A
+    return line
+
+
 def workload_batched(args):
     """512 uneven FP32 matrices, sigma_j = exp(-j/r), p = 8, q = 1, one rsvd_batched call per step."""
     import numpy as np
@@ -697,7 +772,18 @@ def compact_sub_workloads(args):
     guarded("fp64_2000x1000", fp64)
     guarded("srft_32768x16384", srft)
     guarded("batched_512", batched)
+    def psd():
+        s2 = copy.copy(sub)
+        s2.only = "bf16x3"
+        d = workload_psd(s2)
+        pth = d["paths"]["bf16x3"]
+        return {name: {x: pth[name][x] for x in ("ms_per_call", "a_read_gbs", "err_ratio",
+                                                 "lambda_rel_err_vs_construction")}
+                | {"stream_nn_frac": pth[name]["roofline"]["frac"]} for name in ("eigh", "nystrom")} | {
+            "floor_ms": d["floor_ms"], "steps": s2.steps}
+
     guarded("differentiable_32x4096x2048", differentiable)
+    guarded("psd_stage_b_16384", psd)
     return out
 
 
@@ -729,12 +815,14 @@ def main():
     ap.add_argument("--keep-state", action="store_true",
                     help="differentiable workload: the forward keeps its bases for the adjoint instead of the "
                          "adjoint recomputing them")
-    ap.add_argument("--workload", choices=["power", "srft", "batched", "differentiable", "fp64"], default="power",
+    ap.add_argument("--workload", choices=["power", "srft", "batched", "differentiable", "fp64", "psd"],
+                    default="power",
                     help="power: the power-iteration rSVD (default); srft: SRFT vs Gaussian sketch, "
                          "FP32 32768 x 16384 with a spectral gap, k = 50, p = 78, q = 0; batched: 512 "
                          "uneven FP32 matrices, p = 8, q = 1; differentiable: 32 FP32 4096 x 2048 "
                          "matrices, forward + loss + adjoint; fp64: FP64 2000 x 1000, k = 20, p = 10, "
-                         "q = 0 (200 steps unless --steps is given)")
+                         "q = 0 (200 steps unless --steps is given); psd: Stage B for a 16384 x 16384 "
+                         "psd matrix (Algorithms 5.3 and 5.5), k = 100, p = 20")
     ap.add_argument("--srft-prec", choices=["bf16x3", "native"], default="bf16x3",
                     help="arithmetic of the GEMMs that stream A in the srft workload")
     ap.add_argument("--calib-copy", action="store_true",
@@ -761,6 +849,9 @@ def main():
         return
     if args.workload == "differentiable":
         print(json.dumps(workload_differentiable(args)))
+        return
+    if args.workload == "psd":
+        print(json.dumps(workload_psd(args)))
         return
     if args.workload == "srft":
         args.m, args.n, args.k, args.p, args.q = 32768, 16384, 50, 78, 0
