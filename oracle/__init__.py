@@ -21,6 +21,9 @@ adaptive    The fixed-precision range finder: Algorithm 4.2 one sample at a time
             eq. (4.3) as its stopping test (Sections 4.3-4.4).
 herm        Stage B for Hermitian and positive semidefinite A: Algorithm 5.3
             (direct eigenvalue decomposition) and Algorithm 5.5 (Nystrom).
+single_pass The eigenvalue decomposition of a Hermitian matrix in one pass over it:
+            Algorithm 5.6 with the oversampled basis of the closing remark of
+            Section 5.5.
 evaluate    Residual norms ||A - QQ*A|| and ||A - U S V*|| and the paper's error
             bounds (Theorems 9.1-9.3, 10.5, 10.6, Corollaries 10.9, 10.10).
 rsvd_grad   The reference gradient of the fixed-Omega randomized SVD: the same
@@ -33,5 +36,5 @@ something other than itself: numpy's own Philox, brute-force DFTs and SVDs,
 exact-rank recovery and the deterministic theorems of Section 9.
 """
 
-from . import philox, rsvd, evaluate, adaptive, herm  # noqa: F401
+from . import philox, rsvd, evaluate, adaptive, herm, single_pass  # noqa: F401
 # rsvd_grad imports torch; it is imported on its own where needed.
