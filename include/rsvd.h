@@ -265,6 +265,22 @@ rsvd_status rsvd_eigh(rsvd_handle handle, const rsvd_problem* problem, const voi
 rsvd_status rsvd_nystrom(rsvd_handle handle, const rsvd_problem* problem, const void* A, const void* Q, void* U,
                          void* Lam, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* rsvd_eigh_onepass: Algorithm 5.6 (eigenvalue decomposition in one pass,
+ * Section 5.5) for symmetric A (m == n, n x n, row-major, leading dimension
+ * lda): A is read once, by the sample Y = A Omega with Omega (n x l, l = k + p)
+ * drawn from (seed, stream_id) exactly as rsvd_draw_omega draws it.  Q is the
+ * n x k matrix of the k leading left singular vectors of Y when p > 0 (the
+ * oversampling of the remark that closes Section 5.5) and an orthonormal basis
+ * of range(Y) when p == 0; B (k x k) is the symmetric part of the standard
+ * least-squares solution of B (Q^T Omega) = Q^T Y (Q^T Omega has full row
+ * rank); B = V Lambda V^T; U = Q V.  Outputs, DEVICE buffers in the element
+ * type: U (n x k, leading dimension k) and Lam (k), all k pairs in decreasing
+ * |lambda| (equal magnitudes: the positive one first).  Workspace:
+ * rsvd_workspace_bytes(problem).  The Gaussian sketch only
+ * (RSVD_E_UNSUPPORTED otherwise); q is not used; m != n is RSVD_E_INVAL. */
+rsvd_status rsvd_eigh_onepass(rsvd_handle handle, const rsvd_problem* problem, const void* A, void* U, void* Lam,
+                              void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Size of the device array that rsvd_full_static uses as its workspace. */
 #define RSVD_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
 

@@ -11,6 +11,7 @@ names:
     rsvd_svd(Bt, Q, k, p, ...)           -> U, S, V Stage B steps 2-3 + truncation
     rsvd_eigh(A, Q, k, ...)              -> U, Lam  Stage B for symmetric A (Algorithm 5.3)
     rsvd_nystrom(A, Q, k, ...)           -> U, Lam  Stage B for psd A (Algorithm 5.5)
+    rsvd_eigh_onepass(A, k, p, ...)      -> U, Lam  one pass over symmetric A (Algorithm 5.6)
 
 and rsvd(A, k, p, q, ...) runs the first four.  If the library is missing the import
 of any of these raises; there is no other implementation.
@@ -203,6 +204,26 @@ def rsvd_nystrom(A, Q, k, *, prec="native", U=None, Lam=None, ws=None):
     """Algorithm 5.5 (Nystrom) for positive semidefinite A (n x n) and a basis Q (n x l):
     returns (U (n x k), Lam (k,)) with U Lam U^T the rank-k part of (AQ)(Q^T A Q)^-1 (AQ)^T."""
     return _herm("rsvd_nystrom", A, Q, k, Q.shape[1] - k, prec, U, Lam, ws)
+
+
+def rsvd_eigh_onepass(A, k, p=10, *, prec="native", seed=0, stream_id=0, U=None, Lam=None, ws=None):
+    """Algorithm 5.6 for symmetric A (n x n): one pass over A (Y = A Omega, Omega n x (k + p) from
+    (seed, stream_id)), B from the least-squares system B (Q^T Omega) = Q^T Y, its eigenpairs lifted by
+    Q.  Returns (U (n x k), Lam (k,)) in decreasing |lambda|."""
+    n = A.shape[0]
+    if A.dim() != 2 or A.shape[1] != n:
+        raise ValueError(f"rsvd_eigh_onepass: A must be square, got {tuple(A.shape)}")
+    pr = problem(n, n, k, p, 0, dtype=A.dtype, prec=prec, seed=seed, stream_id=stream_id)
+    dev = A.device
+    if U is None:
+        U = torch.empty(n, k, dtype=A.dtype, device=dev)
+    if Lam is None:
+        Lam = torch.empty(k, dtype=A.dtype, device=dev)
+    ws = ws or Workspace(pr, dev)
+    h = handle(dev)
+    _lib.check(h.lib.rsvd_eigh_onepass(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(U), _ptr(Lam), ws.ptr, ws.nbytes,
+                                       _stream(dev)), "rsvd_eigh_onepass")
+    return U, Lam
 
 
 def _check_differentiable(sketch):

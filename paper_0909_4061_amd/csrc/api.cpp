@@ -871,6 +871,79 @@ rsvd_status herm_steps(const Ctx& c, const rsvd_problem* pr, const void* A, cons
               nullptr);
 }
 
+// A plan for k columns over the same workspace regions (each sized for l >= k).
+Plan narrowed_plan(const Plan& P, int64_t cols) {
+  Plan q = P;
+  q.l = cols;
+  q.Lg = (int32_t)round_up(cols, 16);
+  return q;
+}
+
+// Algorithm 5.6 (eigenvalue decomposition of a symmetric A in one pass over it)
+// with the oversampled basis of the closing remark of Section 5.5.
+rsvd_status onepass_steps(const Ctx& c, const rsvd_problem* pr, const void* A, void* U, void* Lam) {
+  const Plan& P = c.P;
+  if (c.run->records() || pr->sketch != RSVD_GAUSSIAN) return RSVD_E_UNSUPPORTED;
+  const int64_t n = P.n, l = P.l, k = P.k;
+  const Plan Pk = narrowed_plan(P, k);
+  const Ctx ck{Pk, c.ws, c.st, c.status, c.h, c.run};
+  // Y = A Omega (the one pass; Omega drawn into the plan's omega region)
+  void* Y = c.at<void>(P.Qt);
+  void* Q = c.at<void>(P.Y);
+  rsvd_status s = sketch(c, pr, A, Y);
+  if (s == RSVD_OK) s = reduce_parts(c, P.nn, n, Y);
+  if (s != RSVD_OK) return s;
+  if (k == l) {
+    // no oversampling: Q = an orthonormal basis of range(Y) (CholeskyQR2)
+    s = orth(c, false, no_split(1), Y, n, Q, nullptr);
+  } else {
+    // Q = the k leading left singular vectors of Y: Y = W S V^T from the small SVD of Y^T
+    // (as for B^T in Algorithm 5.1), Q = Y V_k S_k^-1, then CholeskyQR2 of Q
+    JacobiParams j;
+    s = small_svd(c, Y, Lam, j);
+    if (s == RSVD_OK)
+      s = gemm(c, RSVD_NATIVE, false, Y, l, n, l, j.XV, k, (int32_t)k, Q, k, no_split(l), nullptr, nullptr);
+    if (s == RSVD_OK) s = orth(ck, false, no_split(1), Q, n, Q, nullptr);
+  }
+  if (s != RSVD_OK) return s;
+  // M = Q^T Omega, N = Q^T Y (k x l)
+  void* M = c.at<void>(P.XU);
+  void* N = c.at<void>(P.Rb);
+  void* Mt = c.at<void>(P.XV);
+  s = gemm_tn_splitk_into(ck, c.at<void>(P.part), Q, k, k, n, c.at<void>(P.omega), l, (int32_t)l, M, l);
+  if (s == RSVD_OK) s = gemm_tn_splitk_into(ck, c.at<void>(P.part), Q, k, k, n, Y, l, (int32_t)l, N, l);
+  // least squares B M = N with M of full row rank: M^T = Q_M R_M (CholeskyQR2, l x k),
+  // B = N Q_M R_M^-T; then its symmetric part
+  if (s == RSVD_OK) s = copy2d(c, M, P.dtype, l, Mt, P.dtype, k, k, l, true);
+  double* Rm = c.at<double>(P.Uh);
+  if (s == RSVD_OK) s = orth(ck, false, no_split(1), Mt, l, Mt, Rm);
+  if (s != RSVD_OK) return s;
+  double* Rmi = c.at<double>(P.eigZ);
+  RSVD_TRY(c.run->tri_inv(TriInvParams{Rm, Rmi, (int32_t)k}));
+  void* RmiT = c.at<void>(P.R1);
+  s = copy2d(c, Rmi, RSVD_F64, k, RmiT, P.dtype, k, k, k, true);
+  void* T1 = c.at<void>(P.R2);
+  void* Bu = c.at<void>(P.R3);
+  if (s == RSVD_OK)
+    s = gemm(c, RSVD_NATIVE, false, N, l, k, l, Mt, k, (int32_t)k, T1, k, no_split(l), nullptr, nullptr);
+  if (s == RSVD_OK)
+    s = gemm(c, RSVD_NATIVE, false, T1, k, k, k, RmiT, k, (int32_t)k, Bu, k, no_split(k), nullptr, nullptr);
+  if (s != RSVD_OK) return s;
+  {
+    Timed t_(c.h, RSVD_KERNEL_EIG, c.st);
+    RSVD_TRY(launch_sym_gram(SymGramParams{Bu, P.dtype, (int32_t)k, (int32_t)k, Pk.Lg, c.at<double>(P.G)}, c.st));
+  }
+  // B = V Lambda V^T (k x k), every pair kept in decreasing |lambda|; U = Q V
+  EigParams e = eig_params(ck, Lam);
+  for (int stage = 0; stage < 3; ++stage) RSVD_TRY(c.run->eig(stage, e));
+  EigPickParams pick{e.lam, e.Uh, e.sig, (int32_t)k, (int32_t)k, 1, P.dtype, Lam, c.at<void>(P.XU)};
+  {
+    Timed t_(c.h, RSVD_KERNEL_EIG, c.st);
+    RSVD_TRY(launch_eig_pick(pick, c.st));
+  }
+  return gemm(ck, RSVD_NATIVE, false, Q, k, n, k, pick.XU, k, (int32_t)k, U, k, no_split(k), nullptr, nullptr);
+}
+
 rsvd_status gemm_tn_splitk(const Ctx& c, const BwdLayout& L, const void* A, int64_t lda, int64_t rows, int64_t K,
                            const void* X, int64_t ldx, int32_t ncols, void* out, int64_t ldo) {
   return gemm_tn_splitk_into(c, c.at<void>(L.part), A, lda, rows, K, X, ldx, ncols, out, ldo);
@@ -1977,6 +2050,17 @@ rsvd_status rsvd_eigh(rsvd_handle h, const rsvd_problem* pr, const void* A, cons
 rsvd_status rsvd_nystrom(rsvd_handle h, const rsvd_problem* pr, const void* A, const void* Q, void* U, void* Lam,
                          void* ws, size_t ws_bytes, hipStream_t stream) {
   return herm_call(h, pr, A, Q, U, Lam, ws, ws_bytes, stream, true);
+}
+
+rsvd_status rsvd_eigh_onepass(rsvd_handle h, const rsvd_problem* pr, const void* A, void* U, void* Lam, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  if (pr && pr->m != pr->n) return RSVD_E_INVAL;
+  Prologue pro = prologue(h, pr, ws, ws_bytes);
+  if (pro.status != RSVD_OK) return pro.status;
+  if (!A || !U || !Lam) return RSVD_E_INVAL;
+  DirectRunner dr(h, stream);
+  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
+  return onepass_steps(c, pr, A, U, Lam);
 }
 
 size_t rsvd_full_workspace_bytes(const rsvd_problem* problem) {
