@@ -277,7 +277,9 @@ def workload_psd(args):
     """Stage B for a positive semidefinite A (Algorithm 5.3 direct eigendecomposition, Algorithm 5.5
     Nystrom) on an FP32 16384 x 16384 matrix: A = V diag(lam) V^T + 1e-4 I with lam_j = 1/j for
     j <= 4096 (V a thin Haar basis), k = 100, p = 20, Q from the range finder with q = 1.  Each
-    Stage B call reads A once (the product A Q); it is timed alone, with its A Q launch."""
+    Stage B call reads A once (the product A Q); it is timed alone, with its A Q launch.  Then the
+    single-pass Algorithm 5.6 (rsvd_eigh_onepass) end to end against the two-pass route with q = 0
+    (rsvd_range_finder + rsvd_eigh) on the same matrix."""
     import numpy as np
     import torch
     import paper_0909_4061_amd as rs
@@ -331,8 +333,40 @@ def workload_psd(args):
                                       "avg_us": avg_s * 1e6, "per_launch": {"bytes": bytes_launch}}}
             print(f"# psd {prec} {name}: {ms:.3f} ms per call, err ratio {err:.4f}, "
                   f"lambda rel err {lam_err:.2e}", file=sys.stderr, flush=True)
+        # Algorithm 5.6 (one pass over A) against the two-pass route it replaces (the range finder
+        # with q = 0, then Algorithm 5.3): each timed end to end
+        pr0 = rs.problem(n, n, k, p, 0, dtype=A.dtype, prec=prec, seed=args.seed)
+        ws0 = rs.Workspace(pr0, dev)
+        Q0 = torch.empty(n, l, dtype=A.dtype, device=dev)
+
+        def two_pass():
+            rs.rsvd_range_finder(A, k, p, prec=prec, seed=args.seed, Q=Q0, ws=ws0)
+            rs.rsvd_eigh(A, Q0, k, prec=prec, U=U, Lam=Lam, ws=ws0)
+
+        def one_pass():
+            rs.rsvd_eigh_onepass(A, k, p, prec=prec, seed=args.seed, U=U, Lam=Lam, ws=ws0)
+
+        for name, fn in (("onepass", one_pass), ("twopass_q0", two_pass)):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            rs.device_status(dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            flags = rs.device_status(dev)
+            err = spectral_norm_residual(A, U, Lam, U) / exact[k]
+            lam_err = float(np.max(np.abs(Lam.double().cpu().numpy() - exact[:k]) / exact[:k]))
+            res[name] = {"ms_per_call": ms, "passes_over_a": 1 if name == "onepass" else 2, "err_ratio": err,
+                         "lambda_rel_err_vs_construction": lam_err, "flags": flags}
+            print(f"# psd {prec} {name}: {ms:.3f} ms per call, err ratio {err:.4f}, "
+                  f"lambda rel err {lam_err:.2e}", file=sys.stderr, flush=True)
         paths[prec] = res
-        del ws
+        del ws, ws0
     hp = paths[args.only or "bf16x3"]["nystrom"]
     line = {
         "metric": "psd Stage B (Algorithm 5.5 Nystrom): A read rate of one call", "value": hp["a_read_gbs"],
@@ -777,10 +811,12 @@ def compact_sub_workloads(args):
         s2.only = "bf16x3"
         d = workload_psd(s2)
         pth = d["paths"]["bf16x3"]
-        return {name: {x: pth[name][x] for x in ("ms_per_call", "a_read_gbs", "err_ratio",
+        out_ = {name: {x: pth[name][x] for x in ("ms_per_call", "a_read_gbs", "err_ratio",
                                                  "lambda_rel_err_vs_construction")}
-                | {"stream_nn_frac": pth[name]["roofline"]["frac"]} for name in ("eigh", "nystrom")} | {
-            "floor_ms": d["floor_ms"], "steps": s2.steps}
+                | {"stream_nn_frac": pth[name]["roofline"]["frac"]} for name in ("eigh", "nystrom")}
+        out_ |= {name: {x: pth[name][x] for x in ("ms_per_call", "err_ratio", "passes_over_a")}
+                 for name in ("onepass", "twopass_q0")}
+        return out_ | {"floor_ms": d["floor_ms"], "steps": s2.steps}
 
     guarded("differentiable_32x4096x2048", differentiable)
     guarded("psd_stage_b_16384", psd)

@@ -137,9 +137,6 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   int64_t part_elems = 0;
   if (P.nn.S > 1) part_elems = std::max(part_elems, (int64_t)P.nn.S * P.m * P.Lp);
   if (P.tn.S > 1) part_elems = std::max(part_elems, (int64_t)P.tn.S * P.n * P.Lp);
-  // the l x l product Q^T (A Q) of the symmetric Stage B: at most 16 K chunks of
-  // l rows x 128 columns
-  if (!batched) part_elems = std::max(part_elems, (int64_t)16 * P.l * 128);
   const size_t es = (size_t)P.esize;
   const size_t ll8 = (size_t)P.l * P.l * 8;
   size_t off = 0;
@@ -790,6 +787,17 @@ rsvd_status gemm_tn_splitk_into(const Ctx& c, void* part_buf, const void* A, int
   return RSVD_OK;
 }
 
+// C = X1^T X2 (c1 x c2) over n rows with exact FP64 products (cross kernel, the
+// plan's Gram partial region): into out (element type) or, sym, its symmetric
+// part into the plan's G.
+hipError_t cross(const Ctx& c, const void* X1, int64_t ld1, const void* X2, int64_t ld2, int64_t rows, int32_t c1,
+                 int32_t c2, void* out, int64_t ldo, bool sym) {
+  Timed t_(c.h, RSVD_KERNEL_GRAM, c.st);
+  const CrossParams x{X1, ld1, X2, ld2, rows, c1, c2, c.P.dtype, c.P.Lg, c.at<double>(c.P.gpart),
+                      cross_blocks(rows), sym ? 1 : 0, out, ldo, c.at<double>(c.P.G)};
+  return launch_cross(x, c.st);
+}
+
 // The eigensolver of an l x l symmetric matrix held in G (FP64 upper triangle):
 // tridiagonalization, eigenpairs, cluster fix-up.  Outputs in the plan's Uh,
 // sig, XU, XV (value order, the first k); S (k, element type) is scratch here.
@@ -831,14 +839,8 @@ rsvd_status herm_steps(const Ctx& c, const rsvd_problem* pr, const void* A, cons
   if (s != RSVD_OK) return s;
   s = reduce_parts(c, P.nn, n, y);
   if (s != RSVD_OK) return s;
-  // B = Q^T B1 (l x l, element type, into the RinvT region), its symmetric part into G
-  void* B = c.at<void>(P.RinvT);
-  s = gemm_tn_splitk_into(c, c.at<void>(P.part), Q, l, l, n, y, l, (int32_t)l, B, l);
-  if (s != RSVD_OK) return s;
-  {
-    Timed t_(c.h, RSVD_KERNEL_EIG, c.st);
-    RSVD_TRY(launch_sym_gram(SymGramParams{B, P.dtype, (int32_t)l, (int32_t)l, P.Lg, c.at<double>(P.G)}, c.st));
-  }
+  // the symmetric part of B = Q^T B1 (l x l) into G: exact FP64 products summed over chunks of rows
+  RSVD_TRY(cross(c, Q, l, y, l, n, (int32_t)l, (int32_t)l, nullptr, 0, true));
   EigParams e = eig_params(c, Lam);
   EigPickParams pick{e.lam, e.Uh, e.sig, (int32_t)l, (int32_t)P.k, nystrom ? 0 : 1, P.dtype, Lam, nullptr};
   if (!nystrom) {
@@ -910,8 +912,9 @@ rsvd_status onepass_steps(const Ctx& c, const rsvd_problem* pr, const void* A, v
   void* M = c.at<void>(P.XU);
   void* N = c.at<void>(P.Rb);
   void* Mt = c.at<void>(P.XV);
-  s = gemm_tn_splitk_into(ck, c.at<void>(P.part), Q, k, k, n, c.at<void>(P.omega), l, (int32_t)l, M, l);
-  if (s == RSVD_OK) s = gemm_tn_splitk_into(ck, c.at<void>(P.part), Q, k, k, n, Y, l, (int32_t)l, N, l);
+  if (cross(c, Q, k, c.at<void>(P.omega), l, n, (int32_t)k, (int32_t)l, M, l, false) != hipSuccess ||
+      cross(c, Q, k, Y, l, n, (int32_t)k, (int32_t)l, N, l, false) != hipSuccess)
+    return RSVD_E_DEVICE;
   // least squares B M = N with M of full row rank: M^T = Q_M R_M (CholeskyQR2, l x k),
   // B = N Q_M R_M^-T; then its symmetric part
   if (s == RSVD_OK) s = copy2d(c, M, P.dtype, l, Mt, P.dtype, k, k, l, true);

@@ -217,6 +217,28 @@ struct EigPickParams {
   void* XU;   // l x k, element type (magnitude order only; may be null)
 };
 hipError_t launch_sym_gram(const SymGramParams& p, hipStream_t st);
+// C = X1^T X2 (c1 x c2) over `rows` rows: partials of CROSS_ROWS rows into
+// part (nblk blocks of Lg x Lg FP64), then their sum into out (element type,
+// sym == 0) or its symmetric part into G (FP64 upper triangle, sym == 1).
+constexpr int CROSS_ROWS = 64;
+struct CrossParams {
+  const void* X1;
+  int64_t ld1;
+  const void* X2;
+  int64_t ld2;
+  int64_t rows;
+  int32_t c1, c2;
+  int32_t dtype;
+  int32_t Lg;
+  double* part;
+  int64_t nblk;
+  int32_t sym;
+  void* out;
+  int64_t ldo;
+  double* G;
+};
+int64_t cross_blocks(int64_t rows);
+hipError_t launch_cross(const CrossParams& p, hipStream_t st);
 hipError_t launch_eig_pick(const EigPickParams& p, hipStream_t st);
 
 struct GramReduceParams {
