@@ -23,6 +23,12 @@ Readings where the paper is silent:
   * The k eigenpairs are returned in decreasing order of |lambda| (equal
     magnitudes: the positive one first), like Algorithm 5.3.
 
+The same section sketches a single pass for a general A: Y = A Omega and
+Yt = A* Omegat in one pass, orthonormal bases Q and Qt of their ranges, and the
+reduced matrix B = Q* A Qt determined as the minimum-residual solution of its
+two relations B (Qt* Omega) ~ Q* Y and B* (Q* Omegat) ~ Qt* Yt
+(two_sided_svd; its SVD then gives U = Q Ub, V = Qt Vb).
+
 Library primitives stand in for single steps only: numpy products, Householder
 QR and SVD (LAPACK), numpy's least-squares solver and Hermitian eigensolver.
 """
@@ -60,3 +66,41 @@ def one_pass_eig(A, Omega, k):
     lam, V = np.linalg.eigh(B)
     order = sorted(range(lam.size), key=lambda i: (-abs(lam[i]), -lam[i]))
     return Q @ V[:, order], lam[order]
+
+
+# ---------------------------------------------------------------------------
+# The two-sided single pass for a general A (Section 5.5, after Algorithm 5.6)
+# ---------------------------------------------------------------------------
+
+def two_sided_core(M1, N1, M2, N2):
+    """The minimum-residual B of the two relations of Section 5.5:
+        B M1 ~ N1   (M1 = Qt* Omega,  N1 = Q* Y)
+        B* M2 ~ N2  (M2 = Q* Omegat, N2 = Qt* Yt)
+    i.e. argmin_B ||B M1 - N1||_F^2 + ||B* M2 - N2||_F^2, as one linear least-squares problem in the
+    entries of B (numpy's lstsq on the stacked, vectorized relations)."""
+    l, lt = N1.shape[0], M1.shape[0]  # B is l x lt
+    # row-major vec: vec(B M1) = kron(I_l, M1^T) vec(B); vec(B^T M2) = kron(M2^T, I_lt) P vec(B) with
+    # P the l x lt -> lt x l transposition, written out entry by entry
+    rows1 = np.kron(np.eye(l), M1.T)
+    T = np.zeros((l * lt, l * lt))
+    for i in range(l):
+        for j in range(lt):
+            T[j * l + i, i * lt + j] = 1.0
+    rows2 = np.kron(np.eye(lt), M2.T) @ T
+    Asys = np.vstack([rows1, rows2])
+    rhs = np.concatenate([N1.reshape(-1), N2.reshape(-1)])
+    b, *_ = np.linalg.lstsq(Asys, rhs, rcond=None)
+    return b.reshape(l, lt)
+
+
+def two_sided_svd(A, Omega, Omegat, k):
+    """The single-pass factorization of a general A: Y = A Omega and Yt = A* Omegat (one pass over A),
+    Y = Q R and Yt = Qt Rt (orthonormal bases), B from the two least-squares relations, B = Ub S Vb*,
+    U = Q Ub, V = Qt Vb, truncated to k.  Returns (U (m x k), S (k,), V (n x k))."""
+    Y = A @ Omega
+    Yt = adj(A) @ Omegat
+    Q, R = qr_pos(Y)
+    Qt, Rt = qr_pos(Yt)
+    B = two_sided_core(adj(Qt) @ Omega, adj(Q) @ Y, adj(Q) @ Omegat, adj(Qt) @ Yt)
+    Ub, S, Vbh = np.linalg.svd(B, full_matrices=False)
+    return (Q @ Ub)[:, :k], S[:k], (Qt @ adj(Vbh))[:, :k]

@@ -11,6 +11,10 @@ Section 5.5.
    E = Q*A(I - QQ*)Omega, so the least-squares B differs from B_true by at most
    ||E|| / sigma_min(Q*Omega), and ||A - U Lambda U*|| <= ||A - Q B_true Q*|| + ||E|| / sigma_min
    (checked on decaying spectra, with and without oversampling).
+4. The two-sided single pass for a general A: the core recovers B exactly from two consistent
+   rectangular relations; a rank-r A is factored exactly from l >= r samples on each side; and the
+   least-squares B is within ||(E1, E2)||_F / sqrt(sigma_min(M1)^2 + sigma_min(M2)^2) of Q*A Qt
+   (Frobenius), E1, E2 the residuals of the two relations at Q*A Qt.
 """
 
 import numpy as np
@@ -68,3 +72,54 @@ def test_one_pass_error_bound(decay, p, seed):
     # and the core itself is within ||E|| / sigma_min of Q*AQ
     B = single_pass.least_squares_core(Q, Om, Y)
     assert np.linalg.norm(B - Btrue, 2) <= np.linalg.norm(E, 2) / smin * (1 + 1e-10)
+
+
+# --- the two-sided single pass for a general A (Section 5.5) -------------------------------------
+
+@pytest.mark.parametrize("l,lt,s1,s2", [(5, 4, 6, 7), (6, 6, 6, 6), (3, 5, 8, 4)])
+def test_two_sided_core_recovers_b(l, lt, s1, s2):
+    # consistent relations B M1 = N1, B^T M2 = N2 with full-rank M1 (lt x s1), M2 (l x s2): B exactly
+    rng = np.random.default_rng(200 + l + lt)
+    B0 = rng.standard_normal((l, lt))
+    M1 = rng.standard_normal((lt, s1))
+    M2 = rng.standard_normal((l, s2))
+    B = single_pass.two_sided_core(M1, B0 @ M1, M2, B0.T @ M2)
+    assert np.linalg.norm(B - B0) <= 1e-10 * np.linalg.norm(B0)
+
+
+@pytest.mark.parametrize("m,n,r,l", [(90, 60, 5, 8), (70, 110, 6, 6)])
+def test_two_sided_exact_rank(m, n, r, l):
+    from workloads import build_matrix
+    sigma = np.zeros(min(m, n))
+    sigma[:r] = np.linspace(3.0, 0.5, r)
+    A = build_matrix(m, n, sigma, seed=101)
+    Om = rsvd.gaussian_test_matrix(n, l, 102, 0)
+    Omt = rsvd.gaussian_test_matrix(m, l, 102, 1)
+    U, S, V = single_pass.two_sided_svd(A, Om, Omt, r)
+    assert np.allclose(S, sigma[:r], rtol=1e-10, atol=0)
+    assert np.linalg.norm(A - (U * S[None, :]) @ V.T, 2) <= 1e-10 * 3.0
+    assert np.linalg.norm(U.T @ U - np.eye(r), 2) <= 1e-12
+    assert np.linalg.norm(V.T @ V - np.eye(r), 2) <= 1e-12
+
+
+@pytest.mark.parametrize("decay,seed", [(1.0, 111), (2.0, 112)])
+def test_two_sided_core_error_bound(decay, seed):
+    # N1 = B_true M1 + E1, N2 = B_true^T M2 + E2 with B_true = Q*A Qt: the least-squares B is within
+    # ||(E1, E2)||_F / sqrt(sigma_min(M1)^2 + sigma_min(M2)^2) of B_true (Frobenius)
+    from workloads import build_matrix
+    m, n, l = 120, 90, 10
+    sigma = np.arange(1, 91, dtype=np.float64) ** -decay
+    A = build_matrix(m, n, sigma, seed=seed)
+    Om = rsvd.gaussian_test_matrix(n, l, seed + 1, 0)
+    Omt = rsvd.gaussian_test_matrix(m, l, seed + 1, 1)
+    Q, _ = rsvd.qr_pos(A @ Om)
+    Qt, _ = rsvd.qr_pos(A.T @ Omt)
+    M1, M2 = Qt.T @ Om, Q.T @ Omt
+    N1, N2 = Q.T @ A @ Om, Qt.T @ A.T @ Omt
+    Bt = Q.T @ A @ Qt
+    E1, E2 = N1 - Bt @ M1, N2 - Bt.T @ M2
+    s1 = np.linalg.svd(M1, compute_uv=False)[-1]
+    s2 = np.linalg.svd(M2, compute_uv=False)[-1]
+    bound = np.sqrt(np.linalg.norm(E1) ** 2 + np.linalg.norm(E2) ** 2) / np.sqrt(s1 ** 2 + s2 ** 2)
+    B = single_pass.two_sided_core(M1, N1, M2, N2)
+    assert np.linalg.norm(B - Bt) <= bound * (1 + 1e-10), (np.linalg.norm(B - Bt), bound)
