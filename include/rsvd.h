@@ -281,6 +281,23 @@ rsvd_status rsvd_nystrom(rsvd_handle handle, const rsvd_problem* problem, const 
 rsvd_status rsvd_eigh_onepass(rsvd_handle handle, const rsvd_problem* problem, const void* A, void* U, void* Lam,
                               void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* rsvd_svd_onepass: the single-pass factorization of a general A that closes
+ * Section 5.5.  Omega (n x l, l = k + p) is drawn from (seed, stream_id) as
+ * rsvd_draw_omega draws it and Omegat (m x l) from (seed, stream_id with its
+ * top bit flipped); Y = A Omega and Yt = A^T Omegat are the only products with
+ * A (two launches here, each reading A once: with A resident in device memory
+ * a fused launch would trade the second read for partial sums of the same
+ * size); Q, Qt = CholeskyQR2 bases of their ranges (Q^T Y = R, Qt^T Yt = Rt);
+ * B (l x l) = the minimum-residual solution of B (Qt^T Omega) = R and
+ * B^T (Q^T Omegat) = Rt, through its normal equations B G1 + G2 B = C and the
+ * eigendecompositions of G1 = M1 M1^T and G2 = M2 M2^T; B = Ub S Vb^T;
+ * U = Q Ub_k, V = Qt Vb_k.  Outputs and workspace as rsvd_full's hot-path
+ * calls: U (m x k), S (k, descending), V (n x k), DEVICE buffers in the element
+ * type, workspace rsvd_workspace_bytes(problem).  The Gaussian sketch only
+ * (RSVD_E_UNSUPPORTED otherwise); q is not used. */
+rsvd_status rsvd_svd_onepass(rsvd_handle handle, const rsvd_problem* problem, const void* A, void* U, void* S,
+                             void* V, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Size of the device array that rsvd_full_static uses as its workspace. */
 #define RSVD_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
 

@@ -12,6 +12,7 @@ names:
     rsvd_eigh(A, Q, k, ...)              -> U, Lam  Stage B for symmetric A (Algorithm 5.3)
     rsvd_nystrom(A, Q, k, ...)           -> U, Lam  Stage B for psd A (Algorithm 5.5)
     rsvd_eigh_onepass(A, k, p, ...)      -> U, Lam  one pass over symmetric A (Algorithm 5.6)
+    rsvd_svd_onepass(A, k, p, ...)       -> U, S, V single-pass factorization of a general A
 
 and rsvd(A, k, p, q, ...) runs the first four.  If the library is missing the import
 of any of these raises; there is no other implementation.
@@ -224,6 +225,23 @@ def rsvd_eigh_onepass(A, k, p=10, *, prec="native", seed=0, stream_id=0, U=None,
     _lib.check(h.lib.rsvd_eigh_onepass(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(U), _ptr(Lam), ws.ptr, ws.nbytes,
                                        _stream(dev)), "rsvd_eigh_onepass")
     return U, Lam
+
+
+def rsvd_svd_onepass(A, k, p=10, *, prec="native", seed=0, stream_id=0, U=None, S=None, V=None, ws=None):
+    """The single-pass factorization of a general A (Section 5.5): Y = A Omega and Yt = A^T Omegat,
+    bases Q and Qt, B from its two least-squares relations, B = Ub S Vb^T.  Returns (U (m x k), S (k,),
+    V (n x k))."""
+    m, n = A.shape
+    pr = problem(m, n, k, p, 0, dtype=A.dtype, prec=prec, seed=seed, stream_id=stream_id)
+    dev = A.device
+    U = torch.empty(m, k, dtype=A.dtype, device=dev) if U is None else U
+    S = torch.empty(k, dtype=A.dtype, device=dev) if S is None else S
+    V = torch.empty(n, k, dtype=A.dtype, device=dev) if V is None else V
+    ws = ws or Workspace(pr, dev)
+    h = handle(dev)
+    _lib.check(h.lib.rsvd_svd_onepass(h.ptr, ctypes.byref(pr), _ptr(A), _ptr(U), _ptr(S), _ptr(V), ws.ptr,
+                                      ws.nbytes, _stream(dev)), "rsvd_svd_onepass")
+    return U, S, V
 
 
 def _check_differentiable(sketch):

@@ -36,7 +36,7 @@ EXPORTS = [
     "rsvd_full_static", "rsvd_range_finder_tol_workspace_bytes", "rsvd_range_finder_tol",
     "rsvd_sketch", "rsvd_draw_omega", "rsvd_draw_srft", "rsvd_orth", "rsvd_device_status",
     "rsvd_profile_enable", "rsvd_profile_select", "rsvd_profile_read", "rsvd_probe_hbm_read", "rsvd_probe_mfma",
-    "rsvd_eigh", "rsvd_nystrom", "rsvd_eigh_onepass",
+    "rsvd_eigh", "rsvd_nystrom", "rsvd_eigh_onepass", "rsvd_svd_onepass",
 ]
 KERNEL_KINDS = ["stream_nn", "stream_tn", "small_gemm", "gram", "chol", "jacobi", "pack", "srft", "eig"]
 
@@ -85,6 +85,7 @@ def load():
         "rsvd_eigh": ([vp, prob, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_nystrom": ([vp, prob, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_eigh_onepass": ([vp, prob, vp, vp, vp, vp, sz, vp], i32),
+        "rsvd_svd_onepass": ([vp, prob, vp, vp, vp, vp, vp, sz, vp], i32),
         "rsvd_sketch": ([vp, prob, vp, vp, vp, sz, vp], i32),
         "rsvd_batched_workspace_bytes": ([i32, prob], sz),
         "rsvd_backward_workspace_bytes": ([prob], sz),

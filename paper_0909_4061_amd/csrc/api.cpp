@@ -81,7 +81,7 @@ struct Plan {
   bool stream;  // FP32 data: the A-streaming products take the streaming kernels (X packed first)
   Split nn, tn;
   size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rb, RinvT, XU, XV, Uh, sig, flags, srft_d,
-      srft_R, eigV, eigZ, eigT, total;
+      srft_R, eigV, eigZ, eigT, omega2, sx, total;
 };
 
 bool valid_enum(int32_t v, int32_t lo, int32_t hi) { return v >= lo && v <= hi; }
@@ -172,6 +172,10 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   P.eigV = take(eig ? (size_t)P.l * EIG_LDV * 8 : 0);
   P.eigZ = take(eig ? ll8 : 0);
   P.eigT = take(eig ? (size_t)(4 * P.l + 1) * 8 + (size_t)P.l * 4 : 0);
+  // the two-sided single pass (single problems): its second test matrix (m x l) and
+  // eight l x l FP64 matrices for the least-squares core
+  P.omega2 = take(batched ? 0 : (size_t)P.m * P.l * es);
+  P.sx = take(batched ? 0 : 8 * ll8);
   P.total = off;
   return P;
 }
@@ -791,10 +795,10 @@ rsvd_status gemm_tn_splitk_into(const Ctx& c, void* part_buf, const void* A, int
 // plan's Gram partial region): into out (element type) or, sym, its symmetric
 // part into the plan's G.
 hipError_t cross(const Ctx& c, const void* X1, int64_t ld1, const void* X2, int64_t ld2, int64_t rows, int32_t c1,
-                 int32_t c2, void* out, int64_t ldo, bool sym) {
+                 int32_t c2, void* out, int64_t ldo, bool sym, bool out_f64 = false) {
   Timed t_(c.h, RSVD_KERNEL_GRAM, c.st);
   const CrossParams x{X1, ld1, X2, ld2, rows, c1, c2, c.P.dtype, c.P.Lg, c.at<double>(c.P.gpart),
-                      cross_blocks(rows), sym ? 1 : 0, out, ldo, c.at<double>(c.P.G)};
+                      cross_blocks(rows), sym ? 1 : 0, out, ldo, c.at<double>(c.P.G), out_f64 ? 1 : 0};
   return launch_cross(x, c.st);
 }
 
@@ -945,6 +949,98 @@ rsvd_status onepass_steps(const Ctx& c, const rsvd_problem* pr, const void* A, v
     RSVD_TRY(launch_eig_pick(pick, c.st));
   }
   return gemm(ck, RSVD_NATIVE, false, Q, k, n, k, pick.XU, k, (int32_t)k, U, k, no_split(k), nullptr, nullptr);
+}
+
+// The two-sided single pass for a general A (Section 5.5): Y = A Omega and
+// Yt = A^T Omegat, Q = orth(Y), Qt = orth(Yt) (CholeskyQR2, so Q^T Y = R and
+// Qt^T Yt = Rt), B (l x l) the minimum-residual solution of B M1 = R and
+// B^T M2 = Rt with M1 = Qt^T Omega, M2 = Q^T Omegat: the normal equations
+// B G1 + G2 B = R M1^T + M2 Rt^T (G1 = M1 M1^T, G2 = M2 M2^T), solved through
+// the eigendecompositions of G1 and G2; then the SVD of B (its FP64 Gram and
+// the eigensolver), U = Q Ub_k, V = Qt B^T Ub_k S_k^-1.
+rsvd_status svd_onepass_steps(const Ctx& c, const rsvd_problem* pr, const void* A, void* U, void* S, void* V) {
+  const Plan& P = c.P;
+  if (c.run->records() || pr->sketch != RSVD_GAUSSIAN) return RSVD_E_UNSUPPORTED;
+  const int64_t m = P.m, n = P.n, l = P.l, k = P.k;
+  const int32_t li = (int32_t)l;
+  const Plan p64 = [&] {
+    Plan q = P;
+    q.dtype = RSVD_F64;
+    q.esize = 8;
+    return q;
+  }();
+  const Ctx c64{p64, c.ws, c.st, c.status, c.h, c.run};
+  double* X[8];
+  for (int i = 0; i < 8; ++i) X[i] = c.at<double>(P.sx) + (int64_t)i * l * l;
+  double* R1 = c.at<double>(P.R1);
+  double* R2 = c.at<double>(P.R2);
+  double* R3 = c.at<double>(P.R3);
+  double* Rt = c.at<double>(P.Rt);
+  double* G = c.at<double>(P.G);
+  const int64_t Lg = P.Lg;
+  void* Y = c.at<void>(P.Y);       // m x l, then Q
+  void* Yt = c.at<void>(P.Qt);     // n x l, then Qt
+  void* Om2 = c.at<void>(P.omega2);
+  // the one pass: Y = A Omega, Yt = A^T Omegat (Omegat from (seed, stream_id with its top bit flipped))
+  rsvd_status s = sketch(c, pr, A, Y);
+  if (s == RSVD_OK) s = reduce_parts(c, P.nn, m, Y);
+  if (s != RSVD_OK) return s;
+  RSVD_TRY(c.run->omega(pr->dtype, OmegaParams{Om2, m, li, pr->seed, pr->stream_id ^ (uint64_t{1} << 63)}));
+  s = gemm(c, pr->prec, true, A, pr->lda, n, m, Om2, l, li, Yt, l, P.tn, P.tn.S > 1 ? c.at<void>(P.part) : nullptr,
+           nullptr, true);
+  if (s == RSVD_OK) s = reduce_parts(c, P.tn, n, Yt);
+  // bases and their triangular factors: Q^T Y = R -> X2, Qt^T Yt = Rt -> X3
+  if (s == RSVD_OK) s = orth(c, false, no_split(1), Y, m, Y, X[2]);
+  if (s == RSVD_OK) s = orth(c, false, no_split(1), Yt, n, Yt, X[3]);
+  if (s != RSVD_OK) return s;
+  // M1 = Qt^T Omega -> X0, M2 = Q^T Omegat -> X1 (exact FP64 products)
+  RSVD_TRY(cross(c, Yt, l, c.at<void>(P.omega), l, n, li, li, X[0], l, false, true));
+  RSVD_TRY(cross(c, Y, l, Om2, l, m, li, li, X[1], l, false, true));
+  auto mm = [&](bool trans, const double* a, const double* b, double* out, int64_t ldo, bool accum = false) {
+    return gemm(c64, RSVD_NATIVE, trans, a, l, l, l, b, l, li, out, ldo, no_split(l), nullptr, nullptr, false,
+                accum);
+  };
+  auto tr = [&](const double* a, double* out) { return copy2d(c, a, RSVD_F64, l, out, RSVD_F64, l, l, l, true); };
+  EigParams e = eig_params(c, S);
+  // G1 = M1 M1^T = W1 D1 W1^T -> W1 in X4, d1 in X5; G2 = M2 M2^T = W2 D2 W2^T -> X6, X7
+  for (int side = 0; side < 2; ++side) {
+    const double* M = X[side];
+    s = tr(M, R3);
+    if (s == RSVD_OK) s = mm(false, M, R3, G, Lg);
+    if (s != RSVD_OK) return s;
+    for (int stage = 0; stage < 3; ++stage) RSVD_TRY(c.run->eig(stage, e));
+    RSVD_TRY(c.run->copy(CopyParams{e.Uh, X[4 + 2 * side], l * l, nullptr}));
+    RSVD_TRY(c.run->copy(CopyParams{e.lam, X[5 + 2 * side], l, nullptr}));
+  }
+  // C = R M1^T + M2 Rt^T -> R1
+  s = tr(X[0], R3);
+  if (s == RSVD_OK) s = mm(false, X[2], R3, R1, l);
+  if (s == RSVD_OK) s = tr(X[3], R3);
+  if (s == RSVD_OK) s = mm(false, X[1], R3, R1, l, true);
+  // Chat = W2^T C W1 -> Rt; Bhat = Chat ./ (d2_i + d1_j); B = W2 Bhat W1^T -> R1
+  if (s == RSVD_OK) s = mm(true, X[6], R1, R2, l);
+  if (s == RSVD_OK) s = mm(false, R2, X[4], Rt, l);
+  if (s != RSVD_OK) return s;
+  RSVD_TRY(launch_sylv_div(Rt, l, X[7], X[5], li, c.st));
+  s = mm(false, X[6], Rt, R2, l);
+  if (s == RSVD_OK) s = tr(X[4], R3);
+  if (s == RSVD_OK) s = mm(false, R2, R3, R1, l);
+  // the SVD of B from its FP64 Gram B B^T: Ub (XU), S, Ub S^-1 (XV)
+  if (s == RSVD_OK) s = tr(R1, R3);
+  if (s == RSVD_OK) s = mm(false, R1, R3, G, Lg);
+  if (s != RSVD_OK) return s;
+  for (int stage = 0; stage < 3; ++stage) RSVD_TRY(c.run->eig(stage, e));
+  // U = Q Ub_k; V = Qt (B^T Ub_k S_k^-1), B^T rounded to the element type first (RinvT region)
+  void* Bt = c.at<void>(P.RinvT);
+  void* Vb = X[0];
+  s = copy2d(c, R1, RSVD_F64, l, Bt, P.dtype, l, l, l, true);
+  if (s == RSVD_OK)
+    s = gemm(c, RSVD_NATIVE, false, Bt, l, l, l, e.XV, k, (int32_t)k, Vb, k, no_split(l), nullptr, nullptr);
+  if (s == RSVD_OK)
+    s = gemm(c, RSVD_NATIVE, false, Y, l, m, l, e.XU, k, (int32_t)k, U, k, no_split(l), nullptr, nullptr);
+  if (s == RSVD_OK)
+    s = gemm(c, RSVD_NATIVE, false, Yt, l, n, l, Vb, k, (int32_t)k, V, k, no_split(l), nullptr, nullptr);
+  return s;
 }
 
 rsvd_status gemm_tn_splitk(const Ctx& c, const BwdLayout& L, const void* A, int64_t lda, int64_t rows, int64_t K,
@@ -2064,6 +2160,16 @@ rsvd_status rsvd_eigh_onepass(rsvd_handle h, const rsvd_problem* pr, const void*
   DirectRunner dr(h, stream);
   const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
   return onepass_steps(c, pr, A, U, Lam);
+}
+
+rsvd_status rsvd_svd_onepass(rsvd_handle h, const rsvd_problem* pr, const void* A, void* U, void* S, void* V,
+                             void* ws, size_t ws_bytes, hipStream_t stream) {
+  Prologue pro = prologue(h, pr, ws, ws_bytes);
+  if (pro.status != RSVD_OK) return pro.status;
+  if (!A || !U || !S || !V) return RSVD_E_INVAL;
+  DirectRunner dr(h, stream);
+  const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
+  return svd_onepass_steps(c, pr, A, U, S, V);
 }
 
 size_t rsvd_full_workspace_bytes(const rsvd_problem* problem) {

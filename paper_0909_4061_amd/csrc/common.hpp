@@ -236,8 +236,12 @@ struct CrossParams {
   void* out;
   int64_t ldo;
   double* G;
+  int32_t out_f64;  // sym == 0: out holds doubles instead of the element type
 };
 int64_t cross_blocks(int64_t rows);
+// X_ij /= (d2_i + d1_j) for an l x l FP64 matrix X (row stride ld): the
+// diagonalized Sylvester equation of the two-sided single pass.
+hipError_t launch_sylv_div(double* X, int64_t ld, const double* d2, const double* d1, int32_t l, hipStream_t st);
 hipError_t launch_cross(const CrossParams& p, hipStream_t st);
 hipError_t launch_eig_pick(const EigPickParams& p, hipStream_t st);
 

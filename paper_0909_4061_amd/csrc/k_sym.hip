@@ -177,14 +177,28 @@ __global__ __launch_bounds__(256) void cross_reduce_kernel(const CrossParams p) 
   b = (red[1][0][t] + red[1][1][t]) + (red[1][2][t] + red[1][3][t]);
   if (p.sym) {
     p.G[(int64_t)i * p.Lg + j] = 0.5 * (a + b);
-  } else if (p.dtype == RSVD_F64) {
+  } else if (p.dtype == RSVD_F64 || p.out_f64) {
     ((double*)p.out)[(int64_t)i * p.ldo + j] = a;
   } else {
     ((float*)p.out)[(int64_t)i * p.ldo + j] = (float)a;
   }
 }
 
+__global__ __launch_bounds__(256) void sylv_div_kernel(double* X, int64_t ld, const double* d2, const double* d1,
+                                                       int l) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= l * l) return;
+  const int i = e / l, j = e - i * l;
+  X[(int64_t)i * ld + j] /= d2[i] + d1[j];
+}
+
 }  // namespace
+
+hipError_t launch_sylv_div(double* X, int64_t ld, const double* d2, const double* d1, int32_t l, hipStream_t st) {
+  if (l < 1 || l > RSVD_MAX_L || ld < l || !X || !d2 || !d1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sylv_div_kernel, dim3((unsigned)((l * l + 255) / 256)), dim3(256), 0, st, X, ld, d2, d1, l);
+  return hipGetLastError();
+}
 
 int64_t cross_blocks(int64_t rows) { return (rows + CROSS_ROWS - 1) / CROSS_ROWS; }
 

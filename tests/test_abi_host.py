@@ -125,6 +125,7 @@ def test_null_arguments_fail_before_launch(lib):
     assert lib.rsvd_nystrom(None, ctypes.byref(rect), None, None, None, None, None, 0, None) == 1
     assert lib.rsvd_eigh_onepass(None, ctypes.byref(sq), None, None, None, None, 0, None) == 1
     assert lib.rsvd_eigh_onepass(None, ctypes.byref(rect), None, None, None, None, 0, None) == 1
+    assert lib.rsvd_svd_onepass(None, ctypes.byref(rect), None, None, None, None, None, 0, None) == 1
 
 
 def test_batched_workspace_and_validation(lib):

@@ -1,5 +1,6 @@
 """The single-pass eigendecomposition of a symmetric A on the GPU (rsvd_eigh_onepass: Algorithm 5.6
-with the oversampled basis of the closing remark of Section 5.5) against the oracle
+with the oversampled basis of the closing remark of Section 5.5), and the two-sided single pass for a
+general A (rsvd_svd_onepass, Section 5.5), against the oracle
 (oracle.single_pass) on the same A and the same test matrix Omega (the GPU draws Omega from
 (seed, stream_id); the oracle draws the same values from its own generator), through the C ABI.
 
@@ -110,4 +111,62 @@ def test_onepass_largest_basis_fp32():
     print(f"fp32 l=128: sigma_min {tau:.3f}, max |lambda - ref| {err:.3e} (tol {eps_b:.3e})")
     assert err <= eps_b
     assert np.linalg.norm(U.T @ U - np.eye(k), 2) <= 1e-4
+    assert flags & ~rs.RSVD_FLAG_SHIFTED == 0
+
+
+# --- the two-sided single pass for a general A (rsvd_svd_onepass) --------------------------------
+# Omegat is drawn from the stream id with its top bit flipped.  The least-squares B moves by at most
+# ||(dN1, dN2)|| / sqrt(sigma_min(M1)^2 + sigma_min(M2)^2) for perturbations dN of the right-hand
+# sides (the bound pinned on the oracle), and every singular value by at most that (Weyl);
+# ||dN|| <= delta ||A|| max(||Omega||, ||Omegat||) with delta as above.
+
+def _two_sided_case(m, n, sigma, k, p, npd, seed, prec="native"):
+    from workloads import build_matrix
+    A = build_matrix(m, n, sigma, seed=seed, dtype=npd)
+    A64 = A.astype(np.float64)
+    l = k + p
+    print(f"svd onepass {m}x{n} k={k} p={p} {A.dtype} {prec}", flush=True)
+    rs.device_status(DEV)
+    U, S, V = rs.rsvd_svd_onepass(torch.from_numpy(A).to(DEV), k, p, prec=prec, seed=seed + 1)
+    flags = rs.device_status(DEV)
+    Om = orsvd.gaussian_test_matrix(n, l, seed + 1, 0, npd)
+    Omt = orsvd.gaussian_test_matrix(m, l, seed + 1, 1 << 63, npd)
+    Ur, Sr, Vr = single_pass.two_sided_svd(A64, Om, Omt, k)
+    Q, _ = orsvd.qr_pos(A64 @ Om)
+    Qt, _ = orsvd.qr_pos(A64.T @ Omt)
+    s1 = np.linalg.svd(Qt.T @ Om, compute_uv=False)[-1]
+    s2 = np.linalg.svd(Q.T @ Omt, compute_uv=False)[-1]
+    amp = max(np.linalg.norm(Om, 2), np.linalg.norm(Omt, 2)) / np.sqrt(s1 ** 2 + s2 ** 2)
+    return A64, [to_np(t).astype(np.float64) for t in (U, S, V)], flags, (Ur, Sr, Vr), amp
+
+
+@pytest.mark.parametrize("npd,prec", [(np.float64, "native"), (np.float32, "native"), (np.float32, "bf16x3")])
+def test_svd_onepass_matches_oracle(npd, prec):
+    m, n, k, p = (300, 200, 10, 8) if npd == np.float64 else (1200, 800, 16, 8)
+    sigma = 1.0 / np.arange(1, min(m, n) + 1, dtype=np.float64)
+    A64, (U, S, V), flags, (Ur, Sr, Vr), amp = _two_sided_case(m, n, sigma, k, p, npd, 95, prec)
+    if npd == np.float64:
+        delta = 4 * 2.0 ** -53 * np.sqrt(max(m, n))
+    else:
+        delta = 2.0 ** -24 * np.sqrt(max(m, n)) + (2.0 ** -16 if prec == "bf16x3" else 0.0)
+    eps_b = 2 * delta * sigma[0] * amp
+    err = np.max(np.abs(S - Sr))
+    print(f"svd onepass {npd.__name__} {prec}: amplification {amp:.2f}, max |s - ref| {err:.3e} (tol {eps_b:.3e})")
+    assert flags & ~rs.RSVD_FLAG_SHIFTED == 0
+    assert err <= eps_b
+    res = np.linalg.norm(A64 - (U * S[None, :]) @ V.T, 2)
+    res_ref = np.linalg.norm(A64 - (Ur * Sr[None, :]) @ Vr.T, 2)
+    assert abs(res - res_ref) <= 2 * eps_b + 1e-3 * res_ref, (res, res_ref)
+    tol_o = 1e-12 if npd == np.float64 else 1e-5
+    assert np.linalg.norm(U.T @ U - np.eye(k), 2) <= tol_o
+    assert np.linalg.norm(V.T @ V - np.eye(k), 2) <= tol_o
+
+
+def test_svd_onepass_exact_rank_fp64():
+    m, n, r = 160, 120, 5
+    sigma = np.zeros(n)
+    sigma[:r] = np.linspace(3.0, 0.5, r)
+    A64, (U, S, V), flags, _, _ = _two_sided_case(m, n, sigma, r, 3, np.float64, 96)
+    assert np.max(np.abs(S - sigma[:r])) <= 1e-11 * 3.0
+    assert np.linalg.norm(A64 - (U * S[None, :]) @ V.T, 2) <= 1e-10 * 3.0
     assert flags & ~rs.RSVD_FLAG_SHIFTED == 0
