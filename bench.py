@@ -160,6 +160,57 @@ def run_path(A, k, p, q, prec, steps, warmup, seed):
     return dict(ms_per_step=ms_total / steps, prof=prof, breakdown=breakdown, flags=flags, U=U, S=S, V=V)
 
 
+def single_pass_general(A, k, p, sigma, prec, steps, warmup, seed):
+    """The two-sided single pass of Section 5.5 (rsvd_svd_onepass: Y = A Omega and Yt = A^T Omegat,
+    the core from its two least-squares relations) against the two-pass route it replaces (range
+    finder with q = 0, B = Q^T A, small SVD), each timed end to end on the same A."""
+    import torch
+    import paper_0909_4061_amd as rs
+
+    m, n = A.shape
+    l = k + p
+    dev = A.device
+    pr = rs.problem(m, n, k, p, 0, dtype=A.dtype, prec=prec, seed=seed, lda=A.stride(0))
+    ws = rs.Workspace(pr, dev)
+    Q = torch.empty(m, l, dtype=A.dtype, device=dev)
+    Bt = torch.empty(n, l, dtype=A.dtype, device=dev)
+    U = torch.empty(m, k, dtype=A.dtype, device=dev)
+    S = torch.empty(k, dtype=A.dtype, device=dev)
+    V = torch.empty(n, k, dtype=A.dtype, device=dev)
+    kw = dict(prec=prec, seed=seed, ws=ws)
+
+    def one_pass():
+        rs.rsvd_svd_onepass(A, k, p, U=U, S=S, V=V, **kw)
+
+    def two_pass():
+        rs.rsvd_range_finder(A, k, p, Q=Q, **kw)
+        rs.rsvd_project(A, Q, k, p, Bt=Bt, **kw)
+        rs.rsvd_svd(Bt, Q, m, n, k, p, dtype=A.dtype, U=U, S=S, V=V, **kw)
+
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for name, fn in (("onepass", one_pass), ("twopass_q0", two_pass)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        rs.device_status(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        flags = rs.device_status(dev)
+        err = spectral_norm_residual(A, U, S, V) / sigma[k]
+        out[name] = {"ms_per_call": ms, "passes_over_a": 1 if name == "onepass" else 2, "err_ratio": err,
+                     "flags": flags}
+        print(f"# general single pass {prec} {name}: {ms:.3f} ms per call, err ratio {err:.4f}",
+              file=sys.stderr, flush=True)
+    del ws
+    return out
+
+
 def srft_flops(m, n, l, k):
     """Flops of the SRFT rSVD per step: the real FFT of every row (2.5 n log2 n
     each, the usual count for a length-n real transform), CholeskyQR2 of Y
@@ -954,6 +1005,9 @@ def main():
     }
     if "native" in paths and head != "native":
         line["speedup_vs_fp32"] = paths["native"]["ms_per_step"] / hp["ms_per_step"]
+    if args.input == "construct":
+        line["single_pass_two_sided"] = single_pass_general(A, k, p, sigma, head, args.steps, args.warmup,
+                                                            args.seed)
     ceil = measured_ceilings(A)
     line["measured_ceilings"] = ceil
     for d in [line["roofline"]] + [pd["roofline"] for pd in line["paths"].values()]:

@@ -81,7 +81,7 @@ struct Plan {
   bool stream;  // FP32 data: the A-streaming products take the streaming kernels (X packed first)
   Split nn, tn;
   size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rb, RinvT, XU, XV, Uh, sig, flags, srft_d,
-      srft_R, eigV, eigZ, eigT, omega2, sx, total;
+      srft_R, eigV, eigZ, eigT, omega2, sx, eig2, total;
 };
 
 bool valid_enum(int32_t v, int32_t lo, int32_t hi) { return v >= lo && v <= hi; }
@@ -104,6 +104,36 @@ rsvd_status validate(const rsvd_problem* pr) {
   }
   return RSVD_OK;
 }
+
+// The second eigensolver of the two-sided single pass (byte offsets in its
+// region): G (Lg x Lg), reflectors V (l x EIG_LDV), Z (l x l), T (d, e, tau,
+// the eigenvalues, the norm bound, the flags), Uh (l x l), sig (l), XU and XV
+// (l x k elements), S (k elements).
+struct Eig2Layout {
+  size_t G, V, Z, T, Uh, sig, XU, XV, S, total;
+};
+Eig2Layout eig2_layout(const Plan& P) {
+  Eig2Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align_up(std::max<size_t>(bytes, 1));
+    return at;
+  };
+  const size_t ll8 = (size_t)P.l * P.l * 8;
+  L.G = take((size_t)P.Lg * P.Lg * 8);
+  L.V = take((size_t)P.l * EIG_LDV * 8);
+  L.Z = take(ll8);
+  L.T = take((size_t)(4 * P.l + 1) * 8 + (size_t)P.l * 4);
+  L.Uh = take(ll8);
+  L.sig = take((size_t)P.l * 8);
+  L.XU = take((size_t)P.l * P.k * P.esize);
+  L.XV = take((size_t)P.l * P.k * P.esize);
+  L.S = take((size_t)P.k * P.esize);
+  L.total = off;
+  return L;
+}
+size_t eig2_bytes(const Plan& P) { return eig2_layout(P).total; }
 
 // Workspace regions of one problem.  `batched`: no split-K (every problem of
 // a batch runs the same launch sequence, and the batch itself fills the chip);
@@ -173,9 +203,11 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   P.eigZ = take(eig ? ll8 : 0);
   P.eigT = take(eig ? (size_t)(4 * P.l + 1) * 8 + (size_t)P.l * 4 : 0);
   // the two-sided single pass (single problems): its second test matrix (m x l) and
-  // eight l x l FP64 matrices for the least-squares core
+  // four l x l FP64 matrices for the least-squares core
   P.omega2 = take(batched ? 0 : (size_t)P.m * P.l * es);
-  P.sx = take(batched ? 0 : 8 * ll8);
+  P.sx = take(batched ? 0 : 4 * ll8);
+  // and the eigensolver of its second Gram matrix, which runs beside the first
+  P.eig2 = take(batched ? 0 : eig2_bytes(P));
   P.total = off;
   return P;
 }
@@ -970,8 +1002,8 @@ rsvd_status svd_onepass_steps(const Ctx& c, const rsvd_problem* pr, const void* 
     return q;
   }();
   const Ctx c64{p64, c.ws, c.st, c.status, c.h, c.run};
-  double* X[8];
-  for (int i = 0; i < 8; ++i) X[i] = c.at<double>(P.sx) + (int64_t)i * l * l;
+  double* X[4];
+  for (int i = 0; i < 4; ++i) X[i] = c.at<double>(P.sx) + (int64_t)i * l * l;
   double* R1 = c.at<double>(P.R1);
   double* R2 = c.at<double>(P.R2);
   double* R3 = c.at<double>(P.R3);
@@ -1001,29 +1033,50 @@ rsvd_status svd_onepass_steps(const Ctx& c, const rsvd_problem* pr, const void* 
                 accum);
   };
   auto tr = [&](const double* a, double* out) { return copy2d(c, a, RSVD_F64, l, out, RSVD_F64, l, l, l, true); };
+  // G1 = M1 M1^T = W1 D1 W1^T (the plan's eigensolver regions) and G2 = M2 M2^T = W2 D2 W2^T (the
+  // second region), both eigensolvers in one launch per stage
   EigParams e = eig_params(c, S);
-  // G1 = M1 M1^T = W1 D1 W1^T -> W1 in X4, d1 in X5; G2 = M2 M2^T = W2 D2 W2^T -> X6, X7
+  EigParams e2 = e;
+  {
+    const Eig2Layout L2 = eig2_layout(P);
+    char* b2 = c.at<char>(P.eig2);
+    double* t2 = reinterpret_cast<double*>(b2 + L2.T);
+    e2.G = reinterpret_cast<const double*>(b2 + L2.G);
+    e2.V = reinterpret_cast<double*>(b2 + L2.V);
+    e2.Z = reinterpret_cast<double*>(b2 + L2.Z);
+    e2.tri = t2;
+    e2.lam = t2 + 3 * l;
+    e2.tnorm = t2 + 4 * l;
+    e2.flag = reinterpret_cast<int32_t*>(t2 + 4 * l + 1);
+    e2.Uh = reinterpret_cast<double*>(b2 + L2.Uh);
+    e2.sig = reinterpret_cast<double*>(b2 + L2.sig);
+    e2.XU = b2 + L2.XU;
+    e2.XV = b2 + L2.XV;
+    e2.S = b2 + L2.S;
+  }
   for (int side = 0; side < 2; ++side) {
     const double* M = X[side];
     s = tr(M, R3);
-    if (s == RSVD_OK) s = mm(false, M, R3, G, Lg);
+    if (s == RSVD_OK) s = mm(false, M, R3, const_cast<double*>(side == 0 ? e.G : e2.G), Lg);
     if (s != RSVD_OK) return s;
-    for (int stage = 0; stage < 3; ++stage) RSVD_TRY(c.run->eig(stage, e));
-    RSVD_TRY(c.run->copy(CopyParams{e.Uh, X[4 + 2 * side], l * l, nullptr}));
-    RSVD_TRY(c.run->copy(CopyParams{e.lam, X[5 + 2 * side], l, nullptr}));
   }
+  for (int stage = 0; stage < 3; ++stage) RSVD_TRY(launch_eig_pair(stage, e, e2, c.st));
+  const double* W1 = e.Uh;
+  const double* d1 = e.lam;
+  const double* W2 = e2.Uh;
+  const double* d2 = e2.lam;
   // C = R M1^T + M2 Rt^T -> R1
   s = tr(X[0], R3);
   if (s == RSVD_OK) s = mm(false, X[2], R3, R1, l);
   if (s == RSVD_OK) s = tr(X[3], R3);
   if (s == RSVD_OK) s = mm(false, X[1], R3, R1, l, true);
   // Chat = W2^T C W1 -> Rt; Bhat = Chat ./ (d2_i + d1_j); B = W2 Bhat W1^T -> R1
-  if (s == RSVD_OK) s = mm(true, X[6], R1, R2, l);
-  if (s == RSVD_OK) s = mm(false, R2, X[4], Rt, l);
+  if (s == RSVD_OK) s = mm(true, W2, R1, R2, l);
+  if (s == RSVD_OK) s = mm(false, R2, W1, Rt, l);
   if (s != RSVD_OK) return s;
-  RSVD_TRY(launch_sylv_div(Rt, l, X[7], X[5], li, c.st));
-  s = mm(false, X[6], Rt, R2, l);
-  if (s == RSVD_OK) s = tr(X[4], R3);
+  RSVD_TRY(launch_sylv_div(Rt, l, d2, d1, li, c.st));
+  s = mm(false, W2, Rt, R2, l);
+  if (s == RSVD_OK) s = tr(W1, R3);
   if (s == RSVD_OK) s = mm(false, R2, R3, R1, l);
   // the SVD of B from its FP64 Gram B B^T: Ub (XU), S, Ub S^-1 (XV)
   if (s == RSVD_OK) s = tr(R1, R3);

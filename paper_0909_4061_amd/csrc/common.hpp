@@ -188,6 +188,8 @@ constexpr int EIG_LDV = 128;  // row stride of the reflectors (any compiled vari
 int eig_variant(int32_t l);
 int64_t eig_blocks(int stage, const EigParams& p);
 hipError_t launch_eig(int stage, const EigParams& p, hipStream_t st);
+// Two independent problems of the same l, one launch per stage.
+hipError_t launch_eig_pair(int stage, const EigParams& a, const EigParams& b, hipStream_t st);
 hipError_t launch_eig_batched(int stage, int variant, const EigParams* ps, const BlockMap* bm, int64_t nblocks,
                               hipStream_t st);
 

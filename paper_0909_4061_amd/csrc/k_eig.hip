@@ -778,6 +778,33 @@ __global__ __launch_bounds__(256) void eig_fix_batched(const EigParams* __restri
   eig_fix_body<MAXL>(ps[bm[blockIdx.x].item]);
 }
 
+// Two independent problems of one size in one launch per stage (both parameter
+// sets by value): blocks [0, nb0) serve the first, the rest the second.
+template <int MAXL>
+__global__ __launch_bounds__(tri_threads<MAXL>()) void tridiag_pair(const EigParams p0, const EigParams p1) {
+  if (blockIdx.x == 0)
+    tridiag_body<MAXL>(p0);
+  else
+    tridiag_body<MAXL>(p1);
+}
+
+template <int MAXL>
+__global__ __launch_bounds__(256) void tri_eig_pair(const EigParams p0, const EigParams p1, const int nb0) {
+  const int b = (int)blockIdx.x;
+  if (b < nb0)
+    tri_eig_body<MAXL, true>(p0, b);
+  else
+    tri_eig_body<MAXL, true>(p1, b - nb0);
+}
+
+template <int MAXL>
+__global__ __launch_bounds__(256) void eig_fix_pair(const EigParams p0, const EigParams p1) {
+  if (blockIdx.x == 0)
+    eig_fix_body<MAXL>(p0);
+  else
+    eig_fix_body<MAXL>(p1);
+}
+
 bool eig_params_ok(const EigParams& p) {
   return p.l >= 1 && p.l <= 128 && p.k >= 1 && p.k <= p.l && p.Lg >= p.l;
 }
@@ -816,6 +843,27 @@ hipError_t launch_eig(int stage, const EigParams& p, hipStream_t st) {
 #undef RSVD_L1
 #undef RSVD_L2
 #undef RSVD_L3
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_pair(int stage, const EigParams& a, const EigParams& b, hipStream_t st) {
+  if (!eig_params_ok(a) || !eig_params_ok(b) || a.l != b.l || stage < 0 || stage > 2) return hipErrorInvalidValue;
+  const int v = eig_variant(a.l);
+  const int nb0 = (int)tri_eig_blocks(a);
+  const dim3 g2((unsigned)(nb0 + tri_eig_blocks(b)));
+#define RSVD_P1(M) hipLaunchKernelGGL(tridiag_pair<M>, dim3(2), dim3(tri_threads<M>()), 0, st, a, b)
+#define RSVD_P2(M) hipLaunchKernelGGL(tri_eig_pair<M>, g2, dim3(256), 0, st, a, b, nb0)
+#define RSVD_P3(M) hipLaunchKernelGGL(eig_fix_pair<M>, dim3(2), dim3(256), 0, st, a, b)
+  if (stage == 0) {
+    RSVD_EIG_SWITCH(v, RSVD_P1)
+  } else if (stage == 1) {
+    RSVD_EIG_SWITCH(v, RSVD_P2)
+  } else {
+    RSVD_EIG_SWITCH(v, RSVD_P3)
+  }
+#undef RSVD_P1
+#undef RSVD_P2
+#undef RSVD_P3
   return hipGetLastError();
 }
 
