@@ -902,14 +902,16 @@ def main():
     ap.add_argument("--keep-state", action="store_true",
                     help="differentiable workload: the forward keeps its bases for the adjoint instead of the "
                          "adjoint recomputing them")
-    ap.add_argument("--workload", choices=["power", "srft", "batched", "differentiable", "fp64", "psd"],
+    ap.add_argument("--workload", choices=["power", "srft", "batched", "differentiable", "fp64", "psd", "onepass"],
                     default="power",
                     help="power: the power-iteration rSVD (default); srft: SRFT vs Gaussian sketch, "
                          "FP32 32768 x 16384 with a spectral gap, k = 50, p = 78, q = 0; batched: 512 "
                          "uneven FP32 matrices, p = 8, q = 1; differentiable: 32 FP32 4096 x 2048 "
                          "matrices, forward + loss + adjoint; fp64: FP64 2000 x 1000, k = 20, p = 10, "
                          "q = 0 (200 steps unless --steps is given); psd: Stage B for a 16384 x 16384 "
-                         "psd matrix (Algorithms 5.3 and 5.5), k = 100, p = 20")
+                         "psd matrix (Algorithms 5.3 and 5.5), k = 100, p = 20; onepass: the two-sided "
+                         "single pass (Section 5.5) against the two-pass route with q = 0 on the power "
+                         "workload's matrix")
     ap.add_argument("--srft-prec", choices=["bf16x3", "native"], default="bf16x3",
                     help="arithmetic of the GEMMs that stream A in the srft workload")
     ap.add_argument("--calib-copy", action="store_true",
@@ -947,7 +949,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t = time.perf_counter()
-    sigma = spectrum("inv" if args.workload == "power" else "gap", min(m, n))
+    sigma = spectrum("inv" if args.workload in ("power", "onepass") else "gap", min(m, n))
     if args.input == "construct":
         A = build_matrix_torch(m, n, sigma, seed=args.seed, dtype=torch.float32, device=dev)
     else:
@@ -966,6 +968,19 @@ def main():
 
     if args.workload == "srft":
         print(json.dumps(workload_srft(args, A, sigma)))
+        return
+    if args.workload == "onepass":
+        prec = args.only or "bf16x3"
+        res = single_pass_general(A, k, p, sigma, prec, args.steps, args.warmup, args.seed)
+        one = res["onepass"]
+        print(json.dumps({
+            "metric": "two-sided single pass (Section 5.5): time per factorization", "value": one["ms_per_call"],
+            "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": one["ms_per_call"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16" if prec == "bf16x3" else "f32", "prec": prec, "data": "synthetic",
+            "config": {"workload": f"two-sided single pass, FP32 {m}x{n}, sigma_j=1/j, k={k}, p={p}",
+                       "m": m, "n": n, "k": k, "p": p},
+            "paths": res}))
         return
 
     flops = algorithmic_flops(m, n, l, k, q)

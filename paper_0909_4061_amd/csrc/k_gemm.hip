@@ -415,6 +415,52 @@ __device__ __forceinline__ void gemm_f64_body(const GemmParams& p, const int bid
 template <bool TRANS>
 __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmParams p) { gemm_f64_body<TRANS>(p, blockIdx.x); }
 
+// FP64 products of at most 128 x 128 x 128 (the l x l factors of the
+// small-matrix steps): one wave per 16 x 16 tile of the output, operands read
+// straight from memory (they sit in L2), K in steps of 4 in increasing order
+// -- the order of gemm_f64_body, so the sums round the same way.
+constexpr int SMALL_F64_MAX = 128;
+template <bool TRANS>
+__global__ __launch_bounds__(64) void gemm_f64_small_kernel(const GemmParams p) {
+  if (p.gate && *p.gate == 0) return;
+  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + r;  // row of op(A) this lane feeds
+  const int j = (int)blockIdx.y * 16 + r;          // column of X this lane feeds
+  const int K = (int)p.K;
+  const bool iok = i < p.rows, jok = j < p.ncols;
+  const int64_t ic = iok ? i : p.rows - 1;
+  const int jc = jok ? j : p.ncols - 1;
+  const double* __restrict__ a = (const double*)p.A;
+  const double* __restrict__ x = (const double*)p.X;
+  const int nk = (K + 3) / 4;
+  double av[SMALL_F64_MAX / 4], xv[SMALL_F64_MAX / 4];
+#pragma unroll
+  for (int t = 0; t < SMALL_F64_MAX / 4; ++t) {
+    if (t < nk) {
+      const int k = 4 * t + g;
+      const bool kok = k < K;
+      const int64_t kc = kok ? k : K - 1;
+      const double va = TRANS ? a[kc * p.lda + ic] : a[ic * p.lda + kc];
+      const double vx = x[kc * p.ldx + jc];
+      av[t] = (kok && iok) ? va : 0.0;
+      xv[t] = (kok && jok) ? vx : 0.0;
+    }
+  }
+  f64x4 acc{};
+#pragma unroll
+  for (int t = 0; t < SMALL_F64_MAX / 4; ++t)
+    if (t < nk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], xv[t], acc, 0, 0, 0);
+  double* out = (double*)p.out;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t row = (int64_t)blockIdx.x * 16 + 4 * e + g;
+    if (row < p.rows && jok) {
+      const int64_t o = row * p.ldo + j;
+      out[o] = p.accum ? out[o] + acc[e] : acc[e];
+    }
+  }
+}
+
 template <bool TRANS>
 __global__ __launch_bounds__(256, 2) void gemm_f64_batched(const GemmParams* __restrict__ ps, const BlockMap* __restrict__ bm) {
   const BlockMap b = bm[blockIdx.x];
@@ -580,7 +626,15 @@ hipError_t launch_gemm(int dtype, int prec, bool trans, const GemmParams& p, hip
   if (p.rows <= 0) return hipSuccess;
   if (!gemm_params_ok(dtype, prec, p)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)gemm_blocks(dtype, prec, p)), block(256);
-  if (dtype == RSVD_F64) {
+  const bool small_f64 =
+      p.S == 1 && p.rows <= SMALL_F64_MAX && p.K <= SMALL_F64_MAX && p.K >= 1 && p.ncols >= 1;
+  if (dtype == RSVD_F64 && small_f64) {
+    const dim3 gs((unsigned)((p.rows + 15) / 16), (unsigned)((p.ncols + 15) / 16));
+    if (trans)
+      hipLaunchKernelGGL(gemm_f64_small_kernel<true>, gs, dim3(64), 0, st, p);
+    else
+      hipLaunchKernelGGL(gemm_f64_small_kernel<false>, gs, dim3(64), 0, st, p);
+  } else if (dtype == RSVD_F64) {
     if (trans)
       hipLaunchKernelGGL(gemm_f64_kernel<true>, grid, block, 0, st, p);
     else
