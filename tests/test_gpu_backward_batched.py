@@ -151,8 +151,10 @@ def test_backward_batched_full_size_differentiable_workload():
     grads = _batched_grads(As, Ts, ws, [k, k], p, q, seed, prec="bf16x3")
     Gref = _reference(As[1], k, p, q, seed, 1, Ts[1], ws[1], torch.float32)
     err = _rel(grads[1], Gref)
-    # bf16x3 products: x = hi + lo carries a relative error up to 2^-16 per element
-    assert err <= 64.0 * (k + p) * 2.0 ** -16, err
+    print(f"batched backward bf16x3 {m}x{n} k={k}: rel err {err:.3e} ({err / (k + p) / 2.0 ** -16:.3f} l 2^-16)")
+    # bf16x3 products: x = hi + lo carries a relative error up to 2^-16 per element; the bound is
+    # the one of the single-matrix adjoint tests, 2 l 2^-16 (measured here: 0.013 l 2^-16)
+    assert err <= 2.0 * (k + p) * 2.0 ** -16, err
 
 
 def test_backward_batched_kept_matches_recomputation():
