@@ -30,7 +30,8 @@ two relations B (Qt* Omega) ~ Q* Y and B* (Q* Omegat) ~ Qt* Yt
 (two_sided_svd; its SVD then gives U = Q Ub, V = Qt Vb).
 
 Library primitives stand in for single steps only: numpy products, Householder
-QR and SVD (LAPACK), numpy's least-squares solver and Hermitian eigensolver.
+QR and SVD (LAPACK), numpy's least-squares solver and Hermitian eigensolver,
+scipy's Sylvester solver (the normal-equation route to the two-sided core).
 """
 
 import numpy as np
@@ -93,14 +94,25 @@ def two_sided_core(M1, N1, M2, N2):
     return b.reshape(l, lt)
 
 
-def two_sided_svd(A, Omega, Omegat, k):
+def two_sided_core_normal(M1, N1, M2, N2):
+    """The same minimizer from its normal equations (the gradient of the objective set to zero):
+        B (M1 M1*) + (M2 M2*) B = N1 M1* + M2 N2*,
+    a Sylvester equation, solved by scipy's Bartels-Stewart solver.  For large l, where the stacked
+    system of two_sided_core (2 l^2 x l^2) is too slow; squares the conditioning of the relations."""
+    from scipy.linalg import solve_sylvester
+    return solve_sylvester(M2 @ adj(M2), M1 @ adj(M1), N1 @ adj(M1) + M2 @ adj(N2))
+
+
+def two_sided_svd(A, Omega, Omegat, k, solver="lstsq"):
     """The single-pass factorization of a general A: Y = A Omega and Yt = A* Omegat (one pass over A),
     Y = Q R and Yt = Qt Rt (orthonormal bases), B from the two least-squares relations, B = Ub S Vb*,
-    U = Q Ub, V = Qt Vb, truncated to k.  Returns (U (m x k), S (k,), V (n x k))."""
+    U = Q Ub, V = Qt Vb, truncated to k.  Returns (U (m x k), S (k,), V (n x k)).  solver: "lstsq"
+    (two_sided_core) or "normal" (two_sided_core_normal, for large l)."""
     Y = A @ Omega
     Yt = adj(A) @ Omegat
     Q, R = qr_pos(Y)
     Qt, Rt = qr_pos(Yt)
-    B = two_sided_core(adj(Qt) @ Omega, adj(Q) @ Y, adj(Q) @ Omegat, adj(Qt) @ Yt)
+    core = two_sided_core if solver == "lstsq" else two_sided_core_normal
+    B = core(adj(Qt) @ Omega, adj(Q) @ Y, adj(Q) @ Omegat, adj(Qt) @ Yt)
     Ub, S, Vbh = np.linalg.svd(B, full_matrices=False)
     return (Q @ Ub)[:, :k], S[:k], (Qt @ adj(Vbh))[:, :k]

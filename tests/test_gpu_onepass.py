@@ -131,7 +131,8 @@ def _two_sided_case(m, n, sigma, k, p, npd, seed, prec="native"):
     flags = rs.device_status(DEV)
     Om = orsvd.gaussian_test_matrix(n, l, seed + 1, 0, npd)
     Omt = orsvd.gaussian_test_matrix(m, l, seed + 1, 1 << 63, npd)
-    Ur, Sr, Vr = single_pass.two_sided_svd(A64, Om, Omt, k)
+    # the stacked least-squares system has 2 l^2 x l^2 entries: its normal-equation route beyond l = 64
+    Ur, Sr, Vr = single_pass.two_sided_svd(A64, Om, Omt, k, solver="lstsq" if l <= 64 else "normal")
     Q, _ = orsvd.qr_pos(A64 @ Om)
     Qt, _ = orsvd.qr_pos(A64.T @ Omt)
     s1 = np.linalg.svd(Qt.T @ Om, compute_uv=False)[-1]
@@ -170,3 +171,24 @@ def test_svd_onepass_exact_rank_fp64():
     assert np.max(np.abs(S - sigma[:r])) <= 1e-11 * 3.0
     assert np.linalg.norm(A64 - (U * S[None, :]) @ V.T, 2) <= 1e-10 * 3.0
     assert flags & ~rs.RSVD_FLAG_SHIFTED == 0
+
+
+@pytest.mark.parametrize("m,n,k,p,npd", [
+    (200, 300, 10, 8, np.float64),    # wide: the bases of the row space are the longer ones
+    (160, 120, 12, 0, np.float64),    # p = 0: square relations (l x l coefficient matrices)
+    (1000, 777, 24, 9, np.float32),   # ragged sizes, several tiles and a tail in every product
+    (700, 500, 100, 28, np.float32),  # l = 128, the largest the library takes
+])
+def test_svd_onepass_shapes(m, n, k, p, npd):
+    sigma = 1.0 / np.arange(1, min(m, n) + 1, dtype=np.float64) ** 1.5
+    A64, (U, S, V), flags, (Ur, Sr, Vr), amp = _two_sided_case(m, n, sigma, k, p, npd, 97 + k)
+    unit = 4 * 2.0 ** -53 if npd == np.float64 else 2.0 ** -24
+    eps_b = 2 * unit * np.sqrt(max(m, n)) * sigma[0] * amp
+    err = np.max(np.abs(S - Sr))
+    print(f"svd onepass {m}x{n} k={k} p={p}: amplification {amp:.2f}, max |s - ref| {err:.3e} (tol {eps_b:.3e})")
+    assert flags & ~rs.RSVD_FLAG_SHIFTED == 0
+    assert err <= eps_b
+    tol_o = 1e-12 if npd == np.float64 else 1e-4
+    assert np.linalg.norm(U.T @ U - np.eye(k), 2) <= tol_o
+    assert np.linalg.norm(V.T @ V - np.eye(k), 2) <= tol_o
+    assert U.shape == (m, k) and V.shape == (n, k)

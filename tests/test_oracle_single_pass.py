@@ -15,6 +15,8 @@ Section 5.5.
    rectangular relations; a rank-r A is factored exactly from l >= r samples on each side; and the
    least-squares B is within ||(E1, E2)||_F / sqrt(sigma_min(M1)^2 + sigma_min(M2)^2) of Q*A Qt
    (Frobenius), E1, E2 the residuals of the two relations at Q*A Qt.
+5. The normal-equation route to the same core (for large l) agrees with the stacked least-squares
+   solve on well-conditioned relations, and recovers B exactly from consistent ones.
 """
 
 import numpy as np
@@ -123,3 +125,18 @@ def test_two_sided_core_error_bound(decay, seed):
     bound = np.sqrt(np.linalg.norm(E1) ** 2 + np.linalg.norm(E2) ** 2) / np.sqrt(s1 ** 2 + s2 ** 2)
     B = single_pass.two_sided_core(M1, N1, M2, N2)
     assert np.linalg.norm(B - Bt) <= bound * (1 + 1e-10), (np.linalg.norm(B - Bt), bound)
+
+
+@pytest.mark.parametrize("l,lt,s1,s2,consistent", [(5, 4, 6, 7, True), (8, 8, 8, 8, False), (6, 9, 12, 7, False)])
+def test_two_sided_normal_route_matches_lstsq(l, lt, s1, s2, consistent):
+    rng = np.random.default_rng(300 + l + lt)
+    B0 = rng.standard_normal((l, lt))
+    M1 = rng.standard_normal((lt, s1))
+    M2 = rng.standard_normal((l, s2))
+    N1 = B0 @ M1 + (0.0 if consistent else 0.1 * rng.standard_normal((l, s1)))
+    N2 = B0.T @ M2 + (0.0 if consistent else 0.1 * rng.standard_normal((lt, s2)))
+    Bn = single_pass.two_sided_core_normal(M1, N1, M2, N2)
+    Bl = single_pass.two_sided_core(M1, N1, M2, N2)
+    assert np.linalg.norm(Bn - Bl) <= 1e-10 * np.linalg.norm(Bl)
+    if consistent:
+        assert np.linalg.norm(Bn - B0) <= 1e-10 * np.linalg.norm(B0)
