@@ -34,6 +34,16 @@ Generator contract (written out here and implemented twice)
   (the product can round up to n - t when u is within an ulp of 1) and swaps
   perm[t] with perm[j]; R[t] = perm[t].  R lists l distinct coordinates in draw
   order, so the sample is uniform without replacement as Section 4.6 requires.
+* GSRFT (the Givens-chain transform of the remark on random Givens rotations in
+  Section 4.6), chain c = 0 (Theta, D') and c = 1 (Theta', D''):
+    - signs: d_p = 1 - 2 * (w0 & 1), w0 from counter (p, s, 3, c) (D' for c = 0,
+      D'' for c = 1);
+    - angles: theta_j = TWO_PI * u(w0), w0 from counter (j, s, 4, c),
+      j = 0..n-2 (the rotation in the coordinate plane (j, j + 1));
+    - permutation: key_p = ((w0 >> 16) << 16) | p with w0 from counter
+      (p, s, 5, c); pi lists the indices p in increasing order of key_p (the top
+      48 bits of w0, ties broken by p), a uniformly random permutation of [0, n)
+      for n <= 2^16.
 * Streams: s = 0 for a single matrix, s = 10 + b for matrix b of a batch.
 """
 
@@ -52,6 +62,9 @@ TWO_PI = 2.0 * np.pi  # doubling is exact, so this is the double nearest 2*pi
 KIND_GAUSS = 0
 KIND_SRFT_SIGN = 1
 KIND_SRFT_SAMPLE = 2
+KIND_GIVENS_SIGN = 3
+KIND_GIVENS_ANGLE = 4
+KIND_GIVENS_PERM = 5
 
 
 def _mulhilo(a, b):
@@ -147,6 +160,31 @@ def srft_sample(n, l, seed, stream=0):
         perm[step], perm[j] = perm[j], perm[step]
         out.append(perm[step])
     return np.array(out, dtype=np.int64)
+
+
+def givens_signs(n, seed, chain, stream=0):
+    """The +-1 diagonal of GSRFT chain `chain` (D' for 0, D'' for 1), length-n FP64."""
+    p = np.arange(int(n), dtype=np.uint64)
+    w0, _, _, _ = philox4x64(p, np.uint64(stream), np.uint64(KIND_GIVENS_SIGN), np.uint64(chain), seed)
+    return 1.0 - 2.0 * (w0 & np.uint64(1)).astype(np.float64)
+
+
+def givens_angles(n, seed, chain, stream=0):
+    """theta_0 .. theta_{n-2} of GSRFT chain `chain`, uniform on [0, 2 pi), FP64."""
+    j = np.arange(max(int(n) - 1, 0), dtype=np.uint64)
+    w0, _, _, _ = philox4x64(j, np.uint64(stream), np.uint64(KIND_GIVENS_ANGLE), np.uint64(chain), seed)
+    return TWO_PI * uniform_from_word(w0)
+
+
+def givens_permutation(n, seed, chain, stream=0):
+    """pi of GSRFT chain `chain`: the indices p ordered by ((w0 >> 16) << 16) | p (n <= 2^16)."""
+    n = int(n)
+    if n > 1 << 16:
+        raise ValueError("the permutation key holds the index in 16 bits")
+    p = np.arange(n, dtype=np.uint64)
+    w0, _, _, _ = philox4x64(p, np.uint64(stream), np.uint64(KIND_GIVENS_PERM), np.uint64(chain), seed)
+    keys = ((w0 >> np.uint64(16)) << np.uint64(16)) | p
+    return (np.sort(keys) & np.uint64(0xFFFF)).astype(np.int64)
 
 
 def round_to_dtype(x, dtype):
