@@ -78,8 +78,15 @@ enum { RSVD_F32 = 0, RSVD_F64 = 1 };
 /* problem->sketch: the test matrix of Stage A */
 enum {
   RSVD_GAUSSIAN = 0,  /* i.i.d. N(0,1) n x l (Section 4.1) */
-  RSVD_SRFT = 1       /* sqrt(n/l) D F_r R with D = random +-1 signs and F_r the real
+  RSVD_SRFT = 1,      /* sqrt(n/l) D F_r R with D = random +-1 signs and F_r the real
                          orthonormal Fourier basis (Section 4.6); q must be 0 */
+  RSVD_GSRFT = 2      /* D'' Theta' D' Theta (sqrt(n/l) D F_r R): the SRFT behind two chains
+                         of random Givens rotations, each a random permutation followed by
+                         rotations in the planes (j, j + 1) with angles uniform on [0, 2 pi),
+                         and random +-1 diagonals D', D'' (the remark on random Givens
+                         rotations in Section 4.6, real form).  q must be 0; n a power of
+                         two, 8 <= n <= 16384 (FP32) or 8192 (FP64).  The workspace holds a
+                         transformed copy of A (m x n elements) */
 };
 /* problem->prec: arithmetic of the products that stream A (the sketch,
  * power-step and projection GEMMs).  Gram matrices, Cholesky factors and the
@@ -105,7 +112,7 @@ typedef struct rsvd_problem {
   int32_t p;        /* oversampling, p >= 0; l = k + p <= min(m, n) and l <= RSVD_MAX_L */
   int32_t q;        /* power steps, q >= 0 (must be 0 with the SRFT sketch) */
   int32_t dtype;    /* RSVD_F32 or RSVD_F64 */
-  int32_t sketch;   /* RSVD_GAUSSIAN or RSVD_SRFT */
+  int32_t sketch;   /* RSVD_GAUSSIAN, RSVD_SRFT or RSVD_GSRFT */
   int32_t prec;     /* RSVD_NATIVE, RSVD_BF16 or RSVD_BF16X3 (the last two need RSVD_F32) */
   uint64_t seed;    /* Philox4x64-10 key word 0 */
   uint64_t stream_id; /* Philox counter word 1: independent draws for the same seed */

@@ -25,11 +25,11 @@ import torch
 from . import _lib
 from ._lib import (  # noqa: F401
     RSVD_BF16, RSVD_BF16X3, RSVD_F32, RSVD_F64, RSVD_FLAG_NOCONV, RSVD_FLAG_NONFINITE,
-    RSVD_FLAG_SHIFTED, RSVD_GAUSSIAN, RSVD_MAX_L, RSVD_NATIVE, RSVD_SRFT, RsvdError, RsvdProblem,
+    RSVD_FLAG_SHIFTED, RSVD_GAUSSIAN, RSVD_GSRFT, RSVD_MAX_L, RSVD_NATIVE, RSVD_SRFT, RsvdError, RsvdProblem,
 )
 
 PRECISIONS = {"native": RSVD_NATIVE, "bf16": RSVD_BF16, "bf16x3": RSVD_BF16X3}
-SKETCHES = {"gaussian": RSVD_GAUSSIAN, "srft": RSVD_SRFT}
+SKETCHES = {"gaussian": RSVD_GAUSSIAN, "srft": RSVD_SRFT, "gsrft": RSVD_GSRFT}
 _DTYPES = {torch.float32: RSVD_F32, torch.float64: RSVD_F64}
 
 

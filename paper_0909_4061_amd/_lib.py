@@ -21,7 +21,7 @@ RSVD_E_NOCONV = 7
 
 # enums
 RSVD_F32, RSVD_F64 = 0, 1
-RSVD_GAUSSIAN, RSVD_SRFT = 0, 1
+RSVD_GAUSSIAN, RSVD_SRFT, RSVD_GSRFT = 0, 1, 2
 RSVD_NATIVE, RSVD_BF16, RSVD_BF16X3 = 0, 1, 2
 RSVD_FLAG_SHIFTED, RSVD_FLAG_NONFINITE, RSVD_FLAG_NOCONV = 1, 2, 4
 RSVD_MAX_L = 128

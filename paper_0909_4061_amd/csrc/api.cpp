@@ -81,7 +81,7 @@ struct Plan {
   bool stream;  // FP32 data: the A-streaming products take the streaming kernels (X packed first)
   Split nn, tn;
   size_t omega, part, Y, Qt, pack, gpart, G, R1, R2, R3, Rt, Rb, RinvT, XU, XV, Uh, sig, flags, srft_d,
-      srft_R, eigV, eigZ, eigT, omega2, sx, eig2, total;
+      srft_R, eigV, eigZ, eigT, omega2, sx, eig2, gsrft_tab, gsrft_at, total;
 };
 
 bool valid_enum(int32_t v, int32_t lo, int32_t hi) { return v >= lo && v <= hi; }
@@ -90,17 +90,19 @@ rsvd_status validate(const rsvd_problem* pr) {
   if (!pr) return RSVD_E_INVAL;
   if (pr->m < 1 || pr->n < 1 || pr->k < 1 || pr->p < 0 || pr->q < 0) return RSVD_E_INVAL;
   if (pr->lda < pr->n) return RSVD_E_INVAL;
-  if (!valid_enum(pr->dtype, RSVD_F32, RSVD_F64) || !valid_enum(pr->sketch, RSVD_GAUSSIAN, RSVD_SRFT) ||
+  if (!valid_enum(pr->dtype, RSVD_F32, RSVD_F64) || !valid_enum(pr->sketch, RSVD_GAUSSIAN, RSVD_GSRFT) ||
       !valid_enum(pr->prec, RSVD_NATIVE, RSVD_BF16X3))
     return RSVD_E_INVAL;
   const int64_t l = (int64_t)pr->k + pr->p;
   if (l > std::min(pr->m, pr->n)) return RSVD_E_INVAL;
   if (l > RSVD_MAX_L) return RSVD_E_UNSUPPORTED;
   if (pr->dtype == RSVD_F64 && pr->prec != RSVD_NATIVE) return RSVD_E_UNSUPPORTED;
-  if (pr->sketch == RSVD_SRFT) {
+  if (pr->sketch != RSVD_GAUSSIAN) {
     // One row of A, as n/2 complex values, is transformed in a workgroup's LDS.
     const int64_t nmax = int64_t{2} << (pr->dtype == RSVD_F64 ? SRFT_MAX_LOGN_F64 : SRFT_MAX_LOGN_F32);
     if (pr->q != 0 || pr->n < 8 || pr->n > nmax || (pr->n & (pr->n - 1)) != 0) return RSVD_E_UNSUPPORTED;
+    // the Givens chains: a row and its gathered copy in LDS
+    if (pr->sketch == RSVD_GSRFT && !gsrft_shape_ok(pr->dtype, pr->n)) return RSVD_E_UNSUPPORTED;
   }
   return RSVD_OK;
 }
@@ -193,8 +195,11 @@ Plan make_plan(const rsvd_problem* pr, bool batched = false, bool stream = true)
   P.Uh = take(ll8);
   P.sig = take((size_t)P.l * 8);
   P.flags = take(64);
-  P.srft_d = take(pr->sketch == RSVD_SRFT ? (size_t)P.n * 8 : 0);
-  P.srft_R = take(pr->sketch == RSVD_SRFT ? (size_t)P.l * 4 : 0);
+  P.srft_d = take(pr->sketch != RSVD_GAUSSIAN ? (size_t)P.n * 8 : 0);
+  P.srft_R = take(pr->sketch != RSVD_GAUSSIAN ? (size_t)P.l * 4 : 0);
+  // the Givens-chain sketch: its tables and the transformed copy of A
+  P.gsrft_tab = take(pr->sketch == RSVD_GSRFT ? gsrft_table_bytes(P.n, P.esize) : 0);
+  P.gsrft_at = take(pr->sketch == RSVD_GSRFT ? (size_t)P.m * P.n * es : 0);
   // eigensolver of the small SVD (FP32 data) and of the symmetric Stage B (a
   // single problem of either type): reflectors, eigenvectors, then d, e, tau,
   // the eigenvalues, the norm bound and the flags
@@ -589,13 +594,24 @@ rsvd_status reduce_parts(const Ctx& c, const Split& sp, int64_t rows, void* out)
 // partials for the Gaussian GEMM when the plan splits it).
 rsvd_status sketch(const Ctx& c, const rsvd_problem* pr, const void* A, void* y) {
   const Plan& P = c.P;
-  if (pr->sketch == RSVD_SRFT) {
+  if (pr->sketch != RSVD_GAUSSIAN) {
     if (c.run->records()) return RSVD_E_UNSUPPORTED;
+    const void* src = A;
+    int64_t ld = pr->lda;
+    if (pr->sketch == RSVD_GSRFT) {
+      // A D'' Theta' D' Theta into the workspace copy, which the SRFT then sketches
+      void* tab = c.at<void>(P.gsrft_tab);
+      void* at = c.at<void>(P.gsrft_at);
+      RSVD_TRY(launch_gsrft_draw(pr->dtype, tab, pr->n, pr->seed, pr->stream_id, c.st));
+      RSVD_TRY(launch_gsrft_rows(pr->dtype, A, pr->lda, pr->m, pr->n, tab, at, c.st));
+      src = at;
+      ld = pr->n;
+    }
     double* d = c.at<double>(P.srft_d);
     int32_t* R = c.at<int32_t>(P.srft_R);
     RSVD_TRY(launch_srft_draw(d, R, pr->n, (int32_t)P.l, pr->seed, pr->stream_id, c.st));
     Timed t_(c.h, RSVD_KERNEL_SRFT, c.st);
-    RSVD_TRY(launch_srft_rows(pr->dtype, A, pr->lda, pr->m, pr->n, (int32_t)P.l, d, R, y, c.st));
+    RSVD_TRY(launch_srft_rows(pr->dtype, src, ld, pr->m, pr->n, (int32_t)P.l, d, R, y, c.st));
     return RSVD_OK;
   }
   void* omega = c.at<void>(P.omega);
@@ -2149,7 +2165,7 @@ rsvd_status rsvd_sketch(rsvd_handle h, const rsvd_problem* pr, const void* A, vo
   DirectRunner dr(h, stream);
   const Ctx c{pro.plan, static_cast<char*>(ws), stream, h->status, h, &dr};
   rsvd_status s = sketch(c, pr, A, Y);
-  if (s != RSVD_OK || pr->sketch == RSVD_SRFT || c.P.nn.S == 1) return s;
+  if (s != RSVD_OK || pr->sketch != RSVD_GAUSSIAN || c.P.nn.S == 1) return s;
   return reduce_parts(c, c.P.nn, pr->m, Y);
 }
 

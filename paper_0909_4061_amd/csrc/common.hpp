@@ -145,6 +145,25 @@ hipError_t launch_omega(int dtype, void* omega, int64_t n, int32_t l, uint64_t s
 hipError_t launch_srft_draw(double* d, int32_t* R, int64_t n, int32_t l, uint64_t seed,
                             uint64_t stream_id, hipStream_t st);
 
+// Givens-chain structured test matrix: the tables of its two chains (c = 0:
+// D', Theta; c = 1: D'', Theta') in a workspace region of gsrft_table_bytes(n,
+// element size), and the pretransform out (m x n, row stride n) = A D'' Theta'
+// D' Theta, which the SRFT kernels then sketch.  n a power of two, 8 <= n <=
+// 16384 (FP32) or 8192 (FP64): a row and its gathered copy in one workgroup's LDS.
+constexpr int GSRFT_MAX_N = 16384;
+template <typename T>
+struct GsrftTables {
+  uint64_t* key[2];  // sort keys of the permutations
+  T* sign[2];        // +-1
+  T* cs[2];          // (cos theta_j, sin theta_j) pairs, j < n - 1; (1, 0) at j = n - 1
+  int32_t* perm[2];  // pi: (x Pi)_j = x_pi(j)
+};
+size_t gsrft_table_bytes(int64_t n, int esize);
+bool gsrft_shape_ok(int dtype, int64_t n);
+hipError_t launch_gsrft_draw(int dtype, void* tables, int64_t n, uint64_t seed, uint64_t sid, hipStream_t st);
+hipError_t launch_gsrft_rows(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, void* tables, void* out,
+                             hipStream_t st);
+
 // SRFT sketch Y (m x l, row-major) = A Omega for the real SRFT with signs d
 // and sampled frequencies R; n = 2^(LOGN+1) with 2 <= LOGN <= SRFT_MAX_LOGN_*.
 constexpr int SRFT_MAX_LOGN_F32 = 13;  // n <= 16384

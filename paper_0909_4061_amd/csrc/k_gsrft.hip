@@ -1,0 +1,260 @@
+// The structured test matrix built from chains of random Givens rotations
+// (the remark on random Givens rotations in Section 4.6), real form:
+//     Omega = D'' Theta' D' Theta (sqrt(n/l) D F_r R),
+//     Theta = Pi G(1, 2; theta_1) ... G(n-1, n; theta_{n-1}),
+// with D', D'' random +-1 diagonals, Pi a uniformly random permutation acting
+// on a row vector as the gather (x Pi)_j = x_pi(j), and G(i, k; theta) the
+// rotation that maps entries (x_i, x_k) of a row vector to
+// (c x_i - s x_k, s x_i + c x_k).  The SRFT kernels supply D F_r R; this file
+// applies the part in front of them, T = D'' Theta' D' Theta, to every row of
+// A, into a copy of A that the SRFT kernel then reads.
+//
+// Draws (the generator contract, chain c = 0 for (D', Theta), c = 1 for
+// (D'', Theta')): sign p from counter (p, s, 3, c), d = 1 - 2 (w0 & 1); angle j
+// from counter (j, s, 4, c), theta = 2 pi u(w0); permutation key p from
+// counter (p, s, 5, c), key = ((w0 >> 16) << 16) | p, pi = the indices in
+// increasing key order.
+//
+//   gsrft_table_kernel : signs, (cos, sin) pairs and permutation keys.
+//   gsrft_sort_kernel  : one workgroup per chain sorts the n keys in LDS
+//                        (bitonic; n is a power of two) into pi.
+//   gsrft_rows_kernel  : one row of A at a time in LDS: signs, gather, the
+//                        rotation chain, for each chain in turn.  The chain is
+//                        the affine recurrence
+//                            v_0 = x_0,  v_{j+1} = s_j v_j + c_j x_{j+1},
+//                            out_j = c_j v_j - s_j x_{j+1},  out_{n-1} = v_{n-1}
+//                        (the rotation j acts on the running value v_j and the
+//                        untouched x_{j+1}); each thread composes the affine maps
+//                        of its segment of S = n / 256 steps, a scan over the
+//                        256 segment maps gives every segment's starting value,
+//                        and each thread then replays its segment.  The step
+//                        past the end is padded with (c, s) = (1, 0), x_n = 0.
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace rsvd {
+
+namespace {
+
+constexpr double kTwoPiG = 0x1.921fb54442d18p+2;  // the double nearest 2*pi
+constexpr int GSRFT_THREADS = 256;
+
+template <typename T>
+__global__ __launch_bounds__(256) void gsrft_table_kernel(GsrftTables<T> t, int64_t n, uint64_t seed, uint64_t sid) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = (int)blockIdx.y;
+  if (p >= n) return;
+  T* sign = c == 0 ? t.sign[0] : t.sign[1];
+  T* cs = c == 0 ? t.cs[0] : t.cs[1];
+  uint64_t* key = c == 0 ? t.key[0] : t.key[1];
+  const Philox4 ws = philox4x64_10((uint64_t)p, sid, 3, (uint64_t)c, seed, 0);
+  sign[p] = (T)(1.0 - 2.0 * (double)(ws.w[0] & 1));
+  T cs0 = (T)1, cs1 = (T)0;  // the padded step past the end
+  if (p < n - 1) {
+    const Philox4 wa = philox4x64_10((uint64_t)p, sid, 4, (uint64_t)c, seed, 0);
+    const double th = kTwoPiG * philox_uniform(wa.w[0]);
+    cs0 = (T)cos(th);
+    cs1 = (T)sin(th);
+  }
+  cs[2 * p] = cs0;
+  cs[2 * p + 1] = cs1;
+  const Philox4 wp = philox4x64_10((uint64_t)p, sid, 5, (uint64_t)c, seed, 0);
+  key[p] = ((wp.w[0] >> 16) << 16) | (uint64_t)p;
+}
+
+// n <= GSRFT_MAX_N, a power of two
+__global__ __launch_bounds__(1024) void gsrft_sort_kernel(const uint64_t* __restrict__ key0,
+                                                         const uint64_t* __restrict__ key1, int32_t* perm0,
+                                                         int32_t* perm1, int n) {
+  __shared__ uint64_t buf[GSRFT_MAX_N];
+  const uint64_t* key = blockIdx.x == 0 ? key0 : key1;
+  int32_t* perm = blockIdx.x == 0 ? perm0 : perm1;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = key[i];
+  __syncthreads();
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = buf[i], b = buf[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            buf[i] = b;
+            buf[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = (int32_t)(buf[i] & 0xFFFFull);
+}
+
+// The rotation chain of one row in LDS (see the file comment).  S = n / 256 steps per thread
+// (S = 1 and n threads when n < 256); SMAX its compile-time bound.
+template <typename T, int SMAX>
+__device__ __forceinline__ void rotation_chain(T* buf, const T* __restrict__ cs, const int n, T* sp, T* sq) {
+  const int tid = threadIdx.x;
+  const int S = n >= GSRFT_THREADS ? n / GSRFT_THREADS : 1;
+  const int nact = n / S;
+  const bool act = tid < nact;
+  const int j0 = tid * S;
+  T c[SMAX], s[SMAX], xv[SMAX];
+  T x0 = buf[0];
+#pragma unroll
+  for (int i = 0; i < SMAX; ++i) {
+    if (i < S && act) {
+      const int j = j0 + i;
+      c[i] = cs[2 * j];
+      s[i] = cs[2 * j + 1];
+      xv[i] = j + 1 < n ? buf[j + 1] : (T)0;
+    } else {
+      c[i] = (T)1;
+      s[i] = (T)0;
+      xv[i] = (T)0;
+    }
+  }
+  // this segment's map v -> P v + Q
+  T P = (T)1, Q = (T)0;
+#pragma unroll
+  for (int i = 0; i < SMAX; ++i) {
+    if (i < S) {
+      P = s[i] * P;
+      Q = s[i] * Q + c[i] * xv[i];
+    }
+  }
+  __syncthreads();  // every read of buf is done: segments may now be overwritten
+  if (act) {
+    sp[tid] = P;
+    sq[tid] = Q;
+  }
+  __syncthreads();
+  // inclusive scan of the maps: I_t = map_t o ... o map_0 (Hillis-Steele, double-buffered)
+  int cur = 0;
+  for (int off = 1; off < nact; off <<= 1) {
+    const T* pin = sp + cur * GSRFT_THREADS;
+    const T* qin = sq + cur * GSRFT_THREADS;
+    T* pout = sp + (cur ^ 1) * GSRFT_THREADS;
+    T* qout = sq + (cur ^ 1) * GSRFT_THREADS;
+    if (act) {
+      T pt = pin[tid], qt = qin[tid];
+      if (tid >= off) {
+        const T pe = pin[tid - off], qe = qin[tid - off];
+        qt = pt * qe + qt;
+        pt = pt * pe;
+      }
+      pout[tid] = pt;
+      qout[tid] = qt;
+    }
+    cur ^= 1;
+    __syncthreads();
+  }
+  if (act) {
+    T v = x0;
+    if (tid > 0) v = sp[cur * GSRFT_THREADS + tid - 1] * x0 + sq[cur * GSRFT_THREADS + tid - 1];
+#pragma unroll
+    for (int i = 0; i < SMAX; ++i) {
+      if (i < S) {
+        buf[j0 + i] = c[i] * v - s[i] * xv[i];
+        v = s[i] * v + c[i] * xv[i];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+constexpr int gsrft_lds_n() {
+  return 65536 / (int)sizeof(T);  // two row buffers of 64 KB
+}
+
+template <typename T>
+__global__ __launch_bounds__(GSRFT_THREADS) void gsrft_rows_kernel(const T* __restrict__ A, int64_t lda, int64_t m,
+                                                                  int n, GsrftTables<T> t, T* __restrict__ out) {
+  constexpr int NMAX = gsrft_lds_n<T>();
+  constexpr int SMAX = NMAX / GSRFT_THREADS;
+  __shared__ __attribute__((aligned(16))) T b0[NMAX];
+  __shared__ __attribute__((aligned(16))) T b1[NMAX];
+  __shared__ T sp[2 * GSRFT_THREADS], sq[2 * GSRFT_THREADS];
+  const int tid = threadIdx.x;
+  for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
+    const T* a = A + r * lda;
+    // D'' and the gather of Pi': b1[j] = d''[pi'(j)] a[pi'(j)]
+    for (int p = tid; p < n; p += GSRFT_THREADS) b0[p] = a[p] * t.sign[1][p];
+    __syncthreads();
+    for (int j = tid; j < n; j += GSRFT_THREADS) b1[j] = b0[t.perm[1][j]];
+    __syncthreads();
+    rotation_chain<T, SMAX>(b1, t.cs[1], n, sp, sq);
+    // D' and the gather of Pi: b0[j] = d'[pi(j)] b1[pi(j)]
+    for (int j = tid; j < n; j += GSRFT_THREADS) {
+      const int q = t.perm[0][j];
+      b0[j] = b1[q] * t.sign[0][q];
+    }
+    __syncthreads();
+    rotation_chain<T, SMAX>(b0, t.cs[0], n, sp, sq);
+    T* o = out + r * (int64_t)n;
+    for (int p = tid; p < n; p += GSRFT_THREADS) o[p] = b0[p];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t draw_t(GsrftTables<T> t, int64_t n, uint64_t seed, uint64_t sid, hipStream_t st) {
+  hipLaunchKernelGGL(gsrft_table_kernel<T>, dim3((unsigned)((n + 255) / 256), 2), dim3(256), 0, st, t, n, seed, sid);
+  hipLaunchKernelGGL(gsrft_sort_kernel, dim3(2), dim3(1024), 0, st, t.key[0], t.key[1], t.perm[0], t.perm[1], (int)n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t gsrft_table_bytes(int64_t n, int esize) {
+  // per chain: n signs, n (cos, sin) pairs (element type), n keys, n permutation entries
+  return 2 * (size_t)n * (3 * (size_t)esize + 8 + 4) + 64;
+}
+
+template <typename T>
+GsrftTables<T> gsrft_tables(void* base, int64_t n) {
+  GsrftTables<T> t;
+  char* b = static_cast<char*>(base);
+  for (int c = 0; c < 2; ++c) {
+    t.key[c] = reinterpret_cast<uint64_t*>(b);
+    b += (size_t)n * 8;
+  }
+  for (int c = 0; c < 2; ++c) {
+    t.sign[c] = reinterpret_cast<T*>(b);
+    b += (size_t)n * sizeof(T);
+    t.cs[c] = reinterpret_cast<T*>(b);
+    b += 2 * (size_t)n * sizeof(T);
+  }
+  for (int c = 0; c < 2; ++c) {
+    t.perm[c] = reinterpret_cast<int32_t*>(b);
+    b += (size_t)n * 4;
+  }
+  return t;
+}
+
+bool gsrft_shape_ok(int dtype, int64_t n) {
+  const int64_t nmax = dtype == RSVD_F64 ? gsrft_lds_n<double>() : gsrft_lds_n<float>();
+  return n >= 8 && n <= nmax && n <= GSRFT_MAX_N && (n & (n - 1)) == 0;
+}
+
+hipError_t launch_gsrft_draw(int dtype, void* tables, int64_t n, uint64_t seed, uint64_t sid, hipStream_t st) {
+  if (!gsrft_shape_ok(dtype, n)) return hipErrorInvalidValue;
+  if (dtype == RSVD_F64) return draw_t(gsrft_tables<double>(tables, n), n, seed, sid, st);
+  return draw_t(gsrft_tables<float>(tables, n), n, seed, sid, st);
+}
+
+hipError_t launch_gsrft_rows(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, void* tables, void* out,
+                             hipStream_t st) {
+  if (!gsrft_shape_ok(dtype, n) || lda < n || m < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(m < 512 ? m : 512));
+  if (dtype == RSVD_F64)
+    hipLaunchKernelGGL(gsrft_rows_kernel<double>, grid, dim3(GSRFT_THREADS), 0, st, (const double*)A, lda, m, (int)n,
+                       gsrft_tables<double>(tables, n), (double*)out);
+  else
+    hipLaunchKernelGGL(gsrft_rows_kernel<float>, grid, dim3(GSRFT_THREADS), 0, st, (const float*)A, lda, m, (int)n,
+                       gsrft_tables<float>(tables, n), (float*)out);
+  return hipGetLastError();
+}
+
+}  // namespace rsvd

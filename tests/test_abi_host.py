@@ -71,6 +71,14 @@ def _prob(**kw):
     ({"m": 40000, "n": 32768, "sketch": "srft", "dtype": "f32"}, 4),
     ({"m": 8, "n": 8, "k": 4, "p": 4, "sketch": "srft"}, 0),
     ({"m": 8, "n": 4, "k": 2, "p": 2, "sketch": "srft"}, 4),
+    # Givens-chain sketch: the SRFT's constraints
+    ({"n": 1024, "sketch": "gsrft"}, 0),
+    ({"n": 1024, "sketch": "gsrft", "q": 1}, 4),
+    ({"n": 1000, "sketch": "gsrft"}, 4),
+    ({"n": 8192, "sketch": "gsrft"}, 0),
+    ({"m": 20000, "n": 16384, "sketch": "gsrft"}, 4),
+    ({"m": 20000, "n": 16384, "sketch": "gsrft", "dtype": "f32"}, 0),
+    ({"m": 8, "n": 8, "k": 4, "p": 4, "sketch": "gsrft"}, 0),
 ])
 def test_validate(lib, kw, expect):
     import torch
