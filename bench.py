@@ -234,7 +234,7 @@ def run_srft_workload(A, k, p, prec, steps, warmup, seed):
     V = torch.empty(n, k, dtype=A.dtype, device=dev)
     stream = torch.cuda.current_stream(dev)
     out = {}
-    for sketch in ("srft", "gaussian"):
+    for sketch in ("srft", "gaussian", "gsrft"):
         pr = rs.problem(m, n, k, p, 0, dtype=A.dtype, sketch=sketch, prec=prec, seed=seed, lda=A.stride(0))
         ws = rs.Workspace(pr, dev)
         kw = dict(sketch=sketch, prec=prec, seed=seed, ws=ws)
@@ -251,7 +251,7 @@ def run_srft_workload(A, k, p, prec, steps, warmup, seed):
             stage_b()
         torch.cuda.synchronize()
         rs.profile_enable(16 * max(steps, 1), dev)
-        rs.profile_select(["srft", "stream_nn", "stream_tn"], dev)
+        rs.profile_select(["srft", "gsrft", "stream_nn", "stream_tn"], dev)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
         torch.cuda.synchronize()
         ev[0].record(stream)
@@ -273,6 +273,7 @@ def run_srft_workload(A, k, p, prec, steps, warmup, seed):
         flags = rs.device_status(dev)
         out[sketch] = dict(ms_per_step=total_ms, stage_a_ms=a_ms, prof=prof, breakdown=breakdown, flags=flags,
                            U=U.clone(), S=S.clone(), V=V.clone())
+        del ws
     return out
 
 
@@ -301,7 +302,7 @@ def workload_srft(args, A, sigma):
     for sk, r in res.items():
         err = spectral_norm_residual(A, r["U"], r["S"], r["V"]) / sigma[k]
         sig_err = float(np.max(np.abs(r["S"].double().cpu().numpy() - sigma[:k]) / sigma[:k]))
-        fl = srft_flops(m, n, l, k) if sk == "srft" else gflops
+        fl = srft_flops(m, n, l, k) if sk != "gaussian" else gflops
         s = r["ms_per_step"] / 1e3
         paths[sk] = {"ms_per_step": r["ms_per_step"], "stage_a_ms": r["stage_a_ms"], "tflops": fl / s / 1e12,
                      "a_read_gbs_stage_a": 4.0 * m * n / (r["stage_a_ms"] / 1e3) / 1e9,
@@ -319,9 +320,22 @@ def workload_srft(args, A, sigma):
                    "m": m, "n": n, "k": k, "p": p, "q": 0, "sketch": "srft"},
         "err_ratio": hp["err_ratio"], "roofline": srft_roofline(res["srft"], m, n, l),
         "stage_a_speedup_vs_gaussian": paths["gaussian"]["stage_a_ms"] / hp["stage_a_ms"],
+        "gsrft_pretransform": gsrft_roofline(res["gsrft"], m, n),
         "paths": paths,
     }
     return line
+
+
+def gsrft_roofline(res, m, n):
+    """The Givens-chain pretransform kernel: A read once and its transformed copy written once
+    (8 m n bytes for FP32; the tables, 72 n bytes, are read from L2 by every row)."""
+    launches, total_ms = res["prof"]["gsrft"]
+    avg_s = total_ms / launches / 1e3
+    bytes_launch = 8.0 * m * n
+    achieved = bytes_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "gsrft_rows_f32", "launches": launches,
+            "avg_us": avg_s * 1e6, "per_launch": {"bytes": bytes_launch}}
 
 
 def workload_psd(args):
@@ -836,8 +850,10 @@ def compact_sub_workloads(args):
         return {"srft": {x: d["paths"]["srft"][x] for x in ("ms_per_step", "stage_a_ms", "err_ratio", "tflops")},
                 "gaussian": {x: d["paths"]["gaussian"][x] for x in ("ms_per_step", "stage_a_ms", "err_ratio",
                                                                     "tflops")},
+                "gsrft": {x: d["paths"]["gsrft"][x] for x in ("ms_per_step", "stage_a_ms", "err_ratio", "tflops")},
                 "stage_a_speedup_vs_gaussian": d["stage_a_speedup_vs_gaussian"],
                 "roofline_srft_kernel": {x: d["roofline"][x] for x in ("achieved", "frac", "avg_us")},
+                "roofline_gsrft_pretransform": {x: d["gsrft_pretransform"][x] for x in ("achieved", "frac", "avg_us")},
                 "steps": s2.steps}
 
     def batched():

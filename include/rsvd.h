@@ -494,7 +494,8 @@ enum {
   RSVD_KERNEL_PACK = 6,       /* packing of the l-column operand before a streaming GEMM */
   RSVD_KERNEL_SRFT = 7,       /* SRFT sketch: one FFT per row of A D, sampled */
   RSVD_KERNEL_EIG = 8,        /* l x l symmetric eigensolver of B B* (small SVD of FP32 data) */
-  RSVD_KERNEL_KINDS = 9
+  RSVD_KERNEL_GSRFT = 9,      /* the Givens chains in front of the SRFT, one row of A at a time */
+  RSVD_KERNEL_KINDS = 10
 };
 
 /* capacity > 0: create `capacity` pairs of hipEvents (an allocation made here,

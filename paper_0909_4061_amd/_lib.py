@@ -38,7 +38,7 @@ EXPORTS = [
     "rsvd_profile_enable", "rsvd_profile_select", "rsvd_profile_read", "rsvd_probe_hbm_read", "rsvd_probe_mfma",
     "rsvd_eigh", "rsvd_nystrom", "rsvd_eigh_onepass", "rsvd_svd_onepass",
 ]
-KERNEL_KINDS = ["stream_nn", "stream_tn", "small_gemm", "gram", "chol", "jacobi", "pack", "srft", "eig"]
+KERNEL_KINDS = ["stream_nn", "stream_tn", "small_gemm", "gram", "chol", "jacobi", "pack", "srft", "eig", "gsrft"]
 
 
 class RsvdProblem(ctypes.Structure):

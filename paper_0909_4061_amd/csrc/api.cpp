@@ -603,7 +603,10 @@ rsvd_status sketch(const Ctx& c, const rsvd_problem* pr, const void* A, void* y)
       void* tab = c.at<void>(P.gsrft_tab);
       void* at = c.at<void>(P.gsrft_at);
       RSVD_TRY(launch_gsrft_draw(pr->dtype, tab, pr->n, pr->seed, pr->stream_id, c.st));
-      RSVD_TRY(launch_gsrft_rows(pr->dtype, A, pr->lda, pr->m, pr->n, tab, at, c.st));
+      {
+        Timed t_(c.h, RSVD_KERNEL_GSRFT, c.st);
+        RSVD_TRY(launch_gsrft_rows(pr->dtype, A, pr->lda, pr->m, pr->n, tab, at, c.st));
+      }
       src = at;
       ld = pr->n;
     }

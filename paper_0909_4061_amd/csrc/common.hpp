@@ -156,6 +156,7 @@ struct GsrftTables {
   uint64_t* key[2];  // sort keys of the permutations
   T* sign[2];        // +-1
   T* cs[2];          // (cos theta_j, sin theta_j) pairs, j < n - 1; (1, 0) at j = n - 1
+  T* psign[2];       // sign[pi(j)]
   int32_t* perm[2];  // pi: (x Pi)_j = x_pi(j)
 };
 size_t gsrft_table_bytes(int64_t n, int esize);

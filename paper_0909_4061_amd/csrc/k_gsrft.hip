@@ -19,14 +19,14 @@
 //   gsrft_sort_kernel  : one workgroup per chain sorts the n keys in LDS
 //                        (bitonic; n is a power of two) into pi.
 //   gsrft_rows_kernel  : one row of A at a time in LDS: signs, gather, the
-//                        rotation chain, for each chain in turn.  The chain is
+//                        rotation chain, for each chain in turn (512 threads).  The chain is
 //                        the affine recurrence
 //                            v_0 = x_0,  v_{j+1} = s_j v_j + c_j x_{j+1},
 //                            out_j = c_j v_j - s_j x_{j+1},  out_{n-1} = v_{n-1}
 //                        (the rotation j acts on the running value v_j and the
 //                        untouched x_{j+1}); each thread composes the affine maps
-//                        of its segment of S = n / 256 steps, a scan over the
-//                        256 segment maps gives every segment's starting value,
+//                        of its segment of S = n / 512 steps, a scan over the
+//                        512 segment maps gives every segment's starting value,
 //                        and each thread then replays its segment.  The step
 //                        past the end is padded with (c, s) = (1, 0), x_n = 0.
 #include "common.hpp"
@@ -37,7 +37,7 @@ namespace rsvd {
 namespace {
 
 constexpr double kTwoPiG = 0x1.921fb54442d18p+2;  // the double nearest 2*pi
-constexpr int GSRFT_THREADS = 256;
+constexpr int GSRFT_THREADS = 512;
 
 template <typename T>
 __global__ __launch_bounds__(256) void gsrft_table_kernel(GsrftTables<T> t, int64_t n, uint64_t seed, uint64_t sid) {
@@ -63,12 +63,13 @@ __global__ __launch_bounds__(256) void gsrft_table_kernel(GsrftTables<T> t, int6
 }
 
 // n <= GSRFT_MAX_N, a power of two
-__global__ __launch_bounds__(1024) void gsrft_sort_kernel(const uint64_t* __restrict__ key0,
-                                                         const uint64_t* __restrict__ key1, int32_t* perm0,
-                                                         int32_t* perm1, int n) {
+template <typename T>
+__global__ __launch_bounds__(1024) void gsrft_sort_kernel(GsrftTables<T> t, int n) {
   __shared__ uint64_t buf[GSRFT_MAX_N];
-  const uint64_t* key = blockIdx.x == 0 ? key0 : key1;
-  int32_t* perm = blockIdx.x == 0 ? perm0 : perm1;
+  const uint64_t* key = blockIdx.x == 0 ? t.key[0] : t.key[1];
+  int32_t* perm = blockIdx.x == 0 ? t.perm[0] : t.perm[1];
+  const T* sign = blockIdx.x == 0 ? t.sign[0] : t.sign[1];
+  T* psign = blockIdx.x == 0 ? t.psign[0] : t.psign[1];
   for (int i = threadIdx.x; i < n; i += blockDim.x) buf[i] = key[i];
   __syncthreads();
   for (int k = 2; k <= n; k <<= 1) {
@@ -87,41 +88,55 @@ __global__ __launch_bounds__(1024) void gsrft_sort_kernel(const uint64_t* __rest
       __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = (int32_t)(buf[i] & 0xFFFFull);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int q = (int)(buf[i] & 0xFFFFull);
+    perm[i] = q;
+    psign[i] = sign[q];
+  }
 }
 
-// The rotation chain of one row in LDS (see the file comment).  S = n / 256 steps per thread
-// (S = 1 and n threads when n < 256); SMAX its compile-time bound.
-template <typename T, int SMAX>
+template <typename T> struct GVec2;
+template <> struct GVec2<float> { typedef float __attribute__((ext_vector_type(2))) type; };
+template <> struct GVec2<double> { typedef double __attribute__((ext_vector_type(2))) type; };
+
+// The rotation chain of one row in LDS (see the file comment).  S steps per thread, n / S threads
+// (all of them when n >= GSRFT_THREADS * S; S = 1 and n threads for n < GSRFT_THREADS).  Loads are
+// branch-free (clamped indices, values masked afterwards) and issued a group at a time; the
+// (cos, sin) pairs are read again for the replay rather than held (they would not fit in registers
+// at S = 32).
+template <typename T, int S>
 __device__ __forceinline__ void rotation_chain(T* buf, const T* __restrict__ cs, const int n, T* sp, T* sq) {
+  typedef typename GVec2<T>::type V;
+  constexpr int G = S < 8 ? S : 8;  // steps whose (cos, sin) and x are loaded together
   const int tid = threadIdx.x;
-  const int S = n >= GSRFT_THREADS ? n / GSRFT_THREADS : 1;
   const int nact = n / S;
   const bool act = tid < nact;
-  const int j0 = tid * S;
-  T c[SMAX], s[SMAX], xv[SMAX];
-  T x0 = buf[0];
-#pragma unroll
-  for (int i = 0; i < SMAX; ++i) {
-    if (i < S && act) {
-      const int j = j0 + i;
-      c[i] = cs[2 * j];
-      s[i] = cs[2 * j + 1];
-      xv[i] = j + 1 < n ? buf[j + 1] : (T)0;
-    } else {
-      c[i] = (T)1;
-      s[i] = (T)0;
-      xv[i] = (T)0;
-    }
-  }
+  const int j0 = act ? tid * S : 0;
+  const V* csv = reinterpret_cast<const V*>(cs) + j0;
+  const T x0 = buf[0];
+  // x_{j+1} of the segment's last step is the next segment's first entry (zero past the end): kept
+  // in a register, since the next thread overwrites it; the others are re-read from this thread's
+  // own segment, which only this thread writes
+  const int jl = j0 + S;
+  const T xl = buf[jl < n ? jl : n - 1];
+  const T xlast = jl < n ? xl : (T)0;
   // this segment's map v -> P v + Q
   T P = (T)1, Q = (T)0;
 #pragma unroll
-  for (int i = 0; i < SMAX; ++i) {
-    if (i < S) {
-      P = s[i] * P;
-      Q = s[i] * Q + c[i] * xv[i];
+  for (int g = 0; g < S; g += G) {
+    V cv[G];
+    T x[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      cv[i] = csv[g + i];
+      x[i] = g + i < S - 1 ? buf[j0 + g + i + 1] : xlast;
     }
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      P = cv[i].y * P;
+      Q = cv[i].y * Q + cv[i].x * x[i];
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();  // every read of buf is done: segments may now be overwritten
   if (act) {
@@ -153,11 +168,20 @@ __device__ __forceinline__ void rotation_chain(T* buf, const T* __restrict__ cs,
     T v = x0;
     if (tid > 0) v = sp[cur * GSRFT_THREADS + tid - 1] * x0 + sq[cur * GSRFT_THREADS + tid - 1];
 #pragma unroll
-    for (int i = 0; i < SMAX; ++i) {
-      if (i < S) {
-        buf[j0 + i] = c[i] * v - s[i] * xv[i];
-        v = s[i] * v + c[i] * xv[i];
+    for (int g = 0; g < S; g += G) {
+      V cv[G];
+      T x[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        cv[i] = csv[g + i];
+        x[i] = g + i < S - 1 ? buf[j0 + g + i + 1] : xlast;
       }
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        buf[j0 + g + i] = cv[i].x * v - cv[i].y * x[i];
+        v = cv[i].y * v + cv[i].x * x[i];
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   __syncthreads();
@@ -168,32 +192,84 @@ constexpr int gsrft_lds_n() {
   return 65536 / (int)sizeof(T);  // two row buffers of 64 KB
 }
 
-template <typename T>
+template <typename T, int S>
 __global__ __launch_bounds__(GSRFT_THREADS) void gsrft_rows_kernel(const T* __restrict__ A, int64_t lda, int64_t m,
                                                                   int n, GsrftTables<T> t, T* __restrict__ out) {
   constexpr int NMAX = gsrft_lds_n<T>();
-  constexpr int SMAX = NMAX / GSRFT_THREADS;
   __shared__ __attribute__((aligned(16))) T b0[NMAX];
   __shared__ __attribute__((aligned(16))) T b1[NMAX];
   __shared__ T sp[2 * GSRFT_THREADS], sq[2 * GSRFT_THREADS];
   const int tid = threadIdx.x;
+  // element p = tid + it * GSRFT_THREADS, it < S: for S > 1, n = S * GSRFT_THREADS exactly (n is a
+  // power of two), so every p is in range; for S = 1 (n <= GSRFT_THREADS) threads past n idle.
+  // Every load of a pass is issued before the first use.
+  const bool live = S > 1 || tid < n;
+  const int tc = S > 1 ? tid : (tid < n ? tid : n - 1);
+  // passes over the row's elements go in groups of G (loads of a group issued together, a
+  // scheduling barrier between groups so that the registers of one group are free for the next)
+  constexpr int G = S < 8 ? S : 8;
+  const unsigned tu = (unsigned)tc;
   for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
+    // the tables do not change from row to row; holding their values or addresses in registers
+    // across rows would not fit, so they are loaded again for every row (from L2)
+    asm volatile("" ::: "memory");
     const T* a = A + r * lda;
     // D'' and the gather of Pi': b1[j] = d''[pi'(j)] a[pi'(j)]
-    for (int p = tid; p < n; p += GSRFT_THREADS) b0[p] = a[p] * t.sign[1][p];
-    __syncthreads();
-    for (int j = tid; j < n; j += GSRFT_THREADS) b1[j] = b0[t.perm[1][j]];
-    __syncthreads();
-    rotation_chain<T, SMAX>(b1, t.cs[1], n, sp, sq);
-    // D' and the gather of Pi: b0[j] = d'[pi(j)] b1[pi(j)]
-    for (int j = tid; j < n; j += GSRFT_THREADS) {
-      const int q = t.perm[0][j];
-      b0[j] = b1[q] * t.sign[0][q];
+#pragma unroll
+    for (int g = 0; g < S; g += G) {
+      T x[G], d[G];
+#pragma unroll
+      for (int it = 0; it < G; ++it) {
+        x[it] = (a + (g + it) * GSRFT_THREADS)[tu];
+        d[it] = (t.sign[1] + (g + it) * GSRFT_THREADS)[tu];
+      }
+      if (live) {
+#pragma unroll
+        for (int it = 0; it < G; ++it) b0[tc + (g + it) * GSRFT_THREADS] = x[it] * d[it];
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
-    rotation_chain<T, SMAX>(b0, t.cs[0], n, sp, sq);
+#pragma unroll
+    for (int g = 0; g < S; g += G) {
+      int q[G];
+#pragma unroll
+      for (int it = 0; it < G; ++it) q[it] = (t.perm[1] + (g + it) * GSRFT_THREADS)[tu];
+      if (live) {
+#pragma unroll
+        for (int it = 0; it < G; ++it) b1[tc + (g + it) * GSRFT_THREADS] = b0[q[it]];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    rotation_chain<T, S>(b1, t.cs[1], n, sp, sq);
+    // D' and the gather of Pi: b0[j] = d'[pi(j)] b1[pi(j)]
+#pragma unroll
+    for (int g = 0; g < S; g += G) {
+      int q[G];
+      T d[G];
+#pragma unroll
+      for (int it = 0; it < G; ++it) {
+        q[it] = (t.perm[0] + (g + it) * GSRFT_THREADS)[tu];
+        d[it] = (t.psign[0] + (g + it) * GSRFT_THREADS)[tu];
+      }
+      if (live) {
+#pragma unroll
+        for (int it = 0; it < G; ++it) b0[tc + (g + it) * GSRFT_THREADS] = b1[q[it]] * d[it];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    rotation_chain<T, S>(b0, t.cs[0], n, sp, sq);
     T* o = out + r * (int64_t)n;
-    for (int p = tid; p < n; p += GSRFT_THREADS) o[p] = b0[p];
+#pragma unroll
+    for (int g = 0; g < S; g += G) {
+      if (live) {
+#pragma unroll
+        for (int it = 0; it < G; ++it) (o + (g + it) * GSRFT_THREADS)[tu] = b0[tc + (g + it) * GSRFT_THREADS];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
     __syncthreads();
   }
 }
@@ -201,15 +277,15 @@ __global__ __launch_bounds__(GSRFT_THREADS) void gsrft_rows_kernel(const T* __re
 template <typename T>
 hipError_t draw_t(GsrftTables<T> t, int64_t n, uint64_t seed, uint64_t sid, hipStream_t st) {
   hipLaunchKernelGGL(gsrft_table_kernel<T>, dim3((unsigned)((n + 255) / 256), 2), dim3(256), 0, st, t, n, seed, sid);
-  hipLaunchKernelGGL(gsrft_sort_kernel, dim3(2), dim3(1024), 0, st, t.key[0], t.key[1], t.perm[0], t.perm[1], (int)n);
+  hipLaunchKernelGGL(gsrft_sort_kernel<T>, dim3(2), dim3(1024), 0, st, t, (int)n);
   return hipGetLastError();
 }
 
 }  // namespace
 
 size_t gsrft_table_bytes(int64_t n, int esize) {
-  // per chain: n signs, n (cos, sin) pairs (element type), n keys, n permutation entries
-  return 2 * (size_t)n * (3 * (size_t)esize + 8 + 4) + 64;
+  // per chain: n signs, n (cos, sin) pairs, n permuted signs (element type), n keys, n permutation entries
+  return 2 * (size_t)n * (4 * (size_t)esize + 8 + 4) + 64;
 }
 
 template <typename T>
@@ -225,6 +301,10 @@ GsrftTables<T> gsrft_tables(void* base, int64_t n) {
     b += (size_t)n * sizeof(T);
     t.cs[c] = reinterpret_cast<T*>(b);
     b += 2 * (size_t)n * sizeof(T);
+  }
+  for (int c = 0; c < 2; ++c) {
+    t.psign[c] = reinterpret_cast<T*>(b);
+    b += (size_t)n * sizeof(T);
   }
   for (int c = 0; c < 2; ++c) {
     t.perm[c] = reinterpret_cast<int32_t*>(b);
@@ -244,16 +324,39 @@ hipError_t launch_gsrft_draw(int dtype, void* tables, int64_t n, uint64_t seed, 
   return draw_t(gsrft_tables<float>(tables, n), n, seed, sid, st);
 }
 
+template <typename T, int S>
+void rows_launch(const dim3 grid, const void* A, int64_t lda, int64_t m, int64_t n, void* tables, void* out,
+                 hipStream_t st) {
+  hipLaunchKernelGGL((gsrft_rows_kernel<T, S>), grid, dim3(GSRFT_THREADS), 0, st, (const T*)A, lda, m, (int)n,
+                     gsrft_tables<T>(tables, n), (T*)out);
+}
+
+template <typename T>
+void rows_dispatch(const dim3 grid, const void* A, int64_t lda, int64_t m, int64_t n, void* tables, void* out,
+                   hipStream_t st) {
+  // S = n / GSRFT_THREADS steps per thread (1 for small n); n <= gsrft_lds_n<T>() keeps S <= 32
+  const int64_t S = n > GSRFT_THREADS ? n / GSRFT_THREADS : 1;
+  switch (S) {
+    case 1: rows_launch<T, 1>(grid, A, lda, m, n, tables, out, st); break;
+    case 2: rows_launch<T, 2>(grid, A, lda, m, n, tables, out, st); break;
+    case 4: rows_launch<T, 4>(grid, A, lda, m, n, tables, out, st); break;
+    case 8: rows_launch<T, 8>(grid, A, lda, m, n, tables, out, st); break;
+    case 16: rows_launch<T, 16>(grid, A, lda, m, n, tables, out, st); break;
+    default:
+      // FP64 rows stop at n = 8192 (S = 16): only FP32 has an S = 32 variant
+      if constexpr (sizeof(T) == 4) rows_launch<T, 32>(grid, A, lda, m, n, tables, out, st);
+      break;
+  }
+}
+
 hipError_t launch_gsrft_rows(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, void* tables, void* out,
                              hipStream_t st) {
   if (!gsrft_shape_ok(dtype, n) || lda < n || m < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(m < 512 ? m : 512));
   if (dtype == RSVD_F64)
-    hipLaunchKernelGGL(gsrft_rows_kernel<double>, grid, dim3(GSRFT_THREADS), 0, st, (const double*)A, lda, m, (int)n,
-                       gsrft_tables<double>(tables, n), (double*)out);
+    rows_dispatch<double>(grid, A, lda, m, n, tables, out, st);
   else
-    hipLaunchKernelGGL(gsrft_rows_kernel<float>, grid, dim3(GSRFT_THREADS), 0, st, (const float*)A, lda, m, (int)n,
-                       gsrft_tables<float>(tables, n), (float*)out);
+    rows_dispatch<float>(grid, A, lda, m, n, tables, out, st);
   return hipGetLastError();
 }
 
