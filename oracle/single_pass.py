@@ -13,8 +13,8 @@ vectors of Y, and the system B (Q* Omega) ~ Q* Y for the k x k matrix B is
 overdetermined (k x (k + p) coefficient matrix).
 
 Readings where the paper is silent:
-  * "A standard least-squares solver to find an Hermitian matrix": the
-    standard (unconstrained) least-squares solution of B M = N with
+  * The Hermitian B of step 1, asked of an ordinary least-squares solver: the
+    unconstrained least-squares solution of B M = N with
     M = Q* Omega, N = Q* Y, i.e. B M M* = N M* (M has full row rank), then its
     Hermitian part (B + B*)/2.
   * p = 0 (no oversampling): Q = an orthonormal basis of range(Y) (the square
