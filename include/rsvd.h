@@ -19,8 +19,8 @@
  *     truncation remark of Section 5.1).
  *
  * The problem statement follows the fixed-rank problem of Section 1.3: an
- * m x n matrix A, a target rank k and an oversampling parameter p, with
- * l = k + p samples, and q power steps (Section 1.6, Section 4.5).
+ * m x n matrix A, the rank k sought, p extra samples (l = k + p columns in
+ * the test matrix), and q power steps (Section 1.6, Section 4.5).
  *
  * Conventions for every call
  * --------------------------
