@@ -95,6 +95,11 @@ __global__ __launch_bounds__(1024) void gsrft_sort_kernel(GsrftTables<T> t, int 
   }
 }
 
+// LDS position of row entry j: one pad word after every 32 entries, so that the chain's per-thread
+// segments (entry t S + i for thread t) fall in different banks (unpadded, S = 32 puts every lane of
+// a wave on one bank)
+__device__ __forceinline__ int pidx(int j) { return j + (j >> 5); }
+
 template <typename T> struct GVec2;
 template <> struct GVec2<float> { typedef float __attribute__((ext_vector_type(2))) type; };
 template <> struct GVec2<double> { typedef double __attribute__((ext_vector_type(2))) type; };
@@ -107,7 +112,7 @@ template <> struct GVec2<double> { typedef double __attribute__((ext_vector_type
 template <typename T, int S>
 __device__ __forceinline__ void rotation_chain(T* buf, const T* __restrict__ cs, const int n, T* sp, T* sq) {
   typedef typename GVec2<T>::type V;
-  constexpr int G = S < 8 ? S : 8;  // steps whose (cos, sin) and x are loaded together
+  constexpr int G = S < 16 ? S : 16;  // steps whose (cos, sin) and x are loaded together
   const int tid = threadIdx.x;
   const int nact = n / S;
   const bool act = tid < nact;
@@ -118,7 +123,7 @@ __device__ __forceinline__ void rotation_chain(T* buf, const T* __restrict__ cs,
   // in a register, since the next thread overwrites it; the others are re-read from this thread's
   // own segment, which only this thread writes
   const int jl = j0 + S;
-  const T xl = buf[jl < n ? jl : n - 1];
+  const T xl = buf[pidx(jl < n ? jl : n - 1)];
   const T xlast = jl < n ? xl : (T)0;
   // this segment's map v -> P v + Q
   T P = (T)1, Q = (T)0;
@@ -129,7 +134,7 @@ __device__ __forceinline__ void rotation_chain(T* buf, const T* __restrict__ cs,
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       cv[i] = csv[g + i];
-      x[i] = g + i < S - 1 ? buf[j0 + g + i + 1] : xlast;
+      x[i] = g + i < S - 1 ? buf[pidx(j0 + g + i + 1)] : xlast;
     }
 #pragma unroll
     for (int i = 0; i < G; ++i) {
@@ -174,17 +179,42 @@ __device__ __forceinline__ void rotation_chain(T* buf, const T* __restrict__ cs,
 #pragma unroll
       for (int i = 0; i < G; ++i) {
         cv[i] = csv[g + i];
-        x[i] = g + i < S - 1 ? buf[j0 + g + i + 1] : xlast;
+        x[i] = g + i < S - 1 ? buf[pidx(j0 + g + i + 1)] : xlast;
       }
 #pragma unroll
       for (int i = 0; i < G; ++i) {
-        buf[j0 + g + i] = cv[i].x * v - cv[i].y * x[i];
+        buf[pidx(j0 + g + i)] = cv[i].x * v - cv[i].y * x[i];
         v = cv[i].y * v + cv[i].x * x[i];
       }
       __builtin_amdgcn_sched_barrier(0);
     }
   }
   __syncthreads();
+}
+
+// Raw buffer access for the element passes: the base address and size sit in a scalar
+// resource, so every element of a thread is its one offset register plus a constant (global
+// addressing would hold a 64-bit address per element and table, which does not fit at S = 32).
+constexpr int kGsrftBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t gsrft_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kGsrftBufferWord3);
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff, float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff, double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ int buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff, int*) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
 
 template <typename T>
@@ -196,8 +226,8 @@ template <typename T, int S>
 __global__ __launch_bounds__(GSRFT_THREADS) void gsrft_rows_kernel(const T* __restrict__ A, int64_t lda, int64_t m,
                                                                   int n, GsrftTables<T> t, T* __restrict__ out) {
   constexpr int NMAX = gsrft_lds_n<T>();
-  __shared__ __attribute__((aligned(16))) T b0[NMAX];
-  __shared__ __attribute__((aligned(16))) T b1[NMAX];
+  __shared__ __attribute__((aligned(16))) T b0[NMAX + NMAX / 32];
+  __shared__ __attribute__((aligned(16))) T b1[NMAX + NMAX / 32];
   __shared__ T sp[2 * GSRFT_THREADS], sq[2 * GSRFT_THREADS];
   const int tid = threadIdx.x;
   // element p = tid + it * GSRFT_THREADS, it < S: for S > 1, n = S * GSRFT_THREADS exactly (n is a
@@ -207,39 +237,48 @@ __global__ __launch_bounds__(GSRFT_THREADS) void gsrft_rows_kernel(const T* __re
   const int tc = S > 1 ? tid : (tid < n ? tid : n - 1);
   // passes over the row's elements go in groups of G (loads of a group issued together, a
   // scheduling barrier between groups so that the registers of one group are free for the next)
-  constexpr int G = S < 8 ? S : 8;
-  const unsigned tu = (unsigned)tc;
-  for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
-    // the tables do not change from row to row; holding their values or addresses in registers
-    // across rows would not fit, so they are loaded again for every row (from L2)
-    asm volatile("" ::: "memory");
-    const T* a = A + r * lda;
+  constexpr int G = S;
+  const int vo = tc * (int)sizeof(T), vi = tc * 4;  // this thread's offsets (elements p = tc + k 512)
+  constexpr int ST = GSRFT_THREADS * (int)sizeof(T), SI = GSRFT_THREADS * 4;
+  const int64_t nb = (int64_t)n * (int64_t)sizeof(T), ni = (int64_t)n * 4;
+  const __amdgpu_buffer_rsrc_t rq1 = gsrft_rsrc(t.psign[1], nb), rp1 = gsrft_rsrc(t.perm[1], ni);
+  const __amdgpu_buffer_rsrc_t rp0 = gsrft_rsrc(t.perm[0], ni), rq0 = gsrft_rsrc(t.psign[0], nb);
+  // the row is loaded one iteration ahead: its loads are in flight while the previous row is
+  // transformed
+  T xa[S];
+  int64_t r = blockIdx.x;
+  if (r < m) {
+    const __amdgpu_buffer_rsrc_t ra = gsrft_rsrc(A + r * lda, nb);
+#pragma unroll
+    for (int it = 0; it < S; ++it) xa[it] = buf_load(ra, vo, it * ST, (T*)nullptr);
+  }
+  for (; r < m; r += gridDim.x) {
+    const __amdgpu_buffer_rsrc_t ro = gsrft_rsrc(out + r * (int64_t)n, nb);
+    if (live) {
+#pragma unroll
+      for (int it = 0; it < S; ++it) b0[pidx(tc + it * GSRFT_THREADS)] = xa[it];
+    }
+    const int64_t rn = r + gridDim.x;
+    if (rn < m) {
+      const __amdgpu_buffer_rsrc_t ra = gsrft_rsrc(A + rn * lda, nb);
+#pragma unroll
+      for (int it = 0; it < S; ++it) xa[it] = buf_load(ra, vo, it * ST, (T*)nullptr);
+    }
+    __syncthreads();
     // D'' and the gather of Pi': b1[j] = d''[pi'(j)] a[pi'(j)]
 #pragma unroll
     for (int g = 0; g < S; g += G) {
-      T x[G], d[G];
+      int q[G];
+      T d[G];
 #pragma unroll
       for (int it = 0; it < G; ++it) {
-        x[it] = (a + (g + it) * GSRFT_THREADS)[tu];
-        d[it] = (t.sign[1] + (g + it) * GSRFT_THREADS)[tu];
+        q[it] = buf_load(rp1, vi, (g + it) * SI, (int*)nullptr);
+        d[it] = buf_load(rq1, vo, (g + it) * ST, (T*)nullptr);
       }
       if (live) {
 #pragma unroll
-        for (int it = 0; it < G; ++it) b0[tc + (g + it) * GSRFT_THREADS] = x[it] * d[it];
+        for (int it = 0; it < G; ++it) b1[pidx(tc + (g + it) * GSRFT_THREADS)] = b0[pidx(q[it])] * d[it];
       }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int g = 0; g < S; g += G) {
-      int q[G];
-#pragma unroll
-      for (int it = 0; it < G; ++it) q[it] = (t.perm[1] + (g + it) * GSRFT_THREADS)[tu];
-      if (live) {
-#pragma unroll
-        for (int it = 0; it < G; ++it) b1[tc + (g + it) * GSRFT_THREADS] = b0[q[it]];
-      }
-      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     rotation_chain<T, S>(b1, t.cs[1], n, sp, sq);
@@ -250,25 +289,19 @@ __global__ __launch_bounds__(GSRFT_THREADS) void gsrft_rows_kernel(const T* __re
       T d[G];
 #pragma unroll
       for (int it = 0; it < G; ++it) {
-        q[it] = (t.perm[0] + (g + it) * GSRFT_THREADS)[tu];
-        d[it] = (t.psign[0] + (g + it) * GSRFT_THREADS)[tu];
+        q[it] = buf_load(rp0, vi, (g + it) * SI, (int*)nullptr);
+        d[it] = buf_load(rq0, vo, (g + it) * ST, (T*)nullptr);
       }
       if (live) {
 #pragma unroll
-        for (int it = 0; it < G; ++it) b0[tc + (g + it) * GSRFT_THREADS] = b1[q[it]] * d[it];
+        for (int it = 0; it < G; ++it) b0[pidx(tc + (g + it) * GSRFT_THREADS)] = b1[pidx(q[it])] * d[it];
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     rotation_chain<T, S>(b0, t.cs[0], n, sp, sq);
-    T* o = out + r * (int64_t)n;
+    if (live) {
 #pragma unroll
-    for (int g = 0; g < S; g += G) {
-      if (live) {
-#pragma unroll
-        for (int it = 0; it < G; ++it) (o + (g + it) * GSRFT_THREADS)[tu] = b0[tc + (g + it) * GSRFT_THREADS];
-      }
-      __builtin_amdgcn_sched_barrier(0);
+      for (int it = 0; it < S; ++it) buf_store(b0[pidx(tc + it * GSRFT_THREADS)], ro, vo, it * ST);
     }
     __syncthreads();
   }
