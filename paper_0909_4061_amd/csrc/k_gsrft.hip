@@ -26,7 +26,8 @@
 //                        (the rotation j acts on the running value v_j and the
 //                        untouched x_{j+1}); each thread composes the affine maps
 //                        of its segment of S = n / 512 steps, a scan over the
-//                        512 segment maps gives every segment's starting value,
+//                        512 segment maps (lane shuffles within a wave, then the
+//                        eight wave totals) gives every segment's starting value,
 //                        and each thread then replays its segment.  The step
 //                        past the end is padded with (c, s) = (1, 0), x_n = 0.
 #include "common.hpp"
@@ -143,35 +144,44 @@ __device__ __forceinline__ void rotation_chain(T* buf, const T* __restrict__ cs,
     }
     __builtin_amdgcn_sched_barrier(0);
   }
+  if (!act) {  // threads past the row carry the identity map
+    P = (T)1;
+    Q = (T)0;
+  }
   __syncthreads();  // every read of buf is done: segments may now be overwritten
-  if (act) {
-    sp[tid] = P;
-    sq[tid] = Q;
+  // inclusive scan of the maps over the threads, I_t = map_t o ... o map_0: within each wave by
+  // lane shuffles, then across the waves through their totals
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T Pe = __shfl_up(P, off, 64), Qe = __shfl_up(Q, off, 64);
+    if (lane >= off) {
+      Q = P * Qe + Q;
+      P = P * Pe;
+    }
+  }
+  if (lane == 63) {
+    sp[GSRFT_THREADS + wv] = P;
+    sq[GSRFT_THREADS + wv] = Q;
   }
   __syncthreads();
-  // inclusive scan of the maps: I_t = map_t o ... o map_0 (Hillis-Steele, double-buffered)
-  int cur = 0;
-  for (int off = 1; off < nact; off <<= 1) {
-    const T* pin = sp + cur * GSRFT_THREADS;
-    const T* qin = sq + cur * GSRFT_THREADS;
-    T* pout = sp + (cur ^ 1) * GSRFT_THREADS;
-    T* qout = sq + (cur ^ 1) * GSRFT_THREADS;
-    if (act) {
-      T pt = pin[tid], qt = qin[tid];
-      if (tid >= off) {
-        const T pe = pin[tid - off], qe = qin[tid - off];
-        qt = pt * qe + qt;
-        pt = pt * pe;
-      }
-      pout[tid] = pt;
-      qout[tid] = qt;
+  {
+    // the waves before this one, composed in order: E = total_{wv-1} o ... o total_0
+    T PE = (T)1, QE = (T)0;
+    for (int w = 0; w < wv; ++w) {
+      const T pw = sp[GSRFT_THREADS + w], qw = sq[GSRFT_THREADS + w];
+      QE = pw * QE + qw;
+      PE = pw * PE;
     }
-    cur ^= 1;
-    __syncthreads();
+    Q = P * QE + Q;
+    P = P * PE;
   }
+  sp[tid] = P;
+  sq[tid] = Q;
+  __syncthreads();
   if (act) {
     T v = x0;
-    if (tid > 0) v = sp[cur * GSRFT_THREADS + tid - 1] * x0 + sq[cur * GSRFT_THREADS + tid - 1];
+    if (tid > 0) v = sp[tid - 1] * x0 + sq[tid - 1];
 #pragma unroll
     for (int g = 0; g < S; g += G) {
       V cv[G];
