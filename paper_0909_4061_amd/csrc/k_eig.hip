@@ -679,13 +679,20 @@ __device__ __forceinline__ void eig_fix_body(const EigParams& p) {
           {
             const int i = tid >> 1, h = tid & 1;
             double s4[4] = {0.0, 0.0, 0.0, 0.0};  // coef is zero for the columns not used
+            // only the columns that can have a nonzero coefficient ([clu0[j], j) in phase 1), in
+            // steps of four from a multiple of four: each term keeps its partial sum and the skipped
+            // terms were exact zeros, so the sums are the ones of the full loop
+            const int clo = phase == 1 ? clu0[j] : 0, chi = phase == 1 ? j : l;
+            const int qlo = max(0, (clo - h * HALF) & ~3), qhi = min(HALF, ((chi - h * HALF) + 3) & ~3);
             if (i < l) {
+              for (int q = qlo; q < qhi; q += 4) {
 #pragma unroll
-              for (int q = 0; q < HALF; q += 2) {
-                const int c = h * HALF + q;
-                const dbl2 cf = *reinterpret_cast<const dbl2*>(coef + c);
-                s4[q & 2] = fma(-cf.x, Zs[c * LDZ + i], s4[q & 2]);
-                s4[(q & 2) + 1] = fma(-cf.y, Zs[(c + 1) * LDZ + i], s4[(q & 2) + 1]);
+                for (int u = 0; u < 4; u += 2) {
+                  const int c = h * HALF + q + u;
+                  const dbl2 cf = *reinterpret_cast<const dbl2*>(coef + c);
+                  s4[u] = fma(-cf.x, Zs[c * LDZ + i], s4[u]);
+                  s4[u + 1] = fma(-cf.y, Zs[(c + 1) * LDZ + i], s4[u + 1]);
+                }
               }
             }
             double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
