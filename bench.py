@@ -14,9 +14,12 @@ FP32 accumulation); the plain FP32 form runs on the same matrix for comparison.
 
 Prints one JSON line.  `value` is algorithmic TFLOP/s of the whole step
 (flops the method must do, not padded tiles or the three bf16 products).
-The default run also times the other workloads briefly (FP64 2000 x 1000; the
-SRFT workload, FP32 32768 x 16384; 512 uneven matrices; 32 differentiable
-4096 x 2048 matrices) and reports them compactly under "workloads"; each has
+The default run also times the two-sided single pass (Section 5.5) against the
+two-pass route with q = 0 on the same matrix ("single_pass_two_sided"), and the
+other workloads briefly (FP64 2000 x 1000; the SRFT workload, FP32
+32768 x 16384, with the SRFT, Gaussian and Givens-chain test matrices; 512
+uneven matrices; 32 differentiable 4096 x 2048 matrices; Stage B of a psd
+16384 x 16384 matrix) and reports them compactly under "workloads"; each has
 its own --workload mode with a full line.
 """
 
