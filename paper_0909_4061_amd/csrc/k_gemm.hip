@@ -432,24 +432,27 @@ __global__ __launch_bounds__(64) void gemm_f64_small_kernel(const GemmParams p) 
   const int jc = jok ? j : p.ncols - 1;
   const double* __restrict__ a = (const double*)p.A;
   const double* __restrict__ x = (const double*)p.X;
-  const int nk = (K + 3) / 4;
+  // every load is issued unconditionally (indices clamped, values past K zeroed): a guard on the
+  // runtime bound would make the compiler branch around each load and wait after it.  The steps
+  // past K add exact zeros.
   double av[SMALL_F64_MAX / 4], xv[SMALL_F64_MAX / 4];
 #pragma unroll
   for (int t = 0; t < SMALL_F64_MAX / 4; ++t) {
-    if (t < nk) {
-      const int k = 4 * t + g;
-      const bool kok = k < K;
-      const int64_t kc = kok ? k : K - 1;
-      const double va = TRANS ? a[kc * p.lda + ic] : a[ic * p.lda + kc];
-      const double vx = x[kc * p.ldx + jc];
-      av[t] = (kok && iok) ? va : 0.0;
-      xv[t] = (kok && jok) ? vx : 0.0;
-    }
+    const int k = 4 * t + g;
+    const bool kok = k < K;
+    const int64_t kc = kok ? k : K - 1;
+    const double va = TRANS ? a[kc * p.lda + ic] : a[ic * p.lda + kc];
+    const double vx = x[kc * p.ldx + jc];
+    av[t] = (kok && iok) ? va : 0.0;
+    xv[t] = (kok && jok) ? vx : 0.0;
   }
+  const int nk = (K + 3) / 4;
   f64x4 acc{};
 #pragma unroll
-  for (int t = 0; t < SMALL_F64_MAX / 4; ++t)
-    if (t < nk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], xv[t], acc, 0, 0, 0);
+  for (int t = 0; t < SMALL_F64_MAX / 4; ++t) {
+    const f64x4 nxt = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], xv[t], acc, 0, 0, 0);
+    acc = t < nk ? nxt : acc;
+  }
   double* out = (double*)p.out;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
