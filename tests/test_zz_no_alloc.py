@@ -43,7 +43,7 @@ def test_static_matches_rsvd_full_twice():
 
 
 def test_static_refuses_oversized_problem():
-    # 4096 x 2048, l = 80, q = 1: rsvd_full needs 33.9 MiB > RSVD_STATIC_SCRATCH_BYTES
+    # 4096 x 2048, l = 80, q = 1: rsvd_full needs 35.8 MiB > RSVD_STATIC_SCRATCH_BYTES
     A = torch.empty(4096, 2048, dtype=torch.float32, device=DEV)
     pr = rs.problem(4096, 2048, 64, 16, 1, dtype=torch.float32)
     lib = rs._lib.load()
