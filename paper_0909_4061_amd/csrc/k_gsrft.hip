@@ -126,23 +126,22 @@ __device__ __forceinline__ void rotation_chain(T* buf, const T* __restrict__ cs,
   const int jl = j0 + S;
   const T xl = buf[pidx(jl < n ? jl : n - 1)];
   const T xlast = jl < n ? xl : (T)0;
+  // this segment's (cos, sin) pairs, held for both passes
+  V cv[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) cv[i] = csv[i];
   // this segment's map v -> P v + Q
   T P = (T)1, Q = (T)0;
 #pragma unroll
   for (int g = 0; g < S; g += G) {
-    V cv[G];
     T x[G];
 #pragma unroll
-    for (int i = 0; i < G; ++i) {
-      cv[i] = csv[g + i];
-      x[i] = g + i < S - 1 ? buf[pidx(j0 + g + i + 1)] : xlast;
-    }
+    for (int i = 0; i < G; ++i) x[i] = g + i < S - 1 ? buf[pidx(j0 + g + i + 1)] : xlast;
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      P = cv[i].y * P;
-      Q = cv[i].y * Q + cv[i].x * x[i];
+      P = cv[g + i].y * P;
+      Q = cv[g + i].y * Q + cv[g + i].x * x[i];
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
   if (!act) {  // threads past the row carry the identity map
     P = (T)1;
@@ -184,19 +183,14 @@ __device__ __forceinline__ void rotation_chain(T* buf, const T* __restrict__ cs,
     if (tid > 0) v = sp[tid - 1] * x0 + sq[tid - 1];
 #pragma unroll
     for (int g = 0; g < S; g += G) {
-      V cv[G];
       T x[G];
 #pragma unroll
-      for (int i = 0; i < G; ++i) {
-        cv[i] = csv[g + i];
-        x[i] = g + i < S - 1 ? buf[pidx(j0 + g + i + 1)] : xlast;
-      }
+      for (int i = 0; i < G; ++i) x[i] = g + i < S - 1 ? buf[pidx(j0 + g + i + 1)] : xlast;
 #pragma unroll
       for (int i = 0; i < G; ++i) {
-        buf[pidx(j0 + g + i)] = cv[i].x * v - cv[i].y * x[i];
-        v = cv[i].y * v + cv[i].x * x[i];
+        buf[pidx(j0 + g + i)] = cv[g + i].x * v - cv[g + i].y * x[i];
+        v = cv[g + i].y * v + cv[g + i].x * x[i];
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
   }
   __syncthreads();
@@ -253,26 +247,17 @@ __global__ __launch_bounds__(GSRFT_THREADS) void gsrft_rows_kernel(const T* __re
   const int64_t nb = (int64_t)n * (int64_t)sizeof(T), ni = (int64_t)n * 4;
   const __amdgpu_buffer_rsrc_t rq1 = gsrft_rsrc(t.psign[1], nb), rp1 = gsrft_rsrc(t.perm[1], ni);
   const __amdgpu_buffer_rsrc_t rp0 = gsrft_rsrc(t.perm[0], ni), rq0 = gsrft_rsrc(t.psign[0], nb);
-  // the row is loaded one iteration ahead: its loads are in flight while the previous row is
-  // transformed
-  T xa[S];
-  int64_t r = blockIdx.x;
-  if (r < m) {
-    const __amdgpu_buffer_rsrc_t ra = gsrft_rsrc(A + r * lda, nb);
-#pragma unroll
-    for (int it = 0; it < S; ++it) xa[it] = buf_load(ra, vo, it * ST, (T*)nullptr);
-  }
-  for (; r < m; r += gridDim.x) {
+  for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
     const __amdgpu_buffer_rsrc_t ro = gsrft_rsrc(out + r * (int64_t)n, nb);
-    if (live) {
-#pragma unroll
-      for (int it = 0; it < S; ++it) b0[pidx(tc + it * GSRFT_THREADS)] = xa[it];
-    }
-    const int64_t rn = r + gridDim.x;
-    if (rn < m) {
-      const __amdgpu_buffer_rsrc_t ra = gsrft_rsrc(A + rn * lda, nb);
+    {
+      const __amdgpu_buffer_rsrc_t ra = gsrft_rsrc(A + r * lda, nb);
+      T xa[S];
 #pragma unroll
       for (int it = 0; it < S; ++it) xa[it] = buf_load(ra, vo, it * ST, (T*)nullptr);
+      if (live) {
+#pragma unroll
+        for (int it = 0; it < S; ++it) b0[pidx(tc + it * GSRFT_THREADS)] = xa[it];
+      }
     }
     __syncthreads();
     // D'' and the gather of Pi': b1[j] = d''[pi'(j)] a[pi'(j)]
