@@ -26,6 +26,8 @@ single_pass The eigenvalue decomposition of a Hermitian matrix in one pass over 
             Section 5.5; the two-sided single pass for a general matrix.
 gsrft       The test matrix built from chains of random Givens rotations (the
             remark on random Givens rotations in Section 4.6), real form.
+row_extraction  Stage B by row extraction: the interpolative decomposition of the
+            basis and Algorithm 5.2.
 evaluate    Residual norms ||A - QQ*A|| and ||A - U S V*|| and the paper's error
             bounds (Theorems 9.1-9.3, 10.5, 10.6, Corollaries 10.9, 10.10).
 rsvd_grad   The reference gradient of the fixed-Omega randomized SVD: the same
@@ -38,5 +40,5 @@ something other than itself: numpy's own Philox, brute-force DFTs and SVDs,
 exact-rank recovery and the deterministic theorems of Section 9.
 """
 
-from . import philox, rsvd, evaluate, adaptive, herm, single_pass, gsrft  # noqa: F401
+from . import philox, rsvd, evaluate, adaptive, herm, single_pass, gsrft, row_extraction  # noqa: F401
 # rsvd_grad imports torch; it is imported on its own where needed.
