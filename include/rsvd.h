@@ -288,8 +288,8 @@ rsvd_status rsvd_nystrom(rsvd_handle handle, const rsvd_problem* problem, const 
 rsvd_status rsvd_eigh_onepass(rsvd_handle handle, const rsvd_problem* problem, const void* A, void* U, void* Lam,
                               void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* rsvd_svd_onepass: the single-pass factorization of a general A that closes
- * Section 5.5.  Omega (n x l, l = k + p) is drawn from (seed, stream_id) as
+/* rsvd_svd_onepass: the single-pass factorization of a general A that
+ * Section 5.5 describes after Algorithm 5.6.  Omega (n x l, l = k + p) is drawn from (seed, stream_id) as
  * rsvd_draw_omega draws it and Omegat (m x l) from (seed, stream_id with its
  * top bit flipped); Y = A Omega and Yt = A^T Omegat are the only products with
  * A (two launches here, each reading A once: with A resident in device memory
